@@ -1,0 +1,197 @@
+"""FP64 CPU oracle for the adaptive-force-update gravity path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``; never by the product package.
+It shares no code with the HIP path.  Each wrapper below calls the plain C
+routine of the same name in ``oracle.c`` (built into ``liboracle.so`` by
+:func:`build`), which states the definition it implements:
+
+* :func:`field` / :func:`direct` -- softened direct sum for the acceleration,
+  the jerk (the particle discretisation of the jerk integral, Eq. 5) and the
+  tidal tensor (whose Frobenius norm enters Eq. 7).
+* :func:`timestep` -- the tidal timestep of Eq. 7 and its power-of-two bin.
+* :func:`select` -- force-age counter (Eq. 3) and update condition (Eq. 4).
+* :func:`predict` -- jerk predictor (Eq. 6) in closed form ``a0 + j (t - t0)``.
+* :func:`adjoint` -- exact gradient of ``L = sum_i w_i . a_i``.
+* :func:`moments` -- node multipoles (mass, centre of mass, mean velocity,
+  traceless quadrupole and its rate) of a particle set.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# Compiled for the generic x86-64-v3 level (any recent EPYC/Xeon host) with
+# fused multiply-add contraction off, so every operation is rounded once as
+# written in the C source.
+CFLAGS = ["-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
+          "-fopenmp", "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        lib.orc_kernel.argtypes = [I64, P, D, P, P, P]
+        lib.orc_field.argtypes = [I64, P, P, P, D, D, I64, P, P, P, P, P, P]
+        lib.orc_direct.argtypes = [I64, P, P, P, D, D, I64, P, P, P, P]
+        lib.orc_abs_scale.argtypes = [I64, P, P, D, D, I64, P, P]
+        lib.orc_timestep.argtypes = [I64, P, D, D, ctypes.c_int32, P, P]
+        lib.orc_select.argtypes = [I64, P, P, I64, ctypes.c_int32, D, P]
+        lib.orc_select.restype = I64
+        lib.orc_predict.argtypes = [I64, P, P, P, D, P]
+        lib.orc_adjoint.argtypes = [I64, P, P, P, D, D, I64, P, P, P]
+        lib.orc_moments.argtypes = [I64, P, P, P, P, P]
+        lib.orc_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def kernel(r, h):
+    """Return (f, D, W) of the cubic-spline kernel at separations ``r``."""
+    r = _f64(r).ravel()
+    f = np.empty_like(r)
+    D = np.empty_like(r)
+    W = np.empty_like(r)
+    _load().orc_kernel(r.size, _ptr(r), float(h), _ptr(f), _ptr(D), _ptr(W))
+    return f, D, W
+
+
+def field(x, v, m, eps, G, p, pv=None, excl=None):
+    """Acceleration, jerk and tidal tensor at probe points ``p`` (np x 3)."""
+    x = _f64(x, (-1, 3))
+    v = _f64(v, (-1, 3))
+    m = _f64(m).ravel()
+    p = _f64(p, (-1, 3))
+    pv = np.zeros_like(p) if pv is None else _f64(pv, (-1, 3))
+    ex = None if excl is None else np.ascontiguousarray(excl, dtype=np.int64)
+    k = p.shape[0]
+    acc = np.empty((k, 3))
+    jerk = np.empty((k, 3))
+    tid = np.empty((k, 6))
+    _load().orc_field(x.shape[0], _ptr(x), _ptr(v), _ptr(m), float(eps), float(G),
+                      k, _ptr(p), _ptr(pv), _ptr(ex), _ptr(acc), _ptr(jerk), _ptr(tid))
+    return acc, jerk, tid
+
+
+def direct(x, v, m, eps, G, targets=None):
+    """Direct sum at particles ``targets`` (default: all), self excluded."""
+    x = _f64(x, (-1, 3))
+    v = _f64(v, (-1, 3))
+    m = _f64(m).ravel()
+    n = x.shape[0]
+    tgt = np.arange(n, dtype=np.int64) if targets is None else \
+        np.ascontiguousarray(targets, dtype=np.int64)
+    k = tgt.size
+    acc = np.empty((k, 3))
+    jerk = np.empty((k, 3))
+    tid = np.empty((k, 6))
+    _load().orc_direct(n, _ptr(x), _ptr(v), _ptr(m), float(eps), float(G), k, _ptr(tgt),
+                       _ptr(acc), _ptr(jerk), _ptr(tid))
+    return acc, jerk, tid
+
+
+def abs_scale(x, m, eps, G, targets=None):
+    """G sum_j m_j |f d| per target: the cancellation-free size of the sum."""
+    x = _f64(x, (-1, 3))
+    m = _f64(m).ravel()
+    n = x.shape[0]
+    tgt = np.arange(n, dtype=np.int64) if targets is None else \
+        np.ascontiguousarray(targets, dtype=np.int64)
+    out = np.empty(tgt.size)
+    _load().orc_abs_scale(n, _ptr(x), _ptr(m), float(eps), float(G), tgt.size, _ptr(tgt),
+                          _ptr(out))
+    return out
+
+
+def timestep(tidal, eta, dt_max, k_max):
+    """Eq. 7 tidal timestep and its block bin for each row of ``tidal`` (n x 6)."""
+    t = _f64(tidal, (-1, 6))
+    n = t.shape[0]
+    dt = np.empty(n)
+    b = np.empty(n, dtype=np.int8)
+    _load().orc_timestep(n, _ptr(t), float(eta), float(dt_max), int(k_max), _ptr(dt), _ptr(b))
+    return dt, b
+
+
+def select(tf_ticks, bins, step_ticks, tick_bin, q_f):
+    """Eq. 3 + Eq. 4.  Returns (new tf, active mask uint8, active indices)."""
+    tf = np.array(tf_ticks, dtype=np.int64, copy=True)
+    b = np.ascontiguousarray(bins, dtype=np.int8)
+    act = np.empty(tf.size, dtype=np.uint8)
+    _load().orc_select(tf.size, _ptr(tf), _ptr(b), int(step_ticks), int(tick_bin),
+                       float(q_f), _ptr(act))
+    return tf, act, np.nonzero(act)[0].astype(np.int64)
+
+
+def predict(a0, jerk, t0, t):
+    """Eq. 6 predictor a0 + j (t - t0), row by row."""
+    a0 = _f64(a0, (-1, 3))
+    j = _f64(jerk, (-1, 3))
+    t0 = _f64(t0).ravel()
+    out = np.empty_like(a0)
+    _load().orc_predict(a0.shape[0], _ptr(a0), _ptr(j), _ptr(t0), float(t), _ptr(out))
+    return out
+
+
+def adjoint(x, m, w, eps, G, k=None):
+    """Exact dL/dx_k and dL/dm_k of L = sum_i w_i . a_i at particles ``k``."""
+    x = _f64(x, (-1, 3))
+    m = _f64(m).ravel()
+    w = _f64(w, (-1, 3))
+    n = x.shape[0]
+    kk = np.arange(n, dtype=np.int64) if k is None else np.ascontiguousarray(k, dtype=np.int64)
+    dx = np.empty((kk.size, 3))
+    dm = np.empty(kk.size)
+    _load().orc_adjoint(n, _ptr(x), _ptr(m), _ptr(w), float(eps), float(G), kk.size, _ptr(kk),
+                        _ptr(dx), _ptr(dm))
+    return dx, dm
+
+
+def moments(x, v, m, idx):
+    """Multipoles of the particles ``idx``: dict of M, com, u, Q, Qdot, lo, hi."""
+    x = _f64(x, (-1, 3))
+    v = _f64(v, (-1, 3))
+    m = _f64(m).ravel()
+    ii = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(25)
+    _load().orc_moments(ii.size, _ptr(ii), _ptr(x), _ptr(v), _ptr(m), _ptr(out))
+    return {"M": out[0], "com": out[1:4], "u": out[4:7], "Q": out[7:13], "Qdot": out[13:19],
+            "lo": out[19:22], "hi": out[22:25]}

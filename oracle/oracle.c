@@ -1,0 +1,380 @@
+/*
+ * oracle.c -- plain, slow FP64 reference for the adaptive-force-update gravity
+ * path of Grudic (2020), "Accelerating self-gravitating hydrodynamics
+ * simulations with adaptive force updates".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source, header, table or helper with
+ * the HIP path.
+ *
+ * Every routine is the textbook definition written out in double precision,
+ * looping over all pairs in index order with no blocking, reordering or
+ * approximation:
+ *
+ *   - field():      softened direct sum for acceleration g, jerk j = dg/dt
+ *                   (the discretised form of the paper's jerk integral,
+ *                   Sec. 2.2, Eq. 5) and tidal tensor T = grad g (Sec. 3,
+ *                   Eq. 7 uses its Frobenius norm).
+ *   - timestep():   tidal timestep Eq. 7 and its power-of-two block bin
+ *                   (the hierarchical block steps of Sec. 3).
+ *   - select():     force-age counter Eq. 3 and update test Eq. 4 (Sec. 2.1).
+ *   - predict():    first-order jerk predictor Eq. 6 in closed form
+ *                   a0 + j (t - t0) (Sec. 2.2).
+ *   - adjoint():    exact gradient of L = sum_i w_i . a_i with respect to
+ *                   positions and masses (not in the paper; the analytic
+ *                   derivative of the direct sum above).
+ *   - moments():    mass, centre of mass, mean velocity, traceless quadrupole
+ *                   and its time derivative for a particle set (the node
+ *                   multipoles of an oct-tree, Sec. 3).
+ *
+ * Softening kernel (a reading; the paper only says softening follows the
+ * hydro kernel): cubic-spline M4 density kernel with compact support h = eps,
+ * W(r) = 8/(pi h^3) w(u), u = r/h,
+ *     w = 1 - 6u^2 + 6u^3 (u < 1/2), 2(1-u)^3 (1/2 <= u < 1), 0 (u >= 1).
+ * The pair force factor is f(r) = mu(u)/r^3, mu(u) the kernel mass inside r,
+ * so g_i = G sum_j m_j f(r) d_ij with d_ij = x_j - x_i; D(r) = f'(r)/r.
+ * Written in the u^3-cancelled form, exactly equal algebraically:
+ *     u < 1/2:   f = h^-3 (32/3 - 192/5 u^2 + 32 u^3),  D = h^-5 (96u - 384/5)
+ *     1/2<=u<1:  f = h^-3 (64/3 - 48u + 192/5 u^2 - 32/3 u^3 - 1/(15u^3)),
+ *                D = h^-5 (-48/u + 384/5 - 32u + 1/(5u^5))
+ *     u >= 1:    f = r^-3, D = -3 r^-5 (Newtonian).
+ * The self pair (j == i) is excluded from every sum.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ---- softening kernel --------------------------------------------------- */
+
+static void kernel_fd(double r, double h, double *f, double *D)
+{
+    if (r >= h) {
+        double r2 = r * r;
+        *f = 1.0 / (r2 * r);
+        *D = -3.0 / (r2 * r2 * r);
+        return;
+    }
+    double hi = 1.0 / h;
+    double h3 = hi * hi * hi;
+    double h5 = h3 * hi * hi;
+    double u = r * hi;
+    if (u < 0.5) {
+        *f = h3 * (32.0 / 3.0 - 192.0 / 5.0 * u * u + 32.0 * u * u * u);
+        *D = h5 * (96.0 * u - 384.0 / 5.0);
+    } else {
+        double u3 = u * u * u;
+        *f = h3 * (64.0 / 3.0 - 48.0 * u + 192.0 / 5.0 * u * u
+                   - 32.0 / 3.0 * u3 - 1.0 / (15.0 * u3));
+        *D = h5 * (-48.0 / u + 384.0 / 5.0 - 32.0 * u + 1.0 / (5.0 * u3 * u * u));
+    }
+}
+
+static double kernel_w(double r, double h)
+{
+    double u = r / h;
+    double c = 8.0 / (ORC_PI * h * h * h);
+    if (u < 0.5) return c * (1.0 - 6.0 * u * u + 6.0 * u * u * u);
+    if (u < 1.0) { double t = 1.0 - u; return c * 2.0 * t * t * t; }
+    return 0.0;
+}
+
+/* Exported for the kernel pins: f, D and W at separation r. */
+void orc_kernel(int64_t n, const double *r, double h, double *f, double *D, double *W)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        kernel_fd(r[k], h, &f[k], &D[k]);
+        W[k] = kernel_w(r[k], h);
+    }
+}
+
+/* ---- direct-sum field ---------------------------------------------------- */
+/*
+ * Field at np probe points p (np x 3, row-major) moving with velocity pv, due
+ * to n sources (x, v: n x 3 row-major; m: n).  excl[k] names a source index
+ * skipped for probe k (the probe's own particle), or -1; excl may be NULL.
+ * Outputs (np rows): acc (3), jerk (3), tidal (6: xx yy zz xy xz yz).
+ *
+ *   g  =  G sum_j m_j f d
+ *   j  =  G sum_j m_j [ f nu + D (d.nu) d ]          nu = v_j - pv
+ *   T  = -G sum_j m_j [ f I  + D d d^T ]             (T = grad g)
+ */
+void orc_field(int64_t n, const double *x, const double *v, const double *m,
+               double eps, double G,
+               int64_t np, const double *p, const double *pv, const int64_t *excl,
+               double *acc, double *jerk, double *tidal)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < np; ++k) {
+        double px = p[3 * k], py = p[3 * k + 1], pz = p[3 * k + 2];
+        double qx = pv[3 * k], qy = pv[3 * k + 1], qz = pv[3 * k + 2];
+        int64_t skip = excl ? excl[k] : -1;
+        double ax = 0, ay = 0, az = 0, jx = 0, jy = 0, jz = 0;
+        double txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == skip) continue;
+            double dx = x[3 * j] - px, dy = x[3 * j + 1] - py, dz = x[3 * j + 2] - pz;
+            double nx = v[3 * j] - qx, ny = v[3 * j + 1] - qy, nz = v[3 * j + 2] - qz;
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double f, D;
+            kernel_fd(r, eps, &f, &D);
+            double mj = m[j];
+            double dn = dx * nx + dy * ny + dz * nz;
+            ax += mj * f * dx; ay += mj * f * dy; az += mj * f * dz;
+            jx += mj * (f * nx + D * dn * dx);
+            jy += mj * (f * ny + D * dn * dy);
+            jz += mj * (f * nz + D * dn * dz);
+            txx -= mj * (f + D * dx * dx);
+            tyy -= mj * (f + D * dy * dy);
+            tzz -= mj * (f + D * dz * dz);
+            txy -= mj * (D * dx * dy);
+            txz -= mj * (D * dx * dz);
+            tyz -= mj * (D * dy * dz);
+        }
+        acc[3 * k] = G * ax; acc[3 * k + 1] = G * ay; acc[3 * k + 2] = G * az;
+        jerk[3 * k] = G * jx; jerk[3 * k + 1] = G * jy; jerk[3 * k + 2] = G * jz;
+        tidal[6 * k] = G * txx; tidal[6 * k + 1] = G * tyy; tidal[6 * k + 2] = G * tzz;
+        tidal[6 * k + 3] = G * txy; tidal[6 * k + 4] = G * txz; tidal[6 * k + 5] = G * tyz;
+    }
+}
+
+/* Direct sum at the particles listed in tgt (self excluded); outputs have
+ * ntgt rows in the order of tgt. */
+void orc_direct(int64_t n, const double *x, const double *v, const double *m,
+                double eps, double G, int64_t ntgt, const int64_t *tgt,
+                double *acc, double *jerk, double *tidal)
+{
+    double *p = (double *)malloc(sizeof(double) * 3 * (size_t)(ntgt > 0 ? ntgt : 1));
+    double *q = (double *)malloc(sizeof(double) * 3 * (size_t)(ntgt > 0 ? ntgt : 1));
+    for (int64_t k = 0; k < ntgt; ++k)
+        for (int c = 0; c < 3; ++c) {
+            p[3 * k + c] = x[3 * tgt[k] + c];
+            q[3 * k + c] = v[3 * tgt[k] + c];
+        }
+    orc_field(n, x, v, m, eps, G, ntgt, p, q, tgt, acc, jerk, tidal);
+    free(p);
+    free(q);
+}
+
+/* Sum of |pair acceleration terms| G sum_j m_j |f d|, the scale against which
+ * the FP64 direct sum's cancellation error is normalised. */
+void orc_abs_scale(int64_t n, const double *x, const double *m, double eps, double G,
+                   int64_t ntgt, const int64_t *tgt, double *scale)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < ntgt; ++k) {
+        int64_t i = tgt[k];
+        double s = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[3 * j] - x[3 * i], dy = x[3 * j + 1] - x[3 * i + 1],
+                   dz = x[3 * j + 2] - x[3 * i + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double f, D;
+            kernel_fd(r, eps, &f, &D);
+            s += m[j] * f * r;
+        }
+        scale[k] = G * s;
+    }
+}
+
+/* ---- tidal timestep (Eq. 7) and block bin --------------------------------- */
+/*
+ * dt_grav = sqrt(eta) * (|T|_F^2 / 6)^(-1/4),
+ * |T|_F^2 = Txx^2 + Tyy^2 + Tzz^2 + 2 (Txy^2 + Txz^2 + Tyz^2).
+ * Bin: the smallest k >= 0 with dt_max 2^-k <= dt_grav, clamped to k_max;
+ * |T| = 0 gives k = 0 (dt_max).  The bin is decided on the exactly defined
+ * ratio Q = (dt_max/dt_grav)^4 = |T|^2 dt_max^4 / (6 eta^2), evaluated as
+ *     a = dt_max*dt_max; b = a*a; e2 = eta*eta; Q = (n2*b)/(6*e2)
+ * with each operation rounded once (no fused multiply-add), and
+ * dt_max 2^-k <= dt_grav  <=>  Q <= 2^(4k).
+ * Non-finite Q (a non-finite tensor) is put in bin k_max.
+ */
+static int bin_of(double n2, double eta, double dt_max, int k_max)
+{
+    double a = dt_max * dt_max;
+    double b = a * a;
+    double e2 = eta * eta;
+    double den = 6.0 * e2;
+    double num = n2 * b;
+    double Q = num / den;
+    if (!(Q == Q) || Q > 1.7976931348623157e308) return k_max;
+    if (Q <= 0.0) return 0;
+    int e;
+    double fr = frexp(Q, &e);            /* Q = fr 2^e, fr in [1/2, 1) */
+    int mexp = (fr == 0.5) ? e - 1 : e;  /* smallest integer m with Q <= 2^m */
+    int k = mexp <= 0 ? 0 : (mexp + 3) / 4;
+    if (k > k_max) k = k_max;
+    return k;
+}
+
+void orc_timestep(int64_t n, const double *tidal, double eta, double dt_max, int32_t k_max,
+                  double *dt_grav, int8_t *bin)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const double *t = tidal + 6 * i;
+        double d2 = t[0] * t[0] + t[1] * t[1];
+        d2 = d2 + t[2] * t[2];
+        double o2 = t[3] * t[3] + t[4] * t[4];
+        o2 = o2 + t[5] * t[5];
+        double n2 = d2 + 2.0 * o2;
+        dt_grav[i] = (n2 > 0.0) ? sqrt(eta) * pow(n2 / 6.0, -0.25) : INFINITY;
+        bin[i] = (int8_t)bin_of(n2, eta, dt_max, k_max);
+    }
+}
+
+/* ---- force-age bookkeeping (Eq. 3, Eq. 4) -------------------------------- */
+/*
+ * Integer time: one tick is the step of bin `tick_bin`, so bin k spans
+ * 2^(tick_bin - min(k, tick_bin)) ticks.  At the start of a step, for every
+ * particle: T_f += step_ticks (Eq. 3); it is due iff T_f >= q_f dt_bin
+ * (Eq. 4, inclusive); a due particle gets T_f = 0.  active[i] is set to 1 for
+ * due particles and 0 otherwise; returns the number due.
+ */
+int64_t orc_select(int64_t n, int64_t *tf, const int8_t *bin, int64_t step_ticks,
+                   int32_t tick_bin, double q_f, uint8_t *active)
+{
+    int64_t count = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int k = bin[i];
+        if (k > tick_bin) k = tick_bin;
+        if (k < 0) k = 0;
+        int64_t span = (int64_t)1 << (tick_bin - k);
+        tf[i] += step_ticks;
+        double thresh = q_f * (double)span;
+        if ((double)tf[i] >= thresh) {
+            active[i] = 1;
+            tf[i] = 0;
+            ++count;
+        } else {
+            active[i] = 0;
+        }
+    }
+    return count;
+}
+
+/* ---- jerk predictor (Eq. 6), closed form ----------------------------------- */
+/* acc = a0 + j (t - t0), row by row; each operation rounded once. */
+void orc_predict(int64_t n, const double *a0, const double *jerk, const double *t0, double t,
+                 double *acc)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double dt = t - t0[i];
+        for (int c = 0; c < 3; ++c) {
+            double jd = jerk[3 * i + c] * dt;
+            acc[3 * i + c] = a0[3 * i + c] + jd;
+        }
+    }
+}
+
+/* ---- adjoint of L = sum_i w_i . a_i ----------------------------------------- */
+/*
+ * For each listed particle k:
+ *   dL/dx_k = G m_k sum_{j != k} J(d_kj) w_j  +  T_k w_k,
+ *   dL/dm_k = -G sum_{j != k} f(r_kj) d_kj . w_j,
+ * with d_kj = x_j - x_k, J = f I + D d d^T, and T_k the tidal tensor at k.
+ * Derivation: a_i depends on x_k through the pair (i, k) twice -- as the
+ * target (i = k, giving T_k w_k) and as a source (j = k, giving
+ * G m_k J(x_k - x_i) w_i, and J is even in d).
+ */
+void orc_adjoint(int64_t n, const double *x, const double *m, const double *w,
+                 double eps, double G, int64_t nk, const int64_t *kidx,
+                 double *dldx, double *dldm)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < nk; ++t) {
+        int64_t k = kidx[t];
+        double vx = 0, vy = 0, vz = 0, s = 0;
+        double txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == k) continue;
+            double dx = x[3 * j] - x[3 * k], dy = x[3 * j + 1] - x[3 * k + 1],
+                   dz = x[3 * j + 2] - x[3 * k + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double f, D;
+            kernel_fd(r, eps, &f, &D);
+            double wx = w[3 * j], wy = w[3 * j + 1], wz = w[3 * j + 2];
+            double dw = dx * wx + dy * wy + dz * wz;
+            vx += f * wx + D * dw * dx;
+            vy += f * wy + D * dw * dy;
+            vz += f * wz + D * dw * dz;
+            s += f * dw;
+            double mj = m[j];
+            txx -= mj * (f + D * dx * dx);
+            tyy -= mj * (f + D * dy * dy);
+            tzz -= mj * (f + D * dz * dz);
+            txy -= mj * (D * dx * dy);
+            txz -= mj * (D * dx * dz);
+            tyz -= mj * (D * dy * dz);
+        }
+        double wkx = w[3 * k], wky = w[3 * k + 1], wkz = w[3 * k + 2];
+        double twx = G * (txx * wkx + txy * wky + txz * wkz);
+        double twy = G * (txy * wkx + tyy * wky + tyz * wkz);
+        double twz = G * (txz * wkx + tyz * wky + tzz * wkz);
+        dldx[3 * t] = G * m[k] * vx + twx;
+        dldx[3 * t + 1] = G * m[k] * vy + twy;
+        dldx[3 * t + 2] = G * m[k] * vz + twz;
+        dldm[t] = -G * s;
+    }
+}
+
+/* ---- node multipoles ------------------------------------------------------- */
+/*
+ * For the particles idx[0..cnt):  out[0] = M,  out[1..3] = centre of mass c,
+ * out[4..6] = mass-weighted mean velocity u,
+ * out[7..12]  = Q    = sum m (3 y y^T - |y|^2 I),              y = x - c,
+ * out[13..18] = Qdot = sum m (3 (y w^T + w y^T) - 2 (y.w) I),  w = v - u,
+ * (tensors in xx yy zz xy xz yz order), out[19..24] = AABB min xyz, max xyz.
+ */
+void orc_moments(int64_t cnt, const int64_t *idx, const double *x, const double *v,
+                 const double *m, double *out)
+{
+    double M = 0, cx = 0, cy = 0, cz = 0, ux = 0, uy = 0, uz = 0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t t = 0; t < cnt; ++t) {
+        int64_t i = idx[t];
+        M += m[i];
+        cx += m[i] * x[3 * i]; cy += m[i] * x[3 * i + 1]; cz += m[i] * x[3 * i + 2];
+        ux += m[i] * v[3 * i]; uy += m[i] * v[3 * i + 1]; uz += m[i] * v[3 * i + 2];
+        for (int c = 0; c < 3; ++c) {
+            if (x[3 * i + c] < lo[c]) lo[c] = x[3 * i + c];
+            if (x[3 * i + c] > hi[c]) hi[c] = x[3 * i + c];
+        }
+    }
+    cx /= M; cy /= M; cz /= M; ux /= M; uy /= M; uz /= M;
+    double q[6] = {0}, qd[6] = {0};
+    for (int64_t t = 0; t < cnt; ++t) {
+        int64_t i = idx[t];
+        double y[3] = {x[3 * i] - cx, x[3 * i + 1] - cy, x[3 * i + 2] - cz};
+        double w[3] = {v[3 * i] - ux, v[3 * i + 1] - uy, v[3 * i + 2] - uz};
+        double y2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+        double yw = y[0] * w[0] + y[1] * w[1] + y[2] * w[2];
+        const int a[6] = {0, 1, 2, 0, 0, 1}, b[6] = {0, 1, 2, 1, 2, 2};
+        for (int c = 0; c < 6; ++c) {
+            double del = (a[c] == b[c]) ? 1.0 : 0.0;
+            q[c] += m[i] * (3.0 * y[a[c]] * y[b[c]] - y2 * del);
+            qd[c] += m[i] * (3.0 * (y[a[c]] * w[b[c]] + w[a[c]] * y[b[c]]) - 2.0 * yw * del);
+        }
+    }
+    out[0] = M;
+    out[1] = cx; out[2] = cy; out[3] = cz;
+    out[4] = ux; out[5] = uy; out[6] = uz;
+    for (int c = 0; c < 6; ++c) { out[7 + c] = q[c]; out[13 + c] = qd[c]; }
+    for (int c = 0; c < 3; ++c) { out[19 + c] = lo[c]; out[22 + c] = hi[c]; }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
