@@ -1,0 +1,235 @@
+/*
+ * adaptgrav.h -- C ABI of the MI355X (gfx950) gravity library for adaptive
+ * force updates (Grudic 2020, "Accelerating self-gravitating hydrodynamics
+ * simulations with adaptive force updates").
+ *
+ * The library evaluates softened self-gravity -- acceleration g, its time
+ * derivative (jerk) j and the tidal tensor T -- for a chosen subset of
+ * particles, by direct summation or with a Barnes-Hut oct-tree, and provides
+ * the bookkeeping the paper builds around the solver: the tidal timestep
+ * (Eq. 7), the force-age counter and update test (Eq. 3, Eq. 4) and the jerk
+ * predictor (Eq. 6).  Every step runs in hand-written HIP kernels.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Units: the caller passes G; positions, velocities and masses are in any
+ *    consistent units.
+ *  - Arrays are caller-owned DEVICE memory (hipMalloc or a torch CUDA/HIP
+ *    tensor) unless a parameter says "host".  Layouts are row-major:
+ *    vectors are (n, 3) doubles (x0 y0 z0 x1 ...), symmetric tensors are
+ *    (n, 6) doubles in xx yy zz xy xz yz order, scalars are (n,).
+ *  - Index lists (active_idx) are int32 row numbers in [0, n), unique, in any
+ *    order.
+ *  - Calls are asynchronous and ordered on the context's stream; input
+ *    arrays must stay valid and unchanged until the stream reaches the call.
+ *    The library never frees or keeps caller pointers.
+ *  - Return value: AG_OK or a negative error code; ag_last_error() gives a
+ *    message (per thread).  A failing call leaves the context usable.
+ *    Invalid device-resident data (indices out of range or repeated,
+ *    non-finite positions) cannot be seen by the host without a wait: kernels
+ *    skip such entries and raise a device flag that the next ag_sync() or
+ *    ag_stats_read() reports as AG_EDEVICE or AG_ENONFINITE.
+ *  - A context is bound to one device and one stream and is not
+ *    thread-safe; use one context per host thread.
+ *
+ * Softening: cubic-spline (M4) kernel of compact support h = eps; pairs
+ * closer than eps feel the kernel-smoothed force, beyond it Newton's.  The
+ * self pair is excluded.
+ */
+#ifndef ADAPTGRAV_H
+#define ADAPTGRAV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ag_ctx ag_ctx;
+
+enum {
+    AG_OK = 0,
+    AG_EINVAL = -1,      /* bad argument (n <= 0, eps <= 0, theta < 0, null pointer ...) */
+    AG_ENOMEM = -2,      /* device allocation failed */
+    AG_EHIP = -3,        /* HIP runtime error; message in ag_last_error() */
+    AG_ESTATE = -4,      /* call out of order (eval before build, size mismatch) */
+    AG_ENONFINITE = -5,  /* a position was NaN or Inf in the last tree build */
+    AG_EDEVICE = -6      /* an index list held an out-of-range or repeated entry */
+};
+
+enum { AG_FP64 = 0, AG_FP32_PAIRS = 1 };
+
+/* Counters accumulated on the device since the last ag_stats_reset(). */
+typedef struct ag_stats {
+    uint64_t n_pp;       /* particle-particle interactions evaluated          */
+    uint64_t n_pn;       /* particle-node (multipole) interactions evaluated  */
+    uint64_t n_targets;  /* force evaluations: targets given fresh g, j, T    */
+    int64_t  n_nodes;    /* nodes of the current tree                          */
+    int32_t  n_leaf;     /* leaf capacity of the current tree                  */
+    int32_t  max_level;  /* deepest tree level in use                          */
+} ag_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, bound to the HIP stream `stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+int ag_create(ag_ctx **out, int device, void *stream);
+/* Release the context and all library-owned device memory (waits for the
+ * stream first).  NULL is accepted. */
+int ag_destroy(ag_ctx *ctx);
+/* Rebind the context to another stream of the same device. */
+int ag_set_stream(ag_ctx *ctx, void *stream);
+/* Wait for the stream; return AG_OK or the first device-side error raised
+ * since the last check (the flag is then cleared). */
+int ag_sync(ag_ctx *ctx);
+/* Synchronising read of the counters (also reports device errors as ag_sync). */
+int ag_stats_read(ag_ctx *ctx, ag_stats *out);
+int ag_stats_reset(ag_ctx *ctx);
+/* Message for the last failing call on this host thread. */
+const char *ag_last_error(void);
+
+/* Per-phase GPU timing.  While enabled, every library call records HIP
+ * events on the context's stream around each phase it launches; the
+ * accumulated milliseconds per phase (and launch counts) are returned by the
+ * synchronising ag_timing_read, which also resets them when reset != 0.
+ * Phases, in array order: AG_PHASE_BUILD (keys, sort, topology, moments),
+ * AG_PHASE_GROUPS (active rows -> walk groups), AG_PHASE_WALK (forward
+ * walk kernel only), AG_PHASE_DIRECT, AG_PHASE_STEP (timestep, select,
+ * predict), AG_PHASE_ADJOINT (adjoint walk kernel only). */
+enum { AG_PHASE_BUILD = 0, AG_PHASE_GROUPS, AG_PHASE_WALK, AG_PHASE_DIRECT, AG_PHASE_STEP,
+       AG_PHASE_ADJOINT, AG_NPHASE };
+int ag_timing_enable(ag_ctx *ctx, int enable);
+int ag_timing_read(ag_ctx *ctx, double *ms /* [AG_NPHASE] */, int64_t *launches /* [AG_NPHASE], nullable */,
+                   int reset);
+
+/* ---- oct-tree (Sec. 3: Barnes-Hut tree code) ---------------------------- */
+
+/* Build the oct-tree over all n particles.  x, v: (n,3); m: (n,).
+ * Particles are ordered along a 63-bit Morton curve (21 bits per axis) of
+ * the bounding cube; a cell is split while it holds more than n_leaf
+ * particles (1 <= n_leaf <= 64), down to level 21.  Each node stores FP64
+ * mass, centre of mass, mean velocity, traceless quadrupole
+ * Q = sum m (3 y y^T - |y|^2 I) and its rate, and its bounding box.
+ * The tree, and sorted copies of x, v, m, belong to the context and stay
+ * valid until the next build or refit; the caller's arrays are not kept. */
+int ag_tree_build(ag_ctx *ctx, int64_t n, const double *x, const double *v, const double *m,
+                  int32_t n_leaf);
+
+/* One build over n_sys independent systems stored back to back:
+ * sys_offsets is a DEVICE int64 array of n_sys + 1 non-decreasing row
+ * offsets (sys_offsets[0] = 0, sys_offsets[n_sys] = n).  Systems never
+ * interact.  1 <= n_sys <= 512. */
+int ag_tree_build_batched(ag_ctx *ctx, int64_t n, const double *x, const double *v,
+                          const double *m, int32_t n_sys, const int64_t *sys_offsets,
+                          int32_t n_leaf);
+
+/* Recompute every node's moments and bounding box from new x, v, m of the
+ * same n particles, keeping the topology of the last build (the opening
+ * test uses the refitted boxes, so the result stays a valid tree walk). */
+int ag_tree_refit(ag_ctx *ctx, const double *x, const double *v, const double *m);
+
+/* Synchronising query of the current tree: number of nodes and deepest level. */
+int ag_tree_info(ag_ctx *ctx, int64_t *n_nodes, int32_t *max_level);
+
+/* Copy the current tree into caller DEVICE buffers (inspection and tests).
+ * Nodes are in depth-first pre-order (a node's first child is the next node).
+ *   link    (n_nodes, 4) int32: skip (first node after the subtree), first
+ *           sorted position, particle count, level | 0x100 for leaves
+ *   moments (n_nodes, 25) double: M, centre of mass (3), mean velocity (3),
+ *           Q (6), dQ/dt (6), box min (3), box max (3); tensors xx yy zz xy xz yz
+ *   perm    (n,) int32: input row of each sorted position
+ * Any pointer may be NULL; cap is the row capacity of link and moments
+ * (AG_EINVAL if smaller than n_nodes). */
+int ag_tree_export(ag_ctx *ctx, int64_t cap, int32_t *link, double *moments, int32_t *perm);
+
+/* ---- gravity evaluation ------------------------------------------------- */
+
+/* Tree gravity at the particles listed in active_idx (n_active entries;
+ * NULL = all n particles, in which case n_active must equal n).
+ * Writes rows active_idx[k] of acc (n,3), jerk (n,3), tidal (n,6); all other
+ * rows are left untouched.  Any of the three outputs may be NULL to skip it.
+ *
+ * acc   g_i = G sum_j m_j f(r) d_ij            (d_ij = x_j - x_i)
+ * jerk  j_i = dg_i/dt, the particle form of the paper's jerk integral (Eq. 5)
+ * tidal T_i = grad g at x_i, whose Frobenius norm sets the tidal timestep (Eq. 7)
+ *
+ * Opening test (Sec. 3, geometric Barnes-Hut criterion): a node of extent L
+ * (longest side of its bounding box) is used as a multipole for a group of
+ * up to 64 targets only if L <= theta * r for every point of the group's
+ * bounding box, r measured to the node's centre of mass, and the node's box
+ * lies at least eps from the group's box.  Accepted nodes act through their
+ * monopole and quadrupole (acceleration and tide) and through the mean
+ * velocity plus the quadrupole rate (jerk); opened leaves act pairwise.
+ * theta = 0 opens every node: direct summation.  Pair terms run in FP32 on
+ * coordinates relative to the group centre, accumulated in FP64.
+ * The tree must have been built (or refitted) on this context. */
+int ag_grav_eval(ag_ctx *ctx, const int32_t *active_idx, int64_t n_active, double theta,
+                 double eps, double G, double *acc, double *jerk, double *tidal);
+
+/* Batched variant after ag_tree_build_batched: active_idx lists global rows;
+ * each target only feels its own system. */
+int ag_grav_eval_batched(ag_ctx *ctx, const int32_t *active_idx, int64_t n_active,
+                         double theta, double eps, double G, double *acc, double *jerk,
+                         double *tidal);
+
+/* Direct summation over all n sources (no tree needed) at the rows listed in
+ * active_idx (NULL = all).  precision = AG_FP64: every operation in FP64;
+ * AG_FP32_PAIRS: pair terms in FP32 on relative coordinates, FP64 sums. */
+int ag_grav_direct(ag_ctx *ctx, int64_t n, const double *x, const double *v, const double *m,
+                   const int32_t *active_idx, int64_t n_active, double eps, double G,
+                   int precision, double *acc, double *jerk, double *tidal);
+
+/* ---- timestep, bookkeeping, predictor (Sec. 2, Sec. 3) ------------------- */
+
+/* Tidal timestep (Eq. 7) dt_grav = sqrt(eta) (|T|_F^2 / 6)^(-1/4) and its
+ * power-of-two bin: the smallest k >= 0 with dt_max 2^-k <= dt_grav, clamped
+ * to [0, k_max]; |T| = 0 gives dt_grav = +inf and k = 0; a non-finite T
+ * gives k = k_max.  The bin is decided exactly: with
+ *   n2 = (Txx^2 + Tyy^2 + Tzz^2) + 2 (Txy^2 + Txz^2 + Tyz^2),
+ *   Q  = (n2 * (dt_max^2)^2) / (6 eta^2)  [each operation rounded once],
+ * k is the least k with Q <= 16^k.  Rows processed: idx[0..n_idx) (device
+ * int32) or, with idx = NULL, all n rows.  tidal (n,6) in; dt_grav (n,)
+ * and bin (n,) int8 out (rows not processed are untouched). */
+int ag_grav_timestep(ag_ctx *ctx, int64_t n, const int32_t *idx, int64_t n_idx,
+                     const double *tidal, double eta, double dt_max, int32_t k_max,
+                     double *dt_grav, int8_t *bin);
+
+/* Force-age bookkeeping (Eq. 3, Eq. 4) for all n particles at the start of
+ * a step.  Time is integer: one tick is the step of bin tick_bin, so bin k
+ * spans 2^(tick_bin - min(k, tick_bin)) ticks.  For each particle:
+ *   tf += step_ticks;  due iff tf >= q_f * span (Eq. 4, inclusive);
+ *   a due particle gets tf = 0 (it is re-evaluated now).
+ * tf_ticks (n,) int64 is updated in place; the due rows are written in
+ * ascending order to active_idx (capacity n) and their number to the DEVICE
+ * int64 *n_active_dev.  q_f = 0 marks every particle due. */
+int ag_adaptive_select(ag_ctx *ctx, int64_t n, int64_t *tf_ticks, const int8_t *bin,
+                       int64_t step_ticks, int32_t tick_bin, double q_f,
+                       int32_t *active_idx, int64_t *n_active_dev);
+
+/* Jerk predictor (Eq. 6) in closed form: acc_out_i = acc0_i + jerk_i (t - t0_i)
+ * with t - t0 and the product and sum each rounded once (no fused
+ * multiply-add).  Equal to repeated application of Eq. 6 in exact arithmetic,
+ * since the jerk only changes at a force update.  Rows with mask[i] == 0 are
+ * left untouched (mask may be NULL = all rows).  acc_out may alias acc0. */
+int ag_grav_predict(ag_ctx *ctx, int64_t n, const uint8_t *mask, const double *acc0,
+                    const double *jerk, const double *t0, double t, double *acc_out);
+
+/* ---- adjoint -------------------------------------------------------------- */
+
+/* Gradient of L = sum_k w_k . g_k over the listed rows (w is (n,3), read at
+ * rows active_idx only) with respect to every particle's position and mass,
+ * using the current tree (rebuild it if positions changed):
+ *   dL/dx_k = G m_k sum_j J(d_kj) w_j + T_k w_k,   J = f I + D d d^T,
+ *   dL/dm_k = -G sum_j f(r_kj) d_kj . w_j,         D = f'(r)/r,
+ * with j running over the listed rows.  The sums are evaluated by a second
+ * tree walk over the vector charges w (their sum and first moment per node,
+ * under the same opening test); T_k comes from a fresh forward walk.
+ * dLdx (n,3) and dLdm (n,) are overwritten for all n rows. */
+int ag_grav_backward(ag_ctx *ctx, const int32_t *active_idx, int64_t n_active,
+                     const double *w, double theta, double eps, double G,
+                     double *dLdx, double *dLdm);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADAPTGRAV_H */

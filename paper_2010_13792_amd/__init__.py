@@ -1,0 +1,266 @@
+"""Python binding of ``libadaptgrav.so`` (the C ABI in ``include/adaptgrav.h``).
+
+Argument marshalling only: every method of :class:`Context` checks tensor
+device, dtype, shape and contiguity, then calls the C entry point of the same
+name (``ag_<name>``) with raw device pointers and the context's stream.  All
+computation happens in the library's HIP kernels; there is no fallback, and
+importing this module fails if the library has not been built.
+
+PyTorch supplies device memory and streams.  Arrays follow the C layouts:
+vectors ``(n, 3)`` float64, symmetric tensors ``(n, 6)`` float64 in
+xx yy zz xy xz yz order, index lists int32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime first, so the library binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadaptgrav.so")
+
+AG_OK = 0
+AG_EINVAL = -1
+AG_ENOMEM = -2
+AG_EHIP = -3
+AG_ESTATE = -4
+AG_ENONFINITE = -5
+AG_EDEVICE = -6
+AG_FP64 = 0
+AG_FP32_PAIRS = 1
+
+ENTRY_POINTS = [
+    "ag_create", "ag_destroy", "ag_set_stream", "ag_sync", "ag_stats_read", "ag_stats_reset",
+    "ag_last_error", "ag_tree_build", "ag_tree_build_batched", "ag_tree_refit", "ag_tree_info",
+    "ag_tree_export", "ag_grav_eval",
+    "ag_grav_eval_batched", "ag_grav_direct", "ag_grav_timestep", "ag_adaptive_select",
+    "ag_grav_predict", "ag_grav_backward",
+]
+
+
+class AgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"adaptgrav error {code}: {msg}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_pp", ctypes.c_uint64), ("n_pn", ctypes.c_uint64),
+                ("n_targets", ctypes.c_uint64), ("n_nodes", ctypes.c_int64),
+                ("n_leaf", ctypes.c_int32), ("max_level", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with __graft_entry__.build() "
+                          "or python -m paper_2010_13792_amd._build")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ag_create": [ctypes.POINTER(P), ctypes.c_int, P],
+        "ag_destroy": [P], "ag_set_stream": [P, P], "ag_sync": [P],
+        "ag_stats_read": [P, ctypes.POINTER(Stats)], "ag_stats_reset": [P],
+        "ag_tree_build": [P, I64, P, P, P, I32],
+        "ag_tree_build_batched": [P, I64, P, P, P, I32, P, I32],
+        "ag_tree_refit": [P, P, P, P],
+        "ag_tree_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I32)],
+        "ag_tree_export": [P, I64, P, P, P],
+        "ag_grav_eval": [P, P, I64, D, D, D, P, P, P],
+        "ag_grav_eval_batched": [P, P, I64, D, D, D, P, P, P],
+        "ag_grav_direct": [P, I64, P, P, P, P, I64, D, D, ctypes.c_int, P, P, P],
+        "ag_grav_timestep": [P, I64, P, I64, P, D, D, I32, P, P],
+        "ag_adaptive_select": [P, I64, P, P, I64, I32, D, P, P],
+        "ag_grav_predict": [P, I64, P, P, P, P, D, P],
+        "ag_grav_backward": [P, P, I64, P, D, D, D, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ag_last_error.argtypes = []
+    lib.ag_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != AG_OK:
+        raise AgError(code, _lib.ag_last_error().decode())
+
+
+def _ptr(t, dtype, shape_tail=None, name="array", n=None):
+    """Device pointer of a contiguous CUDA/HIP tensor after checking it."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape (n, {', '.join(map(str, shape_tail))})")
+    if n is not None and t.shape[0] < n:
+        raise ValueError(f"{name} has {t.shape[0]} rows, needs {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An ``ag_ctx``: one device, one stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        lib = load_library()
+        self.device = device
+        self._stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        _check(lib.ag_create(ctypes.byref(h), device, ctypes.c_void_p(self._stream.cuda_stream)))
+        self._h = h
+        self.n = None
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ag_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._stream = stream
+        _check(_lib.ag_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def sync(self):
+        _check(_lib.ag_sync(self._h))
+
+    def stats_read(self) -> dict:
+        s = Stats()
+        _check(_lib.ag_stats_read(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def stats_reset(self):
+        _check(_lib.ag_stats_reset(self._h))
+
+    # -- tree ---------------------------------------------------------------
+    def tree_build(self, x, v, m, n_leaf: int = 16):
+        n = x.shape[0]
+        _check(_lib.ag_tree_build(self._h, n, _ptr(x, torch.float64, (3,), "x"),
+                                  _ptr(v, torch.float64, (3,), "v", n),
+                                  _ptr(m, torch.float64, None, "m", n), int(n_leaf)))
+        self.n = n
+
+    def tree_build_batched(self, x, v, m, sys_offsets, n_leaf: int = 16):
+        n = x.shape[0]
+        n_sys = sys_offsets.shape[0] - 1
+        _check(_lib.ag_tree_build_batched(self._h, n, _ptr(x, torch.float64, (3,), "x"),
+                                          _ptr(v, torch.float64, (3,), "v", n),
+                                          _ptr(m, torch.float64, None, "m", n), int(n_sys),
+                                          _ptr(sys_offsets, torch.int64, None, "sys_offsets"),
+                                          int(n_leaf)))
+        self.n = n
+
+    def tree_refit(self, x, v, m):
+        _check(_lib.ag_tree_refit(self._h, _ptr(x, torch.float64, (3,), "x", self.n),
+                                  _ptr(v, torch.float64, (3,), "v", self.n),
+                                  _ptr(m, torch.float64, None, "m", self.n)))
+
+    def tree_info(self):
+        nn = ctypes.c_int64()
+        ml = ctypes.c_int32()
+        _check(_lib.ag_tree_info(self._h, ctypes.byref(nn), ctypes.byref(ml)))
+        return int(nn.value), int(ml.value)
+
+    def tree_export(self):
+        """Copy the tree to new device tensors: (link (nn,4) int32,
+        moments (nn,25) float64, perm (n,) int32)."""
+        nn, _ = self.tree_info()
+        dev = torch.device("cuda", self.device)
+        link = torch.empty((nn, 4), dtype=torch.int32, device=dev)
+        mom = torch.empty((nn, 25), dtype=torch.float64, device=dev)
+        perm = torch.empty((self.n,), dtype=torch.int32, device=dev)
+        _check(_lib.ag_tree_export(self._h, nn, _ptr(link, torch.int32, (4,), "link"),
+                                   _ptr(mom, torch.float64, (25,), "moments"),
+                                   _ptr(perm, torch.int32, None, "perm")))
+        self.sync()
+        return link, mom, perm
+
+    # -- gravity ------------------------------------------------------------
+    def grav_eval(self, active_idx, theta, eps, G, acc, jerk, tidal, batched=False):
+        n = self.n
+        k = n if active_idx is None else active_idx.shape[0]
+        fn = _lib.ag_grav_eval_batched if batched else _lib.ag_grav_eval
+        _check(fn(self._h, _ptr(active_idx, torch.int32, None, "active_idx"), k, float(theta),
+                  float(eps), float(G), _ptr(acc, torch.float64, (3,), "acc", n),
+                  _ptr(jerk, torch.float64, (3,), "jerk", n),
+                  _ptr(tidal, torch.float64, (6,), "tidal", n)))
+
+    def grav_eval_batched(self, active_idx, theta, eps, G, acc, jerk, tidal):
+        self.grav_eval(active_idx, theta, eps, G, acc, jerk, tidal, batched=True)
+
+    def grav_direct(self, x, v, m, active_idx, eps, G, acc, jerk, tidal, precision=AG_FP64):
+        n = x.shape[0]
+        k = n if active_idx is None else active_idx.shape[0]
+        _check(_lib.ag_grav_direct(self._h, n, _ptr(x, torch.float64, (3,), "x"),
+                                   _ptr(v, torch.float64, (3,), "v", n),
+                                   _ptr(m, torch.float64, None, "m", n),
+                                   _ptr(active_idx, torch.int32, None, "active_idx"), k,
+                                   float(eps), float(G), int(precision),
+                                   _ptr(acc, torch.float64, (3,), "acc", n),
+                                   _ptr(jerk, torch.float64, (3,), "jerk", n),
+                                   _ptr(tidal, torch.float64, (6,), "tidal", n)))
+
+    def grav_timestep(self, tidal, eta, dt_max, k_max, dt_grav, bins, idx=None):
+        n = tidal.shape[0]
+        k = n if idx is None else idx.shape[0]
+        _check(_lib.ag_grav_timestep(self._h, n, _ptr(idx, torch.int32, None, "idx"), k,
+                                     _ptr(tidal, torch.float64, (6,), "tidal"), float(eta),
+                                     float(dt_max), int(k_max),
+                                     _ptr(dt_grav, torch.float64, None, "dt_grav", n),
+                                     _ptr(bins, torch.int8, None, "bin", n)))
+
+    def adaptive_select(self, tf_ticks, bins, step_ticks, tick_bin, q_f, active_idx, n_active_dev):
+        n = tf_ticks.shape[0]
+        _check(_lib.ag_adaptive_select(self._h, n, _ptr(tf_ticks, torch.int64, None, "tf_ticks"),
+                                       _ptr(bins, torch.int8, None, "bin", n), int(step_ticks),
+                                       int(tick_bin), float(q_f),
+                                       _ptr(active_idx, torch.int32, None, "active_idx", n),
+                                       _ptr(n_active_dev, torch.int64, None, "n_active", 1)))
+
+    def grav_predict(self, acc0, jerk, t0, t, acc_out, mask=None):
+        n = acc0.shape[0]
+        _check(_lib.ag_grav_predict(self._h, n, _ptr(mask, torch.uint8, None, "mask", n),
+                                    _ptr(acc0, torch.float64, (3,), "acc0"),
+                                    _ptr(jerk, torch.float64, (3,), "jerk", n),
+                                    _ptr(t0, torch.float64, None, "t0", n), float(t),
+                                    _ptr(acc_out, torch.float64, (3,), "acc_out", n)))
+
+    def grav_backward(self, active_idx, w, theta, eps, G, dLdx, dLdm):
+        n = self.n
+        k = n if active_idx is None else active_idx.shape[0]
+        _check(_lib.ag_grav_backward(self._h, _ptr(active_idx, torch.int32, None, "active_idx"), k,
+                                     _ptr(w, torch.float64, (3,), "w", n), float(theta), float(eps),
+                                     float(G), _ptr(dLdx, torch.float64, (3,), "dLdx", n),
+                                     _ptr(dLdm, torch.float64, None, "dLdm", n)))
+
+
+from .autograd import GravEval, grav_eval  # noqa: E402,F401

@@ -1,0 +1,411 @@
+// ag_api.hip -- the C ABI entry points: argument validation, context and
+// buffer management, dispatch to the kernel launchers.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ag_internal.h"
+
+static thread_local char g_err[512] = "";
+
+int ag_fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+extern "C" const char* ag_last_error(void) { return g_err; }
+
+int ag_ensure(DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return AG_OK;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess) return ag_fail(AG_EHIP, "hipFree failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return ag_fail(AG_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    return AG_OK;
+}
+
+void ag_release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+static hipEvent_t take_event(Timing& t) {
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+PhaseScope::PhaseScope(ag_ctx* ctx, int ph) : c(ctx), phase(ph) {
+    if (!c->timing.on) return;
+    a = take_event(c->timing);
+    if (a) (void)hipEventRecord(a, c->stream);
+}
+
+PhaseScope::~PhaseScope() {
+    if (!a) return;
+    hipEvent_t b = take_event(c->timing);
+    if (!b) {
+        c->timing.pool.push_back(a);
+        return;
+    }
+    (void)hipEventRecord(b, c->stream);
+    c->timing.pending.push_back({phase, a, b});
+}
+
+extern "C" int ag_timing_enable(ag_ctx* c, int enable) {
+    if (!c) return ag_fail(AG_EINVAL, "null context");
+    c->timing.on = enable != 0;
+    return AG_OK;
+}
+
+extern "C" int ag_timing_read(ag_ctx* c, double* ms, int64_t* launches, int reset) {
+    if (!c) return ag_fail(AG_EINVAL, "null context");
+    if (!ms) return ag_fail(AG_EINVAL, "ms is null");
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != c->device) (void)hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) {
+        for (PhaseEvents& p : c->timing.pending) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+                c->timing.ms[p.phase] += t;
+                c->timing.launches[p.phase] += 1;
+            }
+            c->timing.pool.push_back(p.a);
+            c->timing.pool.push_back(p.b);
+        }
+        c->timing.pending.clear();
+    }
+    for (int k = 0; k < AG_NPHASE; ++k) {
+        ms[k] = c->timing.ms[k];
+        if (launches) launches[k] = c->timing.launches[k];
+        if (reset) {
+            c->timing.ms[k] = 0.0;
+            c->timing.launches[k] = 0;
+        }
+    }
+    if (prev >= 0 && prev != c->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return ag_fail(AG_EHIP, "stream synchronize failed: %s", hipGetErrorString(e));
+    return AG_OK;
+}
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int check_ctx(ag_ctx* c) {
+    if (!c) return ag_fail(AG_EINVAL, "null context");
+    return AG_OK;
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ag_fail(AG_EHIP, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
+    return AG_OK;
+}
+
+int read_flags(ag_ctx* c) {
+    int32_t f = 0;
+    AG_HIP(hipMemcpyAsync(&f, c->dflags.p, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    AG_HIP(hipStreamSynchronize(c->stream));
+    if (f) {
+        AG_HIP(hipMemsetAsync(c->dflags.p, 0, sizeof(int32_t), c->stream));
+        AG_HIP(hipStreamSynchronize(c->stream));
+        if (f & AGF_NONFINITE) return ag_fail(AG_ENONFINITE, "non-finite particle position in tree build");
+        return ag_fail(AG_EDEVICE, "index list held an out-of-range or repeated entry");
+    }
+    return AG_OK;
+}
+
+}  // namespace
+
+extern "C" int ag_create(ag_ctx** out, int device, void* stream) {
+    if (!out) return ag_fail(AG_EINVAL, "out is null");
+    *out = nullptr;
+    int ndev = 0;
+    AG_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return ag_fail(AG_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    ag_ctx* c = new (std::nothrow) ag_ctx();
+    if (!c) return ag_fail(AG_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    DeviceGuard g(device);
+    int r = ag_ensure(c->stats, 4 * sizeof(uint64_t));
+    if (r == AG_OK) r = ag_ensure(c->dflags, 4 * sizeof(int32_t));
+    if (r == AG_OK) r = ag_ensure(c->tree_hdr, 8 * sizeof(int64_t));
+    if (r != AG_OK) {
+        ag_destroy(c);
+        return r;
+    }
+    if (hipMemsetAsync(c->stats.p, 0, 4 * sizeof(uint64_t), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->dflags.p, 0, 4 * sizeof(int32_t), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        ag_destroy(c);
+        return ag_fail(AG_EHIP, "context initialisation failed");
+    }
+    *out = c;
+    return AG_OK;
+}
+
+extern "C" int ag_destroy(ag_ctx* c) {
+    if (!c) return AG_OK;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf* bufs[] = {&c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->sort_hist, &c->perm,
+                      &c->rank, &c->spos, &c->svel, &c->svf, &c->cdig, &c->pos_cnt, &c->pos_off,
+                      &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
+                      &c->nd_64, &c->nd_w, &c->nd_wf, &c->lvl_cnt, &c->lvl_nodes, &c->lvl_fill,
+                      &c->tree_hdr, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
+                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->sys_act, &c->wsorted,
+                      &c->direct_part, &c->tmp_tidal, &c->sel_flag, &c->sel_off, &c->stats, &c->dflags};
+    for (DevBuf* b : bufs) ag_release(*b);
+    for (PhaseEvents& p : c->timing.pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
+    delete c;
+    return AG_OK;
+}
+
+extern "C" int ag_set_stream(ag_ctx* c, void* stream) {
+    AG_TRY(check_ctx(c));
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    return AG_OK;
+}
+
+extern "C" int ag_sync(ag_ctx* c) {
+    AG_TRY(check_ctx(c));
+    DeviceGuard g(c->device);
+    AG_HIP(hipStreamSynchronize(c->stream));
+    return read_flags(c);
+}
+
+extern "C" int ag_stats_reset(ag_ctx* c) {
+    AG_TRY(check_ctx(c));
+    DeviceGuard g(c->device);
+    AG_HIP(hipMemsetAsync(c->stats.p, 0, 4 * sizeof(uint64_t), c->stream));
+    return AG_OK;
+}
+
+extern "C" int ag_stats_read(ag_ctx* c, ag_stats* out) {
+    AG_TRY(check_ctx(c));
+    if (!out) return ag_fail(AG_EINVAL, "out is null");
+    DeviceGuard g(c->device);
+    uint64_t s[4] = {0, 0, 0, 0};
+    int64_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    AG_HIP(hipMemcpyAsync(s, c->stats.p, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+    AG_HIP(hipMemcpyAsync(h, c->tree_hdr.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    AG_HIP(hipStreamSynchronize(c->stream));
+    out->n_pp = s[0];
+    out->n_pn = s[1];
+    out->n_targets = s[2];
+    out->n_nodes = c->built ? h[0] : 0;
+    out->n_leaf = c->built ? c->n_leaf : 0;
+    out->max_level = c->built ? (int32_t)h[1] : 0;
+    return read_flags(c);
+}
+
+// ---------------------------------------------------------------------------
+// tree
+// ---------------------------------------------------------------------------
+static int build_common(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                        int32_t n_sys, const int64_t* offs, int32_t n_leaf, bool batched) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive (got %lld)", (long long)n);
+    if (n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n = %lld exceeds 2^30", (long long)n);
+    if (!x || !v || !m) return ag_fail(AG_EINVAL, "x, v and m must be non-null");
+    if (n_leaf < 1 || n_leaf > 64) return ag_fail(AG_EINVAL, "n_leaf must be in [1, 64] (got %d)", n_leaf);
+    if (n_sys < 1 || n_sys > AG_MAX_SYS) return ag_fail(AG_EINVAL, "n_sys must be in [1, %d]", AG_MAX_SYS);
+    if (batched && !offs) return ag_fail(AG_EINVAL, "sys_offsets must be non-null");
+    DeviceGuard g(c->device);
+    c->built = false;
+    c->host_n_nodes = -1;
+    int r = ag_launch_build(c, n, x, v, m, n_sys, offs, n_leaf);
+    if (r != AG_OK) return r;
+    AG_TRY(check_launch("tree build"));
+    c->built = true;
+    c->batched = batched;
+    return AG_OK;
+}
+
+extern "C" int ag_tree_build(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                             int32_t n_leaf) {
+    return build_common(c, n, x, v, m, 1, nullptr, n_leaf, false);
+}
+
+extern "C" int ag_tree_build_batched(ag_ctx* c, int64_t n, const double* x, const double* v,
+                                     const double* m, int32_t n_sys, const int64_t* offs, int32_t n_leaf) {
+    return build_common(c, n, x, v, m, n_sys, offs, n_leaf, true);
+}
+
+extern "C" int ag_tree_refit(ag_ctx* c, const double* x, const double* v, const double* m) {
+    AG_TRY(check_ctx(c));
+    if (!c->built) return ag_fail(AG_ESTATE, "refit before a tree build");
+    if (!x || !v || !m) return ag_fail(AG_EINVAL, "x, v and m must be non-null");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_refit(c, x, v, m));
+    return check_launch("tree refit");
+}
+
+extern "C" int ag_tree_info(ag_ctx* c, int64_t* n_nodes, int32_t* max_level) {
+    AG_TRY(check_ctx(c));
+    if (!c->built) return ag_fail(AG_ESTATE, "no tree has been built");
+    DeviceGuard g(c->device);
+    int64_t h[8];
+    AG_HIP(hipMemcpyAsync(h, c->tree_hdr.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    AG_HIP(hipStreamSynchronize(c->stream));
+    c->host_n_nodes = h[0];
+    if (n_nodes) *n_nodes = h[0];
+    if (max_level) *max_level = (int32_t)h[1];
+    return read_flags(c);
+}
+
+extern "C" int ag_tree_export(ag_ctx* c, int64_t cap, int32_t* link, double* moments, int32_t* perm) {
+    int64_t nn = 0;
+    AG_TRY(ag_tree_info(c, &nn, nullptr));
+    if ((link || moments) && cap < nn) return ag_fail(AG_EINVAL, "cap %lld < n_nodes %lld", (long long)cap, (long long)nn);
+    DeviceGuard g(c->device);
+    if (link) AG_HIP(hipMemcpyAsync(link, c->nd_link.p, nn * 16, hipMemcpyDeviceToDevice, c->stream));
+    if (moments) AG_HIP(hipMemcpyAsync(moments, c->nd_64.p, nn * 25 * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (perm) AG_HIP(hipMemcpyAsync(perm, c->perm.p, c->n * 4, hipMemcpyDeviceToDevice, c->stream));
+    return AG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// evaluation
+// ---------------------------------------------------------------------------
+static int check_eval_args(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps,
+                           double G) {
+    AG_TRY(check_ctx(c));
+    if (!c->built) return ag_fail(AG_ESTATE, "gravity evaluation before a tree build");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return ag_fail(AG_EINVAL, "eps must be positive and finite");
+    if (!(theta >= 0.0) || !std::isfinite(theta)) return ag_fail(AG_EINVAL, "theta must be >= 0 and finite");
+    if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
+    if (n_act < 0 || n_act > c->n) return ag_fail(AG_EINVAL, "n_active out of range");
+    if (!idx && n_act != c->n) return ag_fail(AG_EINVAL, "active_idx = NULL requires n_active = n");
+    return AG_OK;
+}
+
+extern "C" int ag_grav_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps,
+                            double G, double* acc, double* jerk, double* tidal) {
+    AG_TRY(check_eval_args(c, idx, n_act, theta, eps, G));
+    if (c->batched) return ag_fail(AG_ESTATE, "tree was built batched: use ag_grav_eval_batched");
+    if (n_act == 0) return AG_OK;
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_eval(c, idx, n_act, theta, eps, G, acc, jerk, tidal));
+    return check_launch("grav eval");
+}
+
+extern "C" int ag_grav_eval_batched(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta,
+                                    double eps, double G, double* acc, double* jerk, double* tidal) {
+    AG_TRY(check_eval_args(c, idx, n_act, theta, eps, G));
+    if (!c->batched) return ag_fail(AG_ESTATE, "tree was not built batched: use ag_grav_eval");
+    if (n_act == 0) return AG_OK;
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_eval(c, idx, n_act, theta, eps, G, acc, jerk, tidal));
+    return check_launch("grav eval batched");
+}
+
+extern "C" int ag_grav_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                              const int32_t* idx, int64_t n_act, double eps, double G, int precision,
+                              double* acc, double* jerk, double* tidal) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n exceeds 2^30");
+    if (!x || !v || !m) return ag_fail(AG_EINVAL, "x, v and m must be non-null");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return ag_fail(AG_EINVAL, "eps must be positive and finite");
+    if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
+    if (precision != AG_FP64 && precision != AG_FP32_PAIRS) return ag_fail(AG_EINVAL, "unknown precision %d", precision);
+    if (n_act < 0 || n_act > n) return ag_fail(AG_EINVAL, "n_active out of range");
+    if (!idx && n_act != n) return ag_fail(AG_EINVAL, "active_idx = NULL requires n_active = n");
+    if (n_act == 0) return AG_OK;
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_direct(c, n, x, v, m, idx, n_act, eps, G, precision, acc, jerk, tidal));
+    return check_launch("grav direct");
+}
+
+extern "C" int ag_grav_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx,
+                                const double* tidal, double eta, double dt_max, int32_t k_max,
+                                double* dt, int8_t* bin) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (!tidal || !dt || !bin) return ag_fail(AG_EINVAL, "tidal, dt_grav and bin must be non-null");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return ag_fail(AG_EINVAL, "eta must be positive and finite");
+    if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return ag_fail(AG_EINVAL, "dt_max must be positive and finite");
+    if (k_max < 0 || k_max > 62) return ag_fail(AG_EINVAL, "k_max must be in [0, 62]");
+    if (idx && (n_idx < 0 || n_idx > n)) return ag_fail(AG_EINVAL, "n_idx out of range");
+    if (!idx) n_idx = n;
+    if (n_idx == 0) return AG_OK;
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_timestep(c, n, idx, n_idx, tidal, eta, dt_max, k_max, dt, bin));
+    return check_launch("grav timestep");
+}
+
+extern "C" int ag_adaptive_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin,
+                                  int64_t step_ticks, int32_t tick_bin, double q_f, int32_t* active_idx,
+                                  int64_t* n_active_dev) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n exceeds 2^30");
+    if (!tf || !bin || !active_idx || !n_active_dev) return ag_fail(AG_EINVAL, "null pointer argument");
+    if (step_ticks < 0) return ag_fail(AG_EINVAL, "step_ticks must be >= 0");
+    if (tick_bin < 0 || tick_bin > 52) return ag_fail(AG_EINVAL, "tick_bin must be in [0, 52]");
+    if (!(q_f >= 0.0) || !std::isfinite(q_f)) return ag_fail(AG_EINVAL, "q_f must be >= 0 and finite");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_select(c, n, tf, bin, step_ticks, tick_bin, q_f, active_idx, n_active_dev));
+    return check_launch("adaptive select");
+}
+
+extern "C" int ag_grav_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0,
+                               const double* j, const double* t0, double t, double* out) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (!a0 || !j || !t0 || !out) return ag_fail(AG_EINVAL, "null pointer argument");
+    if (!std::isfinite(t)) return ag_fail(AG_EINVAL, "t must be finite");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_predict(c, n, mask, a0, j, t0, t, out));
+    return check_launch("grav predict");
+}
+
+extern "C" int ag_grav_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w,
+                                double theta, double eps, double G, double* dLdx, double* dLdm) {
+    AG_TRY(check_eval_args(c, idx, n_act, theta, eps, G));
+    if (c->batched) return ag_fail(AG_ESTATE, "backward is not available for a batched tree");
+    if (!w || !dLdx || !dLdm) return ag_fail(AG_EINVAL, "w, dLdx and dLdm must be non-null");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_backward(c, idx, n_act, w, theta, eps, G, dLdx, dLdm));
+    return check_launch("grav backward");
+}

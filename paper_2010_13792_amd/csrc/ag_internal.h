@@ -1,0 +1,207 @@
+// ag_internal.h -- context layout and device helpers shared by the library's
+// translation units (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <vector>
+
+#include "adaptgrav.h"
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+int ag_fail(int code, const char* fmt, ...);
+
+#define AG_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return ag_fail(AG_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define AG_TRY(call)              \
+    do {                          \
+        int r_ = (call);          \
+        if (r_ != AG_OK) return r_; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffers owned by the context (grow-only)
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// device-side flag bits (ag_ctx::dflags)
+enum { AGF_BADINDEX = 1, AGF_NONFINITE = 2 };
+
+constexpr int AG_MAX_LEVEL = 21;   // Morton digits: 21 x 3 bits = 63-bit keys
+constexpr int AG_MAX_SYS = 512;    // batched systems: 3 octal digits of prefix
+constexpr int AG_GROUP = 64;       // targets per walk group = one wave64
+
+// per-phase event timing (enabled by ag_timing_enable)
+struct PhaseEvents {
+    int phase;
+    hipEvent_t a, b;
+};
+struct Timing {
+    bool on = false;
+    std::vector<PhaseEvents> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[AG_NPHASE] = {0};
+    int64_t launches[AG_NPHASE] = {0};
+};
+
+struct ag_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Timing timing;
+
+    // --- tree state ---
+    bool built = false;
+    bool batched = false;
+    int64_t n = 0;
+    int32_t n_leaf = 16;
+    int32_t n_sys = 1;
+    int32_t sys_levels = 0;  // octal digits taken by the system prefix
+    int64_t max_nodes = 0;
+
+    DevBuf keys[2], vals[2];      // radix-sort ping-pong (u64 keys, i32 values)
+    DevBuf sort_hist;             // per-block digit counts (u32)
+    DevBuf perm;                  // i32 [n]: sorted position -> input row
+    DevBuf rank;                  // i32 [n]: input row -> sorted position
+    DevBuf spos;                  // double4 [n]: sorted x, y, z, m
+    DevBuf svel;                  // double4 [n]: sorted vx, vy, vz, 0
+    DevBuf svf;                   // float4  [n]: sorted vx, vy, vz, m (FP32 copies)
+    DevBuf cdig;                  // i32 [n]: octal digits shared with the previous key
+    DevBuf pos_cnt, pos_off;      // i32 [n+1]: nodes starting at each position, offsets
+    DevBuf scan_tmp;              // scan block partials
+
+    // node arrays, depth-first (pre-order) numbering
+    DevBuf nd_com;                // double4: centre of mass x y z, extent L
+    DevBuf nd_lo, nd_hi;          // float4: bounding box (rounded outward)
+    DevBuf nd_link;               // int4: skip (next node after subtree), start, count, level|leafbit
+    DevBuf nd_mp;                 // float4 x4: M ux uy uz | Q xx yy zz xy | Q xz yz, Qd xx yy | Qd zz xy xz yz
+    DevBuf nd_64;                 // double [25]: FP64 moments (M, c, u, Q, Qd, lo, hi)
+    DevBuf nd_w;                  // double [12]: vector-charge moments W0 (3), W1 (9) for the adjoint
+    DevBuf nd_wf;                 // float4 x3: W0, W1 in FP32 for the adjoint walk
+    DevBuf lvl_cnt;               // i32 [AG_MAX_LEVEL + 2]
+    DevBuf lvl_nodes;             // i32 [max_nodes]: node ids bucketed by level
+    DevBuf lvl_fill;              // i32 [AG_MAX_LEVEL + 2]
+    DevBuf tree_hdr;              // i64 [8]: n_nodes, max_level, ...
+
+    DevBuf sys_off;               // i64 [n_sys+1]
+    DevBuf sys_root;              // i32 [n_sys]: root node per system
+    DevBuf sys_box;               // u64 [6 n_sys]: order-preserving encoded min/max
+
+    // --- evaluation scratch ---
+    DevBuf act_flag;              // i32 [n]
+    DevBuf act_pos;               // i32 [n]: active sorted positions, ascending
+    DevBuf act_off;               // i32 [n+1]: exclusive scan of act_flag
+    DevBuf grp;                   // int4 [max groups]: start, count, system, -
+    DevBuf grp_hdr;               // i32 [4 + n_sys + 1]
+    DevBuf sys_act;               // i32 [n_sys + 1]
+    DevBuf wsorted;               // double4 [n]: adjoint weights in sorted order
+    DevBuf direct_part;           // double: direct-sum source-split partials
+    DevBuf tmp_tidal;             // double [n*6]
+    DevBuf sel_flag;              // i32 [n]: due flags of the last select
+    DevBuf sel_off;               // i32 [n+1]: their exclusive scan
+
+    // --- counters and flags (device) ---
+    DevBuf stats;                 // u64 [4]: n_pp, n_pn, n_targets
+    DevBuf dflags;                // i32 [1]
+
+    int64_t host_n_nodes = -1;    // cached after a synchronising read
+};
+
+int ag_ensure(DevBuf& b, size_t bytes);
+void ag_release(DevBuf& b);
+
+// Records a start event on construction and a stop event on destruction on
+// the context's stream, when timing is enabled.
+struct PhaseScope {
+    ag_ctx* c;
+    int phase;
+    hipEvent_t a = nullptr;
+    PhaseScope(ag_ctx* ctx, int ph);
+    ~PhaseScope();
+};
+
+// ---------------------------------------------------------------------------
+// launchers implemented in the kernel translation units
+// ---------------------------------------------------------------------------
+int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                     const int32_t* idx, int64_t n_act, double eps, double G, int precision,
+                     double* acc, double* jerk, double* tidal);
+int ag_launch_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx,
+                       const double* tidal, double eta, double dt_max, int32_t k_max,
+                       double* dt, int8_t* bin);
+int ag_launch_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin, int64_t step_ticks,
+                     int32_t tick_bin, double q_f, int32_t* active_idx, int64_t* n_active_dev);
+int ag_launch_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0,
+                      const double* j, const double* t0, double t, double* out);
+int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                    int32_t n_sys, const int64_t* sys_offsets, int32_t n_leaf);
+int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m);
+int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps,
+                   double G, double* acc, double* jerk, double* tidal);
+int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w,
+                       double theta, double eps, double G, double* dLdx, double* dLdm);
+// exclusive scan of n int32 counts into out (n+1 entries; out[n] = total) on c->stream
+int ag_scan_i32(ag_ctx* c, const int32_t* in, int32_t* out, int64_t n);
+// active rows -> ascending sorted positions and walk groups; returns upper bound of groups
+int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max_groups);
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+#if defined(__HIPCC__)
+__device__ __forceinline__ int ag_lane() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// number of set bits of `mask` in lanes below this one
+__device__ __forceinline__ int ag_prefix_count(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <class T> __device__ __forceinline__ T ag_wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <class T> __device__ __forceinline__ T ag_wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { T w = __shfl_xor(v, o, 64); v = w < v ? w : v; }
+    return v;
+}
+template <class T> __device__ __forceinline__ T ag_wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { T w = __shfl_xor(v, o, 64); v = w > v ? w : v; }
+    return v;
+}
+// inclusive prefix sum over the wave
+__device__ __forceinline__ int ag_wave_incl_scan(int v) {
+    const int lane = ag_lane();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int w = __shfl_up(v, o, 64);
+        if (lane >= o) v += w;
+    }
+    return v;
+}
+
+// order-preserving map of doubles onto uint64 (for atomic min/max)
+__device__ __forceinline__ uint64_t ag_ord(double x) {
+    uint64_t b = __double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double ag_unord(uint64_t u) {
+    uint64_t b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+    return __longlong_as_double(b);
+}
+#endif

@@ -1,0 +1,674 @@
+// k_tree.hip -- oct-tree construction on the GPU.
+//
+// Pipeline (all on the context's stream, no host synchronisation):
+//   1. bounding cube of each system (order-preserving integer atomics, one
+//      atomic per workgroup and axis), non-finite detection;
+//   2. 63-bit Morton keys: 21 octal digits; with several systems the top
+//      digits hold the system number and the rest its own cube's Morton code;
+//   3. stable LSD radix sort of (key, row) pairs, 8 bits per pass;
+//   4. gather of x, v, m into key order (FP64 and FP32 copies);
+//   5. topology straight from the sorted keys: with c_p the number of octal
+//      digits key[p] shares with key[p-1], the cell of level l that contains
+//      position p starts at p iff c_p < l.  A cell is split while it holds
+//      more than n_leaf particles (and below level 21); system-prefix levels
+//      are always split.  Counting, per position, the cells that start there
+//      and exist in the tree, then an exclusive scan, numbers the nodes in
+//      depth-first pre-order: node (l, p) has id off[p] + l - c_p - 1, its
+//      first child is id + 1 and its "skip" link (next node outside its
+//      subtree) is off[e], e = the first position past the cell;
+//   6. moments level by level from the deepest: leaves from their particles,
+//      inner nodes from their children (parallel-axis shifts), in FP64.
+#include <float.h>
+
+#include "ag_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ float f_down(double d) {
+    float f = (float)d;
+    if ((double)f > d) f = nextafterf(f, -FLT_MAX);
+    return f;
+}
+__device__ __forceinline__ float f_up(double d) {
+    float f = (float)d;
+    if ((double)f < d) f = nextafterf(f, FLT_MAX);
+    return f;
+}
+
+__device__ __forceinline__ int sys_of(const int64_t* __restrict__ off, int n_sys, int64_t i) {
+    int lo = 0, hi = n_sys;   // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// 1. bounding cubes
+// ---------------------------------------------------------------------------
+constexpr int64_t kBoxChunk = 8192;
+
+__global__ void k_box_init(int n_sys, uint64_t* __restrict__ box, int32_t* __restrict__ blk_off,
+                           const int64_t* __restrict__ off) {
+    // one block: blk_off[s] = first box-workgroup of system s (exclusive scan)
+    __shared__ int s_sum[AG_MAX_SYS + 1];
+    for (int s = threadIdx.x; s < n_sys; s += blockDim.x) {
+        for (int c = 0; c < 3; ++c) {
+            box[6 * s + c] = ~0ull;        // min slots start at the top
+            box[6 * s + 3 + c] = 0ull;     // max slots at the bottom
+        }
+        int64_t sz = off[s + 1] - off[s];
+        s_sum[s] = (int)((sz + kBoxChunk - 1) / kBoxChunk);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int s = 0; s < n_sys; ++s) {
+            int v = s_sum[s];
+            blk_off[s] = acc;
+            acc += v;
+        }
+        blk_off[n_sys] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_box(const double* __restrict__ x, const int64_t* __restrict__ off,
+                                                  int n_sys, const int32_t* __restrict__ blk_off,
+                                                  uint64_t* __restrict__ box, int32_t* __restrict__ flags) {
+    __shared__ double s_red[6][kThreads / 64];
+    const int b = blockIdx.x;
+    if (b >= blk_off[n_sys]) return;
+    int lo = 0, hi = n_sys;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (blk_off[mid] <= b) lo = mid; else hi = mid;
+    }
+    const int s = lo;
+    const int64_t i0 = off[s] + (int64_t)(b - blk_off[s]) * kBoxChunk;
+    const int64_t i1 = i0 + kBoxChunk < off[s + 1] ? i0 + kBoxChunk : off[s + 1];
+    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    bool bad = false;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double q = x[3 * i + c];
+            if (!isfinite(q)) { bad = true; continue; }
+            mn[c] = q < mn[c] ? q : mn[c];
+            mx[c] = q > mx[c] ? q : mx[c];
+        }
+    }
+    if (bad) atomicOr(flags, AGF_NONFINITE);
+    const int lane = ag_lane(), w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double a = ag_wave_min(mn[c]), z = ag_wave_max(mx[c]);
+        if (lane == 0) { s_red[c][w] = a; s_red[3 + c][w] = z; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int c = threadIdx.x;
+        double r = s_red[c][0];
+        for (int k = 1; k < kThreads / 64; ++k)
+            r = c < 3 ? (s_red[c][k] < r ? s_red[c][k] : r) : (s_red[c][k] > r ? s_red[c][k] : r);
+        if (c < 3) atomicMin((unsigned long long*)&box[6 * s + c], (unsigned long long)ag_ord(r));
+        else atomicMax((unsigned long long*)&box[6 * s + c], (unsigned long long)ag_ord(r));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. Morton keys
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+    // spread the low 21 bits of v to every third bit
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ void k_keys(int64_t n, const double* __restrict__ x, const int64_t* __restrict__ off, int n_sys,
+                       int bits, const uint64_t* __restrict__ box, uint64_t* __restrict__ keys,
+                       int32_t* __restrict__ vals) {
+    const double scale_cells = (double)(1u << bits);
+    const int64_t maxc = ((int64_t)1 << bits) - 1;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int s = n_sys > 1 ? sys_of(off, n_sys, i) : 0;
+        double lo[3], ext = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = ag_unord(box[6 * s + c]);
+            double e = ag_unord(box[6 * s + 3 + c]) - lo[c];
+            ext = e > ext ? e : ext;
+        }
+        if (!(ext > 0.0) || !isfinite(ext)) ext = 1.0;
+        const double inv = scale_cells / (ext * (1.0 + 1e-12));
+        uint64_t code = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double q = (x[3 * i + c] - lo[c]) * inv;
+            int64_t k = isfinite(q) ? (int64_t)q : 0;
+            k = k < 0 ? 0 : (k > maxc ? maxc : k);
+            code |= spread3((uint64_t)k) << (2 - c);
+        }
+        keys[i] = ((uint64_t)s << (3 * bits)) | code;
+        vals[i] = (int32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. stable LSD radix sort, 8 bits per pass
+// ---------------------------------------------------------------------------
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kThreads * kRsItems;
+
+__global__ void __launch_bounds__(kThreads) k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                      int nblocks, int32_t* __restrict__ hist) {
+    __shared__ int s_h[4][256];
+    for (int w = 0; w < 4; ++w) s_h[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+        int64_t i = base + k * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&s_h[w][(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    int t = s_h[0][threadIdx.x] + s_h[1][threadIdx.x] + s_h[2][threadIdx.x] + s_h[3][threadIdx.x];
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                         const int32_t* __restrict__ vin, int64_t n,
+                                                         int shift, int nblocks,
+                                                         const int32_t* __restrict__ hoff,
+                                                         uint64_t* __restrict__ kout,
+                                                         int32_t* __restrict__ vout) {
+    __shared__ int s_goff[256];
+    __shared__ int s_run[256];
+    __shared__ int s_w[4][256];
+    s_goff[threadIdx.x] = hoff[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    s_run[threadIdx.x] = 0;
+    const int w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t i = base + k * kThreads + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t key = valid ? kin[i] : 0ull;
+        int32_t val = valid ? vin[i] : 0;
+        const int d = (int)((key >> shift) & 255);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const int r = ag_prefix_count(peers);
+        const int cnt = __popcll(peers);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_w[q][threadIdx.x] = 0;
+        __syncthreads();
+        if (valid && r == 0) s_w[w][d] = cnt;
+        __syncthreads();
+        {
+            const int t = threadIdx.x;
+            int run = s_run[t];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int c = s_w[q][t];
+                s_w[q][t] = run;
+                run += c;
+            }
+            s_run[t] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const int pos = s_goff[d] + s_w[w][d] + r;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. gather into key order
+// ---------------------------------------------------------------------------
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
+                         const double* __restrict__ v, const double* __restrict__ m,
+                         int32_t* __restrict__ rank, double4* __restrict__ spos,
+                         double4* __restrict__ svel, float4* __restrict__ svf) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = perm[p];
+        if (rank) rank[i] = (int32_t)p;
+        const double mi = m[i];
+        const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
+        spos[p] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], mi);
+        svel[p] = make_double4(vx, vy, vz, 0.0);
+        svf[p] = make_float4((float)vx, (float)vy, (float)vz, (float)mi);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 5. topology
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
+    const uint64_t d = a ^ b;
+    if (d == 0) return AG_MAX_LEVEL;
+    return (__clzll(d) - 1) / 3;   // bit 63 is always clear
+}
+
+__global__ void k_cdig(int64_t n, const uint64_t* __restrict__ keys, int32_t* __restrict__ cd) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        cd[p] = p == 0 ? -1 : common_digits(keys[p - 1], keys[p]);
+}
+
+struct TopoParams {
+    int64_t n;
+    int n_leaf;
+    int sys_levels;
+};
+
+__device__ __forceinline__ bool is_split(const TopoParams& P, int level, int64_t count_or_big) {
+    if (level < P.sys_levels) return true;
+    return level < AG_MAX_LEVEL && count_or_big > P.n_leaf;
+}
+
+// end of the level-l cell starting at p if it holds <= n_leaf particles,
+// else -1 (bounded forward scan of the shared-digit counts)
+__device__ __forceinline__ int64_t small_cell_end(const TopoParams& P, const int32_t* __restrict__ cd,
+                                                  int64_t p, int l) {
+    int64_t q = p + 1;
+    const int64_t lim = p + P.n_leaf;
+    while (q < P.n && q <= lim) {
+        if (cd[q] < l) return q;
+        ++q;
+    }
+    if (q >= P.n && P.n - p <= P.n_leaf) return P.n;
+    return -1;
+}
+
+// does the level-c cell containing p (which does not start at p) get split?
+__device__ __forceinline__ bool parent_split(const TopoParams& P, const int32_t* __restrict__ cd, int64_t p,
+                                             int c) {
+    if (c < P.sys_levels) return true;
+    if (c >= AG_MAX_LEVEL) return false;
+    int64_t a = p - 1;
+    int steps = 0;
+    while (cd[a] >= c) {       // cd[0] = -1 stops the scan
+        --a;
+        if (++steps > P.n_leaf) return true;
+    }
+    int64_t q = p + 1;
+    while (q < P.n && cd[q] >= c) {
+        ++q;
+        if (++steps > P.n_leaf) return true;
+    }
+    return (q - a) > P.n_leaf;
+}
+
+// number of tree nodes starting at position p
+__device__ __forceinline__ int nodes_at(const TopoParams& P, const int32_t* __restrict__ cd, int64_t p) {
+    const int c = cd[p];
+    if (p > 0 && (c >= AG_MAX_LEVEL || !parent_split(P, cd, p, c))) return 0;
+    int cnt = 0;
+    for (int l = c + 1; l <= AG_MAX_LEVEL; ++l) {
+        ++cnt;
+        const int64_t e = small_cell_end(P, cd, p, l);
+        const bool small = e >= 0;
+        if (!is_split(P, l, small ? 0 : P.n_leaf + 1)) break;
+    }
+    return cnt;
+}
+
+__global__ void k_count_nodes(TopoParams P, const int32_t* __restrict__ cd, int32_t* __restrict__ cnt) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        cnt[p] = nodes_at(P, cd, p);
+}
+
+// first position after p whose key differs from key[p] in the top l digits
+__device__ __forceinline__ int64_t cell_end(const TopoParams& P, const uint64_t* __restrict__ keys, int64_t p,
+                                            int l) {
+    if (l == 0) return P.n;
+    const int sh = 63 - 3 * l;
+    const uint64_t pre = keys[p] >> sh;
+    int64_t lo = p + 1, hi = P.n;   // answer in [lo, hi]
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((keys[mid] >> sh) == pre) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, const int32_t* __restrict__ cd,
+                              const int32_t* __restrict__ off, int4* __restrict__ link,
+                              int32_t* __restrict__ lvl_cnt, int64_t* __restrict__ hdr) {
+    const int64_t n_nodes = off[P.n];
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int k = off[p + 1] - off[p];
+        if (k == 0) continue;
+        const int c = cd[p];
+        int maxl = 0;
+        for (int t = 0; t < k; ++t) {
+            const int l = c + 1 + t;
+            const int64_t id = off[p] + t;
+            int64_t e = small_cell_end(P, cd, p, l);
+            const bool leaf = (t == k - 1);
+            if (e < 0) e = cell_end(P, keys, p, l);
+            const int64_t skip = e < P.n ? (int64_t)off[e] : n_nodes;
+            link[id] = make_int4((int)skip, (int)p, (int)(e - p), l | (leaf ? 0x100 : 0));
+            atomicAdd(&lvl_cnt[l], 1);
+            maxl = l;
+        }
+        atomicMax((unsigned long long*)&hdr[1], (unsigned long long)maxl);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) hdr[0] = n_nodes;
+}
+
+__global__ void k_level_offsets(int32_t* __restrict__ lvl_cnt, int32_t* __restrict__ lvl_fill) {
+    // lvl_cnt[0..21] counts -> lvl_cnt[22 + l] start offsets; lvl_fill zeroed
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int l = 0; l <= AG_MAX_LEVEL; ++l) {
+            lvl_cnt[AG_MAX_LEVEL + 1 + l] = acc;
+            acc += lvl_cnt[l];
+            lvl_fill[l] = 0;
+        }
+        lvl_cnt[2 * (AG_MAX_LEVEL + 1)] = acc;
+    }
+}
+
+__global__ void k_level_scatter(const int4* __restrict__ link, const int64_t* __restrict__ hdr,
+                                const int32_t* __restrict__ lvl_cnt, int32_t* __restrict__ lvl_fill,
+                                int32_t* __restrict__ lvl_nodes) {
+    const int64_t nn = hdr[0];
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < nn;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int l = link[id].w & 0xff;
+        const int slot = lvl_cnt[AG_MAX_LEVEL + 1 + l] + atomicAdd(&lvl_fill[l], 1);
+        lvl_nodes[slot] = (int32_t)id;
+    }
+}
+
+__global__ void k_sys_roots(int n_sys, int sys_levels, const int64_t* __restrict__ off,
+                            const int32_t* __restrict__ cd, const int32_t* __restrict__ noff,
+                            int32_t* __restrict__ root) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sys; s += gridDim.x * blockDim.x) {
+        const int64_t p0 = off[s];
+        if (off[s + 1] <= p0) { root[s] = -1; continue; }
+        root[s] = noff[p0] + (sys_levels - cd[p0] - 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 6. moments
+// ---------------------------------------------------------------------------
+// nd_64 layout per node (25 doubles): M, c(3), u(3), Q(6), Qd(6), lo(3), hi(3)
+constexpr int kM64 = 25;
+
+__device__ void store_node(int64_t id, const double* r, double4* __restrict__ com, float4* __restrict__ lo4,
+                           float4* __restrict__ hi4, float4* __restrict__ mp, double* __restrict__ m64) {
+    double* o = m64 + id * kM64;
+#pragma unroll
+    for (int k = 0; k < kM64; ++k) o[k] = r[k];
+    double L = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double e = r[22 + c] - r[19 + c];
+        L = e > L ? e : L;
+    }
+    com[id] = make_double4(r[1], r[2], r[3], L);
+    lo4[id] = make_float4(f_down(r[19]), f_down(r[20]), f_down(r[21]), 0.f);
+    hi4[id] = make_float4(f_up(r[22]), f_up(r[23]), f_up(r[24]), 0.f);
+    float4* q = mp + 4 * id;
+    q[0] = make_float4((float)r[0], (float)r[4], (float)r[5], (float)r[6]);
+    q[1] = make_float4((float)r[7], (float)r[8], (float)r[9], (float)r[10]);
+    q[2] = make_float4((float)r[11], (float)r[12], (float)r[13], (float)r[14]);
+    q[3] = make_float4((float)r[15], (float)r[16], (float)r[17], (float)r[18]);
+}
+
+// Q  += m (3 y y^T - |y|^2 I),  Qd += m (3 (y w^T + w y^T) - 2 (y.w) I)
+__device__ __forceinline__ void add_quad(double* Q, double* Qd, double mm, const double* y, const double* w) {
+    const double y2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    const double yw = y[0] * w[0] + y[1] * w[1] + y[2] * w[2];
+    const int a[6] = {0, 1, 2, 0, 0, 1}, b[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double del = k < 3 ? 1.0 : 0.0;
+        Q[k] += mm * (3.0 * y[a[k]] * y[b[k]] - y2 * del);
+        Qd[k] += mm * (3.0 * (y[a[k]] * w[b[k]] + w[a[k]] * y[b[k]]) - 2.0 * yw * del);
+    }
+}
+
+__global__ void k_moments_level(int level, const int32_t* __restrict__ lvl_cnt,
+                                const int32_t* __restrict__ lvl_nodes, const int4* __restrict__ link,
+                                const double4* __restrict__ spos, const double4* __restrict__ svel,
+                                double4* __restrict__ com, float4* __restrict__ lo4, float4* __restrict__ hi4,
+                                float4* __restrict__ mp, double* __restrict__ m64) {
+    const int cnt = lvl_cnt[level];
+    const int base = lvl_cnt[AG_MAX_LEVEL + 1 + level];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+        const int id = lvl_nodes[base + t];
+        const int4 L = link[id];
+        double r[kM64];
+#pragma unroll
+        for (int k = 0; k < kM64; ++k) r[k] = 0.0;
+        r[19] = r[20] = r[21] = DBL_MAX;
+        r[22] = r[23] = r[24] = -DBL_MAX;
+        if (L.w & 0x100) {   // leaf: from its particles
+            const int p0 = L.y, p1 = L.y + L.z;
+            for (int p = p0; p < p1; ++p) {
+                const double4 q = spos[p];
+                const double4 u = svel[p];
+                r[0] += q.w;
+                r[1] += q.w * q.x; r[2] += q.w * q.y; r[3] += q.w * q.z;
+                r[4] += q.w * u.x; r[5] += q.w * u.y; r[6] += q.w * u.z;
+                r[19] = fmin(r[19], q.x); r[20] = fmin(r[20], q.y); r[21] = fmin(r[21], q.z);
+                r[22] = fmax(r[22], q.x); r[23] = fmax(r[23], q.y); r[24] = fmax(r[24], q.z);
+            }
+            const double Mi = r[0] > 0.0 ? 1.0 / r[0] : 0.0;
+            for (int c = 1; c < 7; ++c) r[c] *= Mi;
+            if (!(r[0] > 0.0)) {   // massless cell: centre of its box
+                for (int c = 0; c < 3; ++c) r[1 + c] = 0.5 * (r[19 + c] + r[22 + c]);
+            }
+            for (int p = p0; p < p1; ++p) {
+                const double4 q = spos[p];
+                const double4 u = svel[p];
+                const double y[3] = {q.x - r[1], q.y - r[2], q.z - r[3]};
+                const double w[3] = {u.x - r[4], u.y - r[5], u.z - r[6]};
+                add_quad(r + 7, r + 13, q.w, y, w);
+            }
+        } else {             // inner node: from its children
+            const int end = L.x;
+            for (int ch = id + 1; ch < end; ch = link[ch].x) {
+                const double4 cc = com[ch];
+                const float4 q0 = mp[4 * ch];
+                const double Mc = m64[(int64_t)ch * kM64];
+                const double* cm = m64 + (int64_t)ch * kM64;
+                r[0] += Mc;
+                r[1] += Mc * cc.x; r[2] += Mc * cc.y; r[3] += Mc * cc.z;
+                r[4] += Mc * cm[4]; r[5] += Mc * cm[5]; r[6] += Mc * cm[6];
+                for (int c = 0; c < 3; ++c) {
+                    r[19 + c] = fmin(r[19 + c], cm[19 + c]);
+                    r[22 + c] = fmax(r[22 + c], cm[22 + c]);
+                }
+                (void)q0;
+            }
+            const double Mi = r[0] > 0.0 ? 1.0 / r[0] : 0.0;
+            for (int c = 1; c < 7; ++c) r[c] *= Mi;
+            if (!(r[0] > 0.0)) {
+                for (int c = 0; c < 3; ++c) r[1 + c] = 0.5 * (r[19 + c] + r[22 + c]);
+            }
+            for (int ch = id + 1; ch < end; ch = link[ch].x) {
+                const double* cm = m64 + (int64_t)ch * kM64;
+                const double y[3] = {cm[1] - r[1], cm[2] - r[2], cm[3] - r[3]};
+                const double w[3] = {cm[4] - r[4], cm[5] - r[5], cm[6] - r[6]};
+                for (int k = 0; k < 6; ++k) {
+                    r[7 + k] += cm[7 + k];
+                    r[13 + k] += cm[13 + k];
+                }
+                add_quad(r + 7, r + 13, cm[0], y, w);
+            }
+        }
+        store_node(id, r, com, lo4, hi4, mp, m64);
+    }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_i64(int64_t* __restrict__ p, int64_t n, int64_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_copy_offsets(int n_sys, int64_t n, const int64_t* __restrict__ in, int64_t* __restrict__ out,
+                               int32_t* __restrict__ flags) {
+    for (int s = threadIdx.x; s <= n_sys; s += blockDim.x) {
+        int64_t v = in ? in[s] : (s == 0 ? 0 : n);
+        if (in) {
+            const bool bad = (s == 0 && v != 0) || (s == n_sys && v != n) || v < 0 || v > n ||
+                             (s > 0 && in[s - 1] > v);
+            if (bad) atomicOr(flags, AGF_BADINDEX);
+        }
+        out[s] = v;
+    }
+}
+
+int grid_for(int64_t n, int threads = kThreads) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b > 8192) b = 8192;
+    return (int)(b < 1 ? 1 : b);
+}
+
+int moments_pass(ag_ctx* c) {
+    const int grid = grid_for(c->max_nodes);
+    for (int l = AG_MAX_LEVEL; l >= 0; --l) {
+        hipLaunchKernelGGL(k_moments_level, dim3(grid), dim3(kThreads), 0, c->stream, l, c->lvl_cnt.as<int32_t>(),
+                           c->lvl_nodes.as<int32_t>(), c->nd_link.as<int4>(), c->spos.as<double4>(),
+                           c->svel.as<double4>(), c->nd_com.as<double4>(), c->nd_lo.as<float4>(),
+                           c->nd_hi.as<float4>(), c->nd_mp.as<float4>(), c->nd_64.as<double>());
+    }
+    return AG_OK;
+}
+
+}  // namespace
+
+int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m, int32_t n_sys,
+                    const int64_t* sys_offsets, int32_t n_leaf) {
+    int sys_levels = 0;
+    if (sys_offsets) {
+        while ((1 << (3 * sys_levels)) < n_sys) ++sys_levels;
+        if (sys_levels < 1) sys_levels = 1;
+    }
+    const int bits = AG_MAX_LEVEL - sys_levels;
+    const int64_t max_nodes = n + (int64_t)(AG_MAX_LEVEL + 1) * (n / (n_leaf + 1) + n_sys) + 1;
+
+    AG_TRY(ag_ensure(c->keys[0], n * 8)); AG_TRY(ag_ensure(c->keys[1], n * 8));
+    AG_TRY(ag_ensure(c->vals[0], n * 4)); AG_TRY(ag_ensure(c->vals[1], n * 4));
+    const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
+    AG_TRY(ag_ensure(c->sort_hist, (size_t)(256 * nblocks + 1) * 4));
+    AG_TRY(ag_ensure(c->pos_off, (size_t)(256 * (int64_t)nblocks + 1 > n + 1 ? 256 * (int64_t)nblocks + 1 : n + 1) * 4));
+    AG_TRY(ag_ensure(c->perm, n * 4)); AG_TRY(ag_ensure(c->rank, n * 4));
+    AG_TRY(ag_ensure(c->spos, n * 32)); AG_TRY(ag_ensure(c->svel, n * 32)); AG_TRY(ag_ensure(c->svf, n * 16));
+    AG_TRY(ag_ensure(c->cdig, n * 4)); AG_TRY(ag_ensure(c->pos_cnt, (n + 1) * 4));
+    AG_TRY(ag_ensure(c->nd_com, max_nodes * 32)); AG_TRY(ag_ensure(c->nd_lo, max_nodes * 16));
+    AG_TRY(ag_ensure(c->nd_hi, max_nodes * 16)); AG_TRY(ag_ensure(c->nd_link, max_nodes * 16));
+    AG_TRY(ag_ensure(c->nd_mp, max_nodes * 64)); AG_TRY(ag_ensure(c->nd_64, max_nodes * kM64 * 8));
+    AG_TRY(ag_ensure(c->lvl_cnt, 64 * 4)); AG_TRY(ag_ensure(c->lvl_fill, 64 * 4));
+    AG_TRY(ag_ensure(c->lvl_nodes, max_nodes * 4));
+    AG_TRY(ag_ensure(c->sys_off, (n_sys + 1) * 8)); AG_TRY(ag_ensure(c->sys_root, (n_sys + 1) * 4));
+    AG_TRY(ag_ensure(c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
+
+    PhaseScope phase(c, AG_PHASE_BUILD);
+    hipStream_t st = c->stream;
+    int32_t* flags = c->dflags.as<int32_t>();
+    int64_t* off = c->sys_off.as<int64_t>();
+    hipLaunchKernelGGL(k_copy_offsets, dim3(1), dim3(512), 0, st, n_sys, n, sys_offsets, off, flags);
+
+    // 1. bounding cubes
+    uint64_t* box = c->sys_box.as<uint64_t>();
+    int32_t* blk_off = reinterpret_cast<int32_t*>(box + 6 * n_sys);
+    hipLaunchKernelGGL(k_box_init, dim3(1), dim3(512), 0, st, n_sys, box, blk_off, off);
+    const int64_t box_blocks = n / kBoxChunk + n_sys + 1;
+    hipLaunchKernelGGL(k_box, dim3((unsigned)box_blocks), dim3(kThreads), 0, st, x, off, n_sys, blk_off, box, flags);
+
+    // 2. keys
+    uint64_t* k0 = c->keys[0].as<uint64_t>();
+    uint64_t* k1 = c->keys[1].as<uint64_t>();
+    int32_t* v0 = c->vals[0].as<int32_t>();
+    int32_t* v1 = c->vals[1].as<int32_t>();
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kThreads), 0, st, n, x, off, n_sys, bits, box, k0, v0);
+
+    // 3. sort (8 passes: result back in k0/v0)
+    int32_t* hist = c->sort_hist.as<int32_t>();
+    int32_t* hoff = c->pos_off.as<int32_t>();
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        uint64_t* kin = (pass & 1) ? k1 : k0;
+        uint64_t* kout = (pass & 1) ? k0 : k1;
+        int32_t* vin = (pass & 1) ? v1 : v0;
+        int32_t* vout = (pass & 1) ? v0 : v1;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, n, shift, nblocks, hist);
+        AG_TRY(ag_scan_i32(c, hist, hoff, (int64_t)256 * nblocks));
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin, vin, n, shift, nblocks, hoff,
+                           kout, vout);
+    }
+    // sorted keys in k0, permutation in v0
+    AG_HIP(hipMemcpyAsync(c->perm.p, v0, n * 4, hipMemcpyDeviceToDevice, st));
+
+    // 4. gather
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, st, n, c->perm.as<int32_t>(), x, v, m,
+                       c->rank.as<int32_t>(), c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
+
+    // 5. topology
+    int32_t* cd = c->cdig.as<int32_t>();
+    hipLaunchKernelGGL(k_cdig, dim3(grid_for(n)), dim3(kThreads), 0, st, n, k0, cd);
+    TopoParams P{n, n_leaf, sys_levels};
+    int32_t* pcnt = c->pos_cnt.as<int32_t>();
+    int32_t* poff = c->pos_off.as<int32_t>();
+    hipLaunchKernelGGL(k_count_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, cd, pcnt);
+    AG_TRY(ag_scan_i32(c, pcnt, poff, n));
+    int32_t* lvl = c->lvl_cnt.as<int32_t>();
+    int64_t* hdr = c->tree_hdr.as<int64_t>();
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, lvl, (int64_t)64, 0);
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, hdr, (int64_t)8, (int64_t)0);
+    hipLaunchKernelGGL(k_write_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, k0, cd, poff,
+                       c->nd_link.as<int4>(), lvl, hdr);
+    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, st, lvl, c->lvl_fill.as<int32_t>());
+    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(max_nodes)), dim3(kThreads), 0, st, c->nd_link.as<int4>(),
+                       hdr, lvl, c->lvl_fill.as<int32_t>(), c->lvl_nodes.as<int32_t>());
+    hipLaunchKernelGGL(k_sys_roots, dim3(1), dim3(512), 0, st, n_sys, sys_levels, off, cd, poff,
+                       c->sys_root.as<int32_t>());
+
+    c->n = n;
+    c->n_leaf = n_leaf;
+    c->n_sys = n_sys;
+    c->sys_levels = sys_levels;
+    c->max_nodes = max_nodes;
+
+    // 6. moments
+    return moments_pass(c);
+}
+
+int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m) {
+    const int64_t n = c->n;
+    PhaseScope phase(c, AG_PHASE_BUILD);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, c->perm.as<int32_t>(), x, v,
+                       m, (int32_t*)nullptr, c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
+    return moments_pass(c);
+}

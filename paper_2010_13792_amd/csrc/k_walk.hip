@@ -1,0 +1,537 @@
+// k_walk.hip -- Barnes-Hut tree walks: the forward walk (g, j, T at the
+// active targets) and the adjoint walk (gradient of L = sum_k w_k . g_k).
+//
+// Work decomposition: the active targets, in key (Morton) order, are cut
+// into groups of at most 64 consecutive targets of one system; one wave64
+// (one workgroup) walks the tree once for its whole group, every lane owning
+// one target.  The opening test is applied to the group's bounding box
+// (conservative: a node is accepted only if it would be for every point of
+// the box), so the whole wave follows one traversal with no divergence in
+// the interaction loops.
+//
+// Traversal: nodes are numbered in depth-first pre-order with a "skip" link
+// past each subtree, so any range [a, b) of sibling subtrees can be walked
+// by one cursor without a stack (test a; accept or leaf -> a = skip[a];
+// open -> a = a + 1).  The 64 lanes hold 64 such cursors and test 64 nodes
+// per step; a lane that opens a node hands the rest of its range to an LDS
+// stack of ranges that idle lanes pop (load balancing).  Accepted nodes and
+// the particles of opened leaves are appended (ballot prefix sums) to LDS
+// lists; every 64 entries the wave stages them as FP32 data relative to the
+// group centre in LDS and all lanes evaluate the tile (LDS broadcast reads),
+// folding the FP32 tile sums into FP64 accumulators.
+#include <float.h>
+
+#include "ag_internal.h"
+#include "pair.h"
+
+namespace {
+
+constexpr int kW = 64;          // lanes per wave = targets per group = tile size
+constexpr int kPCap = 256;      // pending particle indices
+constexpr int kNCap = 128;      // pending accepted nodes
+constexpr int kSCap = 128;      // stacked cursor ranges
+constexpr int kSmallNode = 2;   // accepted nodes this small are summed pairwise
+
+// algorithmic operation count of one particle-node interaction (monopole +
+// quadrupole g and T, mean-velocity + quadrupole-rate jerk; fused
+// multiply-add = 2, reciprocal square root = 1)
+constexpr int AG_PN_FLOPS = 222;
+
+struct Tree {
+    const double4* __restrict__ com;   // centre of mass, extent
+    const float4* __restrict__ lo;
+    const float4* __restrict__ hi;
+    const int4* __restrict__ link;     // skip, start, count, level | leaf
+    const float4* __restrict__ mp;     // 4 per node
+    const double4* __restrict__ spos;  // sorted x, y, z, m
+    const float4* __restrict__ svf;    // sorted vx, vy, vz, m
+    const int32_t* __restrict__ perm;
+    const int32_t* __restrict__ sys_root;
+};
+
+struct Groups {
+    const int32_t* __restrict__ act_pos;
+    const int4* __restrict__ grp;      // start, count, system
+    const int32_t* __restrict__ hdr;   // [0] = number of groups
+};
+
+struct WalkOut {
+    double* acc;
+    double* jerk;
+    double* tidal;
+    unsigned long long* stats;
+    double G;
+};
+
+// group geometry shared by every lane (uniform values)
+struct GroupBox {
+    double cx, cy, cz;          // centre (FP64)
+    float hx, hy, hz;           // half extents (rounded up)
+    float lox, loy, loz, hix, hiy, hiz;   // absolute box, rounded outward
+};
+
+__device__ __forceinline__ float f_dn(double d) {
+    float f = (float)d;
+    return (double)f > d ? nextafterf(f, -FLT_MAX) : f;
+}
+__device__ __forceinline__ float f_upr(double d) {
+    float f = (float)d;
+    return (double)f < d ? nextafterf(f, FLT_MAX) : f;
+}
+
+__device__ __forceinline__ GroupBox group_box(bool valid, double x, double y, double z) {
+    double mnx = valid ? x : DBL_MAX, mny = valid ? y : DBL_MAX, mnz = valid ? z : DBL_MAX;
+    double mxx = valid ? x : -DBL_MAX, mxy = valid ? y : -DBL_MAX, mxz = valid ? z : -DBL_MAX;
+    mnx = ag_wave_min(mnx); mny = ag_wave_min(mny); mnz = ag_wave_min(mnz);
+    mxx = ag_wave_max(mxx); mxy = ag_wave_max(mxy); mxz = ag_wave_max(mxz);
+    GroupBox g;
+    g.cx = 0.5 * (mnx + mxx); g.cy = 0.5 * (mny + mxy); g.cz = 0.5 * (mnz + mxz);
+    g.hx = f_upr(0.5 * (mxx - mnx)); g.hy = f_upr(0.5 * (mxy - mny)); g.hz = f_upr(0.5 * (mxz - mnz));
+    g.lox = f_dn(mnx); g.loy = f_dn(mny); g.loz = f_dn(mnz);
+    g.hix = f_upr(mxx); g.hiy = f_upr(mxy); g.hiz = f_upr(mxz);
+    return g;
+}
+
+// Opening test for node data (com, extent, box) against the group box.
+// Accept iff  L <= theta * r_min  (r_min: distance from the node's centre of
+// mass to the nearest point of the group box)  and the node's box is at
+// least eps away from the group box (so only Newtonian pairs are
+// approximated).
+__device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
+                                           float theta2, float eps2) {
+    const float rx = fmaxf(fabsf((float)(c.x - g.cx)) - g.hx, 0.f);
+    const float ry = fmaxf(fabsf((float)(c.y - g.cy)) - g.hy, 0.f);
+    const float rz = fmaxf(fabsf((float)(c.z - g.cz)) - g.hz, 0.f);
+    const float r2 = rx * rx + ry * ry + rz * rz;
+    const float L = (float)c.w;
+    const float gx = fmaxf(fmaxf(lo.x - g.hix, g.lox - hi.x), 0.f);
+    const float gy = fmaxf(fmaxf(lo.y - g.hiy, g.loy - hi.y), 0.f);
+    const float gz = fmaxf(fmaxf(lo.z - g.hiz, g.loz - hi.z), 0.f);
+    const float sep2 = gx * gx + gy * gy + gz * gz;
+    return r2 > 0.f && L * L <= theta2 * r2 && sep2 >= eps2;
+}
+
+// particle-node interaction at quadrupole order (see the header of this file
+// for the expansion).  d = node centre - target, nu = node velocity - target
+// velocity.  Accumulates g, j and S = -T (same convention as pair_interact).
+__device__ __forceinline__ void node_interact(float dx, float dy, float dz, float nx, float ny, float nz,
+                                              float M, const float* Q, const float* Qd, PairAcc<float>& A) {
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float ri2 = ri * ri;
+    const float ri3 = ri * ri2;
+    const float ri5 = ri3 * ri2;
+    const float ri7 = ri5 * ri2;
+    const float ri9 = ri7 * ri2;
+    // Q = (xx yy zz xy xz yz)
+    const float Px = Q[0] * dx + Q[3] * dy + Q[4] * dz;
+    const float Py = Q[3] * dx + Q[1] * dy + Q[5] * dz;
+    const float Pz = Q[4] * dx + Q[5] * dy + Q[2] * dz;
+    const float q = dx * Px + dy * Py + dz * Pz;
+    const float ca = M * ri3 + 2.5f * q * ri7;
+    // g = ca d - ri5 P
+    A.ax += ca * dx - ri5 * Px;
+    A.ay += ca * dy - ri5 * Py;
+    A.az += ca * dz - ri5 * Pz;
+    // S = ca I - beta d d^T - ri5 Q + 5 ri7 (P d^T + d P^T)
+    const float beta = 3.f * M * ri5 + 17.5f * q * ri9;
+    const float e = 5.f * ri7;
+    const float ePx = e * Px, ePy = e * Py, ePz = e * Pz;
+    const float wx = ePx - beta * dx, wy = ePy - beta * dy, wz = ePz - beta * dz;
+    A.sxx += ca + (wx + ePx) * dx - ri5 * Q[0];
+    A.syy += ca + (wy + ePy) * dy - ri5 * Q[1];
+    A.szz += ca + (wz + ePz) * dz - ri5 * Q[2];
+    A.sxy += wx * dy + ePy * dx - ri5 * Q[3];
+    A.sxz += wx * dz + ePz * dx - ri5 * Q[4];
+    A.syz += wy * dz + ePz * dy - ri5 * Q[5];
+    // j = S nu - ri5 Qd d + 2.5 (d.Qd.d) ri7 d
+    const float dn = dx * nx + dy * ny + dz * nz;
+    const float Pn = Px * nx + Py * ny + Pz * nz;
+    const float Qnx = Q[0] * nx + Q[3] * ny + Q[4] * nz;
+    const float Qny = Q[3] * nx + Q[1] * ny + Q[5] * nz;
+    const float Qnz = Q[4] * nx + Q[5] * ny + Q[2] * nz;
+    const float Rx = Qd[0] * dx + Qd[3] * dy + Qd[4] * dz;
+    const float Ry = Qd[3] * dx + Qd[1] * dy + Qd[5] * dz;
+    const float Rz = Qd[4] * dx + Qd[5] * dy + Qd[2] * dz;
+    const float qd = dx * Rx + dy * Ry + dz * Rz;
+    const float cd = e * Pn - beta * dn + 2.5f * qd * ri7;   // coefficient of d
+    const float cp = e * dn;                                 // coefficient of P
+    A.jx += ca * nx + cd * dx + cp * Px - ri5 * (Qnx + Rx);
+    A.jy += ca * ny + cd * dy + cp * Py - ri5 * (Qny + Ry);
+    A.jz += ca * nz + cd * dz + cp * Pz - ri5 * (Qnz + Rz);
+}
+
+__device__ __forceinline__ void fold(PairAcc<double>& D, const PairAcc<float>& F) {
+    D.ax += F.ax; D.ay += F.ay; D.az += F.az;
+    D.jx += F.jx; D.jy += F.jy; D.jz += F.jz;
+    D.sxx += F.sxx; D.syy += F.syy; D.szz += F.szz;
+    D.sxy += F.sxy; D.sxz += F.sxz; D.syz += F.syz;
+}
+
+// LDS of one wave
+struct WalkLds {
+    int plist[kPCap];
+    int nlist[kNCap];
+    int2 stack[kSCap];
+    union {
+        struct { float4 pos[kW]; float4 vel[kW]; int idx[kW]; } p;
+        struct { float4 d[5 * kW]; } n;
+    } tile;
+};
+
+__global__ void __launch_bounds__(kW) k_walk(Tree T, Groups Gr, WalkOut O, int n_groups_max, float theta2,
+                                             float eps2, float h2, float hinv) {
+    __shared__ WalkLds S;
+    const int lane = threadIdx.x;
+    // XCD-aware order: consecutive groups (spatial neighbours) land on one XCD
+    const int nb = gridDim.x;
+    const int per = (nb + 7) >> 3;
+    const int g = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (g >= Gr.hdr[0] || g >= n_groups_max) return;
+    const int4 gd = Gr.grp[g];
+    const int count = gd.y;
+    if (count <= 0) return;
+
+    // ---- targets ----
+    const bool valid = lane < count;
+    const int p_i = valid ? Gr.act_pos[gd.x + lane] : -1;
+    double4 xi = valid ? T.spos[p_i] : make_double4(0, 0, 0, 0);
+    float4 vi = valid ? T.svf[p_i] : make_float4(0, 0, 0, 0);
+    const GroupBox gb = group_box(valid, xi.x, xi.y, xi.z);
+    const float tx = valid ? (float)(xi.x - gb.cx) : 0.f;
+    const float ty = valid ? (float)(xi.y - gb.cy) : 0.f;
+    const float tz = valid ? (float)(xi.z - gb.cz) : 0.f;
+
+    PairAcc<double> acc;
+    acc.zero();
+    uint64_t n_pp = 0, n_pn = 0;
+
+    // ---- traversal state ----
+    const int root = T.sys_root[gd.z];
+    int ca = 0, cb = 0;          // cursor range [ca, cb)
+    int ps = 0, pc = 0;          // particles still to be listed from an opened leaf
+    if (lane == 0 && root >= 0) {
+        ca = root;
+        cb = T.link[root].x;
+    }
+    int sp = 0;                  // stack depth (uniform)
+    int npend = 0, ppend = 0;    // list fills (uniform)
+
+    auto flush_particles = [&](int base, int cnt) {
+        // stage
+        if (lane < cnt) {
+            const int pk = S.plist[base + lane];
+            const double4 q = T.spos[pk];
+            const float4 u = T.svf[pk];
+            S.tile.p.pos[lane] = make_float4((float)(q.x - gb.cx), (float)(q.y - gb.cy), (float)(q.z - gb.cz), u.w);
+            S.tile.p.vel[lane] = u;
+            S.tile.p.idx[lane] = pk;
+        }
+        __syncthreads();
+        PairAcc<float> F;
+        F.zero();
+        for (int k = 0; k < cnt; ++k) {
+            const float4 q = S.tile.p.pos[k];
+            const float4 u = S.tile.p.vel[k];
+            const float mj = (S.tile.p.idx[k] == p_i) ? 0.f : q.w;
+            pair_interact<float>(q.x - tx, q.y - ty, q.z - tz, u.x - vi.x, u.y - vi.y, u.z - vi.z, mj, h2, hinv, F);
+        }
+        fold(acc, F);
+        n_pp += (uint64_t)cnt;
+        __syncthreads();
+    };
+    auto flush_nodes = [&](int base, int cnt) {
+        if (lane < cnt) {
+            const int nk = S.nlist[base + lane];
+            const double4 c = T.com[nk];
+            const float4 m0 = T.mp[4 * nk], m1 = T.mp[4 * nk + 1], m2 = T.mp[4 * nk + 2], m3 = T.mp[4 * nk + 3];
+            float4* d = S.tile.n.d;
+            d[lane] = make_float4((float)(c.x - gb.cx), (float)(c.y - gb.cy), (float)(c.z - gb.cz), m0.x);
+            d[kW + lane] = make_float4(m0.y, m0.z, m0.w, m1.x);       // u, Qxx
+            d[2 * kW + lane] = make_float4(m1.y, m1.z, m1.w, m2.x);   // Qyy Qzz Qxy Qxz
+            d[3 * kW + lane] = make_float4(m2.y, m2.z, m2.w, m3.x);   // Qyz, Qd xx yy zz
+            d[4 * kW + lane] = make_float4(m3.y, m3.z, m3.w, 0.f);    // Qd xy xz yz
+        }
+        __syncthreads();
+        PairAcc<float> F;
+        F.zero();
+        const float4* d = S.tile.n.d;
+        for (int k = 0; k < cnt; ++k) {
+            const float4 a0 = d[k], a1 = d[kW + k], a2 = d[2 * kW + k], a3 = d[3 * kW + k], a4 = d[4 * kW + k];
+            const float Q[6] = {a1.w, a2.x, a2.y, a2.z, a2.w, a3.x};
+            const float Qd[6] = {a3.y, a3.z, a3.w, a4.x, a4.y, a4.z};
+            node_interact(a0.x - tx, a0.y - ty, a0.z - tz, a1.x - vi.x, a1.y - vi.y, a1.z - vi.z, a0.w, Q, Qd, F);
+        }
+        fold(acc, F);
+        n_pn += (uint64_t)cnt;
+        __syncthreads();
+    };
+
+    for (;;) {
+        // 1. idle lanes take ranges from the stack
+        {
+            const bool idle = (ca >= cb) && pc == 0;
+            const uint64_t im = __ballot(idle);
+            const int nidle = __popcll(im);
+            const int take = nidle < sp ? nidle : sp;
+            if (take > 0) {
+                const int r = ag_prefix_count(im);
+                if (idle && r < take) {
+                    const int2 e = S.stack[sp - 1 - r];
+                    ca = e.x;
+                    cb = e.y;
+                }
+                sp -= take;
+            }
+            __syncthreads();
+        }
+        const bool walking = (ca < cb) && pc == 0;
+        if (__ballot(walking || pc > 0) == 0) break;
+
+        // 2. test one node per walking lane
+        int push_node = -1;
+        int push_range_a = 0, push_range_b = 0;
+        bool want_push = false;
+        if (walking) {
+            const int a = ca;
+            const int4 L = T.link[a];
+            const bool leaf = (L.w & 0x100) != 0;
+            const bool acc_ok = mac_accept(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2);
+            if (acc_ok && L.z > kSmallNode) {
+                push_node = a;
+                ca = L.x;
+            } else if (acc_ok || leaf) {
+                ps = L.y;
+                pc = L.z;
+                ca = L.x;
+            } else {                       // open an inner node
+                if (L.x < cb) {            // siblings remain: offer them to the stack
+                    want_push = true;
+                    push_range_a = L.x;
+                    push_range_b = cb;
+                }
+                ca = a + 1;
+            }
+        }
+        // 3a. accepted nodes -> node list (always fits: npend < 64 here)
+        {
+            const uint64_t m = __ballot(push_node >= 0);
+            if (m) {
+                const int r = ag_prefix_count(m);
+                if (push_node >= 0) S.nlist[npend + r] = push_node;
+                npend += __popcll(m);
+            }
+        }
+        // 3b. split ranges -> stack (lanes beyond capacity keep their range)
+        {
+            const uint64_t m = __ballot(want_push);
+            if (m) {
+                const int r = ag_prefix_count(m);
+                const int room = kSCap - sp;
+                if (want_push && r < room) {
+                    S.stack[sp + r] = make_int2(push_range_a, push_range_b);
+                    cb = push_range_a;
+                }
+                const int pushed = __popcll(m);
+                sp += pushed < room ? pushed : room;
+            }
+        }
+        // 3c. particles of opened leaves -> particle list, as room allows
+        {
+            const int want = pc;
+            const int incl = ag_wave_incl_scan(want);
+            const int excl = incl - want;
+            const int total = __shfl(incl, 63, 64);
+            if (total > 0) {
+                const int room = kPCap - ppend;
+                int give = room - excl;
+                give = give < 0 ? 0 : (give > want ? want : give);
+                for (int k = 0; k < give; ++k) S.plist[ppend + excl + k] = ps + k;
+                ps += give;
+                pc -= give;
+                ppend += total < room ? total : room;
+            }
+        }
+        __syncthreads();
+        // 4. evaluate full tiles
+        while (npend >= kW) {
+            npend -= kW;
+            flush_nodes(npend, kW);
+        }
+        while (ppend >= kW) {
+            ppend -= kW;
+            flush_particles(ppend, kW);
+        }
+    }
+    if (npend > 0) flush_nodes(0, npend);
+    if (ppend > 0) flush_particles(0, ppend);
+
+    // ---- results ----
+    if (valid) {
+        const int64_t i = T.perm[p_i];
+        const double G = O.G;
+        if (O.acc) {
+            O.acc[3 * i] = G * acc.ax; O.acc[3 * i + 1] = G * acc.ay; O.acc[3 * i + 2] = G * acc.az;
+        }
+        if (O.jerk) {
+            O.jerk[3 * i] = G * acc.jx; O.jerk[3 * i + 1] = G * acc.jy; O.jerk[3 * i + 2] = G * acc.jz;
+        }
+        if (O.tidal) {
+            double* t = O.tidal + 6 * i;
+            t[0] = -G * acc.sxx; t[1] = -G * acc.syy; t[2] = -G * acc.szz;
+            t[3] = -G * acc.sxy; t[4] = -G * acc.sxz; t[5] = -G * acc.syz;
+        }
+    }
+    if (lane == 0 && O.stats) {
+        atomicAdd(&O.stats[0], (unsigned long long)(n_pp * (uint64_t)count));
+        atomicAdd(&O.stats[1], (unsigned long long)(n_pn * (uint64_t)count));
+        atomicAdd(&O.stats[2], (unsigned long long)count);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// active rows -> groups
+// ---------------------------------------------------------------------------
+__global__ void k_fill0(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_mark(int64_t n_act, const int32_t* __restrict__ idx, int64_t n, const int32_t* __restrict__ rank,
+                       int32_t* __restrict__ flag, int32_t* __restrict__ flags) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_act;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx ? (int64_t)idx[k] : k;
+        if (i < 0 || i >= n) {
+            atomicOr(flags, AGF_BADINDEX);
+            continue;
+        }
+        const int p = rank[i];
+        if (atomicOr(&flag[p], 1) & 1) atomicOr(flags, AGF_BADINDEX);
+    }
+}
+
+__global__ void k_compact_pos(int64_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
+                              int32_t* __restrict__ out) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        if (flag[p]) out[off[p]] = (int32_t)p;
+}
+
+// one block: per-system active counts and group offsets
+__global__ void k_group_counts(int n_sys, const int64_t* __restrict__ sys_off, const int32_t* __restrict__ off,
+                               int32_t* __restrict__ hdr, int32_t* __restrict__ sys_act) {
+    __shared__ int s_g[AG_MAX_SYS + 1];
+    for (int s = threadIdx.x; s < n_sys; s += blockDim.x) {
+        const int a0 = off[sys_off[s]];
+        const int a1 = off[sys_off[s + 1]];
+        sys_act[s] = a0;
+        if (s == n_sys - 1) sys_act[n_sys] = a1;
+        s_g[s] = (a1 - a0 + kW - 1) / kW;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int accg = 0;
+        for (int s = 0; s < n_sys; ++s) {
+            const int v = s_g[s];
+            hdr[4 + s] = accg;
+            accg += v;
+        }
+        hdr[4 + n_sys] = accg;
+        hdr[0] = accg;
+    }
+}
+
+__global__ void k_group_desc(int n_sys, int64_t max_groups, const int32_t* __restrict__ hdr,
+                             const int32_t* __restrict__ sys_act, int4* __restrict__ grp) {
+    const int total = hdr[0];
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < max_groups;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        if (g >= total) {
+            grp[g] = make_int4(0, 0, 0, 0);
+            continue;
+        }
+        int lo = 0, hi = n_sys;   // hdr[4+lo] <= g < hdr[4+hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (hdr[4 + mid] <= g) lo = mid; else hi = mid;
+        }
+        const int s = lo;
+        const int j = (int)g - hdr[4 + s];
+        const int a = sys_act[s + 1] - sys_act[s];
+        const int start = sys_act[s] + kW * j;
+        const int cnt = a - kW * j < kW ? a - kW * j : kW;
+        grp[g] = make_int4(start, cnt, s, 0);
+    }
+}
+
+int grid_for(int64_t n, int threads = 256) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b > 8192) b = 8192;
+    return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max_groups) {
+    const int64_t n = c->n;
+    const int64_t mg = (n_act + kW - 1) / kW + c->n_sys;
+    AG_TRY(ag_ensure(c->act_flag, n * 4));
+    AG_TRY(ag_ensure(c->act_off, (n + 1) * 4));
+    AG_TRY(ag_ensure(c->act_pos, n * 4));
+    AG_TRY(ag_ensure(c->grp, mg * 16));
+    AG_TRY(ag_ensure(c->grp_hdr, (8 + AG_MAX_SYS + 1) * 4));
+    AG_TRY(ag_ensure(c->sys_act, (AG_MAX_SYS + 1) * 4));
+    PhaseScope phase(c, AG_PHASE_GROUPS);
+    hipStream_t st = c->stream;
+    int32_t* flag = c->act_flag.as<int32_t>();
+    int32_t* off = c->act_off.as<int32_t>();
+    hipLaunchKernelGGL(k_fill0, dim3(grid_for(n)), dim3(256), 0, st, flag, n);
+    hipLaunchKernelGGL(k_mark, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, idx, n, c->rank.as<int32_t>(), flag,
+                       c->dflags.as<int32_t>());
+    AG_TRY(ag_scan_i32(c, flag, off, n));
+    hipLaunchKernelGGL(k_compact_pos, dim3(grid_for(n)), dim3(256), 0, st, n, flag, off, c->act_pos.as<int32_t>());
+    hipLaunchKernelGGL(k_group_counts, dim3(1), dim3(512), 0, st, c->n_sys, c->sys_off.as<int64_t>(), off,
+                       c->grp_hdr.as<int32_t>(), c->sys_act.as<int32_t>());
+    hipLaunchKernelGGL(k_group_desc, dim3(grid_for(mg)), dim3(256), 0, st, c->n_sys, mg, c->grp_hdr.as<int32_t>(),
+                       c->sys_act.as<int32_t>(), c->grp.as<int4>());
+    *max_groups = mg;
+    return AG_OK;
+}
+
+static Tree make_tree(ag_ctx* c) {
+    Tree T;
+    T.com = c->nd_com.as<double4>();
+    T.lo = c->nd_lo.as<float4>();
+    T.hi = c->nd_hi.as<float4>();
+    T.link = c->nd_link.as<int4>();
+    T.mp = c->nd_mp.as<float4>();
+    T.spos = c->spos.as<double4>();
+    T.svf = c->svf.as<float4>();
+    T.perm = c->perm.as<int32_t>();
+    T.sys_root = c->sys_root.as<int32_t>();
+    return T;
+}
+
+int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps, double G, double* acc,
+                   double* jerk, double* tidal) {
+    int64_t mg = 0;
+    AG_TRY(ag_prepare_groups(c, idx, n_act, &mg));
+    Groups Gr{c->act_pos.as<int32_t>(), c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    WalkOut O{acc, jerk, tidal, c->stats.as<unsigned long long>(), G};
+    const int64_t blocks = (mg + 7) / 8 * 8;
+    const float th = (float)theta;
+    const float e2 = (float)(eps * eps);
+    {
+        PhaseScope phase(c, AG_PHASE_WALK);
+        hipLaunchKernelGGL(k_walk, dim3((unsigned)blocks), dim3(kW), 0, c->stream, make_tree(c), Gr, O, (int)mg,
+                           th * th, e2, e2, (float)(1.0 / eps));
+    }
+    return AG_OK;
+}
+
+int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w, double theta, double eps,
+                       double G, double* dLdx, double* dLdm) {
+    return ag_fail(AG_ESTATE, "backward walk not built yet");
+}

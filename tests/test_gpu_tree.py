@@ -1,0 +1,249 @@
+"""GPU parity: oct-tree build (topology invariants, node multipoles against the
+oracle's brute-force moments) and the tree walk against the FP64 direct sum."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from conftest import rel_err, tensor_rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _t(a, dtype=None):
+    return torch.tensor(a, device=DEV) if dtype is None else torch.tensor(a, dtype=dtype, device=DEV)
+
+
+def _eval(ctx, x, v, m, theta, eps, G=1.0, active=None, n_leaf=16, build=True):
+    n = len(m)
+    if build:
+        ctx.tree_build(_t(x), _t(v), _t(m), n_leaf)
+    acc = torch.full((n, 3), float("nan"), dtype=torch.float64, device=DEV)
+    jerk = torch.full((n, 3), float("nan"), dtype=torch.float64, device=DEV)
+    tid = torch.full((n, 6), float("nan"), dtype=torch.float64, device=DEV)
+    ia = None if active is None else _t(active, torch.int32)
+    ctx.grav_eval(ia, theta, eps, G, acc, jerk, tid)
+    ctx.sync()
+    return acc.cpu().numpy(), jerk.cpu().numpy(), tid.cpu().numpy()
+
+
+def _check_topology(link, mom, perm, n, n_leaf, x, v, m, orc, sample=300):
+    nn = link.shape[0]
+    skip, start, cnt, lv = link[:, 0], link[:, 1], link[:, 2], link[:, 3]
+    leaf = (lv & 0x100) != 0
+    level = lv & 0xff
+    # permutation
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    # root covers everything; leaves tile [0, n) exactly once, in order
+    assert start[0] == 0 and cnt[0] == n and skip[0] == nn
+    ls = start[leaf]
+    lc = cnt[leaf]
+    assert np.all(lc >= 1)
+    assert ls[0] == 0 and np.array_equal(ls[1:], (ls + lc)[:-1]) and ls[-1] + lc[-1] == n
+    # leaves respect the capacity unless at the deepest level
+    assert np.all((lc <= n_leaf) | (level[leaf] == 21))
+    # pre-order: first child of an inner node is the next node, children tile the parent
+    inner = np.nonzero(~leaf)[0]
+    for i in inner[:2000]:
+        ch = i + 1
+        tot = 0
+        pos = start[i]
+        while ch < skip[i]:
+            assert level[ch] > level[i] and start[ch] == pos
+            pos += cnt[ch]
+            tot += cnt[ch]
+            ch = skip[ch]
+        assert ch == skip[i] and tot == cnt[i]
+    # node moments against brute force over the node's particles
+    rng = np.random.default_rng(0)
+    picks = np.concatenate([[0], rng.choice(nn, min(sample, nn), replace=False)])
+    for i in picks:
+        rows = perm[start[i]:start[i] + cnt[i]]
+        ref = orc.moments(x, v, m, rows)
+        got = mom[i]
+        scale_x = max(1.0, np.abs(ref["com"]).max())
+        assert got[0] == pytest.approx(ref["M"], rel=1e-12)
+        np.testing.assert_allclose(got[1:4], ref["com"], rtol=0, atol=1e-12 * scale_x)
+        np.testing.assert_allclose(got[4:7], ref["u"], rtol=0, atol=1e-12 * max(1, np.abs(ref["u"]).max()))
+        qs = max(np.abs(ref["Q"]).max(), 1e-300)
+        np.testing.assert_allclose(got[7:13], ref["Q"], rtol=0, atol=1e-9 * qs + 1e-280)
+        qds = max(np.abs(ref["Qdot"]).max(), 1e-300)
+        np.testing.assert_allclose(got[13:19], ref["Qdot"], rtol=0, atol=1e-9 * qds + 1e-280)
+        np.testing.assert_array_equal(got[19:22], ref["lo"])
+        np.testing.assert_array_equal(got[22:25], ref["hi"])
+
+
+@pytest.mark.parametrize("n,n_leaf,kind", [(1, 16, "plummer"), (17, 16, "plummer"), (5000, 16, "plummer"),
+                                           (20000, 8, "sphere"), (30000, 32, "clumps")])
+def test_tree_topology_and_moments(ctx, orc, n, n_leaf, kind):
+    if kind == "plummer":
+        x, v, m = workloads.plummer(n, seed=n)
+    elif kind == "sphere":
+        x, v, m = workloads.turbulent_sphere(n, seed=2, grid=32)
+    else:
+        x, v, m, _ = workloads.clumps(n, seed=3)
+    m = m * np.random.default_rng(1).uniform(0.5, 1.5, n)
+    ctx.tree_build(_t(x), _t(v), _t(m), n_leaf)
+    link, mom, perm = (t.cpu().numpy() for t in ctx.tree_export())
+    _check_topology(link, mom, perm, n, n_leaf, x, v, m, orc)
+
+
+def test_tree_coincident_particles(ctx, orc):
+    """More coincident particles than a leaf holds: the cell splits down to
+    the deepest level and keeps them all in one leaf."""
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(500, 3))
+    x[100:200] = x[7]
+    v = rng.normal(size=(500, 3))
+    m = np.full(500, 1 / 500)
+    ctx.tree_build(_t(x), _t(v), _t(m), 8)
+    link, mom, perm = (t.cpu().numpy() for t in ctx.tree_export())
+    _check_topology(link, mom, perm, 500, 8, x, v, m, orc)
+    a, j, t = _eval(ctx, x, v, m, 0.0, 0.05, build=False)
+    ar, jr, tr = orc.direct(x, v, m, 0.05, 1.0)
+    assert np.median(rel_err(a, ar)) < 1e-5
+
+
+def test_tree_deterministic(ctx):
+    x, v, m = workloads.turbulent_sphere(1 << 15, seed=2, grid=32)
+    r1 = _eval(ctx, x, v, m, 0.7, 1e-3)
+    l1 = ctx.tree_export()[0].cpu().numpy()
+    r2 = _eval(ctx, x, v, m, 0.7, 1e-3)
+    l2 = ctx.tree_export()[0].cpu().numpy()
+    assert np.array_equal(l1, l2)
+    for p, q in zip(r1, r2):
+        assert np.array_equal(p, q)
+
+
+@pytest.mark.parametrize("n", [100, 4096, 10007])
+def test_walk_theta0_is_direct_sum(ctx, orc, n):
+    """theta = 0 opens every node: the walk is the direct sum (FP32 pairs)."""
+    x, v, m = workloads.plummer(n, seed=n)
+    eps = 0.01
+    a, j, t = _eval(ctx, x, v, m, 0.0, eps)
+    ar, jr, tr = orc.direct(x, v, m, eps, 1.0)
+    assert np.median(rel_err(a, ar)) <= 1e-5
+    assert np.median(rel_err(j, jr)) <= 1e-5
+    assert np.median(tensor_rel_err(t, tr)) <= 1e-5
+    st = ctx.stats_read()
+    assert st["n_pp"] > 0
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.7])
+def test_walk_accuracy_turbulent_sphere(ctx, orc, theta):
+    """Uniform sphere with k^-4 velocities, N = 2^16, eps = 1e-3: median
+    relative force error <= 1e-3 and 99th percentile <= 1e-2 (all rows);
+    jerk and tidal tensor with the same statistics."""
+    n = 1 << 16
+    x, v, m = workloads.turbulent_sphere(n, seed=2, grid=64)
+    eps = 1e-3
+    a, j, t = _eval(ctx, x, v, m, theta, eps)
+    rows = np.random.default_rng(3).choice(n, 4096, replace=False)
+    ar, jr, tr = orc.direct(x, v, m, eps, 1.0, rows)
+    ea, ej, et = rel_err(a[rows], ar), rel_err(j[rows], jr), tensor_rel_err(t[rows], tr)
+    for e in (ea, ej, et):
+        assert np.median(e) <= 1e-3 and np.percentile(e, 99) <= 1e-2, (np.median(e), np.percentile(e, 99))
+
+
+def test_walk_plummer_clustered(ctx, orc):
+    x, v, m, _ = workloads.clumps(1 << 16, seed=3)
+    eps = 1e-3
+    a, j, t = _eval(ctx, x, v, m, 0.7, eps)
+    rows = np.random.default_rng(4).choice(len(m), 4096, replace=False)
+    ar, jr, tr = orc.direct(x, v, m, eps, 1.0, rows)
+    ea = rel_err(a[rows], ar)
+    assert np.median(ea) <= 1e-3 and np.percentile(ea, 99) <= 1e-2
+
+
+@pytest.mark.parametrize("frac", [0.003, 0.2, 0.77])
+def test_walk_partial_active(ctx, orc, frac):
+    n = 20011
+    x, v, m = workloads.plummer(n, seed=5)
+    act = np.random.default_rng(6).permutation(workloads.random_subset(n, frac, seed=7))
+    a, j, t = _eval(ctx, x, v, m, 0.6, 0.01, active=act)
+    other = np.setdiff1d(np.arange(n), act)
+    assert np.all(np.isnan(a[other])) and np.all(np.isnan(j[other])) and np.all(np.isnan(t[other]))
+    ar, jr, tr = orc.direct(x, v, m, 0.01, 1.0, act)
+    ea = rel_err(a[act], ar)
+    assert np.median(ea) <= 1e-3 and np.percentile(ea, 99) <= 1e-2
+    st = ctx.stats_read()
+    assert st["n_targets"] >= len(act)
+
+
+def test_refit_after_drift(ctx, orc):
+    n = 30000
+    x, v, m = workloads.plummer(n, seed=8)
+    ctx.tree_build(_t(x), _t(v), _t(m), 16)
+    x2 = x + 0.01 * v
+    ctx.tree_refit(_t(x2), _t(v), _t(m))
+    link, mom, perm = (t.cpu().numpy() for t in ctx.tree_export())
+    _check_topology(link, mom, perm, n, 16, x2, v, m, orc, sample=100)
+    a, _, _ = _eval(ctx, x2, v, m, 0.6, 0.01, build=False)
+    rows = np.arange(0, n, 7)
+    ar, _, _ = orc.direct(x2, v, m, 0.01, 1.0, rows)
+    ea = rel_err(a[rows], ar)
+    assert np.median(ea) <= 1e-3 and np.percentile(ea, 99) <= 1e-2
+
+
+def test_batched_systems(ctx, orc):
+    d = workloads.batched_plummer(nsys=12, seed=4, nmin=100, nmax=3000)
+    x, v, m = d["x"], d["v"], d["m"]
+    n = len(m)
+    ctx.tree_build_batched(_t(x), _t(v), _t(m), _t(d["offsets"], torch.int64), 16)
+    acc = torch.full((n, 3), float("nan"), dtype=torch.float64, device=DEV)
+    jerk = torch.full_like(acc, float("nan"))
+    tid = torch.full((n, 6), float("nan"), dtype=torch.float64, device=DEV)
+    ctx.grav_eval_batched(_t(d["active"], torch.int32), 0.5, 0.01, 1.0, acc, jerk, tid)
+    ctx.sync()
+    a = acc.cpu().numpy()
+    act = d["active"]
+    other = np.setdiff1d(np.arange(n), act)
+    assert np.all(np.isnan(a[other]))
+    off = d["offsets"]
+    for s in range(12):
+        lo, hi = off[s], off[s + 1]
+        rows = act[(act >= lo) & (act < hi)]
+        ar, _, _ = orc.direct(x[lo:hi], v[lo:hi], m[lo:hi], 0.01, 1.0, rows - lo)
+        ea = rel_err(a[rows], ar)
+        assert np.median(ea) <= 1e-3 and np.percentile(ea, 99) <= 1e-2, s
+
+
+def test_eval_errors(ag, orc):
+    c = ag.Context(0)
+    try:
+        x, v, m = workloads.plummer(100, seed=1)
+        acc = torch.zeros((100, 3), dtype=torch.float64, device=DEV)
+        with pytest.raises(ag.AgError) as e:
+            c.n = 100
+            c.grav_eval(None, 0.5, 0.01, 1.0, acc, None, None)
+        assert e.value.code == ag.AG_ESTATE
+        c.tree_build(_t(x), _t(v), _t(m), 16)
+        for th, ep in ((-0.1, 0.01), (0.5, 0.0), (0.5, -1.0)):
+            with pytest.raises(ag.AgError) as e:
+                c.grav_eval(None, th, ep, 1.0, acc, None, None)
+            assert e.value.code == ag.AG_EINVAL
+        # repeated and out-of-range active rows raise a device flag
+        with pytest.raises(ag.AgError) as e:
+            c.grav_eval(_t(np.array([1, 2, 2]), torch.int32), 0.5, 0.01, 1.0, acc, None, None)
+            c.sync()
+        assert e.value.code == ag.AG_EDEVICE
+        with pytest.raises(ag.AgError) as e:
+            c.grav_eval(_t(np.array([1, 100]), torch.int32), 0.5, 0.01, 1.0, acc, None, None)
+            c.sync()
+        assert e.value.code == ag.AG_EDEVICE
+        # non-finite positions are reported
+        xb = x.copy()
+        xb[5, 1] = np.nan
+        with pytest.raises(ag.AgError) as e:
+            c.tree_build(_t(xb), _t(v), _t(m), 16)
+            c.sync()
+        assert e.value.code == ag.AG_ENONFINITE
+        # still usable
+        c.tree_build(_t(x), _t(v), _t(m), 16)
+        c.grav_eval(None, 0.5, 0.01, 1.0, acc, None, None)
+        c.sync()
+        ar, _, _ = orc.direct(x, v, m, 0.01, 1.0)
+        assert np.median(rel_err(acc.cpu().numpy(), ar)) < 1e-3
+    finally:
+        c.close()
