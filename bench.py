@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the adaptive-force-update gravity path on one MI355X.
+
+One step is one pass of the hot path over one synthetic batch, with every
+input already resident in device memory:
+  tree build (bounding cube, Morton keys, radix sort, topology, FP64 moments)
+  -> grouping of the active targets -> tree walk (g, j, T for every active
+  particle) -> tidal timestep and block bins (Eq. 7) -> force-age
+  bookkeeping and selection (Eq. 3, Eq. 4) -> jerk predictor (Eq. 6).
+
+Default workload: N = 2^20 equal-mass particles uniform in the unit sphere,
+Gaussian-random-field velocities with P(k) ~ k^-4 and rms 1, Barnes-Hut
+theta = 0.7 with monopole + quadrupole nodes, eps = 1e-3, all particles
+active.  The reported value is force evaluations per second (targets given
+fresh g, j, T per second of whole-step GPU time).  The accuracy condition of
+the metric (median relative force error <= 1e-3) is checked on a sample of
+targets against the FP64 oracle, which is also timed on the host cores as
+the CPU baseline.
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "force evals/s at ≤1e-3 median rel force error; adaptive vs every-step speedup"
+PP_FLOPS = 60     # per particle-particle interaction (counted from the written formulas)
+PN_FLOPS = 222    # per particle-node interaction
+PEAK_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6: VALU FMA issue, packed FP32 off
+PEAK_FP32_PACKED_SPEC = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--theta", type=float, default=0.7)
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--n-leaf", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target host time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads
+    import paper_2010_13792_amd as ag
+
+    assert torch.cuda.is_available(), "no HIP device visible"
+    dev = torch.device("cuda:0")
+    n = args.n
+    log(f"bench: generating turbulent sphere n={n}")
+    x, v, m = workloads.turbulent_sphere(n, seed=2, grid=128)
+    tx, tv, tm = (torch.tensor(a, device=dev) for a in (x, v, m))
+    acc = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+    jerk = torch.zeros_like(acc)
+    tid = torch.zeros((n, 6), dtype=torch.float64, device=dev)
+    dt_grav = torch.zeros(n, dtype=torch.float64, device=dev)
+    bins = torch.zeros(n, dtype=torch.int8, device=dev)
+    tf = torch.zeros(n, dtype=torch.int64, device=dev)
+    act = torch.zeros(n, dtype=torch.int32, device=dev)
+    n_act = torch.zeros(1, dtype=torch.int64, device=dev)
+    t0 = torch.zeros(n, dtype=torch.float64, device=dev)
+    acc_pred = torch.zeros_like(acc)
+    eta, G, q_f = 0.01, 1.0, 0.5
+
+    ctx = ag.Context(0)
+    # time grid from the initial forces: dt_max = 2^ceil(log2 max dt), tick = deepest bin
+    ctx.tree_build(tx, tv, tm, args.n_leaf)
+    ctx.grav_eval(None, args.theta, args.eps, G, acc, jerk, tid)
+    ctx.grav_timestep(tid, eta, 1.0, 60, dt_grav, bins)
+    ctx.sync()
+    dtg = dt_grav.cpu().numpy()
+    dt_max = 2.0 ** np.ceil(np.log2(np.max(dtg[np.isfinite(dtg)])))
+    ctx.grav_timestep(tid, eta, dt_max, 60, dt_grav, bins)
+    ctx.sync()
+    tick_bin = int(bins.max().item())
+    dt_step = dt_max * 2.0 ** (-tick_bin)
+
+    state = {"t": 0.0}
+
+    def step():
+        ctx.tree_build(tx, tv, tm, args.n_leaf)
+        ctx.grav_eval(None, args.theta, args.eps, G, acc, jerk, tid)
+        ctx.grav_timestep(tid, eta, dt_max, tick_bin, dt_grav, bins)
+        ctx.adaptive_select(tf, bins, 1, tick_bin, q_f, act, n_act)
+        state["t"] += dt_step
+        ctx.grav_predict(acc, jerk, t0, state["t"], acc_pred)
+
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.stats_reset()
+    ctx.timing_enable(True)
+    ctx.timing_read(reset=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    log(f"bench: timing {args.steps} steps")
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_step = total_ms / args.steps
+    phases = ctx.timing_read(reset=True)
+    ctx.timing_enable(False)
+    st = ctx.stats_read()
+    nn, max_level = ctx.tree_info()
+
+    evals_per_step = st["n_targets"] / args.steps
+    pp_step = st["n_pp"] / args.steps
+    pn_step = st["n_pn"] / args.steps
+    walk_ms = phases["walk"]["ms"] / max(1, phases["walk"]["launches"])
+    walk_flops = pp_step * PP_FLOPS + pn_step * PN_FLOPS
+    achieved_tflops = walk_flops / (walk_ms * 1e-3) / 1e12
+    value = evals_per_step / (ms_step * 1e-3)
+    log(f"bench: {ms_step:.3f} ms/step, walk {walk_ms:.3f} ms, {achieved_tflops:.2f} TFLOP/s")
+
+    # accuracy on a sample against the FP64 oracle; the same run times the oracle
+    a_gpu = acc.cpu().numpy()
+    cpu = None
+    err_med = err_p99 = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(12345)
+        probe = rng.choice(n, 64, replace=False)
+        t_a = time.perf_counter()
+        oracle.direct(x, v, m, args.eps, G, probe)
+        t_probe = time.perf_counter() - t_a
+        k = int(min(n, max(256, 64 * args.cpu_seconds / max(t_probe, 1e-6))))
+        rows = rng.choice(n, k, replace=False)
+        log(f"bench: oracle sample {k} targets (probe {t_probe:.2f} s / 64)")
+        t_a = time.perf_counter()
+        ar, _, _ = oracle.direct(x, v, m, args.eps, G, rows)
+        t_o = time.perf_counter() - t_a
+        err = np.linalg.norm(a_gpu[rows] - ar, axis=1) / np.linalg.norm(ar, axis=1)
+        err_med = float(np.median(err))
+        err_p99 = float(np.percentile(err, 99))
+        cpu = {"value": k / t_o, "unit": "force evals/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{k} random targets of the same N={n} particle set; FP64 direct sum "
+                         f"over all {n} sources ({t_o:.1f} s)"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "force evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"turbulent uniform sphere N=2^{int(np.log2(n))} tree walk, all active",
+            "n": n, "theta": args.theta, "eps": args.eps, "n_leaf": args.n_leaf,
+            "multipoles": "monopole+quadrupole", "accumulation": "f64",
+            "step": "build+groups+walk+timestep+select+predict",
+            "median_rel_force_err": err_med, "p99_rel_force_err": err_p99,
+        },
+        "roofline": {
+            "bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
+            "kernel": "k_walk", "kernel_ms": walk_ms,
+            "flops_per_launch": walk_flops,
+            "peak_note": "FP32 VALU FMA issue rate with packed FP32 disabled "
+                         f"(spec sheet {PEAK_FP32_PACKED_SPEC} TFLOP/s counts packed FP32)",
+        },
+        "cpu_baseline": cpu,
+        "interactions_per_s": (pp_step + pn_step) / (ms_step * 1e-3),
+        "walk_interactions_per_s": (pp_step + pn_step) / (walk_ms * 1e-3),
+        "per_target": {"pp": pp_step / max(1, evals_per_step), "pn": pn_step / max(1, evals_per_step)},
+        "phases_ms_per_step": {p: phases[p]["ms"] / args.steps for p in phases},
+        "tree": {"nodes": nn, "max_level": max_level,
+                 "groups_per_step": st["n_groups"] / args.steps,
+                 "targets_per_group": st["n_targets"] / max(1, st["n_groups"])},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -67,6 +67,7 @@ typedef struct ag_stats {
     int64_t  n_nodes;    /* nodes of the current tree                          */
     int32_t  n_leaf;     /* leaf capacity of the current tree                  */
     int32_t  max_level;  /* deepest tree level in use                          */
+    uint64_t n_groups;   /* target groups walked (one wave each)               */
 } ag_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -35,8 +35,9 @@ ENTRY_POINTS = [
     "ag_last_error", "ag_tree_build", "ag_tree_build_batched", "ag_tree_refit", "ag_tree_info",
     "ag_tree_export", "ag_grav_eval",
     "ag_grav_eval_batched", "ag_grav_direct", "ag_grav_timestep", "ag_adaptive_select",
-    "ag_grav_predict", "ag_grav_backward",
+    "ag_grav_predict", "ag_grav_backward", "ag_timing_enable", "ag_timing_read",
 ]
+PHASES = ["build", "groups", "walk", "direct", "step", "adjoint"]
 
 
 class AgError(RuntimeError):
@@ -48,7 +49,8 @@ class AgError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("n_pp", ctypes.c_uint64), ("n_pn", ctypes.c_uint64),
                 ("n_targets", ctypes.c_uint64), ("n_nodes", ctypes.c_int64),
-                ("n_leaf", ctypes.c_int32), ("max_level", ctypes.c_int32)]
+                ("n_leaf", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("n_groups", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,6 +85,8 @@ def load_library(path: str = LIB_PATH):
         "ag_adaptive_select": [P, I64, P, P, I64, I32, D, P, P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
         "ag_grav_backward": [P, P, I64, P, D, D, D, P, P],
+        "ag_timing_enable": [P, ctypes.c_int],
+        "ag_timing_read": [P, P, P, ctypes.c_int],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -160,6 +164,17 @@ class Context:
 
     def stats_reset(self):
         _check(_lib.ag_stats_reset(self._h))
+
+    def timing_enable(self, on: bool = True):
+        _check(_lib.ag_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self, reset: bool = True) -> dict:
+        """Accumulated GPU milliseconds and launch counts per phase."""
+        ms = (ctypes.c_double * len(PHASES))()
+        cnt = (ctypes.c_int64 * len(PHASES))()
+        _check(_lib.ag_timing_read(self._h, ctypes.cast(ms, ctypes.c_void_p),
+                                   ctypes.cast(cnt, ctypes.c_void_p), 1 if reset else 0))
+        return {p: {"ms": ms[k], "launches": cnt[k]} for k, p in enumerate(PHASES)}
 
     # -- tree ---------------------------------------------------------------
     def tree_build(self, x, v, m, n_leaf: int = 16):

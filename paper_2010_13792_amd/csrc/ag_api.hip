@@ -144,6 +144,7 @@ int read_flags(ag_ctx* c) {
         AG_HIP(hipMemsetAsync(c->dflags.p, 0, sizeof(int32_t), c->stream));
         AG_HIP(hipStreamSynchronize(c->stream));
         if (f & AGF_NONFINITE) return ag_fail(AG_ENONFINITE, "non-finite particle position in tree build");
+        if (f & AGF_INTERNAL) return ag_fail(AG_EHIP, "internal consistency check failed in a tree kernel");
         return ag_fail(AG_EDEVICE, "index list held an out-of-range or repeated entry");
     }
     return AG_OK;
@@ -186,9 +187,9 @@ extern "C" int ag_destroy(ag_ctx* c) {
     DevBuf* bufs[] = {&c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->sort_hist, &c->perm,
                       &c->rank, &c->spos, &c->svel, &c->svf, &c->cdig, &c->pos_cnt, &c->pos_off,
                       &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
-                      &c->nd_64, &c->nd_w, &c->nd_wf, &c->lvl_cnt, &c->lvl_nodes, &c->lvl_fill,
+                      &c->nd_64, &c->nd_w, &c->nd_wf, &c->nd_parent, &c->nd_nchild, &c->nd_done,
                       &c->tree_hdr, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
-                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->sys_act, &c->wsorted,
+                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
                       &c->direct_part, &c->tmp_tidal, &c->sel_flag, &c->sel_off, &c->stats, &c->dflags};
     for (DevBuf* b : bufs) ag_release(*b);
     for (PhaseEvents& p : c->timing.pending) {
@@ -235,6 +236,7 @@ extern "C" int ag_stats_read(ag_ctx* c, ag_stats* out) {
     out->n_nodes = c->built ? h[0] : 0;
     out->n_leaf = c->built ? c->n_leaf : 0;
     out->max_level = c->built ? (int32_t)h[1] : 0;
+    out->n_groups = s[3];
     return read_flags(c);
 }
 

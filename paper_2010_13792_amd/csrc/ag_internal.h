@@ -38,7 +38,7 @@ struct DevBuf {
 };
 
 // device-side flag bits (ag_ctx::dflags)
-enum { AGF_BADINDEX = 1, AGF_NONFINITE = 2 };
+enum { AGF_BADINDEX = 1, AGF_NONFINITE = 2, AGF_INTERNAL = 4 };
 
 constexpr int AG_MAX_LEVEL = 21;   // Morton digits: 21 x 3 bits = 63-bit keys
 constexpr int AG_MAX_SYS = 512;    // batched systems: 3 octal digits of prefix
@@ -90,9 +90,9 @@ struct ag_ctx {
     DevBuf nd_64;                 // double [25]: FP64 moments (M, c, u, Q, Qd, lo, hi)
     DevBuf nd_w;                  // double [12]: vector-charge moments W0 (3), W1 (9) for the adjoint
     DevBuf nd_wf;                 // float4 x3: W0, W1 in FP32 for the adjoint walk
-    DevBuf lvl_cnt;               // i32 [AG_MAX_LEVEL + 2]
-    DevBuf lvl_nodes;             // i32 [max_nodes]: node ids bucketed by level
-    DevBuf lvl_fill;              // i32 [AG_MAX_LEVEL + 2]
+    DevBuf nd_parent;             // i32 [max_nodes]: parent node (-1 at a root)
+    DevBuf nd_nchild;             // i32 [max_nodes]: number of children
+    DevBuf nd_done;               // i32 [max_nodes]: children finished (upward moments pass)
     DevBuf tree_hdr;              // i64 [8]: n_nodes, max_level, ...
 
     DevBuf sys_off;               // i64 [n_sys+1]
@@ -104,7 +104,8 @@ struct ag_ctx {
     DevBuf act_pos;               // i32 [n]: active sorted positions, ascending
     DevBuf act_off;               // i32 [n+1]: exclusive scan of act_flag
     DevBuf grp;                   // int4 [max groups]: start, count, system, -
-    DevBuf grp_hdr;               // i32 [4 + n_sys + 1]
+    DevBuf grp_hdr;               // i32: [0] number of groups, [8..15] walk work-queue counters
+    DevBuf grp_cnt, grp_off;      // i32 [max_nodes (+1)]: groups owned per node, offsets
     DevBuf sys_act;               // i32 [n_sys + 1]
     DevBuf wsorted;               // double4 [n]: adjoint weights in sorted order
     DevBuf direct_part;           // double: direct-sum source-split partials

@@ -351,55 +351,56 @@ __device__ __forceinline__ int64_t cell_end(const TopoParams& P, const uint64_t*
     return lo;
 }
 
+// first position of the level-c cell that contains position p
+__device__ __forceinline__ int64_t cell_start(const uint64_t* __restrict__ keys, int64_t p, int c) {
+    if (c <= 0) return 0;
+    const int sh = 63 - 3 * c;
+    const uint64_t pre = keys[p] >> sh;
+    int64_t lo = 0, hi = p;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((keys[mid] >> sh) < pre) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Writes every node (link, parent) and counts each node's children.
 __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, const int32_t* __restrict__ cd,
                               const int32_t* __restrict__ off, int4* __restrict__ link,
-                              int32_t* __restrict__ lvl_cnt, int64_t* __restrict__ hdr) {
+                              int32_t* __restrict__ parent, int32_t* __restrict__ nchild,
+                              int64_t* __restrict__ hdr) {
     const int64_t n_nodes = off[P.n];
+    int maxl = 0;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int k = off[p + 1] - off[p];
         if (k == 0) continue;
         const int c = cd[p];
-        int maxl = 0;
         for (int t = 0; t < k; ++t) {
             const int l = c + 1 + t;
             const int64_t id = off[p] + t;
             int64_t e = small_cell_end(P, cd, p, l);
-            const bool leaf = (t == k - 1);
             if (e < 0) e = cell_end(P, keys, p, l);
             const int64_t skip = e < P.n ? (int64_t)off[e] : n_nodes;
+            const bool leaf = (t == k - 1);
             link[id] = make_int4((int)skip, (int)p, (int)(e - p), l | (leaf ? 0x100 : 0));
-            atomicAdd(&lvl_cnt[l], 1);
-            maxl = l;
+            int64_t par;
+            if (t > 0) {
+                par = id - 1;                       // the same position's shallower cell
+            } else if (p == 0) {
+                par = -1;                           // the root
+            } else {
+                const int64_t a = cell_start(keys, p, c);
+                par = off[a] + (c - cd[a] - 1);     // the level-c cell around p starts at a
+            }
+            parent[id] = (int32_t)par;
+            if (par >= 0) atomicAdd(&nchild[par], 1);
+            maxl = l > maxl ? l : maxl;
         }
-        atomicMax((unsigned long long*)&hdr[1], (unsigned long long)maxl);
     }
+    maxl = ag_wave_max(maxl);
+    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&hdr[1], (unsigned long long)maxl);
     if (blockIdx.x == 0 && threadIdx.x == 0) hdr[0] = n_nodes;
-}
-
-__global__ void k_level_offsets(int32_t* __restrict__ lvl_cnt, int32_t* __restrict__ lvl_fill) {
-    // lvl_cnt[0..21] counts -> lvl_cnt[22 + l] start offsets; lvl_fill zeroed
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int l = 0; l <= AG_MAX_LEVEL; ++l) {
-            lvl_cnt[AG_MAX_LEVEL + 1 + l] = acc;
-            acc += lvl_cnt[l];
-            lvl_fill[l] = 0;
-        }
-        lvl_cnt[2 * (AG_MAX_LEVEL + 1)] = acc;
-    }
-}
-
-__global__ void k_level_scatter(const int4* __restrict__ link, const int64_t* __restrict__ hdr,
-                                const int32_t* __restrict__ lvl_cnt, int32_t* __restrict__ lvl_fill,
-                                int32_t* __restrict__ lvl_nodes) {
-    const int64_t nn = hdr[0];
-    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < nn;
-         id += (int64_t)gridDim.x * blockDim.x) {
-        const int l = link[id].w & 0xff;
-        const int slot = lvl_cnt[AG_MAX_LEVEL + 1 + l] + atomicAdd(&lvl_fill[l], 1);
-        lvl_nodes[slot] = (int32_t)id;
-    }
 }
 
 __global__ void k_sys_roots(int n_sys, int sys_levels, const int64_t* __restrict__ off,
@@ -452,77 +453,110 @@ __device__ __forceinline__ void add_quad(double* Q, double* Qd, double mm, const
     }
 }
 
-__global__ void k_moments_level(int level, const int32_t* __restrict__ lvl_cnt,
-                                const int32_t* __restrict__ lvl_nodes, const int4* __restrict__ link,
-                                const double4* __restrict__ spos, const double4* __restrict__ svel,
-                                double4* __restrict__ com, float4* __restrict__ lo4, float4* __restrict__ hi4,
-                                float4* __restrict__ mp, double* __restrict__ m64) {
-    const int cnt = lvl_cnt[level];
-    const int base = lvl_cnt[AG_MAX_LEVEL + 1 + level];
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
-        const int id = lvl_nodes[base + t];
-        const int4 L = link[id];
-        double r[kM64];
+// moments of a leaf from its particles: two passes (centre of mass and mean
+// velocity, then the quadrupole and its rate about them)
+__device__ void leaf_moments(const int4 L, const double4* __restrict__ spos, const double4* __restrict__ svel,
+                             double* r) {
 #pragma unroll
-        for (int k = 0; k < kM64; ++k) r[k] = 0.0;
-        r[19] = r[20] = r[21] = DBL_MAX;
-        r[22] = r[23] = r[24] = -DBL_MAX;
-        if (L.w & 0x100) {   // leaf: from its particles
-            const int p0 = L.y, p1 = L.y + L.z;
-            for (int p = p0; p < p1; ++p) {
-                const double4 q = spos[p];
-                const double4 u = svel[p];
-                r[0] += q.w;
-                r[1] += q.w * q.x; r[2] += q.w * q.y; r[3] += q.w * q.z;
-                r[4] += q.w * u.x; r[5] += q.w * u.y; r[6] += q.w * u.z;
-                r[19] = fmin(r[19], q.x); r[20] = fmin(r[20], q.y); r[21] = fmin(r[21], q.z);
-                r[22] = fmax(r[22], q.x); r[23] = fmax(r[23], q.y); r[24] = fmax(r[24], q.z);
-            }
-            const double Mi = r[0] > 0.0 ? 1.0 / r[0] : 0.0;
-            for (int c = 1; c < 7; ++c) r[c] *= Mi;
-            if (!(r[0] > 0.0)) {   // massless cell: centre of its box
-                for (int c = 0; c < 3; ++c) r[1 + c] = 0.5 * (r[19 + c] + r[22 + c]);
-            }
-            for (int p = p0; p < p1; ++p) {
-                const double4 q = spos[p];
-                const double4 u = svel[p];
-                const double y[3] = {q.x - r[1], q.y - r[2], q.z - r[3]};
-                const double w[3] = {u.x - r[4], u.y - r[5], u.z - r[6]};
-                add_quad(r + 7, r + 13, q.w, y, w);
-            }
-        } else {             // inner node: from its children
-            const int end = L.x;
-            for (int ch = id + 1; ch < end; ch = link[ch].x) {
-                const double4 cc = com[ch];
-                const float4 q0 = mp[4 * ch];
-                const double Mc = m64[(int64_t)ch * kM64];
-                const double* cm = m64 + (int64_t)ch * kM64;
-                r[0] += Mc;
-                r[1] += Mc * cc.x; r[2] += Mc * cc.y; r[3] += Mc * cc.z;
-                r[4] += Mc * cm[4]; r[5] += Mc * cm[5]; r[6] += Mc * cm[6];
-                for (int c = 0; c < 3; ++c) {
-                    r[19 + c] = fmin(r[19 + c], cm[19 + c]);
-                    r[22 + c] = fmax(r[22 + c], cm[22 + c]);
-                }
-                (void)q0;
-            }
-            const double Mi = r[0] > 0.0 ? 1.0 / r[0] : 0.0;
-            for (int c = 1; c < 7; ++c) r[c] *= Mi;
-            if (!(r[0] > 0.0)) {
-                for (int c = 0; c < 3; ++c) r[1 + c] = 0.5 * (r[19 + c] + r[22 + c]);
-            }
-            for (int ch = id + 1; ch < end; ch = link[ch].x) {
-                const double* cm = m64 + (int64_t)ch * kM64;
-                const double y[3] = {cm[1] - r[1], cm[2] - r[2], cm[3] - r[3]};
-                const double w[3] = {cm[4] - r[4], cm[5] - r[5], cm[6] - r[6]};
-                for (int k = 0; k < 6; ++k) {
-                    r[7 + k] += cm[7 + k];
-                    r[13 + k] += cm[13 + k];
-                }
-                add_quad(r + 7, r + 13, cm[0], y, w);
-            }
+    for (int k = 0; k < kM64; ++k) r[k] = 0.0;
+    r[19] = r[20] = r[21] = DBL_MAX;
+    r[22] = r[23] = r[24] = -DBL_MAX;
+    const int p0 = L.y, p1 = L.y + L.z;
+    for (int p = p0; p < p1; ++p) {
+        const double4 q = spos[p];
+        const double4 u = svel[p];
+        r[0] += q.w;
+        r[1] += q.w * q.x; r[2] += q.w * q.y; r[3] += q.w * q.z;
+        r[4] += q.w * u.x; r[5] += q.w * u.y; r[6] += q.w * u.z;
+        r[19] = fmin(r[19], q.x); r[20] = fmin(r[20], q.y); r[21] = fmin(r[21], q.z);
+        r[22] = fmax(r[22], q.x); r[23] = fmax(r[23], q.y); r[24] = fmax(r[24], q.z);
+    }
+    const double Mi = r[0] > 0.0 ? 1.0 / r[0] : 0.0;
+    for (int c = 1; c < 7; ++c) r[c] *= Mi;
+    if (!(r[0] > 0.0))   // massless cell: centre of its box
+        for (int c = 0; c < 3; ++c) r[1 + c] = 0.5 * (r[19 + c] + r[22 + c]);
+    for (int p = p0; p < p1; ++p) {
+        const double4 q = spos[p];
+        const double4 u = svel[p];
+        const double y[3] = {q.x - r[1], q.y - r[2], q.z - r[3]};
+        const double w[3] = {u.x - r[4], u.y - r[5], u.z - r[6]};
+        add_quad(r + 7, r + 13, q.w, y, w);
+    }
+}
+
+// moments of an inner node from its children (parallel-axis shifts)
+__device__ void inner_moments(int id, const int4 L, const int4* __restrict__ link, const double* __restrict__ m64,
+                              double* r) {
+#pragma unroll
+    for (int k = 0; k < kM64; ++k) r[k] = 0.0;
+    r[19] = r[20] = r[21] = DBL_MAX;
+    r[22] = r[23] = r[24] = -DBL_MAX;
+    const int end = L.x;
+    for (int ch = id + 1, k8 = 0; ch < end && k8 < 8; ch = link[ch].x, ++k8) {
+        const double* cm = m64 + (int64_t)ch * kM64;
+        const double Mc = cm[0];
+        r[0] += Mc;
+        r[1] += Mc * cm[1]; r[2] += Mc * cm[2]; r[3] += Mc * cm[3];
+        r[4] += Mc * cm[4]; r[5] += Mc * cm[5]; r[6] += Mc * cm[6];
+        for (int c = 0; c < 3; ++c) {
+            r[19 + c] = fmin(r[19 + c], cm[19 + c]);
+            r[22 + c] = fmax(r[22 + c], cm[22 + c]);
         }
+    }
+    const double Mi = r[0] > 0.0 ? 1.0 / r[0] : 0.0;
+    for (int c = 1; c < 7; ++c) r[c] *= Mi;
+    if (!(r[0] > 0.0))
+        for (int c = 0; c < 3; ++c) r[1 + c] = 0.5 * (r[19 + c] + r[22 + c]);
+    for (int ch = id + 1, k8 = 0; ch < end && k8 < 8; ch = link[ch].x, ++k8) {
+        const double* cm = m64 + (int64_t)ch * kM64;
+        const double y[3] = {cm[1] - r[1], cm[2] - r[2], cm[3] - r[3]};
+        const double w[3] = {cm[4] - r[4], cm[5] - r[5], cm[6] - r[6]};
+        for (int k = 0; k < 6; ++k) {
+            r[7 + k] += cm[7 + k];
+            r[13 + k] += cm[13 + k];
+        }
+        add_quad(r + 7, r + 13, cm[0], y, w);
+    }
+}
+
+// One pass from the leaves up.  Each leaf stores its moments, then climbs:
+// at every parent it bumps the parent's completed-children counter, and the
+// thread that completes it (the last child to finish) combines the parent
+// from all its children and continues upward.  A parent's result is a fixed
+// function of its children, so the output does not depend on which thread
+// combines it.  Device-scope fences order each child's stores before the
+// counter update and the counter before the parent's loads.
+__global__ void k_moments_up(const int64_t* __restrict__ hdr, const int4* __restrict__ link,
+                             const int32_t* __restrict__ parent, const int32_t* __restrict__ nchild,
+                             int32_t* __restrict__ done, const double4* __restrict__ spos,
+                             const double4* __restrict__ svel, double4* __restrict__ com, float4* __restrict__ lo4,
+                             float4* __restrict__ hi4, float4* __restrict__ mp, double* __restrict__ m64,
+                             int32_t* __restrict__ flags) {
+    const int64_t nn = hdr[0];
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < nn;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int4 L = link[id];
+        if (!(L.w & 0x100)) continue;
+        double r[kM64];
+        leaf_moments(L, spos, svel, r);
         store_node(id, r, com, lo4, hi4, mp, m64);
+        int cur = (int)id;
+        int climbed = 0;
+        for (;;) {
+            const int par = parent[cur];
+            if (par < 0) break;
+            if (++climbed > AG_MAX_LEVEL + 1) {
+                atomicOr(flags, AGF_INTERNAL);
+                break;
+            }
+            __threadfence();
+            const int prev = atomicAdd(&done[par], 1);
+            if (prev != nchild[par] - 1) break;
+            __threadfence();
+            inner_moments(par, link[par], link, m64, r);
+            store_node(par, r, com, lo4, hi4, mp, m64);
+            cur = par;
+        }
     }
 }
 
@@ -556,13 +590,14 @@ int grid_for(int64_t n, int threads = kThreads) {
 }
 
 int moments_pass(ag_ctx* c) {
-    const int grid = grid_for(c->max_nodes);
-    for (int l = AG_MAX_LEVEL; l >= 0; --l) {
-        hipLaunchKernelGGL(k_moments_level, dim3(grid), dim3(kThreads), 0, c->stream, l, c->lvl_cnt.as<int32_t>(),
-                           c->lvl_nodes.as<int32_t>(), c->nd_link.as<int4>(), c->spos.as<double4>(),
-                           c->svel.as<double4>(), c->nd_com.as<double4>(), c->nd_lo.as<float4>(),
-                           c->nd_hi.as<float4>(), c->nd_mp.as<float4>(), c->nd_64.as<double>());
-    }
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->max_nodes)), dim3(kThreads), 0, st, c->nd_done.as<int32_t>(),
+                       c->max_nodes, 0);
+    hipLaunchKernelGGL(k_moments_up, dim3(grid_for(c->max_nodes)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
+                       c->nd_link.as<int4>(), c->nd_parent.as<int32_t>(), c->nd_nchild.as<int32_t>(),
+                       c->nd_done.as<int32_t>(), c->spos.as<double4>(), c->svel.as<double4>(), c->nd_com.as<double4>(),
+                       c->nd_lo.as<float4>(), c->nd_hi.as<float4>(), c->nd_mp.as<float4>(), c->nd_64.as<double>(),
+                       c->dflags.as<int32_t>());
     return AG_OK;
 }
 
@@ -576,6 +611,8 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
         if (sys_levels < 1) sys_levels = 1;
     }
     const int bits = AG_MAX_LEVEL - sys_levels;
+    // leaves <= n; at each level the split cells are disjoint and hold more
+    // than n_leaf particles (or are system-prefix cells)
     const int64_t max_nodes = n + (int64_t)(AG_MAX_LEVEL + 1) * (n / (n_leaf + 1) + n_sys) + 1;
 
     AG_TRY(ag_ensure(c->keys[0], n * 8)); AG_TRY(ag_ensure(c->keys[1], n * 8));
@@ -589,8 +626,8 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     AG_TRY(ag_ensure(c->nd_com, max_nodes * 32)); AG_TRY(ag_ensure(c->nd_lo, max_nodes * 16));
     AG_TRY(ag_ensure(c->nd_hi, max_nodes * 16)); AG_TRY(ag_ensure(c->nd_link, max_nodes * 16));
     AG_TRY(ag_ensure(c->nd_mp, max_nodes * 64)); AG_TRY(ag_ensure(c->nd_64, max_nodes * kM64 * 8));
-    AG_TRY(ag_ensure(c->lvl_cnt, 64 * 4)); AG_TRY(ag_ensure(c->lvl_fill, 64 * 4));
-    AG_TRY(ag_ensure(c->lvl_nodes, max_nodes * 4));
+    AG_TRY(ag_ensure(c->nd_parent, max_nodes * 4)); AG_TRY(ag_ensure(c->nd_nchild, max_nodes * 4));
+    AG_TRY(ag_ensure(c->nd_done, max_nodes * 4));
     AG_TRY(ag_ensure(c->sys_off, (n_sys + 1) * 8)); AG_TRY(ag_ensure(c->sys_root, (n_sys + 1) * 4));
     AG_TRY(ag_ensure(c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
 
@@ -614,25 +651,24 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     int32_t* v1 = c->vals[1].as<int32_t>();
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kThreads), 0, st, n, x, off, n_sys, bits, box, k0, v0);
 
-    // 3. sort (8 passes: result back in k0/v0)
+    // 3. sort, 8 passes; the last pass writes the permutation in place
     int32_t* hist = c->sort_hist.as<int32_t>();
     int32_t* hoff = c->pos_off.as<int32_t>();
+    int32_t* perm = c->perm.as<int32_t>();
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
         uint64_t* kin = (pass & 1) ? k1 : k0;
         uint64_t* kout = (pass & 1) ? k0 : k1;
         int32_t* vin = (pass & 1) ? v1 : v0;
-        int32_t* vout = (pass & 1) ? v0 : v1;
+        int32_t* vout = pass == 7 ? perm : ((pass & 1) ? v0 : v1);
         hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, n, shift, nblocks, hist);
         AG_TRY(ag_scan_i32(c, hist, hoff, (int64_t)256 * nblocks));
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin, vin, n, shift, nblocks, hoff,
                            kout, vout);
     }
-    // sorted keys in k0, permutation in v0
-    AG_HIP(hipMemcpyAsync(c->perm.p, v0, n * 4, hipMemcpyDeviceToDevice, st));
 
-    // 4. gather
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, st, n, c->perm.as<int32_t>(), x, v, m,
+    // 4. gather into key order
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, st, n, perm, x, v, m,
                        c->rank.as<int32_t>(), c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
 
     // 5. topology
@@ -643,15 +679,12 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     int32_t* poff = c->pos_off.as<int32_t>();
     hipLaunchKernelGGL(k_count_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, cd, pcnt);
     AG_TRY(ag_scan_i32(c, pcnt, poff, n));
-    int32_t* lvl = c->lvl_cnt.as<int32_t>();
     int64_t* hdr = c->tree_hdr.as<int64_t>();
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, lvl, (int64_t)64, 0);
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, hdr, (int64_t)8, (int64_t)0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(max_nodes)), dim3(kThreads), 0, st, c->nd_nchild.as<int32_t>(),
+                       max_nodes, 0);
     hipLaunchKernelGGL(k_write_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, k0, cd, poff,
-                       c->nd_link.as<int4>(), lvl, hdr);
-    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, st, lvl, c->lvl_fill.as<int32_t>());
-    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(max_nodes)), dim3(kThreads), 0, st, c->nd_link.as<int4>(),
-                       hdr, lvl, c->lvl_fill.as<int32_t>(), c->lvl_nodes.as<int32_t>());
+                       c->nd_link.as<int4>(), c->nd_parent.as<int32_t>(), c->nd_nchild.as<int32_t>(), hdr);
     hipLaunchKernelGGL(k_sys_roots, dim3(1), dim3(512), 0, st, n_sys, sys_levels, off, cd, poff,
                        c->sys_root.as<int32_t>());
 

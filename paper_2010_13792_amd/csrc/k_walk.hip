@@ -61,6 +61,8 @@ struct WalkOut {
     double* tidal;
     unsigned long long* stats;
     double G;
+    int32_t* flags;
+    int64_t iter_cap;   // > nodes + particles: every group finishes well within it
 };
 
 // group geometry shared by every lane (uniform values)
@@ -179,16 +181,10 @@ struct WalkLds {
     } tile;
 };
 
-__global__ void __launch_bounds__(kW) k_walk(Tree T, Groups Gr, WalkOut O, int n_groups_max, float theta2,
-                                             float eps2, float h2, float hinv) {
-    __shared__ WalkLds S;
+// Walk the tree for one group of targets (one wave).
+__device__ __forceinline__ void walk_group(WalkLds& S, const Tree& T, const Groups& Gr, const WalkOut& O,
+                                           const int4 gd, float theta2, float eps2, float h2, float hinv) {
     const int lane = threadIdx.x;
-    // XCD-aware order: consecutive groups (spatial neighbours) land on one XCD
-    const int nb = gridDim.x;
-    const int per = (nb + 7) >> 3;
-    const int g = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (g >= Gr.hdr[0] || g >= n_groups_max) return;
-    const int4 gd = Gr.grp[g];
     const int count = gd.y;
     if (count <= 0) return;
 
@@ -267,7 +263,14 @@ __global__ void __launch_bounds__(kW) k_walk(Tree T, Groups Gr, WalkOut O, int n
         __syncthreads();
     };
 
+    int64_t iters = 0;
     for (;;) {
+        // every step tests a node or lists particles, so the loop ends within
+        // (nodes + particles) steps; the cap only guards against a corrupt tree
+        if (++iters > O.iter_cap) {
+            if (lane == 0) atomicOr(O.flags, AGF_INTERNAL);
+            break;
+        }
         // 1. idle lanes take ranges from the stack
         {
             const bool idle = (ca >= cb) && pc == 0;
@@ -386,12 +389,57 @@ __global__ void __launch_bounds__(kW) k_walk(Tree T, Groups Gr, WalkOut O, int n
         atomicAdd(&O.stats[0], (unsigned long long)(n_pp * (uint64_t)count));
         atomicAdd(&O.stats[1], (unsigned long long)(n_pn * (uint64_t)count));
         atomicAdd(&O.stats[2], (unsigned long long)count);
+        atomicAdd(&O.stats[3], 1ull);
+    }
+}
+
+
+// Persistent walk: each workgroup (one wave) pops groups from eight work
+// queues, one per contiguous eighth of the (Morton-ordered) group list.  A
+// workgroup starts on queue blockIdx % 8 -- the XCD the hardware dispatches
+// it to, so spatially neighbouring groups share that XCD's L2 -- and steals
+// from the other queues when its own runs dry.
+__global__ void __launch_bounds__(kW) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
+                                             float theta2, float eps2, float h2, float hinv) {
+    __shared__ WalkLds S;
+    __shared__ int s_g;
+    const int n_groups = Gr.hdr[0];
+    const int home = blockIdx.x & 7;
+    int q = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int g = -1;
+            while (q < 8) {
+                const int qq = (home + q) & 7;
+                const int lo = (int)((int64_t)n_groups * qq / 8);
+                const int hi = (int)((int64_t)n_groups * (qq + 1) / 8);
+                const int k = atomicAdd(&qctr[qq], 1);
+                if (lo + k < hi) {
+                    g = lo + k;
+                    break;
+                }
+                ++q;
+            }
+            s_g = g;
+        }
+        __syncthreads();
+        const int g = s_g;
+        __syncthreads();
+        if (g < 0) break;
+        walk_group(S, T, Gr, O, Gr.grp[g], theta2, eps2, h2, hinv);
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // active rows -> groups
 // ---------------------------------------------------------------------------
+// A group is a run of consecutive sibling cells, each with at most 64 active
+// targets, whose parent holds more than 64 (so a group never reaches beyond
+// its parent cell), packed up to 64 targets; a leaf holding more than 64
+// active targets (coincident points at the deepest level) is cut in chunks
+// of 64.  Cells of the system-prefix levels are never packed together, so a
+// group never mixes systems.
 __global__ void k_fill0(int32_t* __restrict__ p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -419,51 +467,90 @@ __global__ void k_compact_pos(int64_t n, const int32_t* __restrict__ flag, const
         if (flag[p]) out[off[p]] = (int32_t)p;
 }
 
-// one block: per-system active counts and group offsets
-__global__ void k_group_counts(int n_sys, const int64_t* __restrict__ sys_off, const int32_t* __restrict__ off,
-                               int32_t* __restrict__ hdr, int32_t* __restrict__ sys_act) {
-    __shared__ int s_g[AG_MAX_SYS + 1];
-    for (int s = threadIdx.x; s < n_sys; s += blockDim.x) {
-        const int a0 = off[sys_off[s]];
-        const int a1 = off[sys_off[s + 1]];
-        sys_act[s] = a0;
-        if (s == n_sys - 1) sys_act[n_sys] = a1;
-        s_g[s] = (a1 - a0 + kW - 1) / kW;
+struct GroupCtx {
+    const int4* __restrict__ link;
+    const int32_t* __restrict__ aoff;   // exclusive scan of the active flags over sorted positions
+    const int64_t* __restrict__ sys_off;
+    int n_sys;
+    int sys_levels;
+};
+
+__device__ __forceinline__ int sys_of_pos(const GroupCtx& C, int64_t p) {
+    int lo = 0, hi = C.n_sys;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (C.sys_off[mid] <= p) lo = mid; else hi = mid;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int accg = 0;
-        for (int s = 0; s < n_sys; ++s) {
-            const int v = s_g[s];
-            hdr[4 + s] = accg;
-            accg += v;
-        }
-        hdr[4 + n_sys] = accg;
-        hdr[0] = accg;
-    }
+    return lo;
 }
 
-__global__ void k_group_desc(int n_sys, int64_t max_groups, const int32_t* __restrict__ hdr,
-                             const int32_t* __restrict__ sys_act, int4* __restrict__ grp) {
-    const int total = hdr[0];
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < max_groups;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        if (g >= total) {
-            grp[g] = make_int4(0, 0, 0, 0);
+// Count (out == nullptr) or write the groups node `id` is responsible for.
+__device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
+    const int4 L = C.link[id];
+    const int lvl = L.w & 0xff;
+    const bool leaf = (L.w & 0x100) != 0;
+    const int a0 = C.aoff[L.y];
+    const int a = C.aoff[L.y + L.z] - a0;
+    const bool forced = lvl < C.sys_levels;
+    const bool big = forced || a > kW;
+    int ng = 0;
+    auto emit = [&](int start, int cnt, int64_t pos) {
+        if (out) out[ng] = make_int4(start, cnt, C.n_sys > 1 ? sys_of_pos(C, pos) : 0, 0);
+        ++ng;
+    };
+    if (!big) {
+        if (id == 0 && a > 0) emit(a0, a, L.y);   // a small whole tree is one group
+        return ng;
+    }
+    if (leaf) {
+        for (int k = 0; k < a; k += kW) emit(a0 + k, a - k < kW ? a - k : kW, L.y);
+        return ng;
+    }
+    int run_start = 0, run_cnt = 0;
+    int64_t run_pos = 0;
+    for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = C.link[ch].x, ++k8) {
+        const int4 Lc = C.link[ch];
+        const int c0 = C.aoff[Lc.y];
+        const int ac = C.aoff[Lc.y + Lc.z] - c0;
+        const bool bigc = (Lc.w & 0xff) < C.sys_levels || ac > kW;
+        if (bigc || ac == 0 || forced) {
+            if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
+            run_cnt = 0;
+            if (forced && !bigc && ac > 0) emit(c0, ac, Lc.y);
             continue;
         }
-        int lo = 0, hi = n_sys;   // hdr[4+lo] <= g < hdr[4+hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (hdr[4 + mid] <= g) lo = mid; else hi = mid;
+        if (run_cnt + ac > kW) {
+            emit(run_start, run_cnt, run_pos);
+            run_cnt = 0;
         }
-        const int s = lo;
-        const int j = (int)g - hdr[4 + s];
-        const int a = sys_act[s + 1] - sys_act[s];
-        const int start = sys_act[s] + kW * j;
-        const int cnt = a - kW * j < kW ? a - kW * j : kW;
-        grp[g] = make_int4(start, cnt, s, 0);
+        if (run_cnt == 0) {
+            run_start = c0;
+            run_pos = Lc.y;
+        }
+        run_cnt += ac;
     }
+    if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
+    return ng;
+}
+
+// counts for every slot up to the node bound (zero past the last node)
+__global__ void k_group_count(GroupCtx C, const int64_t* __restrict__ hdr, int64_t max_nodes,
+                              int32_t* __restrict__ gcnt) {
+    const int64_t nn = hdr[0];
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < max_nodes;
+         id += (int64_t)gridDim.x * blockDim.x)
+        gcnt[id] = id < nn ? node_groups(C, (int)id, nullptr) : 0;
+}
+
+__global__ void k_group_emit(GroupCtx C, const int64_t* __restrict__ hdr, const int32_t* __restrict__ goff,
+                             int4* __restrict__ grp, int32_t* __restrict__ ghdr, int* __restrict__ qctr) {
+    const int64_t nn = hdr[0];
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < nn;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        if (goff[id + 1] > goff[id]) node_groups(C, (int)id, grp + goff[id]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 8) qctr[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ghdr[0] = goff[nn];
 }
 
 int grid_for(int64_t n, int threads = 256) {
@@ -476,13 +563,14 @@ int grid_for(int64_t n, int threads = 256) {
 
 int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max_groups) {
     const int64_t n = c->n;
-    const int64_t mg = (n_act + kW - 1) / kW + c->n_sys;
+    const int64_t mg = n_act + c->n_sys + 1;   // every group holds at least one target
     AG_TRY(ag_ensure(c->act_flag, n * 4));
     AG_TRY(ag_ensure(c->act_off, (n + 1) * 4));
     AG_TRY(ag_ensure(c->act_pos, n * 4));
     AG_TRY(ag_ensure(c->grp, mg * 16));
-    AG_TRY(ag_ensure(c->grp_hdr, (8 + AG_MAX_SYS + 1) * 4));
-    AG_TRY(ag_ensure(c->sys_act, (AG_MAX_SYS + 1) * 4));
+    AG_TRY(ag_ensure(c->grp_hdr, (16 + AG_MAX_SYS + 1) * 4));
+    AG_TRY(ag_ensure(c->grp_cnt, (c->max_nodes + 1) * 4));
+    AG_TRY(ag_ensure(c->grp_off, (c->max_nodes + 1) * 4));
     PhaseScope phase(c, AG_PHASE_GROUPS);
     hipStream_t st = c->stream;
     int32_t* flag = c->act_flag.as<int32_t>();
@@ -492,10 +580,15 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
                        c->dflags.as<int32_t>());
     AG_TRY(ag_scan_i32(c, flag, off, n));
     hipLaunchKernelGGL(k_compact_pos, dim3(grid_for(n)), dim3(256), 0, st, n, flag, off, c->act_pos.as<int32_t>());
-    hipLaunchKernelGGL(k_group_counts, dim3(1), dim3(512), 0, st, c->n_sys, c->sys_off.as<int64_t>(), off,
-                       c->grp_hdr.as<int32_t>(), c->sys_act.as<int32_t>());
-    hipLaunchKernelGGL(k_group_desc, dim3(grid_for(mg)), dim3(256), 0, st, c->n_sys, mg, c->grp_hdr.as<int32_t>(),
-                       c->sys_act.as<int32_t>(), c->grp.as<int4>());
+    GroupCtx C{c->nd_link.as<int4>(), off, c->sys_off.as<int64_t>(), c->n_sys, c->sys_levels};
+    const int64_t* hdr = c->tree_hdr.as<int64_t>();
+    int32_t* gcnt = c->grp_cnt.as<int32_t>();
+    int32_t* goff = c->grp_off.as<int32_t>();
+    hipLaunchKernelGGL(k_group_count, dim3(grid_for(c->max_nodes)), dim3(256), 0, st, C, hdr, c->max_nodes, gcnt);
+    AG_TRY(ag_scan_i32(c, gcnt, goff, c->max_nodes));
+    int32_t* ghdr = c->grp_hdr.as<int32_t>();
+    hipLaunchKernelGGL(k_group_emit, dim3(grid_for(c->max_nodes)), dim3(256), 0, st, C, hdr, goff,
+                       c->grp.as<int4>(), ghdr, ghdr + 8);
     *max_groups = mg;
     return AG_OK;
 }
@@ -514,19 +607,28 @@ static Tree make_tree(ag_ctx* c) {
     return T;
 }
 
+static int walk_grid(ag_ctx* c, int64_t max_groups) {
+    int dev_cus = 256;
+    (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    int64_t blocks = (int64_t)dev_cus * 16;                 // resident waves per CU at this register use
+    if (blocks > max_groups) blocks = (max_groups + 7) / 8 * 8;
+    if (blocks < 8) blocks = 8;
+    return (int)blocks;
+}
+
 int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps, double G, double* acc,
                    double* jerk, double* tidal) {
     int64_t mg = 0;
     AG_TRY(ag_prepare_groups(c, idx, n_act, &mg));
     Groups Gr{c->act_pos.as<int32_t>(), c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
-    WalkOut O{acc, jerk, tidal, c->stats.as<unsigned long long>(), G};
-    const int64_t blocks = (mg + 7) / 8 * 8;
+    WalkOut O{acc, jerk, tidal, c->stats.as<unsigned long long>(), G, c->dflags.as<int32_t>(),
+              c->max_nodes + c->n + 1024};
     const float th = (float)theta;
     const float e2 = (float)(eps * eps);
     {
         PhaseScope phase(c, AG_PHASE_WALK);
-        hipLaunchKernelGGL(k_walk, dim3((unsigned)blocks), dim3(kW), 0, c->stream, make_tree(c), Gr, O, (int)mg,
-                           th * th, e2, e2, (float)(1.0 / eps));
+        hipLaunchKernelGGL(k_walk, dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
+                           c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2, (float)(1.0 / eps));
     }
     return AG_OK;
 }
