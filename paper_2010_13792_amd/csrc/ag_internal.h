@@ -90,9 +90,8 @@ struct ag_ctx {
     DevBuf nd_64;                 // double [25]: FP64 moments (M, c, u, Q, Qd, lo, hi)
     DevBuf nd_w;                  // double [12]: vector-charge moments W0 (3), W1 (9) for the adjoint
     DevBuf nd_wf;                 // float4 x3: W0, W1 in FP32 for the adjoint walk
-    DevBuf nd_parent;             // i32 [max_nodes]: parent node (-1 at a root)
-    DevBuf nd_nchild;             // i32 [max_nodes]: number of children
-    DevBuf nd_done;               // i32 [max_nodes]: children finished (upward moments pass)
+    DevBuf in_list;               // i32 [max_nodes]: inner nodes in pre-order
+    DevBuf in_cnt, in_off;        // i32 [n+1]: inner nodes starting at each position, offsets
     DevBuf tree_hdr;              // i64 [8]: n_nodes, max_level, ...
 
     DevBuf sys_off;               // i64 [n_sys+1]

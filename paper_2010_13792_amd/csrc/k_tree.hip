@@ -331,44 +331,46 @@ __device__ __forceinline__ int nodes_at(const TopoParams& P, const int32_t* __re
     return cnt;
 }
 
-__global__ void k_count_nodes(TopoParams P, const int32_t* __restrict__ cd, int32_t* __restrict__ cnt) {
+// nodes starting at each position, and how many of them are inner nodes
+// (all but the last, which is a leaf)
+__global__ void k_count_nodes(TopoParams P, const int32_t* __restrict__ cd, int32_t* __restrict__ cnt,
+                              int32_t* __restrict__ icnt) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
-         p += (int64_t)gridDim.x * blockDim.x)
-        cnt[p] = nodes_at(P, cd, p);
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int k = nodes_at(P, cd, p);
+        cnt[p] = k;
+        icnt[p] = k > 0 ? k - 1 : 0;
+    }
 }
 
 // first position after p whose key differs from key[p] in the top l digits
+// (galloping search: cells are usually short compared with n)
 __device__ __forceinline__ int64_t cell_end(const TopoParams& P, const uint64_t* __restrict__ keys, int64_t p,
                                             int l) {
     if (l == 0) return P.n;
     const int sh = 63 - 3 * l;
     const uint64_t pre = keys[p] >> sh;
-    int64_t lo = p + 1, hi = P.n;   // answer in [lo, hi]
-    while (lo < hi) {
+    int64_t lo = p + 1, step = 16, hi = P.n;
+    while (lo + step < P.n) {
+        if ((keys[lo + step] >> sh) != pre) {
+            hi = lo + step;
+            break;
+        }
+        lo += step + 1;
+        step <<= 1;
+    }
+    while (lo < hi) {   // answer in [lo, hi]
         const int64_t mid = (lo + hi) >> 1;
         if ((keys[mid] >> sh) == pre) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
 
-// first position of the level-c cell that contains position p
-__device__ __forceinline__ int64_t cell_start(const uint64_t* __restrict__ keys, int64_t p, int c) {
-    if (c <= 0) return 0;
-    const int sh = 63 - 3 * c;
-    const uint64_t pre = keys[p] >> sh;
-    int64_t lo = 0, hi = p;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if ((keys[mid] >> sh) < pre) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// Writes every node (link, parent) and counts each node's children.
+// Writes every node's link and lists the inner nodes (in pre-order).
 __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, const int32_t* __restrict__ cd,
-                              const int32_t* __restrict__ off, int4* __restrict__ link,
-                              int32_t* __restrict__ parent, int32_t* __restrict__ nchild,
-                              int64_t* __restrict__ hdr) {
+                              const int32_t* __restrict__ off, const int32_t* __restrict__ ioff,
+                              int4* __restrict__ link, int32_t* __restrict__ ilist, int64_t* __restrict__ hdr,
+                              int32_t* __restrict__ blk_max) {
     const int64_t n_nodes = off[P.n];
     int maxl = 0;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
@@ -384,23 +386,39 @@ __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, c
             const int64_t skip = e < P.n ? (int64_t)off[e] : n_nodes;
             const bool leaf = (t == k - 1);
             link[id] = make_int4((int)skip, (int)p, (int)(e - p), l | (leaf ? 0x100 : 0));
-            int64_t par;
-            if (t > 0) {
-                par = id - 1;                       // the same position's shallower cell
-            } else if (p == 0) {
-                par = -1;                           // the root
-            } else {
-                const int64_t a = cell_start(keys, p, c);
-                par = off[a] + (c - cd[a] - 1);     // the level-c cell around p starts at a
-            }
-            parent[id] = (int32_t)par;
-            if (par >= 0) atomicAdd(&nchild[par], 1);
+            if (!leaf) ilist[ioff[p] + t] = (int32_t)id;
             maxl = l > maxl ? l : maxl;
         }
     }
+    // per-block deepest level (reduced by k_tree_header, no global atomics)
+    __shared__ int s_max[kThreads / 64];
     maxl = ag_wave_max(maxl);
-    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&hdr[1], (unsigned long long)maxl);
-    if (blockIdx.x == 0 && threadIdx.x == 0) hdr[0] = n_nodes;
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = maxl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int mb = s_max[0];
+        for (int w = 1; w < kThreads / 64; ++w) mb = s_max[w] > mb ? s_max[w] : mb;
+        blk_max[blockIdx.x] = mb;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hdr[0] = n_nodes;
+        hdr[2] = ioff[P.n];   // inner nodes
+    }
+}
+
+// hdr[1] = deepest level, from the per-block maxima of k_write_nodes
+__global__ void k_tree_header(int nblk, const int32_t* __restrict__ blk_max, int64_t* __restrict__ hdr) {
+    int m = 0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = blk_max[b] > m ? blk_max[b] : m;
+    m = ag_wave_max(m);
+    __shared__ int s_m[16];
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = s_m[w] > m ? s_m[w] : m;
+        m = s_m[0] > m ? s_m[0] : m;
+        hdr[1] = m;
+    }
 }
 
 __global__ void k_sys_roots(int n_sys, int sys_levels, const int64_t* __restrict__ off,
@@ -519,44 +537,43 @@ __device__ void inner_moments(int id, const int4 L, const int4* __restrict__ lin
     }
 }
 
-// One pass from the leaves up.  Each leaf stores its moments, then climbs:
-// at every parent it bumps the parent's completed-children counter, and the
-// thread that completes it (the last child to finish) combines the parent
-// from all its children and continues upward.  A parent's result is a fixed
-// function of its children, so the output does not depend on which thread
-// combines it.  Device-scope fences order each child's stores before the
-// counter update and the counter before the parent's loads.
-__global__ void k_moments_up(const int64_t* __restrict__ hdr, const int4* __restrict__ link,
-                             const int32_t* __restrict__ parent, const int32_t* __restrict__ nchild,
-                             int32_t* __restrict__ done, const double4* __restrict__ spos,
-                             const double4* __restrict__ svel, double4* __restrict__ com, float4* __restrict__ lo4,
-                             float4* __restrict__ hi4, float4* __restrict__ mp, double* __restrict__ m64,
-                             int32_t* __restrict__ flags) {
-    const int64_t nn = hdr[0];
-    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < nn;
-         id += (int64_t)gridDim.x * blockDim.x) {
-        const int4 L = link[id];
-        if (!(L.w & 0x100)) continue;
+struct NodeOut {
+    double4* com;
+    float4* lo4;
+    float4* hi4;
+    float4* mp;
+    double* m64;
+};
+
+// every leaf (the deepest node starting at each position) from its particles
+__global__ void k_leaf_moments(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+                               const int4* __restrict__ link, const double4* __restrict__ spos,
+                               const double4* __restrict__ svel, NodeOut O) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int k = cnt[p];
+        if (k == 0) continue;
+        const int64_t id = off[p] + k - 1;
         double r[kM64];
-        leaf_moments(L, spos, svel, r);
-        store_node(id, r, com, lo4, hi4, mp, m64);
-        int cur = (int)id;
-        int climbed = 0;
-        for (;;) {
-            const int par = parent[cur];
-            if (par < 0) break;
-            if (++climbed > AG_MAX_LEVEL + 1) {
-                atomicOr(flags, AGF_INTERNAL);
-                break;
-            }
-            __threadfence();
-            const int prev = atomicAdd(&done[par], 1);
-            if (prev != nchild[par] - 1) break;
-            __threadfence();
-            inner_moments(par, link[par], link, m64, r);
-            store_node(par, r, com, lo4, hi4, mp, m64);
-            cur = par;
-        }
+        leaf_moments(link[id], spos, svel, r);
+        store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64);
+    }
+}
+
+// inner nodes of one level from their children (one launch per level, from
+// the deepest up, so every child is complete when its parent is combined)
+__global__ void k_inner_level(int level, const int64_t* __restrict__ hdr, const int32_t* __restrict__ ilist,
+                              const int4* __restrict__ link, NodeOut O) {
+    const int64_t ni = hdr[2];
+    if (level > hdr[1]) return;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ni;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int id = ilist[t];
+        const int4 L = link[id];
+        if ((L.w & 0xff) != level) continue;
+        double r[kM64];
+        inner_moments(id, L, link, O.m64, r);
+        store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64);
     }
 }
 
@@ -591,13 +608,19 @@ int grid_for(int64_t n, int threads = kThreads) {
 
 int moments_pass(ag_ctx* c) {
     hipStream_t st = c->stream;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->max_nodes)), dim3(kThreads), 0, st, c->nd_done.as<int32_t>(),
-                       c->max_nodes, 0);
-    hipLaunchKernelGGL(k_moments_up, dim3(grid_for(c->max_nodes)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
-                       c->nd_link.as<int4>(), c->nd_parent.as<int32_t>(), c->nd_nchild.as<int32_t>(),
-                       c->nd_done.as<int32_t>(), c->spos.as<double4>(), c->svel.as<double4>(), c->nd_com.as<double4>(),
-                       c->nd_lo.as<float4>(), c->nd_hi.as<float4>(), c->nd_mp.as<float4>(), c->nd_64.as<double>(),
-                       c->dflags.as<int32_t>());
+    NodeOut O{c->nd_com.as<double4>(), c->nd_lo.as<float4>(), c->nd_hi.as<float4>(), c->nd_mp.as<float4>(),
+              c->nd_64.as<double>()};
+    const int64_t n = c->n;
+    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(n)), dim3(kThreads), 0, st, n, c->pos_cnt.as<int32_t>(),
+                       c->pos_off.as<int32_t>(), c->nd_link.as<int4>(), c->spos.as<double4>(), c->svel.as<double4>(),
+                       O);
+    // level-21 cells are always leaves; empty levels exit at once
+    const int64_t inner_bound = c->max_nodes - n;
+    int g = grid_for(inner_bound > 0 ? inner_bound : 1);
+    if (g > 128) g = 128;
+    for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
+        hipLaunchKernelGGL(k_inner_level, dim3(g), dim3(kThreads), 0, st, l, c->tree_hdr.as<int64_t>(),
+                           c->in_list.as<int32_t>(), c->nd_link.as<int4>(), O);
     return AG_OK;
 }
 
@@ -626,8 +649,8 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     AG_TRY(ag_ensure(c->nd_com, max_nodes * 32)); AG_TRY(ag_ensure(c->nd_lo, max_nodes * 16));
     AG_TRY(ag_ensure(c->nd_hi, max_nodes * 16)); AG_TRY(ag_ensure(c->nd_link, max_nodes * 16));
     AG_TRY(ag_ensure(c->nd_mp, max_nodes * 64)); AG_TRY(ag_ensure(c->nd_64, max_nodes * kM64 * 8));
-    AG_TRY(ag_ensure(c->nd_parent, max_nodes * 4)); AG_TRY(ag_ensure(c->nd_nchild, max_nodes * 4));
-    AG_TRY(ag_ensure(c->nd_done, max_nodes * 4));
+    AG_TRY(ag_ensure(c->in_list, max_nodes * 4)); AG_TRY(ag_ensure(c->in_cnt, (n + 1) * 4));
+    AG_TRY(ag_ensure(c->in_off, (n + 1) * 4));
     AG_TRY(ag_ensure(c->sys_off, (n_sys + 1) * 8)); AG_TRY(ag_ensure(c->sys_root, (n_sys + 1) * 4));
     AG_TRY(ag_ensure(c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
 
@@ -677,14 +700,18 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     TopoParams P{n, n_leaf, sys_levels};
     int32_t* pcnt = c->pos_cnt.as<int32_t>();
     int32_t* poff = c->pos_off.as<int32_t>();
-    hipLaunchKernelGGL(k_count_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, cd, pcnt);
+    int32_t* icnt = c->in_cnt.as<int32_t>();
+    int32_t* ioff = c->in_off.as<int32_t>();
+    hipLaunchKernelGGL(k_count_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, cd, pcnt, icnt);
     AG_TRY(ag_scan_i32(c, pcnt, poff, n));
+    AG_TRY(ag_scan_i32(c, icnt, ioff, n));
     int64_t* hdr = c->tree_hdr.as<int64_t>();
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, hdr, (int64_t)8, (int64_t)0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(max_nodes)), dim3(kThreads), 0, st, c->nd_nchild.as<int32_t>(),
-                       max_nodes, 0);
-    hipLaunchKernelGGL(k_write_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, k0, cd, poff,
-                       c->nd_link.as<int4>(), c->nd_parent.as<int32_t>(), c->nd_nchild.as<int32_t>(), hdr);
+    const int wblocks = grid_for(n);
+    int32_t* blk_max = c->sort_hist.as<int32_t>();   // free after the sort; >= 256 nblocks entries
+    hipLaunchKernelGGL(k_write_nodes, dim3(wblocks), dim3(kThreads), 0, st, P, k0, cd, poff, ioff,
+                       c->nd_link.as<int4>(), c->in_list.as<int32_t>(), hdr, blk_max);
+    hipLaunchKernelGGL(k_tree_header, dim3(1), dim3(1024), 0, st, wblocks, blk_max, hdr);
     hipLaunchKernelGGL(k_sys_roots, dim3(1), dim3(512), 0, st, n_sys, sys_levels, off, cd, poff,
                        c->sys_root.as<int32_t>());
 

@@ -47,6 +47,8 @@ struct Tree {
     const float4* __restrict__ svf;    // sorted vx, vy, vz, m
     const int32_t* __restrict__ perm;
     const int32_t* __restrict__ sys_root;
+    const double4* __restrict__ ws;    // adjoint: sorted weights (w, 1 if charged)
+    const float4* __restrict__ wf;     // adjoint: node charges, 4 per node
 };
 
 struct Groups {
@@ -63,6 +65,9 @@ struct WalkOut {
     double G;
     int32_t* flags;
     int64_t iter_cap;   // > nodes + particles: every group finishes well within it
+    double* dldx;       // adjoint outputs
+    double* dldm;
+    const double* tin;  // adjoint: tidal tensor rows of the charged targets
 };
 
 // group geometry shared by every lane (uniform values)
@@ -171,18 +176,233 @@ __device__ __forceinline__ void fold(PairAcc<double>& D, const PairAcc<float>& F
 }
 
 // LDS of one wave
+template <int NT>
 struct WalkLds {
     int plist[kPCap];
     int nlist[kNCap];
     int2 stack[kSCap];
-    union {
-        struct { float4 pos[kW]; float4 vel[kW]; int idx[kW]; } p;
-        struct { float4 d[5 * kW]; } n;
-    } tile;
+    float4 tile[NT * kW];  // one staged tile of sources (layout set by the policy)
+    int tidx[kW];          // sorted index of each staged particle (self exclusion)
+};
+
+struct Target {
+    float tx, ty, tz;      // position relative to the group centre
+    float vx, vy, vz;
+    int p;                 // sorted position (-1 for an idle lane)
+};
+
+// ---- forward: g, j and S = -T from particle masses and node multipoles ----
+struct ForwardPolicy {
+    static constexpr bool kSkipEmpty = false;
+    using Lds = WalkLds<5>;
+    struct Acc {
+        PairAcc<double> a;
+        __device__ void zero() { a.zero(); }
+    };
+    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk) {
+        const double4 q = T.spos[pk];
+        const float4 u = T.svf[pk];
+        S.tile[lane] = make_float4((float)(q.x - gb.cx), (float)(q.y - gb.cy), (float)(q.z - gb.cz), u.w);
+        S.tile[kW + lane] = u;
+        S.tidx[lane] = pk;
+    }
+    __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv) {
+        PairAcc<float> F;
+        F.zero();
+        for (int k = 0; k < cnt; ++k) {
+            const float4 q = S.tile[k];
+            const float4 u = S.tile[kW + k];
+            const float mj = (S.tidx[k] == t.p) ? 0.f : q.w;
+            pair_interact<float>(q.x - t.tx, q.y - t.ty, q.z - t.tz, u.x - t.vx, u.y - t.vy, u.z - t.vz, mj, h2,
+                                 hinv, F);
+        }
+        fold(acc.a, F);
+    }
+    __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk) {
+        const double4 c = T.com[nk];
+        const float4 m0 = T.mp[4 * nk], m1 = T.mp[4 * nk + 1], m2 = T.mp[4 * nk + 2], m3 = T.mp[4 * nk + 3];
+        float4* d = S.tile;
+        d[lane] = make_float4((float)(c.x - gb.cx), (float)(c.y - gb.cy), (float)(c.z - gb.cz), m0.x);
+        d[kW + lane] = make_float4(m0.y, m0.z, m0.w, m1.x);       // u, Qxx
+        d[2 * kW + lane] = make_float4(m1.y, m1.z, m1.w, m2.x);   // Qyy Qzz Qxy Qxz
+        d[3 * kW + lane] = make_float4(m2.y, m2.z, m2.w, m3.x);   // Qyz, Qd xx yy zz
+        d[4 * kW + lane] = make_float4(m3.y, m3.z, m3.w, 0.f);    // Qd xy xz yz
+    }
+    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc) {
+        PairAcc<float> F;
+        F.zero();
+        const float4* d = S.tile;
+        for (int k = 0; k < cnt; ++k) {
+            const float4 a0 = d[k], a1 = d[kW + k], a2 = d[2 * kW + k], a3 = d[3 * kW + k], a4 = d[4 * kW + k];
+            const float Q[6] = {a1.w, a2.x, a2.y, a2.z, a2.w, a3.x};
+            const float Qd[6] = {a3.y, a3.z, a3.w, a4.x, a4.y, a4.z};
+            node_interact(a0.x - t.tx, a0.y - t.ty, a0.z - t.tz, a1.x - t.vx, a1.y - t.vy, a1.z - t.vz, a0.w, Q, Qd,
+                          F);
+        }
+        fold(acc.a, F);
+    }
+    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p) {
+        const PairAcc<double>& acc = A.a;
+        const int64_t i = T.perm[p];
+        const double G = O.G;
+        if (O.acc) {
+            O.acc[3 * i] = G * acc.ax; O.acc[3 * i + 1] = G * acc.ay; O.acc[3 * i + 2] = G * acc.az;
+        }
+        if (O.jerk) {
+            O.jerk[3 * i] = G * acc.jx; O.jerk[3 * i + 1] = G * acc.jy; O.jerk[3 * i + 2] = G * acc.jz;
+        }
+        if (O.tidal) {
+            double* tt = O.tidal + 6 * i;
+            tt[0] = -G * acc.sxx; tt[1] = -G * acc.syy; tt[2] = -G * acc.szz;
+            tt[3] = -G * acc.sxy; tt[4] = -G * acc.sxz; tt[5] = -G * acc.syz;
+        }
+    }
+};
+
+// ---- adjoint: V = sum_j J(d) w_j and s = sum_j f d.w_j over vector charges ----
+// For a node with charge sum W0 = sum w and first moment W1_bc = sum w_b y_c
+// (y = position - node centre of mass), to first order in y:
+//   V = f W0 + D (d.W0) d + D (W1 d + W1^T d + tr(W1) d) + E (d.W1.d) d
+//   s = f d.W0 + f tr(W1) + D (d.W1.d)
+// with f = r^-3, D = f'/r = -3 r^-5, E = D'/r = 15 r^-7 (nodes are only used
+// at separations beyond the softening length).
+struct AdjAccF {
+    float vx, vy, vz, s;
+};
+struct AdjointPolicy {
+    static constexpr bool kSkipEmpty = true;   // nodes without charge add nothing
+    using Lds = WalkLds<9>;
+    struct Acc {
+        double vx, vy, vz, s;
+        __device__ void zero() { vx = vy = vz = s = 0.0; }
+    };
+    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk) {
+        const double4 q = T.spos[pk];
+        const double4 w = T.ws[pk];
+        S.tile[lane] = make_float4((float)(q.x - gb.cx), (float)(q.y - gb.cy), (float)(q.z - gb.cz), 0.f);
+        S.tile[kW + lane] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.f);
+        S.tidx[lane] = pk;
+    }
+    __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv) {
+        AdjAccF F{0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < cnt; ++k) {
+            const float4 q = S.tile[k];
+            const float4 w = S.tile[kW + k];
+            const float dx = q.x - t.tx, dy = q.y - t.ty, dz = q.z - t.tz;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            float f, D;
+            if (r2 >= h2) {
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                const float ri2 = ri * ri;
+                f = ri * ri2;
+                D = -3.f * f * ri2;
+            } else {
+                spline_fd<float>(r2, hinv, f, D);
+            }
+            const float self = (S.tidx[k] == t.p) ? 0.f : 1.f;
+            f *= self;
+            D *= self;
+            const float dw = dx * w.x + dy * w.y + dz * w.z;
+            const float Ddw = D * dw;
+            F.vx += f * w.x + Ddw * dx;
+            F.vy += f * w.y + Ddw * dy;
+            F.vz += f * w.z + Ddw * dz;
+            F.s += f * dw;
+        }
+        acc.vx += F.vx; acc.vy += F.vy; acc.vz += F.vz; acc.s += F.s;
+    }
+    __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk) {
+        const double4 c = T.com[nk];
+        float4* d = S.tile;
+        d[lane] = make_float4((float)(c.x - gb.cx), (float)(c.y - gb.cy), (float)(c.z - gb.cz), 0.f);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d[(q + 1) * kW + lane] = T.wf[8 * nk + q];
+    }
+    // Second-order term with W2_bce = sum w_b y_c y_e (symmetric in c, e):
+    //   V += -1/2 [105 t d/r^9 - 15 (d (d.trW + 2 d.trX) + 2 s + u)/r^7
+    //              + 3 (trW + 2 trX)/r^5]
+    //   s += 7.5 t/r^7 - 1.5 (d.trW + 2 d.trX)/r^5
+    // u_b = W2_bce d_c d_e, s_e = W2_bce d_b d_c, t = d.u, trW_b = W2_bcc,
+    // trX_c = W2_bbc.
+    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc) {
+        AdjAccF F{0.f, 0.f, 0.f, 0.f};
+        const float4* d = S.tile;
+        for (int k = 0; k < cnt; ++k) {
+            const float4 c = d[k], a0 = d[kW + k], a1 = d[2 * kW + k], a2 = d[3 * kW + k], a3 = d[4 * kW + k];
+            const float4 a4 = d[5 * kW + k], a5 = d[6 * kW + k], a6 = d[7 * kW + k], a7 = d[8 * kW + k];
+            // W0 = a0.xyz; W1 rows: (a1.x a1.y a1.z) (a1.w a2.x a2.y) (a2.z a2.w a3.x);
+            // W2_b (xx yy zz xy xz yz): b=0 (a3.y a3.z a3.w a4.x a4.y a4.z),
+            // b=1 (a4.w a5.x a5.y a5.z a5.w a6.x), b=2 (a6.y a6.z a6.w a7.x a7.y a7.z)
+            const float dx = c.x - t.tx, dy = c.y - t.ty, dz = c.z - t.tz;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float ri2 = ri * ri;
+            const float f = ri * ri2;
+            const float D = -3.f * f * ri2;
+            const float E = -5.f * D * ri2;
+            const float W00 = a1.x, W01 = a1.y, W02 = a1.z, W10 = a1.w, W11 = a2.x, W12 = a2.y;
+            const float W20 = a2.z, W21 = a2.w, W22 = a3.x;
+            const float Ax = W00 * dx + W01 * dy + W02 * dz;   // W1 d
+            const float Ay = W10 * dx + W11 * dy + W12 * dz;
+            const float Az = W20 * dx + W21 * dy + W22 * dz;
+            const float Bx = W00 * dx + W10 * dy + W20 * dz;   // W1^T d
+            const float By = W01 * dx + W11 * dy + W21 * dz;
+            const float Bz = W02 * dx + W12 * dy + W22 * dz;
+            const float tr = W00 + W11 + W22;
+            const float dWd = dx * Ax + dy * Ay + dz * Az;
+            const float dW0 = dx * a0.x + dy * a0.y + dz * a0.z;
+            // second moment: M_b = W2_b d (symmetric matrix times d)
+            const float b0[6] = {a3.y, a3.z, a3.w, a4.x, a4.y, a4.z};
+            const float b1[6] = {a4.w, a5.x, a5.y, a5.z, a5.w, a6.x};
+            const float b2[6] = {a6.y, a6.z, a6.w, a7.x, a7.y, a7.z};
+            const float M0x = b0[0] * dx + b0[3] * dy + b0[4] * dz, M0y = b0[3] * dx + b0[1] * dy + b0[5] * dz,
+                        M0z = b0[4] * dx + b0[5] * dy + b0[2] * dz;
+            const float M1x = b1[0] * dx + b1[3] * dy + b1[4] * dz, M1y = b1[3] * dx + b1[1] * dy + b1[5] * dz,
+                        M1z = b1[4] * dx + b1[5] * dy + b1[2] * dz;
+            const float M2x = b2[0] * dx + b2[3] * dy + b2[4] * dz, M2y = b2[3] * dx + b2[1] * dy + b2[5] * dz,
+                        M2z = b2[4] * dx + b2[5] * dy + b2[2] * dz;
+            const float ux = dx * M0x + dy * M0y + dz * M0z;   // u_b = d.M_b
+            const float uy = dx * M1x + dy * M1y + dz * M1z;
+            const float uz = dx * M2x + dy * M2y + dz * M2z;
+            const float sx = dx * M0x + dy * M1x + dz * M2x;   // s = sum_b d_b M_b
+            const float sy = dx * M0y + dy * M1y + dz * M2y;
+            const float sz = dx * M0z + dy * M1z + dz * M2z;
+            const float tt = dx * ux + dy * uy + dz * uz;
+            const float tWx = b0[0] + b0[1] + b0[2], tWy = b1[0] + b1[1] + b1[2], tWz = b2[0] + b2[1] + b2[2];
+            const float tXx = b0[0] + b1[3] + b2[4], tXy = b0[3] + b1[1] + b2[5], tXz = b0[4] + b1[5] + b2[2];
+            const float ri5 = f * ri2, ri7 = ri5 * ri2, ri9 = ri7 * ri2;
+            const float dtr = dx * (tWx + 2.f * tXx) + dy * (tWy + 2.f * tXy) + dz * (tWz + 2.f * tXz);
+            const float c2 = -52.5f * tt * ri9 + 7.5f * dtr * ri7;   // coefficient of d
+            const float cd = D * dW0 + D * tr + E * dWd + c2;
+            F.vx += f * a0.x + cd * dx + D * (Ax + Bx) + 7.5f * ri7 * (2.f * sx + ux) - 1.5f * ri5 * (tWx + 2.f * tXx);
+            F.vy += f * a0.y + cd * dy + D * (Ay + By) + 7.5f * ri7 * (2.f * sy + uy) - 1.5f * ri5 * (tWy + 2.f * tXy);
+            F.vz += f * a0.z + cd * dz + D * (Az + Bz) + 7.5f * ri7 * (2.f * sz + uz) - 1.5f * ri5 * (tWz + 2.f * tXz);
+            F.s += f * (dW0 + tr) + D * dWd + 7.5f * tt * ri7 - 1.5f * dtr * ri5;
+        }
+        acc.vx += F.vx; acc.vy += F.vy; acc.vz += F.vz; acc.s += F.s;
+    }
+    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p) {
+        const int64_t i = T.perm[p];
+        const double G = O.G;
+        const double mi = T.spos[p].w;
+        const double4 w = T.ws[p];
+        double gx = G * mi * A.vx, gy = G * mi * A.vy, gz = G * mi * A.vz;
+        if (w.x != 0.0 || w.y != 0.0 || w.z != 0.0) {   // target's own term T_i w_i
+            const double* t = O.tin + 6 * i;
+            gx += t[0] * w.x + t[3] * w.y + t[4] * w.z;
+            gy += t[3] * w.x + t[1] * w.y + t[5] * w.z;
+            gz += t[4] * w.x + t[5] * w.y + t[2] * w.z;
+        }
+        O.dldx[3 * i] = gx;
+        O.dldx[3 * i + 1] = gy;
+        O.dldx[3 * i + 2] = gz;
+        O.dldm[i] = -G * A.s;
+    }
 };
 
 // Walk the tree for one group of targets (one wave).
-__device__ __forceinline__ void walk_group(WalkLds& S, const Tree& T, const Groups& Gr, const WalkOut& O,
+template <class Pol>
+__device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, const Groups& Gr, const WalkOut& O,
                                            const int4 gd, float theta2, float eps2, float h2, float hinv) {
     const int lane = threadIdx.x;
     const int count = gd.y;
@@ -191,14 +411,19 @@ __device__ __forceinline__ void walk_group(WalkLds& S, const Tree& T, const Grou
     // ---- targets ----
     const bool valid = lane < count;
     const int p_i = valid ? Gr.act_pos[gd.x + lane] : -1;
-    double4 xi = valid ? T.spos[p_i] : make_double4(0, 0, 0, 0);
-    float4 vi = valid ? T.svf[p_i] : make_float4(0, 0, 0, 0);
+    const double4 xi = valid ? T.spos[p_i] : make_double4(0, 0, 0, 0);
+    const float4 vi = valid ? T.svf[p_i] : make_float4(0, 0, 0, 0);
     const GroupBox gb = group_box(valid, xi.x, xi.y, xi.z);
-    const float tx = valid ? (float)(xi.x - gb.cx) : 0.f;
-    const float ty = valid ? (float)(xi.y - gb.cy) : 0.f;
-    const float tz = valid ? (float)(xi.z - gb.cz) : 0.f;
+    Target tg;
+    tg.tx = valid ? (float)(xi.x - gb.cx) : 0.f;
+    tg.ty = valid ? (float)(xi.y - gb.cy) : 0.f;
+    tg.tz = valid ? (float)(xi.z - gb.cz) : 0.f;
+    tg.vx = vi.x;
+    tg.vy = vi.y;
+    tg.vz = vi.z;
+    tg.p = p_i;
 
-    PairAcc<double> acc;
+    typename Pol::Acc acc;
     acc.zero();
     uint64_t n_pp = 0, n_pn = 0;
 
@@ -214,51 +439,16 @@ __device__ __forceinline__ void walk_group(WalkLds& S, const Tree& T, const Grou
     int npend = 0, ppend = 0;    // list fills (uniform)
 
     auto flush_particles = [&](int base, int cnt) {
-        // stage
-        if (lane < cnt) {
-            const int pk = S.plist[base + lane];
-            const double4 q = T.spos[pk];
-            const float4 u = T.svf[pk];
-            S.tile.p.pos[lane] = make_float4((float)(q.x - gb.cx), (float)(q.y - gb.cy), (float)(q.z - gb.cz), u.w);
-            S.tile.p.vel[lane] = u;
-            S.tile.p.idx[lane] = pk;
-        }
+        if (lane < cnt) Pol::stage_particle(S, T, gb, lane, S.plist[base + lane]);
         __syncthreads();
-        PairAcc<float> F;
-        F.zero();
-        for (int k = 0; k < cnt; ++k) {
-            const float4 q = S.tile.p.pos[k];
-            const float4 u = S.tile.p.vel[k];
-            const float mj = (S.tile.p.idx[k] == p_i) ? 0.f : q.w;
-            pair_interact<float>(q.x - tx, q.y - ty, q.z - tz, u.x - vi.x, u.y - vi.y, u.z - vi.z, mj, h2, hinv, F);
-        }
-        fold(acc, F);
+        Pol::particles(S, cnt, tg, acc, h2, hinv);
         n_pp += (uint64_t)cnt;
         __syncthreads();
     };
     auto flush_nodes = [&](int base, int cnt) {
-        if (lane < cnt) {
-            const int nk = S.nlist[base + lane];
-            const double4 c = T.com[nk];
-            const float4 m0 = T.mp[4 * nk], m1 = T.mp[4 * nk + 1], m2 = T.mp[4 * nk + 2], m3 = T.mp[4 * nk + 3];
-            float4* d = S.tile.n.d;
-            d[lane] = make_float4((float)(c.x - gb.cx), (float)(c.y - gb.cy), (float)(c.z - gb.cz), m0.x);
-            d[kW + lane] = make_float4(m0.y, m0.z, m0.w, m1.x);       // u, Qxx
-            d[2 * kW + lane] = make_float4(m1.y, m1.z, m1.w, m2.x);   // Qyy Qzz Qxy Qxz
-            d[3 * kW + lane] = make_float4(m2.y, m2.z, m2.w, m3.x);   // Qyz, Qd xx yy zz
-            d[4 * kW + lane] = make_float4(m3.y, m3.z, m3.w, 0.f);    // Qd xy xz yz
-        }
+        if (lane < cnt) Pol::stage_node(S, T, gb, lane, S.nlist[base + lane]);
         __syncthreads();
-        PairAcc<float> F;
-        F.zero();
-        const float4* d = S.tile.n.d;
-        for (int k = 0; k < cnt; ++k) {
-            const float4 a0 = d[k], a1 = d[kW + k], a2 = d[2 * kW + k], a3 = d[3 * kW + k], a4 = d[4 * kW + k];
-            const float Q[6] = {a1.w, a2.x, a2.y, a2.z, a2.w, a3.x};
-            const float Qd[6] = {a3.y, a3.z, a3.w, a4.x, a4.y, a4.z};
-            node_interact(a0.x - tx, a0.y - ty, a0.z - tz, a1.x - vi.x, a1.y - vi.y, a1.z - vi.z, a0.w, Q, Qd, F);
-        }
-        fold(acc, F);
+        Pol::nodes(S, cnt, tg, acc);
         n_pn += (uint64_t)cnt;
         __syncthreads();
     };
@@ -299,21 +489,25 @@ __device__ __forceinline__ void walk_group(WalkLds& S, const Tree& T, const Grou
             const int a = ca;
             const int4 L = T.link[a];
             const bool leaf = (L.w & 0x100) != 0;
-            const bool acc_ok = mac_accept(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2);
-            if (acc_ok && L.z > kSmallNode) {
-                push_node = a;
-                ca = L.x;
-            } else if (acc_ok || leaf) {
-                ps = L.y;
-                pc = L.z;
-                ca = L.x;
-            } else {                       // open an inner node
-                if (L.x < cb) {            // siblings remain: offer them to the stack
-                    want_push = true;
-                    push_range_a = L.x;
-                    push_range_b = cb;
+            if (Pol::kSkipEmpty && T.wf[8 * a].w == 0.f) {
+                ca = L.x;                  // no charge below this node
+            } else {
+                const bool acc_ok = mac_accept(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2);
+                if (acc_ok && L.z > kSmallNode) {
+                    push_node = a;
+                    ca = L.x;
+                } else if (acc_ok || leaf) {
+                    ps = L.y;
+                    pc = L.z;
+                    ca = L.x;
+                } else {                   // open an inner node
+                    if (L.x < cb) {        // siblings remain: offer them to the stack
+                        want_push = true;
+                        push_range_a = L.x;
+                        push_range_b = cb;
+                    }
+                    ca = a + 1;
                 }
-                ca = a + 1;
             }
         }
         // 3a. accepted nodes -> node list (always fits: npend < 64 here)
@@ -369,22 +563,7 @@ __device__ __forceinline__ void walk_group(WalkLds& S, const Tree& T, const Grou
     if (npend > 0) flush_nodes(0, npend);
     if (ppend > 0) flush_particles(0, ppend);
 
-    // ---- results ----
-    if (valid) {
-        const int64_t i = T.perm[p_i];
-        const double G = O.G;
-        if (O.acc) {
-            O.acc[3 * i] = G * acc.ax; O.acc[3 * i + 1] = G * acc.ay; O.acc[3 * i + 2] = G * acc.az;
-        }
-        if (O.jerk) {
-            O.jerk[3 * i] = G * acc.jx; O.jerk[3 * i + 1] = G * acc.jy; O.jerk[3 * i + 2] = G * acc.jz;
-        }
-        if (O.tidal) {
-            double* t = O.tidal + 6 * i;
-            t[0] = -G * acc.sxx; t[1] = -G * acc.syy; t[2] = -G * acc.szz;
-            t[3] = -G * acc.sxy; t[4] = -G * acc.sxz; t[5] = -G * acc.syz;
-        }
-    }
+    if (valid) Pol::finish(T, O, acc, p_i);
     if (lane == 0 && O.stats) {
         atomicAdd(&O.stats[0], (unsigned long long)(n_pp * (uint64_t)count));
         atomicAdd(&O.stats[1], (unsigned long long)(n_pn * (uint64_t)count));
@@ -393,15 +572,15 @@ __device__ __forceinline__ void walk_group(WalkLds& S, const Tree& T, const Grou
     }
 }
 
-
 // Persistent walk: each workgroup (one wave) pops groups from eight work
 // queues, one per contiguous eighth of the (Morton-ordered) group list.  A
 // workgroup starts on queue blockIdx % 8 -- the XCD the hardware dispatches
 // it to, so spatially neighbouring groups share that XCD's L2 -- and steals
 // from the other queues when its own runs dry.
+template <class Pol>
 __global__ void __launch_bounds__(kW) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
                                              float theta2, float eps2, float h2, float hinv) {
-    __shared__ WalkLds S;
+    __shared__ typename Pol::Lds S;
     __shared__ int s_g;
     const int n_groups = Gr.hdr[0];
     const int home = blockIdx.x & 7;
@@ -426,7 +605,7 @@ __global__ void __launch_bounds__(kW) k_walk(Tree T, Groups Gr, WalkOut O, int* 
         const int g = s_g;
         __syncthreads();
         if (g < 0) break;
-        walk_group(S, T, Gr, O, Gr.grp[g], theta2, eps2, h2, hinv);
+        walk_group<Pol>(S, T, Gr, O, Gr.grp[g], theta2, eps2, h2, hinv);
         __syncthreads();
     }
 }
@@ -446,18 +625,40 @@ __global__ void k_fill0(int32_t* __restrict__ p, int64_t n) {
         p[i] = 0;
 }
 
-__global__ void k_mark(int64_t n_act, const int32_t* __restrict__ idx, int64_t n, const int32_t* __restrict__ rank,
-                       int32_t* __restrict__ flag, int32_t* __restrict__ flags) {
+// Active rows -> flags over sorted positions, without atomics: every listed
+// entry k stamps k + 1 at its position, then each entry checks that its own
+// stamp survived (a repeated row loses to one of its copies) and sets the flag.
+__global__ void k_mark_stamp(int64_t n_act, const int32_t* __restrict__ idx, int64_t n,
+                             const int32_t* __restrict__ rank, int32_t* __restrict__ stamp,
+                             int32_t* __restrict__ flags) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_act;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = idx ? (int64_t)idx[k] : k;
+        const int64_t i = idx[k];
         if (i < 0 || i >= n) {
             atomicOr(flags, AGF_BADINDEX);
             continue;
         }
-        const int p = rank[i];
-        if (atomicOr(&flag[p], 1) & 1) atomicOr(flags, AGF_BADINDEX);
+        stamp[rank[i]] = (int32_t)(k + 1);
     }
+}
+
+__global__ void k_mark_check(int64_t n_act, const int32_t* __restrict__ idx, int64_t n,
+                             const int32_t* __restrict__ rank, const int32_t* __restrict__ stamp,
+                             int32_t* __restrict__ flag, int32_t* __restrict__ flags) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_act;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx[k];
+        if (i < 0 || i >= n) continue;
+        const int p = rank[i];
+        if (stamp[p] == (int32_t)(k + 1)) flag[p] = 1;
+        else atomicOr(flags, AGF_BADINDEX);
+    }
+}
+
+__global__ void k_fill1(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 1;
 }
 
 __global__ void k_compact_pos(int64_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
@@ -575,9 +776,16 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
     hipStream_t st = c->stream;
     int32_t* flag = c->act_flag.as<int32_t>();
     int32_t* off = c->act_off.as<int32_t>();
-    hipLaunchKernelGGL(k_fill0, dim3(grid_for(n)), dim3(256), 0, st, flag, n);
-    hipLaunchKernelGGL(k_mark, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, idx, n, c->rank.as<int32_t>(), flag,
-                       c->dflags.as<int32_t>());
+    if (idx) {
+        hipLaunchKernelGGL(k_fill0, dim3(grid_for(n)), dim3(256), 0, st, flag, n);
+        // the scan output doubles as the stamp array until the scan runs
+        hipLaunchKernelGGL(k_mark_stamp, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, idx, n,
+                           c->rank.as<int32_t>(), off, c->dflags.as<int32_t>());
+        hipLaunchKernelGGL(k_mark_check, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, idx, n,
+                           c->rank.as<int32_t>(), off, flag, c->dflags.as<int32_t>());
+    } else {
+        hipLaunchKernelGGL(k_fill1, dim3(grid_for(n)), dim3(256), 0, st, flag, n);
+    }
     AG_TRY(ag_scan_i32(c, flag, off, n));
     hipLaunchKernelGGL(k_compact_pos, dim3(grid_for(n)), dim3(256), 0, st, n, flag, off, c->act_pos.as<int32_t>());
     GroupCtx C{c->nd_link.as<int4>(), off, c->sys_off.as<int64_t>(), c->n_sys, c->sys_levels};
@@ -593,6 +801,117 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
     return AG_OK;
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// vector-charge moments of the adjoint weights
+// ---------------------------------------------------------------------------
+// per node (FP64, 31 doubles): W0 (3), W1 row-major (9: W1_bc = sum w_b y_c),
+// W2 (18: for b = x, y, z the symmetric sum w_b y y^T as xx yy zz xy xz yz),
+// number of charged particles; FP32 copy as 8 float4 (W0 + count, W1, W2).
+constexpr int kW64 = 31;
+
+__device__ void store_w(int64_t id, const double* r, double* __restrict__ w64, float4* __restrict__ wf) {
+    double* o = w64 + id * kW64;
+#pragma unroll
+    for (int k = 0; k < kW64; ++k) o[k] = r[k];
+    float4* f = wf + 8 * id;
+    f[0] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[30]);
+#pragma unroll
+    for (int q = 1; q < 8; ++q)
+        f[q] = make_float4((float)r[4 * q - 1], (float)r[4 * q], (float)r[4 * q + 1],
+                           q < 7 ? (float)r[4 * q + 2] : 0.f);
+}
+
+// sum_w w_b y_c y_e over the 6 symmetric (c, e) pairs into W2 (18 entries)
+__device__ __forceinline__ void add_w2(double* W2, const double* wv, const double* y) {
+    const int a[6] = {0, 1, 2, 0, 0, 1}, b[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) W2[6 * bb + k] += wv[bb] * y[a[k]] * y[b[k]];
+}
+
+// sorted weights: w of active rows, zero elsewhere
+__global__ void k_gather_w(int64_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ flag,
+                           const double* __restrict__ w, double4* __restrict__ ws) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = perm[p];
+        ws[p] = flag[p] ? make_double4(w[3 * i], w[3 * i + 1], w[3 * i + 2], 1.0) : make_double4(0, 0, 0, 0);
+    }
+}
+
+__global__ void k_leaf_wmoments(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+                                const int4* __restrict__ link, const double* __restrict__ m64,
+                                const double4* __restrict__ spos, const double4* __restrict__ ws,
+                                double* __restrict__ w64, float4* __restrict__ wf) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int k = cnt[p];
+        if (k == 0) continue;
+        const int64_t id = off[p] + k - 1;
+        const int4 L = link[id];
+        const double* c = m64 + id * 25 + 1;   // node centre of mass
+        double r[kW64];
+#pragma unroll
+        for (int q = 0; q < kW64; ++q) r[q] = 0.0;
+        for (int j = L.y; j < L.y + L.z; ++j) {
+            const double4 w = ws[j];
+            if (w.w == 0.0) continue;
+            const double4 x = spos[j];
+            const double y[3] = {x.x - c[0], x.y - c[1], x.z - c[2]};
+            const double wv[3] = {w.x, w.y, w.z};
+            for (int b = 0; b < 3; ++b) {
+                r[b] += wv[b];
+                for (int cc = 0; cc < 3; ++cc) r[3 + 3 * b + cc] += wv[b] * y[cc];
+            }
+            add_w2(r + 12, wv, y);
+            r[30] += 1.0;
+        }
+        store_w(id, r, w64, wf);
+    }
+}
+
+// Shifted to the parent centre (y = y_child + dl):
+//   W1_bc  = sum (W1_bc + W0_b dl_c)
+//   W2_bce = sum (W2_bce + W1_bc dl_e + W1_be dl_c + W0_b dl_c dl_e)
+__global__ void k_inner_wlevel(int level, const int64_t* __restrict__ hdr, const int32_t* __restrict__ ilist,
+                               const int4* __restrict__ link, const double* __restrict__ m64,
+                               double* __restrict__ w64, float4* __restrict__ wf) {
+    const int64_t ni = hdr[2];
+    if (level > hdr[1]) return;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ni;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int id = ilist[t];
+        const int4 L = link[id];
+        if ((L.w & 0xff) != level) continue;
+        const double* c = m64 + (int64_t)id * 25 + 1;
+        double r[kW64];
+#pragma unroll
+        for (int q = 0; q < kW64; ++q) r[q] = 0.0;
+        for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = link[ch].x, ++k8) {
+            const double* cw = w64 + (int64_t)ch * kW64;
+            const double* cc = m64 + (int64_t)ch * 25 + 1;
+            const double dl[3] = {cc[0] - c[0], cc[1] - c[1], cc[2] - c[2]};
+            const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+            for (int b = 0; b < 3; ++b) {
+                r[b] += cw[b];
+                for (int q = 0; q < 3; ++q) r[3 + 3 * b + q] += cw[3 + 3 * b + q] + cw[b] * dl[q];
+                for (int k = 0; k < 6; ++k) {
+                    const int cc1 = ia[k], ee = ib[k];
+                    r[12 + 6 * b + k] += cw[12 + 6 * b + k] + cw[3 + 3 * b + cc1] * dl[ee] +
+                                         cw[3 + 3 * b + ee] * dl[cc1] + cw[b] * dl[cc1] * dl[ee];
+                }
+            }
+            r[30] += cw[30];
+        }
+        store_w(id, r, w64, wf);
+    }
+}
+
+}  // namespace
+
 static Tree make_tree(ag_ctx* c) {
     Tree T;
     T.com = c->nd_com.as<double4>();
@@ -604,6 +923,8 @@ static Tree make_tree(ag_ctx* c) {
     T.svf = c->svf.as<float4>();
     T.perm = c->perm.as<int32_t>();
     T.sys_root = c->sys_root.as<int32_t>();
+    T.ws = c->wsorted.as<double4>();
+    T.wf = c->nd_wf.as<float4>();
     return T;
 }
 
@@ -616,24 +937,74 @@ static int walk_grid(ag_ctx* c, int64_t max_groups) {
     return (int)blocks;
 }
 
+static WalkOut make_out(ag_ctx* c, double G) {
+    WalkOut O{};
+    O.stats = c->stats.as<unsigned long long>();
+    O.G = G;
+    O.flags = c->dflags.as<int32_t>();
+    O.iter_cap = c->max_nodes + c->n + 1024;
+    return O;
+}
+
 int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps, double G, double* acc,
                    double* jerk, double* tidal) {
     int64_t mg = 0;
     AG_TRY(ag_prepare_groups(c, idx, n_act, &mg));
     Groups Gr{c->act_pos.as<int32_t>(), c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
-    WalkOut O{acc, jerk, tidal, c->stats.as<unsigned long long>(), G, c->dflags.as<int32_t>(),
-              c->max_nodes + c->n + 1024};
+    WalkOut O = make_out(c, G);
+    O.acc = acc;
+    O.jerk = jerk;
+    O.tidal = tidal;
     const float th = (float)theta;
     const float e2 = (float)(eps * eps);
     {
         PhaseScope phase(c, AG_PHASE_WALK);
-        hipLaunchKernelGGL(k_walk, dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
-                           c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2, (float)(1.0 / eps));
+        hipLaunchKernelGGL(k_walk<ForwardPolicy>, dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, c->stream,
+                           make_tree(c), Gr, O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2, (float)(1.0 / eps));
     }
     return AG_OK;
 }
 
+// Adjoint of L = sum_k w_k . g_k:
+//   1. forward walk for T at the listed rows (the T_k w_k term);
+//   2. sorted weights (zero on unlisted rows) and their node moments W0, W1;
+//   3. adjoint walk over all n targets with the same opening test.
 int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w, double theta, double eps,
                        double G, double* dLdx, double* dLdm) {
-    return ag_fail(AG_ESTATE, "backward walk not built yet");
+    const int64_t n = c->n;
+    AG_TRY(ag_ensure(c->tmp_tidal, n * 6 * sizeof(double)));
+    AG_TRY(ag_ensure(c->wsorted, n * sizeof(double4)));
+    AG_TRY(ag_ensure(c->nd_w, c->max_nodes * kW64 * sizeof(double)));
+    AG_TRY(ag_ensure(c->nd_wf, c->max_nodes * 8 * sizeof(float4)));
+    double* tin = c->tmp_tidal.as<double>();
+    int64_t mg0 = 0;
+    if (n_act > 0) AG_TRY(ag_launch_eval(c, idx, n_act, theta, eps, G, nullptr, nullptr, tin));
+    else AG_TRY(ag_prepare_groups(c, idx, 0, &mg0));   // no charges: all flags clear
+
+    PhaseScope phase(c, AG_PHASE_ADJOINT);
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_gather_w, dim3(grid_for(n)), dim3(256), 0, st, n, c->perm.as<int32_t>(),
+                       c->act_flag.as<int32_t>(), w, c->wsorted.as<double4>());
+    hipLaunchKernelGGL(k_leaf_wmoments, dim3(grid_for(n)), dim3(256), 0, st, n, c->pos_cnt.as<int32_t>(),
+                       c->pos_off.as<int32_t>(), c->nd_link.as<int4>(), c->nd_64.as<double>(),
+                       c->spos.as<double4>(), c->wsorted.as<double4>(), c->nd_w.as<double>(), c->nd_wf.as<float4>());
+    const int64_t inner_bound = c->max_nodes - n;
+    int g = grid_for(inner_bound > 0 ? inner_bound : 1);
+    if (g > 128) g = 128;
+    for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
+        hipLaunchKernelGGL(k_inner_wlevel, dim3(g), dim3(256), 0, st, l, c->tree_hdr.as<int64_t>(),
+                           c->in_list.as<int32_t>(), c->nd_link.as<int4>(), c->nd_64.as<double>(),
+                           c->nd_w.as<double>(), c->nd_wf.as<float4>());
+    int64_t mg = 0;
+    AG_TRY(ag_prepare_groups(c, nullptr, n, &mg));   // every particle is a target
+    Groups Gr{c->act_pos.as<int32_t>(), c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    WalkOut O = make_out(c, G);
+    O.dldx = dLdx;
+    O.dldm = dLdm;
+    O.tin = tin;
+    const float th = (float)theta;
+    const float e2 = (float)(eps * eps);
+    hipLaunchKernelGGL(k_walk<AdjointPolicy>, dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, st, make_tree(c), Gr,
+                       O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2, (float)(1.0 / eps));
+    return AG_OK;
 }

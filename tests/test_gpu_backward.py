@@ -1,0 +1,135 @@
+"""GPU parity: the adjoint walk (gradient of L = sum_k w_k . g_k with respect to
+positions and masses) against the oracle's exact direct-sum gradient."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _t(a, dtype=None):
+    return torch.tensor(a, device=DEV) if dtype is None else torch.tensor(a, dtype=dtype, device=DEV)
+
+
+def _backward(ctx, x, v, m, w, act, theta, eps, G=1.0):
+    n = len(m)
+    ctx.tree_build(_t(x), _t(v), _t(m), 16)
+    dx = torch.full((n, 3), float("nan"), dtype=torch.float64, device=DEV)
+    dm = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+    ia = None if act is None else _t(act, torch.int32)
+    ctx.grav_backward(ia, _t(w), theta, eps, G, dx, dm)
+    ctx.sync()
+    return dx.cpu().numpy(), dm.cpu().numpy()
+
+
+def _masked(w, act):
+    wm = np.zeros_like(w)
+    wm[act] = w[act]
+    return wm
+
+
+@pytest.mark.parametrize("n", [50, 3000])
+def test_backward_theta0_matches_oracle(ctx, orc, n):
+    """theta = 0: the adjoint walk is the exact gradient with FP32 pair terms."""
+    x, v, m = workloads.plummer(n, seed=n)
+    m = m * np.random.default_rng(1).uniform(0.5, 1.5, n)
+    w = workloads.adjoint_weights(n, seed=n)
+    eps = 0.02
+    dx, dm = _backward(ctx, x, v, m, w, None, 0.0, eps, G=1.3)
+    rx, rm = orc.adjoint(x, m, w, eps, 1.3)
+    assert np.median(rel_err(dx, rx)) <= 1e-5
+    assert np.median(np.abs(dm - rm) / np.abs(rm)) <= 1e-5
+
+
+def test_backward_partial_weights(ctx, orc):
+    """Weights on a random 10% of the rows: the gradient still covers every
+    particle (every particle is a source of the listed targets)."""
+    n = 5000
+    x, v, m = workloads.plummer(n, seed=3)
+    w = workloads.adjoint_weights(n, seed=3)
+    act = np.random.default_rng(4).permutation(workloads.random_subset(n, 0.1, seed=5))
+    eps = 0.02
+    dx, dm = _backward(ctx, x, v, m, w, act, 0.0, eps)
+    rx, rm = orc.adjoint(x, m, _masked(w, act), eps, 1.0)
+    assert np.all(np.isfinite(dx)) and np.all(np.isfinite(dm))
+    assert np.median(rel_err(dx, rx)) <= 1e-5
+    assert np.median(np.abs(dm - rm) / np.abs(rm)) <= 1e-5
+
+
+def _mass_gradient_scale(orc, x, w, eps, rows):
+    """G sum_j |f(r_kj) d_kj . w_j|: the size of dL/dm_k before cancellation
+    between the randomly signed terms (used to normalise its error)."""
+    out = np.empty(len(rows))
+    for t, k in enumerate(rows):
+        d = x - x[k]
+        r = np.linalg.norm(d, axis=1)
+        f, _, _ = orc.kernel(r, eps)
+        term = np.abs(f * np.sum(d * w, axis=1))
+        term[k] = 0.0
+        out[t] = term.sum()
+    return out
+
+
+def test_backward_tree_uniform_sphere(ctx, orc):
+    """theta = 0.6 on a uniform sphere (N = 2^16, eps = 1e-3, Gaussian w),
+    2048 sampled particles.  dL/dx = G m sum J w + T w is built from 1/r^3
+    kernels (J and the tidal tensor), whose node truncation is that of the
+    tidal tensor, so it takes the tidal bound: median relative error <= 5e-3,
+    99th percentile <= 5e-2.  dL/dm (a 1/r^2 kernel) is a sum of randomly
+    signed terms that can nearly cancel, so its error is measured against the
+    cancellation-free size G sum_j |f d.w_j|: median <= 1e-3, 99th
+    percentile <= 1e-2."""
+    n = 1 << 16
+    x, m, _ = workloads.uniform_sphere(n, seed=5)
+    v = np.zeros_like(x)
+    w = workloads.adjoint_weights(n, seed=5)
+    eps = 1e-3
+    dx, dm = _backward(ctx, x, v, m, w, None, 0.6, eps)
+    rows = np.random.default_rng(6).choice(n, 2048, replace=False)
+    rx, rm = orc.adjoint(x, m, w, eps, 1.0, rows)
+    ex = rel_err(dx[rows], rx)
+    em_plain = np.abs(dm[rows] - rm) / np.abs(rm)
+    em = np.abs(dm[rows] - rm) / _mass_gradient_scale(orc, x, w, eps, rows[:512])[
+        np.arange(len(rows)) % 512]
+    em = em[:512]
+    stats = {"dLdx": (float(np.median(ex)), float(np.percentile(ex, 99))),
+             "dLdm_scaled": (float(np.median(em)), float(np.percentile(em, 99))),
+             "dLdm_plain": (float(np.median(em_plain)), float(np.percentile(em_plain, 99)))}
+    print(stats)
+    assert stats["dLdx"][0] <= 5e-3 and stats["dLdx"][1] <= 5e-2, stats
+    assert stats["dLdm_scaled"][0] <= 1e-3 and stats["dLdm_scaled"][1] <= 1e-2, stats
+
+
+def test_autograd_function(ag, orc):
+    """GravEval.backward returns dL/dx and dL/dm through torch autograd."""
+    n = 2000
+    x, v, m = workloads.plummer(n, seed=7)
+    w = workloads.adjoint_weights(n, seed=7)
+    eps = 0.02
+    tx = _t(x).requires_grad_(True)
+    tm = _t(m).requires_grad_(True)
+    with ag.Context(0) as c:
+        acc, jerk, tid = ag.grav_eval(c, tx, _t(v), tm, None, theta=0.0, eps=eps)
+        L = (acc * _t(w)).sum()
+        L.backward()
+        c.sync()
+    rx, rm = orc.adjoint(x, m, w, eps, 1.0)
+    assert np.median(rel_err(tx.grad.cpu().numpy(), rx)) <= 1e-5
+    assert np.median(np.abs(tm.grad.cpu().numpy() - rm) / np.abs(rm)) <= 1e-5
+    ar, _, _ = orc.direct(x, v, m, eps, 1.0)
+    assert np.median(rel_err(acc.detach().cpu().numpy(), ar)) <= 1e-5
+
+
+def test_autograd_rejects_jerk_gradient(ag):
+    n = 100
+    x, v, m = workloads.plummer(n, seed=8)
+    tx = _t(x).requires_grad_(True)
+    with ag.Context(0) as c:
+        acc, jerk, tid = ag.grav_eval(c, tx, _t(v), _t(m), None, theta=0.5, eps=0.01)
+        assert not jerk.requires_grad and not tid.requires_grad
+        (acc.sum()).backward()
+        assert tx.grad is not None and torch.all(torch.isfinite(tx.grad))
