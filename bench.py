@@ -54,6 +54,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target host time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="tree",
+                    choices=["tree", "direct", "adaptive", "batched", "adjoint"],
+                    help="tree: the headline line (default); the others measure the remaining "
+                         "configurations and print their own JSON line")
+    ap.add_argument("--adaptive-steps", type=int, default=200)
+    ap.add_argument("--rebuild-every", type=int, default=1)
     return ap.parse_args()
 
 
@@ -63,6 +69,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "tree":
+        import bench_workloads
+        out = getattr(bench_workloads, "run_" + args.workload)(args)
+        print(json.dumps(out), flush=True)
+        return
     import numpy as np
     import torch
 
@@ -106,7 +117,7 @@ def main():
         ctx.tree_build(tx, tv, tm, args.n_leaf)
         ctx.grav_eval(None, args.theta, args.eps, G, acc, jerk, tid)
         ctx.grav_timestep(tid, eta, dt_max, tick_bin, dt_grav, bins)
-        ctx.adaptive_select(tf, bins, 1, tick_bin, q_f, act, n_act)
+        ctx.adaptive_select(tf, bins, 1, tick_bin, q_f, act, n_act, t0=t0, t=state["t"] + dt_step)
         state["t"] += dt_step
         ctx.grav_predict(acc, jerk, t0, state["t"], acc_pred)
 

@@ -1,0 +1,267 @@
+"""The non-default measurement configurations of ``bench.py``.
+
+  direct    Plummer sphere N = 4096 (eps = 0.01): direct summation in FP64 and
+            with FP32 pair terms; time, pairs/s, error against the oracle.
+  adaptive  64 Plummer clumps, N = 2^22 (eps = 1e-3, theta = 0.7, eta = 0.01):
+            the integrator of ``driver.py`` for q_f in {0, 1/8, 1/4, 1/2, 1}
+            (q_f = 0 is the every-step scheme); force evaluations, gravity
+            and total GPU time, and the error of the force actually used
+            (fresh or predicted) against the oracle at sampled steps.
+  batched   256 Plummer systems of 1k-64k particles with 1-100% active
+            (eps = 0.01, theta = 0.5): one batched build and one persistent
+            walk recorded in a HIP graph and replayed; walk options from the
+            autotuner; error on 64 sampled targets per system.
+  adjoint   uniform sphere N = 2^18 (eps = 1e-3, theta = 0.6), Gaussian w:
+            forward and adjoint walks, errors against the oracle gradient.
+Inputs are seeded synthetic particle sets standing in for the paper's
+hydro test problems.
+"""
+from __future__ import annotations
+
+import statistics
+import sys
+import time
+
+import numpy as np
+import torch
+
+import workloads
+import paper_2010_13792_amd as ag
+from paper_2010_13792_amd import autotune
+from paper_2010_13792_amd.driver import AdaptiveIntegrator
+
+DEV = torch.device("cuda:0")
+PP_FLOPS, PN_FLOPS = 60, 222
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _t(a, dtype=None):
+    return torch.tensor(a, device=DEV) if dtype is None else torch.tensor(a, dtype=dtype, device=DEV)
+
+
+def _events():
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+# ---------------------------------------------------------------------------
+def run_direct(args):
+    import oracle
+    n, eps = 4096, 0.01
+    x, v, m = workloads.plummer(n, seed=1)
+    tx, tv, tm = _t(x), _t(v), _t(m)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+    jerk, tid = torch.zeros_like(acc), torch.zeros((n, 6), dtype=torch.float64, device=DEV)
+    ar, jr, tr = oracle.direct(x, v, m, eps, 1.0)
+    out = {"workload": "direct Plummer N=4096 eps=0.01", "pairs": n * (n - 1)}
+    with ag.Context(0) as c:
+        for name, prec in (("fp64", ag.AG_FP64), ("fp32_pairs", ag.AG_FP32_PAIRS)):
+            for _ in range(3):
+                c.grav_direct(tx, tv, tm, None, eps, 1.0, acc, jerk, tid, precision=prec)
+            torch.cuda.synchronize()
+            e0, e1 = _events()
+            reps = 20
+            e0.record()
+            for _ in range(reps):
+                c.grav_direct(tx, tv, tm, None, eps, 1.0, acc, jerk, tid, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            err = _rel(acc.cpu().numpy(), ar)
+            out[name] = {"ms": ms, "pairs_per_s": n * (n - 1) / (ms * 1e-3), "evals_per_s": n / (ms * 1e-3),
+                         "median_rel_err": float(np.median(err)), "max_rel_err": float(err.max())}
+    t_a = time.perf_counter()
+    oracle.direct(x, v, m, eps, 1.0)
+    t_o = time.perf_counter() - t_a
+    out["cpu_baseline"] = {"value": n / t_o, "unit": "force evals/s", "cores": oracle.num_threads(),
+                           "kind": "oracle", "sample": f"all {n} targets"}
+    return out
+
+
+# ---------------------------------------------------------------------------
+def run_adaptive(args):
+    import oracle
+    n = 1 << 22 if args.n == (1 << 20) else args.n
+    steps = args.adaptive_steps
+    log(f"adaptive: generating {n} particles in 64 clumps")
+    x, v, m, _ = workloads.clumps(n, seed=3)
+    tx, tv, tm = _t(x), _t(v), _t(m)
+    rng = np.random.default_rng(33)
+    rows = rng.choice(n, 1024, replace=False)
+    checkpoints = sorted({0, steps // 2, steps})
+    runs = {}
+    for q in [0.0, 0.125, 0.25, 0.5, 1.0]:
+        with ag.Context(0) as c:
+            integ = AdaptiveIntegrator(c, tx, tv, tm, q_f=q, theta=0.7, eps=1e-3, eta=0.01,
+                                       rebuild_every=args.rebuild_every)
+            c.sync()
+            errs = {}
+
+            def check(step):
+                xs = integ.x.cpu().numpy()
+                vs = integ.vpred.cpu().numpy() if step > 0 else integ.v.cpu().numpy()
+                ar, _, _ = oracle.direct(xs, vs, m, 1e-3, 1.0, rows)
+                errs[step] = float(np.median(_rel(integ.acc.cpu().numpy()[rows], ar)))
+
+            if 0 in checkpoints:
+                check(0)
+            c.timing_enable(True)
+            c.timing_read(reset=True)
+            ev0, ev1 = _events()
+            total_ms = 0.0
+            active_hist = []
+            for s in range(1, steps + 1):
+                ev0.record()
+                k = integ.step()
+                ev1.record()
+                torch.cuda.synchronize()
+                total_ms += ev0.elapsed_time(ev1)
+                active_hist.append(k)
+                if s in checkpoints:
+                    check(s)
+            ph = c.timing_read(reset=True)
+            c.timing_enable(False)
+            grav_ms = ph["build"]["ms"] + ph["groups"]["ms"] + ph["walk"]["ms"]
+            runs[q] = {"evaluations": int(integ.evaluations - n), "gravity_ms": grav_ms,
+                       "walk_ms": ph["walk"]["ms"], "build_ms": ph["build"]["ms"], "total_ms": total_ms,
+                       "median_rel_err_used_force": errs, "dt_step": integ.dt, "tick_bin": integ.tick_bin,
+                       "mean_active_fraction": float(np.mean(active_hist)) / n}
+            log(f"adaptive q_f={q}: {runs[q]}")
+    base = runs[0.0]
+    res = {}
+    for q, r in runs.items():
+        res[str(q)] = dict(r, eval_ratio=base["evaluations"] / max(1, r["evaluations"]),
+                           gravity_speedup=base["gravity_ms"] / r["gravity_ms"],
+                           walk_speedup=base["walk_ms"] / r["walk_ms"],
+                           total_speedup=base["total_ms"] / r["total_ms"])
+    ok = [q for q, r in runs.items() if max(r["median_rel_err_used_force"].values()) <= 1e-3]
+    return {"workload": f"64 Plummer clumps N={n}, {steps} steps, theta=0.7 eps=1e-3 eta=0.01",
+            "metric": "adaptive vs every-step speedup", "rebuild_every": args.rebuild_every,
+            "runs": res, "largest_q_f_within_1e-3": max(ok) if ok else None}
+
+
+# ---------------------------------------------------------------------------
+def run_batched(args):
+    import oracle
+    d = workloads.batched_plummer(256, seed=4)
+    x, v, m = d["x"], d["v"], d["m"]
+    n = len(m)
+    act = d["active"]
+    tx, tv, tm = _t(x), _t(v), _t(m)
+    toff = _t(d["offsets"], torch.int64)
+    tact = _t(act, torch.int32)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+    jerk, tid = torch.zeros_like(acc), torch.zeros((n, 6), dtype=torch.float64, device=DEV)
+    theta, eps = 0.5, 0.01
+    stream = torch.cuda.Stream()
+    out = {"workload": f"256 Plummer systems, N={n}, active={len(act)}, theta=0.5 eps=0.01"}
+    with torch.cuda.stream(stream), ag.Context(0, stream) as c:
+        def once(p):
+            c.set_option(ag.AG_OPT_WALK_WAVES_PER_CU, p["waves_per_cu"])
+            c.tree_build_batched(tx, tv, tm, toff, p["n_leaf"])
+            c.grav_eval_batched(tact, theta, eps, 1.0, acc, jerk, tid)
+
+        def run(p):
+            once(p)
+            e0, e1 = _events()
+            e0.record(stream)
+            for _ in range(3):
+                once(p)
+            e1.record(stream)
+            stream.synchronize()
+            return e0.elapsed_time(e1) / 3
+
+        cands = autotune.grid(n_leaf=[8, 16, 32], waves_per_cu=[8, 12, 16])
+        best, table = autotune.tune(run, cands, f"batched256|n={n}|act={len(act)}", use_cache=False)
+        log(f"batched: autotuner picked {best}")
+        once(best)
+        c.sync()
+        c.graph_begin()
+        c.tree_build_batched(tx, tv, tm, toff, best["n_leaf"])
+        c.grav_eval_batched(tact, theta, eps, 1.0, acc, jerk, tid)
+        c.graph_end()
+        for _ in range(3):
+            c.graph_replay()
+        stream.synchronize()
+        c.stats_reset()
+        reps = 20
+        e0, e1 = _events()
+        e0.record(stream)
+        for _ in range(reps):
+            c.graph_replay()
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        st = c.stats_read()
+        c.sync()
+    a = acc.cpu().numpy()
+    errs = []
+    rng = np.random.default_rng(44)
+    off, aoff = d["offsets"], d["act_offsets"]
+    for s in range(256):
+        sa = act[aoff[s]:aoff[s + 1]]
+        pick = rng.choice(sa, min(64, len(sa)), replace=False)
+        ar, _, _ = oracle.direct(x[off[s]:off[s + 1]], v[off[s]:off[s + 1]], m[off[s]:off[s + 1]], eps, 1.0,
+                                 pick - off[s])
+        errs.append(_rel(a[pick], ar))
+    e = np.concatenate(errs)
+    pp, pn = st["n_pp"] / reps, st["n_pn"] / reps
+    out.update({"value": len(act) / (ms * 1e-3), "unit": "force evals/s", "graph_replay_ms": ms,
+                "interactions_per_s": (pp + pn) / (ms * 1e-3),
+                "flops_per_replay": pp * PP_FLOPS + pn * PN_FLOPS,
+                "autotune": {"best": best, "table_ms": table},
+                "median_rel_force_err": float(np.median(e)), "p99_rel_force_err": float(np.percentile(e, 99))})
+    return out
+
+
+# ---------------------------------------------------------------------------
+def run_adjoint(args):
+    import oracle
+    n = 1 << 18
+    x, m, _ = workloads.uniform_sphere(n, seed=5)
+    v = np.zeros_like(x)
+    w = workloads.adjoint_weights(n, seed=5)
+    theta, eps = 0.6, 1e-3
+    tx, tv, tm, tw = _t(x), _t(v), _t(m), _t(w)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+    jerk, tid = torch.zeros_like(acc), torch.zeros((n, 6), dtype=torch.float64, device=DEV)
+    dx = torch.zeros_like(acc)
+    dm = torch.zeros(n, dtype=torch.float64, device=DEV)
+    out = {"workload": f"uniform sphere N=2^18 theta=0.6 eps=1e-3, L = sum w.a"}
+    with ag.Context(0) as c:
+        def fwd():
+            c.tree_build(tx, tv, tm, 16)
+            c.grav_eval(None, theta, eps, 1.0, acc, jerk, tid)
+
+        def bwd():
+            c.tree_build(tx, tv, tm, 16)
+            c.grav_backward(None, tw, theta, eps, 1.0, dx, dm)
+
+        for name, fn in (("forward", fwd), ("backward", bwd)):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            c.stats_reset()
+            e0, e1 = _events()
+            reps = 10
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            st = c.stats_read()
+            out[name] = {"ms": ms, "interactions_per_s": (st["n_pp"] + st["n_pn"]) / reps / (ms * 1e-3)}
+    rows = np.random.default_rng(6).choice(n, 2048, replace=False)
+    rx, rm = oracle.adjoint(x, m, w, eps, 1.0, rows)
+    ex = _rel(dx.cpu().numpy()[rows], rx)
+    out["dLdx_rel_err"] = {"median": float(np.median(ex)), "p99": float(np.percentile(ex, 99))}
+    em = np.abs(dm.cpu().numpy()[rows] - rm) / np.abs(rm)
+    out["dLdm_rel_err_plain"] = {"median": float(np.median(em)), "p99": float(np.percentile(em, 99))}
+    return out

@@ -89,6 +89,25 @@ int ag_stats_reset(ag_ctx *ctx);
 /* Message for the last failing call on this host thread. */
 const char *ag_last_error(void);
 
+/* Tunable launch options (picked by an autotuner; defaults in brackets):
+ *   AG_OPT_WALK_WAVES_PER_CU   resident walk waves launched per CU [16]
+ *   AG_OPT_SMALL_NODE          accepted nodes with at most this many particles
+ *                              are summed pair by pair instead [2]
+ * Values outside the documented ranges (1..64, 0..16) give AG_EINVAL. */
+enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2 };
+int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
+
+/* HIP-graph capture of a call sequence on the context's stream (which must
+ * not be the legacy default stream).  Between ag_graph_begin and
+ * ag_graph_end, library calls are recorded, not run; device buffers they
+ * need must already exist (run the same sequence once before capturing).
+ * ag_graph_replay launches the recorded sequence again on the stream with
+ * the same pointers (refill the input arrays in place between replays).
+ * Timing must be disabled while capturing. */
+int ag_graph_begin(ag_ctx *ctx);
+int ag_graph_end(ag_ctx *ctx);
+int ag_graph_replay(ag_ctx *ctx);
+
 /* Per-phase GPU timing.  While enabled, every library call records HIP
  * events on the context's stream around each phase it launches; the
  * accumulated milliseconds per phase (and launch counts) are returned by the
@@ -202,10 +221,17 @@ int ag_grav_timestep(ag_ctx *ctx, int64_t n, const int32_t *idx, int64_t n_idx,
  *   a due particle gets tf = 0 (it is re-evaluated now).
  * tf_ticks (n,) int64 is updated in place; the due rows are written in
  * ascending order to active_idx (capacity n) and their number to the DEVICE
- * int64 *n_active_dev.  q_f = 0 marks every particle due. */
+ * int64 *n_active_dev.  q_f = 0 marks every particle due.  If t0 (n,) is
+ * non-NULL, the due rows also get t0 = t: the time their fresh force (and
+ * jerk) will refer to in the predictor. */
 int ag_adaptive_select(ag_ctx *ctx, int64_t n, int64_t *tf_ticks, const int8_t *bin,
                        int64_t step_ticks, int32_t tick_bin, double q_f,
-                       int32_t *active_idx, int64_t *n_active_dev);
+                       int32_t *active_idx, int64_t *n_active_dev, double *t0, double t);
+
+/* Kick-drift for a leapfrog integrator driving the scheme: for every row,
+ * v += acc * dt_kick, then x += v * dt_drift.  x, v, acc: (n,3). */
+int ag_kick_drift(ag_ctx *ctx, int64_t n, double *x, double *v, const double *acc,
+                  double dt_kick, double dt_drift);
 
 /* Jerk predictor (Eq. 6) in closed form: acc_out_i = acc0_i + jerk_i (t - t0_i)
  * with t - t0 and the product and sum each rounded once (no fused

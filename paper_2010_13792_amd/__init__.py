@@ -36,7 +36,10 @@ ENTRY_POINTS = [
     "ag_tree_export", "ag_grav_eval",
     "ag_grav_eval_batched", "ag_grav_direct", "ag_grav_timestep", "ag_adaptive_select",
     "ag_grav_predict", "ag_grav_backward", "ag_timing_enable", "ag_timing_read",
+    "ag_kick_drift", "ag_set_option", "ag_graph_begin", "ag_graph_end", "ag_graph_replay",
 ]
+AG_OPT_WALK_WAVES_PER_CU = 1
+AG_OPT_SMALL_NODE = 2
 PHASES = ["build", "groups", "walk", "direct", "step", "adjoint"]
 
 
@@ -82,7 +85,10 @@ def load_library(path: str = LIB_PATH):
         "ag_grav_eval_batched": [P, P, I64, D, D, D, P, P, P],
         "ag_grav_direct": [P, I64, P, P, P, P, I64, D, D, ctypes.c_int, P, P, P],
         "ag_grav_timestep": [P, I64, P, I64, P, D, D, I32, P, P],
-        "ag_adaptive_select": [P, I64, P, P, I64, I32, D, P, P],
+        "ag_adaptive_select": [P, I64, P, P, I64, I32, D, P, P, P, D],
+        "ag_kick_drift": [P, I64, P, P, P, D, D],
+        "ag_set_option": [P, I32, I64],
+        "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
         "ag_grav_backward": [P, P, I64, P, D, D, D, P, P],
         "ag_timing_enable": [P, ctypes.c_int],
@@ -253,13 +259,34 @@ class Context:
                                      _ptr(dt_grav, torch.float64, None, "dt_grav", n),
                                      _ptr(bins, torch.int8, None, "bin", n)))
 
-    def adaptive_select(self, tf_ticks, bins, step_ticks, tick_bin, q_f, active_idx, n_active_dev):
+    def adaptive_select(self, tf_ticks, bins, step_ticks, tick_bin, q_f, active_idx, n_active_dev,
+                        t0=None, t=0.0):
         n = tf_ticks.shape[0]
         _check(_lib.ag_adaptive_select(self._h, n, _ptr(tf_ticks, torch.int64, None, "tf_ticks"),
                                        _ptr(bins, torch.int8, None, "bin", n), int(step_ticks),
                                        int(tick_bin), float(q_f),
                                        _ptr(active_idx, torch.int32, None, "active_idx", n),
-                                       _ptr(n_active_dev, torch.int64, None, "n_active", 1)))
+                                       _ptr(n_active_dev, torch.int64, None, "n_active", 1),
+                                       _ptr(t0, torch.float64, None, "t0", n), float(t)))
+
+    def kick_drift(self, x, v, acc, dt_kick, dt_drift):
+        n = x.shape[0]
+        _check(_lib.ag_kick_drift(self._h, n, _ptr(x, torch.float64, (3,), "x"),
+                                  _ptr(v, torch.float64, (3,), "v", n),
+                                  _ptr(acc, torch.float64, (3,), "acc", n), float(dt_kick),
+                                  float(dt_drift)))
+
+    def set_option(self, option: int, value: int):
+        _check(_lib.ag_set_option(self._h, int(option), int(value)))
+
+    def graph_begin(self):
+        _check(_lib.ag_graph_begin(self._h))
+
+    def graph_end(self):
+        _check(_lib.ag_graph_end(self._h))
+
+    def graph_replay(self):
+        _check(_lib.ag_graph_replay(self._h))
 
     def grav_predict(self, acc0, jerk, t0, t, acc_out, mask=None):
         n = acc0.shape[0]

@@ -197,6 +197,8 @@ extern "C" int ag_destroy(ag_ctx* c) {
         (void)hipEventDestroy(p.b);
     }
     for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     delete c;
     return AG_OK;
 }
@@ -378,7 +380,7 @@ extern "C" int ag_grav_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_
 
 extern "C" int ag_adaptive_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin,
                                   int64_t step_ticks, int32_t tick_bin, double q_f, int32_t* active_idx,
-                                  int64_t* n_active_dev) {
+                                  int64_t* n_active_dev, double* t0, double t) {
     AG_TRY(check_ctx(c));
     if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
     if (n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n exceeds 2^30");
@@ -386,9 +388,71 @@ extern "C" int ag_adaptive_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_
     if (step_ticks < 0) return ag_fail(AG_EINVAL, "step_ticks must be >= 0");
     if (tick_bin < 0 || tick_bin > 52) return ag_fail(AG_EINVAL, "tick_bin must be in [0, 52]");
     if (!(q_f >= 0.0) || !std::isfinite(q_f)) return ag_fail(AG_EINVAL, "q_f must be >= 0 and finite");
+    if (t0 && !std::isfinite(t)) return ag_fail(AG_EINVAL, "t must be finite");
     DeviceGuard g(c->device);
-    AG_TRY(ag_launch_select(c, n, tf, bin, step_ticks, tick_bin, q_f, active_idx, n_active_dev));
+    AG_TRY(ag_launch_select(c, n, tf, bin, step_ticks, tick_bin, q_f, active_idx, n_active_dev, t0, t));
     return check_launch("adaptive select");
+}
+
+extern "C" int ag_kick_drift(ag_ctx* c, int64_t n, double* x, double* v, const double* acc, double dt_kick,
+                             double dt_drift) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (!x || !v || !acc) return ag_fail(AG_EINVAL, "null pointer argument");
+    if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift)) return ag_fail(AG_EINVAL, "non-finite step");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_kick_drift(c, n, x, v, acc, dt_kick, dt_drift));
+    return check_launch("kick drift");
+}
+
+extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
+    AG_TRY(check_ctx(c));
+    switch (option) {
+        case AG_OPT_WALK_WAVES_PER_CU:
+            if (value < 1 || value > 64) return ag_fail(AG_EINVAL, "walk waves per CU must be in [1, 64]");
+            c->walk_waves_per_cu = (int)value;
+            return AG_OK;
+        case AG_OPT_SMALL_NODE:
+            if (value < 0 || value > 16) return ag_fail(AG_EINVAL, "small-node size must be in [0, 16]");
+            c->small_node = (int)value;
+            return AG_OK;
+        default:
+            return ag_fail(AG_EINVAL, "unknown option %d", option);
+    }
+}
+
+extern "C" int ag_graph_begin(ag_ctx* c) {
+    AG_TRY(check_ctx(c));
+    if (c->capturing) return ag_fail(AG_ESTATE, "already capturing");
+    if (c->stream == nullptr) return ag_fail(AG_ESTATE, "capture needs a non-default stream");
+    if (c->timing.on) return ag_fail(AG_ESTATE, "disable timing before capturing");
+    DeviceGuard g(c->device);
+    AG_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    return AG_OK;
+}
+
+extern "C" int ag_graph_end(ag_ctx* c) {
+    AG_TRY(check_ctx(c));
+    if (!c->capturing) return ag_fail(AG_ESTATE, "not capturing");
+    DeviceGuard g(c->device);
+    c->capturing = false;
+    hipGraph_t gr = nullptr;
+    AG_HIP(hipStreamEndCapture(c->stream, &gr));
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph = gr;
+    c->graph_exec = nullptr;
+    AG_HIP(hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0));
+    return AG_OK;
+}
+
+extern "C" int ag_graph_replay(ag_ctx* c) {
+    AG_TRY(check_ctx(c));
+    if (!c->graph_exec) return ag_fail(AG_ESTATE, "no captured graph");
+    DeviceGuard g(c->device);
+    AG_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+    return AG_OK;
 }
 
 extern "C" int ag_grav_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0,

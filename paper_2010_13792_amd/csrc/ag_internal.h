@@ -61,6 +61,11 @@ struct ag_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     Timing timing;
+    int walk_waves_per_cu = 16;
+    int small_node = 2;
+    bool capturing = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 
     // --- tree state ---
     bool built = false;
@@ -142,7 +147,10 @@ int ag_launch_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx,
                        const double* tidal, double eta, double dt_max, int32_t k_max,
                        double* dt, int8_t* bin);
 int ag_launch_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin, int64_t step_ticks,
-                     int32_t tick_bin, double q_f, int32_t* active_idx, int64_t* n_active_dev);
+                     int32_t tick_bin, double q_f, int32_t* active_idx, int64_t* n_active_dev,
+                     double* t0, double t);
+int ag_launch_kick_drift(ag_ctx* c, int64_t n, double* x, double* v, const double* acc, double dt_kick,
+                         double dt_drift);
 int ag_launch_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0,
                       const double* j, const double* t0, double t, double* out);
 int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,

@@ -85,12 +85,28 @@ __global__ void k_select(int64_t n, int64_t* __restrict__ tf, const int8_t* __re
 
 __global__ void k_compact(int64_t n, const int32_t* __restrict__ flag,
                           const int32_t* __restrict__ off, int32_t* __restrict__ out,
-                          int64_t* __restrict__ count) {
+                          int64_t* __restrict__ count, double* __restrict__ t0, double t) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        if (flag[i]) out[off[i]] = (int32_t)i;
+        if (flag[i]) {
+            out[off[i]] = (int32_t)i;
+            if (t0) t0[i] = t;
+        }
     }
     if (count && blockIdx.x == 0 && threadIdx.x == 0) *count = (int64_t)off[n];
+}
+
+// leapfrog kick then drift: v += a dt_kick; x += v dt_drift
+__global__ void k_kick_drift(int64_t n3, double* __restrict__ x, double* __restrict__ v,
+                             const double* __restrict__ a, double dt_kick, double dt_drift) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n3;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double ak = a[k] * dt_kick;
+        const double vk = v[k] + ak;
+        v[k] = vk;
+        const double dx = vk * dt_drift;
+        x[k] = x[k] + dx;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -214,8 +230,17 @@ int ag_launch_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx, 
     return AG_OK;
 }
 
+int ag_launch_kick_drift(ag_ctx* c, int64_t n, double* x, double* v, const double* acc, double dt_kick,
+                         double dt_drift) {
+    PhaseScope phase(c, AG_PHASE_STEP);
+    hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(3 * n)), dim3(kThreads), 0, c->stream, 3 * n, x, v, acc,
+                       dt_kick, dt_drift);
+    return AG_OK;
+}
+
 int ag_launch_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin, int64_t step_ticks,
-                     int32_t tick_bin, double q_f, int32_t* active_idx, int64_t* n_active_dev) {
+                     int32_t tick_bin, double q_f, int32_t* active_idx, int64_t* n_active_dev,
+                     double* t0, double t) {
     PhaseScope phase(c, AG_PHASE_STEP);
     AG_TRY(ag_ensure(c->sel_flag, (size_t)n * sizeof(int32_t)));
     AG_TRY(ag_ensure(c->sel_off, (size_t)(n + 1) * sizeof(int32_t)));
@@ -225,7 +250,7 @@ int ag_launch_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin, int64
                        (int)tick_bin, q_f, flag);
     AG_TRY(ag_scan_i32(c, flag, off, n));
     hipLaunchKernelGGL(k_compact, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, flag, off,
-                       active_idx, n_active_dev);
+                       active_idx, n_active_dev, t0, t);
     return AG_OK;
 }
 

@@ -30,7 +30,6 @@ constexpr int kW = 64;          // lanes per wave = targets per group = tile siz
 constexpr int kPCap = 256;      // pending particle indices
 constexpr int kNCap = 128;      // pending accepted nodes
 constexpr int kSCap = 128;      // stacked cursor ranges
-constexpr int kSmallNode = 2;   // accepted nodes this small are summed pairwise
 
 // algorithmic operation count of one particle-node interaction (monopole +
 // quadrupole g and T, mean-velocity + quadrupole-rate jerk; fused
@@ -65,6 +64,7 @@ struct WalkOut {
     double G;
     int32_t* flags;
     int64_t iter_cap;   // > nodes + particles: every group finishes well within it
+    int small_node;     // accepted nodes this small are summed pairwise
     double* dldx;       // adjoint outputs
     double* dldm;
     const double* tin;  // adjoint: tidal tensor rows of the charged targets
@@ -493,7 +493,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
                 ca = L.x;                  // no charge below this node
             } else {
                 const bool acc_ok = mac_accept(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2);
-                if (acc_ok && L.z > kSmallNode) {
+                if (acc_ok && L.z > O.small_node) {
                     push_node = a;
                     ca = L.x;
                 } else if (acc_ok || leaf) {
@@ -931,7 +931,7 @@ static Tree make_tree(ag_ctx* c) {
 static int walk_grid(ag_ctx* c, int64_t max_groups) {
     int dev_cus = 256;
     (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    int64_t blocks = (int64_t)dev_cus * 16;                 // resident waves per CU at this register use
+    int64_t blocks = (int64_t)dev_cus * c->walk_waves_per_cu;
     if (blocks > max_groups) blocks = (max_groups + 7) / 8 * 8;
     if (blocks < 8) blocks = 8;
     return (int)blocks;
@@ -943,6 +943,7 @@ static WalkOut make_out(ag_ctx* c, double G) {
     O.G = G;
     O.flags = c->dflags.as<int32_t>();
     O.iter_cap = c->max_nodes + c->n + 1024;
+    O.small_node = c->small_node;
     return O;
 }
 

@@ -1,0 +1,117 @@
+"""Adaptive force updates driving a leapfrog integrator (the scheme of Sec. 2).
+
+Every particle advances with one global step dt (a stand-in for the hydro
+step of the paper, which a gravity-only code does not have).  At the start
+of each step the force-age counters advance by one tick (Eq. 3) and only the
+particles whose counter has reached q_f times their gravity bin (Eq. 4) get a
+fresh tree force, jerk and tidal tensor; their tidal timestep and bin are
+recomputed (Eq. 7).  Every other particle uses the jerk predictor (Eq. 6).
+q_f = 0 re-evaluates everybody every step: the standard scheme.
+
+Time is kept in integer ticks: dt_max = 2^ceil(log2 max dt_grav(0)) and one
+tick is the step of the deepest bin at t = 0, so every comparison in Eq. 4 is
+exact.  Bins deeper than the tick are clamped to it (updated every step).
+
+Step (kick-drift-kick):
+  v += a dt/2;  x += v dt;  t += dt
+  select due particles (Eq. 3, Eq. 4), stamping t0 = t for them
+  tree rebuild (or refit every other step, see ``rebuild_every``) with the
+  velocities predicted to time t (v + a dt/2)
+  fresh g, j, T for the due particles; their dt_grav and bin
+  a = a0 + j (t - t0) for all particles (exact a0 for the due ones)
+  v += a dt/2
+All arithmetic runs in the library's kernels; this module sequences calls.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import Context
+
+
+class AdaptiveIntegrator:
+    def __init__(self, ctx: Context, x, v, m, q_f: float, theta: float, eps: float, eta: float = 0.01,
+                 G: float = 1.0, n_leaf: int = 16, rebuild_every: int = 1):
+        self.ctx = ctx
+        dev = x.device
+        self.n = n = x.shape[0]
+        self.x = x.clone()
+        self.v = v.clone()
+        self.m = m
+        self.q_f, self.theta, self.eps, self.eta, self.G = q_f, theta, eps, eta, G
+        self.n_leaf = n_leaf
+        self.rebuild_every = max(1, int(rebuild_every))
+        self.a0 = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+        self.jerk = torch.zeros_like(self.a0)
+        self.tidal = torch.zeros((n, 6), dtype=torch.float64, device=dev)
+        self.acc = torch.zeros_like(self.a0)
+        self.t0 = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.tf = torch.zeros(n, dtype=torch.int64, device=dev)
+        self.bins = torch.zeros(n, dtype=torch.int8, device=dev)
+        self.dt_grav = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.active = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.n_active = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.vpred = torch.zeros_like(self.v)
+        self.scratch = torch.zeros_like(self.x)
+        self.t = 0.0
+        self.step_index = 0
+        self.evaluations = 0
+        # initial forces for everybody, then the time grid
+        ctx.tree_build(self.x, self.v, self.m, n_leaf)
+        ctx.grav_eval(None, theta, eps, G, self.a0, self.jerk, self.tidal)
+        ctx.grav_timestep(self.tidal, eta, 1.0, 60, self.dt_grav, self.bins)
+        ctx.sync()
+        dtg = self.dt_grav[torch.isfinite(self.dt_grav)]
+        self.dt_max = 2.0 ** math.ceil(math.log2(float(dtg.max().item())))
+        ctx.grav_timestep(self.tidal, eta, self.dt_max, 60, self.dt_grav, self.bins)
+        ctx.sync()
+        self.tick_bin = int(self.bins.max().item())
+        self.dt = self.dt_max * 2.0 ** (-self.tick_bin)
+        self.acc.copy_(self.a0)
+        self.evaluations += n
+        self._need_build = False
+
+    def step(self) -> int:
+        c, dt = self.ctx, self.dt
+        c.kick_drift(self.x, self.v, self.acc, 0.5 * dt, dt)
+        self.t += dt
+        self.step_index += 1
+        c.adaptive_select(self.tf, self.bins, 1, self.tick_bin, self.q_f, self.active, self.n_active,
+                          t0=self.t0, t=self.t)
+        # velocities at time t for the jerk: v(t) ~ v(t - dt/2) + a dt/2
+        self.vpred.copy_(self.v)
+        c.kick_drift(self.scratch, self.vpred, self.acc, 0.5 * dt, 0.0)
+        if self._need_build or (self.step_index - 1) % self.rebuild_every == 0:
+            c.tree_build(self.x, self.vpred, self.m, self.n_leaf)
+            self._need_build = False
+        else:
+            c.tree_refit(self.x, self.vpred, self.m)
+        k = int(self.n_active.item())
+        if k > 0:
+            idx = self.active[:k]
+            c.grav_eval(idx, self.theta, self.eps, self.G, self.a0, self.jerk, self.tidal)
+            c.grav_timestep(self.tidal, self.eta, self.dt_max, 60, self.dt_grav, self.bins, idx=idx)
+        c.grav_predict(self.a0, self.jerk, self.t0, self.t, self.acc)
+        c.kick_drift(self.x, self.v, self.acc, 0.5 * dt, 0.0)
+        self.evaluations += k
+        return k
+
+    def state(self) -> dict:
+        """Everything needed to resume bit for bit (see ``restore``)."""
+        keys = ["x", "v", "a0", "jerk", "tidal", "acc", "t0", "tf", "bins", "dt_grav"]
+        s = {k: getattr(self, k).clone() for k in keys}
+        s.update(t=self.t, step_index=self.step_index, evaluations=self.evaluations, dt=self.dt,
+                 dt_max=self.dt_max, tick_bin=self.tick_bin)
+        return s
+
+    def restore(self, s: dict):
+        """Resume from ``state()``.  The next step rebuilds the tree, so the
+        continuation is bit-identical when the saved step was followed by a
+        rebuild anyway (always with rebuild_every = 1)."""
+        for k in ["x", "v", "a0", "jerk", "tidal", "acc", "t0", "tf", "bins", "dt_grav"]:
+            getattr(self, k).copy_(s[k])
+        for k in ["t", "step_index", "evaluations", "dt", "dt_max", "tick_bin"]:
+            setattr(self, k, s[k])
+        self._need_build = True

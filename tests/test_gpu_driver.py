@@ -1,0 +1,158 @@
+"""GPU tests of the adaptive integrator (Sec. 2 scheme around the solver), the
+kick-drift kernel, graph capture/replay and the launch options."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _t(a, dtype=None):
+    return torch.tensor(a, device=DEV) if dtype is None else torch.tensor(a, dtype=dtype, device=DEV)
+
+
+def test_kick_drift_bit_exact(ctx):
+    rng = np.random.default_rng(1)
+    n = 10001
+    x, v, a = rng.normal(size=(3, n, 3))
+    tx, tv = _t(x), _t(v)
+    ctx.kick_drift(tx, tv, _t(a), 0.125, 0.37)
+    ctx.sync()
+    v2 = v + a * 0.125
+    x2 = x + v2 * 0.37
+    assert np.array_equal(tv.cpu().numpy(), v2)
+    assert np.array_equal(tx.cpu().numpy(), x2)
+
+
+def test_select_stamps_t0(ctx, orc):
+    rng = np.random.default_rng(2)
+    n = 5000
+    bins = rng.integers(0, 6, n).astype(np.int8)
+    tf = rng.integers(0, 32, n).astype(np.int64)
+    t0 = rng.uniform(0, 1, n)
+    tt0 = _t(t0)
+    tfd = _t(tf)
+    act = torch.empty(n, dtype=torch.int32, device=DEV)
+    cnt = torch.empty(1, dtype=torch.int64, device=DEV)
+    ctx.adaptive_select(tfd, _t(bins), 1, 5, 0.5, act, cnt, t0=tt0, t=7.25)
+    ctx.sync()
+    _, mask, idx = orc.select(tf, bins, 1, 5, 0.5)
+    got = tt0.cpu().numpy()
+    assert np.all(got[idx] == 7.25)
+    assert np.array_equal(got[mask == 0], t0[mask == 0])
+
+
+def _clumps(n):
+    x, v, m, _ = workloads.clumps(n, seed=3)
+    return _t(x), _t(v), _t(m), (x, v, m)
+
+
+def test_adaptive_counts_and_force_error(ag, orc):
+    from paper_2010_13792_amd.driver import AdaptiveIntegrator
+    n = 1 << 14
+    tx, tv, tm, (x, v, m) = _clumps(n)
+    steps = 12
+    with ag.Context(0) as c:
+        base = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.0, theta=0.5, eps=1e-3)
+        for _ in range(steps):
+            assert base.step() == n          # q_f = 0: the every-step scheme
+        ad = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.5, theta=0.5, eps=1e-3)
+        counts = [ad.step() for _ in range(steps)]
+        c.sync()
+        assert sum(counts) < steps * n
+        # the deepest bin holds particles, and they are refreshed every step
+        assert min(counts) > 0
+        xs = ad.x.cpu().numpy()
+        vs = ad.vpred.cpu().numpy()
+        rows = np.random.default_rng(3).choice(n, 1024, replace=False)
+        ar, _, _ = orc.direct(xs, vs, m, 1e-3, 1.0, rows)
+        err = rel_err(ad.acc.cpu().numpy()[rows], ar)
+        assert np.median(err) < 2e-3
+
+
+def test_adaptive_resume_bit_exact(ag):
+    from paper_2010_13792_amd.driver import AdaptiveIntegrator
+    n = 1 << 13
+    tx, tv, tm, _ = _clumps(n)
+    with ag.Context(0) as c:
+        a = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.25, theta=0.6, eps=1e-3)
+        for _ in range(6):
+            a.step()
+        c.sync()
+        ref = a.state()
+        b = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.25, theta=0.6, eps=1e-3)
+        for _ in range(3):
+            b.step()
+        saved = {k: (v.cpu() if torch.is_tensor(v) else v) for k, v in b.state().items()}
+        r = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.25, theta=0.6, eps=1e-3)
+        r.restore({k: (v.to(DEV) if torch.is_tensor(v) else v) for k, v in saved.items()})
+        for _ in range(3):
+            r.step()
+        c.sync()
+        got = r.state()
+        for k in ["x", "v", "acc", "tf", "bins", "t0"]:
+            assert torch.equal(got[k], ref[k]), k
+        assert got["evaluations"] == ref["evaluations"]
+
+
+def test_graph_replay_matches_eager(ag):
+    d = workloads.batched_plummer(nsys=8, seed=9, nmin=500, nmax=4000)
+    x, v, m = d["x"], d["v"], d["m"]
+    n = len(m)
+    tx, tv, tm = _t(x), _t(v), _t(m)
+    toff = _t(d["offsets"], torch.int64)
+    tact = _t(d["active"], torch.int32)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+    jerk, tid = torch.zeros_like(acc), torch.zeros((n, 6), dtype=torch.float64, device=DEV)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream), ag.Context(0, stream) as c:
+        c.tree_build_batched(tx, tv, tm, toff, 16)
+        c.grav_eval_batched(tact, 0.5, 0.01, 1.0, acc, jerk, tid)
+        c.sync()
+        eager = acc.clone()
+        c.graph_begin()
+        c.tree_build_batched(tx, tv, tm, toff, 16)
+        c.grav_eval_batched(tact, 0.5, 0.01, 1.0, acc, jerk, tid)
+        c.graph_end()
+        for rep in range(3):
+            acc.zero_()
+            stream.synchronize()
+            c.graph_replay()
+            c.sync()
+            assert torch.equal(acc, eager), rep
+        # new positions in place, replay again: same as an eager run on them
+        tx.mul_(1.5)
+        c.graph_replay()
+        c.sync()
+        replayed = acc.clone()
+        c.tree_build_batched(tx, tv, tm, toff, 16)
+        c.grav_eval_batched(tact, 0.5, 0.01, 1.0, acc, jerk, tid)
+        c.sync()
+        assert torch.equal(acc, replayed)
+
+
+def test_options(ag, ctx):
+    x, v, m = workloads.plummer(3000, seed=4)
+    res = []
+    for waves, small in [(16, 2), (4, 2), (8, 8)]:
+        ctx.set_option(ag.AG_OPT_WALK_WAVES_PER_CU, waves)
+        ctx.set_option(ag.AG_OPT_SMALL_NODE, small)
+        ctx.tree_build(_t(x), _t(v), _t(m), 16)
+        acc = torch.zeros((3000, 3), dtype=torch.float64, device=DEV)
+        ctx.grav_eval(None, 0.6, 0.01, 1.0, acc, None, None)
+        ctx.sync()
+        res.append(acc.cpu().numpy())
+    ctx.set_option(ag.AG_OPT_WALK_WAVES_PER_CU, 16)
+    ctx.set_option(ag.AG_OPT_SMALL_NODE, 2)
+    # the number of resident waves only changes which wave walks which group
+    assert np.array_equal(res[0], res[1])
+    # summing small accepted nodes pairwise only changes the approximation
+    assert np.median(rel_err(res[2], res[0])) < 1e-3
+    with pytest.raises(ag.AgError):
+        ctx.set_option(ag.AG_OPT_WALK_WAVES_PER_CU, 0)
+    with pytest.raises(ag.AgError):
+        ctx.set_option(99, 1)
