@@ -60,6 +60,8 @@ def parse():
                          "configurations and print their own JSON line")
     ap.add_argument("--adaptive-steps", type=int, default=200)
     ap.add_argument("--rebuild-every", type=int, default=1)
+    ap.add_argument("--step-shift", type=int, default=0,
+                    help="adaptive: global step = 2^-shift x the shortest gravity bin")
     return ap.parse_args()
 
 

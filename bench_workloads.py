@@ -99,7 +99,7 @@ def run_adaptive(args):
     for q in [0.0, 0.125, 0.25, 0.5, 1.0]:
         with ag.Context(0) as c:
             integ = AdaptiveIntegrator(c, tx, tv, tm, q_f=q, theta=0.7, eps=1e-3, eta=0.01,
-                                       rebuild_every=args.rebuild_every)
+                                       rebuild_every=args.rebuild_every, step_shift=args.step_shift)
             c.sync()
             errs = {}
 
@@ -108,6 +108,7 @@ def run_adaptive(args):
                 vs = integ.vpred.cpu().numpy() if step > 0 else integ.v.cpu().numpy()
                 ar, _, _ = oracle.direct(xs, vs, m, 1e-3, 1.0, rows)
                 errs[step] = float(np.median(_rel(integ.acc.cpu().numpy()[rows], ar)))
+                log(f"adaptive q_f={q} step {step}: median error of the force in use {errs[step]:.2e}")
 
             if 0 in checkpoints:
                 check(0)
@@ -143,6 +144,7 @@ def run_adaptive(args):
     ok = [q for q, r in runs.items() if max(r["median_rel_err_used_force"].values()) <= 1e-3]
     return {"workload": f"64 Plummer clumps N={n}, {steps} steps, theta=0.7 eps=1e-3 eta=0.01",
             "metric": "adaptive vs every-step speedup", "rebuild_every": args.rebuild_every,
+            "step_shift": args.step_shift,
             "runs": res, "largest_q_f_within_1e-3": max(ok) if ok else None}
 
 

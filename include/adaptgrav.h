@@ -93,8 +93,13 @@ const char *ag_last_error(void);
  *   AG_OPT_WALK_WAVES_PER_CU   resident walk waves launched per CU [16]
  *   AG_OPT_SMALL_NODE          accepted nodes with at most this many particles
  *                              are summed pair by pair instead [2]
- * Values outside the documented ranges (1..64, 0..16) give AG_EINVAL. */
-enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2 };
+ *   AG_OPT_GROUP_SPAN          a target group never spans a cell holding more
+ *                              than this many particles (active or not), so
+ *                              sparse active sets still give compact groups;
+ *                              0 = no limit [128]
+ * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30) give
+ * AG_EINVAL. */
+enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
 /* HIP-graph capture of a call sequence on the context's stream (which must

@@ -416,6 +416,11 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
             if (value < 0 || value > 16) return ag_fail(AG_EINVAL, "small-node size must be in [0, 16]");
             c->small_node = (int)value;
             return AG_OK;
+        case AG_OPT_GROUP_SPAN:
+            if (value != 0 && (value < 64 || value > ((int64_t)1 << 30)))
+                return ag_fail(AG_EINVAL, "group span must be 0 or in [64, 2^30]");
+            c->group_span = (int)value;
+            return AG_OK;
         default:
             return ag_fail(AG_EINVAL, "unknown option %d", option);
     }

@@ -63,6 +63,7 @@ struct ag_ctx {
     Timing timing;
     int walk_waves_per_cu = 16;
     int small_node = 2;
+    int group_span = 128;
     bool capturing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

@@ -674,6 +674,7 @@ struct GroupCtx {
     const int64_t* __restrict__ sys_off;
     int n_sys;
     int sys_levels;
+    int span;   // cap on the particles of a group's cells (0 = none)
 };
 
 __device__ __forceinline__ int sys_of_pos(const GroupCtx& C, int64_t p) {
@@ -693,7 +694,9 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
     const int a0 = C.aoff[L.y];
     const int a = C.aoff[L.y + L.z] - a0;
     const bool forced = lvl < C.sys_levels;
-    const bool big = forced || a > kW;
+    // too many targets for one wave, or (span) a cell too large to be one
+    // compact group even if few of its particles are active
+    const bool big = forced || a > kW || (C.span > 0 && !leaf && L.z > C.span);
     int ng = 0;
     auto emit = [&](int start, int cnt, int64_t pos) {
         if (out) out[ng] = make_int4(start, cnt, C.n_sys > 1 ? sys_of_pos(C, pos) : 0, 0);
@@ -707,28 +710,32 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
         for (int k = 0; k < a; k += kW) emit(a0 + k, a - k < kW ? a - k : kW, L.y);
         return ng;
     }
-    int run_start = 0, run_cnt = 0;
+    int run_start = 0, run_cnt = 0, run_span = 0;
     int64_t run_pos = 0;
     for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = C.link[ch].x, ++k8) {
         const int4 Lc = C.link[ch];
         const int c0 = C.aoff[Lc.y];
         const int ac = C.aoff[Lc.y + Lc.z] - c0;
-        const bool bigc = (Lc.w & 0xff) < C.sys_levels || ac > kW;
+        const bool leafc = (Lc.w & 0x100) != 0;
+        const bool bigc = (Lc.w & 0xff) < C.sys_levels || ac > kW || (C.span > 0 && !leafc && Lc.z > C.span);
         if (bigc || ac == 0 || forced) {
             if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
             run_cnt = 0;
+            run_span = 0;
             if (forced && !bigc && ac > 0) emit(c0, ac, Lc.y);
             continue;
         }
-        if (run_cnt + ac > kW) {
-            emit(run_start, run_cnt, run_pos);
+        if (run_cnt + ac > kW || (C.span > 0 && run_span + Lc.z > C.span)) {
+            if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
             run_cnt = 0;
+            run_span = 0;
         }
         if (run_cnt == 0) {
             run_start = c0;
             run_pos = Lc.y;
         }
         run_cnt += ac;
+        run_span += Lc.z;
     }
     if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
     return ng;
@@ -788,7 +795,7 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
     }
     AG_TRY(ag_scan_i32(c, flag, off, n));
     hipLaunchKernelGGL(k_compact_pos, dim3(grid_for(n)), dim3(256), 0, st, n, flag, off, c->act_pos.as<int32_t>());
-    GroupCtx C{c->nd_link.as<int4>(), off, c->sys_off.as<int64_t>(), c->n_sys, c->sys_levels};
+    GroupCtx C{c->nd_link.as<int4>(), off, c->sys_off.as<int64_t>(), c->n_sys, c->sys_levels, c->group_span};
     const int64_t* hdr = c->tree_hdr.as<int64_t>();
     int32_t* gcnt = c->grp_cnt.as<int32_t>();
     int32_t* goff = c->grp_off.as<int32_t>();

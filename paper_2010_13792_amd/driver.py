@@ -33,7 +33,11 @@ from . import Context
 
 class AdaptiveIntegrator:
     def __init__(self, ctx: Context, x, v, m, q_f: float, theta: float, eps: float, eta: float = 0.01,
-                 G: float = 1.0, n_leaf: int = 16, rebuild_every: int = 1):
+                 G: float = 1.0, n_leaf: int = 16, rebuild_every: int = 1, step_shift: int = 0):
+        """step_shift h: the global step is 2^-h times the shortest gravity
+        bin at t = 0 (h = 0: the step equals the shortest gravity step; h > 0
+        models a non-gravity step constraint tighter than gravity's, the
+        regime in which the scheme saves work)."""
         self.ctx = ctx
         dev = x.device
         self.n = n = x.shape[0]
@@ -67,7 +71,7 @@ class AdaptiveIntegrator:
         self.dt_max = 2.0 ** math.ceil(math.log2(float(dtg.max().item())))
         ctx.grav_timestep(self.tidal, eta, self.dt_max, 60, self.dt_grav, self.bins)
         ctx.sync()
-        self.tick_bin = int(self.bins.max().item())
+        self.tick_bin = int(self.bins.max().item()) + int(step_shift)
         self.dt = self.dt_max * 2.0 ** (-self.tick_bin)
         self.acc.copy_(self.a0)
         self.evaluations += n
