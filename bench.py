@@ -32,10 +32,60 @@ sys.path.insert(0, ROOT)
 
 METRIC = "force evals/s at ≤1e-3 median rel force error; adaptive vs every-step speedup"
 PP_FLOPS = 60     # per particle-particle interaction (counted from the written formulas)
-PN_FLOPS = 222    # per particle-node interaction
+PN_FLOPS = 183    # per particle-node interaction
 PEAK_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6: VALU FMA issue, packed FP32 off
 PEAK_FP32_PACKED_SPEC = 157.3
 PEAK_HBM_GBS = 8000.0
+
+# HBM traffic of the walk kernel at the default workload, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 4 dispatches)
+# scaled by what the same counters read for a plain 1 GiB device copy
+# (FETCH_SIZE 524305 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  Valid only
+# while the walk kernel's sources hash to `src_sha256`; reported as null
+# otherwise, or for another workload.
+WALK_COUNTERS = {
+    "src_sha256": "20932e01ba3653aa0df3c6af35bc261baa2b686b87a1f1e61a89a7586693f9ff",
+    "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16},
+    "fetch_kib": 124548.7, "write_kib": 169624.8,
+    "fetch_factor": 1048576.0 / 524304.8, "write_factor": 1.0,
+}
+WALK_SOURCES = ("paper_2010_13792_amd/csrc/k_walk.hip", "paper_2010_13792_amd/csrc/pair.h",
+                "paper_2010_13792_amd/csrc/ag_internal.h")
+# algorithmic bytes of one build: per particle, read x, v, m (56), write them
+# in key order (56), keys and rows (24); per node, link 16, centre 32, box 32,
+# FP32 moments 64 and FP64 moments 200 (344)
+BUILD_BYTES_PER_PARTICLE = 56 + 56 + 24
+BUILD_BYTES_PER_NODE = 344
+
+
+def walk_src_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def walk_traffic(args):
+    """HBM bytes per walk launch from the stored counters, or None."""
+    w = WALK_COUNTERS["workload"]
+    same = (args.n, args.theta, args.eps, args.n_leaf) == (w["n"], w["theta"], w["eps"], w["n_leaf"])
+    if not same or walk_src_digest() != WALK_COUNTERS["src_sha256"]:
+        return None
+    return 1024.0 * (WALK_COUNTERS["fetch_kib"] * WALK_COUNTERS["fetch_factor"] +
+                     WALK_COUNTERS["write_kib"] * WALK_COUNTERS["write_factor"])
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def log(msg):
@@ -51,13 +101,16 @@ def parse():
     ap.add_argument("--theta", type=float, default=0.7)
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--n-leaf", type=int, default=16)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target host time of the oracle baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0,
+                    help="upper bound on the host time of the oracle baseline sample")
+    ap.add_argument("--sample", type=int, default=16384,
+                    help="targets checked against the oracle (and timed as the CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="tree",
-                    choices=["tree", "direct", "adaptive", "batched", "adjoint"],
+                    choices=["tree", "direct", "adaptive", "batched", "adjoint", "copy"],
                     help="tree: the headline line (default); the others measure the remaining "
-                         "configurations and print their own JSON line")
+                         "configurations and print their own JSON line (copy: a plain 1 GiB device "
+                         "copy that calibrates the HBM byte counters)")
     ap.add_argument("--adaptive-steps", type=int, default=200)
     ap.add_argument("--rebuild-every", type=int, default=1)
     ap.add_argument("--step-shift", type=int, default=0,
@@ -154,6 +207,9 @@ def main():
     walk_flops = pp_step * PP_FLOPS + pn_step * PN_FLOPS
     achieved_tflops = walk_flops / (walk_ms * 1e-3) / 1e12
     value = evals_per_step / (ms_step * 1e-3)
+    build_ms = phases["build"]["ms"] / max(1, phases["build"]["launches"])
+    build_bytes = n * BUILD_BYTES_PER_PARTICLE + nn * BUILD_BYTES_PER_NODE
+    traffic = walk_traffic(args)
     log(f"bench: {ms_step:.3f} ms/step, walk {walk_ms:.3f} ms, {achieved_tflops:.2f} TFLOP/s")
 
     # accuracy on a sample against the FP64 oracle; the same run times the oracle
@@ -167,7 +223,7 @@ def main():
         t_a = time.perf_counter()
         oracle.direct(x, v, m, args.eps, G, probe)
         t_probe = time.perf_counter() - t_a
-        k = int(min(n, max(256, 64 * args.cpu_seconds / max(t_probe, 1e-6))))
+        k = int(min(n, args.sample, max(256, 64 * args.cpu_seconds / max(t_probe, 1e-6))))
         rows = rng.choice(n, k, replace=False)
         log(f"bench: oracle sample {k} targets (probe {t_probe:.2f} s / 64)")
         t_a = time.perf_counter()
@@ -176,10 +232,18 @@ def main():
         err = np.linalg.norm(a_gpu[rows] - ar, axis=1) / np.linalg.norm(ar, axis=1)
         err_med = float(np.median(err))
         err_p99 = float(np.percentile(err, 99))
-        cpu = {"value": k / t_o, "unit": "force evals/s", "cores": oracle.num_threads(),
+        # one-thread rate on the first 256 sampled targets
+        threads = oracle.num_threads()
+        oracle.set_threads(1)
+        t_a = time.perf_counter()
+        oracle.direct(x, v, m, args.eps, G, rows[:256])
+        t_1 = time.perf_counter() - t_a
+        oracle.set_threads(0)
+        cpu = {"value": k / t_o, "unit": "force evals/s", "cores": threads,
                "kind": "oracle",
                "sample": f"{k} random targets of the same N={n} particle set; FP64 direct sum "
-                         f"over all {n} sources ({t_o:.1f} s)"}
+                         f"over all {n} sources ({t_o:.1f} s)",
+               "one_thread_value": 256 / t_1, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
     out = {
         "metric": METRIC,
@@ -203,7 +267,9 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
+            "hbm_gbs": None if traffic is None else traffic / (walk_ms * 1e-3) / 1e9,
+            "hbm_frac": None if traffic is None else traffic / (walk_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "kernel": "k_walk", "kernel_ms": walk_ms,
             "flops_per_launch": walk_flops,
             "peak_note": "FP32 VALU FMA issue rate with packed FP32 disabled "
@@ -214,6 +280,9 @@ def main():
         "walk_interactions_per_s": (pp_step + pn_step) / (walk_ms * 1e-3),
         "per_target": {"pp": pp_step / max(1, evals_per_step), "pn": pn_step / max(1, evals_per_step)},
         "phases_ms_per_step": {p: phases[p]["ms"] / args.steps for p in phases},
+        "build": {"ms": build_ms, "algorithmic_bytes": build_bytes,
+                  "gbs": build_bytes / (build_ms * 1e-3) / 1e9,
+                  "hbm_frac": build_bytes / (build_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
         "tree": {"nodes": nn, "max_level": max_level,
                  "groups_per_step": st["n_groups"] / args.steps,
                  "targets_per_group": st["n_targets"] / max(1, st["n_groups"])},

@@ -13,6 +13,8 @@
             autotuner; error on 64 sampled targets per system.
   adjoint   uniform sphere N = 2^18 (eps = 1e-3, theta = 0.6), Gaussian w:
             forward and adjoint walks, errors against the oracle gradient.
+  copy      a plain device copy of 1 GiB, the calibration of the HBM byte
+            counters (FETCH_SIZE, WRITE_SIZE) used for the walk's traffic.
 Inputs are seeded synthetic particle sets standing in for the paper's
 hydro test problems.
 """
@@ -31,7 +33,8 @@ from paper_2010_13792_amd import autotune
 from paper_2010_13792_amd.driver import AdaptiveIntegrator
 
 DEV = torch.device("cuda:0")
-PP_FLOPS, PN_FLOPS = 60, 222
+PP_FLOPS, PN_FLOPS = 60, 183
+PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # FP64 vector and unpacked FP32 FMA issue rate
 
 
 def log(msg):
@@ -75,6 +78,8 @@ def run_direct(args):
             ms = e0.elapsed_time(e1) / reps
             err = _rel(acc.cpu().numpy(), ar)
             out[name] = {"ms": ms, "pairs_per_s": n * (n - 1) / (ms * 1e-3), "evals_per_s": n / (ms * 1e-3),
+                         "tflops": n * (n - 1) * PP_FLOPS / (ms * 1e-3) / 1e12,
+                         "frac_of_peak": n * (n - 1) * PP_FLOPS / (ms * 1e-3) / 1e12 / PEAK_TFLOPS,
                          "median_rel_err": float(np.median(err)), "max_rel_err": float(err.max())}
     t_a = time.perf_counter()
     oracle.direct(x, v, m, eps, 1.0)
@@ -93,8 +98,8 @@ def run_adaptive(args):
     x, v, m, _ = workloads.clumps(n, seed=3)
     tx, tv, tm = _t(x), _t(v), _t(m)
     rng = np.random.default_rng(33)
-    rows = rng.choice(n, 1024, replace=False)
-    checkpoints = sorted({0, steps // 2, steps})
+    rows = rng.choice(n, 4096, replace=False)
+    checkpoints = sorted({0, steps // 4, steps // 2, 3 * steps // 4, steps})
     runs = {}
     for q in [0.0, 0.125, 0.25, 0.5, 1.0]:
         with ag.Context(0) as c:
@@ -260,10 +265,27 @@ def run_adjoint(args):
             ms = e0.elapsed_time(e1) / reps
             st = c.stats_read()
             out[name] = {"ms": ms, "interactions_per_s": (st["n_pp"] + st["n_pn"]) / reps / (ms * 1e-3)}
-    rows = np.random.default_rng(6).choice(n, 2048, replace=False)
+    rows = np.random.default_rng(6).choice(n, 16384, replace=False)
     rx, rm = oracle.adjoint(x, m, w, eps, 1.0, rows)
     ex = _rel(dx.cpu().numpy()[rows], rx)
     out["dLdx_rel_err"] = {"median": float(np.median(ex)), "p99": float(np.percentile(ex, 99))}
     em = np.abs(dm.cpu().numpy()[rows] - rm) / np.abs(rm)
     out["dLdm_rel_err_plain"] = {"median": float(np.median(em)), "p99": float(np.percentile(em, 99))}
     return out
+
+
+# ---------------------------------------------------------------------------
+def run_copy(args):
+    n = 1 << 27                      # 2^27 doubles = 1 GiB
+    a = torch.ones(n, dtype=torch.float64, device=DEV)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for _ in range(3):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    return {"workload": "device copy of 1 GiB (counter calibration)", "bytes_read": n * 8,
+            "bytes_written": n * 8, "ms": ms, "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9}

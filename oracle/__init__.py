@@ -65,6 +65,7 @@ def _load():
         lib.orc_adjoint.argtypes = [I64, P, P, P, D, D, I64, P, P, P]
         lib.orc_moments.argtypes = [I64, P, P, P, P, P]
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -82,6 +83,11 @@ def _ptr(a):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(k: int) -> None:
+    """Use ``k`` OpenMP threads in later calls (``k <= 0``: the default)."""
+    _load().orc_set_threads(int(k))
 
 
 def kernel(r, h):

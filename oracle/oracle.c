@@ -378,3 +378,15 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of later calls (k <= 0: the OpenMP default). */
+void orc_set_threads(int k)
+{
+#ifdef _OPENMP
+    static int dflt = 0;
+    if (dflt == 0) dflt = omp_get_max_threads();
+    omp_set_num_threads(k > 0 ? k : dflt);
+#else
+    (void)k;
+#endif
+}

@@ -209,6 +209,37 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t* __re
     }
 }
 
+// Second pass of the two-launch scan: every tile first sums the totals of
+// the tiles before it (at most kScanThreads * kScanTopItems of them), then
+// scans its own items; the last tile writes the grand total.
+constexpr int kScanTopItems = 4;
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply2(const int32_t* __restrict__ in, int64_t n,
+                                                              const int32_t* __restrict__ tile_sum,
+                                                              int32_t* __restrict__ out) {
+    __shared__ int s_w[17];
+    int pre = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += kScanThreads) pre += tile_sum[t];
+    int pre_tot;
+    block_excl_scan(pre, s_w, &pre_tot);
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int off = block_excl_scan(s, s_w, &tot) + pre_tot;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = off;
+        off += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = pre_tot + tot;
+}
+
 }  // namespace
 
 int ag_scan_i32(ag_ctx* c, const int32_t* in, int32_t* out, int64_t n) {
@@ -217,6 +248,11 @@ int ag_scan_i32(ag_ctx* c, const int32_t* in, int32_t* out, int64_t n) {
     AG_TRY(ag_ensure(c->scan_tmp, (size_t)ntiles * sizeof(int32_t)));
     int32_t* ts = c->scan_tmp.as<int32_t>();
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, c->stream, in, n, ts);
+    if (ntiles <= (int64_t)kScanThreads * kScanTopItems) {
+        hipLaunchKernelGGL(k_scan_apply2, dim3((unsigned)ntiles), dim3(kScanThreads), 0, c->stream, in, n, ts,
+                           out);
+        return AG_OK;
+    }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, c->stream, ts, ntiles, out + n);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, c->stream, in, n, ts, out);
     return AG_OK;

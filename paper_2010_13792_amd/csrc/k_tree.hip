@@ -6,7 +6,7 @@
 //   2. 63-bit Morton keys: 21 octal digits; with several systems the top
 //      digits hold the system number and the rest its own cube's Morton code;
 //   3. stable LSD radix sort of (key, row) pairs, 8 bits per pass;
-//   4. gather of x, v, m into key order (FP64 and FP32 copies);
+//   4. x, v, m into key order (FP64 and FP32 copies);
 //   5. topology straight from the sorted keys: with c_p the number of octal
 //      digits key[p] shares with key[p-1], the cell of level l that contains
 //      position p starts at p iff c_p < l.  A cell is split while it holds
@@ -49,7 +49,7 @@ __device__ __forceinline__ int sys_of(const int64_t* __restrict__ off, int n_sys
 // ---------------------------------------------------------------------------
 // 1. bounding cubes
 // ---------------------------------------------------------------------------
-constexpr int64_t kBoxChunk = 8192;
+constexpr int64_t kBoxChunk = 2048;
 
 __global__ void k_box_init(int n_sys, uint64_t* __restrict__ box, int32_t* __restrict__ blk_off,
                            const int64_t* __restrict__ off) {
@@ -185,24 +185,79 @@ __global__ void __launch_bounds__(kThreads) k_rs_hist(const uint64_t* __restrict
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = t;
 }
 
+// exclusive scan of one value per thread over a 256-thread block; *total
+// receives the block's sum
+__device__ __forceinline__ int block_excl_scan256(int v, int* s_tmp, int* total) {
+    const int lane = ag_lane(), w = threadIdx.x >> 6;
+    const int inc = ag_wave_incl_scan(v);
+    if (lane == 63) s_tmp[w] = inc;
+    __syncthreads();
+    int pre = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < kThreads / 64; ++q) {
+        pre += q < w ? s_tmp[q] : 0;
+        all += s_tmp[q];
+    }
+    __syncthreads();
+    *total = all;
+    return pre + inc - v;
+}
+
+// Per digit d (one block each): exclusive scan of the per-block counts
+// hist[d][0 .. nblocks) into hoff, and the digit's total into tot[d].
+__global__ void __launch_bounds__(kThreads) k_rs_rowscan(const int32_t* __restrict__ hist, int nblocks,
+                                                         int32_t* __restrict__ hoff, int32_t* __restrict__ tot) {
+    __shared__ int s_tmp[kThreads / 64];
+    const int64_t row = (int64_t)blockIdx.x * nblocks;
+    int carry = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += kThreads) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nblocks ? hist[row + b] : 0;
+        int sum;
+        const int ex = block_excl_scan256(v, s_tmp, &sum);
+        if (b < nblocks) hoff[row + b] = carry + ex;
+        carry += sum;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Stable scatter of one tile of (key, value) pairs by one 8-bit digit.  The
+// tile is first ranked and reordered by digit in LDS (ballot matching within
+// each wave, per-wave counts across the block), then written out in digit
+// order so that each digit's run goes to consecutive addresses.  With `rank`
+// set (last pass), rank[value] receives the value's final position.
 __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restrict__ kin,
                                                          const int32_t* __restrict__ vin, int64_t n,
                                                          int shift, int nblocks,
+                                                         const int32_t* __restrict__ hist,
                                                          const int32_t* __restrict__ hoff,
+                                                         const int32_t* __restrict__ tot,
                                                          uint64_t* __restrict__ kout,
-                                                         int32_t* __restrict__ vout) {
-    __shared__ int s_goff[256];
+                                                         int32_t* __restrict__ vout,
+                                                         int32_t* __restrict__ rank) {
+    __shared__ uint64_t s_key[kRsTile];
+    __shared__ int s_val[kRsTile];
+    __shared__ int s_gofs[256];   // global position of the tile's first digit-d element minus its tile slot
+    __shared__ int s_loc[256];    // tile slot of the first digit-d element
     __shared__ int s_run[256];
     __shared__ int s_w[4][256];
-    s_goff[threadIdx.x] = hoff[(int64_t)threadIdx.x * nblocks + blockIdx.x];
-    s_run[threadIdx.x] = 0;
-    const int w = threadIdx.x >> 6;
+    __shared__ int s_tmp[kThreads / 64];
+    const int t = threadIdx.x;
+    {
+        int all;
+        const int base_d = block_excl_scan256(tot[t], s_tmp, &all);
+        const int loc = block_excl_scan256(hist[(int64_t)t * nblocks + blockIdx.x], s_tmp, &all);
+        s_loc[t] = loc;
+        s_gofs[t] = base_d + hoff[(int64_t)t * nblocks + blockIdx.x] - loc;
+        s_run[t] = 0;
+    }
+    const int w = t >> 6;
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     for (int k = 0; k < kRsItems; ++k) {
-        const int64_t i = base + k * kThreads + threadIdx.x;
+        const int64_t i = base + k * kThreads + t;
         const bool valid = i < n;
-        uint64_t key = valid ? kin[i] : 0ull;
-        int32_t val = valid ? vin[i] : 0;
+        const uint64_t key = valid ? kin[i] : 0ull;
+        const int32_t val = valid ? vin[i] : 0;
         const int d = (int)((key >> shift) & 255);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -214,16 +269,15 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restr
         const int r = ag_prefix_count(peers);
         const int cnt = __popcll(peers);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s_w[q][threadIdx.x] = 0;
+        for (int q = 0; q < 4; ++q) s_w[q][t] = 0;
         __syncthreads();
         if (valid && r == 0) s_w[w][d] = cnt;
         __syncthreads();
         {
-            const int t = threadIdx.x;
             int run = s_run[t];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                int c = s_w[q][t];
+                const int c = s_w[q][t];
                 s_w[q][t] = run;
                 run += c;
             }
@@ -231,25 +285,35 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restr
         }
         __syncthreads();
         if (valid) {
-            const int pos = s_goff[d] + s_w[w][d] + r;
-            kout[pos] = key;
-            vout[pos] = val;
+            const int slot = s_loc[d] + s_w[w][d] + r;
+            s_key[slot] = key;
+            s_val[slot] = val;
         }
         __syncthreads();
+    }
+    const int64_t rem = n - base;
+    const int nvalid = rem < kRsTile ? (int)rem : kRsTile;
+    for (int j = t; j < nvalid; j += kThreads) {
+        const uint64_t key = s_key[j];
+        const int d = (int)((key >> shift) & 255);
+        const int pos = s_gofs[d] + j;
+        kout[pos] = key;
+        const int32_t val = s_val[j];
+        vout[pos] = val;
+        if (rank) rank[val] = pos;
     }
 }
 
 // ---------------------------------------------------------------------------
-// 4. gather into key order
+// 4. particle data into key order: coalesced reads in input order, each row
+//    written to its sorted position (scattered 32-byte stores)
 // ---------------------------------------------------------------------------
-__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
-                         const double* __restrict__ v, const double* __restrict__ m,
-                         int32_t* __restrict__ rank, double4* __restrict__ spos,
-                         double4* __restrict__ svel, float4* __restrict__ svf) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = perm[p];
-        if (rank) rank[i] = (int32_t)p;
+__global__ void k_to_sorted(int64_t n, const int32_t* __restrict__ rank, const double* __restrict__ x,
+                            const double* __restrict__ v, const double* __restrict__ m,
+                            double4* __restrict__ spos, double4* __restrict__ svel, float4* __restrict__ svf) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = rank[i];
         const double mi = m[i];
         const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
         spos[p] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], mi);
@@ -641,7 +705,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     AG_TRY(ag_ensure(c->keys[0], n * 8)); AG_TRY(ag_ensure(c->keys[1], n * 8));
     AG_TRY(ag_ensure(c->vals[0], n * 4)); AG_TRY(ag_ensure(c->vals[1], n * 4));
     const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
-    AG_TRY(ag_ensure(c->sort_hist, (size_t)(256 * nblocks + 1) * 4));
+    AG_TRY(ag_ensure(c->sort_hist, (size_t)(256 * nblocks + 256 + 1) * 4));
     AG_TRY(ag_ensure(c->pos_off, (size_t)(256 * (int64_t)nblocks + 1 > n + 1 ? 256 * (int64_t)nblocks + 1 : n + 1) * 4));
     AG_TRY(ag_ensure(c->perm, n * 4)); AG_TRY(ag_ensure(c->rank, n * 4));
     AG_TRY(ag_ensure(c->spos, n * 32)); AG_TRY(ag_ensure(c->svel, n * 32)); AG_TRY(ag_ensure(c->svf, n * 16));
@@ -674,10 +738,12 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     int32_t* v1 = c->vals[1].as<int32_t>();
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kThreads), 0, st, n, x, off, n_sys, bits, box, k0, v0);
 
-    // 3. sort, 8 passes; the last pass writes the permutation in place
+    // 3. sort, 8 passes; the last pass writes the permutation and its inverse
     int32_t* hist = c->sort_hist.as<int32_t>();
+    int32_t* tot = hist + (int64_t)256 * nblocks;
     int32_t* hoff = c->pos_off.as<int32_t>();
     int32_t* perm = c->perm.as<int32_t>();
+    int32_t* rank = c->rank.as<int32_t>();
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
         uint64_t* kin = (pass & 1) ? k1 : k0;
@@ -685,14 +751,14 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
         int32_t* vin = (pass & 1) ? v1 : v0;
         int32_t* vout = pass == 7 ? perm : ((pass & 1) ? v0 : v1);
         hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, n, shift, nblocks, hist);
-        AG_TRY(ag_scan_i32(c, hist, hoff, (int64_t)256 * nblocks));
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin, vin, n, shift, nblocks, hoff,
-                           kout, vout);
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kThreads), 0, st, hist, nblocks, hoff, tot);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin, vin, n, shift, nblocks, hist,
+                           hoff, tot, kout, vout, pass == 7 ? rank : (int32_t*)nullptr);
     }
 
-    // 4. gather into key order
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, st, n, perm, x, v, m,
-                       c->rank.as<int32_t>(), c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
+    // 4. particle data into key order
+    hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rank, x, v, m,
+                       c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
 
     // 5. topology
     int32_t* cd = c->cdig.as<int32_t>();
@@ -728,7 +794,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
 int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m) {
     const int64_t n = c->n;
     PhaseScope phase(c, AG_PHASE_BUILD);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, c->perm.as<int32_t>(), x, v,
-                       m, (int32_t*)nullptr, c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
+    hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, c->rank.as<int32_t>(), x,
+                       v, m, c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
     return moments_pass(c);
 }

@@ -3,8 +3,10 @@
 //
 // Work decomposition: the active targets, in key (Morton) order, are cut
 // into groups of at most 64 consecutive targets of one system; one wave64
-// (one workgroup) walks the tree once for its whole group, every lane owning
-// one target.  The opening test is applied to the group's bounding box
+// (one workgroup) walks the tree once for its whole group.  Every lane owns
+// one target; in a group of fewer than 64 targets each target is given
+// several lanes, which share out the interaction list and add their parts
+// at the end, so the wave stays full.  The opening test is applied to the group's bounding box
 // (conservative: a node is accepted only if it would be for every point of
 // the box), so the whole wave follows one traversal with no divergence in
 // the interaction loops.
@@ -30,11 +32,15 @@ constexpr int kW = 64;          // lanes per wave = targets per group = tile siz
 constexpr int kPCap = 256;      // pending particle indices
 constexpr int kNCap = 128;      // pending accepted nodes
 constexpr int kSCap = 128;      // stacked cursor ranges
+constexpr int kMaxSub = 32;     // most lanes given to one target of a small group
 
-// algorithmic operation count of one particle-node interaction (monopole +
-// quadrupole g and T, mean-velocity + quadrupole-rate jerk; fused
-// multiply-add = 2, reciprocal square root = 1)
-constexpr int AG_PN_FLOPS = 222;
+// algorithmic operation count of one particle-node interaction as written in
+// node_interact (monopole + quadrupole g and T, mean-velocity + quadrupole-rate
+// jerk; every add, subtract and multiply = 1, reciprocal square root = 1):
+//   d and nu 6, r2 5, rsqrt 1, powers 5, P = Q d 15, d.P 5, ca 4, g 12,
+//   beta 5, e 1, e P 3, w 6, S diagonal 18, S off-diagonal 18, d.nu and P.nu
+//   10, Q nu 15, R = Qd d 15, d.R 5, cd 6, cp 1, j 27                  = 183
+constexpr int AG_PN_FLOPS = 183;
 
 struct Tree {
     const double4* __restrict__ com;   // centre of mass, extent
@@ -86,9 +92,9 @@ __device__ __forceinline__ float f_upr(double d) {
     return (double)f < d ? nextafterf(f, FLT_MAX) : f;
 }
 
-__device__ __forceinline__ GroupBox group_box(bool valid, double x, double y, double z) {
-    double mnx = valid ? x : DBL_MAX, mny = valid ? y : DBL_MAX, mnz = valid ? z : DBL_MAX;
-    double mxx = valid ? x : -DBL_MAX, mxy = valid ? y : -DBL_MAX, mxz = valid ? z : -DBL_MAX;
+__device__ __forceinline__ GroupBox group_box(double x, double y, double z) {
+    double mnx = x, mny = y, mnz = z;
+    double mxx = x, mxy = y, mxz = z;
     mnx = ag_wave_min(mnx); mny = ag_wave_min(mny); mnz = ag_wave_min(mnz);
     mxx = ag_wave_max(mxx); mxy = ag_wave_max(mxy); mxz = ag_wave_max(mxz);
     GroupBox g;
@@ -188,7 +194,7 @@ struct WalkLds {
 struct Target {
     float tx, ty, tz;      // position relative to the group centre
     float vx, vy, vz;
-    int p;                 // sorted position (-1 for an idle lane)
+    int p;                 // sorted position
 };
 
 // ---- forward: g, j and S = -T from particle masses and node multipoles ----
@@ -198,6 +204,12 @@ struct ForwardPolicy {
     struct Acc {
         PairAcc<double> a;
         __device__ void zero() { a.zero(); }
+        __device__ void add(const Acc& o) {
+            a.ax += o.a.ax; a.ay += o.a.ay; a.az += o.a.az;
+            a.jx += o.a.jx; a.jy += o.a.jy; a.jz += o.a.jz;
+            a.sxx += o.a.sxx; a.syy += o.a.syy; a.szz += o.a.szz;
+            a.sxy += o.a.sxy; a.sxz += o.a.sxz; a.syz += o.a.syz;
+        }
     };
     __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk) {
         const double4 q = T.spos[pk];
@@ -206,10 +218,11 @@ struct ForwardPolicy {
         S.tile[kW + lane] = u;
         S.tidx[lane] = pk;
     }
-    __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv) {
+    __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
+                                     int k0, int ks) {
         PairAcc<float> F;
         F.zero();
-        for (int k = 0; k < cnt; ++k) {
+        for (int k = k0; k < cnt; k += ks) {
             const float4 q = S.tile[k];
             const float4 u = S.tile[kW + k];
             const float mj = (S.tidx[k] == t.p) ? 0.f : q.w;
@@ -228,11 +241,11 @@ struct ForwardPolicy {
         d[3 * kW + lane] = make_float4(m2.y, m2.z, m2.w, m3.x);   // Qyz, Qd xx yy zz
         d[4 * kW + lane] = make_float4(m3.y, m3.z, m3.w, 0.f);    // Qd xy xz yz
     }
-    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc) {
+    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks) {
         PairAcc<float> F;
         F.zero();
         const float4* d = S.tile;
-        for (int k = 0; k < cnt; ++k) {
+        for (int k = k0; k < cnt; k += ks) {
             const float4 a0 = d[k], a1 = d[kW + k], a2 = d[2 * kW + k], a3 = d[3 * kW + k], a4 = d[4 * kW + k];
             const float Q[6] = {a1.w, a2.x, a2.y, a2.z, a2.w, a3.x};
             const float Qd[6] = {a3.y, a3.z, a3.w, a4.x, a4.y, a4.z};
@@ -275,6 +288,7 @@ struct AdjointPolicy {
     struct Acc {
         double vx, vy, vz, s;
         __device__ void zero() { vx = vy = vz = s = 0.0; }
+        __device__ void add(const Acc& o) { vx += o.vx; vy += o.vy; vz += o.vz; s += o.s; }
     };
     __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk) {
         const double4 q = T.spos[pk];
@@ -283,9 +297,10 @@ struct AdjointPolicy {
         S.tile[kW + lane] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.f);
         S.tidx[lane] = pk;
     }
-    __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv) {
+    __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
+                                     int k0, int ks) {
         AdjAccF F{0.f, 0.f, 0.f, 0.f};
-        for (int k = 0; k < cnt; ++k) {
+        for (int k = k0; k < cnt; k += ks) {
             const float4 q = S.tile[k];
             const float4 w = S.tile[kW + k];
             const float dx = q.x - t.tx, dy = q.y - t.ty, dz = q.z - t.tz;
@@ -324,10 +339,10 @@ struct AdjointPolicy {
     //   s += 7.5 t/r^7 - 1.5 (d.trW + 2 d.trX)/r^5
     // u_b = W2_bce d_c d_e, s_e = W2_bce d_b d_c, t = d.u, trW_b = W2_bcc,
     // trX_c = W2_bbc.
-    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc) {
+    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks) {
         AdjAccF F{0.f, 0.f, 0.f, 0.f};
         const float4* d = S.tile;
-        for (int k = 0; k < cnt; ++k) {
+        for (int k = k0; k < cnt; k += ks) {
             const float4 c = d[k], a0 = d[kW + k], a1 = d[2 * kW + k], a2 = d[3 * kW + k], a3 = d[4 * kW + k];
             const float4 a4 = d[5 * kW + k], a5 = d[6 * kW + k], a6 = d[7 * kW + k], a7 = d[8 * kW + k];
             // W0 = a0.xyz; W1 rows: (a1.x a1.y a1.z) (a1.w a2.x a2.y) (a2.z a2.w a3.x);
@@ -409,15 +424,21 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     if (count <= 0) return;
 
     // ---- targets ----
-    const bool valid = lane < count;
-    const int p_i = valid ? Gr.act_pos[gd.x + lane] : -1;
-    const double4 xi = valid ? T.spos[p_i] : make_double4(0, 0, 0, 0);
-    const float4 vi = valid ? T.svf[p_i] : make_float4(0, 0, 0, 0);
-    const GroupBox gb = group_box(valid, xi.x, xi.y, xi.z);
+    // A group of count < 64 targets gives each target sub = min(kMaxSub,
+    // 64 / count) lanes: lane = part * count + slot, and part k of a target
+    // takes every sub-th entry of each tile (lanes with part >= sub repeat
+    // work that is not used).  The parts are summed at the end.
+    const int sub = count * 2 > kW ? 1 : (kW / count < kMaxSub ? kW / count : kMaxSub);
+    const int slot = lane % count;
+    const int part = lane / count;
+    const int p_i = Gr.act_pos[gd.x + slot];   // every lane holds some target of the group
+    const double4 xi = T.spos[p_i];
+    const float4 vi = T.svf[p_i];
+    const GroupBox gb = group_box(xi.x, xi.y, xi.z);
     Target tg;
-    tg.tx = valid ? (float)(xi.x - gb.cx) : 0.f;
-    tg.ty = valid ? (float)(xi.y - gb.cy) : 0.f;
-    tg.tz = valid ? (float)(xi.z - gb.cz) : 0.f;
+    tg.tx = (float)(xi.x - gb.cx);
+    tg.ty = (float)(xi.y - gb.cy);
+    tg.tz = (float)(xi.z - gb.cz);
     tg.vx = vi.x;
     tg.vy = vi.y;
     tg.vz = vi.z;
@@ -441,14 +462,14 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     auto flush_particles = [&](int base, int cnt) {
         if (lane < cnt) Pol::stage_particle(S, T, gb, lane, S.plist[base + lane]);
         __syncthreads();
-        Pol::particles(S, cnt, tg, acc, h2, hinv);
+        Pol::particles(S, cnt, tg, acc, h2, hinv, part, sub);
         n_pp += (uint64_t)cnt;
         __syncthreads();
     };
     auto flush_nodes = [&](int base, int cnt) {
         if (lane < cnt) Pol::stage_node(S, T, gb, lane, S.nlist[base + lane]);
         __syncthreads();
-        Pol::nodes(S, cnt, tg, acc);
+        Pol::nodes(S, cnt, tg, acc, part, sub);
         n_pn += (uint64_t)cnt;
         __syncthreads();
     };
@@ -563,7 +584,18 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     if (npend > 0) flush_nodes(0, npend);
     if (ppend > 0) flush_particles(0, ppend);
 
-    if (valid) Pol::finish(T, O, acc, p_i);
+    if (sub > 1) {
+        // sum the parts of every target in LDS (the walk lists are free now)
+        static_assert(sizeof(typename Pol::Lds) >= sizeof(typename Pol::Acc) * kW, "LDS too small");
+        typename Pol::Acc* red = reinterpret_cast<typename Pol::Acc*>(&S);
+        __syncthreads();
+        red[lane] = acc;
+        __syncthreads();
+        if (part == 0)
+            for (int j = 1; j < sub; ++j) acc.add(red[slot + j * count]);
+        __syncthreads();
+    }
+    if (part == 0) Pol::finish(T, O, acc, p_i);
     if (lane == 0 && O.stats) {
         atomicAdd(&O.stats[0], (unsigned long long)(n_pp * (uint64_t)count));
         atomicAdd(&O.stats[1], (unsigned long long)(n_pn * (uint64_t)count));
