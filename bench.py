@@ -40,15 +40,19 @@ PEAK_HBM_GBS = 8000.0
 # HBM traffic of the walk kernel at the default workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 4 dispatches)
 # scaled by what the same counters read for a plain 1 GiB device copy
-# (FETCH_SIZE 524305 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  Valid only
+# (FETCH_SIZE 524306 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  Valid only
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "20932e01ba3653aa0df3c6af35bc261baa2b686b87a1f1e61a89a7586693f9ff",
+    "src_sha256": "68fde27d437d321fb4782661354a60830b13b2b14bfd2b52bff6869d83240d73",
     "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16},
-    "fetch_kib": 124548.7, "write_kib": 169624.8,
-    "fetch_factor": 1048576.0 / 524304.8, "write_factor": 1.0,
+    "fetch_kib": 152994.2, "write_kib": 169521.5,
+    "fetch_factor": 1048576.0 / 524306.0, "write_factor": 1.0,
 }
+# FP32 flops the hardware executed in one walk launch at the same workload
+# (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);
+# they include the repeated work of lanes left over in small groups
+WALK_EXECUTED_FP32_FLOPS = (2280053965.0 + 18980876.0) * 64
 WALK_SOURCES = ("paper_2010_13792_amd/csrc/k_walk.hip", "paper_2010_13792_amd/csrc/pair.h",
                 "paper_2010_13792_amd/csrc/ag_internal.h")
 # algorithmic bytes of one build: per particle, read x, v, m (56), write them
@@ -67,14 +71,31 @@ def walk_src_digest():
     return h.hexdigest()
 
 
-def walk_traffic(args):
-    """HBM bytes per walk launch from the stored counters, or None."""
+def walk_counters_valid(args):
     w = WALK_COUNTERS["workload"]
     same = (args.n, args.theta, args.eps, args.n_leaf) == (w["n"], w["theta"], w["eps"], w["n_leaf"])
-    if not same or walk_src_digest() != WALK_COUNTERS["src_sha256"]:
+    return same and walk_src_digest() == WALK_COUNTERS["src_sha256"]
+
+
+def walk_traffic(args):
+    """HBM bytes per walk launch from the stored counters, or None."""
+    if not walk_counters_valid(args):
         return None
     return 1024.0 * (WALK_COUNTERS["fetch_kib"] * WALK_COUNTERS["fetch_factor"] +
                      WALK_COUNTERS["write_kib"] * WALK_COUNTERS["write_factor"])
+
+
+def measured_peak():
+    """Run the FMA issue-rate microbenchmark (a child process); its JSON or None."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2010_13792_amd", "peak", "fma_peak")
+    if not os.path.exists(exe):
+        return None
+    try:
+        res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        return json.loads(res.stdout.strip().splitlines()[-1]) if res.returncode == 0 else None
+    except (OSError, ValueError, IndexError, subprocess.TimeoutExpired):
+        return None
 
 
 def cpu_model():
@@ -129,6 +150,7 @@ def main():
         out = getattr(bench_workloads, "run_" + args.workload)(args)
         print(json.dumps(out), flush=True)
         return
+    peak = measured_peak()   # before this process touches the GPU
     import numpy as np
     import torch
 
@@ -272,8 +294,13 @@ def main():
             "hbm_frac": None if traffic is None else traffic / (walk_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "kernel": "k_walk", "kernel_ms": walk_ms,
             "flops_per_launch": walk_flops,
+            "executed_fp32_tflops": (WALK_EXECUTED_FP32_FLOPS / (walk_ms * 1e-3) / 1e12
+                                     if walk_counters_valid(args) else None),
+            "peak_measured": None if peak is None else peak["fp32_fma_tflops"],
+            "frac_of_measured": None if peak is None else achieved_tflops / peak["fp32_fma_tflops"],
             "peak_note": "FP32 VALU FMA issue rate with packed FP32 disabled "
-                         f"(spec sheet {PEAK_FP32_PACKED_SPEC} TFLOP/s counts packed FP32)",
+                         f"(spec sheet {PEAK_FP32_PACKED_SPEC} TFLOP/s counts packed FP32); "
+                         "peak_measured: peak/fma_peak on this GPU",
         },
         "cpu_baseline": cpu,
         "interactions_per_s": (pp_step + pn_step) / (ms_step * 1e-3),

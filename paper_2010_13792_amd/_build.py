@@ -4,7 +4,8 @@ Every translation unit is compiled with hipcc for gfx950 only, with packed
 FP32 instructions disabled; ``k_step.hip`` additionally disables fused
 multiply-add contraction, because the timestep bin and the predictor are
 defined one rounding per operation.  Objects go to ``_build/`` at the repo
-root; the shared library is written next to this file.
+root; the shared library is written next to this file.  ``peak/fma_peak`` is
+the FMA issue-rate microbenchmark behind the VALU rooflines.
 """
 from __future__ import annotations
 
@@ -19,6 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libadaptgrav.so")
+PEAK_SRC = os.path.join(HERE, "peak", "fma_peak.hip")
+PEAK_EXE = os.path.join(HERE, "peak", "fma_peak")
 
 SOURCES = ["ag_api.hip", "k_direct.hip", "k_step.hip", "k_tree.hip", "k_walk.hip"]
 EXTRA = {"k_step.hip": ["-ffp-contract=off"]}
@@ -54,8 +57,14 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
     os.replace(tmp, LIB)
+    # the VALU issue-rate microbenchmark (same code-generation flags)
+    cmd = [HIPCC, *FLAGS, PEAK_SRC, "-o", PEAK_EXE + ".tmp"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for fma_peak.hip:\n{res.stderr}")
+    os.replace(PEAK_EXE + ".tmp", PEAK_EXE)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PEAK_EXE)
     return LIB
 
 

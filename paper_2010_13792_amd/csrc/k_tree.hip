@@ -16,8 +16,9 @@
 //      depth-first pre-order: node (l, p) has id off[p] + l - c_p - 1, its
 //      first child is id + 1 and its "skip" link (next node outside its
 //      subtree) is off[e], e = the first position past the cell;
-//   6. moments level by level from the deepest: leaves from their particles,
-//      inner nodes from their children (parallel-axis shifts), in FP64.
+//   6. moments level by level from the deepest, in FP64: leaves from their
+//      particles, inner nodes from their children, each in one pass about
+//      its first member, shifted to the centre of mass at the end.
 #include <float.h>
 
 #include "ag_internal.h"
@@ -49,7 +50,7 @@ __device__ __forceinline__ int sys_of(const int64_t* __restrict__ off, int n_sys
 // ---------------------------------------------------------------------------
 // 1. bounding cubes
 // ---------------------------------------------------------------------------
-constexpr int64_t kBoxChunk = 2048;
+constexpr int64_t kBoxChunk = 8192;
 
 __global__ void k_box_init(int n_sys, uint64_t* __restrict__ box, int32_t* __restrict__ blk_off,
                            const int64_t* __restrict__ off) {
@@ -535,71 +536,79 @@ __device__ __forceinline__ void add_quad(double* Q, double* Qd, double mm, const
     }
 }
 
-// moments of a leaf from its particles: two passes (centre of mass and mean
-// velocity, then the quadrupole and its rate about them)
-__device__ void leaf_moments(const int4 L, const double4* __restrict__ spos, const double4* __restrict__ svel,
-                             double* r) {
-#pragma unroll
-    for (int k = 0; k < kM64; ++k) r[k] = 0.0;
-    r[19] = r[20] = r[21] = DBL_MAX;
-    r[22] = r[23] = r[24] = -DBL_MAX;
-    const int p0 = L.y, p1 = L.y + L.z;
-    for (int p = p0; p < p1; ++p) {
-        const double4 q = spos[p];
-        const double4 u = svel[p];
-        r[0] += q.w;
-        r[1] += q.w * q.x; r[2] += q.w * q.y; r[3] += q.w * q.z;
-        r[4] += q.w * u.x; r[5] += q.w * u.y; r[6] += q.w * u.z;
-        r[19] = fmin(r[19], q.x); r[20] = fmin(r[20], q.y); r[21] = fmin(r[21], q.z);
-        r[22] = fmax(r[22], q.x); r[23] = fmax(r[23], q.y); r[24] = fmax(r[24], q.z);
-    }
-    const double Mi = r[0] > 0.0 ? 1.0 / r[0] : 0.0;
-    for (int c = 1; c < 7; ++c) r[c] *= Mi;
-    if (!(r[0] > 0.0))   // massless cell: centre of its box
-        for (int c = 0; c < 3; ++c) r[1 + c] = 0.5 * (r[19 + c] + r[22 + c]);
-    for (int p = p0; p < p1; ++p) {
-        const double4 q = spos[p];
-        const double4 u = svel[p];
-        const double y[3] = {q.x - r[1], q.y - r[2], q.z - r[3]};
-        const double w[3] = {u.x - r[4], u.y - r[5], u.z - r[6]};
-        add_quad(r + 7, r + 13, q.w, y, w);
-    }
-}
-
-// moments of an inner node from its children (parallel-axis shifts)
-__device__ void inner_moments(int id, const int4 L, const int4* __restrict__ link, const double* __restrict__ m64,
-                              double* r) {
-#pragma unroll
-    for (int k = 0; k < kM64; ++k) r[k] = 0.0;
-    r[19] = r[20] = r[21] = DBL_MAX;
-    r[22] = r[23] = r[24] = -DBL_MAX;
-    const int end = L.x;
-    for (int ch = id + 1, k8 = 0; ch < end && k8 < 8; ch = link[ch].x, ++k8) {
-        const double* cm = m64 + (int64_t)ch * kM64;
-        const double Mc = cm[0];
-        r[0] += Mc;
-        r[1] += Mc * cm[1]; r[2] += Mc * cm[2]; r[3] += Mc * cm[3];
-        r[4] += Mc * cm[4]; r[5] += Mc * cm[5]; r[6] += Mc * cm[6];
+// One-pass accumulation of the moments of a set of point masses (particles,
+// or children's centres of mass carrying their own Q and Qd): positions and
+// velocities are taken relative to the first member (r0, u0), and the sums
+// are moved to the centre of mass at the end with the parallel-axis rule
+//   sum m (3 y y^T - y^2 I) = sum m (3 e e^T - e^2 I) - M (3 E E^T - E^2 I),
+// y = e - E, E = sum m e / M (and the same bilinear rule for Qd).
+struct MomentSums {
+    double r0[3], u0[3];
+    double M, e[3], f[3];         // mass, sum m e, sum m f (e = x - r0, f = u - u0)
+    double Q[6], Qd[6];           // about r0, u0 (plus the members' own Q, Qd)
+    double lo[3], hi[3];
+    bool first;
+    __device__ void init() {
+        M = 0.0;
         for (int c = 0; c < 3; ++c) {
-            r[19 + c] = fmin(r[19 + c], cm[19 + c]);
-            r[22 + c] = fmax(r[22 + c], cm[22 + c]);
+            e[c] = f[c] = 0.0;
+            lo[c] = DBL_MAX;
+            hi[c] = -DBL_MAX;
+        }
+        for (int k = 0; k < 6; ++k) Q[k] = Qd[k] = 0.0;
+        first = true;
+    }
+    __device__ void add(double m, const double* x, const double* u) {
+        if (first) {
+            for (int c = 0; c < 3; ++c) { r0[c] = x[c]; u0[c] = u[c]; }
+            first = false;
+        }
+        const double ee[3] = {x[0] - r0[0], x[1] - r0[1], x[2] - r0[2]};
+        const double ff[3] = {u[0] - u0[0], u[1] - u0[1], u[2] - u0[2]};
+        M += m;
+        for (int c = 0; c < 3; ++c) {
+            e[c] += m * ee[c];
+            f[c] += m * ff[c];
+        }
+        add_quad(Q, Qd, m, ee, ff);
+    }
+    __device__ void box(const double* l, const double* h) {
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fmin(lo[c], l[c]);
+            hi[c] = fmax(hi[c], h[c]);
         }
     }
-    const double Mi = r[0] > 0.0 ? 1.0 / r[0] : 0.0;
-    for (int c = 1; c < 7; ++c) r[c] *= Mi;
-    if (!(r[0] > 0.0))
-        for (int c = 0; c < 3; ++c) r[1 + c] = 0.5 * (r[19 + c] + r[22 + c]);
-    for (int ch = id + 1, k8 = 0; ch < end && k8 < 8; ch = link[ch].x, ++k8) {
-        const double* cm = m64 + (int64_t)ch * kM64;
-        const double y[3] = {cm[1] - r[1], cm[2] - r[2], cm[3] - r[3]};
-        const double w[3] = {cm[4] - r[4], cm[5] - r[5], cm[6] - r[6]};
+    // r: M, c(3), u(3), Q(6), Qd(6), lo(3), hi(3)
+    __device__ void finish(double* r) const {
+        r[0] = M;
+        const double Mi = M > 0.0 ? 1.0 / M : 0.0;
+        double E[3] = {0, 0, 0}, F[3] = {0, 0, 0};
+        for (int c = 0; c < 3; ++c) {
+            r[19 + c] = lo[c];
+            r[22 + c] = hi[c];
+        }
+        if (M > 0.0) {
+            for (int c = 0; c < 3; ++c) {
+                E[c] = e[c] * Mi;
+                F[c] = f[c] * Mi;
+                r[1 + c] = r0[c] + E[c];
+                r[4 + c] = u0[c] + F[c];
+            }
+        } else {   // massless cell: centre of its box, velocity zero
+            for (int c = 0; c < 3; ++c) {
+                r[1 + c] = 0.5 * (lo[c] + hi[c]);
+                r[4 + c] = 0.0;
+            }
+        }
+        double q[6], qd[6];
+        for (int k = 0; k < 6; ++k) q[k] = qd[k] = 0.0;
+        add_quad(q, qd, M, E, F);
         for (int k = 0; k < 6; ++k) {
-            r[7 + k] += cm[7 + k];
-            r[13 + k] += cm[13 + k];
+            r[7 + k] = Q[k] - q[k];
+            r[13 + k] = Qd[k] - qd[k];
         }
-        add_quad(r + 7, r + 13, cm[0], y, w);
     }
-}
+};
 
 struct NodeOut {
     double4* com;
@@ -618,8 +627,18 @@ __global__ void k_leaf_moments(int64_t n, const int32_t* __restrict__ cnt, const
         const int k = cnt[p];
         if (k == 0) continue;
         const int64_t id = off[p] + k - 1;
+        const int4 L = link[id];
+        MomentSums S;
+        S.init();
+        for (int q = L.y; q < L.y + L.z; ++q) {
+            const double4 a = spos[q];
+            const double4 u = svel[q];
+            const double x[3] = {a.x, a.y, a.z}, v[3] = {u.x, u.y, u.z};
+            S.add(a.w, x, v);
+            S.box(x, x);
+        }
         double r[kM64];
-        leaf_moments(link[id], spos, svel, r);
+        S.finish(r);
         store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64);
     }
 }
@@ -635,8 +654,19 @@ __global__ void k_inner_level(int level, const int64_t* __restrict__ hdr, const 
         const int id = ilist[t];
         const int4 L = link[id];
         if ((L.w & 0xff) != level) continue;
+        MomentSums S;
+        S.init();
+        for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = link[ch].x, ++k8) {
+            const double* cm = O.m64 + (int64_t)ch * kM64;
+            S.add(cm[0], cm + 1, cm + 4);
+            for (int k = 0; k < 6; ++k) {
+                S.Q[k] += cm[7 + k];
+                S.Qd[k] += cm[13 + k];
+            }
+            S.box(cm + 19, cm + 22);
+        }
         double r[kM64];
-        inner_moments(id, L, link, O.m64, r);
+        S.finish(r);
         store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64);
     }
 }
