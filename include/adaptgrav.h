@@ -97,9 +97,13 @@ const char *ag_last_error(void);
  *                              than this many particles (active or not), so
  *                              sparse active sets still give compact groups;
  *                              0 = no limit [128]
- * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30) give
- * AG_EINVAL. */
-enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3 };
+ *   AG_OPT_MAC_OFFSET          1: the opening test adds the distance from a
+ *                              node's centre of mass to the centre of its box
+ *                              to the node's extent (opens lopsided nodes
+ *                              sooner; more accurate, more interactions) [0]
+ * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30, 0..1)
+ * give AG_EINVAL. */
+enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3, AG_OPT_MAC_OFFSET = 4 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
 /* HIP-graph capture of a call sequence on the context's stream (which must

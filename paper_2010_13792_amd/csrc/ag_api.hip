@@ -421,6 +421,10 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
                 return ag_fail(AG_EINVAL, "group span must be 0 or in [64, 2^30]");
             c->group_span = (int)value;
             return AG_OK;
+        case AG_OPT_MAC_OFFSET:
+            if (value != 0 && value != 1) return ag_fail(AG_EINVAL, "opening-test offset flag must be 0 or 1");
+            c->mac_offset = (int)value;
+            return AG_OK;
         default:
             return ag_fail(AG_EINVAL, "unknown option %d", option);
     }

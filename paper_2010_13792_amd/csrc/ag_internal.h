@@ -64,6 +64,7 @@ struct ag_ctx {
     int walk_waves_per_cu = 16;
     int small_node = 2;
     int group_span = 128;
+    int mac_offset = 0;
     bool capturing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

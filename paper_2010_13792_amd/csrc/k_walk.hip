@@ -37,10 +37,10 @@ constexpr int kMaxSub = 32;     // most lanes given to one target of a small gro
 // algorithmic operation count of one particle-node interaction as written in
 // node_interact (monopole + quadrupole g and T, mean-velocity + quadrupole-rate
 // jerk; every add, subtract and multiply = 1, reciprocal square root = 1):
-//   d and nu 6, r2 5, rsqrt 1, powers 5, P = Q d 15, d.P 5, ca 4, g 12,
-//   beta 5, e 1, e P 3, w 6, S diagonal 18, S off-diagonal 18, d.nu and P.nu
-//   10, Q nu 15, R = Qd d 15, d.R 5, cd 6, cp 1, j 27                  = 183
-constexpr int AG_PN_FLOPS = 183;
+//   d and nu 6, r2 5, rsqrt 1, powers 4, P = Q d 15, d.P 5, h e hq 3, ca 2,
+//   beta 4, g 12, e P 3, w 6, ca I 1, S diagonal 15, S off-diagonal 18,
+//   V = Q nu + Qd d 33, d.nu 5, P.nu 5, d.Qd.d 6, cd 5, cp 1, j 24     = 179
+constexpr int AG_PN_FLOPS = 179;
 
 struct Tree {
     const double4* __restrict__ com;   // centre of mass, extent
@@ -71,6 +71,7 @@ struct WalkOut {
     int32_t* flags;
     int64_t iter_cap;   // > nodes + particles: every group finishes well within it
     int small_node;     // accepted nodes this small are summed pairwise
+    bool mac_offset;    // opening test adds the centre-of-mass offset to the extent
     double* dldx;       // adjoint outputs
     double* dldm;
     const double* tin;  // adjoint: tidal tensor rows of the charged targets
@@ -106,17 +107,24 @@ __device__ __forceinline__ GroupBox group_box(double x, double y, double z) {
 }
 
 // Opening test for node data (com, extent, box) against the group box.
-// Accept iff  L <= theta * r_min  (r_min: distance from the node's centre of
-// mass to the nearest point of the group box)  and the node's box is at
-// least eps away from the group box (so only Newtonian pairs are
-// approximated).
+// Accept iff  L' <= theta * r_min  (r_min: distance from the node's centre of
+// mass to the nearest point of the group box; L' the node's extent L, plus,
+// with `offset` set, the distance from its centre of mass to the centre of
+// its box, which opens lopsided nodes sooner)  and the node's box is at least
+// eps away from the group box (so only Newtonian pairs are approximated).
 __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
-                                           float theta2, float eps2) {
+                                           float theta2, float eps2, bool offset) {
     const float rx = fmaxf(fabsf((float)(c.x - g.cx)) - g.hx, 0.f);
     const float ry = fmaxf(fabsf((float)(c.y - g.cy)) - g.hy, 0.f);
     const float rz = fmaxf(fabsf((float)(c.z - g.cz)) - g.hz, 0.f);
     const float r2 = rx * rx + ry * ry + rz * rz;
-    const float L = (float)c.w;
+    float L = (float)c.w;
+    if (offset) {
+        const float ox = (float)c.x - 0.5f * (lo.x + hi.x);
+        const float oy = (float)c.y - 0.5f * (lo.y + hi.y);
+        const float oz = (float)c.z - 0.5f * (lo.z + hi.z);
+        L += sqrtf(ox * ox + oy * oy + oz * oz);
+    }
     const float gx = fmaxf(fmaxf(lo.x - g.hix, g.lox - hi.x), 0.f);
     const float gy = fmaxf(fmaxf(lo.y - g.hiy, g.loy - hi.y), 0.f);
     const float gz = fmaxf(fmaxf(lo.z - g.hiz, g.loz - hi.z), 0.f);
@@ -124,54 +132,66 @@ __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, c
     return r2 > 0.f && L * L <= theta2 * r2 && sep2 >= eps2;
 }
 
-// particle-node interaction at quadrupole order (see the header of this file
-// for the expansion).  d = node centre - target, nu = node velocity - target
-// velocity.  Accumulates g, j and S = -T (same convention as pair_interact).
+// particle-node interaction at quadrupole order.  d = node centre - target,
+// nu = node velocity - target velocity, P = Q d, q = d.P:
+//   g = ca d - ri5 P,                 ca = M ri3 + 2.5 q ri7
+//   S = ca I - beta d d^T - ri5 Q + e (P d^T + d P^T),
+//                                     beta = 3 M ri5 + 17.5 q ri9, e = 5 ri7
+//   j = S nu - ri5 Qd d + 2.5 (d.Qd.d) ri7 d
+//     = ca nu + cd d + cp P - ri5 V,  V = Q nu + Qd d,
+//       cd = e P.nu - beta d.nu + 2.5 ri7 (d.Qd.d),  cp = e d.nu,
+// with d.Qd.d = d.V - P.nu (Q is symmetric).  Accumulates g, j and S = -T
+// (same convention as pair_interact); the ca I part of S is summed into
+// `sca` and added to the diagonal once per tile.
 __device__ __forceinline__ void node_interact(float dx, float dy, float dz, float nx, float ny, float nz,
-                                              float M, const float* Q, const float* Qd, PairAcc<float>& A) {
-    const float r2 = dx * dx + dy * dy + dz * dz;
+                                              float M, const float* Q, const float* Qd, PairAcc<float>& A,
+                                              float& sca) {
+    // written as explicit multiply-add chains into the accumulators (the
+    // compiler does not reassociate sums on its own)
+    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float ri2 = ri * ri;
     const float ri3 = ri * ri2;
     const float ri5 = ri3 * ri2;
     const float ri7 = ri5 * ri2;
-    const float ri9 = ri7 * ri2;
     // Q = (xx yy zz xy xz yz)
-    const float Px = Q[0] * dx + Q[3] * dy + Q[4] * dz;
-    const float Py = Q[3] * dx + Q[1] * dy + Q[5] * dz;
-    const float Pz = Q[4] * dx + Q[5] * dy + Q[2] * dz;
-    const float q = dx * Px + dy * Py + dz * Pz;
-    const float ca = M * ri3 + 2.5f * q * ri7;
-    // g = ca d - ri5 P
-    A.ax += ca * dx - ri5 * Px;
-    A.ay += ca * dy - ri5 * Py;
-    A.az += ca * dz - ri5 * Pz;
-    // S = ca I - beta d d^T - ri5 Q + 5 ri7 (P d^T + d P^T)
-    const float beta = 3.f * M * ri5 + 17.5f * q * ri9;
+    const float Px = __builtin_fmaf(Q[4], dz, __builtin_fmaf(Q[3], dy, Q[0] * dx));
+    const float Py = __builtin_fmaf(Q[5], dz, __builtin_fmaf(Q[1], dy, Q[3] * dx));
+    const float Pz = __builtin_fmaf(Q[2], dz, __builtin_fmaf(Q[5], dy, Q[4] * dx));
+    const float q = __builtin_fmaf(dz, Pz, __builtin_fmaf(dy, Py, dx * Px));
+    const float h = 2.5f * ri7;
     const float e = 5.f * ri7;
+    const float hq = h * q;
+    const float ca = __builtin_fmaf(M, ri3, hq);
+    const float beta = ri2 * __builtin_fmaf(4.f, hq, 3.f * ca);
+    const float nr5 = -ri5;
+    A.ax = __builtin_fmaf(nr5, Px, __builtin_fmaf(ca, dx, A.ax));
+    A.ay = __builtin_fmaf(nr5, Py, __builtin_fmaf(ca, dy, A.ay));
+    A.az = __builtin_fmaf(nr5, Pz, __builtin_fmaf(ca, dz, A.az));
     const float ePx = e * Px, ePy = e * Py, ePz = e * Pz;
-    const float wx = ePx - beta * dx, wy = ePy - beta * dy, wz = ePz - beta * dz;
-    A.sxx += ca + (wx + ePx) * dx - ri5 * Q[0];
-    A.syy += ca + (wy + ePy) * dy - ri5 * Q[1];
-    A.szz += ca + (wz + ePz) * dz - ri5 * Q[2];
-    A.sxy += wx * dy + ePy * dx - ri5 * Q[3];
-    A.sxz += wx * dz + ePz * dx - ri5 * Q[4];
-    A.syz += wy * dz + ePz * dy - ri5 * Q[5];
-    // j = S nu - ri5 Qd d + 2.5 (d.Qd.d) ri7 d
-    const float dn = dx * nx + dy * ny + dz * nz;
-    const float Pn = Px * nx + Py * ny + Pz * nz;
-    const float Qnx = Q[0] * nx + Q[3] * ny + Q[4] * nz;
-    const float Qny = Q[3] * nx + Q[1] * ny + Q[5] * nz;
-    const float Qnz = Q[4] * nx + Q[5] * ny + Q[2] * nz;
-    const float Rx = Qd[0] * dx + Qd[3] * dy + Qd[4] * dz;
-    const float Ry = Qd[3] * dx + Qd[1] * dy + Qd[5] * dz;
-    const float Rz = Qd[4] * dx + Qd[5] * dy + Qd[2] * dz;
-    const float qd = dx * Rx + dy * Ry + dz * Rz;
-    const float cd = e * Pn - beta * dn + 2.5f * qd * ri7;   // coefficient of d
-    const float cp = e * dn;                                 // coefficient of P
-    A.jx += ca * nx + cd * dx + cp * Px - ri5 * (Qnx + Rx);
-    A.jy += ca * ny + cd * dy + cp * Py - ri5 * (Qny + Ry);
-    A.jz += ca * nz + cd * dz + cp * Pz - ri5 * (Qnz + Rz);
+    const float wx = __builtin_fmaf(-beta, dx, ePx), wy = __builtin_fmaf(-beta, dy, ePy),
+                wz = __builtin_fmaf(-beta, dz, ePz);
+    sca += ca;
+    A.sxx = __builtin_fmaf(nr5, Q[0], __builtin_fmaf(wx + ePx, dx, A.sxx));
+    A.syy = __builtin_fmaf(nr5, Q[1], __builtin_fmaf(wy + ePy, dy, A.syy));
+    A.szz = __builtin_fmaf(nr5, Q[2], __builtin_fmaf(wz + ePz, dz, A.szz));
+    A.sxy = __builtin_fmaf(nr5, Q[3], __builtin_fmaf(ePy, dx, __builtin_fmaf(wx, dy, A.sxy)));
+    A.sxz = __builtin_fmaf(nr5, Q[4], __builtin_fmaf(ePz, dx, __builtin_fmaf(wx, dz, A.sxz)));
+    A.syz = __builtin_fmaf(nr5, Q[5], __builtin_fmaf(ePz, dy, __builtin_fmaf(wy, dz, A.syz)));
+    const float Vx = __builtin_fmaf(Qd[4], dz, __builtin_fmaf(Qd[3], dy, __builtin_fmaf(Qd[0], dx,
+                     __builtin_fmaf(Q[4], nz, __builtin_fmaf(Q[3], ny, Q[0] * nx)))));
+    const float Vy = __builtin_fmaf(Qd[5], dz, __builtin_fmaf(Qd[1], dy, __builtin_fmaf(Qd[3], dx,
+                     __builtin_fmaf(Q[5], nz, __builtin_fmaf(Q[1], ny, Q[3] * nx)))));
+    const float Vz = __builtin_fmaf(Qd[2], dz, __builtin_fmaf(Qd[5], dy, __builtin_fmaf(Qd[4], dx,
+                     __builtin_fmaf(Q[2], nz, __builtin_fmaf(Q[5], ny, Q[4] * nx)))));
+    const float dn = __builtin_fmaf(dz, nz, __builtin_fmaf(dy, ny, dx * nx));
+    const float Pn = __builtin_fmaf(Pz, nz, __builtin_fmaf(Py, ny, Px * nx));
+    const float qd = __builtin_fmaf(dz, Vz, __builtin_fmaf(dy, Vy, __builtin_fmaf(dx, Vx, -Pn)));
+    const float cd = __builtin_fmaf(h, qd, __builtin_fmaf(-beta, dn, e * Pn));
+    const float cp = e * dn;
+    A.jx = __builtin_fmaf(nr5, Vx, __builtin_fmaf(cp, Px, __builtin_fmaf(cd, dx, __builtin_fmaf(ca, nx, A.jx))));
+    A.jy = __builtin_fmaf(nr5, Vy, __builtin_fmaf(cp, Py, __builtin_fmaf(cd, dy, __builtin_fmaf(ca, ny, A.jy))));
+    A.jz = __builtin_fmaf(nr5, Vz, __builtin_fmaf(cp, Pz, __builtin_fmaf(cd, dz, __builtin_fmaf(ca, nz, A.jz))));
 }
 
 __device__ __forceinline__ void fold(PairAcc<double>& D, const PairAcc<float>& F) {
@@ -244,14 +264,18 @@ struct ForwardPolicy {
     __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks) {
         PairAcc<float> F;
         F.zero();
+        float sca = 0.f;
         const float4* d = S.tile;
         for (int k = k0; k < cnt; k += ks) {
             const float4 a0 = d[k], a1 = d[kW + k], a2 = d[2 * kW + k], a3 = d[3 * kW + k], a4 = d[4 * kW + k];
             const float Q[6] = {a1.w, a2.x, a2.y, a2.z, a2.w, a3.x};
             const float Qd[6] = {a3.y, a3.z, a3.w, a4.x, a4.y, a4.z};
             node_interact(a0.x - t.tx, a0.y - t.ty, a0.z - t.tz, a1.x - t.vx, a1.y - t.vy, a1.z - t.vz, a0.w, Q, Qd,
-                          F);
+                          F, sca);
         }
+        F.sxx += sca;
+        F.syy += sca;
+        F.szz += sca;
         fold(acc.a, F);
     }
     __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p) {
@@ -513,7 +537,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
             if (Pol::kSkipEmpty && T.wf[8 * a].w == 0.f) {
                 ca = L.x;                  // no charge below this node
             } else {
-                const bool acc_ok = mac_accept(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2);
+                const bool acc_ok = mac_accept(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2, O.mac_offset);
                 if (acc_ok && L.z > O.small_node) {
                     push_node = a;
                     ca = L.x;
@@ -608,9 +632,11 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
 // queues, one per contiguous eighth of the (Morton-ordered) group list.  A
 // workgroup starts on queue blockIdx % 8 -- the XCD the hardware dispatches
 // it to, so spatially neighbouring groups share that XCD's L2 -- and steals
-// from the other queues when its own runs dry.
+// from the other queues when its own runs dry.  The register budget is held
+// to 128 VGPRs (four waves per SIMD); the few values this spills live
+// outside the interaction loops.
 template <class Pol>
-__global__ void __launch_bounds__(kW) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
+__global__ void __launch_bounds__(kW, 4) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
                                              float theta2, float eps2, float h2, float hinv) {
     __shared__ typename Pol::Lds S;
     __shared__ int s_g;
@@ -983,6 +1009,7 @@ static WalkOut make_out(ag_ctx* c, double G) {
     O.flags = c->dflags.as<int32_t>();
     O.iter_cap = c->max_nodes + c->n + 1024;
     O.small_node = c->small_node;
+    O.mac_offset = c->mac_offset != 0;
     return O;
 }
 

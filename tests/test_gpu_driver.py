@@ -156,3 +156,30 @@ def test_options(ag, ctx):
         ctx.set_option(ag.AG_OPT_WALK_WAVES_PER_CU, 0)
     with pytest.raises(ag.AgError):
         ctx.set_option(99, 1)
+
+
+@pytest.mark.gpu
+def test_mac_offset_option(ag, ctx, orc):
+    """The offset-aware opening test opens at least as many nodes and keeps
+    the tree force within the tolerance of the oracle's direct sum; it is
+    never less accurate in the median on a clustered set."""
+    x, v, m, _ = workloads.clumps(20000, seed=8, nclump=8)
+    n = len(m)
+    rows = np.random.default_rng(1).choice(n, 512, replace=False)
+    ar, _, _ = orc.direct(x, v, m, 1e-3, 1.0, rows)
+    out = {}
+    for off in (0, 1):
+        ctx.set_option(ag.AG_OPT_MAC_OFFSET, off)
+        ctx.tree_build(_t(x), _t(v), _t(m), 16)
+        acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+        ctx.stats_reset()
+        ctx.grav_eval(None, 0.7, 1e-3, 1.0, acc, None, None)
+        st = ctx.stats_read()
+        out[off] = (rel_err(acc.cpu().numpy()[rows], ar), st["n_pp"] + st["n_pn"])
+    ctx.set_option(ag.AG_OPT_MAC_OFFSET, 0)
+    assert out[1][1] >= out[0][1]
+    for off in (0, 1):
+        assert np.median(out[off][0]) < 1e-3 and np.percentile(out[off][0], 99) < 1e-2
+    assert np.median(out[1][0]) <= np.median(out[0][0])
+    with pytest.raises(ag.AgError):
+        ctx.set_option(ag.AG_OPT_MAC_OFFSET, 2)
