@@ -34,6 +34,12 @@ constexpr int kNCap = 128;      // pending accepted nodes
 constexpr int kSCap = 128;      // stacked cursor ranges
 constexpr int kMaxSub = 32;     // most lanes given to one target of a small group
 
+// algorithmic operation count of one particle-particle interaction as written
+// in ForwardPolicy::particles (outside the softening kernel; every add,
+// subtract and multiply = 1, reciprocal square root = 1):
+//   d and nu 6, r2 5, rsqrt 1, ri2 1, mf 2, mD 2, g 6, d.nu 5, s 1, j 12,
+//   t 3, m f I 1, S 12                                                 = 57
+constexpr int AG_WALK_PP_FLOPS = 57;
 // algorithmic operation count of one particle-node interaction as written in
 // node_interact (monopole + quadrupole g and T, mean-velocity + quadrupole-rate
 // jerk; every add, subtract and multiply = 1, reciprocal square root = 1):
@@ -238,17 +244,53 @@ struct ForwardPolicy {
         S.tile[kW + lane] = u;
         S.tidx[lane] = pk;
     }
+    // The quantities of pair_interact, written as multiply-add chains into
+    // the accumulators, with the m f I part of S summed once per tile.  The
+    // self pair has d = 0 exactly (both sides round the same FP64 position),
+    // so it always takes the softened branch, where it is dropped.
     __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
                                      int k0, int ks) {
         PairAcc<float> F;
         F.zero();
+        float smf = 0.f;
         for (int k = k0; k < cnt; k += ks) {
             const float4 q = S.tile[k];
             const float4 u = S.tile[kW + k];
-            const float mj = (S.tidx[k] == t.p) ? 0.f : q.w;
-            pair_interact<float>(q.x - t.tx, q.y - t.ty, q.z - t.tz, u.x - t.vx, u.y - t.vy, u.z - t.vz, mj, h2,
-                                 hinv, F);
+            const float dx = q.x - t.tx, dy = q.y - t.ty, dz = q.z - t.tz;
+            const float nx = u.x - t.vx, ny = u.y - t.vy, nz = u.z - t.vz;
+            const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+            float mf, mD;
+            if (r2 >= h2) {
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                const float ri2 = ri * ri;
+                mf = q.w * (ri * ri2);
+                mD = -3.f * mf * ri2;
+            } else {
+                float f, D;
+                spline_fd<float>(r2, hinv, f, D);
+                const float mj = (S.tidx[k] == t.p) ? 0.f : q.w;
+                mf = mj * f;
+                mD = mj * D;
+            }
+            F.ax = __builtin_fmaf(mf, dx, F.ax);
+            F.ay = __builtin_fmaf(mf, dy, F.ay);
+            F.az = __builtin_fmaf(mf, dz, F.az);
+            const float sd = mD * __builtin_fmaf(dz, nz, __builtin_fmaf(dy, ny, dx * nx));
+            F.jx = __builtin_fmaf(sd, dx, __builtin_fmaf(mf, nx, F.jx));
+            F.jy = __builtin_fmaf(sd, dy, __builtin_fmaf(mf, ny, F.jy));
+            F.jz = __builtin_fmaf(sd, dz, __builtin_fmaf(mf, nz, F.jz));
+            const float tx = mD * dx, ty = mD * dy, tz = mD * dz;
+            smf += mf;
+            F.sxx = __builtin_fmaf(tx, dx, F.sxx);
+            F.syy = __builtin_fmaf(ty, dy, F.syy);
+            F.szz = __builtin_fmaf(tz, dz, F.szz);
+            F.sxy = __builtin_fmaf(tx, dy, F.sxy);
+            F.sxz = __builtin_fmaf(tx, dz, F.sxz);
+            F.syz = __builtin_fmaf(ty, dz, F.syz);
         }
+        F.sxx += smf;
+        F.syy += smf;
+        F.szz += smf;
         fold(acc.a, F);
     }
     __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk) {
