@@ -44,6 +44,12 @@ constexpr int AG_MAX_LEVEL = 21;   // Morton digits: 21 x 3 bits = 63-bit keys
 constexpr int AG_MAX_SYS = 512;    // batched systems: 3 octal digits of prefix
 constexpr int AG_GROUP = 64;       // targets per walk group = one wave64
 
+// level table after the eight i64 header words of tree_hdr (as i32): inner
+// nodes per level, a scatter cursor per level, and the level offsets into
+// lvl_list (AG_MAX_LEVEL + 1 entries)
+constexpr int kLvlCnt = 0, kLvlCur = 32, kLvlOff = 64, kLvlWords = 128;
+constexpr size_t kTreeHdrBytes = 8 * sizeof(int64_t) + kLvlWords * sizeof(int32_t);
+
 // per-phase event timing (enabled by ag_timing_enable)
 struct PhaseEvents {
     int phase;
@@ -99,7 +105,9 @@ struct ag_ctx {
     DevBuf nd_wf;                 // float4 x3: W0, W1 in FP32 for the adjoint walk
     DevBuf in_list;               // i32 [max_nodes]: inner nodes in pre-order
     DevBuf in_cnt, in_off;        // i32 [n+1]: inner nodes starting at each position, offsets
-    DevBuf tree_hdr;              // i64 [8]: n_nodes, max_level, ...
+    DevBuf tree_hdr;              // i64 [8]: n_nodes, max_level, inner nodes; then the level table (kLvl*)
+    DevBuf lvl_list;              // i32 [inner bound]: inner nodes grouped by level
+    DevBuf leaf_list;             // i32 [n]: leaf node ids in pre-order
 
     DevBuf sys_off;               // i64 [n_sys+1]
     DevBuf sys_root;              // i32 [n_sys]: root node per system

@@ -434,8 +434,11 @@ __device__ __forceinline__ int64_t cell_end(const TopoParams& P, const uint64_t*
 // Writes every node's link and lists the inner nodes (in pre-order).
 __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, const int32_t* __restrict__ cd,
                               const int32_t* __restrict__ off, const int32_t* __restrict__ ioff,
-                              int4* __restrict__ link, int32_t* __restrict__ ilist, int64_t* __restrict__ hdr,
-                              int32_t* __restrict__ blk_max) {
+                              int4* __restrict__ link, int32_t* __restrict__ ilist, int32_t* __restrict__ leaves,
+                              int64_t* __restrict__ hdr, int32_t* __restrict__ blk_max) {
+    __shared__ int s_lc[AG_MAX_LEVEL + 1];   // inner nodes of this block per level
+    if (threadIdx.x <= AG_MAX_LEVEL) s_lc[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t n_nodes = off[P.n];
     int maxl = 0;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
@@ -451,10 +454,18 @@ __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, c
             const int64_t skip = e < P.n ? (int64_t)off[e] : n_nodes;
             const bool leaf = (t == k - 1);
             link[id] = make_int4((int)skip, (int)p, (int)(e - p), l | (leaf ? 0x100 : 0));
-            if (!leaf) ilist[ioff[p] + t] = (int32_t)id;
+            if (!leaf) {
+                ilist[ioff[p] + t] = (int32_t)id;
+                atomicAdd(&s_lc[l], 1);
+            } else {
+                leaves[off[p] - ioff[p]] = (int32_t)id;   // leaves before p = nodes - inner nodes before p
+            }
             maxl = l > maxl ? l : maxl;
         }
     }
+    __syncthreads();
+    if (threadIdx.x <= AG_MAX_LEVEL && s_lc[threadIdx.x] > 0)
+        atomicAdd(reinterpret_cast<int32_t*>(hdr + 8) + kLvlCnt + threadIdx.x, s_lc[threadIdx.x]);
     // per-block deepest level (reduced by k_tree_header, no global atomics)
     __shared__ int s_max[kThreads / 64];
     maxl = ag_wave_max(maxl);
@@ -618,15 +629,14 @@ struct NodeOut {
     double* m64;
 };
 
-// every leaf (the deepest node starting at each position) from its particles
-__global__ void k_leaf_moments(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+// every leaf from its particles (one thread per leaf of the dense leaf list)
+__global__ void k_leaf_moments(const int64_t* __restrict__ hdr, const int32_t* __restrict__ leaves,
                                const int4* __restrict__ link, const double4* __restrict__ spos,
                                const double4* __restrict__ svel, NodeOut O) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int k = cnt[p];
-        if (k == 0) continue;
-        const int64_t id = off[p] + k - 1;
+    const int64_t nl = hdr[0] - hdr[2];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nl;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int id = leaves[t];
         const int4 L = link[id];
         MomentSums S;
         S.init();
@@ -643,17 +653,55 @@ __global__ void k_leaf_moments(int64_t n, const int32_t* __restrict__ cnt, const
     }
 }
 
+// Inner nodes grouped by level (order within a level is immaterial): every
+// block ranks its nodes per level in LDS and takes one slot range per level
+// with a global atomic; block 0 also writes the level offsets.
+__global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restrict__ hdr,
+                                                          const int32_t* __restrict__ ilist,
+                                                          const int4* __restrict__ link,
+                                                          int32_t* __restrict__ lvl,
+                                                          int32_t* __restrict__ lvl_list) {
+    __shared__ int s_off[AG_MAX_LEVEL + 2], s_cnt[AG_MAX_LEVEL + 1], s_base[AG_MAX_LEVEL + 1];
+    const int64_t ni = hdr[2];
+    if (threadIdx.x == 0) {
+        int a = 0;
+        for (int l = 0; l <= AG_MAX_LEVEL; ++l) {
+            s_off[l] = a;
+            a += lvl[kLvlCnt + l];
+        }
+        s_off[AG_MAX_LEVEL + 1] = a;
+    }
+    if (threadIdx.x <= AG_MAX_LEVEL) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x <= AG_MAX_LEVEL + 1) lvl[kLvlOff + threadIdx.x] = s_off[threadIdx.x];
+    for (int64_t t0 = (int64_t)blockIdx.x * kThreads; t0 < ni; t0 += (int64_t)gridDim.x * kThreads) {
+        const int64_t t = t0 + threadIdx.x;
+        int id = -1, l = 0, r = 0;
+        if (t < ni) {
+            id = ilist[t];
+            l = link[id].w & 0xff;
+            r = atomicAdd(&s_cnt[l], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x <= AG_MAX_LEVEL && s_cnt[threadIdx.x] > 0) {
+            s_base[threadIdx.x] = atomicAdd(&lvl[kLvlCur + threadIdx.x], s_cnt[threadIdx.x]);
+            s_cnt[threadIdx.x] = 0;
+        }
+        __syncthreads();
+        if (id >= 0) lvl_list[s_off[l] + s_base[l] + r] = id;
+        __syncthreads();
+    }
+}
+
 // inner nodes of one level from their children (one launch per level, from
 // the deepest up, so every child is complete when its parent is combined)
-__global__ void k_inner_level(int level, const int64_t* __restrict__ hdr, const int32_t* __restrict__ ilist,
+__global__ void k_inner_level(int level, const int32_t* __restrict__ lvl, const int32_t* __restrict__ lvl_list,
                               const int4* __restrict__ link, NodeOut O) {
-    const int64_t ni = hdr[2];
-    if (level > hdr[1]) return;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ni;
+    const int a = lvl[kLvlOff + level], b = lvl[kLvlOff + level + 1];
+    for (int64_t t = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < b;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int id = ilist[t];
+        const int id = lvl_list[t];
         const int4 L = link[id];
-        if ((L.w & 0xff) != level) continue;
         MomentSums S;
         S.init();
         for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = link[ch].x, ++k8) {
@@ -705,16 +753,17 @@ int moments_pass(ag_ctx* c) {
     NodeOut O{c->nd_com.as<double4>(), c->nd_lo.as<float4>(), c->nd_hi.as<float4>(), c->nd_mp.as<float4>(),
               c->nd_64.as<double>()};
     const int64_t n = c->n;
-    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(n)), dim3(kThreads), 0, st, n, c->pos_cnt.as<int32_t>(),
-                       c->pos_off.as<int32_t>(), c->nd_link.as<int4>(), c->spos.as<double4>(), c->svel.as<double4>(),
-                       O);
+    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(n / 4 + 1)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
+                       c->leaf_list.as<int32_t>(), c->nd_link.as<int4>(), c->spos.as<double4>(),
+                       c->svel.as<double4>(), O);
     // level-21 cells are always leaves; empty levels exit at once
     const int64_t inner_bound = c->max_nodes - n;
     int g = grid_for(inner_bound > 0 ? inner_bound : 1);
-    if (g > 128) g = 128;
+    if (g > 512) g = 512;
+    const int32_t* lvl = reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8);
     for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
-        hipLaunchKernelGGL(k_inner_level, dim3(g), dim3(kThreads), 0, st, l, c->tree_hdr.as<int64_t>(),
-                           c->in_list.as<int32_t>(), c->nd_link.as<int4>(), O);
+        hipLaunchKernelGGL(k_inner_level, dim3(g), dim3(kThreads), 0, st, l, lvl, c->lvl_list.as<int32_t>(),
+                           c->nd_link.as<int4>(), O);
     return AG_OK;
 }
 
@@ -746,6 +795,9 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     AG_TRY(ag_ensure(c->in_list, max_nodes * 4)); AG_TRY(ag_ensure(c->in_cnt, (n + 1) * 4));
     AG_TRY(ag_ensure(c->in_off, (n + 1) * 4));
     AG_TRY(ag_ensure(c->sys_off, (n_sys + 1) * 8)); AG_TRY(ag_ensure(c->sys_root, (n_sys + 1) * 4));
+    const int64_t inner_bound = max_nodes - n;   // inner nodes never exceed this
+    AG_TRY(ag_ensure(c->lvl_list, (size_t)(inner_bound > 0 ? inner_bound : 1) * 4));
+    AG_TRY(ag_ensure(c->leaf_list, n * 4));   // at most one leaf starts at each position
     AG_TRY(ag_ensure(c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
 
     PhaseScope phase(c, AG_PHASE_BUILD);
@@ -802,14 +854,17 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     AG_TRY(ag_scan_i32(c, pcnt, poff, n));
     AG_TRY(ag_scan_i32(c, icnt, ioff, n));
     int64_t* hdr = c->tree_hdr.as<int64_t>();
-    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, hdr, (int64_t)8, (int64_t)0);
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(256), 0, st, hdr, (int64_t)(kTreeHdrBytes / 8), (int64_t)0);
     const int wblocks = grid_for(n);
     int32_t* blk_max = c->sort_hist.as<int32_t>();   // free after the sort; >= 256 nblocks entries
     hipLaunchKernelGGL(k_write_nodes, dim3(wblocks), dim3(kThreads), 0, st, P, k0, cd, poff, ioff,
-                       c->nd_link.as<int4>(), c->in_list.as<int32_t>(), hdr, blk_max);
+                       c->nd_link.as<int4>(), c->in_list.as<int32_t>(), c->leaf_list.as<int32_t>(), hdr, blk_max);
     hipLaunchKernelGGL(k_tree_header, dim3(1), dim3(1024), 0, st, wblocks, blk_max, hdr);
     hipLaunchKernelGGL(k_sys_roots, dim3(1), dim3(512), 0, st, n_sys, sys_levels, off, cd, poff,
                        c->sys_root.as<int32_t>());
+    hipLaunchKernelGGL(k_level_lists, dim3(grid_for(inner_bound) < 1024 ? grid_for(inner_bound) : 1024),
+                       dim3(kThreads), 0, st, hdr, c->in_list.as<int32_t>(), c->nd_link.as<int4>(),
+                       reinterpret_cast<int32_t*>(hdr + 8), c->lvl_list.as<int32_t>());
 
     c->n = n;
     c->n_leaf = n_leaf;

@@ -949,15 +949,14 @@ __global__ void k_gather_w(int64_t n, const int32_t* __restrict__ perm, const in
     }
 }
 
-__global__ void k_leaf_wmoments(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+__global__ void k_leaf_wmoments(const int64_t* __restrict__ hdr, const int32_t* __restrict__ leaves,
                                 const int4* __restrict__ link, const double* __restrict__ m64,
                                 const double4* __restrict__ spos, const double4* __restrict__ ws,
                                 double* __restrict__ w64, float4* __restrict__ wf) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int k = cnt[p];
-        if (k == 0) continue;
-        const int64_t id = off[p] + k - 1;
+    const int64_t nl = hdr[0] - hdr[2];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nl;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t id = leaves[t];
         const int4 L = link[id];
         const double* c = m64 + id * 25 + 1;   // node centre of mass
         double r[kW64];
@@ -983,16 +982,14 @@ __global__ void k_leaf_wmoments(int64_t n, const int32_t* __restrict__ cnt, cons
 // Shifted to the parent centre (y = y_child + dl):
 //   W1_bc  = sum (W1_bc + W0_b dl_c)
 //   W2_bce = sum (W2_bce + W1_bc dl_e + W1_be dl_c + W0_b dl_c dl_e)
-__global__ void k_inner_wlevel(int level, const int64_t* __restrict__ hdr, const int32_t* __restrict__ ilist,
+__global__ void k_inner_wlevel(int level, const int32_t* __restrict__ lvl, const int32_t* __restrict__ lvl_list,
                                const int4* __restrict__ link, const double* __restrict__ m64,
                                double* __restrict__ w64, float4* __restrict__ wf) {
-    const int64_t ni = hdr[2];
-    if (level > hdr[1]) return;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ni;
+    const int a = lvl[kLvlOff + level], b = lvl[kLvlOff + level + 1];
+    for (int64_t t = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < b;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int id = ilist[t];
+        const int id = lvl_list[t];
         const int4 L = link[id];
-        if ((L.w & 0xff) != level) continue;
         const double* c = m64 + (int64_t)id * 25 + 1;
         double r[kW64];
 #pragma unroll
@@ -1094,15 +1091,16 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
     hipStream_t st = c->stream;
     hipLaunchKernelGGL(k_gather_w, dim3(grid_for(n)), dim3(256), 0, st, n, c->perm.as<int32_t>(),
                        c->act_flag.as<int32_t>(), w, c->wsorted.as<double4>());
-    hipLaunchKernelGGL(k_leaf_wmoments, dim3(grid_for(n)), dim3(256), 0, st, n, c->pos_cnt.as<int32_t>(),
-                       c->pos_off.as<int32_t>(), c->nd_link.as<int4>(), c->nd_64.as<double>(),
+    hipLaunchKernelGGL(k_leaf_wmoments, dim3(grid_for(n / 4 + 1)), dim3(256), 0, st, c->tree_hdr.as<int64_t>(),
+                       c->leaf_list.as<int32_t>(), c->nd_link.as<int4>(), c->nd_64.as<double>(),
                        c->spos.as<double4>(), c->wsorted.as<double4>(), c->nd_w.as<double>(), c->nd_wf.as<float4>());
     const int64_t inner_bound = c->max_nodes - n;
     int g = grid_for(inner_bound > 0 ? inner_bound : 1);
     if (g > 128) g = 128;
     for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
-        hipLaunchKernelGGL(k_inner_wlevel, dim3(g), dim3(256), 0, st, l, c->tree_hdr.as<int64_t>(),
-                           c->in_list.as<int32_t>(), c->nd_link.as<int4>(), c->nd_64.as<double>(),
+        hipLaunchKernelGGL(k_inner_wlevel, dim3(g), dim3(256), 0, st, l,
+                           reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8),
+                           c->lvl_list.as<int32_t>(), c->nd_link.as<int4>(), c->nd_64.as<double>(),
                            c->nd_w.as<double>(), c->nd_wf.as<float4>());
     int64_t mg = 0;
     AG_TRY(ag_prepare_groups(c, nullptr, n, &mg));   // every particle is a target
