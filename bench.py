@@ -44,15 +44,15 @@ PEAK_HBM_GBS = 8000.0
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "aae5663fb2f7fa43f7d9a61bb246f242e6097ade4f25a71676943891934f356b",
+    "src_sha256": "d366a114f3da10696b7627bc449aea859afe24ab8b6401f3fc8326dd5dc35263",
     "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16},
-    "fetch_kib": 332330.8, "write_kib": 215399.1,
-    "fetch_factor": 1048576.0 / 524304.6, "write_factor": 1.0,
+    "fetch_kib": 329719.6, "write_kib": 215368.8,
+    "fetch_factor": 1048576.0 / 524304.8, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);
 # they include the repeated work of lanes left over in small groups
-WALK_EXECUTED_FP32_FLOPS = (2243462500.0 + 18980876.0) * 64
+WALK_EXECUTED_FP32_FLOPS = (2220117717.0 + 18980876.0) * 64
 WALK_SOURCES = ("paper_2010_13792_amd/csrc/k_walk.hip", "paper_2010_13792_amd/csrc/pair.h",
                 "paper_2010_13792_amd/csrc/ag_internal.h")
 # algorithmic bytes of one build: per particle, read x, v, m (56), write them
