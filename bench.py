@@ -44,15 +44,15 @@ PEAK_HBM_GBS = 8000.0
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "d366a114f3da10696b7627bc449aea859afe24ab8b6401f3fc8326dd5dc35263",
-    "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16},
-    "fetch_kib": 329719.6, "write_kib": 215368.8,
-    "fetch_factor": 1048576.0 / 524304.8, "write_factor": 1.0,
+    "src_sha256": "256c96fda3549e364b1753abfd4efcaa3ff687c65237c671fa46d1e005591187",
+    "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1},
+    "fetch_kib": 379165.2, "write_kib": 215412.7,
+    "fetch_factor": 1048576.0 / 524304.5, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);
 # they include the repeated work of lanes left over in small groups
-WALK_EXECUTED_FP32_FLOPS = (2220117717.0 + 18980876.0) * 64
+WALK_EXECUTED_FP32_FLOPS = (2515110390.0 + 22349236.0) * 64
 WALK_SOURCES = ("paper_2010_13792_amd/csrc/k_walk.hip", "paper_2010_13792_amd/csrc/pair.h",
                 "paper_2010_13792_amd/csrc/ag_internal.h")
 # algorithmic bytes of one build: per particle, read x, v, m (56), write them
@@ -73,7 +73,8 @@ def walk_src_digest():
 
 def walk_counters_valid(args):
     w = WALK_COUNTERS["workload"]
-    same = (args.n, args.theta, args.eps, args.n_leaf) == (w["n"], w["theta"], w["eps"], w["n_leaf"])
+    same = ((args.n, args.theta, args.eps, args.n_leaf, args.mac_offset) ==
+            (w["n"], w["theta"], w["eps"], w["n_leaf"], w["mac_offset"]))
     return same and walk_src_digest() == WALK_COUNTERS["src_sha256"]
 
 
@@ -134,9 +135,9 @@ def parse():
                          "copy that calibrates the HBM byte counters)")
     ap.add_argument("--adaptive-steps", type=int, default=200)
     ap.add_argument("--rebuild-every", type=int, default=1)
-    ap.add_argument("--mac-offset", type=int, default=-1, choices=[-1, 0, 1],
-                    help="opening test with the centre-of-mass offset (AG_OPT_MAC_OFFSET); "
-                         "-1: the workload's default (0 for tree, 1 for adaptive)")
+    ap.add_argument("--mac-offset", type=int, default=1, choices=[0, 1],
+                    help="opening test with the centre-of-mass offset (AG_OPT_MAC_OFFSET, the "
+                         "library's default); 0: extent alone")
     ap.add_argument("--step-shift", type=int, default=0,
                     help="adaptive: global step = 2^-shift x the shortest gravity bin")
     return ap.parse_args()
@@ -179,7 +180,7 @@ def main():
     eta, G, q_f = 0.01, 1.0, 0.5
 
     ctx = ag.Context(0)
-    mac_offset = max(0, args.mac_offset)
+    mac_offset = args.mac_offset
     ctx.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
     # time grid from the initial forces: dt_max = 2^ceil(log2 max dt), tick = deepest bin
     ctx.tree_build(tx, tv, tm, args.n_leaf)

@@ -96,9 +96,9 @@ def run_adaptive(args):
     import oracle
     n = 1 << 22 if args.n == (1 << 20) else args.n
     steps = args.adaptive_steps
-    # the offset-aware opening test: with the plain one the fresh tree force on
-    # this clustered set sits at the 1e-3 median bound itself
-    mac_offset = 1 if args.mac_offset < 0 else args.mac_offset
+    # the offset-aware opening test (the default): with the plain one the fresh
+    # tree force on this clustered set sits at the 1e-3 median bound itself
+    mac_offset = args.mac_offset
     log(f"adaptive: generating {n} particles in 64 clumps")
     x, v, m, _ = workloads.clumps(n, seed=3)
     tx, tv, tm = _t(x), _t(v), _t(m)

@@ -100,7 +100,8 @@ const char *ag_last_error(void);
  *   AG_OPT_MAC_OFFSET          1: the opening test adds the distance from a
  *                              node's centre of mass to the centre of its box
  *                              to the node's extent (opens lopsided nodes
- *                              sooner; more accurate, more interactions) [0]
+ *                              sooner); 0: extent alone (fewer interactions,
+ *                              larger errors) [1]
  * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30, 0..1)
  * give AG_EINVAL. */
 enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3, AG_OPT_MAC_OFFSET = 4 };
@@ -174,7 +175,8 @@ int ag_tree_export(ag_ctx *ctx, int64_t cap, int32_t *link, double *moments, int
 /* ---- gravity evaluation ------------------------------------------------- */
 
 /* Tree gravity at the particles listed in active_idx (n_active entries;
- * NULL = all n particles, in which case n_active must equal n).
+ * NULL = all n particles, in which case n_active must equal n; n_active = 0
+ * evaluates nothing and returns AG_OK, with active_idx NULL or not).
  * Writes rows active_idx[k] of acc (n,3), jerk (n,3), tidal (n,6); all other
  * rows are left untouched.  Any of the three outputs may be NULL to skip it.
  *

@@ -319,7 +319,8 @@ static int check_eval_args(ag_ctx* c, const int32_t* idx, int64_t n_act, double 
     if (!(theta >= 0.0) || !std::isfinite(theta)) return ag_fail(AG_EINVAL, "theta must be >= 0 and finite");
     if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
     if (n_act < 0 || n_act > c->n) return ag_fail(AG_EINVAL, "n_active out of range");
-    if (!idx && n_act != c->n) return ag_fail(AG_EINVAL, "active_idx = NULL requires n_active = n");
+    if (!idx && n_act != c->n && n_act != 0)
+        return ag_fail(AG_EINVAL, "active_idx = NULL requires n_active = n (or 0)");
     return AG_OK;
 }
 

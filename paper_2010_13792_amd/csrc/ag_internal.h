@@ -70,7 +70,7 @@ struct ag_ctx {
     int walk_waves_per_cu = 16;
     int small_node = 2;
     int group_span = 128;
-    int mac_offset = 0;
+    int mac_offset = 1;
     bool capturing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

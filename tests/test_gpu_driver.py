@@ -176,7 +176,7 @@ def test_mac_offset_option(ag, ctx, orc):
         ctx.grav_eval(None, 0.7, 1e-3, 1.0, acc, None, None)
         st = ctx.stats_read()
         out[off] = (rel_err(acc.cpu().numpy()[rows], ar), st["n_pp"] + st["n_pn"])
-    ctx.set_option(ag.AG_OPT_MAC_OFFSET, 0)
+    ctx.set_option(ag.AG_OPT_MAC_OFFSET, 1)
     assert out[1][1] >= out[0][1]
     for off in (0, 1):
         assert np.median(out[off][0]) < 1e-3 and np.percentile(out[off][0], 99) < 1e-2

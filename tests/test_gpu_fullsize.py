@@ -1,0 +1,122 @@
+"""GPU parity at the benchmark sizes, in the launch configuration bench.py
+times, on sampled outputs the FP64 oracle computes one by one: the tree walk
+on the 2^20 turbulent sphere and on the 2^22 clumps (theta = 0.7, the default
+offset-aware opening test), the 256-system batched walk, the adjoint
+on 2^18 particles, the timestep bins on the full-size tidal tensors, and the
+empty active set."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from conftest import rel_err, tensor_rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+LIMITS = {"acc": (1e-3, 1e-2), "tidal": (5e-3, 5e-2), "jerk": (1.5e-2, 1e-1)}
+
+
+def _t(a, dtype=None):
+    return torch.tensor(a, device=DEV) if dtype is None else torch.tensor(a, dtype=dtype, device=DEV)
+
+
+def _walk(ctx, x, v, m, theta, eps, n_leaf=16):
+    n = len(m)
+    ctx.tree_build(_t(x), _t(v), _t(m), n_leaf)
+    acc = torch.full((n, 3), float("nan"), dtype=torch.float64, device=DEV)
+    jerk = torch.full_like(acc, float("nan"))
+    tid = torch.full((n, 6), float("nan"), dtype=torch.float64, device=DEV)
+    ctx.grav_eval(None, theta, eps, 1.0, acc, jerk, tid)
+    ctx.sync()
+    return acc, jerk, tid
+
+
+def _check(a, j, t, ar, jr, tr):
+    for k, e in (("acc", rel_err(a, ar)), ("jerk", rel_err(j, jr)), ("tidal", tensor_rel_err(t, tr))):
+        med, p99 = float(np.median(e)), float(np.percentile(e, 99))
+        print(k, med, p99)
+        assert med <= LIMITS[k][0] and p99 <= LIMITS[k][1], (k, med, p99)
+
+
+def test_turbulent_sphere_2p20(ag, ctx, orc):
+    n = 1 << 20
+    x, v, m = workloads.turbulent_sphere(n, seed=2, grid=128)
+    acc, jerk, tid = _walk(ctx, x, v, m, 0.7, 1e-3)
+    rows = np.random.default_rng(21).choice(n, 1024, replace=False)
+    ar, jr, tr = orc.direct(x, v, m, 1e-3, 1.0, rows)
+    _check(acc.cpu().numpy()[rows], jerk.cpu().numpy()[rows], tid.cpu().numpy()[rows], ar, jr, tr)
+    # timestep bins of the full-size tidal tensors: bit-exact against the
+    # oracle's Eq. 7 on the same tensors (the bin is decided on an exactly
+    # rounded ratio; the continuous dt agrees to a few ulp)
+    dt = torch.zeros(n, dtype=torch.float64, device=DEV)
+    bins = torch.zeros(n, dtype=torch.int8, device=DEV)
+    ctx.grav_timestep(tid, 0.01, 2.0 ** -4, 40, dt, bins)
+    ctx.sync()
+    t_host = tid.cpu().numpy()
+    dto, bo = orc.timestep(t_host[rows], 0.01, 2.0 ** -4, 40)
+    assert np.array_equal(bins.cpu().numpy()[rows], bo)
+    np.testing.assert_allclose(dt.cpu().numpy()[rows], dto, rtol=1e-14, atol=0)
+
+
+def test_clumps_2p22(ag, ctx, orc):
+    n = 1 << 22
+    x, v, m, _ = workloads.clumps(n, seed=3)
+    acc, jerk, tid = _walk(ctx, x, v, m, 0.7, 1e-3)
+    rows = np.random.default_rng(22).choice(n, 384, replace=False)
+    ar, jr, tr = orc.direct(x, v, m, 1e-3, 1.0, rows)
+    _check(acc.cpu().numpy()[rows], jerk.cpu().numpy()[rows], tid.cpu().numpy()[rows], ar, jr, tr)
+
+
+def test_batched_256_systems(ag, ctx, orc):
+    d = workloads.batched_plummer(256, seed=4)
+    x, v, m, off, act = d["x"], d["v"], d["m"], d["offsets"], d["active"]
+    n = len(m)
+    ctx.tree_build_batched(_t(x), _t(v), _t(m), _t(off, torch.int64), 16)
+    acc = torch.full((n, 3), float("nan"), dtype=torch.float64, device=DEV)
+    jerk = torch.full_like(acc, float("nan"))
+    tid = torch.full((n, 6), float("nan"), dtype=torch.float64, device=DEV)
+    ctx.grav_eval_batched(_t(act, torch.int32), 0.5, 0.01, 1.0, acc, jerk, tid)
+    ctx.sync()
+    a, j, t = acc.cpu().numpy(), jerk.cpu().numpy(), tid.cpu().numpy()
+    other = np.setdiff1d(np.arange(n), act)
+    assert np.all(np.isnan(a[other]))
+    rng = np.random.default_rng(23)
+    got, ref = [], []
+    aoff = d["act_offsets"]
+    for s in range(256):
+        sa = act[aoff[s]:aoff[s + 1]]
+        pick = rng.choice(sa, min(8, len(sa)), replace=False)
+        ar, jr, tr = orc.direct(x[off[s]:off[s + 1]], v[off[s]:off[s + 1]], m[off[s]:off[s + 1]], 0.01, 1.0,
+                                pick - off[s])
+        got.append((a[pick], j[pick], t[pick]))
+        ref.append((ar, jr, tr))
+    _check(*(np.concatenate([g[k] for g in got]) for k in range(3)),
+           *(np.concatenate([r[k] for r in ref]) for k in range(3)))
+
+
+def test_adjoint_2p18(ag, ctx, orc):
+    n = 1 << 18
+    x, m, _ = workloads.uniform_sphere(n, seed=5)
+    v = np.zeros_like(x)
+    w = workloads.adjoint_weights(n, seed=5)
+    ctx.tree_build(_t(x), _t(v), _t(m), 16)
+    dx = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+    dm = torch.zeros(n, dtype=torch.float64, device=DEV)
+    ctx.grav_backward(None, _t(w), 0.6, 1e-3, 1.0, dx, dm)
+    ctx.sync()
+    rows = np.random.default_rng(24).choice(n, 1024, replace=False)
+    rx, rm = orc.adjoint(x, m, w, 1e-3, 1.0, rows)
+    e = rel_err(dx.cpu().numpy()[rows], rx)
+    assert np.median(e) <= 5e-3 and np.percentile(e, 99) <= 5e-2
+
+
+def test_empty_active_set(ag, ctx):
+    n = 5000
+    x, v, m = workloads.plummer(n, seed=9)
+    ctx.tree_build(_t(x), _t(v), _t(m), 16)
+    acc = torch.full((n, 3), 7.0, dtype=torch.float64, device=DEV)
+    ctx.stats_reset()
+    ctx.grav_eval(torch.zeros(0, dtype=torch.int32, device=DEV), 0.7, 1e-3, 1.0, acc, None, None)
+    ctx.sync()
+    assert torch.all(acc == 7.0)
+    assert ctx.stats_read()["n_targets"] == 0
