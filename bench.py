@@ -45,7 +45,7 @@ PEAK_HBM_GBS = 8000.0
 # otherwise, or for another workload.
 WALK_COUNTERS = {
     "src_sha256": "256c96fda3549e364b1753abfd4efcaa3ff687c65237c671fa46d1e005591187",
-    "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1},
+    "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64},
     "fetch_kib": 379165.2, "write_kib": 215412.7,
     "fetch_factor": 1048576.0 / 524304.5, "write_factor": 1.0,
 }
@@ -71,16 +71,16 @@ def walk_src_digest():
     return h.hexdigest()
 
 
-def walk_counters_valid(args):
+def walk_counters_valid(args, group_targets):
     w = WALK_COUNTERS["workload"]
-    same = ((args.n, args.theta, args.eps, args.n_leaf, args.mac_offset) ==
-            (w["n"], w["theta"], w["eps"], w["n_leaf"], w["mac_offset"]))
+    same = ((args.n, args.theta, args.eps, args.n_leaf, args.mac_offset, group_targets) ==
+            (w["n"], w["theta"], w["eps"], w["n_leaf"], w["mac_offset"], w["group_targets"]))
     return same and walk_src_digest() == WALK_COUNTERS["src_sha256"]
 
 
-def walk_traffic(args):
+def walk_traffic(args, group_targets):
     """HBM bytes per walk launch from the stored counters, or None."""
-    if not walk_counters_valid(args):
+    if not walk_counters_valid(args, group_targets):
         return None
     return 1024.0 * (WALK_COUNTERS["fetch_kib"] * WALK_COUNTERS["fetch_factor"] +
                      WALK_COUNTERS["write_kib"] * WALK_COUNTERS["write_factor"])
@@ -182,8 +182,24 @@ def main():
     ctx = ag.Context(0)
     mac_offset = args.mac_offset
     ctx.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
-    # time grid from the initial forces: dt_max = 2^ceil(log2 max dt), tick = deepest bin
     ctx.tree_build(tx, tv, tm, args.n_leaf)
+    # targets per walk group, picked by the autotuner on this particle set (untimed)
+    from paper_2010_13792_amd import autotune
+
+    def trial(p):
+        ctx.set_option(ag.AG_OPT_GROUP_TARGETS, p["group_targets"])
+        ctx.timing_enable(True)
+        ctx.timing_read(reset=True)
+        ctx.grav_eval(None, args.theta, args.eps, G, acc, jerk, tid)
+        ph = ctx.timing_read(reset=True)
+        ctx.timing_enable(False)
+        return ph["groups"]["ms"] + ph["walk"]["ms"]
+
+    tuned, tune_table = autotune.tune(trial, autotune.grid(group_targets=[64, 32]),
+                                      f"tree|n={n}|theta={args.theta}", use_cache=False)
+    ctx.set_option(ag.AG_OPT_GROUP_TARGETS, tuned["group_targets"])
+    log(f"bench: autotuner picked {tuned}")
+    # time grid from the initial forces: dt_max = 2^ceil(log2 max dt), tick = deepest bin
     ctx.grav_eval(None, args.theta, args.eps, G, acc, jerk, tid)
     ctx.grav_timestep(tid, eta, 1.0, 60, dt_grav, bins)
     ctx.sync()
@@ -237,7 +253,7 @@ def main():
     value = evals_per_step / (ms_step * 1e-3)
     build_ms = phases["build"]["ms"] / max(1, phases["build"]["launches"])
     build_bytes = n * BUILD_BYTES_PER_PARTICLE + nn * BUILD_BYTES_PER_NODE
-    traffic = walk_traffic(args)
+    traffic = walk_traffic(args, tuned["group_targets"])
     log(f"bench: {ms_step:.3f} ms/step, walk {walk_ms:.3f} ms, {achieved_tflops:.2f} TFLOP/s")
 
     # accuracy on a sample against the FP64 oracle; the same run times the oracle
@@ -290,6 +306,7 @@ def main():
             "workload": f"turbulent uniform sphere N=2^{int(np.log2(n))} tree walk, all active",
             "n": n, "theta": args.theta, "eps": args.eps, "n_leaf": args.n_leaf,
             "multipoles": "monopole+quadrupole", "accumulation": "f64", "mac_offset": mac_offset,
+            "autotune": {"best": tuned, "walk_ms": tune_table},
             "step": "build+groups+walk+timestep+select+predict",
             "median_rel_force_err": err_med, "p99_rel_force_err": err_p99,
         },
@@ -301,7 +318,7 @@ def main():
             "kernel": "k_walk", "kernel_ms": walk_ms,
             "flops_per_launch": walk_flops,
             "executed_fp32_tflops": (WALK_EXECUTED_FP32_FLOPS / (walk_ms * 1e-3) / 1e12
-                                     if walk_counters_valid(args) else None),
+                                     if walk_counters_valid(args, tuned["group_targets"]) else None),
             "peak_measured": None if peak is None else peak["fp32_fma_tflops"],
             "frac_of_measured": None if peak is None else achieved_tflops / peak["fp32_fma_tflops"],
             "peak_note": "FP32 VALU FMA issue rate with packed FP32 disabled "

@@ -105,10 +105,31 @@ def run_adaptive(args):
     rng = np.random.default_rng(33)
     rows = rng.choice(n, 4096, replace=False)
     checkpoints = sorted({0, steps // 4, steps // 2, 3 * steps // 4, steps})
+    # targets per walk group: autotuned on the initial particle set, all active
+    with ag.Context(0) as c:
+        c.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
+        c.tree_build(tx, tv, tm, 16)
+        acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+        jerk, tid = torch.zeros_like(acc), torch.zeros((n, 6), dtype=torch.float64, device=DEV)
+
+        def trial(p):
+            c.set_option(ag.AG_OPT_GROUP_TARGETS, p["group_targets"])
+            c.timing_enable(True)
+            c.timing_read(reset=True)
+            c.grav_eval(None, 0.7, 1e-3, 1.0, acc, jerk, tid)
+            ph = c.timing_read(reset=True)
+            c.timing_enable(False)
+            return ph["groups"]["ms"] + ph["walk"]["ms"]
+
+        tuned, tune_table = autotune.tune(trial, autotune.grid(group_targets=[64, 32]), f"clumps|n={n}",
+                                          reps=2, use_cache=False)
+        del acc, jerk, tid
+    log(f"adaptive: autotuner picked {tuned}")
     runs = {}
     for q in [0.0, 0.125, 0.25, 0.5, 1.0]:
         with ag.Context(0) as c:
             c.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
+            c.set_option(ag.AG_OPT_GROUP_TARGETS, tuned["group_targets"])
             integ = AdaptiveIntegrator(c, tx, tv, tm, q_f=q, theta=0.7, eps=1e-3, eta=0.01,
                                        rebuild_every=args.rebuild_every, step_shift=args.step_shift)
             c.sync()
@@ -155,7 +176,7 @@ def run_adaptive(args):
     ok = [q for q, r in runs.items() if max(r["median_rel_err_used_force"].values()) <= 1e-3]
     return {"workload": f"64 Plummer clumps N={n}, {steps} steps, theta=0.7 eps=1e-3 eta=0.01",
             "metric": "adaptive vs every-step speedup", "rebuild_every": args.rebuild_every,
-            "mac_offset": mac_offset,
+            "mac_offset": mac_offset, "autotune": {"best": tuned, "walk_ms": tune_table},
             "step_shift": args.step_shift,
             "runs": res, "largest_q_f_within_1e-3": max(ok) if ok else None}
 
@@ -178,6 +199,7 @@ def run_batched(args):
     with torch.cuda.stream(stream), ag.Context(0, stream) as c:
         def once(p):
             c.set_option(ag.AG_OPT_WALK_WAVES_PER_CU, p["waves_per_cu"])
+            c.set_option(ag.AG_OPT_GROUP_TARGETS, p["group_targets"])
             c.tree_build_batched(tx, tv, tm, toff, p["n_leaf"])
             c.grav_eval_batched(tact, theta, eps, 1.0, acc, jerk, tid)
 
@@ -191,7 +213,7 @@ def run_batched(args):
             stream.synchronize()
             return e0.elapsed_time(e1) / 3
 
-        cands = autotune.grid(n_leaf=[8, 16, 32], waves_per_cu=[8, 12, 16])
+        cands = autotune.grid(n_leaf=[8, 16, 32], waves_per_cu=[8, 12, 16], group_targets=[64, 32])
         best, table = autotune.tune(run, cands, f"batched256|n={n}|act={len(act)}", use_cache=False)
         log(f"batched: autotuner picked {best}")
         once(best)
@@ -257,6 +279,19 @@ def run_adjoint(args):
             c.tree_build(tx, tv, tm, 16)
             c.grav_backward(None, tw, theta, eps, 1.0, dx, dm)
 
+        def trial(p):
+            c.set_option(ag.AG_OPT_GROUP_TARGETS, p["group_targets"])
+            e0, e1 = _events()
+            e0.record()
+            fwd()
+            bwd()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1)
+
+        tuned, _ = autotune.tune(trial, autotune.grid(group_targets=[64, 32]), "adjoint", reps=2, use_cache=False)
+        c.set_option(ag.AG_OPT_GROUP_TARGETS, tuned["group_targets"])
+        out["autotune"] = tuned
         for name, fn in (("forward", fwd), ("backward", bwd)):
             for _ in range(2):
                 fn()

@@ -102,9 +102,13 @@ const char *ag_last_error(void);
  *                              to the node's extent (opens lopsided nodes
  *                              sooner); 0: extent alone (fewer interactions,
  *                              larger errors) [1]
- * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30, 0..1)
- * give AG_EINVAL. */
-enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3, AG_OPT_MAC_OFFSET = 4 };
+ *   AG_OPT_GROUP_TARGETS       most targets in one walk group (one wave walks
+ *                              the tree per group; a group of k targets gives
+ *                              each target min(32, 64 / k) lanes) [64]
+ * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30, 0..1,
+ * 1..64) give AG_EINVAL. */
+enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3, AG_OPT_MAC_OFFSET = 4,
+       AG_OPT_GROUP_TARGETS = 5 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
 /* HIP-graph capture of a call sequence on the context's stream (which must

@@ -42,6 +42,7 @@ AG_OPT_WALK_WAVES_PER_CU = 1
 AG_OPT_SMALL_NODE = 2
 AG_OPT_GROUP_SPAN = 3
 AG_OPT_MAC_OFFSET = 4
+AG_OPT_GROUP_TARGETS = 5
 PHASES = ["build", "groups", "walk", "direct", "step", "adjoint"]
 
 

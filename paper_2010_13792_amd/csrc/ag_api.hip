@@ -422,6 +422,10 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
                 return ag_fail(AG_EINVAL, "group span must be 0 or in [64, 2^30]");
             c->group_span = (int)value;
             return AG_OK;
+        case AG_OPT_GROUP_TARGETS:
+            if (value < 1 || value > 64) return ag_fail(AG_EINVAL, "targets per group must be in [1, 64]");
+            c->group_cap = (int)value;
+            return AG_OK;
         case AG_OPT_MAC_OFFSET:
             if (value != 0 && value != 1) return ag_fail(AG_EINVAL, "opening-test offset flag must be 0 or 1");
             c->mac_offset = (int)value;

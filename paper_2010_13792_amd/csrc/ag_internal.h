@@ -71,6 +71,7 @@ struct ag_ctx {
     int small_node = 2;
     int group_span = 128;
     int mac_offset = 1;
+    int group_cap = 64;
     bool capturing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

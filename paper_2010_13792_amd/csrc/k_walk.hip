@@ -775,6 +775,7 @@ struct GroupCtx {
     int n_sys;
     int sys_levels;
     int span;   // cap on the particles of a group's cells (0 = none)
+    int cap;    // targets per group (at most one wave)
 };
 
 __device__ __forceinline__ int sys_of_pos(const GroupCtx& C, int64_t p) {
@@ -796,7 +797,7 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
     const bool forced = lvl < C.sys_levels;
     // too many targets for one wave, or (span) a cell too large to be one
     // compact group even if few of its particles are active
-    const bool big = forced || a > kW || (C.span > 0 && !leaf && L.z > C.span);
+    const bool big = forced || a > C.cap || (C.span > 0 && !leaf && L.z > C.span);
     int ng = 0;
     auto emit = [&](int start, int cnt, int64_t pos) {
         if (out) out[ng] = make_int4(start, cnt, C.n_sys > 1 ? sys_of_pos(C, pos) : 0, 0);
@@ -807,7 +808,7 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
         return ng;
     }
     if (leaf) {
-        for (int k = 0; k < a; k += kW) emit(a0 + k, a - k < kW ? a - k : kW, L.y);
+        for (int k = 0; k < a; k += C.cap) emit(a0 + k, a - k < C.cap ? a - k : C.cap, L.y);
         return ng;
     }
     int run_start = 0, run_cnt = 0, run_span = 0;
@@ -817,7 +818,7 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
         const int c0 = C.aoff[Lc.y];
         const int ac = C.aoff[Lc.y + Lc.z] - c0;
         const bool leafc = (Lc.w & 0x100) != 0;
-        const bool bigc = (Lc.w & 0xff) < C.sys_levels || ac > kW || (C.span > 0 && !leafc && Lc.z > C.span);
+        const bool bigc = (Lc.w & 0xff) < C.sys_levels || ac > C.cap || (C.span > 0 && !leafc && Lc.z > C.span);
         if (bigc || ac == 0 || forced) {
             if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
             run_cnt = 0;
@@ -825,7 +826,7 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
             if (forced && !bigc && ac > 0) emit(c0, ac, Lc.y);
             continue;
         }
-        if (run_cnt + ac > kW || (C.span > 0 && run_span + Lc.z > C.span)) {
+        if (run_cnt + ac > C.cap || (C.span > 0 && run_span + Lc.z > C.span)) {
             if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
             run_cnt = 0;
             run_span = 0;
@@ -895,7 +896,8 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
     }
     AG_TRY(ag_scan_i32(c, flag, off, n));
     hipLaunchKernelGGL(k_compact_pos, dim3(grid_for(n)), dim3(256), 0, st, n, flag, off, c->act_pos.as<int32_t>());
-    GroupCtx C{c->nd_link.as<int4>(), off, c->sys_off.as<int64_t>(), c->n_sys, c->sys_levels, c->group_span};
+    GroupCtx C{c->nd_link.as<int4>(), off, c->sys_off.as<int64_t>(), c->n_sys, c->sys_levels, c->group_span,
+               c->group_cap};
     const int64_t* hdr = c->tree_hdr.as<int64_t>();
     int32_t* gcnt = c->grp_cnt.as<int32_t>();
     int32_t* goff = c->grp_off.as<int32_t>();
