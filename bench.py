@@ -38,7 +38,8 @@ PEAK_FP32_PACKED_SPEC = 157.3
 PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of the walk kernel at the default workload, from two rocprofv3
-# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 4 dispatches)
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of the 4
+# dispatches of the tuned configuration)
 # scaled by what the same counters read for a plain 1 GiB device copy
 # (FETCH_SIZE 524305 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  Valid only
 # while the walk kernel's sources hash to `src_sha256`; reported as null
@@ -46,13 +47,13 @@ PEAK_HBM_GBS = 8000.0
 WALK_COUNTERS = {
     "src_sha256": "9edae7fb49749b0566e6575805d2f4c4db9da3f61698ddee165fb6669c590d91",
     "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64},
-    "fetch_kib": 330907.1, "write_kib": 228475.9,
+    "fetch_kib": 377545.2, "write_kib": 215416.8,
     "fetch_factor": 1048576.0 / 524305.0, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);
 # they include the repeated work of lanes left over in small groups
-WALK_EXECUTED_FP32_FLOPS = (2481304492.7 + 21769853.0) * 64
+WALK_EXECUTED_FP32_FLOPS = (2515110390.0 + 22349236.0) * 64
 WALK_SOURCES = ("paper_2010_13792_amd/csrc/k_walk.hip", "paper_2010_13792_amd/csrc/pair.h",
                 "paper_2010_13792_amd/csrc/ag_internal.h")
 # algorithmic bytes of one build: per particle, read x, v, m (56), write them
