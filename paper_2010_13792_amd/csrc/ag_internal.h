@@ -109,6 +109,7 @@ struct ag_ctx {
     DevBuf tree_hdr;              // i64 [8]: n_nodes, max_level, inner nodes; then the level table (kLvl*)
     DevBuf lvl_list;              // i32 [inner bound]: inner nodes grouped by level
     DevBuf leaf_list;             // i32 [n]: leaf node ids in pre-order
+    DevBuf child;                 // i32 [8 x inner bound]: children of each inner node by octant (-1: none)
 
     DevBuf sys_off;               // i64 [n_sys+1]
     DevBuf sys_root;              // i32 [n_sys]: root node per system

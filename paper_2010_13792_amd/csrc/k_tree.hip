@@ -629,7 +629,42 @@ struct NodeOut {
     double* m64;
 };
 
-// every leaf from its particles (one thread per leaf of the dense leaf list)
+// sums over the eight lanes of one inner node (one lane per octant)
+__device__ __forceinline__ double oct_sum(double v) {
+    v += __shfl_xor(v, 1, 8);
+    v += __shfl_xor(v, 2, 8);
+    v += __shfl_xor(v, 4, 8);
+    return v;
+}
+__device__ __forceinline__ double oct_min(double v) {
+    v = fmin(v, __shfl_xor(v, 1, 8));
+    v = fmin(v, __shfl_xor(v, 2, 8));
+    v = fmin(v, __shfl_xor(v, 4, 8));
+    return v;
+}
+__device__ __forceinline__ double oct_max(double v) {
+    v = fmax(v, __shfl_xor(v, 1, 8));
+    v = fmax(v, __shfl_xor(v, 2, 8));
+    v = fmax(v, __shfl_xor(v, 4, 8));
+    return v;
+}
+__device__ __forceinline__ void oct_reduce(MomentSums& S) {
+    S.M = oct_sum(S.M);
+    for (int c = 0; c < 3; ++c) {
+        S.e[c] = oct_sum(S.e[c]);
+        S.f[c] = oct_sum(S.f[c]);
+        S.lo[c] = oct_min(S.lo[c]);
+        S.hi[c] = oct_max(S.hi[c]);
+    }
+    for (int k = 0; k < 6; ++k) {
+        S.Q[k] = oct_sum(S.Q[k]);
+        S.Qd[k] = oct_sum(S.Qd[k]);
+    }
+}
+
+// every leaf from its particles (one thread per leaf of the dense leaf list;
+// a leaf's particles are contiguous and its record is written by one lane,
+// which keeps the scattered node writes to one instruction per field)
 __global__ void k_leaf_moments(const int64_t* __restrict__ hdr, const int32_t* __restrict__ leaves,
                                const int4* __restrict__ link, const double4* __restrict__ spos,
                                const double4* __restrict__ svel, NodeOut O) {
@@ -653,7 +688,30 @@ __global__ void k_leaf_moments(const int64_t* __restrict__ hdr, const int32_t* _
     }
 }
 
-// Inner nodes grouped by level (order within a level is immaterial): every
+// Children of every inner node by octant (-1 where an octant is empty), from
+// the pre-order links: the first child follows the node, the next one
+// follows the first child's subtree, and so on.
+__global__ void k_child_slots(const int64_t* __restrict__ hdr, const int32_t* __restrict__ ilist,
+                              const int4* __restrict__ link, const uint64_t* __restrict__ keys,
+                              int4* __restrict__ child) {
+    const int64_t ni = hdr[2];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ni;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int id = ilist[t];
+        const int4 L = link[id];
+        const int sh = 63 - 3 * ((L.w & 0xff) + 1);   // the children's own octal digit
+        int c8[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ++k8) {
+            const int4 C = link[ch];
+            c8[(int)((keys[C.y] >> sh) & 7)] = ch;
+            ch = C.x;
+        }
+        child[2 * t] = make_int4(c8[0], c8[1], c8[2], c8[3]);
+        child[2 * t + 1] = make_int4(c8[4], c8[5], c8[6], c8[7]);
+    }
+}
+
+// Inner-node indices grouped by level (order within a level is immaterial): every
 // block ranks its nodes per level in LDS and takes one slot range per level
 // with a global atomic; block 0 also writes the level offsets.
 __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restrict__ hdr,
@@ -678,8 +736,8 @@ __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restr
         const int64_t t = t0 + threadIdx.x;
         int id = -1, l = 0, r = 0;
         if (t < ni) {
-            id = ilist[t];
-            l = link[id].w & 0xff;
+            l = link[ilist[t]].w & 0xff;
+            id = (int)t;   // listed by inner index
             r = atomicAdd(&s_cnt[l], 1);
         }
         __syncthreads();
@@ -694,17 +752,34 @@ __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restr
 }
 
 // inner nodes of one level from their children (one launch per level, from
-// the deepest up, so every child is complete when its parent is combined)
-__global__ void k_inner_level(int level, const int32_t* __restrict__ lvl, const int32_t* __restrict__ lvl_list,
-                              const int4* __restrict__ link, NodeOut O) {
-    const int a = lvl[kLvlOff + level], b = lvl[kLvlOff + level + 1];
-    for (int64_t t = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < b;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int id = lvl_list[t];
-        const int4 L = link[id];
+// the deepest up, so every child is complete when its parent is combined).
+// Eight lanes per node, one per octant: each lane forms its child's terms
+// about the first child's centre of mass and velocity, and the eight lanes
+// sum them by shuffles.
+__global__ void __launch_bounds__(kThreads) k_inner_level(int level, const int32_t* __restrict__ lvl,
+                                                          const int32_t* __restrict__ lvl_list,
+                                                          const int32_t* __restrict__ ilist,
+                                                          const int32_t* __restrict__ child, NodeOut O) {
+    const int t_lo = lvl[kLvlOff + level], t_hi = lvl[kLvlOff + level + 1];
+    const int oct = threadIdx.x & 7;
+    const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int64_t nslot = ((int64_t)gridDim.x * blockDim.x) >> 3;
+    for (int64_t t = t_lo + slot; t < t_hi; t += nslot) {   // uniform over the eight lanes
+        const int in = lvl_list[t];
+        const int id = ilist[in];
+        const int ch = child[8 * (int64_t)in + oct];
+        // the first octant that holds a child supplies the reference point
+        const uint64_t occ = __ballot(ch >= 0);
+        const unsigned gm = (unsigned)((occ >> (ag_lane() & ~7)) & 0xffu);   // every inner node has a child
+        const int chf = gm ? child[8 * (int64_t)in + __builtin_ctz(gm)] : -1;
         MomentSums S;
         S.init();
-        for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = link[ch].x, ++k8) {
+        for (int c = 0; c < 3; ++c) {
+            S.r0[c] = chf >= 0 ? O.m64[(int64_t)chf * kM64 + 1 + c] : 0.0;
+            S.u0[c] = chf >= 0 ? O.m64[(int64_t)chf * kM64 + 4 + c] : 0.0;
+        }
+        S.first = false;
+        if (ch >= 0) {
             const double* cm = O.m64 + (int64_t)ch * kM64;
             S.add(cm[0], cm + 1, cm + 4);
             for (int k = 0; k < 6; ++k) {
@@ -713,9 +788,12 @@ __global__ void k_inner_level(int level, const int32_t* __restrict__ lvl, const 
             }
             S.box(cm + 19, cm + 22);
         }
-        double r[kM64];
-        S.finish(r);
-        store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64);
+        oct_reduce(S);
+        if (oct == 0) {
+            double r[kM64];
+            S.finish(r);
+            store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64);
+        }
     }
 }
 
@@ -758,12 +836,12 @@ int moments_pass(ag_ctx* c) {
                        c->svel.as<double4>(), O);
     // level-21 cells are always leaves; empty levels exit at once
     const int64_t inner_bound = c->max_nodes - n;
-    int g = grid_for(inner_bound > 0 ? inner_bound : 1);
-    if (g > 512) g = 512;
+    int g = grid_for(8 * (inner_bound > 0 ? inner_bound : 1));
+    if (g > 1024) g = 1024;
     const int32_t* lvl = reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8);
     for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_inner_level, dim3(g), dim3(kThreads), 0, st, l, lvl, c->lvl_list.as<int32_t>(),
-                           c->nd_link.as<int4>(), O);
+                           c->in_list.as<int32_t>(), c->child.as<int32_t>(), O);
     return AG_OK;
 }
 
@@ -798,6 +876,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     const int64_t inner_bound = max_nodes - n;   // inner nodes never exceed this
     AG_TRY(ag_ensure(c->lvl_list, (size_t)(inner_bound > 0 ? inner_bound : 1) * 4));
     AG_TRY(ag_ensure(c->leaf_list, n * 4));   // at most one leaf starts at each position
+    AG_TRY(ag_ensure(c->child, (size_t)(inner_bound > 0 ? inner_bound : 1) * 32));
     AG_TRY(ag_ensure(c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
 
     PhaseScope phase(c, AG_PHASE_BUILD);
@@ -862,6 +941,8 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     hipLaunchKernelGGL(k_tree_header, dim3(1), dim3(1024), 0, st, wblocks, blk_max, hdr);
     hipLaunchKernelGGL(k_sys_roots, dim3(1), dim3(512), 0, st, n_sys, sys_levels, off, cd, poff,
                        c->sys_root.as<int32_t>());
+    hipLaunchKernelGGL(k_child_slots, dim3(grid_for(inner_bound)), dim3(kThreads), 0, st, hdr,
+                       c->in_list.as<int32_t>(), c->nd_link.as<int4>(), k0, c->child.as<int4>());
     hipLaunchKernelGGL(k_level_lists, dim3(grid_for(inner_bound) < 1024 ? grid_for(inner_bound) : 1024),
                        dim3(kThreads), 0, st, hdr, c->in_list.as<int32_t>(), c->nd_link.as<int4>(),
                        reinterpret_cast<int32_t*>(hdr + 8), c->lvl_list.as<int32_t>());

@@ -985,18 +985,22 @@ __global__ void k_leaf_wmoments(const int64_t* __restrict__ hdr, const int32_t* 
 //   W1_bc  = sum (W1_bc + W0_b dl_c)
 //   W2_bce = sum (W2_bce + W1_bc dl_e + W1_be dl_c + W0_b dl_c dl_e)
 __global__ void k_inner_wlevel(int level, const int32_t* __restrict__ lvl, const int32_t* __restrict__ lvl_list,
-                               const int4* __restrict__ link, const double* __restrict__ m64,
-                               double* __restrict__ w64, float4* __restrict__ wf) {
-    const int a = lvl[kLvlOff + level], b = lvl[kLvlOff + level + 1];
-    for (int64_t t = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < b;
+                               const int32_t* __restrict__ ilist, const int4* __restrict__ child,
+                               const double* __restrict__ m64, double* __restrict__ w64, float4* __restrict__ wf) {
+    const int t_lo = lvl[kLvlOff + level], t_hi = lvl[kLvlOff + level + 1];
+    for (int64_t t = t_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t_hi;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int id = lvl_list[t];
-        const int4 L = link[id];
+        const int in = lvl_list[t];
+        const int id = ilist[in];
+        const int4 c0 = child[2 * in], c1 = child[2 * in + 1];
+        const int ch8[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
         const double* c = m64 + (int64_t)id * 25 + 1;
         double r[kW64];
 #pragma unroll
         for (int q = 0; q < kW64; ++q) r[q] = 0.0;
-        for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = link[ch].x, ++k8) {
+        for (int k8 = 0; k8 < 8; ++k8) {
+            const int ch = ch8[k8];
+            if (ch < 0) continue;
             const double* cw = w64 + (int64_t)ch * kW64;
             const double* cc = m64 + (int64_t)ch * 25 + 1;
             const double dl[3] = {cc[0] - c[0], cc[1] - c[1], cc[2] - c[2]};
@@ -1102,7 +1106,8 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
     for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_inner_wlevel, dim3(g), dim3(256), 0, st, l,
                            reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8),
-                           c->lvl_list.as<int32_t>(), c->nd_link.as<int4>(), c->nd_64.as<double>(),
+                           c->lvl_list.as<int32_t>(), c->in_list.as<int32_t>(), c->child.as<int4>(),
+                           c->nd_64.as<double>(),
                            c->nd_w.as<double>(), c->nd_wf.as<float4>());
     int64_t mg = 0;
     AG_TRY(ag_prepare_groups(c, nullptr, n, &mg));   // every particle is a target
