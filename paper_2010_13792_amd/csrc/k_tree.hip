@@ -5,7 +5,9 @@
 //      atomic per workgroup and axis), non-finite detection;
 //   2. 63-bit Morton keys: 21 octal digits; with several systems the top
 //      digits hold the system number and the rest its own cube's Morton code;
-//   3. stable LSD radix sort of (key, row) pairs, 8 bits per pass;
+//   3. stable LSD radix sort of (key, row) pairs over the top 32 key bits,
+//      8 bits per pass, then a full-key sort of each level-10 cell that
+//      holds more than n_leaf particles;
 //   4. x, v, m into key order (FP64 and FP32 copies);
 //   5. topology straight from the sorted keys: with c_p the number of octal
 //      digits key[p] shares with key[p-1], the cell of level l that contains
@@ -429,6 +431,156 @@ __device__ __forceinline__ int64_t cell_end(const TopoParams& P, const uint64_t*
         if ((keys[mid] >> sh) == pre) lo = mid + 1; else hi = mid;
     }
     return lo;
+}
+
+// ---- dense cells (the last step of the sort, which needs cell_end) ----
+// The passes order the keys by bits 31..62 only: every level-10 cell (bits
+// 33..62) ends up contiguous, and the tree splits no cell below level 10
+// unless it holds more than n_leaf particles.  Those cells alone are then
+// sorted by their full keys (rows break ties, which is the order a stable
+// sort of the full keys gives); the order inside the other level-10 cells
+// is never looked at below their leaf level.
+constexpr int kSortedShift = 31;
+constexpr int kCellShift = 33;
+constexpr int kSegLds = 2048;   // cells up to this size sort in LDS
+
+__global__ void k_seg_heads(int64_t n, const uint64_t* __restrict__ k, int n_leaf, int32_t* __restrict__ flag) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t c = k[p] >> kCellShift;
+        const bool head = p == 0 || (k[p - 1] >> kCellShift) != c;
+        flag[p] = head && p + n_leaf < n && (k[p + n_leaf] >> kCellShift) == c;
+    }
+}
+
+__global__ void k_seg_list(int64_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
+                           int32_t* __restrict__ list) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        if (flag[p]) list[off[p]] = (int32_t)p;
+}
+
+__device__ __forceinline__ bool pair_greater(uint64_t ka, int va, uint64_t kb, int vb) {
+    return ka > kb || (ka == kb && va > vb);
+}
+
+// One workgroup per dense cell [a, e): bitonic sort in LDS up to kSegLds
+// entries, else a stable LSD radix sort of bits 0..34 (5 passes of 7 bits)
+// through the spare key buffers at the same positions.
+__global__ void __launch_bounds__(kThreads) k_seg_sort(TopoParams P, const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ count, uint64_t* __restrict__ k0,
+                                                       int32_t* __restrict__ perm, int32_t* __restrict__ rank,
+                                                       uint64_t* __restrict__ k1, int32_t* __restrict__ v1) {
+    __shared__ uint64_t s_k[kSegLds];
+    __shared__ int32_t s_v[kSegLds];
+    __shared__ int s_base[128];
+    __shared__ int s_w[kThreads / 64][128];
+    const int tid = threadIdx.x;
+    const int ns = *count;
+    for (int s = blockIdx.x; s < ns; s += gridDim.x) {
+        const int64_t a = list[s];
+        const int64_t L = cell_end(P, k0, a, 10) - a;
+        if (L <= kSegLds) {
+            int Pw = 1;
+            while (Pw < L) Pw <<= 1;
+            for (int i = tid; i < Pw; i += kThreads) {
+                s_k[i] = i < L ? k0[a + i] : ~0ull;    // real keys have bit 63 clear
+                s_v[i] = i < L ? perm[a + i] : 0x7fffffff;
+            }
+            __syncthreads();
+            for (int kk = 2; kk <= Pw; kk <<= 1)
+                for (int j = kk >> 1; j > 0; j >>= 1) {
+                    for (int i = tid; i < Pw; i += kThreads) {
+                        const int ixj = i ^ j;
+                        if (ixj > i) {
+                            const bool up = (i & kk) == 0;
+                            if (pair_greater(s_k[i], s_v[i], s_k[ixj], s_v[ixj]) == up) {
+                                const uint64_t tk = s_k[i];
+                                s_k[i] = s_k[ixj];
+                                s_k[ixj] = tk;
+                                const int32_t tv = s_v[i];
+                                s_v[i] = s_v[ixj];
+                                s_v[ixj] = tv;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            for (int i = tid; i < L; i += kThreads) {
+                k0[a + i] = s_k[i];
+                perm[a + i] = s_v[i];
+                rank[s_v[i]] = (int32_t)(a + i);
+            }
+            __syncthreads();
+            continue;
+        }
+        const int w = tid >> 6;
+        for (int pass = 0; pass < 5; ++pass) {
+            const int shift = 7 * pass;
+            const uint64_t* ks = (pass & 1) ? k1 : k0;
+            const int32_t* vs = (pass & 1) ? v1 : perm;
+            uint64_t* kd = (pass & 1) ? k0 : k1;
+            int32_t* vd = (pass & 1) ? perm : v1;
+            if (tid < 128) s_base[tid] = 0;
+            __syncthreads();
+            for (int64_t i = tid; i < L; i += kThreads) atomicAdd(&s_base[(int)((ks[a + i] >> shift) & 127)], 1);
+            __syncthreads();
+            if (tid == 0) {
+                int acc = 0;
+                for (int d = 0; d < 128; ++d) {
+                    const int c = s_base[d];
+                    s_base[d] = acc;
+                    acc += c;
+                }
+            }
+            __syncthreads();
+            for (int64_t c0 = 0; c0 < L; c0 += kThreads) {
+                const int64_t i = c0 + tid;
+                const bool valid = i < L;
+                const uint64_t key = valid ? ks[a + i] : 0ull;
+                const int32_t val = valid ? vs[a + i] : 0;
+                const int d = (int)((key >> shift) & 127);
+                uint64_t peers = __ballot(valid);
+#pragma unroll
+                for (int b = 0; b < 7; ++b) {
+                    const bool bit = (d >> b) & 1;
+                    const uint64_t bb = __ballot(bit);
+                    peers &= bit ? bb : ~bb;
+                }
+                const int r = ag_prefix_count(peers);
+                const int cnt = __popcll(peers);
+                if (tid < 128)
+                    for (int q = 0; q < kThreads / 64; ++q) s_w[q][tid] = 0;
+                __syncthreads();
+                if (valid && r == 0) s_w[w][d] = cnt;
+                __syncthreads();
+                if (tid < 128) {
+                    int run = s_base[tid];
+                    for (int q = 0; q < kThreads / 64; ++q) {
+                        const int c = s_w[q][tid];
+                        s_w[q][tid] = run;
+                        run += c;
+                    }
+                    s_base[tid] = run;
+                }
+                __syncthreads();
+                if (valid) {
+                    const int64_t pos = a + s_w[w][d] + r;
+                    kd[pos] = key;
+                    vd[pos] = val;
+                }
+                __syncthreads();
+            }
+        }
+        // five passes end in the spare buffers: copy back
+        for (int64_t i = tid; i < L; i += kThreads) {
+            k0[a + i] = k1[a + i];
+            const int32_t v = v1[a + i];
+            perm[a + i] = v;
+            rank[v] = (int32_t)(a + i);
+        }
+        __syncthreads();
+    }
 }
 
 // Writes every node's link and lists the inner nodes (in pre-order).
@@ -899,22 +1051,36 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     int32_t* v1 = c->vals[1].as<int32_t>();
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kThreads), 0, st, n, x, off, n_sys, bits, box, k0, v0);
 
-    // 3. sort, 8 passes; the last pass writes the permutation and its inverse
+    // 3. sort: four passes over bits 31..62 (the last writes the permutation
+    //    and its inverse), then the level-10 cells holding more than n_leaf
+    //    particles by their full keys
     int32_t* hist = c->sort_hist.as<int32_t>();
     int32_t* tot = hist + (int64_t)256 * nblocks;
     int32_t* hoff = c->pos_off.as<int32_t>();
     int32_t* perm = c->perm.as<int32_t>();
     int32_t* rank = c->rank.as<int32_t>();
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 8 * pass;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = kSortedShift + 8 * pass;
         uint64_t* kin = (pass & 1) ? k1 : k0;
         uint64_t* kout = (pass & 1) ? k0 : k1;
         int32_t* vin = (pass & 1) ? v1 : v0;
-        int32_t* vout = pass == 7 ? perm : ((pass & 1) ? v0 : v1);
+        int32_t* vout = pass == 3 ? perm : ((pass & 1) ? v0 : v1);
         hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, n, shift, nblocks, hist);
         hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kThreads), 0, st, hist, nblocks, hoff, tot);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin, vin, n, shift, nblocks, hist,
-                           hoff, tot, kout, vout, pass == 7 ? rank : (int32_t*)nullptr);
+                           hoff, tot, kout, vout, pass == 3 ? rank : (int32_t*)nullptr);
+    }
+    {
+        TopoParams PS{n, n_leaf, sys_levels};
+        int32_t* flag = c->pos_cnt.as<int32_t>();   // free until the topology
+        int32_t* soff = c->pos_off.as<int32_t>();
+        int32_t* list = c->cdig.as<int32_t>();
+        hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(n)), dim3(kThreads), 0, st, n, k0, n_leaf, flag);
+        AG_TRY(ag_scan_i32(c, flag, soff, n));
+        hipLaunchKernelGGL(k_seg_list, dim3(grid_for(n)), dim3(kThreads), 0, st, n, flag, soff, list);
+        const int64_t cells = n / (n_leaf + 1) + 1;   // dense cells are disjoint and hold > n_leaf each
+        hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)(cells < 2048 ? cells : 2048)), dim3(kThreads), 0, st, PS,
+                           list, soff + n, k0, perm, rank, k1, v1);
     }
 
     // 4. particle data into key order
