@@ -28,7 +28,7 @@ def _eval(ctx, x, v, m, theta, eps, G=1.0, active=None, n_leaf=16, build=True):
     return acc.cpu().numpy(), jerk.cpu().numpy(), tid.cpu().numpy()
 
 
-def _check_topology(link, mom, perm, n, n_leaf, x, v, m, orc, sample=300):
+def _check_topology(link, mom, perm, n, n_leaf, x, v, m, orc, sample=300, cells=True):
     nn = link.shape[0]
     skip, start, cnt, lv = link[:, 0], link[:, 1], link[:, 2], link[:, 3]
     leaf = (lv & 0x100) != 0
@@ -43,6 +43,13 @@ def _check_topology(link, mom, perm, n, n_leaf, x, v, m, orc, sample=300):
     assert ls[0] == 0 and np.array_equal(ls[1:], (ls + lc)[:-1]) and ls[-1] + lc[-1] == n
     # leaves respect the capacity unless at the deepest level
     assert np.all((lc <= n_leaf) | (level[leaf] == 21))
+    # every node's particles fit in a cell of its level: side / 2^level, with
+    # side the root cube's (the largest extent of the whole set); not after a
+    # refit, whose particles have moved since the cells were drawn
+    if cells:
+        side = (x.max(axis=0) - x.min(axis=0)).max() * (1 + 1e-9)
+        ext = (mom[:, 22:25] - mom[:, 19:22]).max(axis=1)
+        assert np.all(ext <= side * np.exp2(-level.astype(np.float64)))
     # pre-order: first child of an inner node is the next node, children tile the parent
     inner = np.nonzero(~leaf)[0]
     for i in inner[:2000]:
@@ -93,6 +100,27 @@ def test_tree_topology_and_moments(ctx, orc, n, n_leaf, kind):
     ctx.tree_build(_t(x), _t(v), _t(m), n_leaf)
     link, mom, perm = (t.cpu().numpy() for t in ctx.tree_export())
     _check_topology(link, mom, perm, n, n_leaf, x, v, m, orc)
+
+
+def test_tree_dense_cells(ctx, orc):
+    """Cells far below the sorted key prefix holding more particles than a
+    workgroup sorts in LDS (4000) and fewer (1500, 40): the tree is still the
+    exact oct-tree of the full keys."""
+    rng = np.random.default_rng(11)
+    xp, vp, mp = workloads.plummer(8000, seed=11)
+    balls = [rng.normal(scale=1e-7, size=(k, 3)) + rng.uniform(-1, 1, 3) for k in (4000, 1500, 40)]
+    x = np.concatenate([xp] + balls)
+    n = len(x)
+    v = rng.normal(size=(n, 3))
+    m = np.full(n, 1.0 / n)
+    ctx.tree_build(_t(x), _t(v), _t(m), 16)
+    link, mom, perm = (t.cpu().numpy() for t in ctx.tree_export())
+    _check_topology(link, mom, perm, n, 16, x, v, m, orc, sample=500)
+    a, _, _ = _eval(ctx, x, v, m, 0.6, 1e-3, build=False)
+    rows = np.random.default_rng(12).choice(n, 512, replace=False)
+    ar, _, _ = orc.direct(x, v, m, 1e-3, 1.0, rows)
+    ea = rel_err(a[rows], ar)
+    assert np.median(ea) < 1e-3 and np.percentile(ea, 99) < 1e-2
 
 
 def test_tree_coincident_particles(ctx, orc):
@@ -193,7 +221,7 @@ def test_refit_after_drift(ctx, orc):
     x2 = x + 0.01 * v
     ctx.tree_refit(_t(x2), _t(v), _t(m))
     link, mom, perm = (t.cpu().numpy() for t in ctx.tree_export())
-    _check_topology(link, mom, perm, n, 16, x2, v, m, orc, sample=100)
+    _check_topology(link, mom, perm, n, 16, x2, v, m, orc, sample=100, cells=False)
     a, _, _ = _eval(ctx, x2, v, m, 0.6, 0.01, build=False)
     rows = np.arange(0, n, 7)
     ar, _, _ = orc.direct(x2, v, m, 0.01, 1.0, rows)
