@@ -257,6 +257,34 @@ def run_batched(args):
 
 
 # ---------------------------------------------------------------------------
+def _adjoint_fd_check(oracle, x, m, w, eps, gx, gm, ks, h=1e-6):
+    """Central differences (FP64, step h) of L = sum_i w_i . a_i in one
+    coordinate of each of the particles ks, and in their masses, against the
+    oracle's gradient gx, gm.  Only the terms of L that involve particle k
+    change: w_k . a_k (k as a target) and sum_i w_i . a_(i <- k) (k as a
+    source), each O(N) through the oracle's probe-point field."""
+    zero = np.zeros((1, 3))
+
+    def L_k(k, xk, mk):
+        others = np.delete(np.arange(len(m)), k)
+        a_k, _, _ = oracle.field(x[others], np.zeros((len(others), 3)), m[others], eps, 1.0, xk[None])
+        a_from, _, _ = oracle.field(xk[None], zero, np.array([mk]), eps, 1.0, x[others])
+        return float(np.dot(w[k], a_k[0]) + np.sum(w[others] * a_from))
+
+    ex, em = [], []
+    for t, k in enumerate(ks):
+        c = t % 3
+        xp, xm = x[k].copy(), x[k].copy()
+        xp[c] += h
+        xm[c] -= h
+        fd = (L_k(k, xp, m[k]) - L_k(k, xm, m[k])) / (2 * h)
+        ex.append(abs(fd - gx[t, c]) / max(abs(gx[t, c]), 1e-30))
+        fdm = (L_k(k, x[k], m[k] + h) - L_k(k, x[k], m[k] - h)) / (2 * h)
+        em.append(abs(fdm - gm[t]) / max(abs(gm[t]), 1e-30))
+    return {"coordinates": len(ks), "masses": len(ks), "h": h,
+            "max_rel_diff_dLdx": float(max(ex)), "max_rel_diff_dLdm": float(max(em))}
+
+
 def run_adjoint(args):
     import oracle
     n = 1 << 18
@@ -309,6 +337,7 @@ def run_adjoint(args):
             out[name] = {"ms": ms, "interactions_per_s": (st["n_pp"] + st["n_pn"]) / reps / (ms * 1e-3)}
     rows = np.random.default_rng(6).choice(n, 16384, replace=False)
     rx, rm = oracle.adjoint(x, m, w, eps, 1.0, rows)
+    out["oracle_fd_check"] = _adjoint_fd_check(oracle, x, m, w, eps, rx[:64], rm[:64], rows[:64])
     ex = _rel(dx.cpu().numpy()[rows], rx)
     out["dLdx_rel_err"] = {"median": float(np.median(ex)), "p99": float(np.percentile(ex, 99))}
     em = np.abs(dm.cpu().numpy()[rows] - rm) / np.abs(rm)
