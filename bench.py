@@ -45,10 +45,10 @@ PEAK_HBM_GBS = 8000.0
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "9edae7fb49749b0566e6575805d2f4c4db9da3f61698ddee165fb6669c590d91",
+    "src_sha256": "452625c6814c9b9cef6771d59f30317b06b3deb42697e902612c138071975b4c",
     "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64},
-    "fetch_kib": 377545.2, "write_kib": 215416.8,
-    "fetch_factor": 1048576.0 / 524305.0, "write_factor": 1.0,
+    "fetch_kib": 382675.2, "write_kib": 215383.7,
+    "fetch_factor": 1048576.0 / 524304.6, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);

@@ -116,6 +116,7 @@ struct ag_ctx {
     DevBuf sys_box;               // u64 [6 n_sys]: order-preserving encoded min/max
 
     // --- evaluation scratch ---
+    bool all_active = false;      // the last grouping listed every particle (no flag, offset or position arrays)
     DevBuf act_flag;              // i32 [n]
     DevBuf act_pos;               // i32 [n]: active sorted positions, ascending
     DevBuf act_off;               // i32 [n+1]: exclusive scan of act_flag

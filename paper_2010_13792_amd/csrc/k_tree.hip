@@ -54,23 +54,37 @@ __device__ __forceinline__ int sys_of(const int64_t* __restrict__ off, int n_sys
 // ---------------------------------------------------------------------------
 constexpr int64_t kBoxChunk = 8192;
 
-__global__ void k_box_init(int n_sys, uint64_t* __restrict__ box, int32_t* __restrict__ blk_off,
-                           const int64_t* __restrict__ off) {
-    // one block: blk_off[s] = first box-workgroup of system s (exclusive scan)
+// One block opens a build: system offsets (checked; NULL = one system), the
+// empty bounding boxes, the first box workgroup of each system (exclusive
+// scan of their chunk counts) and a zeroed tree header.
+__global__ void k_build_init(int n_sys, int64_t n, const int64_t* __restrict__ in, int64_t* __restrict__ off,
+                             int32_t* __restrict__ flags, uint64_t* __restrict__ box, int32_t* __restrict__ blk_off,
+                             int64_t* __restrict__ hdr, int hdr_words) {
     __shared__ int s_sum[AG_MAX_SYS + 1];
+    for (int s = threadIdx.x; s <= n_sys; s += blockDim.x) {
+        const int64_t v = in ? in[s] : (s == 0 ? 0 : n);
+        if (in) {
+            const bool bad = (s == 0 && v != 0) || (s == n_sys && v != n) || v < 0 || v > n ||
+                             (s > 0 && in[s - 1] > v);
+            if (bad) atomicOr(flags, AGF_BADINDEX);
+        }
+        off[s] = v;
+    }
+    for (int i = threadIdx.x; i < hdr_words; i += blockDim.x) hdr[i] = 0;
+    __syncthreads();
     for (int s = threadIdx.x; s < n_sys; s += blockDim.x) {
         for (int c = 0; c < 3; ++c) {
             box[6 * s + c] = ~0ull;        // min slots start at the top
             box[6 * s + 3 + c] = 0ull;     // max slots at the bottom
         }
-        int64_t sz = off[s + 1] - off[s];
+        const int64_t sz = off[s + 1] - off[s];
         s_sum[s] = (int)((sz + kBoxChunk - 1) / kBoxChunk);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int acc = 0;
         for (int s = 0; s < n_sys; ++s) {
-            int v = s_sum[s];
+            const int v = s_sum[s];
             blk_off[s] = acc;
             acc += v;
         }
@@ -618,7 +632,7 @@ __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, c
     __syncthreads();
     if (threadIdx.x <= AG_MAX_LEVEL && s_lc[threadIdx.x] > 0)
         atomicAdd(reinterpret_cast<int32_t*>(hdr + 8) + kLvlCnt + threadIdx.x, s_lc[threadIdx.x]);
-    // per-block deepest level (reduced by k_tree_header, no global atomics)
+    // per-block deepest level (reduced by k_tree_close, no global atomics)
     __shared__ int s_max[kThreads / 64];
     maxl = ag_wave_max(maxl);
     if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = maxl;
@@ -634,8 +648,11 @@ __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, c
     }
 }
 
-// hdr[1] = deepest level, from the per-block maxima of k_write_nodes
-__global__ void k_tree_header(int nblk, const int32_t* __restrict__ blk_max, int64_t* __restrict__ hdr) {
+// One block closes the topology: hdr[1] = deepest level (from the per-block
+// maxima of k_write_nodes) and the root node of every system.
+__global__ void k_tree_close(int nblk, const int32_t* __restrict__ blk_max, int64_t* __restrict__ hdr, int n_sys,
+                             int sys_levels, const int64_t* __restrict__ off, const int32_t* __restrict__ cd,
+                             const int32_t* __restrict__ noff, int32_t* __restrict__ root) {
     int m = 0;
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = blk_max[b] > m ? blk_max[b] : m;
     m = ag_wave_max(m);
@@ -647,14 +664,12 @@ __global__ void k_tree_header(int nblk, const int32_t* __restrict__ blk_max, int
         m = s_m[0] > m ? s_m[0] : m;
         hdr[1] = m;
     }
-}
-
-__global__ void k_sys_roots(int n_sys, int sys_levels, const int64_t* __restrict__ off,
-                            const int32_t* __restrict__ cd, const int32_t* __restrict__ noff,
-                            int32_t* __restrict__ root) {
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sys; s += gridDim.x * blockDim.x) {
+    for (int s = threadIdx.x; s < n_sys; s += blockDim.x) {
         const int64_t p0 = off[s];
-        if (off[s + 1] <= p0) { root[s] = -1; continue; }
+        if (off[s + 1] <= p0) {
+            root[s] = -1;
+            continue;
+        }
         root[s] = noff[p0] + (sys_levels - cd[p0] - 1);
     }
 }
@@ -840,35 +855,17 @@ __global__ void k_leaf_moments(const int64_t* __restrict__ hdr, const int32_t* _
     }
 }
 
-// Children of every inner node by octant (-1 where an octant is empty), from
-// the pre-order links: the first child follows the node, the next one
-// follows the first child's subtree, and so on.
-__global__ void k_child_slots(const int64_t* __restrict__ hdr, const int32_t* __restrict__ ilist,
-                              const int4* __restrict__ link, const uint64_t* __restrict__ keys,
-                              int4* __restrict__ child) {
-    const int64_t ni = hdr[2];
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ni;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int id = ilist[t];
-        const int4 L = link[id];
-        const int sh = 63 - 3 * ((L.w & 0xff) + 1);   // the children's own octal digit
-        int c8[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-        for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ++k8) {
-            const int4 C = link[ch];
-            c8[(int)((keys[C.y] >> sh) & 7)] = ch;
-            ch = C.x;
-        }
-        child[2 * t] = make_int4(c8[0], c8[1], c8[2], c8[3]);
-        child[2 * t + 1] = make_int4(c8[4], c8[5], c8[6], c8[7]);
-    }
-}
-
-// Inner-node indices grouped by level (order within a level is immaterial): every
-// block ranks its nodes per level in LDS and takes one slot range per level
-// with a global atomic; block 0 also writes the level offsets.
+// For every inner node: its children by octant (-1 where an octant is
+// empty), from the pre-order links (the first child follows the node, the
+// next follows the first child's subtree, ...), and its place in the list of
+// inner-node indices grouped by level (order within a level is immaterial:
+// every block ranks its nodes per level in LDS and takes one slot range per
+// level with a global atomic; block 0 also writes the level offsets).
 __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restrict__ hdr,
                                                           const int32_t* __restrict__ ilist,
                                                           const int4* __restrict__ link,
+                                                          const uint64_t* __restrict__ keys,
+                                                          int4* __restrict__ child,
                                                           int32_t* __restrict__ lvl,
                                                           int32_t* __restrict__ lvl_list) {
     __shared__ int s_off[AG_MAX_LEVEL + 2], s_cnt[AG_MAX_LEVEL + 1], s_base[AG_MAX_LEVEL + 1];
@@ -888,9 +885,20 @@ __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restr
         const int64_t t = t0 + threadIdx.x;
         int id = -1, l = 0, r = 0;
         if (t < ni) {
-            l = link[ilist[t]].w & 0xff;
+            const int node = ilist[t];
+            const int4 L = link[node];
+            l = L.w & 0xff;
             id = (int)t;   // listed by inner index
             r = atomicAdd(&s_cnt[l], 1);
+            const int sh = 63 - 3 * (l + 1);   // the children's own octal digit
+            int c8[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+            for (int ch = node + 1, k8 = 0; ch < L.x && k8 < 8; ++k8) {
+                const int4 C = link[ch];
+                c8[(int)((keys[C.y] >> sh) & 7)] = ch;
+                ch = C.x;
+            }
+            child[2 * t] = make_int4(c8[0], c8[1], c8[2], c8[3]);
+            child[2 * t + 1] = make_int4(c8[4], c8[5], c8[6], c8[7]);
         }
         __syncthreads();
         if (threadIdx.x <= AG_MAX_LEVEL && s_cnt[threadIdx.x] > 0) {
@@ -954,24 +962,6 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
-__global__ void k_fill_i64(int64_t* __restrict__ p, int64_t n, int64_t v) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-__global__ void k_copy_offsets(int n_sys, int64_t n, const int64_t* __restrict__ in, int64_t* __restrict__ out,
-                               int32_t* __restrict__ flags) {
-    for (int s = threadIdx.x; s <= n_sys; s += blockDim.x) {
-        int64_t v = in ? in[s] : (s == 0 ? 0 : n);
-        if (in) {
-            const bool bad = (s == 0 && v != 0) || (s == n_sys && v != n) || v < 0 || v > n ||
-                             (s > 0 && in[s - 1] > v);
-            if (bad) atomicOr(flags, AGF_BADINDEX);
-        }
-        out[s] = v;
-    }
-}
-
 int grid_for(int64_t n, int threads = kThreads) {
     int64_t b = (n + threads - 1) / threads;
     if (b > 8192) b = 8192;
@@ -1035,12 +1025,13 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     hipStream_t st = c->stream;
     int32_t* flags = c->dflags.as<int32_t>();
     int64_t* off = c->sys_off.as<int64_t>();
-    hipLaunchKernelGGL(k_copy_offsets, dim3(1), dim3(512), 0, st, n_sys, n, sys_offsets, off, flags);
+    int64_t* hdr = c->tree_hdr.as<int64_t>();
 
     // 1. bounding cubes
     uint64_t* box = c->sys_box.as<uint64_t>();
     int32_t* blk_off = reinterpret_cast<int32_t*>(box + 6 * n_sys);
-    hipLaunchKernelGGL(k_box_init, dim3(1), dim3(512), 0, st, n_sys, box, blk_off, off);
+    hipLaunchKernelGGL(k_build_init, dim3(1), dim3(512), 0, st, n_sys, n, sys_offsets, off, flags, box, blk_off, hdr,
+                       (int)(kTreeHdrBytes / 8));
     const int64_t box_blocks = n / kBoxChunk + n_sys + 1;
     hipLaunchKernelGGL(k_box, dim3((unsigned)box_blocks), dim3(kThreads), 0, st, x, off, n_sys, blk_off, box, flags);
 
@@ -1098,20 +1089,15 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     hipLaunchKernelGGL(k_count_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, cd, pcnt, icnt);
     AG_TRY(ag_scan_i32(c, pcnt, poff, n));
     AG_TRY(ag_scan_i32(c, icnt, ioff, n));
-    int64_t* hdr = c->tree_hdr.as<int64_t>();
-    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(256), 0, st, hdr, (int64_t)(kTreeHdrBytes / 8), (int64_t)0);
     const int wblocks = grid_for(n);
     int32_t* blk_max = c->sort_hist.as<int32_t>();   // free after the sort; >= 256 nblocks entries
     hipLaunchKernelGGL(k_write_nodes, dim3(wblocks), dim3(kThreads), 0, st, P, k0, cd, poff, ioff,
                        c->nd_link.as<int4>(), c->in_list.as<int32_t>(), c->leaf_list.as<int32_t>(), hdr, blk_max);
-    hipLaunchKernelGGL(k_tree_header, dim3(1), dim3(1024), 0, st, wblocks, blk_max, hdr);
-    hipLaunchKernelGGL(k_sys_roots, dim3(1), dim3(512), 0, st, n_sys, sys_levels, off, cd, poff,
-                       c->sys_root.as<int32_t>());
-    hipLaunchKernelGGL(k_child_slots, dim3(grid_for(inner_bound)), dim3(kThreads), 0, st, hdr,
-                       c->in_list.as<int32_t>(), c->nd_link.as<int4>(), k0, c->child.as<int4>());
+    hipLaunchKernelGGL(k_tree_close, dim3(1), dim3(1024), 0, st, wblocks, blk_max, hdr, n_sys, sys_levels, off, cd,
+                       poff, c->sys_root.as<int32_t>());
     hipLaunchKernelGGL(k_level_lists, dim3(grid_for(inner_bound) < 1024 ? grid_for(inner_bound) : 1024),
-                       dim3(kThreads), 0, st, hdr, c->in_list.as<int32_t>(), c->nd_link.as<int4>(),
-                       reinterpret_cast<int32_t*>(hdr + 8), c->lvl_list.as<int32_t>());
+                       dim3(kThreads), 0, st, hdr, c->in_list.as<int32_t>(), c->nd_link.as<int4>(), k0,
+                       c->child.as<int4>(), reinterpret_cast<int32_t*>(hdr + 8), c->lvl_list.as<int32_t>());
 
     c->n = n;
     c->n_leaf = n_leaf;

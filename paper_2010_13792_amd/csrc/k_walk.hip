@@ -497,7 +497,8 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     const int sub = count * 2 > kW ? 1 : (kW / count < kMaxSub ? kW / count : kMaxSub);
     const int slot = lane % count;
     const int part = lane / count;
-    const int p_i = Gr.act_pos[gd.x + slot];   // every lane holds some target of the group
+    // every lane holds some target of the group (no position list: all active)
+    const int p_i = Gr.act_pos ? Gr.act_pos[gd.x + slot] : gd.x + slot;
     const double4 xi = T.spos[p_i];
     const float4 vi = T.svf[p_i];
     const GroupBox gb = group_box(xi.x, xi.y, xi.z);
@@ -755,11 +756,6 @@ __global__ void k_mark_check(int64_t n_act, const int32_t* __restrict__ idx, int
     }
 }
 
-__global__ void k_fill1(int32_t* __restrict__ p, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 1;
-}
 
 __global__ void k_compact_pos(int64_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
                               int32_t* __restrict__ out) {
@@ -770,7 +766,7 @@ __global__ void k_compact_pos(int64_t n, const int32_t* __restrict__ flag, const
 
 struct GroupCtx {
     const int4* __restrict__ link;
-    const int32_t* __restrict__ aoff;   // exclusive scan of the active flags over sorted positions
+    const int32_t* __restrict__ aoff;   // exclusive scan of the active flags over sorted positions (null: all)
     const int64_t* __restrict__ sys_off;
     int n_sys;
     int sys_levels;
@@ -792,8 +788,8 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
     const int4 L = C.link[id];
     const int lvl = L.w & 0xff;
     const bool leaf = (L.w & 0x100) != 0;
-    const int a0 = C.aoff[L.y];
-    const int a = C.aoff[L.y + L.z] - a0;
+    const int a0 = C.aoff ? C.aoff[L.y] : L.y;
+    const int a = (C.aoff ? C.aoff[L.y + L.z] : L.y + L.z) - a0;
     const bool forced = lvl < C.sys_levels;
     // too many targets for one wave, or (span) a cell too large to be one
     // compact group even if few of its particles are active
@@ -815,8 +811,8 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
     int64_t run_pos = 0;
     for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = C.link[ch].x, ++k8) {
         const int4 Lc = C.link[ch];
-        const int c0 = C.aoff[Lc.y];
-        const int ac = C.aoff[Lc.y + Lc.z] - c0;
+        const int c0 = C.aoff ? C.aoff[Lc.y] : Lc.y;
+        const int ac = (C.aoff ? C.aoff[Lc.y + Lc.z] : Lc.y + Lc.z) - c0;
         const bool leafc = (Lc.w & 0x100) != 0;
         const bool bigc = (Lc.w & 0xff) < C.sys_levels || ac > C.cap || (C.span > 0 && !leafc && Lc.z > C.span);
         if (bigc || ac == 0 || forced) {
@@ -884,6 +880,7 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
     hipStream_t st = c->stream;
     int32_t* flag = c->act_flag.as<int32_t>();
     int32_t* off = c->act_off.as<int32_t>();
+    c->all_active = idx == nullptr;
     if (idx) {
         hipLaunchKernelGGL(k_fill0, dim3(grid_for(n)), dim3(256), 0, st, flag, n);
         // the scan output doubles as the stamp array until the scan runs
@@ -891,13 +888,14 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
                            c->rank.as<int32_t>(), off, c->dflags.as<int32_t>());
         hipLaunchKernelGGL(k_mark_check, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, idx, n,
                            c->rank.as<int32_t>(), off, flag, c->dflags.as<int32_t>());
-    } else {
-        hipLaunchKernelGGL(k_fill1, dim3(grid_for(n)), dim3(256), 0, st, flag, n);
+        AG_TRY(ag_scan_i32(c, flag, off, n));
+        hipLaunchKernelGGL(k_compact_pos, dim3(grid_for(n)), dim3(256), 0, st, n, flag, off,
+                           c->act_pos.as<int32_t>());
     }
-    AG_TRY(ag_scan_i32(c, flag, off, n));
-    hipLaunchKernelGGL(k_compact_pos, dim3(grid_for(n)), dim3(256), 0, st, n, flag, off, c->act_pos.as<int32_t>());
-    GroupCtx C{c->nd_link.as<int4>(), off, c->sys_off.as<int64_t>(), c->n_sys, c->sys_levels, c->group_span,
-               c->group_cap};
+    // with every particle active the flags, their scan and the position list
+    // are the identity: the grouping and the walk use sorted positions directly
+    GroupCtx C{c->nd_link.as<int4>(), idx ? off : (const int32_t*)nullptr, c->sys_off.as<int64_t>(), c->n_sys,
+               c->sys_levels, c->group_span, c->group_cap};
     const int64_t* hdr = c->tree_hdr.as<int64_t>();
     int32_t* gcnt = c->grp_cnt.as<int32_t>();
     int32_t* goff = c->grp_off.as<int32_t>();
@@ -942,12 +940,15 @@ __device__ __forceinline__ void add_w2(double* W2, const double* wv, const doubl
 }
 
 // sorted weights: w of active rows, zero elsewhere
-__global__ void k_gather_w(int64_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ flag,
+// weights in key order; a row carries its charge if it is listed: by the
+// flags, or every row (all = 1), or none (all = 0 with no flags)
+__global__ void k_gather_w(int64_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ flag, int all,
                            const double* __restrict__ w, double4* __restrict__ ws) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = perm[p];
-        ws[p] = flag[p] ? make_double4(w[3 * i], w[3 * i + 1], w[3 * i + 2], 1.0) : make_double4(0, 0, 0, 0);
+        const bool charged = flag ? flag[p] != 0 : all != 0;
+        ws[p] = charged ? make_double4(w[3 * i], w[3 * i + 1], w[3 * i + 2], 1.0) : make_double4(0, 0, 0, 0);
     }
 }
 
@@ -1062,7 +1063,8 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
                    double* jerk, double* tidal) {
     int64_t mg = 0;
     AG_TRY(ag_prepare_groups(c, idx, n_act, &mg));
-    Groups Gr{c->act_pos.as<int32_t>(), c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
+              c->grp_hdr.as<int32_t>()};
     WalkOut O = make_out(c, G);
     O.acc = acc;
     O.jerk = jerk;
@@ -1089,14 +1091,15 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
     AG_TRY(ag_ensure(c->nd_w, c->max_nodes * kW64 * sizeof(double)));
     AG_TRY(ag_ensure(c->nd_wf, c->max_nodes * 8 * sizeof(float4)));
     double* tin = c->tmp_tidal.as<double>();
-    int64_t mg0 = 0;
     if (n_act > 0) AG_TRY(ag_launch_eval(c, idx, n_act, theta, eps, G, nullptr, nullptr, tin));
-    else AG_TRY(ag_prepare_groups(c, idx, 0, &mg0));   // no charges: all flags clear
+    // charges: the listed rows (flags of that evaluation), all rows, or none
+    const int32_t* cflag = (n_act > 0 && !c->all_active) ? c->act_flag.as<int32_t>() : nullptr;
+    const int call = n_act > 0 && c->all_active ? 1 : 0;
 
     PhaseScope phase(c, AG_PHASE_ADJOINT);
     hipStream_t st = c->stream;
-    hipLaunchKernelGGL(k_gather_w, dim3(grid_for(n)), dim3(256), 0, st, n, c->perm.as<int32_t>(),
-                       c->act_flag.as<int32_t>(), w, c->wsorted.as<double4>());
+    hipLaunchKernelGGL(k_gather_w, dim3(grid_for(n)), dim3(256), 0, st, n, c->perm.as<int32_t>(), cflag, call, w,
+                       c->wsorted.as<double4>());
     hipLaunchKernelGGL(k_leaf_wmoments, dim3(grid_for(n / 4 + 1)), dim3(256), 0, st, c->tree_hdr.as<int64_t>(),
                        c->leaf_list.as<int32_t>(), c->nd_link.as<int4>(), c->nd_64.as<double>(),
                        c->spos.as<double4>(), c->wsorted.as<double4>(), c->nd_w.as<double>(), c->nd_wf.as<float4>());
@@ -1111,7 +1114,8 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
                            c->nd_w.as<double>(), c->nd_wf.as<float4>());
     int64_t mg = 0;
     AG_TRY(ag_prepare_groups(c, nullptr, n, &mg));   // every particle is a target
-    Groups Gr{c->act_pos.as<int32_t>(), c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
+              c->grp_hdr.as<int32_t>()};
     WalkOut O = make_out(c, G);
     O.dldx = dLdx;
     O.dldm = dLdm;
