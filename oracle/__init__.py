@@ -12,6 +12,9 @@ routine of the same name in ``oracle.c`` (built into ``liboracle.so`` by
 * :func:`timestep` -- the tidal timestep of Eq. 7 and its power-of-two bin.
 * :func:`select` -- force-age counter (Eq. 3) and update condition (Eq. 4).
 * :func:`predict` -- jerk predictor (Eq. 6) in closed form ``a0 + j (t - t0)``.
+* :func:`force_log` / :func:`predict_poly` -- the alternative to Eq. 6 that
+  Sec. 2.2 names: extrapolate g from a few logged past values with an
+  interpolating polynomial (plain numpy, written here rather than in C).
 * :func:`adjoint` -- exact gradient of ``L = sum_i w_i . a_i``.
 * :func:`moments` -- node multipoles (mass, centre of mass, mean velocity,
   traceless quadrupole and its rate) of a particle set.
@@ -174,6 +177,82 @@ def predict(a0, jerk, t0, t):
     t0 = _f64(t0).ravel()
     out = np.empty_like(a0)
     _load().orc_predict(a0.shape[0], _ptr(a0), _ptr(j), _ptr(t0), float(t), _ptr(out))
+    return out
+
+
+def force_log(hist_a, hist_t, hist_n, rows, acc0, t):
+    """Log of past forces for the polynomial predictor (Sec. 2.2).
+
+    For each row in ``rows``: every logged (t_k, g_k) moves one slot older
+    (the oldest of the ``depth`` slots is dropped), slot 0 takes the fresh
+    (t, acc0[row]) and the row's count grows by one up to ``depth``.
+    ``hist_a`` (depth, n, 3), ``hist_t`` (depth, n) and ``hist_n`` (n,) are
+    updated in place; slot 0 is the newest.
+    """
+    depth = hist_t.shape[0]
+    for i in rows:
+        for s in range(depth - 1, 0, -1):
+            hist_a[s, i] = hist_a[s - 1, i]
+            hist_t[s, i] = hist_t[s - 1, i]
+        hist_a[0, i] = acc0[i]
+        hist_t[0, i] = t
+        hist_n[i] = min(int(hist_n[i]) + 1, depth)
+
+
+def poly_nodes(hist_t, hist_n, order, i):
+    """Times of the logged forces row ``i`` extrapolates from: the newest
+    ones, at most ``order + 1`` of them and no more than the row has logged,
+    stopping before the first slot that is not strictly older than the one
+    before it (so the interpolation nodes are distinct)."""
+    cnt = min(int(hist_n[i]), hist_t.shape[0])
+    if cnt == 0:
+        return []
+    ts = [float(hist_t[0, i])]
+    for k in range(1, min(cnt, order + 1)):
+        if not hist_t[k, i] < ts[-1]:
+            break
+        ts.append(float(hist_t[k, i]))
+    return ts
+
+
+def predict_poly(hist_a, hist_t, hist_n, order, t):
+    """Polynomial predictor (Sec. 2.2): for each row, the interpolating
+    polynomial through its logged forces at the times :func:`poly_nodes`
+    picks (degree ``len - 1 <= order``), evaluated at ``t`` in Lagrange form
+    ``sum_k g_k prod_{m != k} (t - t_m) / (t_k - t_m)``.  Order 1 is the
+    linear predictor that removes the leading time-lag error; order 0 holds
+    the newest logged force.  Rows with nothing logged come back as NaN.
+    Returns (n, 3)."""
+    n = hist_t.shape[1]
+    out = np.full((n, 3), np.nan)
+    for i in range(n):
+        ts = poly_nodes(hist_t, hist_n, order, i)
+        if not ts:
+            continue
+        acc = np.zeros(3)
+        for k in range(len(ts)):
+            w = 1.0
+            for mm in range(len(ts)):
+                if mm != k:
+                    w *= (t - ts[mm]) / (ts[k] - ts[mm])
+            acc += w * hist_a[k, i]
+        out[i] = acc
+    return out
+
+
+def predict_poly_weight_sum(hist_t, hist_n, order, t):
+    """sum_k |Lagrange weight k| per row: the factor by which the
+    predictor's rounding can grow relative to the logged forces."""
+    n = hist_t.shape[1]
+    out = np.zeros(n)
+    for i in range(n):
+        ts = poly_nodes(hist_t, hist_n, order, i)
+        for k in range(len(ts)):
+            w = 1.0
+            for mm in range(len(ts)):
+                if mm != k:
+                    w *= (t - ts[mm]) / (ts[k] - ts[mm])
+            out[i] += abs(w)
     return out
 
 
