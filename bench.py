@@ -141,6 +141,11 @@ def parse():
                          "library's default); 0: extent alone")
     ap.add_argument("--step-shift", type=int, default=0,
                     help="adaptive: global step = 2^-shift x the shortest gravity bin")
+    ap.add_argument("--q-list", default="0,0.125,0.25,0.5,1",
+                    help="adaptive: the q_f values to run (0 = every step, the reference run)")
+    ap.add_argument("--predictors", default="jerk",
+                    help="adaptive: comma list of predictors between updates (jerk = Eq. 6, none, "
+                         "linear, quadratic); each runs every q_f > 0 of --q-list")
     return ap.parse_args()
 
 

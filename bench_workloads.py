@@ -125,13 +125,17 @@ def run_adaptive(args):
                                           reps=2, use_cache=False)
         del acc, jerk, tid
     log(f"adaptive: autotuner picked {tuned}")
+    qs = [float(q) for q in args.q_list.split(",")]
+    preds = [p.strip() for p in args.predictors.split(",") if p.strip()]
+    plan = [(preds[0], q) for q in qs] + [(p, q) for p in preds[1:] for q in qs if q > 0]
     runs = {}
-    for q in [0.0, 0.125, 0.25, 0.5, 1.0]:
+    for pred, q in plan:
         with ag.Context(0) as c:
             c.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
             c.set_option(ag.AG_OPT_GROUP_TARGETS, tuned["group_targets"])
             integ = AdaptiveIntegrator(c, tx, tv, tm, q_f=q, theta=0.7, eps=1e-3, eta=0.01,
-                                       rebuild_every=args.rebuild_every, step_shift=args.step_shift)
+                                       rebuild_every=args.rebuild_every, step_shift=args.step_shift,
+                                       predictor=pred)
             c.sync()
             errs = {}
 
@@ -140,7 +144,7 @@ def run_adaptive(args):
                 vs = integ.vpred.cpu().numpy() if step > 0 else integ.v.cpu().numpy()
                 ar, _, _ = oracle.direct(xs, vs, m, 1e-3, 1.0, rows)
                 errs[step] = float(np.median(_rel(integ.acc.cpu().numpy()[rows], ar)))
-                log(f"adaptive q_f={q} step {step}: median error of the force in use {errs[step]:.2e}")
+                log(f"adaptive {pred} q_f={q} step {step}: median error of the force in use {errs[step]:.2e}")
 
             if 0 in checkpoints:
                 check(0)
@@ -161,24 +165,31 @@ def run_adaptive(args):
             ph = c.timing_read(reset=True)
             c.timing_enable(False)
             grav_ms = ph["build"]["ms"] + ph["groups"]["ms"] + ph["walk"]["ms"]
-            runs[q] = {"evaluations": int(integ.evaluations - n), "gravity_ms": grav_ms,
-                       "walk_ms": ph["walk"]["ms"], "build_ms": ph["build"]["ms"], "total_ms": total_ms,
-                       "median_rel_err_used_force": errs, "dt_step": integ.dt, "tick_bin": integ.tick_bin,
-                       "mean_active_fraction": float(np.mean(active_hist)) / n}
-            log(f"adaptive q_f={q}: {runs[q]}")
-    base = runs[0.0]
+            runs[(pred, q)] = {"evaluations": int(integ.evaluations - n), "gravity_ms": grav_ms,
+                               "walk_ms": ph["walk"]["ms"], "build_ms": ph["build"]["ms"],
+                               "total_ms": total_ms, "median_rel_err_used_force": errs, "dt_step": integ.dt,
+                               "tick_bin": integ.tick_bin, "mean_active_fraction": float(np.mean(active_hist)) / n}
+            log(f"adaptive {pred} q_f={q}: {runs[(pred, q)]}")
+    base = runs.get((preds[0], 0.0))
     res = {}
-    for q, r in runs.items():
-        res[str(q)] = dict(r, eval_ratio=base["evaluations"] / max(1, r["evaluations"]),
-                           gravity_speedup=base["gravity_ms"] / r["gravity_ms"],
-                           walk_speedup=base["walk_ms"] / r["walk_ms"],
-                           total_speedup=base["total_ms"] / r["total_ms"])
-    ok = [q for q, r in runs.items() if max(r["median_rel_err_used_force"].values()) <= 1e-3]
+    for (pred, q), r in runs.items():
+        key = str(q) if pred == preds[0] else f"{pred}:{q}"
+        res[key] = dict(r, predictor=pred, q_f=q)
+        if base is not None:
+            res[key].update(eval_ratio=base["evaluations"] / max(1, r["evaluations"]),
+                            gravity_speedup=base["gravity_ms"] / r["gravity_ms"],
+                            walk_speedup=base["walk_ms"] / r["walk_ms"],
+                            total_speedup=base["total_ms"] / r["total_ms"])
+    ok = {}
+    for (pred, q), r in runs.items():
+        if max(r["median_rel_err_used_force"].values()) <= 1e-3:
+            ok[pred] = max(ok.get(pred, 0.0), q)
     return {"workload": f"64 Plummer clumps N={n}, {steps} steps, theta=0.7 eps=1e-3 eta=0.01",
             "metric": "adaptive vs every-step speedup", "rebuild_every": args.rebuild_every,
             "mac_offset": mac_offset, "autotune": {"best": tuned, "walk_ms": tune_table},
-            "step_shift": args.step_shift,
-            "runs": res, "largest_q_f_within_1e-3": max(ok) if ok else None}
+            "step_shift": args.step_shift, "predictors": preds,
+            "runs": res, "largest_q_f_within_1e-3": ok.get(preds[0]),
+            "largest_q_f_within_1e-3_by_predictor": ok}
 
 
 # ---------------------------------------------------------------------------

@@ -223,7 +223,8 @@ int ag_grav_direct(ag_ctx *ctx, int64_t n, const double *x, const double *v, con
  *   n2 = (Txx^2 + Tyy^2 + Tzz^2) + 2 (Txy^2 + Txz^2 + Tyz^2),
  *   Q  = (n2 * (dt_max^2)^2) / (6 eta^2)  [each operation rounded once],
  * k is the least k with Q <= 16^k.  Rows processed: idx[0..n_idx) (device
- * int32) or, with idx = NULL, all n rows.  tidal (n,6) in; dt_grav (n,)
+ * int32) or, with idx = NULL and n_idx = n, all n rows; n_idx = 0 processes
+ * none.  tidal (n,6) in; dt_grav (n,)
  * and bin (n,) int8 out (rows not processed are untouched). */
 int ag_grav_timestep(ag_ctx *ctx, int64_t n, const int32_t *idx, int64_t n_idx,
                      const double *tidal, double eta, double dt_max, int32_t k_max,
@@ -252,9 +253,42 @@ int ag_kick_drift(ag_ctx *ctx, int64_t n, double *x, double *v, const double *ac
  * with t - t0 and the product and sum each rounded once (no fused
  * multiply-add).  Equal to repeated application of Eq. 6 in exact arithmetic,
  * since the jerk only changes at a force update.  Rows with mask[i] == 0 are
- * left untouched (mask may be NULL = all rows).  acc_out may alias acc0. */
+ * left untouched (mask may be NULL = all rows).  acc_out may alias acc0.
+ * jerk = NULL selects no predictor (acc_out = acc0, the ablation of Sec. 4.1;
+ * t0 may then be NULL too). */
 int ag_grav_predict(ag_ctx *ctx, int64_t n, const uint8_t *mask, const double *acc0,
                     const double *jerk, const double *t0, double t, double *acc_out);
+
+/* Deepest force log the polynomial predictor takes. */
+#define AG_PRED_MAX_DEPTH 4
+
+/* Force log for the polynomial predictor, the alternative to Eq. 6 that
+ * Sec. 2.2 names (log a few past g and extrapolate).  For each row r in
+ * idx[0..n_idx) (device int32, unique; NULL with n_idx = n: all rows;
+ * n_idx = 0: none): the logged forces
+ * of r move one slot older (the oldest of `depth` slots is dropped), slot 0
+ * takes (t, acc0[r]) and hist_n[r] grows by one up to depth.  Layout,
+ * slot-major with slot 0 the newest: hist_a (depth, n, 3), hist_t (depth, n),
+ * hist_n (n,) int32; all caller-owned device memory, zeroed by the caller
+ * before the first log.  depth in [1, AG_PRED_MAX_DEPTH].  Rows out of
+ * [0, n) are skipped and raise the device flag reported by the next
+ * ag_sync (AG_EDEVICE). */
+int ag_force_log(ag_ctx *ctx, int64_t n, const int32_t *idx, int64_t n_idx, int32_t depth,
+                 const double *acc0, double t, double *hist_a, double *hist_t, int32_t *hist_n);
+
+/* Polynomial predictor (Sec. 2.2) from a log written by ag_force_log with
+ * the same n and depth: for every row, the interpolating polynomial through
+ * its newest logged forces, evaluated at t in Lagrange form,
+ *   acc_out = sum_k g_k prod_{m != k} (t - t_m) / (t_k - t_m),
+ * over at most order + 1 of them (order in [0, depth - 1]; 1 = the linear
+ * predictor that removes the leading lag error), no more than the row has
+ * logged, and stopping before the first slot that is not strictly older than
+ * the one before it.  Rows with nothing logged, or with mask[i] == 0 (mask
+ * NULL = all rows), are left untouched.  acc_out (n,3) must not alias the
+ * log. */
+int ag_grav_predict_poly(ag_ctx *ctx, int64_t n, const uint8_t *mask, int32_t depth, int32_t order,
+                         const double *hist_a, const double *hist_t, const int32_t *hist_n, double t,
+                         double *acc_out);
 
 /* ---- adjoint -------------------------------------------------------------- */
 

@@ -37,7 +37,9 @@ ENTRY_POINTS = [
     "ag_grav_eval_batched", "ag_grav_direct", "ag_grav_timestep", "ag_adaptive_select",
     "ag_grav_predict", "ag_grav_backward", "ag_timing_enable", "ag_timing_read",
     "ag_kick_drift", "ag_set_option", "ag_graph_begin", "ag_graph_end", "ag_graph_replay",
+    "ag_force_log", "ag_grav_predict_poly",
 ]
+AG_PRED_MAX_DEPTH = 4
 AG_OPT_WALK_WAVES_PER_CU = 1
 AG_OPT_SMALL_NODE = 2
 AG_OPT_GROUP_SPAN = 3
@@ -93,6 +95,8 @@ def load_library(path: str = LIB_PATH):
         "ag_set_option": [P, I32, I64],
         "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
+        "ag_force_log": [P, I64, P, I64, I32, P, D, P, P, P],
+        "ag_grav_predict_poly": [P, I64, P, I32, I32, P, P, P, D, P],
         "ag_grav_backward": [P, P, I64, P, D, D, D, P, P],
         "ag_timing_enable": [P, ctypes.c_int],
         "ag_timing_read": [P, P, P, ctypes.c_int],
@@ -298,6 +302,30 @@ class Context:
                                     _ptr(jerk, torch.float64, (3,), "jerk", n),
                                     _ptr(t0, torch.float64, None, "t0", n), float(t),
                                     _ptr(acc_out, torch.float64, (3,), "acc_out", n)))
+
+    @staticmethod
+    def _log_ptrs(hist_a, hist_t, hist_n):
+        """Checked pointers of a force log: hist_a (depth, n, 3), hist_t
+        (depth, n), hist_n (n,)."""
+        if hist_a.dim() != 3 or hist_a.shape[2] != 3:
+            raise ValueError("hist_a must have shape (depth, n, 3)")
+        depth, n = hist_a.shape[0], hist_a.shape[1]
+        if tuple(hist_t.shape) != (depth, n) or tuple(hist_n.shape) != (n,):
+            raise ValueError("hist_t must be (depth, n) and hist_n (n,) for hist_a (depth, n, 3)")
+        return (depth, n, _ptr(hist_a, torch.float64, None, "hist_a"),
+                _ptr(hist_t, torch.float64, None, "hist_t"), _ptr(hist_n, torch.int32, None, "hist_n"))
+
+    def force_log(self, acc0, t, hist_a, hist_t, hist_n, idx=None):
+        depth, n, pa, pt, pn = self._log_ptrs(hist_a, hist_t, hist_n)
+        k = n if idx is None else idx.shape[0]
+        _check(_lib.ag_force_log(self._h, n, _ptr(idx, torch.int32, None, "idx"), k, depth,
+                                 _ptr(acc0, torch.float64, (3,), "acc0", n), float(t), pa, pt, pn))
+
+    def grav_predict_poly(self, hist_a, hist_t, hist_n, order, t, acc_out, mask=None):
+        depth, n, pa, pt, pn = self._log_ptrs(hist_a, hist_t, hist_n)
+        _check(_lib.ag_grav_predict_poly(self._h, n, _ptr(mask, torch.uint8, None, "mask", n), depth,
+                                         int(order), pa, pt, pn, float(t),
+                                         _ptr(acc_out, torch.float64, (3,), "acc_out", n)))
 
     def grav_backward(self, active_idx, w, theta, eps, G, dLdx, dLdm):
         n = self.n

@@ -371,8 +371,8 @@ extern "C" int ag_grav_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_
     if (!(eta > 0.0) || !std::isfinite(eta)) return ag_fail(AG_EINVAL, "eta must be positive and finite");
     if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return ag_fail(AG_EINVAL, "dt_max must be positive and finite");
     if (k_max < 0 || k_max > 62) return ag_fail(AG_EINVAL, "k_max must be in [0, 62]");
-    if (idx && (n_idx < 0 || n_idx > n)) return ag_fail(AG_EINVAL, "n_idx out of range");
-    if (!idx) n_idx = n;
+    if (n_idx < 0 || n_idx > n) return ag_fail(AG_EINVAL, "n_idx out of range");
+    if (!idx && n_idx != n && n_idx != 0) return ag_fail(AG_EINVAL, "idx = NULL needs n_idx = n (all rows)");
     if (n_idx == 0) return AG_OK;
     DeviceGuard g(c->device);
     AG_TRY(ag_launch_timestep(c, n, idx, n_idx, tidal, eta, dt_max, k_max, dt, bin));
@@ -473,11 +473,42 @@ extern "C" int ag_grav_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const 
                                const double* j, const double* t0, double t, double* out) {
     AG_TRY(check_ctx(c));
     if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
-    if (!a0 || !j || !t0 || !out) return ag_fail(AG_EINVAL, "null pointer argument");
+    if (!a0 || !out || (j && !t0)) return ag_fail(AG_EINVAL, "null pointer argument");
     if (!std::isfinite(t)) return ag_fail(AG_EINVAL, "t must be finite");
     DeviceGuard g(c->device);
     AG_TRY(ag_launch_predict(c, n, mask, a0, j, t0, t, out));
     return check_launch("grav predict");
+}
+
+extern "C" int ag_force_log(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx, int32_t depth,
+                            const double* a0, double t, double* ha, double* ht, int32_t* hn) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n exceeds 2^30");
+    if (depth < 1 || depth > AG_PRED_MAX_DEPTH) return ag_fail(AG_EINVAL, "depth must be in [1, AG_PRED_MAX_DEPTH]");
+    if (!a0 || !ha || !ht || !hn) return ag_fail(AG_EINVAL, "null pointer argument");
+    if (!std::isfinite(t)) return ag_fail(AG_EINVAL, "t must be finite");
+    if (n_idx < 0 || n_idx > n) return ag_fail(AG_EINVAL, "n_idx out of range");
+    if (!idx && n_idx != n && n_idx != 0) return ag_fail(AG_EINVAL, "idx = NULL needs n_idx = n (all rows)");
+    if (n_idx == 0) return AG_OK;
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_force_log(c, n, idx, n_idx, depth, a0, t, ha, ht, hn));
+    return check_launch("force log");
+}
+
+extern "C" int ag_grav_predict_poly(ag_ctx* c, int64_t n, const uint8_t* mask, int32_t depth, int32_t order,
+                                    const double* ha, const double* ht, const int32_t* hn, double t,
+                                    double* out) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n exceeds 2^30");
+    if (depth < 1 || depth > AG_PRED_MAX_DEPTH) return ag_fail(AG_EINVAL, "depth must be in [1, AG_PRED_MAX_DEPTH]");
+    if (order < 0 || order >= depth) return ag_fail(AG_EINVAL, "order must be in [0, depth - 1]");
+    if (!ha || !ht || !hn || !out) return ag_fail(AG_EINVAL, "null pointer argument");
+    if (!std::isfinite(t)) return ag_fail(AG_EINVAL, "t must be finite");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_predict_poly(c, n, mask, depth, order, ha, ht, hn, t, out));
+    return check_launch("grav predict poly");
 }
 
 extern "C" int ag_grav_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w,

@@ -166,6 +166,10 @@ int ag_launch_kick_drift(ag_ctx* c, int64_t n, double* x, double* v, const doubl
                          double dt_drift);
 int ag_launch_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0,
                       const double* j, const double* t0, double t, double* out);
+int ag_launch_force_log(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx, int32_t depth,
+                        const double* a0, double t, double* ha, double* ht, int32_t* hn);
+int ag_launch_predict_poly(ag_ctx* c, int64_t n, const uint8_t* mask, int32_t depth, int32_t order,
+                           const double* ha, const double* ht, const int32_t* hn, double t, double* out);
 int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
                     int32_t n_sys, const int64_t* sys_offsets, int32_t n_leaf);
 int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m);

@@ -118,12 +118,82 @@ __global__ void k_predict(int64_t n, const uint8_t* __restrict__ mask, const dou
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (mask && !mask[i]) continue;
+        if (!j) {   // no predictor: the force of the last evaluation
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[3 * i + c] = a0[3 * i + c];
+            continue;
+        }
         double dt = t - t0[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             double jd = j[3 * i + c] * dt;
             out[3 * i + c] = a0[3 * i + c] + jd;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Polynomial predictor (Sec. 2.2): a log of each row's last `depth` fresh
+// forces, slot-major (slot 0 newest): hist_a (depth, n, 3), hist_t (depth, n)
+// ---------------------------------------------------------------------------
+__global__ void k_force_log(int64_t n_rows, const int32_t* __restrict__ idx, int64_t n, int depth,
+                            const double* __restrict__ a0, double t, double* __restrict__ ha,
+                            double* __restrict__ ht, int32_t* __restrict__ hn, int32_t* __restrict__ flags) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_rows;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx ? (int64_t)idx[k] : k;
+        if (r < 0 || r >= n) {
+            atomicOr(flags, AGF_BADINDEX);
+            continue;
+        }
+        for (int s = depth - 1; s > 0; --s) {
+            ht[s * n + r] = ht[(s - 1) * n + r];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ha[3 * (s * n + r) + c] = ha[3 * ((s - 1) * n + r) + c];
+        }
+        ht[r] = t;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ha[3 * r + c] = a0[3 * r + c];
+        const int cnt = hn[r] + 1;
+        hn[r] = cnt < depth ? cnt : depth;
+    }
+}
+
+// g(t) = sum_k g_k prod_{m != k} (t - t_m) / (t_k - t_m) over the newest
+// logged forces: at most order + 1 of them, as many as the row has, and only
+// while each is strictly older than the one before (distinct nodes).  Rows
+// with nothing logged, or masked out, are left untouched.
+__global__ void k_predict_poly(int64_t n, const uint8_t* __restrict__ mask, int depth, int order,
+                               const double* __restrict__ ha, const double* __restrict__ ht,
+                               const int32_t* __restrict__ hn, double t, double* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (mask && !mask[i]) continue;
+        int cnt = hn[i];
+        cnt = cnt < depth ? cnt : depth;
+        if (cnt <= 0) continue;
+        double tk[AG_PRED_MAX_DEPTH];
+        tk[0] = ht[i];
+        int nodes = 1;
+        for (int k = 1; k < cnt && k <= order; ++k) {
+            const double tt = ht[k * n + i];
+            if (!(tt < tk[k - 1])) break;
+            tk[k] = tt;
+            nodes = k + 1;
+        }
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < nodes; ++k) {
+            double w = 1.0;
+            for (int m = 0; m < nodes; ++m)
+                if (m != k) w = w * ((t - tk[m]) / (tk[k] - tk[m]));
+            const double* a = ha + 3 * (k * n + i);
+            s0 = s0 + w * a[0];
+            s1 = s1 + w * a[1];
+            s2 = s2 + w * a[2];
+        }
+        out[3 * i] = s0;
+        out[3 * i + 1] = s1;
+        out[3 * i + 2] = s2;
     }
 }
 
@@ -271,6 +341,22 @@ int ag_launch_kick_drift(ag_ctx* c, int64_t n, double* x, double* v, const doubl
     PhaseScope phase(c, AG_PHASE_STEP);
     hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(3 * n)), dim3(kThreads), 0, c->stream, 3 * n, x, v, acc,
                        dt_kick, dt_drift);
+    return AG_OK;
+}
+
+int ag_launch_force_log(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx, int32_t depth,
+                        const double* a0, double t, double* ha, double* ht, int32_t* hn) {
+    PhaseScope phase(c, AG_PHASE_STEP);
+    hipLaunchKernelGGL(k_force_log, dim3(grid_for(n_idx)), dim3(kThreads), 0, c->stream, n_idx, idx, n,
+                       (int)depth, a0, t, ha, ht, hn, c->dflags.as<int32_t>());
+    return AG_OK;
+}
+
+int ag_launch_predict_poly(ag_ctx* c, int64_t n, const uint8_t* mask, int32_t depth, int32_t order,
+                           const double* ha, const double* ht, const int32_t* hn, double t, double* out) {
+    PhaseScope phase(c, AG_PHASE_STEP);
+    hipLaunchKernelGGL(k_predict_poly, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, mask, (int)depth,
+                       (int)order, ha, ht, hn, t, out);
     return AG_OK;
 }
 

@@ -5,7 +5,10 @@ step of the paper, which a gravity-only code does not have).  At the start
 of each step the force-age counters advance by one tick (Eq. 3) and only the
 particles whose counter has reached q_f times their gravity bin (Eq. 4) get a
 fresh tree force, jerk and tidal tensor; their tidal timestep and bin are
-recomputed (Eq. 7).  Every other particle uses the jerk predictor (Eq. 6).
+recomputed (Eq. 7).  Every other particle uses the jerk predictor (Eq. 6),
+or one of the variants Sec. 2.2 discusses: none (hold the last force, the
+paper's ablation), or a polynomial through the last two ("linear") or three
+("quadratic") fresh forces of the particle, kept in a force log.
 q_f = 0 re-evaluates everybody every step: the standard scheme.
 
 Time is kept in integer ticks: dt_max = 2^ceil(log2 max dt_grav(0)) and one
@@ -18,7 +21,8 @@ Step (kick-drift-kick):
   tree rebuild (or refit every other step, see ``rebuild_every``) with the
   velocities predicted to time t (v + a dt/2)
   fresh g, j, T for the due particles; their dt_grav and bin
-  a = a0 + j (t - t0) for all particles (exact a0 for the due ones)
+  a = a0 + j (t - t0) for all particles (exact a0 for the due ones), or the
+  chosen variant
   v += a dt/2
 All arithmetic runs in the library's kernels; this module sequences calls.
 """
@@ -31,13 +35,23 @@ import torch
 from . import Context
 
 
+PREDICTORS = {"jerk": None, "none": None, "linear": 1, "quadratic": 2}
+
+
 class AdaptiveIntegrator:
     def __init__(self, ctx: Context, x, v, m, q_f: float, theta: float, eps: float, eta: float = 0.01,
-                 G: float = 1.0, n_leaf: int = 16, rebuild_every: int = 1, step_shift: int = 0):
+                 G: float = 1.0, n_leaf: int = 16, rebuild_every: int = 1, step_shift: int = 0,
+                 predictor: str = "jerk"):
         """step_shift h: the global step is 2^-h times the shortest gravity
         bin at t = 0 (h = 0: the step equals the shortest gravity step; h > 0
         models a non-gravity step constraint tighter than gravity's, the
-        regime in which the scheme saves work)."""
+        regime in which the scheme saves work).  predictor: "jerk" (Eq. 6),
+        "none", "linear" or "quadratic" (polynomial through the last 2 or 3
+        fresh forces; fewer right after the start)."""
+        if predictor not in PREDICTORS:
+            raise ValueError(f"predictor must be one of {sorted(PREDICTORS)}")
+        self.predictor = predictor
+        self.order = PREDICTORS[predictor]
         self.ctx = ctx
         dev = x.device
         self.n = n = x.shape[0]
@@ -59,6 +73,12 @@ class AdaptiveIntegrator:
         self.n_active = torch.zeros(1, dtype=torch.int64, device=dev)
         self.vpred = torch.zeros_like(self.v)
         self.scratch = torch.zeros_like(self.x)
+        self.log = None
+        if self.order is not None:
+            depth = self.order + 1
+            self.log = (torch.zeros((depth, n, 3), dtype=torch.float64, device=dev),
+                        torch.zeros((depth, n), dtype=torch.float64, device=dev),
+                        torch.zeros(n, dtype=torch.int32, device=dev))
         self.t = 0.0
         self.step_index = 0
         self.evaluations = 0
@@ -74,6 +94,8 @@ class AdaptiveIntegrator:
         self.tick_bin = int(self.bins.max().item()) + int(step_shift)
         self.dt = self.dt_max * 2.0 ** (-self.tick_bin)
         self.acc.copy_(self.a0)
+        if self.log is not None:
+            ctx.force_log(self.a0, 0.0, *self.log)
         self.evaluations += n
         self._need_build = False
 
@@ -97,7 +119,14 @@ class AdaptiveIntegrator:
             idx = self.active[:k]
             c.grav_eval(idx, self.theta, self.eps, self.G, self.a0, self.jerk, self.tidal)
             c.grav_timestep(self.tidal, self.eta, self.dt_max, 60, self.dt_grav, self.bins, idx=idx)
-        c.grav_predict(self.a0, self.jerk, self.t0, self.t, self.acc)
+            if self.log is not None:
+                c.force_log(self.a0, self.t, *self.log, idx=idx)
+        if self.predictor == "jerk":
+            c.grav_predict(self.a0, self.jerk, self.t0, self.t, self.acc)
+        elif self.predictor == "none":
+            c.grav_predict(self.a0, None, None, self.t, self.acc)
+        else:
+            c.grav_predict_poly(*self.log, self.order, self.t, self.acc)
         c.kick_drift(self.x, self.v, self.acc, 0.5 * dt, 0.0)
         self.evaluations += k
         return k
@@ -106,6 +135,8 @@ class AdaptiveIntegrator:
         """Everything needed to resume bit for bit (see ``restore``)."""
         keys = ["x", "v", "a0", "jerk", "tidal", "acc", "t0", "tf", "bins", "dt_grav"]
         s = {k: getattr(self, k).clone() for k in keys}
+        if self.log is not None:
+            s["log"] = tuple(a.clone() for a in self.log)
         s.update(t=self.t, step_index=self.step_index, evaluations=self.evaluations, dt=self.dt,
                  dt_max=self.dt_max, tick_bin=self.tick_bin)
         return s
@@ -116,6 +147,9 @@ class AdaptiveIntegrator:
         rebuild anyway (always with rebuild_every = 1)."""
         for k in ["x", "v", "a0", "jerk", "tidal", "acc", "t0", "tf", "bins", "dt_grav"]:
             getattr(self, k).copy_(s[k])
+        if self.log is not None:
+            for a, b in zip(self.log, s["log"]):
+                a.copy_(b)
         for k in ["t", "step_index", "evaluations", "dt", "dt_max", "tick_bin"]:
             setattr(self, k, s[k])
         self._need_build = True

@@ -74,22 +74,32 @@ def test_adaptive_counts_and_force_error(ag, orc):
         assert np.median(err) < 2e-3
 
 
-def test_adaptive_resume_bit_exact(ag):
+def _move(v, dev):
+    if torch.is_tensor(v):
+        return v.to(dev)
+    if isinstance(v, tuple):
+        return tuple(_move(a, dev) for a in v)
+    return v
+
+
+@pytest.mark.parametrize("predictor", ["jerk", "linear"])
+def test_adaptive_resume_bit_exact(ag, predictor):
     from paper_2010_13792_amd.driver import AdaptiveIntegrator
     n = 1 << 13
     tx, tv, tm, _ = _clumps(n)
+    kw = dict(q_f=0.25, theta=0.6, eps=1e-3, predictor=predictor)
     with ag.Context(0) as c:
-        a = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.25, theta=0.6, eps=1e-3)
+        a = AdaptiveIntegrator(c, tx, tv, tm, **kw)
         for _ in range(6):
             a.step()
         c.sync()
         ref = a.state()
-        b = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.25, theta=0.6, eps=1e-3)
+        b = AdaptiveIntegrator(c, tx, tv, tm, **kw)
         for _ in range(3):
             b.step()
-        saved = {k: (v.cpu() if torch.is_tensor(v) else v) for k, v in b.state().items()}
-        r = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.25, theta=0.6, eps=1e-3)
-        r.restore({k: (v.to(DEV) if torch.is_tensor(v) else v) for k, v in saved.items()})
+        saved = {k: _move(v, "cpu") for k, v in b.state().items()}
+        r = AdaptiveIntegrator(c, tx, tv, tm, **kw)
+        r.restore({k: _move(v, DEV) for k, v in saved.items()})
         for _ in range(3):
             r.step()
         c.sync()
@@ -97,6 +107,51 @@ def test_adaptive_resume_bit_exact(ag):
         for k in ["x", "v", "acc", "tf", "bins", "t0"]:
             assert torch.equal(got[k], ref[k]), k
         assert got["evaluations"] == ref["evaluations"]
+
+
+def test_predictor_variants(ag, orc):
+    """Between updates (global step a quarter of the shortest gravity bin,
+    q_f = 1/4), holding the last force (the ablation of Sec. 4.1) leaves a
+    larger force error than the jerk predictor (Eq. 6).  A polynomial
+    through the last fresh forces (Sec. 2.2) needs as many logged forces as
+    its order + 1: on the rows that have them, it beats holding the newest
+    logged force of the same log at the same state."""
+    from paper_2010_13792_amd.driver import AdaptiveIntegrator
+    n = 1 << 14
+    tx, tv, tm, (x, v, m) = _clumps(n)
+    rows = np.random.default_rng(5).choice(n, 2048, replace=False)
+    errs = {}
+    with ag.Context(0) as c:
+        for p in ["none", "jerk", "linear", "quadratic"]:
+            # bins of this set span 4 to 2048 ticks: at q_f = 1/4, by step 30
+            # rows of span <= 64 ticks hold >= 2 logged forces and rows of
+            # span 16 to 64 are extrapolated (not refreshed) at that step
+            ad = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.25, theta=0.5, eps=1e-3, step_shift=2, predictor=p)
+            counts = [ad.step() for _ in range(30)]
+            c.sync()
+            assert 0 < sum(counts) < 30 * n
+            ar, _, _ = orc.direct(ad.x.cpu().numpy(), ad.vpred.cpu().numpy(), m, 1e-3, 1.0, rows)
+            e = rel_err(ad.acc.cpu().numpy()[rows], ar)
+            errs[p] = float(np.median(e))
+            if ad.log is None:
+                continue
+            ha, ht, hn = ad.log
+            hold = torch.empty_like(ad.acc)
+            c.grav_predict_poly(ha, ht, hn, 0, ad.t, hold)
+            c.sync()
+            # rows whose log is full and whose force in use is extrapolated
+            full = np.nonzero((hn.cpu().numpy() == ad.order + 1) & (ht[0].cpu().numpy() < ad.t))[0]
+            assert full.size >= 256
+            full = full[:1024]
+            af, _, _ = orc.direct(ad.x.cpu().numpy(), ad.vpred.cpu().numpy(), m, 1e-3, 1.0, full)
+            ep = np.median(rel_err(ad.acc.cpu().numpy()[full], af))
+            e0 = np.median(rel_err(hold.cpu().numpy()[full], af))
+            errs[f"{p} ({full.size} rows with a full log)"] = float(ep)
+            errs[f"held ({full.size} rows with a full log)"] = float(e0)
+            assert ep < 0.5 * e0
+    print("median force error by predictor:", errs)
+    assert errs["jerk"] < 0.2 * errs["none"]
+    assert errs["jerk"] < 2e-3
 
 
 def test_graph_replay_matches_eager(ag):
