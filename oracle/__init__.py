@@ -8,7 +8,9 @@ routine of the same name in ``oracle.c`` (built into ``liboracle.so`` by
 
 * :func:`field` / :func:`direct` -- softened direct sum for the acceleration,
   the jerk (the particle discretisation of the jerk integral, Eq. 5) and the
-  tidal tensor (whose Frobenius norm enters Eq. 7).
+  tidal tensor (whose Frobenius norm enters Eq. 7); optionally in a periodic
+  cube with every pair at its nearest image (how the paper treats the jerk
+  of periodic problems, Sec. 4).
 * :func:`timestep` -- the tidal timestep of Eq. 7 and its power-of-two bin.
 * :func:`select` -- force-age counter (Eq. 3) and update condition (Eq. 4).
 * :func:`predict` -- jerk predictor (Eq. 6) in closed form ``a0 + j (t - t0)``.
@@ -61,6 +63,9 @@ def _load():
         lib.orc_field.argtypes = [I64, P, P, P, D, D, I64, P, P, P, P, P, P]
         lib.orc_direct.argtypes = [I64, P, P, P, D, D, I64, P, P, P, P]
         lib.orc_abs_scale.argtypes = [I64, P, P, D, D, I64, P, P]
+        lib.orc_field_box.argtypes = [I64, P, P, P, D, D, D, I64, P, P, P, P, P, P]
+        lib.orc_direct_box.argtypes = [I64, P, P, P, D, D, D, I64, P, P, P, P]
+        lib.orc_abs_scale_box.argtypes = [I64, P, P, D, D, D, I64, P, P]
         lib.orc_timestep.argtypes = [I64, P, D, D, ctypes.c_int32, P, P]
         lib.orc_select.argtypes = [I64, P, P, I64, ctypes.c_int32, D, P]
         lib.orc_select.restype = I64
@@ -103,8 +108,9 @@ def kernel(r, h):
     return f, D, W
 
 
-def field(x, v, m, eps, G, p, pv=None, excl=None):
-    """Acceleration, jerk and tidal tensor at probe points ``p`` (np x 3)."""
+def field(x, v, m, eps, G, p, pv=None, excl=None, box=0.0):
+    """Acceleration, jerk and tidal tensor at probe points ``p`` (np x 3).
+    box > 0: every pair at its nearest periodic image in a cube of that side."""
     x = _f64(x, (-1, 3))
     v = _f64(v, (-1, 3))
     m = _f64(m).ravel()
@@ -115,13 +121,14 @@ def field(x, v, m, eps, G, p, pv=None, excl=None):
     acc = np.empty((k, 3))
     jerk = np.empty((k, 3))
     tid = np.empty((k, 6))
-    _load().orc_field(x.shape[0], _ptr(x), _ptr(v), _ptr(m), float(eps), float(G),
-                      k, _ptr(p), _ptr(pv), _ptr(ex), _ptr(acc), _ptr(jerk), _ptr(tid))
+    _load().orc_field_box(x.shape[0], _ptr(x), _ptr(v), _ptr(m), float(eps), float(G), float(box),
+                          k, _ptr(p), _ptr(pv), _ptr(ex), _ptr(acc), _ptr(jerk), _ptr(tid))
     return acc, jerk, tid
 
 
-def direct(x, v, m, eps, G, targets=None):
-    """Direct sum at particles ``targets`` (default: all), self excluded."""
+def direct(x, v, m, eps, G, targets=None, box=0.0):
+    """Direct sum at particles ``targets`` (default: all), self excluded;
+    box > 0: nearest periodic images."""
     x = _f64(x, (-1, 3))
     v = _f64(v, (-1, 3))
     m = _f64(m).ravel()
@@ -132,12 +139,12 @@ def direct(x, v, m, eps, G, targets=None):
     acc = np.empty((k, 3))
     jerk = np.empty((k, 3))
     tid = np.empty((k, 6))
-    _load().orc_direct(n, _ptr(x), _ptr(v), _ptr(m), float(eps), float(G), k, _ptr(tgt),
-                       _ptr(acc), _ptr(jerk), _ptr(tid))
+    _load().orc_direct_box(n, _ptr(x), _ptr(v), _ptr(m), float(eps), float(G), float(box), k,
+                           _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(tid))
     return acc, jerk, tid
 
 
-def abs_scale(x, m, eps, G, targets=None):
+def abs_scale(x, m, eps, G, targets=None, box=0.0):
     """G sum_j m_j |f d| per target: the cancellation-free size of the sum."""
     x = _f64(x, (-1, 3))
     m = _f64(m).ravel()
@@ -145,8 +152,8 @@ def abs_scale(x, m, eps, G, targets=None):
     tgt = np.arange(n, dtype=np.int64) if targets is None else \
         np.ascontiguousarray(targets, dtype=np.int64)
     out = np.empty(tgt.size)
-    _load().orc_abs_scale(n, _ptr(x), _ptr(m), float(eps), float(G), tgt.size, _ptr(tgt),
-                          _ptr(out))
+    _load().orc_abs_scale_box(n, _ptr(x), _ptr(m), float(eps), float(G), float(box), tgt.size,
+                              _ptr(tgt), _ptr(out))
     return out
 
 

@@ -106,10 +106,18 @@ void orc_kernel(int64_t n, const double *r, double h, double *f, double *D, doub
  *   j  =  G sum_j m_j [ f nu + D (d.nu) d ]          nu = v_j - pv
  *   T  = -G sum_j m_j [ f I  + D d d^T ]             (T = grad g)
  */
-void orc_field(int64_t n, const double *x, const double *v, const double *m,
-               double eps, double G,
-               int64_t np, const double *p, const double *pv, const int64_t *excl,
-               double *acc, double *jerk, double *tidal)
+/* Nearest periodic image of a separation in a cubic box of side L:
+ * d - L * round(d / L), ties to even (L <= 0: no box, d unchanged). */
+static double nearest_image(double d, double L)
+{
+    if (L <= 0) return d;
+    return d - L * nearbyint(d / L);
+}
+
+void orc_field_box(int64_t n, const double *x, const double *v, const double *m,
+                   double eps, double G, double box,
+                   int64_t np, const double *p, const double *pv, const int64_t *excl,
+                   double *acc, double *jerk, double *tidal)
 {
     #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < np; ++k) {
@@ -120,7 +128,9 @@ void orc_field(int64_t n, const double *x, const double *v, const double *m,
         double txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == skip) continue;
-            double dx = x[3 * j] - px, dy = x[3 * j + 1] - py, dz = x[3 * j + 2] - pz;
+            double dx = nearest_image(x[3 * j] - px, box);
+            double dy = nearest_image(x[3 * j + 1] - py, box);
+            double dz = nearest_image(x[3 * j + 2] - pz, box);
             double nx = v[3 * j] - qx, ny = v[3 * j + 1] - qy, nz = v[3 * j + 2] - qz;
             double r = sqrt(dx * dx + dy * dy + dz * dz);
             double f, D;
@@ -145,11 +155,20 @@ void orc_field(int64_t n, const double *x, const double *v, const double *m,
     }
 }
 
+void orc_field(int64_t n, const double *x, const double *v, const double *m,
+               double eps, double G,
+               int64_t np, const double *p, const double *pv, const int64_t *excl,
+               double *acc, double *jerk, double *tidal)
+{
+    orc_field_box(n, x, v, m, eps, G, 0.0, np, p, pv, excl, acc, jerk, tidal);
+}
+
 /* Direct sum at the particles listed in tgt (self excluded); outputs have
- * ntgt rows in the order of tgt. */
-void orc_direct(int64_t n, const double *x, const double *v, const double *m,
-                double eps, double G, int64_t ntgt, const int64_t *tgt,
-                double *acc, double *jerk, double *tidal)
+ * ntgt rows in the order of tgt.  box > 0: every pair at its nearest
+ * periodic image in a cube of that side. */
+void orc_direct_box(int64_t n, const double *x, const double *v, const double *m,
+                    double eps, double G, double box, int64_t ntgt, const int64_t *tgt,
+                    double *acc, double *jerk, double *tidal)
 {
     double *p = (double *)malloc(sizeof(double) * 3 * (size_t)(ntgt > 0 ? ntgt : 1));
     double *q = (double *)malloc(sizeof(double) * 3 * (size_t)(ntgt > 0 ? ntgt : 1));
@@ -158,15 +177,22 @@ void orc_direct(int64_t n, const double *x, const double *v, const double *m,
             p[3 * k + c] = x[3 * tgt[k] + c];
             q[3 * k + c] = v[3 * tgt[k] + c];
         }
-    orc_field(n, x, v, m, eps, G, ntgt, p, q, tgt, acc, jerk, tidal);
+    orc_field_box(n, x, v, m, eps, G, box, ntgt, p, q, tgt, acc, jerk, tidal);
     free(p);
     free(q);
 }
 
+void orc_direct(int64_t n, const double *x, const double *v, const double *m,
+                double eps, double G, int64_t ntgt, const int64_t *tgt,
+                double *acc, double *jerk, double *tidal)
+{
+    orc_direct_box(n, x, v, m, eps, G, 0.0, ntgt, tgt, acc, jerk, tidal);
+}
+
 /* Sum of |pair acceleration terms| G sum_j m_j |f d|, the scale against which
  * the FP64 direct sum's cancellation error is normalised. */
-void orc_abs_scale(int64_t n, const double *x, const double *m, double eps, double G,
-                   int64_t ntgt, const int64_t *tgt, double *scale)
+void orc_abs_scale_box(int64_t n, const double *x, const double *m, double eps, double G, double box,
+                       int64_t ntgt, const int64_t *tgt, double *scale)
 {
     #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < ntgt; ++k) {
@@ -174,8 +200,9 @@ void orc_abs_scale(int64_t n, const double *x, const double *m, double eps, doub
         double s = 0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
-            double dx = x[3 * j] - x[3 * i], dy = x[3 * j + 1] - x[3 * i + 1],
-                   dz = x[3 * j + 2] - x[3 * i + 2];
+            double dx = nearest_image(x[3 * j] - x[3 * i], box);
+            double dy = nearest_image(x[3 * j + 1] - x[3 * i + 1], box);
+            double dz = nearest_image(x[3 * j + 2] - x[3 * i + 2], box);
             double r = sqrt(dx * dx + dy * dy + dz * dz);
             double f, D;
             kernel_fd(r, eps, &f, &D);
@@ -183,6 +210,12 @@ void orc_abs_scale(int64_t n, const double *x, const double *m, double eps, doub
         }
         scale[k] = G * s;
     }
+}
+
+void orc_abs_scale(int64_t n, const double *x, const double *m, double eps, double G,
+                   int64_t ntgt, const int64_t *tgt, double *scale)
+{
+    orc_abs_scale_box(n, x, m, eps, G, 0.0, ntgt, tgt, scale);
 }
 
 /* ---- tidal timestep (Eq. 7) and block bin --------------------------------- */
