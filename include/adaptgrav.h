@@ -111,6 +111,18 @@ enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 
        AG_OPT_GROUP_TARGETS = 5 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
+/* Periodic boundaries (the treatment Sec. 4 gives the jerk of its periodic
+ * problem): box > 0 makes every later ag_grav_eval, ag_grav_eval_batched and
+ * ag_grav_direct on this context take each pair at its nearest image in a
+ * cube of side box, d -> d - box * rint(d / box) per axis, for g, j and T
+ * alike (no Ewald sum, so g is the nearest-image force).  Positions may lie
+ * in any image.  The tree opening test then also requires, per axis, all of
+ * a node's box to lie within half a box side of all of the group's box, so
+ * every particle of an accepted node shares one image.  box = 0 restores
+ * open boundaries (the default).  While a box is set, ag_grav_backward
+ * returns AG_ESTATE.  box < 0 or not finite gives AG_EINVAL. */
+int ag_set_periodic(ag_ctx *ctx, double box);
+
 /* HIP-graph capture of a call sequence on the context's stream (which must
  * not be the legacy default stream).  Between ag_graph_begin and
  * ag_graph_end, library calls are recorded, not run; device buffers they

@@ -37,7 +37,7 @@ ENTRY_POINTS = [
     "ag_grav_eval_batched", "ag_grav_direct", "ag_grav_timestep", "ag_adaptive_select",
     "ag_grav_predict", "ag_grav_backward", "ag_timing_enable", "ag_timing_read",
     "ag_kick_drift", "ag_set_option", "ag_graph_begin", "ag_graph_end", "ag_graph_replay",
-    "ag_force_log", "ag_grav_predict_poly",
+    "ag_force_log", "ag_grav_predict_poly", "ag_set_periodic",
 ]
 AG_PRED_MAX_DEPTH = 4
 AG_OPT_WALK_WAVES_PER_CU = 1
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "ag_adaptive_select": [P, I64, P, P, I64, I32, D, P, P, P, D],
         "ag_kick_drift": [P, I64, P, P, P, D, D],
         "ag_set_option": [P, I32, I64],
+        "ag_set_periodic": [P, D],
         "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
         "ag_force_log": [P, I64, P, I64, I32, P, D, P, P, P],
@@ -302,6 +303,10 @@ class Context:
                                     _ptr(jerk, torch.float64, (3,), "jerk", n),
                                     _ptr(t0, torch.float64, None, "t0", n), float(t),
                                     _ptr(acc_out, torch.float64, (3,), "acc_out", n)))
+
+    def set_periodic(self, box: float):
+        """Nearest-image pairs in a periodic cube of side ``box`` (0: open)."""
+        _check(_lib.ag_set_periodic(self._h, float(box)))
 
     @staticmethod
     def _log_ptrs(hist_a, hist_t, hist_n):

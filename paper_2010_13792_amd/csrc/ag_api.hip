@@ -435,6 +435,13 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
     }
 }
 
+extern "C" int ag_set_periodic(ag_ctx* c, double box) {
+    AG_TRY(check_ctx(c));
+    if (!(box >= 0.0) || !std::isfinite(box)) return ag_fail(AG_EINVAL, "box must be >= 0 and finite");
+    c->box = box;
+    return AG_OK;
+}
+
 extern "C" int ag_graph_begin(ag_ctx* c) {
     AG_TRY(check_ctx(c));
     if (c->capturing) return ag_fail(AG_ESTATE, "already capturing");
@@ -515,6 +522,7 @@ extern "C" int ag_grav_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, co
                                 double theta, double eps, double G, double* dLdx, double* dLdm) {
     AG_TRY(check_eval_args(c, idx, n_act, theta, eps, G));
     if (c->batched) return ag_fail(AG_ESTATE, "backward is not available for a batched tree");
+    if (c->box > 0.0) return ag_fail(AG_ESTATE, "backward is not available with periodic boundaries");
     if (!w || !dLdx || !dLdm) return ag_fail(AG_EINVAL, "w, dLdx and dLdm must be non-null");
     DeviceGuard g(c->device);
     AG_TRY(ag_launch_backward(c, idx, n_act, w, theta, eps, G, dLdx, dLdm));

@@ -71,6 +71,7 @@ struct ag_ctx {
     int small_node = 2;
     int group_span = 128;
     int mac_offset = 1;
+    double box = 0.0;     // periodic cube side (0: open boundaries)
     int group_cap = 64;
     bool capturing = false;
     hipGraph_t graph = nullptr;

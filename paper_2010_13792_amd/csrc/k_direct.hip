@@ -11,6 +11,9 @@
 // FP32-pair mode: the separation d = x_j - x_i is formed in FP64 and rounded
 // once to FP32 (the exact relative coordinate), the pair term is computed in
 // FP32, and each tile's FP32 partial sum is folded into FP64 accumulators.
+//
+// Periodic cube of side L (kPer): d is replaced by its nearest image
+// d - L rint(d / L), in FP64, before anything else.
 #include "ag_internal.h"
 #include "pair.h"
 
@@ -19,12 +22,14 @@ namespace {
 constexpr int kT = 256;          // targets per workgroup = sources per LDS tile
 constexpr int kParts = 12;       // g (3), j (3), S (6)
 
-template <bool kFP64>
+__device__ __forceinline__ double near_img(double d, double L) { return d - L * rint(d / L); }
+
+template <bool kFP64, bool kPer>
 __global__ void __launch_bounds__(kT) k_direct(int64_t n, const double* __restrict__ x,
                                                const double* __restrict__ v,
                                                const double* __restrict__ m,
                                                const int32_t* __restrict__ idx, int64_t n_act,
-                                               double h, int64_t chunk,
+                                               double h, double L, int64_t chunk,
                                                double* __restrict__ part,
                                                int32_t* __restrict__ flags) {
     __shared__ double s_x[kT], s_y[kT], s_z[kT];
@@ -80,16 +85,27 @@ __global__ void __launch_bounds__(kT) k_direct(int64_t n, const double* __restri
         if (kFP64) {
             for (int q = 0; q < cnt; ++q) {
                 const double mj = (t0 + q == i) ? 0.0 : s_m[q];   // self pair excluded
-                pair_interact<double>(s_x[q] - xi, s_y[q] - yi, s_z[q] - zi, s_dvx[q] - vxi,
-                                      s_dvy[q] - vyi, s_dvz[q] - vzi, mj, h2, hinv, A);
+                double dx = s_x[q] - xi, dy = s_y[q] - yi, dz = s_z[q] - zi;
+                if (kPer) {
+                    dx = near_img(dx, L);
+                    dy = near_img(dy, L);
+                    dz = near_img(dz, L);
+                }
+                pair_interact<double>(dx, dy, dz, s_dvx[q] - vxi, s_dvy[q] - vyi, s_dvz[q] - vzi, mj, h2, hinv,
+                                      A);
             }
         } else {
             PairAcc<float> B;
             B.zero();
             for (int q = 0; q < cnt; ++q) {
                 const float mj = (t0 + q == i) ? 0.0f : (float)s_m[q];
-                pair_interact<float>((float)(s_x[q] - xi), (float)(s_y[q] - yi),
-                                     (float)(s_z[q] - zi), s_vx[q] - vxf, s_vy[q] - vyf,
+                double dx = s_x[q] - xi, dy = s_y[q] - yi, dz = s_z[q] - zi;
+                if (kPer) {
+                    dx = near_img(dx, L);
+                    dy = near_img(dy, L);
+                    dz = near_img(dz, L);
+                }
+                pair_interact<float>((float)dx, (float)dy, (float)dz, s_vx[q] - vxf, s_vy[q] - vyf,
                                      s_vz[q] - vzf, mj, h2f, hinvf, B);
             }
             A.ax += B.ax; A.ay += B.ay; A.az += B.az;
@@ -154,12 +170,21 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
     double* part = c->direct_part.as<double>();
     PhaseScope phase(c, AG_PHASE_DIRECT);
     dim3 grid((unsigned)tblocks, (unsigned)nsplit);
-    if (precision == AG_FP64)
-        hipLaunchKernelGGL(k_direct<true>, grid, dim3(kT), 0, c->stream, n, x, v, m, idx, n_act, eps,
-                           chunk, part, c->dflags.as<int32_t>());
+    const double L = c->box;
+    int32_t* fl = c->dflags.as<int32_t>();
+    hipStream_t st = c->stream;
+    if (precision == AG_FP64 && L > 0.0)
+        hipLaunchKernelGGL((k_direct<true, true>), grid, dim3(kT), 0, st, n, x, v, m, idx, n_act, eps, L, chunk,
+                           part, fl);
+    else if (precision == AG_FP64)
+        hipLaunchKernelGGL((k_direct<true, false>), grid, dim3(kT), 0, st, n, x, v, m, idx, n_act, eps, L, chunk,
+                           part, fl);
+    else if (L > 0.0)
+        hipLaunchKernelGGL((k_direct<false, true>), grid, dim3(kT), 0, st, n, x, v, m, idx, n_act, eps, L, chunk,
+                           part, fl);
     else
-        hipLaunchKernelGGL(k_direct<false>, grid, dim3(kT), 0, c->stream, n, x, v, m, idx, n_act, eps,
-                           chunk, part, c->dflags.as<int32_t>());
+        hipLaunchKernelGGL((k_direct<false, false>), grid, dim3(kT), 0, st, n, x, v, m, idx, n_act, eps, L, chunk,
+                           part, fl);
     int64_t rb = (n_act + 255) / 256;
     if (rb > 4096) rb = 4096;
     hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)rb), dim3(256), 0, c->stream, n, idx, n_act,

@@ -78,6 +78,8 @@ struct WalkOut {
     int64_t iter_cap;   // > nodes + particles: every group finishes well within it
     int small_node;     // accepted nodes this small are summed pairwise
     bool mac_offset;    // opening test adds the centre-of-mass offset to the extent
+    double box, box_inv;        // periodic cube side and inverse (periodic walks only)
+    float boxf, boxf_inv, box_half;
     double* dldx;       // adjoint outputs
     double* dldm;
     const double* tin;  // adjoint: tidal tensor rows of the charged targets
@@ -112,17 +114,34 @@ __device__ __forceinline__ GroupBox group_box(double x, double y, double z) {
     return g;
 }
 
+// nearest periodic image of a separation: d - L rint(d / L)
+__device__ __forceinline__ double near_img(double d, const WalkOut& O) { return d - O.box * rint(d * O.box_inv); }
+__device__ __forceinline__ float near_imgf(float d, const WalkOut& O) {
+    return __builtin_fmaf(-O.boxf, rintf(d * O.boxf_inv), d);
+}
+
 // Opening test for node data (com, extent, box) against the group box.
 // Accept iff  L' <= theta * r_min  (r_min: distance from the node's centre of
 // mass to the nearest point of the group box; L' the node's extent L, plus,
 // with `offset` set, the distance from its centre of mass to the centre of
 // its box, which opens lopsided nodes sooner)  and the node's box is at least
 // eps away from the group box (so only Newtonian pairs are approximated).
+// Periodic (kPer): distances are taken at the nearest image of the node, and
+// a node is accepted only if, along every axis, all of its box lies within
+// half a box side of all of the group box -- then every particle-target pair
+// of the node has that same nearest image, and the multipole stands for it.
+template <bool kPer>
 __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
-                                           float theta2, float eps2, bool offset) {
-    const float rx = fmaxf(fabsf((float)(c.x - g.cx)) - g.hx, 0.f);
-    const float ry = fmaxf(fabsf((float)(c.y - g.cy)) - g.hy, 0.f);
-    const float rz = fmaxf(fabsf((float)(c.z - g.cz)) - g.hz, 0.f);
+                                           float theta2, float eps2, bool offset, const WalkOut& O) {
+    double cdx = c.x - g.cx, cdy = c.y - g.cy, cdz = c.z - g.cz;
+    if (kPer) {
+        cdx = near_img(cdx, O);
+        cdy = near_img(cdy, O);
+        cdz = near_img(cdz, O);
+    }
+    const float rx = fmaxf(fabsf((float)cdx) - g.hx, 0.f);
+    const float ry = fmaxf(fabsf((float)cdy) - g.hy, 0.f);
+    const float rz = fmaxf(fabsf((float)cdz) - g.hz, 0.f);
     const float r2 = rx * rx + ry * ry + rz * rz;
     float L = (float)c.w;
     if (offset) {
@@ -131,9 +150,24 @@ __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, c
         const float oz = (float)c.z - 0.5f * (lo.z + hi.z);
         L += sqrtf(ox * ox + oy * oy + oz * oz);
     }
-    const float gx = fmaxf(fmaxf(lo.x - g.hix, g.lox - hi.x), 0.f);
-    const float gy = fmaxf(fmaxf(lo.y - g.hiy, g.loy - hi.y), 0.f);
-    const float gz = fmaxf(fmaxf(lo.z - g.hiz, g.loz - hi.z), 0.f);
+    float gx, gy, gz;
+    if (!kPer) {
+        gx = fmaxf(fmaxf(lo.x - g.hix, g.lox - hi.x), 0.f);
+        gy = fmaxf(fmaxf(lo.y - g.hiy, g.loy - hi.y), 0.f);
+        gz = fmaxf(fmaxf(lo.z - g.hiz, g.loz - hi.z), 0.f);
+    } else {
+        // box centre offset at its nearest image, and the half extents
+        const float bx = fabsf((float)near_img(0.5 * ((double)lo.x + (double)hi.x) - g.cx, O));
+        const float by = fabsf((float)near_img(0.5 * ((double)lo.y + (double)hi.y) - g.cy, O));
+        const float bz = fabsf((float)near_img(0.5 * ((double)lo.z + (double)hi.z) - g.cz, O));
+        const float ex = 0.5f * (hi.x - lo.x) + g.hx;
+        const float ey = 0.5f * (hi.y - lo.y) + g.hy;
+        const float ez = 0.5f * (hi.z - lo.z) + g.hz;
+        if (bx + ex >= O.box_half || by + ey >= O.box_half || bz + ez >= O.box_half) return false;
+        gx = fmaxf(bx - ex, 0.f);
+        gy = fmaxf(by - ey, 0.f);
+        gz = fmaxf(bz - ez, 0.f);
+    }
     const float sep2 = gx * gx + gy * gy + gz * gz;
     return r2 > 0.f && L * L <= theta2 * r2 && sep2 >= eps2;
 }
@@ -237,26 +271,41 @@ struct ForwardPolicy {
             a.sxy += o.a.sxy; a.sxz += o.a.sxz; a.syz += o.a.syz;
         }
     };
-    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk) {
+    template <bool kPer>
+    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk,
+                                          const WalkOut& O) {
         const double4 q = T.spos[pk];
         const float4 u = T.svf[pk];
-        S.tile[lane] = make_float4((float)(q.x - gb.cx), (float)(q.y - gb.cy), (float)(q.z - gb.cz), u.w);
+        double dx = q.x - gb.cx, dy = q.y - gb.cy, dz = q.z - gb.cz;
+        if (kPer) {
+            dx = near_img(dx, O);
+            dy = near_img(dy, O);
+            dz = near_img(dz, O);
+        }
+        S.tile[lane] = make_float4((float)dx, (float)dy, (float)dz, u.w);
         S.tile[kW + lane] = u;
         S.tidx[lane] = pk;
     }
     // The quantities of pair_interact, written as multiply-add chains into
     // the accumulators, with the m f I part of S summed once per tile.  The
     // self pair has d = 0 exactly (both sides round the same FP64 position),
-    // so it always takes the softened branch, where it is dropped.
+    // so it always takes the softened branch, where it is dropped.  Periodic:
+    // each pair is taken at its own nearest image.
+    template <bool kPer>
     __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
-                                     int k0, int ks) {
+                                     int k0, int ks, const WalkOut& O) {
         PairAcc<float> F;
         F.zero();
         float smf = 0.f;
         for (int k = k0; k < cnt; k += ks) {
             const float4 q = S.tile[k];
             const float4 u = S.tile[kW + k];
-            const float dx = q.x - t.tx, dy = q.y - t.ty, dz = q.z - t.tz;
+            float dx = q.x - t.tx, dy = q.y - t.ty, dz = q.z - t.tz;
+            if (kPer) {
+                dx = near_imgf(dx, O);
+                dy = near_imgf(dy, O);
+                dz = near_imgf(dz, O);
+            }
             const float nx = u.x - t.vx, ny = u.y - t.vy, nz = u.z - t.vz;
             const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
             float mf, mD;
@@ -293,11 +342,19 @@ struct ForwardPolicy {
         F.szz += smf;
         fold(acc.a, F);
     }
-    __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk) {
+    template <bool kPer>
+    __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk,
+                                      const WalkOut& O) {
         const double4 c = T.com[nk];
         const float4 m0 = T.mp[4 * nk], m1 = T.mp[4 * nk + 1], m2 = T.mp[4 * nk + 2], m3 = T.mp[4 * nk + 3];
         float4* d = S.tile;
-        d[lane] = make_float4((float)(c.x - gb.cx), (float)(c.y - gb.cy), (float)(c.z - gb.cz), m0.x);
+        double dx = c.x - gb.cx, dy = c.y - gb.cy, dz = c.z - gb.cz;
+        if (kPer) {   // the opening test guarantees one image for the whole node
+            dx = near_img(dx, O);
+            dy = near_img(dy, O);
+            dz = near_img(dz, O);
+        }
+        d[lane] = make_float4((float)dx, (float)dy, (float)dz, m0.x);
         d[kW + lane] = make_float4(m0.y, m0.z, m0.w, m1.x);       // u, Qxx
         d[2 * kW + lane] = make_float4(m1.y, m1.z, m1.w, m2.x);   // Qyy Qzz Qxy Qxz
         d[3 * kW + lane] = make_float4(m2.y, m2.z, m2.w, m3.x);   // Qyz, Qd xx yy zz
@@ -356,15 +413,19 @@ struct AdjointPolicy {
         __device__ void zero() { vx = vy = vz = s = 0.0; }
         __device__ void add(const Acc& o) { vx += o.vx; vy += o.vy; vz += o.vz; s += o.s; }
     };
-    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk) {
+    template <bool kPer>
+    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk,
+                                          const WalkOut&) {
+        static_assert(!kPer, "the adjoint walk has no periodic form");
         const double4 q = T.spos[pk];
         const double4 w = T.ws[pk];
         S.tile[lane] = make_float4((float)(q.x - gb.cx), (float)(q.y - gb.cy), (float)(q.z - gb.cz), 0.f);
         S.tile[kW + lane] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.f);
         S.tidx[lane] = pk;
     }
+    template <bool kPer>
     __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
-                                     int k0, int ks) {
+                                     int k0, int ks, const WalkOut&) {
         AdjAccF F{0.f, 0.f, 0.f, 0.f};
         for (int k = k0; k < cnt; k += ks) {
             const float4 q = S.tile[k];
@@ -392,7 +453,8 @@ struct AdjointPolicy {
         }
         acc.vx += F.vx; acc.vy += F.vy; acc.vz += F.vz; acc.s += F.s;
     }
-    __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk) {
+    template <bool kPer>
+    __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk, const WalkOut&) {
         const double4 c = T.com[nk];
         float4* d = S.tile;
         d[lane] = make_float4((float)(c.x - gb.cx), (float)(c.y - gb.cy), (float)(c.z - gb.cz), 0.f);
@@ -482,7 +544,7 @@ struct AdjointPolicy {
 };
 
 // Walk the tree for one group of targets (one wave).
-template <class Pol>
+template <class Pol, bool kPer>
 __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, const Groups& Gr, const WalkOut& O,
                                            const int4 gd, float theta2, float eps2, float h2, float hinv) {
     const int lane = threadIdx.x;
@@ -527,14 +589,14 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     int npend = 0, ppend = 0;    // list fills (uniform)
 
     auto flush_particles = [&](int base, int cnt) {
-        if (lane < cnt) Pol::stage_particle(S, T, gb, lane, S.plist[base + lane]);
+        if (lane < cnt) Pol::template stage_particle<kPer>(S, T, gb, lane, S.plist[base + lane], O);
         __syncthreads();
-        Pol::particles(S, cnt, tg, acc, h2, hinv, part, sub);
+        Pol::template particles<kPer>(S, cnt, tg, acc, h2, hinv, part, sub, O);
         n_pp += (uint64_t)cnt;
         __syncthreads();
     };
     auto flush_nodes = [&](int base, int cnt) {
-        if (lane < cnt) Pol::stage_node(S, T, gb, lane, S.nlist[base + lane]);
+        if (lane < cnt) Pol::template stage_node<kPer>(S, T, gb, lane, S.nlist[base + lane], O);
         __syncthreads();
         Pol::nodes(S, cnt, tg, acc, part, sub);
         n_pn += (uint64_t)cnt;
@@ -580,7 +642,8 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
             if (Pol::kSkipEmpty && T.wf[8 * a].w == 0.f) {
                 ca = L.x;                  // no charge below this node
             } else {
-                const bool acc_ok = mac_accept(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2, O.mac_offset);
+                const bool acc_ok =
+                    mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2, O.mac_offset, O);
                 if (acc_ok && L.z > O.small_node) {
                     push_node = a;
                     ca = L.x;
@@ -678,7 +741,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
 // from the other queues when its own runs dry.  The register budget is held
 // to 128 VGPRs (four waves per SIMD); the few values this spills live
 // outside the interaction loops.
-template <class Pol>
+template <class Pol, bool kPer>
 __global__ void __launch_bounds__(kW, 4) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
                                              float theta2, float eps2, float h2, float hinv) {
     __shared__ typename Pol::Lds S;
@@ -706,7 +769,7 @@ __global__ void __launch_bounds__(kW, 4) k_walk(Tree T, Groups Gr, WalkOut O, in
         const int g = s_g;
         __syncthreads();
         if (g < 0) break;
-        walk_group<Pol>(S, T, Gr, O, Gr.grp[g], theta2, eps2, h2, hinv);
+        walk_group<Pol, kPer>(S, T, Gr, O, Gr.grp[g], theta2, eps2, h2, hinv);
         __syncthreads();
     }
 }
@@ -1056,6 +1119,12 @@ static WalkOut make_out(ag_ctx* c, double G) {
     O.iter_cap = c->max_nodes + c->n + 1024;
     O.small_node = c->small_node;
     O.mac_offset = c->mac_offset != 0;
+    O.box = c->box;
+    O.box_inv = c->box > 0.0 ? 1.0 / c->box : 0.0;
+    O.boxf = (float)O.box;
+    O.boxf_inv = (float)O.box_inv;
+    // a margin of a few float ulps keeps every accepted node clear of the cut
+    O.box_half = (float)(0.5 * c->box * (1.0 - 1e-5));
     return O;
 }
 
@@ -1073,8 +1142,14 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
     const float e2 = (float)(eps * eps);
     {
         PhaseScope phase(c, AG_PHASE_WALK);
-        hipLaunchKernelGGL(k_walk<ForwardPolicy>, dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, c->stream,
-                           make_tree(c), Gr, O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2, (float)(1.0 / eps));
+        if (c->box > 0.0)
+            hipLaunchKernelGGL((k_walk<ForwardPolicy, true>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0,
+                               c->stream, make_tree(c), Gr, O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2,
+                               (float)(1.0 / eps));
+        else
+            hipLaunchKernelGGL((k_walk<ForwardPolicy, false>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0,
+                               c->stream, make_tree(c), Gr, O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2,
+                               (float)(1.0 / eps));
     }
     return AG_OK;
 }
@@ -1122,7 +1197,8 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
     O.tin = tin;
     const float th = (float)theta;
     const float e2 = (float)(eps * eps);
-    hipLaunchKernelGGL(k_walk<AdjointPolicy>, dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, st, make_tree(c), Gr,
+    hipLaunchKernelGGL((k_walk<AdjointPolicy, false>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, st,
+                       make_tree(c), Gr,
                        O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2, (float)(1.0 / eps));
     return AG_OK;
 }

@@ -11,7 +11,8 @@ collapse, Zeldovich pancake, the GMC) need hydro initial conditions that are
 not available; these synthetic particle sets stand in for them with the
 density structures the method is exercised on: a centrally concentrated
 sphere, a uniform sphere with a turbulent velocity field, a clustered field
-of clumps, and many independent small systems.
+of clumps, many independent small systems, and a periodic box with one
+collapsing plane-wave mode (the pancake geometry).
 """
 from __future__ import annotations
 
@@ -135,6 +136,28 @@ def clumps(n, seed=3, nclump=64):
     v = np.concatenate(vs)
     m = np.full(n, 1.0 / n)
     return x, v, m, np.concatenate(ids)
+
+
+def zeldovich_box(n_side, seed=6, box=1.0, growth=0.9, jitter=1e-3):
+    """Periodic cube of side ``box`` holding an n_side^3 lattice displaced by
+    one plane-wave mode along x (the Zeldovich approximation): for lattice
+    points q, x = q - growth (box / 2 pi) sin(2 pi q_x / box), which first
+    crosses (a caustic) at growth = 1; velocities along the displacement,
+    v_x = -(box / 2 pi) sin(2 pi q_x / box).  A Gaussian jitter of
+    ``jitter`` lattice spacings (rms per axis) breaks the lattice symmetry.
+    Positions are returned inside [0, box); equal masses 1/n."""
+    rng = np.random.default_rng(seed)
+    g = (np.arange(n_side) + 0.5) * (box / n_side)
+    q = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    s = np.sin(2.0 * np.pi * q[:, 0] / box) * (box / (2.0 * np.pi))
+    x = q.copy()
+    x[:, 0] -= growth * s
+    x += rng.normal(0.0, jitter * box / n_side, x.shape)
+    x = np.mod(x, box)
+    v = np.zeros_like(x)
+    v[:, 0] = -s
+    n = len(x)
+    return x, v, np.full(n, 1.0 / n)
 
 
 def batched_plummer(nsys=256, seed=4, nmin=1024, nmax=65536, sigma=0.4):
