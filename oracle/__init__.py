@@ -66,6 +66,8 @@ def _load():
         lib.orc_field_box.argtypes = [I64, P, P, P, D, D, D, I64, P, P, P, P, P, P]
         lib.orc_direct_box.argtypes = [I64, P, P, P, D, D, D, I64, P, P, P, P]
         lib.orc_abs_scale_box.argtypes = [I64, P, P, D, D, D, I64, P, P]
+        lib.orc_ewald_unit.argtypes = [I64, P, D, D, ctypes.c_int, ctypes.c_int, P, P, P, P]
+        lib.orc_direct_ewald.argtypes = [I64, P, P, P, D, D, D, I64, P, P, P, P]
         lib.orc_timestep.argtypes = [I64, P, D, D, ctypes.c_int32, P, P]
         lib.orc_select.argtypes = [I64, P, P, I64, ctypes.c_int32, D, P]
         lib.orc_select.restype = I64
@@ -126,9 +128,10 @@ def field(x, v, m, eps, G, p, pv=None, excl=None, box=0.0):
     return acc, jerk, tid
 
 
-def direct(x, v, m, eps, G, targets=None, box=0.0):
+def direct(x, v, m, eps, G, targets=None, box=0.0, ewald=False):
     """Direct sum at particles ``targets`` (default: all), self excluded;
-    box > 0: nearest periodic images."""
+    box > 0: nearest periodic images; with ``ewald`` also the periodic
+    images' (Ewald) correction of g and T (the jerk stays nearest-image)."""
     x = _f64(x, (-1, 3))
     v = _f64(v, (-1, 3))
     m = _f64(m).ravel()
@@ -139,9 +142,28 @@ def direct(x, v, m, eps, G, targets=None, box=0.0):
     acc = np.empty((k, 3))
     jerk = np.empty((k, 3))
     tid = np.empty((k, 6))
-    _load().orc_direct_box(n, _ptr(x), _ptr(v), _ptr(m), float(eps), float(G), float(box), k,
-                           _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(tid))
+    if ewald:
+        if not box > 0:
+            raise ValueError("Ewald sums need a periodic box")
+        _load().orc_direct_ewald(n, _ptr(x), _ptr(v), _ptr(m), float(eps), float(G), float(box), k,
+                                 _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(tid))
+    else:
+        _load().orc_direct_box(n, _ptr(x), _ptr(v), _ptr(m), float(eps), float(G), float(box), k,
+                               _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(tid))
     return acc, jerk, tid
+
+
+def ewald_unit(d, L, alpha=None, nr=3, nk=4):
+    """Periodic (Ewald) field of a unit mass at separations ``d`` (k x 3) in a
+    cube of side L: returns g, T and the corrections dg, dT to the single
+    image d (T as xx yy zz xy xz yz)."""
+    d = _f64(d, (-1, 3))
+    k = d.shape[0]
+    g, dg = np.empty((k, 3)), np.empty((k, 3))
+    T, dT = np.empty((k, 6)), np.empty((k, 6))
+    a = 2.0 / L if alpha is None else float(alpha)
+    _load().orc_ewald_unit(k, _ptr(d), float(L), a, int(nr), int(nk), _ptr(g), _ptr(T), _ptr(dg), _ptr(dT))
+    return g, T, dg, dT
 
 
 def abs_scale(x, m, eps, G, targets=None, box=0.0):

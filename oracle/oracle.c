@@ -218,6 +218,173 @@ void orc_abs_scale(int64_t n, const double *x, const double *m, double eps, doub
     orc_abs_scale_box(n, x, m, eps, G, 0.0, ntgt, tgt, scale);
 }
 
+/* ---- Ewald summation in a periodic cube ----------------------------------- */
+#define ORC_PI 3.14159265358979323846
+/*
+ * Field of a unit mass (G = 1) and all its periodic images in a cube of side
+ * L, with a uniform neutralising background (the k = 0 mode removed), at
+ * separation d = x_source - x_target, split with parameter alpha:
+ *   g(d) = sum_n B(|d_n|) d_n
+ *          + (4 pi / L^3) sum_{k != 0} k / k^2 exp(-k^2 / (4 alpha^2)) sin(k.d),
+ *   d_n = d + n L,  B(r) = erfc(alpha r) / r^3 + (2 alpha / sqrt(pi)) exp(-alpha^2 r^2) / r^2,
+ *   T(d) = dg / dx_target = -grad_d g
+ *        = -sum_n [B I + (B'(r) / r) d_n d_n^T]
+ *          - (4 pi / L^3) sum_{k != 0} k k^T / k^2 exp(-k^2 / (4 alpha^2)) cos(k.d),
+ *   B'(r) = -3 erfc(alpha r) / r^4 - (2 alpha / sqrt(pi)) exp(-alpha^2 r^2) (3 / r^3 + 2 alpha^2 / r),
+ * over images |n_a| <= nr and wave vectors k = 2 pi h / L, |h_a| <= nk.
+ * The correction is what the periodic field adds to the Newtonian field of
+ * the single image d:  dg = g - d / r^3,  dT = T + (I / r^3 - 3 d d^T / r^5).
+ * In the n = 0 term the Newtonian part is subtracted analytically: with
+ * z = alpha r, h(r) = B(r) - 1/r^3 has the series
+ *   h = (2 / sqrt(pi)) sum_{k >= 1} (-1)^k 2k / ((2k + 1) k!) alpha^(2k+1) r^(2k-2),
+ * used for z < 0.5 (the closed form loses digits to cancellation there), so
+ * the correction is exact to rounding down to d = 0, where dg = 0 and dT is
+ * the background's tide.
+ */
+static void ewald_h(double r, double alpha, double *h, double *hp_r)
+{
+    const double sp = 2.0 / sqrt(ORC_PI);
+    const double z = alpha * r;
+    if (z < 0.5) {
+        /* h = sp sum_{k>=1} c_k r^(2k-2) and h'(r)/r = sp sum_{k>=2} c_k (2k-2) r^(2k-4),
+         * c_k = (-1)^k 2k / ((2k+1) k!) alpha^(2k+1); terms fall like z^(2k) / k! */
+        double sh = 0.0, shp = 0.0;
+        double ak = alpha * alpha * alpha;   /* alpha^(2k+1) */
+        double fact = 1.0;                   /* k! */
+        double rp = 1.0;                     /* r^(2k-2) */
+        double rq = 1.0;                     /* r^(2k-4), from k = 2 */
+        for (int k = 1; k <= 30; ++k) {
+            if (k > 1) {
+                ak *= alpha * alpha;
+                fact *= k;
+                rp *= r * r;
+            }
+            if (k > 2) rq *= r * r;
+            const double c = ((k & 1) ? -1.0 : 1.0) * (2.0 * k) / ((2.0 * k + 1.0) * fact) * ak;
+            sh += c * rp;
+            if (k >= 2) shp += c * (2.0 * k - 2.0) * rq;
+        }
+        *h = sp * sh;
+        *hp_r = sp * shp;
+        return;
+    }
+    const double e = exp(-z * z);
+    const double ec = erfc(z);
+    const double r2 = r * r, r3 = r2 * r;
+    const double B = ec / r3 + sp * alpha * e / r2;
+    const double Bp = -3.0 * ec / (r2 * r2) - sp * alpha * e * (3.0 / r3 + 2.0 * alpha * alpha / r);
+    *h = B - 1.0 / r3;
+    *hp_r = (Bp + 3.0 / (r2 * r2)) / r;
+}
+
+/* Periodic field g, T of a unit mass at separation d and its correction dg,
+ * dT to the single image (see above).  T and dT in xx yy zz xy xz yz order. */
+static void ewald_unit(const double d[3], double L, double alpha, int nr, int nk,
+                       double g[3], double T[6], double dg[3], double dT[6])
+{
+    const double sp = 2.0 / sqrt(ORC_PI);
+    double gs[3] = {0, 0, 0}, ts[6] = {0, 0, 0, 0, 0, 0};
+    for (int a = -nr; a <= nr; ++a)
+        for (int b = -nr; b <= nr; ++b)
+            for (int c = -nr; c <= nr; ++c) {
+                const double y[3] = {d[0] + a * L, d[1] + b * L, d[2] + c * L};
+                const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+                double Bv, Bp_r;
+                if (a == 0 && b == 0 && c == 0) {
+                    /* the single image itself, Newtonian part removed */
+                    ewald_h(r, alpha, &Bv, &Bp_r);
+                } else {
+                    const double z = alpha * r, e = exp(-z * z), ec = erfc(z);
+                    const double r2 = r * r, r3 = r2 * r;
+                    Bv = ec / r3 + sp * alpha * e / r2;
+                    Bp_r = (-3.0 * ec / (r2 * r2) - sp * alpha * e * (3.0 / r3 + 2.0 * alpha * alpha / r)) / r;
+                }
+                for (int q = 0; q < 3; ++q) gs[q] += Bv * y[q];
+                ts[0] -= Bv + Bp_r * y[0] * y[0];
+                ts[1] -= Bv + Bp_r * y[1] * y[1];
+                ts[2] -= Bv + Bp_r * y[2] * y[2];
+                ts[3] -= Bp_r * y[0] * y[1];
+                ts[4] -= Bp_r * y[0] * y[2];
+                ts[5] -= Bp_r * y[1] * y[2];
+            }
+    const double pre = 4.0 * ORC_PI / (L * L * L);
+    const double kf = 2.0 * ORC_PI / L;
+    for (int a = -nk; a <= nk; ++a)
+        for (int b = -nk; b <= nk; ++b)
+            for (int c = -nk; c <= nk; ++c) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                const double k[3] = {kf * a, kf * b, kf * c};
+                const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                const double w = pre * exp(-k2 / (4.0 * alpha * alpha)) / k2;
+                const double ph = k[0] * d[0] + k[1] * d[1] + k[2] * d[2];
+                const double sn = sin(ph), cs = cos(ph);
+                for (int q = 0; q < 3; ++q) gs[q] += w * k[q] * sn;
+                ts[0] -= w * k[0] * k[0] * cs;
+                ts[1] -= w * k[1] * k[1] * cs;
+                ts[2] -= w * k[2] * k[2] * cs;
+                ts[3] -= w * k[0] * k[1] * cs;
+                ts[4] -= w * k[0] * k[2] * cs;
+                ts[5] -= w * k[1] * k[2] * cs;
+            }
+    /* gs, ts hold the correction (n = 0 entered without its Newtonian part) */
+    for (int q = 0; q < 3; ++q) dg[q] = gs[q];
+    for (int q = 0; q < 6; ++q) dT[q] = ts[q];
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (r > 0) {
+        const double r3 = r * r * r, r5 = r3 * r * r;
+        for (int q = 0; q < 3; ++q) g[q] = dg[q] + d[q] / r3;
+        T[0] = dT[0] - (1.0 / r3 - 3.0 * d[0] * d[0] / r5);
+        T[1] = dT[1] - (1.0 / r3 - 3.0 * d[1] * d[1] / r5);
+        T[2] = dT[2] - (1.0 / r3 - 3.0 * d[2] * d[2] / r5);
+        T[3] = dT[3] + 3.0 * d[0] * d[1] / r5;
+        T[4] = dT[4] + 3.0 * d[0] * d[2] / r5;
+        T[5] = dT[5] + 3.0 * d[1] * d[2] / r5;
+    } else {
+        for (int q = 0; q < 3; ++q) g[q] = NAN;
+        for (int q = 0; q < 6; ++q) T[q] = NAN;
+    }
+}
+
+void orc_ewald_unit(int64_t n, const double *d, double L, double alpha, int nr, int nk,
+                    double *g, double *T, double *dg, double *dT)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        ewald_unit(d + 3 * i, L, alpha, nr, nk, g + 3 * i, T + 6 * i, dg + 3 * i, dT + 6 * i);
+}
+
+/* Periodic direct sum with Ewald's method for g and T (the jerk keeps the
+ * nearest image only, as Sec. 4 states for its periodic problem):
+ *   g_i = G sum_{j != i} m_j f(r) d_ij  +  G sum_j m_j dg(d_ij),
+ *   T_i = (nearest-image T)             +  G sum_j m_j dT(d_ij),
+ * d_ij the nearest image; the softened single-image terms as in
+ * orc_direct_box; the correction sums include j = i (dg(0) = 0, dT(0) the
+ * tide of the background that neutralises particle i's own images).
+ * alpha = 2 / L, images |n_a| <= 3, wave vectors |h_a| <= 4 (omitted terms
+ * below 1e-20 of the kept ones). */
+void orc_direct_ewald(int64_t n, const double *x, const double *v, const double *m,
+                      double eps, double G, double box, int64_t ntgt, const int64_t *tgt,
+                      double *acc, double *jerk, double *tidal)
+{
+    orc_direct_box(n, x, v, m, eps, G, box, ntgt, tgt, acc, jerk, tidal);
+    const double alpha = 2.0 / box;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < ntgt; ++k) {
+        const int64_t i = tgt[k];
+        double sg[3] = {0, 0, 0}, st[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            double d[3];
+            for (int q = 0; q < 3; ++q) d[q] = nearest_image(x[3 * j + q] - x[3 * i + q], box);
+            double g[3], T[6], dg[3], dT[6];
+            ewald_unit(d, box, alpha, 3, 4, g, T, dg, dT);
+            for (int q = 0; q < 3; ++q) sg[q] += m[j] * dg[q];
+            for (int q = 0; q < 6; ++q) st[q] += m[j] * dT[q];
+        }
+        for (int q = 0; q < 3; ++q) acc[3 * k + q] += G * sg[q];
+        for (int q = 0; q < 6; ++q) tidal[6 * k + q] += G * st[q];
+    }
+}
+
 /* ---- tidal timestep (Eq. 7) and block bin --------------------------------- */
 /*
  * dt_grav = sqrt(eta) * (|T|_F^2 / 6)^(-1/4),
