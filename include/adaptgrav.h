@@ -105,23 +105,44 @@ const char *ag_last_error(void);
  *   AG_OPT_GROUP_TARGETS       most targets in one walk group (one wave walks
  *                              the tree per group; a group of k targets gives
  *                              each target min(32, 64 / k) lanes) [64]
+ *   AG_OPT_EWALD_OPEN          Ewald correction walk: a node acts as a point
+ *                              (mass and quadrupole) if its extent is at most
+ *                              1 / value times its distance to the nearest
+ *                              image point of the lattice [4]
  * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30, 0..1,
- * 1..64) give AG_EINVAL. */
+ * 1..64, 1..64) give AG_EINVAL. */
 enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3, AG_OPT_MAC_OFFSET = 4,
-       AG_OPT_GROUP_TARGETS = 5 };
+       AG_OPT_GROUP_TARGETS = 5, AG_OPT_EWALD_OPEN = 6 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
-/* Periodic boundaries (the treatment Sec. 4 gives the jerk of its periodic
- * problem): box > 0 makes every later ag_grav_eval, ag_grav_eval_batched and
- * ag_grav_direct on this context take each pair at its nearest image in a
- * cube of side box, d -> d - box * rint(d / box) per axis, for g, j and T
- * alike (no Ewald sum, so g is the nearest-image force).  Positions may lie
- * in any image.  The tree opening test then also requires, per axis, all of
- * a node's box to lie within half a box side of all of the group's box, so
- * every particle of an accepted node shares one image.  box = 0 restores
- * open boundaries (the default).  While a box is set, ag_grav_backward
- * returns AG_ESTATE.  box < 0 or not finite gives AG_EINVAL. */
-int ag_set_periodic(ag_ctx *ctx, double box);
+/* Periodic boundaries (Sec. 4: the periodic problem's gravity uses Ewald
+ * sums, its jerk only the nearest image).  box > 0 makes every later
+ * ag_grav_eval, ag_grav_eval_batched and (ewald = 0 only) ag_grav_direct on
+ * this context periodic in a cube of side box; positions may lie in any
+ * image.  Tree builds after the call hold every position in [0, box)^3;
+ * evaluating a tree built under another box gives AG_ESTATE (rebuild it).
+ *   ewald = 0: every pair at its nearest image, d -> d - box * rint(d / box)
+ *              per axis, for g, j and T alike.
+ *   ewald = 1: g and T of all periodic images with a neutralising uniform
+ *              background (Ewald's method, alpha = 2 / box), j at the
+ *              nearest image.  A second walk adds the images' correction
+ *              dg = g_periodic - g_single_image (and dT) from a table built
+ *              on the device (spacing box / 64, second-order expansion
+ *              about the nearest table point); nodes act through mass and
+ *              quadrupole under an opening angle (AG_OPT_EWALD_OPEN) taken
+ *              against the nearest image point, and a group no wider than
+ *              box / 256 sums the correction once and expands it to second
+ *              order about its centre.  The sum includes each
+ *              target's own images (its background tide, 4 pi G m / 3 box^3
+ *              per axis).  ag_grav_direct then returns AG_ESTATE (theta = 0
+ *              in ag_grav_eval is the direct sum).
+ * The tree opening test also requires, per axis, all of a node's box to lie
+ * within half a box side of all of the group's box, so every particle of an
+ * accepted node shares one image.  box = 0 (with ewald = 0) restores open
+ * boundaries, the default.  While a box is set, ag_grav_backward returns
+ * AG_ESTATE.  box < 0 or not finite, ewald not 0 or 1, or ewald with
+ * box = 0 give AG_EINVAL. */
+int ag_set_periodic(ag_ctx *ctx, double box, int32_t ewald);
 
 /* HIP-graph capture of a call sequence on the context's stream (which must
  * not be the legacy default stream).  Between ag_graph_begin and
@@ -141,9 +162,10 @@ int ag_graph_replay(ag_ctx *ctx);
  * Phases, in array order: AG_PHASE_BUILD (keys, sort, topology, moments),
  * AG_PHASE_GROUPS (active rows -> walk groups), AG_PHASE_WALK (forward
  * walk kernel only), AG_PHASE_DIRECT, AG_PHASE_STEP (timestep, select,
- * predict), AG_PHASE_ADJOINT (adjoint walk kernel only). */
+ * predict), AG_PHASE_ADJOINT (adjoint walk kernel only), AG_PHASE_EWALD
+ * (the periodic images' correction walk). */
 enum { AG_PHASE_BUILD = 0, AG_PHASE_GROUPS, AG_PHASE_WALK, AG_PHASE_DIRECT, AG_PHASE_STEP,
-       AG_PHASE_ADJOINT, AG_NPHASE };
+       AG_PHASE_ADJOINT, AG_PHASE_EWALD, AG_NPHASE };
 int ag_timing_enable(ag_ctx *ctx, int enable);
 int ag_timing_read(ag_ctx *ctx, double *ms /* [AG_NPHASE] */, int64_t *launches /* [AG_NPHASE], nullable */,
                    int reset);

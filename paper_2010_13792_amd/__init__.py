@@ -45,7 +45,8 @@ AG_OPT_SMALL_NODE = 2
 AG_OPT_GROUP_SPAN = 3
 AG_OPT_MAC_OFFSET = 4
 AG_OPT_GROUP_TARGETS = 5
-PHASES = ["build", "groups", "walk", "direct", "step", "adjoint"]
+AG_OPT_EWALD_OPEN = 6
+PHASES = ["build", "groups", "walk", "direct", "step", "adjoint", "ewald"]
 
 
 class AgError(RuntimeError):
@@ -93,7 +94,7 @@ def load_library(path: str = LIB_PATH):
         "ag_adaptive_select": [P, I64, P, P, I64, I32, D, P, P, P, D],
         "ag_kick_drift": [P, I64, P, P, P, D, D],
         "ag_set_option": [P, I32, I64],
-        "ag_set_periodic": [P, D],
+        "ag_set_periodic": [P, D, I32],
         "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
         "ag_force_log": [P, I64, P, I64, I32, P, D, P, P, P],
@@ -304,9 +305,10 @@ class Context:
                                     _ptr(t0, torch.float64, None, "t0", n), float(t),
                                     _ptr(acc_out, torch.float64, (3,), "acc_out", n)))
 
-    def set_periodic(self, box: float):
-        """Nearest-image pairs in a periodic cube of side ``box`` (0: open)."""
-        _check(_lib.ag_set_periodic(self._h, float(box)))
+    def set_periodic(self, box: float, ewald: bool = False):
+        """Periodic cube of side ``box`` (0: open): nearest-image pairs, or
+        with ``ewald`` the full periodic g and T (j stays nearest-image)."""
+        _check(_lib.ag_set_periodic(self._h, float(box), 1 if ewald else 0))
 
     @staticmethod
     def _log_ptrs(hist_a, hist_t, hist_n):

@@ -189,7 +189,7 @@ extern "C" int ag_destroy(ag_ctx* c) {
                       &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
                       &c->nd_64, &c->nd_w, &c->nd_wf, &c->in_list, &c->in_cnt, &c->in_off,
                       &c->tree_hdr, &c->lvl_list, &c->leaf_list, &c->child, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
-                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
+                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->ewald_tab, &c->ewald_q, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
                       &c->direct_part, &c->tmp_tidal, &c->sel_flag, &c->sel_off, &c->stats, &c->dflags};
     for (DevBuf* b : bufs) ag_release(*b);
     for (PhaseEvents& p : c->timing.pending) {
@@ -315,6 +315,7 @@ static int check_eval_args(ag_ctx* c, const int32_t* idx, int64_t n_act, double 
                            double G) {
     AG_TRY(check_ctx(c));
     if (!c->built) return ag_fail(AG_ESTATE, "gravity evaluation before a tree build");
+    if (c->box != c->tree_box) return ag_fail(AG_ESTATE, "the periodic box changed since the tree was built");
     if (!(eps > 0.0) || !std::isfinite(eps)) return ag_fail(AG_EINVAL, "eps must be positive and finite");
     if (!(theta >= 0.0) || !std::isfinite(theta)) return ag_fail(AG_EINVAL, "theta must be >= 0 and finite");
     if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
@@ -354,6 +355,7 @@ extern "C" int ag_grav_direct(ag_ctx* c, int64_t n, const double* x, const doubl
     if (!(eps > 0.0) || !std::isfinite(eps)) return ag_fail(AG_EINVAL, "eps must be positive and finite");
     if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
     if (precision != AG_FP64 && precision != AG_FP32_PAIRS) return ag_fail(AG_EINVAL, "unknown precision %d", precision);
+    if (c->ewald) return ag_fail(AG_ESTATE, "direct summation has no Ewald form (use ag_grav_eval with theta = 0)");
     if (n_act < 0 || n_act > n) return ag_fail(AG_EINVAL, "n_active out of range");
     if (!idx && n_act != n) return ag_fail(AG_EINVAL, "active_idx = NULL requires n_active = n");
     if (n_act == 0) return AG_OK;
@@ -426,6 +428,10 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
             if (value < 1 || value > 64) return ag_fail(AG_EINVAL, "targets per group must be in [1, 64]");
             c->group_cap = (int)value;
             return AG_OK;
+        case AG_OPT_EWALD_OPEN:
+            if (value < 1 || value > 64) return ag_fail(AG_EINVAL, "Ewald opening value must be in [1, 64]");
+            c->ewald_open = (int)value;
+            return AG_OK;
         case AG_OPT_MAC_OFFSET:
             if (value != 0 && value != 1) return ag_fail(AG_EINVAL, "opening-test offset flag must be 0 or 1");
             c->mac_offset = (int)value;
@@ -435,10 +441,13 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
     }
 }
 
-extern "C" int ag_set_periodic(ag_ctx* c, double box) {
+extern "C" int ag_set_periodic(ag_ctx* c, double box, int32_t ewald) {
     AG_TRY(check_ctx(c));
     if (!(box >= 0.0) || !std::isfinite(box)) return ag_fail(AG_EINVAL, "box must be >= 0 and finite");
+    if (ewald != 0 && ewald != 1) return ag_fail(AG_EINVAL, "ewald must be 0 or 1");
+    if (ewald && box == 0.0) return ag_fail(AG_EINVAL, "Ewald sums need a periodic box");
     c->box = box;
+    c->ewald = ewald;
     return AG_OK;
 }
 

@@ -72,6 +72,10 @@ struct ag_ctx {
     int group_span = 128;
     int mac_offset = 1;
     double box = 0.0;     // periodic cube side (0: open boundaries)
+    int ewald = 0;        // periodic: Ewald sums for g and T
+    int ewald_open = 4;   // correction walk: opening angle 1 / ewald_open against the image points
+    double ewald_tab_box = 0.0;   // box the Ewald table was built for
+    double tree_box = 0.0;        // periodic box the tree was built in (positions wrapped into it)
     int group_cap = 64;
     bool capturing = false;
     hipGraph_t graph = nullptr;
@@ -122,6 +126,8 @@ struct ag_ctx {
     DevBuf act_pos;               // i32 [n]: active sorted positions, ascending
     DevBuf act_off;               // i32 [n+1]: exclusive scan of act_flag
     DevBuf grp;                   // int4 [max groups]: start, count, system, -
+    DevBuf ewald_tab;             // f32 Ewald correction table (5 float4 per point)
+    DevBuf ewald_q;               // i32 [8]: correction walk work-queue counters
     DevBuf grp_hdr;               // i32: [0] number of groups, [8..15] walk work-queue counters
     DevBuf grp_cnt, grp_off;      // i32 [max_nodes (+1)]: groups owned per node, offsets
     DevBuf sys_act;               // i32 [n_sys + 1]

@@ -92,9 +92,16 @@ __global__ void k_build_init(int n_sys, int64_t n, const int64_t* __restrict__ i
     }
 }
 
+// A periodic tree holds every position in the primary cube [0, pbox): the
+// image is immaterial to the forces, and compact cells keep groups compact.
+__device__ __forceinline__ double in_box(double q, double pbox) {
+    return pbox > 0.0 ? q - pbox * floor(q / pbox) : q;
+}
+
 __global__ void __launch_bounds__(kThreads) k_box(const double* __restrict__ x, const int64_t* __restrict__ off,
                                                   int n_sys, const int32_t* __restrict__ blk_off,
-                                                  uint64_t* __restrict__ box, int32_t* __restrict__ flags) {
+                                                  uint64_t* __restrict__ box, int32_t* __restrict__ flags,
+                                                  double pbox) {
     __shared__ double s_red[6][kThreads / 64];
     const int b = blockIdx.x;
     if (b >= blk_off[n_sys]) return;
@@ -113,6 +120,7 @@ __global__ void __launch_bounds__(kThreads) k_box(const double* __restrict__ x, 
         for (int c = 0; c < 3; ++c) {
             double q = x[3 * i + c];
             if (!isfinite(q)) { bad = true; continue; }
+            q = in_box(q, pbox);
             mn[c] = q < mn[c] ? q : mn[c];
             mx[c] = q > mx[c] ? q : mx[c];
         }
@@ -151,7 +159,7 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
 
 __global__ void k_keys(int64_t n, const double* __restrict__ x, const int64_t* __restrict__ off, int n_sys,
                        int bits, const uint64_t* __restrict__ box, uint64_t* __restrict__ keys,
-                       int32_t* __restrict__ vals) {
+                       int32_t* __restrict__ vals, double pbox) {
     const double scale_cells = (double)(1u << bits);
     const int64_t maxc = ((int64_t)1 << bits) - 1;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -169,7 +177,7 @@ __global__ void k_keys(int64_t n, const double* __restrict__ x, const int64_t* _
         uint64_t code = 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double q = (x[3 * i + c] - lo[c]) * inv;
+            double q = (in_box(x[3 * i + c], pbox) - lo[c]) * inv;
             int64_t k = isfinite(q) ? (int64_t)q : 0;
             k = k < 0 ? 0 : (k > maxc ? maxc : k);
             code |= spread3((uint64_t)k) << (2 - c);
@@ -327,13 +335,14 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restr
 // ---------------------------------------------------------------------------
 __global__ void k_to_sorted(int64_t n, const int32_t* __restrict__ rank, const double* __restrict__ x,
                             const double* __restrict__ v, const double* __restrict__ m,
-                            double4* __restrict__ spos, double4* __restrict__ svel, float4* __restrict__ svf) {
+                            double4* __restrict__ spos, double4* __restrict__ svel, float4* __restrict__ svf,
+                            double pbox) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t p = rank[i];
         const double mi = m[i];
         const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
-        spos[p] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], mi);
+        spos[p] = make_double4(in_box(x[3 * i], pbox), in_box(x[3 * i + 1], pbox), in_box(x[3 * i + 2], pbox), mi);
         svel[p] = make_double4(vx, vy, vz, 0.0);
         svf[p] = make_float4((float)vx, (float)vy, (float)vz, (float)mi);
     }
@@ -1033,14 +1042,15 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     hipLaunchKernelGGL(k_build_init, dim3(1), dim3(512), 0, st, n_sys, n, sys_offsets, off, flags, box, blk_off, hdr,
                        (int)(kTreeHdrBytes / 8));
     const int64_t box_blocks = n / kBoxChunk + n_sys + 1;
-    hipLaunchKernelGGL(k_box, dim3((unsigned)box_blocks), dim3(kThreads), 0, st, x, off, n_sys, blk_off, box, flags);
+    hipLaunchKernelGGL(k_box, dim3((unsigned)box_blocks), dim3(kThreads), 0, st, x, off, n_sys, blk_off, box, flags,
+                       c->box);
 
     // 2. keys
     uint64_t* k0 = c->keys[0].as<uint64_t>();
     uint64_t* k1 = c->keys[1].as<uint64_t>();
     int32_t* v0 = c->vals[0].as<int32_t>();
     int32_t* v1 = c->vals[1].as<int32_t>();
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kThreads), 0, st, n, x, off, n_sys, bits, box, k0, v0);
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kThreads), 0, st, n, x, off, n_sys, bits, box, k0, v0, c->box);
 
     // 3. sort: four passes over bits 31..62 (the last writes the permutation
     //    and its inverse), then the level-10 cells holding more than n_leaf
@@ -1076,7 +1086,8 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
 
     // 4. particle data into key order
     hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rank, x, v, m,
-                       c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
+                       c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->box);
+    c->tree_box = c->box;
 
     // 5. topology
     int32_t* cd = c->cdig.as<int32_t>();
@@ -1113,6 +1124,6 @@ int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m
     const int64_t n = c->n;
     PhaseScope phase(c, AG_PHASE_BUILD);
     hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, c->rank.as<int32_t>(), x,
-                       v, m, c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>());
+                       v, m, c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->tree_box);
     return moments_pass(c);
 }

@@ -33,6 +33,11 @@ constexpr int kPCap = 256;      // pending particle indices
 constexpr int kNCap = 128;      // pending accepted nodes
 constexpr int kSCap = 128;      // stacked cursor ranges
 constexpr int kMaxSub = 32;     // most lanes given to one target of a small group
+// boundary modes of a walk instance
+constexpr int kOpen = 0;        // open boundaries
+constexpr int kNear = 1;        // periodic, every pair at its nearest image
+constexpr int kEwald = 2;       // periodic with Ewald sums: g and T at the images about the group
+                                // centre (the correction walk uses the same ones), j at the nearest
 
 // algorithmic operation count of one particle-particle interaction as written
 // in ForwardPolicy::particles (outside the softening kernel; every add,
@@ -80,6 +85,13 @@ struct WalkOut {
     bool mac_offset;    // opening test adds the centre-of-mass offset to the extent
     double box, box_inv;        // periodic cube side and inverse (periodic walks only)
     float boxf, boxf_inv, box_half;
+    // Ewald correction table: (NE + 1)^3 points of spacing h over [0, NE h]^3,
+    // 5 float4 each (dg 3, dT 6, H 10, pad), and the correction walk's limits
+    const float4* etab;
+    float etab_h, etab_hinv, etab_range;
+    int etab_ne;
+    float ewald_theta;  // correction walk: opening angle against the nearest image point
+    float ewald_grp;    // groups of at most this half extent sum the correction once
     double* dldx;       // adjoint outputs
     double* dldm;
     const double* tin;  // adjoint: tidal tensor rows of the charged targets
@@ -126,11 +138,11 @@ __device__ __forceinline__ float near_imgf(float d, const WalkOut& O) {
 // with `offset` set, the distance from its centre of mass to the centre of
 // its box, which opens lopsided nodes sooner)  and the node's box is at least
 // eps away from the group box (so only Newtonian pairs are approximated).
-// Periodic (kPer): distances are taken at the nearest image of the node, and
+// Periodic (kPer != 0): distances are taken at the nearest image of the node, and
 // a node is accepted only if, along every axis, all of its box lies within
 // half a box side of all of the group box -- then every particle-target pair
 // of the node has that same nearest image, and the multipole stands for it.
-template <bool kPer>
+template <int kPer>
 __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
                                            float theta2, float eps2, bool offset, const WalkOut& O) {
     double cdx = c.x - g.cx, cdy = c.y - g.cy, cdz = c.z - g.cz;
@@ -255,11 +267,14 @@ struct Target {
     float tx, ty, tz;      // position relative to the group centre
     float vx, vy, vz;
     int p;                 // sorted position
+    bool grp;              // Ewald correction summed once for the whole group
 };
 
 // ---- forward: g, j and S = -T from particle masses and node multipoles ----
 struct ForwardPolicy {
     static constexpr bool kSkipEmpty = false;
+    static constexpr bool kImageMac = false;
+    static constexpr bool kGroupSum = false;
     using Lds = WalkLds<5>;
     struct Acc {
         PairAcc<double> a;
@@ -271,7 +286,7 @@ struct ForwardPolicy {
             a.sxy += o.a.sxy; a.sxz += o.a.sxz; a.syz += o.a.syz;
         }
     };
-    template <bool kPer>
+    template <int kPer>
     __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk,
                                           const WalkOut& O) {
         const double4 q = T.spos[pk];
@@ -291,7 +306,7 @@ struct ForwardPolicy {
     // self pair has d = 0 exactly (both sides round the same FP64 position),
     // so it always takes the softened branch, where it is dropped.  Periodic:
     // each pair is taken at its own nearest image.
-    template <bool kPer>
+    template <int kPer>
     __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
                                      int k0, int ks, const WalkOut& O) {
         PairAcc<float> F;
@@ -301,7 +316,7 @@ struct ForwardPolicy {
             const float4 q = S.tile[k];
             const float4 u = S.tile[kW + k];
             float dx = q.x - t.tx, dy = q.y - t.ty, dz = q.z - t.tz;
-            if (kPer) {
+            if (kPer == kNear) {
                 dx = near_imgf(dx, O);
                 dy = near_imgf(dy, O);
                 dz = near_imgf(dz, O);
@@ -324,10 +339,26 @@ struct ForwardPolicy {
             F.ax = __builtin_fmaf(mf, dx, F.ax);
             F.ay = __builtin_fmaf(mf, dy, F.ay);
             F.az = __builtin_fmaf(mf, dz, F.az);
-            const float sd = mD * __builtin_fmaf(dz, nz, __builtin_fmaf(dy, ny, dx * nx));
-            F.jx = __builtin_fmaf(sd, dx, __builtin_fmaf(mf, nx, F.jx));
-            F.jy = __builtin_fmaf(sd, dy, __builtin_fmaf(mf, ny, F.jy));
-            F.jz = __builtin_fmaf(sd, dz, __builtin_fmaf(mf, nz, F.jz));
+            float jdx = dx, jdy = dy, jdz = dz, jmf = mf, jmD = mD;
+            if (kPer == kEwald) {
+                // g and T take the image about the group centre (the Ewald
+                // correction is summed at the same one); the jerk keeps the
+                // pair's nearest image, which differs only across the cut
+                const float ex = near_imgf(dx, O), ey = near_imgf(dy, O), ez = near_imgf(dz, O);
+                if (ex != dx || ey != dy || ez != dz) {
+                    const float r2e = __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex));
+                    const float ri = __builtin_amdgcn_rsqf(r2e);
+                    jmf = q.w * (ri * ri * ri);
+                    jmD = -3.f * jmf * (ri * ri);
+                    jdx = ex;
+                    jdy = ey;
+                    jdz = ez;
+                }
+            }
+            const float sd = jmD * __builtin_fmaf(jdz, nz, __builtin_fmaf(jdy, ny, jdx * nx));
+            F.jx = __builtin_fmaf(sd, jdx, __builtin_fmaf(jmf, nx, F.jx));
+            F.jy = __builtin_fmaf(sd, jdy, __builtin_fmaf(jmf, ny, F.jy));
+            F.jz = __builtin_fmaf(sd, jdz, __builtin_fmaf(jmf, nz, F.jz));
             const float tx = mD * dx, ty = mD * dy, tz = mD * dz;
             smf += mf;
             F.sxx = __builtin_fmaf(tx, dx, F.sxx);
@@ -342,7 +373,7 @@ struct ForwardPolicy {
         F.szz += smf;
         fold(acc.a, F);
     }
-    template <bool kPer>
+    template <int kPer>
     __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk,
                                       const WalkOut& O) {
         const double4 c = T.com[nk];
@@ -360,7 +391,7 @@ struct ForwardPolicy {
         d[3 * kW + lane] = make_float4(m2.y, m2.z, m2.w, m3.x);   // Qyz, Qd xx yy zz
         d[4 * kW + lane] = make_float4(m3.y, m3.z, m3.w, 0.f);    // Qd xy xz yz
     }
-    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks) {
+    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks, const WalkOut&) {
         PairAcc<float> F;
         F.zero();
         float sca = 0.f;
@@ -377,7 +408,8 @@ struct ForwardPolicy {
         F.szz += sca;
         fold(acc.a, F);
     }
-    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p) {
+    static __device__ void wave_sum(Acc&) {}
+    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
         const PairAcc<double>& acc = A.a;
         const int64_t i = T.perm[p];
         const double G = O.G;
@@ -407,13 +439,15 @@ struct AdjAccF {
 };
 struct AdjointPolicy {
     static constexpr bool kSkipEmpty = true;   // nodes without charge add nothing
+    static constexpr bool kImageMac = false;
+    static constexpr bool kGroupSum = false;
     using Lds = WalkLds<9>;
     struct Acc {
         double vx, vy, vz, s;
         __device__ void zero() { vx = vy = vz = s = 0.0; }
         __device__ void add(const Acc& o) { vx += o.vx; vy += o.vy; vz += o.vz; s += o.s; }
     };
-    template <bool kPer>
+    template <int kPer>
     __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk,
                                           const WalkOut&) {
         static_assert(!kPer, "the adjoint walk has no periodic form");
@@ -423,7 +457,7 @@ struct AdjointPolicy {
         S.tile[kW + lane] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.f);
         S.tidx[lane] = pk;
     }
-    template <bool kPer>
+    template <int kPer>
     __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
                                      int k0, int ks, const WalkOut&) {
         AdjAccF F{0.f, 0.f, 0.f, 0.f};
@@ -453,7 +487,7 @@ struct AdjointPolicy {
         }
         acc.vx += F.vx; acc.vy += F.vy; acc.vz += F.vz; acc.s += F.s;
     }
-    template <bool kPer>
+    template <int kPer>
     __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk, const WalkOut&) {
         const double4 c = T.com[nk];
         float4* d = S.tile;
@@ -467,7 +501,7 @@ struct AdjointPolicy {
     //   s += 7.5 t/r^7 - 1.5 (d.trW + 2 d.trX)/r^5
     // u_b = W2_bce d_c d_e, s_e = W2_bce d_b d_c, t = d.u, trW_b = W2_bcc,
     // trX_c = W2_bbc.
-    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks) {
+    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks, const WalkOut&) {
         AdjAccF F{0.f, 0.f, 0.f, 0.f};
         const float4* d = S.tile;
         for (int k = k0; k < cnt; k += ks) {
@@ -524,7 +558,8 @@ struct AdjointPolicy {
         }
         acc.vx += F.vx; acc.vy += F.vy; acc.vz += F.vz; acc.s += F.s;
     }
-    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p) {
+    static __device__ void wave_sum(Acc&) {}
+    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
         const int64_t i = T.perm[p];
         const double G = O.G;
         const double mi = T.spos[p].w;
@@ -544,7 +579,259 @@ struct AdjointPolicy {
 };
 
 // Walk the tree for one group of targets (one wave).
-template <class Pol, bool kPer>
+// ---- Ewald correction: what the periodic images add to g and T ----------
+// Table lookup of the correction field of a unit mass at separation d
+// (source - target): the nearest table point p of |d| (octant [0, range]^3,
+// the field's symmetry supplies the signs) and its second-order expansion
+//   dg(p + u) = dg - dT u - 1/2 H u u,   dT(p + u) = dT + H u,
+// with H_abc = d dT_ab / d d_c (totally symmetric), tabulated exactly.
+struct EwaldVal {
+    float g[3];
+    float t[6];    // xx yy zz xy xz yz
+    float h[10];   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+};
+
+template <bool kWithH>
+__device__ __forceinline__ void ewald_lookup(const WalkOut& O, float dx, float dy, float dz, EwaldVal& E) {
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    if (ax > O.etab_range || ay > O.etab_range || az > O.etab_range) atomicOr(O.flags, AGF_INTERNAL);
+    const int ne = O.etab_ne;
+    int ix = (int)(ax * O.etab_hinv + 0.5f), iy = (int)(ay * O.etab_hinv + 0.5f), iz = (int)(az * O.etab_hinv + 0.5f);
+    ix = ix < ne ? ix : ne;
+    iy = iy < ne ? iy : ne;
+    iz = iz < ne ? iz : ne;
+    const float ux = ax - ix * O.etab_h, uy = ay - iy * O.etab_h, uz = az - iz * O.etab_h;
+    const float4* q = O.etab + 5 * (((int64_t)ix * (ne + 1) + iy) * (ne + 1) + iz);
+    const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
+    const float Txx = a.w, Tyy = b.x, Tzz = b.y, Txy = b.z, Txz = b.w, Tyz = c.x;
+    const float Hxxx = c.y, Hxxy = c.z, Hxxz = c.w, Hxyy = d.x, Hxyz = d.y, Hxzz = d.z;
+    const float Hyyy = d.w, Hyyz = e.x, Hyzz = e.y, Hzzz = e.z;
+    // (H u)_ab
+    const float Pxx = Hxxx * ux + Hxxy * uy + Hxxz * uz;
+    const float Pyy = Hxyy * ux + Hyyy * uy + Hyyz * uz;
+    const float Pzz = Hxzz * ux + Hyzz * uy + Hzzz * uz;
+    const float Pxy = Hxxy * ux + Hxyy * uy + Hxyz * uz;
+    const float Pxz = Hxxz * ux + Hxyz * uy + Hxzz * uz;
+    const float Pyz = Hxyz * ux + Hyyz * uy + Hyzz * uz;
+    // dg - (dT + 1/2 H u) u
+    const float gx = a.x - ((Txx + 0.5f * Pxx) * ux + (Txy + 0.5f * Pxy) * uy + (Txz + 0.5f * Pxz) * uz);
+    const float gy = a.y - ((Txy + 0.5f * Pxy) * ux + (Tyy + 0.5f * Pyy) * uy + (Tyz + 0.5f * Pyz) * uz);
+    const float gz = a.z - ((Txz + 0.5f * Pxz) * ux + (Tyz + 0.5f * Pyz) * uy + (Tzz + 0.5f * Pzz) * uz);
+    const float sx = dx < 0.f ? -1.f : 1.f, sy = dy < 0.f ? -1.f : 1.f, sz = dz < 0.f ? -1.f : 1.f;
+    E.g[0] = sx * gx;
+    E.g[1] = sy * gy;
+    E.g[2] = sz * gz;
+    E.t[0] = Txx + Pxx;
+    E.t[1] = Tyy + Pyy;
+    E.t[2] = Tzz + Pzz;
+    E.t[3] = sx * sy * (Txy + Pxy);
+    E.t[4] = sx * sz * (Txz + Pxz);
+    E.t[5] = sy * sz * (Tyz + Pyz);
+    if (kWithH) {
+        E.h[0] = sx * Hxxx; E.h[1] = sy * Hxxy; E.h[2] = sz * Hxxz;
+        E.h[3] = sx * Hxyy; E.h[4] = sx * sy * sz * Hxyz; E.h[5] = sx * Hxzz;
+        E.h[6] = sy * Hyyy; E.h[7] = sz * Hyyz; E.h[8] = sy * Hyzz; E.h[9] = sz * Hzzz;
+    }
+}
+
+// The correction field dg is smooth except at the lattice points n L, n != 0
+// (the images of the source; the single image's own singularity at d = 0 is
+// subtracted), so the correction walk opens nodes against the nearest of
+// those: a node of extent s at c (its image about the group centre) acts as a
+// point if s <= theta_E (|c - n L| - the group's half diagonal) for the
+// nearest lattice point n != 0 -- the one across the face of c's largest
+// component.
+__device__ __forceinline__ bool ewald_accept(const GroupBox& g, const double4 c, const WalkOut& O) {
+    const float x = fabsf((float)near_img(c.x - g.cx, O));
+    const float y = fabsf((float)near_img(c.y - g.cy, O));
+    const float z = fabsf((float)near_img(c.z - g.cz, O));
+    const float m = fmaxf(fmaxf(x, y), z);
+    const float far = O.boxf - m;
+    const float d2 = x * x + y * y + z * z - m * m + far * far;
+    const float r = sqrtf(d2) - sqrtf(g.hx * g.hx + g.hy * g.hy + g.hz * g.hz);
+    return r > 0.f && (float)c.w <= O.ewald_theta * r;
+}
+
+// The correction walk: accepted nodes (and the particles of opened leaves)
+// act through their mass and (on g) quadrupole at their images about the
+// group centre, the
+// ones the forward walk used for g and T.  A compact group (half extent at
+// most ewald_grp) sums dg, dT and H over the entries once, every lane taking
+// its share, and each target expands about the group centre:
+//   dg(c - t) = dg(c) + dT(c) t - 1/2 H(c) t t,   dT(c - t) = dT(c) - H(c) t;
+// a wider group evaluates the table at every target's own separation (the
+// expansion's error falls as (t / |c - n L|)^3 <= (2 t / L)^3).  The
+// sum includes the target itself (dg(0) = 0; dT(0) is the tide of the
+// background that neutralises its own images).
+struct EwaldPolicy {
+    static constexpr bool kSkipEmpty = false;
+    static constexpr bool kImageMac = true;
+    static constexpr bool kGroupSum = true;
+    using Lds = WalkLds<8>;
+    struct Acc {
+        double v[19];   // g 3, T 6, (group sums only) H 10
+        __device__ void zero() {
+#pragma unroll
+            for (int k = 0; k < 19; ++k) v[k] = 0.0;
+        }
+        __device__ void add(const Acc& o) {
+#pragma unroll
+            for (int k = 0; k < 19; ++k) v[k] += o.v[k];
+        }
+    };
+    // entry k: tile[k] = (position about the group centre, mass), tile[kW + k]
+    // and tile[2 kW + k] = traceless quadrupole xx yy zz xy | xz yz (0 for particles)
+    template <int kPer>
+    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk,
+                                          const WalkOut& O) {
+        const double4 q = T.spos[pk];
+        S.tile[lane] = make_float4((float)near_img(q.x - gb.cx, O), (float)near_img(q.y - gb.cy, O),
+                                   (float)near_img(q.z - gb.cz, O), (float)q.w);
+        S.tile[kW + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        S.tile[2 * kW + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    template <int kPer>
+    __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk, const WalkOut& O) {
+        const double4 c = T.com[nk];
+        const float4 m0 = T.mp[4 * nk], m1 = T.mp[4 * nk + 1], m2 = T.mp[4 * nk + 2];
+        S.tile[lane] = make_float4((float)near_img(c.x - gb.cx, O), (float)near_img(c.y - gb.cy, O),
+                                   (float)near_img(c.z - gb.cz, O), m0.x);
+        S.tile[kW + lane] = m1;
+        S.tile[2 * kW + lane] = make_float4(m2.x, m2.y, 0.f, 0.f);
+    }
+    // Single-image Newtonian field of a mass with traceless quadrupole Q at
+    // separation d (as the forward walk's node term): with P = Q d, q = d.P,
+    //   g = ca d - r^-5 P,  ca = M r^-3 + 2.5 q r^-7,
+    //   T = -(ca I - beta d d^T - r^-5 Q + 5 r^-7 (P d^T + d P^T)),
+    //   beta = 3 M r^-5 + 17.5 q r^-9.
+    __device__ static void newton_quad(float dx, float dy, float dz, float M, const float4 q0, const float4 q1,
+                                       float* g, float* t) {
+        const float Qxx = q0.x, Qyy = q0.y, Qzz = q0.z, Qxy = q0.w, Qxz = q1.x, Qyz = q1.y;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float ri = __builtin_amdgcn_rsqf(r2), ri2 = ri * ri;
+        const float ri3 = ri * ri2, ri5 = ri3 * ri2, ri7 = ri5 * ri2, ri9 = ri7 * ri2;
+        const float Px = Qxx * dx + Qxy * dy + Qxz * dz;
+        const float Py = Qxy * dx + Qyy * dy + Qyz * dz;
+        const float Pz = Qxz * dx + Qyz * dy + Qzz * dz;
+        const float q = dx * Px + dy * Py + dz * Pz;
+        const float ca = M * ri3 + 2.5f * q * ri7;
+        const float beta = 3.f * M * ri5 + 17.5f * q * ri9;
+        const float e = 5.f * ri7;
+        g[0] = ca * dx - ri5 * Px;
+        g[1] = ca * dy - ri5 * Py;
+        g[2] = ca * dz - ri5 * Pz;
+        t[0] = -(ca - beta * dx * dx - ri5 * Qxx + 2.f * e * Px * dx);
+        t[1] = -(ca - beta * dy * dy - ri5 * Qyy + 2.f * e * Py * dy);
+        t[2] = -(ca - beta * dz * dz - ri5 * Qzz + 2.f * e * Pz * dz);
+        t[3] = -(-beta * dx * dy - ri5 * Qxy + e * (Px * dy + dx * Py));
+        t[4] = -(-beta * dx * dz - ri5 * Qxz + e * (Px * dz + dx * Pz));
+        t[5] = -(-beta * dy * dz - ri5 * Qyz + e * (Py * dz + dy * Pz));
+    }
+    // A node's quadrupole adds -(1/6) Q_bc H_abc to dg (dg is harmonic away
+    // from d = 0, so the trace of the second moment drops out).
+    __device__ static void quad_g(const float4 q0, const float4 q1, const EwaldVal& E, float* g) {
+        const float* H = E.h;   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+        const float Qxx = q0.x, Qyy = q0.y, Qzz = q0.z, Qxy = q0.w, Qxz = q1.x, Qyz = q1.y;
+        const float c = 1.f / 6.f;
+        g[0] -= c * (Qxx * H[0] + Qyy * H[3] + Qzz * H[5] + 2.f * (Qxy * H[1] + Qxz * H[2] + Qyz * H[4]));
+        g[1] -= c * (Qxx * H[1] + Qyy * H[6] + Qzz * H[8] + 2.f * (Qxy * H[3] + Qxz * H[4] + Qyz * H[7]));
+        g[2] -= c * (Qxx * H[2] + Qyy * H[7] + Qzz * H[9] + 2.f * (Qxy * H[4] + Qxz * H[5] + Qyz * H[8]));
+    }
+    __device__ static void entries(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks,
+                                   const WalkOut& O) {
+        EwaldVal E;
+        if (t.grp) {
+            for (int k = threadIdx.x; k < cnt; k += kW) {
+                const float4 e = S.tile[k];
+                ewald_lookup<true>(O, e.x, e.y, e.z, E);
+                float gq[3] = {e.w * E.g[0], e.w * E.g[1], e.w * E.g[2]};
+                quad_g(S.tile[kW + k], S.tile[2 * kW + k], E, gq);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc.v[c] += (double)gq[c];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc.v[3 + c] += (double)(e.w * E.t[c]);
+#pragma unroll
+                for (int c = 0; c < 10; ++c) acc.v[9 + c] += (double)(e.w * E.h[c]);
+            }
+        } else {
+            // per target: the forward walk took g and T at d, the image about
+            // the group centre; the periodic field is the same at the nearest
+            // image d', where the table is accurate, so add
+            // dg(d') + g_single(d') - g_single(d)  (the last two only when d' != d)
+            for (int k = k0; k < cnt; k += ks) {
+                const float4 e = S.tile[k];
+                const float4 q0 = S.tile[kW + k], q1 = S.tile[2 * kW + k];
+                const float dx = e.x - t.tx, dy = e.y - t.ty, dz = e.z - t.tz;
+                const float nx = near_imgf(dx, O), ny = near_imgf(dy, O), nz = near_imgf(dz, O);
+                ewald_lookup<true>(O, nx, ny, nz, E);
+                float gq[3] = {e.w * E.g[0], e.w * E.g[1], e.w * E.g[2]};
+                float tq[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) tq[c] = e.w * E.t[c];
+                quad_g(q0, q1, E, gq);
+                if (nx != dx || ny != dy || nz != dz) {
+                    float g1[3], t1[6], g0[3], t0[6];
+                    newton_quad(nx, ny, nz, e.w, q0, q1, g1, t1);
+                    newton_quad(dx, dy, dz, e.w, q0, q1, g0, t0);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) gq[c] += g1[c] - g0[c];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) tq[c] += t1[c] - t0[c];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc.v[c] += (double)gq[c];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc.v[3 + c] += (double)tq[c];
+            }
+        }
+    }
+    template <int kPer>
+    __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float, float, int k0,
+                                     int ks, const WalkOut& O) {
+        entries(S, cnt, t, acc, k0, ks, O);
+    }
+    __device__ static void nodes(const Lds& S, int cnt, const Target& t, Acc& acc, int k0, int ks,
+                                 const WalkOut& O) {
+        entries(S, cnt, t, acc, k0, ks, O);
+    }
+    static __device__ void wave_sum(Acc& A) {
+#pragma unroll
+        for (int k = 0; k < 19; ++k) {
+            double v = A.v[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            A.v[k] = v;
+        }
+    }
+    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target& t) {
+        double g[3], tt[6];
+        if (t.grp) {
+            const double x = t.tx, y = t.ty, z = t.tz;
+            const double* H = A.v + 9;   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+            // (H t)_ab
+            const double Pxx = H[0] * x + H[1] * y + H[2] * z, Pyy = H[3] * x + H[6] * y + H[7] * z;
+            const double Pzz = H[5] * x + H[8] * y + H[9] * z, Pxy = H[1] * x + H[3] * y + H[4] * z;
+            const double Pxz = H[2] * x + H[4] * y + H[5] * z, Pyz = H[4] * x + H[7] * y + H[8] * z;
+            const double* Tv = A.v + 3;  // xx yy zz xy xz yz
+            g[0] = A.v[0] + (Tv[0] - 0.5 * Pxx) * x + (Tv[3] - 0.5 * Pxy) * y + (Tv[4] - 0.5 * Pxz) * z;
+            g[1] = A.v[1] + (Tv[3] - 0.5 * Pxy) * x + (Tv[1] - 0.5 * Pyy) * y + (Tv[5] - 0.5 * Pyz) * z;
+            g[2] = A.v[2] + (Tv[4] - 0.5 * Pxz) * x + (Tv[5] - 0.5 * Pyz) * y + (Tv[2] - 0.5 * Pzz) * z;
+            tt[0] = Tv[0] - Pxx; tt[1] = Tv[1] - Pyy; tt[2] = Tv[2] - Pzz;
+            tt[3] = Tv[3] - Pxy; tt[4] = Tv[4] - Pxz; tt[5] = Tv[5] - Pyz;
+        } else {
+            for (int c = 0; c < 3; ++c) g[c] = A.v[c];
+            for (int c = 0; c < 6; ++c) tt[c] = A.v[3 + c];
+        }
+        const int64_t i = T.perm[p];
+        const double G = O.G;
+        if (O.acc)
+            for (int c = 0; c < 3; ++c) O.acc[3 * i + c] += G * g[c];
+        if (O.tidal)
+            for (int c = 0; c < 6; ++c) O.tidal[6 * i + c] += G * tt[c];
+    }
+};
+
+template <class Pol, int kPer>
 __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, const Groups& Gr, const WalkOut& O,
                                            const int4 gd, float theta2, float eps2, float h2, float hinv) {
     const int lane = threadIdx.x;
@@ -572,6 +859,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     tg.vy = vi.y;
     tg.vz = vi.z;
     tg.p = p_i;
+    tg.grp = Pol::kGroupSum && fmaxf(fmaxf(gb.hx, gb.hy), gb.hz) <= O.ewald_grp;
 
     typename Pol::Acc acc;
     acc.zero();
@@ -598,7 +886,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     auto flush_nodes = [&](int base, int cnt) {
         if (lane < cnt) Pol::template stage_node<kPer>(S, T, gb, lane, S.nlist[base + lane], O);
         __syncthreads();
-        Pol::nodes(S, cnt, tg, acc, part, sub);
+        Pol::nodes(S, cnt, tg, acc, part, sub, O);
         n_pn += (uint64_t)cnt;
         __syncthreads();
     };
@@ -643,7 +931,8 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
                 ca = L.x;                  // no charge below this node
             } else {
                 const bool acc_ok =
-                    mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2, O.mac_offset, O);
+                    Pol::kImageMac ? ewald_accept(gb, T.com[a], O)
+                                   : mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2, O.mac_offset, O);
                 if (acc_ok && L.z > O.small_node) {
                     push_node = a;
                     ca = L.x;
@@ -714,7 +1003,10 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     if (npend > 0) flush_nodes(0, npend);
     if (ppend > 0) flush_particles(0, ppend);
 
-    if (sub > 1) {
+    if (Pol::kGroupSum && tg.grp) {
+        // every lane summed its own share of the entries: add all 64
+        Pol::wave_sum(acc);
+    } else if (sub > 1) {
         // sum the parts of every target in LDS (the walk lists are free now)
         static_assert(sizeof(typename Pol::Lds) >= sizeof(typename Pol::Acc) * kW, "LDS too small");
         typename Pol::Acc* red = reinterpret_cast<typename Pol::Acc*>(&S);
@@ -725,7 +1017,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
             for (int j = 1; j < sub; ++j) acc.add(red[slot + j * count]);
         __syncthreads();
     }
-    if (part == 0) Pol::finish(T, O, acc, p_i);
+    if (part == 0) Pol::finish(T, O, acc, p_i, tg);
     if (lane == 0 && O.stats) {
         atomicAdd(&O.stats[0], (unsigned long long)(n_pp * (uint64_t)count));
         atomicAdd(&O.stats[1], (unsigned long long)(n_pn * (uint64_t)count));
@@ -741,7 +1033,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
 // from the other queues when its own runs dry.  The register budget is held
 // to 128 VGPRs (four waves per SIMD); the few values this spills live
 // outside the interaction loops.
-template <class Pol, bool kPer>
+template <class Pol, int kPer>
 __global__ void __launch_bounds__(kW, 4) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
                                              float theta2, float eps2, float h2, float hinv) {
     __shared__ typename Pol::Lds S;
@@ -772,6 +1064,113 @@ __global__ void __launch_bounds__(kW, 4) k_walk(Tree T, Groups Gr, WalkOut O, in
         walk_group<Pol, kPer>(S, T, Gr, O, Gr.grp[g], theta2, eps2, h2, hinv);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Ewald correction table
+// ---------------------------------------------------------------------------
+// The periodic field of a unit mass (G = 1) and its images with a uniform
+// neutralising background, split with alpha = 2 / L:
+//   g = sum_n B(r_n) y_n + (4 pi / L^3) sum_k k / k^2 exp(-k^2 / 4 alpha^2) sin(k.d),
+//   B(r) = erfc(alpha r) / r^3 + (2 alpha / sqrt(pi)) exp(-alpha^2 r^2) / r^2,
+// y_n = d + n L; with C = B'/r and D = C'/r per image,
+//   T_ab = -(B delta_ab + C y_a y_b),
+//   H_abc = dT_ab / dd_c = -(C (y_c delta_ab + y_b delta_ac + y_a delta_bc) + D y_a y_b y_c),
+// and the reciprocal terms -w k_a k_b cos(k.d), +w k_a k_b k_c sin(k.d).  The
+// n = 0 image enters without its Newtonian part (B -> B - 1/r^3), by the
+// series of that difference where alpha r < 1/2, so the table holds the
+// correction dg = g - d / |d|^3 (and its derivatives), smooth up to d = 0.
+// Images |n_a| <= 3, wave vectors |h_a| <= 4 (dropped terms below 1e-19).
+__device__ void ewald_radial(double r, double alpha, bool newton_removed, double& B, double& C, double& D) {
+    const double sp = 1.1283791670955126;   // 2 / sqrt(pi)
+    const double z = alpha * r;
+    if (newton_removed && z < 0.5) {
+        // c_k = (-1)^k 2k / ((2k + 1) k!) alpha^(2k+1):  B = sp sum_{k>=1} c_k r^(2k-2),
+        // C = sp sum_{k>=2} c_k (2k-2) r^(2k-4),  D = sp sum_{k>=3} c_k (2k-2)(2k-4) r^(2k-6)
+        double sb = 0.0, sc = 0.0, sd = 0.0;
+        double ak = alpha * alpha * alpha, fact = 1.0;
+        double r2 = r * r, pb = 1.0, pc = 1.0, pd = 1.0;
+        for (int k = 1; k <= 24; ++k) {
+            if (k > 1) {
+                ak *= alpha * alpha;
+                fact *= k;
+                pb *= r2;
+            }
+            if (k > 2) pc *= r2;
+            if (k > 3) pd *= r2;
+            const double c = ((k & 1) ? -1.0 : 1.0) * (2.0 * k) / ((2.0 * k + 1.0) * fact) * ak;
+            sb += c * pb;
+            if (k >= 2) sc += c * (2.0 * k - 2.0) * pc;
+            if (k >= 3) sd += c * (2.0 * k - 2.0) * (2.0 * k - 4.0) * pd;
+        }
+        B = sp * sb;
+        C = sp * sc;
+        D = sp * sd;
+        return;
+    }
+    const double e = exp(-z * z), ec = erfc(z);
+    const double r2 = r * r, r3 = r2 * r, r4 = r2 * r2, r5 = r4 * r;
+    double b = ec / r3 + sp * alpha * e / r2;
+    double b1 = -3.0 * ec / r4 - sp * alpha * e * (3.0 / r3 + 2.0 * alpha * alpha / r);
+    double b2 = 12.0 * ec / r5 + sp * alpha * e * (12.0 / r4 + 8.0 * alpha * alpha / r2 + 4.0 * alpha * alpha * alpha * alpha);
+    if (newton_removed) {
+        b -= 1.0 / r3;
+        b1 += 3.0 / r4;
+        b2 -= 12.0 / r5;
+    }
+    B = b;
+    C = b1 / r;
+    D = b2 / r2 - b1 / r3;
+}
+
+__global__ void k_ewald_table(double L, int ne, double h, float4* __restrict__ tab) {
+    const int np = (ne + 1) * (ne + 1) * (ne + 1);
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= np) return;
+    const int iz = id % (ne + 1), iy = (id / (ne + 1)) % (ne + 1), ix = id / ((ne + 1) * (ne + 1));
+    const double d[3] = {ix * h, iy * h, iz * h};
+    const double alpha = 2.0 / L;
+    double g[3] = {0, 0, 0}, T[6] = {0, 0, 0, 0, 0, 0}, H[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // index pairs of T and triples of H
+    const int ta[6] = {0, 1, 2, 0, 0, 1}, tb[6] = {0, 1, 2, 1, 2, 2};
+    const int ha[10] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 2}, hb[10] = {0, 0, 0, 1, 1, 2, 1, 1, 2, 2},
+              hc[10] = {0, 1, 2, 1, 2, 2, 1, 2, 2, 2};
+    for (int a = -3; a <= 3; ++a)
+        for (int b = -3; b <= 3; ++b)
+            for (int c = -3; c <= 3; ++c) {
+                const double y[3] = {d[0] + a * L, d[1] + b * L, d[2] + c * L};
+                const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+                double B, C, D;
+                ewald_radial(r, alpha, a == 0 && b == 0 && c == 0, B, C, D);
+                for (int q = 0; q < 3; ++q) g[q] += B * y[q];
+                for (int q = 0; q < 6; ++q) T[q] -= (ta[q] == tb[q] ? B : 0.0) + C * y[ta[q]] * y[tb[q]];
+                for (int q = 0; q < 10; ++q) {
+                    const int i = ha[q], j = hb[q], k = hc[q];
+                    const double del = (i == j ? y[k] : 0.0) + (i == k ? y[j] : 0.0) + (j == k ? y[i] : 0.0);
+                    H[q] -= C * del + D * y[i] * y[j] * y[k];
+                }
+            }
+    const double pre = 4.0 * 3.14159265358979323846 / (L * L * L);
+    const double kf = 2.0 * 3.14159265358979323846 / L;
+    for (int a = -4; a <= 4; ++a)
+        for (int b = -4; b <= 4; ++b)
+            for (int c = -4; c <= 4; ++c) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                const double k[3] = {kf * a, kf * b, kf * c};
+                const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                const double w = pre * exp(-k2 / (4.0 * alpha * alpha)) / k2;
+                double sn, cs;
+                sincos(k[0] * d[0] + k[1] * d[1] + k[2] * d[2], &sn, &cs);
+                for (int q = 0; q < 3; ++q) g[q] += w * k[q] * sn;
+                for (int q = 0; q < 6; ++q) T[q] -= w * k[ta[q]] * k[tb[q]] * cs;
+                for (int q = 0; q < 10; ++q) H[q] += w * k[ha[q]] * k[hb[q]] * k[hc[q]] * sn;
+            }
+    float4* o = tab + 5 * (int64_t)id;
+    o[0] = make_float4((float)g[0], (float)g[1], (float)g[2], (float)T[0]);
+    o[1] = make_float4((float)T[1], (float)T[2], (float)T[3], (float)T[4]);
+    o[2] = make_float4((float)T[5], (float)H[0], (float)H[1], (float)H[2]);
+    o[3] = make_float4((float)H[3], (float)H[4], (float)H[5], (float)H[6]);
+    o[4] = make_float4((float)H[7], (float)H[8], (float)H[9], 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -1111,6 +1510,21 @@ static int walk_grid(ag_ctx* c, int64_t max_groups) {
     return (int)blocks;
 }
 
+// Ewald table: spacing box / 64 over the octant [0, box / 2]^3 of the cell
+constexpr int kEwaldPerBox = 64;
+constexpr int kEwaldNE = 32;
+constexpr int kEwaldGroupDiv = 512;   // groups of half extent <= box / 512 sum once
+
+static int ewald_table(ag_ctx* c) {
+    if (c->ewald_tab_box == c->box && c->ewald_tab.bytes) return AG_OK;
+    const int np = (kEwaldNE + 1) * (kEwaldNE + 1) * (kEwaldNE + 1);
+    AG_TRY(ag_ensure(c->ewald_tab, (size_t)np * 5 * sizeof(float4)));
+    hipLaunchKernelGGL(k_ewald_table, dim3((np + 127) / 128), dim3(128), 0, c->stream, c->box, kEwaldNE,
+                       c->box / kEwaldPerBox, c->ewald_tab.as<float4>());
+    c->ewald_tab_box = c->box;
+    return AG_OK;
+}
+
 static WalkOut make_out(ag_ctx* c, double G) {
     WalkOut O{};
     O.stats = c->stats.as<unsigned long long>();
@@ -1125,6 +1539,13 @@ static WalkOut make_out(ag_ctx* c, double G) {
     O.boxf_inv = (float)O.box_inv;
     // a margin of a few float ulps keeps every accepted node clear of the cut
     O.box_half = (float)(0.5 * c->box * (1.0 - 1e-5));
+    O.ewald_theta = 1.0f / (float)c->ewald_open;
+    O.ewald_grp = (float)(c->box / kEwaldGroupDiv);
+    O.etab = c->ewald_tab.as<float4>();
+    O.etab_ne = kEwaldNE;
+    O.etab_h = (float)(c->box / kEwaldPerBox);
+    O.etab_hinv = (float)(kEwaldPerBox / c->box);
+    O.etab_range = (float)(c->box * kEwaldNE / kEwaldPerBox * (1.0 + 1e-4));   // a few ulps of slack
     return O;
 }
 
@@ -1140,16 +1561,37 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
     O.tidal = tidal;
     const float th = (float)theta;
     const float e2 = (float)(eps * eps);
+    const bool ewald = c->box > 0.0 && c->ewald;
+    if (ewald) {
+        AG_TRY(ewald_table(c));
+        O = make_out(c, G);   // with the table's address
+        O.acc = acc;
+        O.jerk = jerk;
+        O.tidal = tidal;
+    }
+    const unsigned grid = (unsigned)walk_grid(c, mg);
+    int32_t* qctr = c->grp_hdr.as<int32_t>() + 8;
     {
         PhaseScope phase(c, AG_PHASE_WALK);
-        if (c->box > 0.0)
-            hipLaunchKernelGGL((k_walk<ForwardPolicy, true>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0,
-                               c->stream, make_tree(c), Gr, O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2,
-                               (float)(1.0 / eps));
+        if (ewald)
+            hipLaunchKernelGGL((k_walk<ForwardPolicy, kEwald>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr,
+                               O, qctr, th * th, e2, e2, (float)(1.0 / eps));
+        else if (c->box > 0.0)
+            hipLaunchKernelGGL((k_walk<ForwardPolicy, kNear>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr,
+                               O, qctr, th * th, e2, e2, (float)(1.0 / eps));
         else
-            hipLaunchKernelGGL((k_walk<ForwardPolicy, false>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0,
-                               c->stream, make_tree(c), Gr, O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2,
-                               (float)(1.0 / eps));
+            hipLaunchKernelGGL((k_walk<ForwardPolicy, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr,
+                               O, qctr, th * th, e2, e2, (float)(1.0 / eps));
+    }
+    if (ewald && (acc || tidal)) {
+        // what the periodic images add to g and T, at the same images
+        AG_TRY(ag_ensure(c->ewald_q, 8 * sizeof(int32_t)));
+        PhaseScope phase(c, AG_PHASE_EWALD);
+        hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, c->stream, c->ewald_q.as<int32_t>(), (int64_t)8);
+        WalkOut E = O;
+        E.stats = nullptr;
+        hipLaunchKernelGGL((k_walk<EwaldPolicy, kNear>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, E,
+                           c->ewald_q.as<int32_t>(), 0.f, 0.f, e2, (float)(1.0 / eps));
     }
     return AG_OK;
 }
@@ -1197,7 +1639,7 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
     O.tin = tin;
     const float th = (float)theta;
     const float e2 = (float)(eps * eps);
-    hipLaunchKernelGGL((k_walk<AdjointPolicy, false>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, st,
+    hipLaunchKernelGGL((k_walk<AdjointPolicy, kOpen>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, st,
                        make_tree(c), Gr,
                        O, c->grp_hdr.as<int32_t>() + 8, th * th, e2, e2, (float)(1.0 / eps));
     return AG_OK;

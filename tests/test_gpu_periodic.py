@@ -158,8 +158,10 @@ def test_tree_periodic_subset(ag, orc):
 
 
 def test_large_box_matches_open(ag):
-    """In a box far larger than the set no pair is wrapped."""
+    """In a box far larger than the set (which lies inside it, so the tree
+    holds the same positions) no pair is wrapped."""
     x, v, m, _ = workloads.clumps(1 << 14, seed=4)
+    x = x - x.min(axis=0) + 1.0
     a0, _, T0 = _tree(ag, 0.0, x, v, m, 0.7, 1e-3)
     a1, _, T1 = _tree(ag, 1e6, x, v, m, 0.7, 1e-3)
     assert np.median(rel_err(a1, a0)) <= 1e-6
@@ -182,5 +184,126 @@ def test_periodic_arguments(ag):
             c.grav_backward(None, w, 0.7, 1e-3, 1.0, dx, dm)
         assert e.value.code == ag.AG_ESTATE
         c.set_periodic(0.0)
+        with pytest.raises(ag.AgError) as e:     # the tree was built in the box
+            c.grav_backward(None, w, 0.7, 1e-3, 1.0, dx, dm)
+        assert e.value.code == ag.AG_ESTATE
+        c.tree_build(_t(x), _t(v), _t(m), 16)
         c.grav_backward(None, w, 0.7, 1e-3, 1.0, dx, dm)
         c.sync()
+
+
+# ---- Ewald sums (g and T of all images; j stays nearest-image) ----------
+
+def _tree_ewald(ag, box, x, v, m, theta, eps, ewald_open=None, active=None):
+    with ag.Context(0) as c:
+        c.set_periodic(box, ewald=True)
+        if ewald_open is not None:
+            c.set_option(ag.AG_OPT_EWALD_OPEN, ewald_open)
+        c.tree_build(_t(x), _t(v), _t(m), 16)
+        out = _outputs(len(m))
+        ia = None if active is None else _t(active, torch.int32)
+        c.grav_eval(ia, theta, eps, 1.0, *out)
+        c.sync()
+    return [o.cpu().numpy() for o in out]
+
+
+def _uniform(n, seed=7):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0, 1, (n, 3)), rng.normal(size=(n, 3)), np.full(n, 1.0 / n)
+
+
+@pytest.mark.parametrize("name", ["clumps", "uniform"])
+def test_ewald_theta0(ag, orc, name):
+    """theta = 0 and a correction walk opened down to 1/64 of the distance to
+    the image points: the periodic direct sum up to FP32 pair terms and the
+    table."""
+    if name == "clumps":
+        x, v, m = _clumps_in_box(4096, seed=9)
+    else:
+        x, v, m = _uniform(4096)
+    a, j, T = _tree_ewald(ag, 1.0, x, v, m, 0.0, 1e-3, ewald_open=64)
+    rows = np.random.default_rng(3).choice(len(m), 256, replace=False)
+    ar, jr, Tr = orc.direct(x, v, m, 1e-3, 1.0, rows, box=1.0, ewald=True)
+    # the images add a field of order G M / L^2 that the single images' sum
+    # of |pair terms| leaves out: it joins the scale
+    sa = orc.abs_scale(x, m, 1e-3, 1.0, rows, box=1.0) + m.sum()
+    ea = np.linalg.norm(a[rows] - ar, axis=1) / sa
+    et = tensor_rel_err(T[rows], Tr)
+    print(f"\nEwald theta=0 {name}: g vs abs scale median {np.median(ea):.2e} max {ea.max():.2e}; "
+          f"g relative median {np.median(rel_err(a[rows], ar)):.2e}; T relative median {np.median(et):.2e}")
+    assert np.median(ea) <= 1e-6 and ea.max() <= 1e-4
+    assert np.median(et) <= 1e-4
+    # the jerk is the nearest-image one
+    _, jn, _ = orc.direct(x, v, m, 1e-3, 1.0, rows, box=1.0)
+    assert np.median(rel_err(j[rows], jn)) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["clumps", "pancake", "uniform"])
+def test_ewald_tree(ag, orc, name):
+    if name == "clumps":
+        x, v, m = _clumps_in_box(8192, seed=10)
+        L, eps = 1.0, 1e-3
+    elif name == "pancake":
+        x, v, m = workloads.zeldovich_box(20, box=1.0)
+        L, eps = 1.0, 1.0 / 20 / 8
+    else:
+        x, v, m = _uniform(8192)
+        L, eps = 1.0, 1e-3
+    a, j, T = _tree_ewald(ag, L, x, v, m, 0.7, eps)
+    rows = np.random.default_rng(4).choice(len(m), 256, replace=False)
+    ar, jr, Tr = orc.direct(x, v, m, eps, 1.0, rows, box=L, ewald=True)
+    ea, et = rel_err(a[rows], ar), tensor_rel_err(T[rows], Tr)
+    sa, sj, st = _scales(orc, x, v, m, eps, rows, L)
+    # plus the images' field and tide, of order G M / L^2 and G M / L^3
+    sa, st = sa + m.sum() / L**2, st + m.sum() / L**3
+    w = np.array([1, 1, 1, 2, 2, 2], dtype=float)
+    eas = np.linalg.norm(a[rows] - ar, axis=1) / sa
+    ets = np.sqrt(((T[rows] - Tr) ** 2 * w).sum(1)) / st
+    print(f"\nEwald tree {name}: relative g median {np.median(ea):.2e} p99 {np.percentile(ea, 99):.2e}, "
+          f"T median {np.median(et):.2e} p99 {np.percentile(et, 99):.2e}; against the cancellation-free "
+          f"sizes g {np.median(eas):.2e} / {np.percentile(eas, 99):.2e}, T {np.median(ets):.2e} / "
+          f"{np.percentile(ets, 99):.2e}")
+    if name == "clumps":
+        assert np.median(ea) <= 1e-3 and np.percentile(ea, 99) <= 1e-2
+        assert np.median(et) <= 5e-3 and np.percentile(et, 99) <= 5e-2
+    else:
+        assert np.median(eas) <= 1e-3 and np.percentile(eas, 99) <= 1e-2
+        assert np.median(ets) <= 5e-3 and np.percentile(ets, 99) <= 5e-2
+
+
+def test_ewald_lattice(ag):
+    """A perfect lattice is the uniform box: no force, and the tide of the
+    mean density, (4 pi / 3) G M / L^3 per axis, off-diagonals zero."""
+    k, L = 24, 2.0
+    g = (np.arange(k) + 0.5) * L / k
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    n = len(x)
+    m = np.full(n, 1.0 / n)
+    a, _, T = _tree_ewald(ag, L, x, np.zeros_like(x), m, 0.5, L / k / 8)
+    c = 4 * np.pi / 3 / L**3
+    amax = np.abs(a).max()
+    print(f"\nEwald lattice: max |g| {amax:.2e} (G M / L^2 = {1 / L**2:.2e}); T diag mean "
+          f"{T[:, :3].mean():.6e} vs {c:.6e}; max |T - c I| {np.abs(T[:, :3] - c).max():.2e}, "
+          f"off-diagonal {np.abs(T[:, 3:]).max():.2e}")
+    # tree error budget: 1e-3 of the nearest neighbours' pull (6 m / a^2,
+    # a = L / k) and 2% of the tide
+    assert amax <= 1e-3 * 6 / (k * L**2)
+    assert np.abs(T[:, :3] - c).max() <= 2e-2 * c
+    assert np.abs(T[:, 3:]).max() <= 2e-2 * c
+
+
+def test_ewald_arguments(ag):
+    x, v, m, _ = workloads.clumps(1024, seed=4)
+    with ag.Context(0) as c:
+        with pytest.raises(ag.AgError) as e:
+            c.set_periodic(0.0, ewald=True)
+        assert e.value.code == ag.AG_EINVAL
+        c.set_periodic(1.0, ewald=True)
+        out = _outputs(1024)
+        with pytest.raises(ag.AgError) as e:
+            c.grav_direct(_t(x), _t(v), _t(m), None, 1e-3, 1.0, *out)
+        assert e.value.code == ag.AG_ESTATE
+        for bad in (0, 65):
+            with pytest.raises(ag.AgError) as e:
+                c.set_option(ag.AG_OPT_EWALD_OPEN, bad)
+            assert e.value.code == ag.AG_EINVAL
