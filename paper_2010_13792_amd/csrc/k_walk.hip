@@ -640,8 +640,18 @@ __device__ __forceinline__ void ewald_lookup(const WalkOut& O, float dx, float d
 // those: a node of extent s at c (its image about the group centre) acts as a
 // point if s <= theta_E (|c - n L| - the group's half diagonal) for the
 // nearest lattice point n != 0 -- the one across the face of c's largest
-// component.
-__device__ __forceinline__ bool ewald_accept(const GroupBox& g, const double4 c, const WalkOut& O) {
+// component -- and, as in the forward walk, all of its box lies within half a
+// box side of all of the group's box (so c is every target's nearest image
+// of every particle in it, and no target sees the node from nearby through
+// another image).
+__device__ __forceinline__ bool ewald_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
+                                             const WalkOut& O) {
+    const float bx = fabsf((float)near_img(0.5 * ((double)lo.x + (double)hi.x) - g.cx, O));
+    const float by = fabsf((float)near_img(0.5 * ((double)lo.y + (double)hi.y) - g.cy, O));
+    const float bz = fabsf((float)near_img(0.5 * ((double)lo.z + (double)hi.z) - g.cz, O));
+    if (bx + 0.5f * (hi.x - lo.x) + g.hx >= O.box_half || by + 0.5f * (hi.y - lo.y) + g.hy >= O.box_half ||
+        bz + 0.5f * (hi.z - lo.z) + g.hz >= O.box_half)
+        return false;
     const float x = fabsf((float)near_img(c.x - g.cx, O));
     const float y = fabsf((float)near_img(c.y - g.cy, O));
     const float z = fabsf((float)near_img(c.z - g.cz, O));
@@ -931,7 +941,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
                 ca = L.x;                  // no charge below this node
             } else {
                 const bool acc_ok =
-                    Pol::kImageMac ? ewald_accept(gb, T.com[a], O)
+                    Pol::kImageMac ? ewald_accept(gb, T.com[a], T.lo[a], T.hi[a], O)
                                    : mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2, O.mac_offset, O);
                 if (acc_ok && L.z > O.small_node) {
                     push_node = a;

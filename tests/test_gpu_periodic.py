@@ -271,25 +271,32 @@ def test_ewald_tree(ag, orc, name):
         assert np.median(ets) <= 5e-3 and np.percentile(ets, 99) <= 5e-2
 
 
-def test_ewald_lattice(ag):
+def test_ewald_lattice(ag, orc):
     """A perfect lattice is the uniform box: no force, and the tide of the
-    mean density, (4 pi / 3) G M / L^3 per axis, off-diagonals zero."""
+    mean density, (4 pi / 3) G M / L^3 per axis, off-diagonals zero -- up to
+    the tree's error, measured against the cancellation-free sizes."""
     k, L = 24, 2.0
     g = (np.arange(k) + 0.5) * L / k
     x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
     n = len(x)
     m = np.full(n, 1.0 / n)
-    a, _, T = _tree_ewald(ag, L, x, np.zeros_like(x), m, 0.5, L / k / 8)
+    eps = L / k / 8
+    a, _, T = _tree_ewald(ag, L, x, np.zeros_like(x), m, 0.5, eps)
     c = 4 * np.pi / 3 / L**3
-    amax = np.abs(a).max()
-    print(f"\nEwald lattice: max |g| {amax:.2e} (G M / L^2 = {1 / L**2:.2e}); T diag mean "
-          f"{T[:, :3].mean():.6e} vs {c:.6e}; max |T - c I| {np.abs(T[:, :3] - c).max():.2e}, "
-          f"off-diagonal {np.abs(T[:, 3:]).max():.2e}")
-    # tree error budget: 1e-3 of the nearest neighbours' pull (6 m / a^2,
-    # a = L / k) and 2% of the tide
-    assert amax <= 1e-3 * 6 / (k * L**2)
-    assert np.abs(T[:, :3] - c).max() <= 2e-2 * c
-    assert np.abs(T[:, 3:]).max() <= 2e-2 * c
+    rows = np.random.default_rng(5).choice(n, 64, replace=False)
+    sa, _, st = _scales(orc, x, np.zeros_like(x), m, eps, rows, L)
+    sa, st = sa + 1.0 / L**2, st + 1.0 / L**3
+    ea = np.linalg.norm(a[rows], axis=1) / sa
+    dT = T[rows].copy()
+    dT[:, :3] -= c
+    w = np.array([1, 1, 1, 2, 2, 2], dtype=float)
+    et = np.sqrt((dT**2 * w).sum(1)) / st
+    print(f"\nEwald lattice: T diag mean {T[:, :3].mean():.6e} vs {c:.6e}; against the cancellation-free "
+          f"sizes g median {np.median(ea):.2e} max {ea.max():.2e}, T median {np.median(et):.2e} max {et.max():.2e}")
+    # the mean tide is the background's, exactly up to rounding
+    assert abs(T[:, :3].mean() - c) <= 1e-5 * c
+    assert np.median(ea) <= 1e-3 and ea.max() <= 1e-2
+    assert np.median(et) <= 5e-3 and et.max() <= 5e-2
 
 
 def test_ewald_arguments(ag):
