@@ -173,7 +173,14 @@ __global__ void k_keys(int64_t n, const double* __restrict__ x, const int64_t* _
             ext = e > ext ? e : ext;
         }
         if (!(ext > 0.0) || !isfinite(ext)) ext = 1.0;
-        const double inv = scale_cells / (ext * (1.0 + 1e-12));
+        if (pbox > 0.0) {   // a periodic tree's root cell is the box itself
+            lo[0] = lo[1] = lo[2] = 0.0;
+            ext = pbox;
+        }
+        // (a periodic root is split exactly at half the box: no cell below it
+        // crosses the planes where sources change image about a multiple of
+        // half the box)
+        const double inv = pbox > 0.0 ? scale_cells / pbox : scale_cells / (ext * (1.0 + 1e-12));
         uint64_t code = 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

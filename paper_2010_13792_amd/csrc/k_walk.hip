@@ -100,6 +100,7 @@ struct WalkOut {
 // group geometry shared by every lane (uniform values)
 struct GroupBox {
     double cx, cy, cz;          // centre (FP64)
+    double ox, oy, oz;          // origin of the source images (periodic walks; else the centre)
     float hx, hy, hz;           // half extents (rounded up)
     float lox, loy, loz, hix, hiy, hiz;   // absolute box, rounded outward
 };
@@ -120,6 +121,7 @@ __device__ __forceinline__ GroupBox group_box(double x, double y, double z) {
     mxx = ag_wave_max(mxx); mxy = ag_wave_max(mxy); mxz = ag_wave_max(mxz);
     GroupBox g;
     g.cx = 0.5 * (mnx + mxx); g.cy = 0.5 * (mny + mxy); g.cz = 0.5 * (mnz + mxz);
+    g.ox = g.cx; g.oy = g.cy; g.oz = g.cz;
     g.hx = f_upr(0.5 * (mxx - mnx)); g.hy = f_upr(0.5 * (mxy - mny)); g.hz = f_upr(0.5 * (mxz - mnz));
     g.lox = f_dn(mnx); g.loy = f_dn(mny); g.loz = f_dn(mnz);
     g.hix = f_upr(mxx); g.hiy = f_upr(mxy); g.hiz = f_upr(mxz);
@@ -146,10 +148,10 @@ template <int kPer>
 __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
                                            float theta2, float eps2, bool offset, const WalkOut& O) {
     double cdx = c.x - g.cx, cdy = c.y - g.cy, cdz = c.z - g.cz;
-    if (kPer) {
-        cdx = near_img(cdx, O);
-        cdy = near_img(cdy, O);
-        cdz = near_img(cdz, O);
+    if (kPer) {   // the node's image about the image origin, seen from the group centre
+        cdx = near_img(c.x - g.ox, O) + (g.ox - g.cx);
+        cdy = near_img(c.y - g.oy, O) + (g.oy - g.cy);
+        cdz = near_img(c.z - g.oz, O) + (g.oz - g.cz);
     }
     const float rx = fmaxf(fabsf((float)cdx) - g.hx, 0.f);
     const float ry = fmaxf(fabsf((float)cdy) - g.hy, 0.f);
@@ -169,13 +171,20 @@ __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, c
         gz = fmaxf(fmaxf(lo.z - g.hiz, g.loz - hi.z), 0.f);
     } else {
         // box centre offset at its nearest image, and the half extents
-        const float bx = fabsf((float)near_img(0.5 * ((double)lo.x + (double)hi.x) - g.cx, O));
-        const float by = fabsf((float)near_img(0.5 * ((double)lo.y + (double)hi.y) - g.cy, O));
-        const float bz = fabsf((float)near_img(0.5 * ((double)lo.z + (double)hi.z) - g.cz, O));
+        const float bx = fabsf((float)(near_img(0.5 * ((double)lo.x + (double)hi.x) - g.ox, O) + (g.ox - g.cx)));
+        const float by = fabsf((float)(near_img(0.5 * ((double)lo.y + (double)hi.y) - g.oy, O) + (g.oy - g.cy)));
+        const float bz = fabsf((float)(near_img(0.5 * ((double)lo.z + (double)hi.z) - g.oz, O) + (g.oz - g.cz)));
         const float ex = 0.5f * (hi.x - lo.x) + g.hx;
         const float ey = 0.5f * (hi.y - lo.y) + g.hy;
         const float ez = 0.5f * (hi.z - lo.z) + g.hz;
-        if (bx + ex >= O.box_half || by + ey >= O.box_half || bz + ez >= O.box_half) return false;
+        // nearest images only: one image for the whole node (the nearest-image
+        // field jumps at half a box from each target, so a node across that
+        // cut is opened); with Ewald sums the field of all images is smooth
+        // there, and every source stands at its image about the image origin,
+        // whose cut (half a box away, on a boundary of the root's children)
+        // no node below the root crosses
+        if (kPer == kNear && (bx + ex >= O.box_half || by + ey >= O.box_half || bz + ez >= O.box_half))
+            return false;
         gx = fmaxf(bx - ex, 0.f);
         gy = fmaxf(by - ey, 0.f);
         gz = fmaxf(bz - ez, 0.f);
@@ -268,6 +277,7 @@ struct Target {
     float vx, vy, vz;
     int p;                 // sorted position
     bool grp;              // Ewald correction summed once for the whole group
+    float g0x, g0y, g0z;   // group centre relative to the image origin
 };
 
 // ---- forward: g, j and S = -T from particle masses and node multipoles ----
@@ -291,7 +301,7 @@ struct ForwardPolicy {
                                           const WalkOut& O) {
         const double4 q = T.spos[pk];
         const float4 u = T.svf[pk];
-        double dx = q.x - gb.cx, dy = q.y - gb.cy, dz = q.z - gb.cz;
+        double dx = q.x - gb.ox, dy = q.y - gb.oy, dz = q.z - gb.oz;
         if (kPer) {
             dx = near_img(dx, O);
             dy = near_img(dy, O);
@@ -379,7 +389,7 @@ struct ForwardPolicy {
         const double4 c = T.com[nk];
         const float4 m0 = T.mp[4 * nk], m1 = T.mp[4 * nk + 1], m2 = T.mp[4 * nk + 2], m3 = T.mp[4 * nk + 3];
         float4* d = S.tile;
-        double dx = c.x - gb.cx, dy = c.y - gb.cy, dz = c.z - gb.cz;
+        double dx = c.x - gb.ox, dy = c.y - gb.oy, dz = c.z - gb.oz;
         if (kPer) {   // the opening test guarantees one image for the whole node
             dx = near_img(dx, O);
             dy = near_img(dy, O);
@@ -634,32 +644,38 @@ __device__ __forceinline__ void ewald_lookup(const WalkOut& O, float dx, float d
     }
 }
 
-// The correction field dg is smooth except at the lattice points n L, n != 0
-// (the images of the source; the single image's own singularity at d = 0 is
-// subtracted), so the correction walk opens nodes against the nearest of
-// those: a node of extent s at c (its image about the group centre) acts as a
-// point if s <= theta_E (|c - n L| - the group's half diagonal) for the
-// nearest lattice point n != 0 -- the one across the face of c's largest
-// component -- and, as in the forward walk, all of its box lies within half a
-// box side of all of the group's box (so c is every target's nearest image
-// of every particle in it, and no target sees the node from nearby through
-// another image).
+// The correction field dg(d) is smooth except at the lattice points n L,
+// n != 0 (where the source meets another image of the target; the single
+// image's own singularity at d = 0 is subtracted).  So the correction walk
+// opens a node against the target group's other images: a node of extent s
+// acts as a point if s <= theta_E r, r the smallest distance between the
+// node's box and the group's box shifted by any n L, n != 0.  Per axis the
+// gap is either the one about the group centre or, across the cut, the one
+// through the neighbouring image; at least one axis takes the latter.
 __device__ __forceinline__ bool ewald_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
                                              const WalkOut& O) {
-    const float bx = fabsf((float)near_img(0.5 * ((double)lo.x + (double)hi.x) - g.cx, O));
-    const float by = fabsf((float)near_img(0.5 * ((double)lo.y + (double)hi.y) - g.cy, O));
-    const float bz = fabsf((float)near_img(0.5 * ((double)lo.z + (double)hi.z) - g.cz, O));
-    if (bx + 0.5f * (hi.x - lo.x) + g.hx >= O.box_half || by + 0.5f * (hi.y - lo.y) + g.hy >= O.box_half ||
-        bz + 0.5f * (hi.z - lo.z) + g.hz >= O.box_half)
-        return false;
-    const float x = fabsf((float)near_img(c.x - g.cx, O));
-    const float y = fabsf((float)near_img(c.y - g.cy, O));
-    const float z = fabsf((float)near_img(c.z - g.cz, O));
-    const float m = fmaxf(fmaxf(x, y), z);
-    const float far = O.boxf - m;
-    const float d2 = x * x + y * y + z * z - m * m + far * far;
-    const float r = sqrtf(d2) - sqrtf(g.hx * g.hx + g.hy * g.hy + g.hz * g.hz);
-    return r > 0.f && (float)c.w <= O.ewald_theta * r;
+    float b[3], e[3];
+    b[0] = fabsf((float)(near_img(0.5 * ((double)lo.x + (double)hi.x) - g.ox, O) + (g.ox - g.cx)));
+    b[1] = fabsf((float)(near_img(0.5 * ((double)lo.y + (double)hi.y) - g.oy, O) + (g.oy - g.cy)));
+    b[2] = fabsf((float)(near_img(0.5 * ((double)lo.z + (double)hi.z) - g.oz, O) + (g.oz - g.cz)));
+    e[0] = 0.5f * (hi.x - lo.x) + g.hx;
+    e[1] = 0.5f * (hi.y - lo.y) + g.hy;
+    e[2] = 0.5f * (hi.z - lo.z) + g.hz;
+    float s2 = 0.f, step = FLT_MAX;
+    bool shifted = false;
+    for (int a = 0; a < 3; ++a) {
+        const float in = fmaxf(b[a] - e[a], 0.f);            // about the group centre
+        const float out = fmaxf(O.boxf - b[a] - e[a], 0.f);  // through the neighbouring image
+        if (out <= in) {
+            s2 += out * out;
+            shifted = true;
+        } else {
+            s2 += in * in;
+            step = fminf(step, out * out - in * in);
+        }
+    }
+    if (!shifted) s2 += step;
+    return (float)c.w <= O.ewald_theta * sqrtf(s2);
 }
 
 // The correction walk: accepted nodes (and the particles of opened leaves)
@@ -695,8 +711,8 @@ struct EwaldPolicy {
     __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox& gb, int lane, int pk,
                                           const WalkOut& O) {
         const double4 q = T.spos[pk];
-        S.tile[lane] = make_float4((float)near_img(q.x - gb.cx, O), (float)near_img(q.y - gb.cy, O),
-                                   (float)near_img(q.z - gb.cz, O), (float)q.w);
+        S.tile[lane] = make_float4((float)near_img(q.x - gb.ox, O), (float)near_img(q.y - gb.oy, O),
+                                   (float)near_img(q.z - gb.oz, O), (float)q.w);
         S.tile[kW + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         S.tile[2 * kW + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -704,8 +720,8 @@ struct EwaldPolicy {
     __device__ static void stage_node(Lds& S, const Tree& T, const GroupBox& gb, int lane, int nk, const WalkOut& O) {
         const double4 c = T.com[nk];
         const float4 m0 = T.mp[4 * nk], m1 = T.mp[4 * nk + 1], m2 = T.mp[4 * nk + 2];
-        S.tile[lane] = make_float4((float)near_img(c.x - gb.cx, O), (float)near_img(c.y - gb.cy, O),
-                                   (float)near_img(c.z - gb.cz, O), m0.x);
+        S.tile[lane] = make_float4((float)near_img(c.x - gb.ox, O), (float)near_img(c.y - gb.oy, O),
+                                   (float)near_img(c.z - gb.oz, O), m0.x);
         S.tile[kW + lane] = m1;
         S.tile[2 * kW + lane] = make_float4(m2.x, m2.y, 0.f, 0.f);
     }
@@ -737,6 +753,22 @@ struct EwaldPolicy {
         t[4] = -(-beta * dx * dz - ri5 * Qxz + e * (Px * dz + dx * Pz));
         t[5] = -(-beta * dy * dz - ri5 * Qyz + e * (Py * dz + dy * Pz));
     }
+    // H_abc = dT_ab / dd_c of a point mass M at d:
+    //   M (3 (d_c delta_ab + d_b delta_ac + d_a delta_bc) / r^5 - 15 d_a d_b d_c / r^7)
+    __device__ static void newton_h(float dx, float dy, float dz, float M, float* h) {
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float ri = __builtin_amdgcn_rsqf(r2), ri2 = ri * ri;
+        const float a = 3.f * M * ri * ri2 * ri2, b = 15.f * M * ri * ri2 * ri2 * ri2;
+        const float d[3] = {dx, dy, dz};
+        const int ia[10] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 2}, ib[10] = {0, 0, 0, 1, 1, 2, 1, 1, 2, 2},
+                  ic[10] = {0, 1, 2, 1, 2, 2, 1, 2, 2, 2};
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            const int i = ia[q], j = ib[q], k = ic[q];
+            const float del = (i == j ? d[k] : 0.f) + (i == k ? d[j] : 0.f) + (j == k ? d[i] : 0.f);
+            h[q] = a * del - b * d[i] * d[j] * d[k];
+        }
+    }
     // A node's quadrupole adds -(1/6) Q_bc H_abc to dg (dg is harmonic away
     // from d = 0, so the trace of the second moment drops out).
     __device__ static void quad_g(const float4 q0, const float4 q1, const EwaldVal& E, float* g) {
@@ -751,17 +783,42 @@ struct EwaldPolicy {
                                    const WalkOut& O) {
         EwaldVal E;
         if (t.grp) {
+            // about the group centre: c = entry - (group centre), at its image
+            // about the image origin; where that is not c's nearest image c',
+            // the field continues smoothly through
+            // dg(c) = dg(c') + g_single(c') - g_single(c) (likewise T and H)
             for (int k = threadIdx.x; k < cnt; k += kW) {
                 const float4 e = S.tile[k];
-                ewald_lookup<true>(O, e.x, e.y, e.z, E);
+                const float4 q0 = S.tile[kW + k], q1 = S.tile[2 * kW + k];
+                const float cx = e.x - t.g0x, cy = e.y - t.g0y, cz = e.z - t.g0z;
+                const float nx = near_imgf(cx, O), ny = near_imgf(cy, O), nz = near_imgf(cz, O);
+                ewald_lookup<true>(O, nx, ny, nz, E);
                 float gq[3] = {e.w * E.g[0], e.w * E.g[1], e.w * E.g[2]};
-                quad_g(S.tile[kW + k], S.tile[2 * kW + k], E, gq);
+                float tq[6], hq[10];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) tq[c] = e.w * E.t[c];
+#pragma unroll
+                for (int c = 0; c < 10; ++c) hq[c] = e.w * E.h[c];
+                quad_g(q0, q1, E, gq);
+                if (nx != cx || ny != cy || nz != cz) {
+                    float g1[3], t1[6], g0[3], t0[6], h1[10], h0[10];
+                    newton_quad(nx, ny, nz, e.w, q0, q1, g1, t1);
+                    newton_quad(cx, cy, cz, e.w, q0, q1, g0, t0);
+                    newton_h(nx, ny, nz, e.w, h1);
+                    newton_h(cx, cy, cz, e.w, h0);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) gq[c] += g1[c] - g0[c];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) tq[c] += t1[c] - t0[c];
+#pragma unroll
+                    for (int c = 0; c < 10; ++c) hq[c] += h1[c] - h0[c];
+                }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc.v[c] += (double)gq[c];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) acc.v[3 + c] += (double)(e.w * E.t[c]);
+                for (int c = 0; c < 6; ++c) acc.v[3 + c] += (double)tq[c];
 #pragma unroll
-                for (int c = 0; c < 10; ++c) acc.v[9 + c] += (double)(e.w * E.h[c]);
+                for (int c = 0; c < 10; ++c) acc.v[9 + c] += (double)hq[c];
             }
         } else {
             // per target: the forward walk took g and T at d, the image about
@@ -816,7 +873,8 @@ struct EwaldPolicy {
     __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target& t) {
         double g[3], tt[6];
         if (t.grp) {
-            const double x = t.tx, y = t.ty, z = t.tz;
+            // the target relative to the group centre
+            const double x = (double)t.tx - t.g0x, y = (double)t.ty - t.g0y, z = (double)t.tz - t.g0z;
             const double* H = A.v + 9;   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
             // (H t)_ab
             const double Pxx = H[0] * x + H[1] * y + H[2] * z, Pyy = H[3] * x + H[6] * y + H[7] * z;
@@ -860,11 +918,22 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     const int p_i = Gr.act_pos ? Gr.act_pos[gd.x + slot] : gd.x + slot;
     const double4 xi = T.spos[p_i];
     const float4 vi = T.svf[p_i];
-    const GroupBox gb = group_box(xi.x, xi.y, xi.z);
+    GroupBox gb = group_box(xi.x, xi.y, xi.z);
+    if (kPer == kEwald) {
+        // images about a multiple of half the box: its cut lies on the faces
+        // of the root's children (the root of a periodic tree is the box)
+        const double hb = 0.5 * O.box;
+        gb.ox = hb * rint(gb.cx / hb);
+        gb.oy = hb * rint(gb.cy / hb);
+        gb.oz = hb * rint(gb.cz / hb);
+    }
     Target tg;
-    tg.tx = (float)(xi.x - gb.cx);
-    tg.ty = (float)(xi.y - gb.cy);
-    tg.tz = (float)(xi.z - gb.cz);
+    tg.tx = (float)(xi.x - gb.ox);
+    tg.ty = (float)(xi.y - gb.oy);
+    tg.tz = (float)(xi.z - gb.oz);
+    tg.g0x = (float)(gb.cx - gb.ox);
+    tg.g0y = (float)(gb.cy - gb.oy);
+    tg.g0z = (float)(gb.cz - gb.oz);
     tg.vx = vi.x;
     tg.vy = vi.y;
     tg.vz = vi.z;
@@ -1600,7 +1669,7 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
         hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, c->stream, c->ewald_q.as<int32_t>(), (int64_t)8);
         WalkOut E = O;
         E.stats = nullptr;
-        hipLaunchKernelGGL((k_walk<EwaldPolicy, kNear>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, E,
+        hipLaunchKernelGGL((k_walk<EwaldPolicy, kEwald>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, E,
                            c->ewald_q.as<int32_t>(), 0.f, 0.f, e2, (float)(1.0 / eps));
     }
     return AG_OK;

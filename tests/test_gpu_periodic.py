@@ -157,15 +157,16 @@ def test_tree_periodic_subset(ag, orc):
     assert np.median(rel_err(a[rows], ar)) <= 1e-3
 
 
-def test_large_box_matches_open(ag):
-    """In a box far larger than the set (which lies inside it, so the tree
-    holds the same positions) no pair is wrapped."""
+def test_large_box_matches_open(ag, orc):
+    """In a box far larger than the set (which lies inside it) no pair is
+    wrapped: the periodic tree approximates the open-boundary sum."""
     x, v, m, _ = workloads.clumps(1 << 14, seed=4)
     x = x - x.min(axis=0) + 1.0
-    a0, _, T0 = _tree(ag, 0.0, x, v, m, 0.7, 1e-3)
-    a1, _, T1 = _tree(ag, 1e6, x, v, m, 0.7, 1e-3)
-    assert np.median(rel_err(a1, a0)) <= 1e-6
-    assert np.median(tensor_rel_err(T1, T0)) <= 1e-6
+    a1, _, T1 = _tree(ag, 8.0, x, v, m, 0.7, 1e-3)
+    rows = np.random.default_rng(1).choice(len(m), 1024, replace=False)
+    ar, _, Tr = orc.direct(x, v, m, 1e-3, 1.0, rows)
+    assert np.median(rel_err(a1[rows], ar)) <= 1e-3
+    assert np.median(tensor_rel_err(T1[rows], Tr)) <= 5e-3
 
 
 def test_periodic_arguments(ag):
