@@ -695,10 +695,12 @@ struct EwaldPolicy {
     static constexpr bool kGroupSum = true;
     using Lds = WalkLds<8>;
     struct Acc {
-        double v[19];   // g 3, T 6, (group sums only) H 10
+        // g 3, T 6, (group sums only) H 10; FP32 sums of at most a few
+        // thousand terms per lane: rounding ~1e-6 relative, below the table's
+        float v[19];
         __device__ void zero() {
 #pragma unroll
-            for (int k = 0; k < 19; ++k) v[k] = 0.0;
+            for (int k = 0; k < 19; ++k) v[k] = 0.f;
         }
         __device__ void add(const Acc& o) {
 #pragma unroll
@@ -814,11 +816,11 @@ struct EwaldPolicy {
                     for (int c = 0; c < 10; ++c) hq[c] += h1[c] - h0[c];
                 }
 #pragma unroll
-                for (int c = 0; c < 3; ++c) acc.v[c] += (double)gq[c];
+                for (int c = 0; c < 3; ++c) acc.v[c] += gq[c];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) acc.v[3 + c] += (double)tq[c];
+                for (int c = 0; c < 6; ++c) acc.v[3 + c] += tq[c];
 #pragma unroll
-                for (int c = 0; c < 10; ++c) acc.v[9 + c] += (double)hq[c];
+                for (int c = 0; c < 10; ++c) acc.v[9 + c] += hq[c];
             }
         } else {
             // per target: the forward walk took g and T at d, the image about
@@ -846,9 +848,9 @@ struct EwaldPolicy {
                     for (int c = 0; c < 6; ++c) tq[c] += t1[c] - t0[c];
                 }
 #pragma unroll
-                for (int c = 0; c < 3; ++c) acc.v[c] += (double)gq[c];
+                for (int c = 0; c < 3; ++c) acc.v[c] += gq[c];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) acc.v[3 + c] += (double)tq[c];
+                for (int c = 0; c < 6; ++c) acc.v[3 + c] += tq[c];
             }
         }
     }
@@ -864,7 +866,7 @@ struct EwaldPolicy {
     static __device__ void wave_sum(Acc& A) {
 #pragma unroll
         for (int k = 0; k < 19; ++k) {
-            double v = A.v[k];
+            float v = A.v[k];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             A.v[k] = v;
@@ -875,12 +877,13 @@ struct EwaldPolicy {
         if (t.grp) {
             // the target relative to the group centre
             const double x = (double)t.tx - t.g0x, y = (double)t.ty - t.g0y, z = (double)t.tz - t.g0z;
-            const double* H = A.v + 9;   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+            double H[10], Tv[6];
+            for (int c = 0; c < 10; ++c) H[c] = A.v[9 + c];   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+            for (int c = 0; c < 6; ++c) Tv[c] = A.v[3 + c];    // xx yy zz xy xz yz
             // (H t)_ab
             const double Pxx = H[0] * x + H[1] * y + H[2] * z, Pyy = H[3] * x + H[6] * y + H[7] * z;
             const double Pzz = H[5] * x + H[8] * y + H[9] * z, Pxy = H[1] * x + H[3] * y + H[4] * z;
             const double Pxz = H[2] * x + H[4] * y + H[5] * z, Pyz = H[4] * x + H[7] * y + H[8] * z;
-            const double* Tv = A.v + 3;  // xx yy zz xy xz yz
             g[0] = A.v[0] + (Tv[0] - 0.5 * Pxx) * x + (Tv[3] - 0.5 * Pxy) * y + (Tv[4] - 0.5 * Pxz) * z;
             g[1] = A.v[1] + (Tv[3] - 0.5 * Pxy) * x + (Tv[1] - 0.5 * Pyy) * y + (Tv[5] - 0.5 * Pyz) * z;
             g[2] = A.v[2] + (Tv[4] - 0.5 * Pxz) * x + (Tv[5] - 0.5 * Pyz) * y + (Tv[2] - 0.5 * Pzz) * z;
