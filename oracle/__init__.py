@@ -10,7 +10,8 @@ routine of the same name in ``oracle.c`` (built into ``liboracle.so`` by
   the jerk (the particle discretisation of the jerk integral, Eq. 5) and the
   tidal tensor (whose Frobenius norm enters Eq. 7); optionally in a periodic
   cube with every pair at its nearest image (how the paper treats the jerk
-  of periodic problems, Sec. 4).
+  of periodic problems, Sec. 4); :func:`direct_soft` with a softening length
+  per particle (each pair takes the mean of its two kernels).
 * :func:`timestep` -- the tidal timestep of Eq. 7 and its power-of-two bin.
 * :func:`select` -- force-age counter (Eq. 3) and update condition (Eq. 4).
 * :func:`predict` -- jerk predictor (Eq. 6) in closed form ``a0 + j (t - t0)``.
@@ -66,6 +67,7 @@ def _load():
         lib.orc_field_box.argtypes = [I64, P, P, P, D, D, D, I64, P, P, P, P, P, P]
         lib.orc_direct_box.argtypes = [I64, P, P, P, D, D, D, I64, P, P, P, P]
         lib.orc_abs_scale_box.argtypes = [I64, P, P, D, D, D, I64, P, P]
+        lib.orc_field_soft.argtypes = [I64, P, P, P, P, D, I64, P, P, P, P, P, P, P]
         lib.orc_ewald_unit.argtypes = [I64, P, D, D, ctypes.c_int, ctypes.c_int, P, P, P, P]
         lib.orc_direct_ewald.argtypes = [I64, P, P, P, D, D, D, I64, P, P, P, P]
         lib.orc_timestep.argtypes = [I64, P, D, D, ctypes.c_int32, P, P]
@@ -150,6 +152,27 @@ def direct(x, v, m, eps, G, targets=None, box=0.0, ewald=False):
     else:
         _load().orc_direct_box(n, _ptr(x), _ptr(v), _ptr(m), float(eps), float(G), float(box), k,
                                _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(tid))
+    return acc, jerk, tid
+
+
+def direct_soft(x, v, m, h, G, targets=None):
+    """Direct sum with per-particle softening lengths h (n,): each pair's
+    kernel is the mean of its two particles' kernels.  At particles
+    ``targets`` (default: all), self excluded."""
+    x = _f64(x, (-1, 3))
+    v = _f64(v, (-1, 3))
+    m = _f64(m).ravel()
+    h = _f64(h).ravel()
+    n = x.shape[0]
+    tgt = np.arange(n, dtype=np.int64) if targets is None else \
+        np.ascontiguousarray(targets, dtype=np.int64)
+    k = tgt.size
+    p = np.ascontiguousarray(x[tgt])
+    pv = np.ascontiguousarray(v[tgt])
+    hp = np.ascontiguousarray(h[tgt])
+    acc, jerk, tid = np.empty((k, 3)), np.empty((k, 3)), np.empty((k, 6))
+    _load().orc_field_soft(n, _ptr(x), _ptr(v), _ptr(m), _ptr(h), float(G), k, _ptr(p), _ptr(pv), _ptr(hp),
+                           _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(tid))
     return acc, jerk, tid
 
 

@@ -218,6 +218,56 @@ void orc_abs_scale(int64_t n, const double *x, const double *m, double eps, doub
     orc_abs_scale_box(n, x, m, eps, G, 0.0, ntgt, tgt, scale);
 }
 
+/* ---- per-particle softening ---------------------------------------------- */
+/*
+ * Softening lengths that differ between particles (the paper's fully
+ * adaptive softening, Sec. 4, with the lengths given): the pair kernel is
+ * the mean of the two particles' kernels, so the pair force stays equal and
+ * opposite,
+ *   f_ij = (f(r, h_i) + f(r, h_j)) / 2,   D_ij = (D(r, h_i) + D(r, h_j)) / 2,
+ * and g, j, T follow from f_ij and D_ij exactly as with one softening.
+ * hs (n) holds the sources' lengths, hp (np) the probes'.
+ */
+void orc_field_soft(int64_t n, const double *x, const double *v, const double *m, const double *hs,
+                    double G, int64_t np, const double *p, const double *pv, const double *hp,
+                    const int64_t *excl, double *acc, double *jerk, double *tidal)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < np; ++k) {
+        double px = p[3 * k], py = p[3 * k + 1], pz = p[3 * k + 2];
+        double qx = pv[3 * k], qy = pv[3 * k + 1], qz = pv[3 * k + 2];
+        int64_t skip = excl ? excl[k] : -1;
+        double ax = 0, ay = 0, az = 0, jx = 0, jy = 0, jz = 0;
+        double txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == skip) continue;
+            double dx = x[3 * j] - px, dy = x[3 * j + 1] - py, dz = x[3 * j + 2] - pz;
+            double nx = v[3 * j] - qx, ny = v[3 * j + 1] - qy, nz = v[3 * j + 2] - qz;
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double f1, D1, f2, D2;
+            kernel_fd(r, hp[k], &f1, &D1);
+            kernel_fd(r, hs[j], &f2, &D2);
+            double f = 0.5 * (f1 + f2), D = 0.5 * (D1 + D2);
+            double mj = m[j];
+            double dn = dx * nx + dy * ny + dz * nz;
+            ax += mj * f * dx; ay += mj * f * dy; az += mj * f * dz;
+            jx += mj * (f * nx + D * dn * dx);
+            jy += mj * (f * ny + D * dn * dy);
+            jz += mj * (f * nz + D * dn * dz);
+            txx -= mj * (f + D * dx * dx);
+            tyy -= mj * (f + D * dy * dy);
+            tzz -= mj * (f + D * dz * dz);
+            txy -= mj * (D * dx * dy);
+            txz -= mj * (D * dx * dz);
+            tyz -= mj * (D * dy * dz);
+        }
+        acc[3 * k] = G * ax; acc[3 * k + 1] = G * ay; acc[3 * k + 2] = G * az;
+        jerk[3 * k] = G * jx; jerk[3 * k + 1] = G * jy; jerk[3 * k + 2] = G * jz;
+        tidal[6 * k] = G * txx; tidal[6 * k + 1] = G * tyy; tidal[6 * k + 2] = G * tzz;
+        tidal[6 * k + 3] = G * txy; tidal[6 * k + 4] = G * txz; tidal[6 * k + 5] = G * tyz;
+    }
+}
+
 /* ---- Ewald summation in a periodic cube ----------------------------------- */
 #define ORC_PI 3.14159265358979323846
 /*

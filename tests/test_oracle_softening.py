@@ -1,0 +1,62 @@
+"""Pins of the oracle's direct sum with a softening length per particle
+(each pair takes the mean of its two particles' kernels): it reduces bit for
+bit to the single-length sum, keeps the pair forces equal and opposite,
+satisfies the Poisson identity with the mean kernel, and its T and j are
+finite differences of its g."""
+import numpy as np
+
+import workloads
+from test_oracle_field import W_m4, sym6
+
+
+def _set(n, seed):
+    x, v, m = workloads.plummer(n, seed=seed)
+    h = np.exp(np.random.default_rng(seed).uniform(np.log(0.02), np.log(0.3), n))
+    return x, v, m, h
+
+
+def test_equal_lengths_reduce_to_single_softening(orc):
+    x, v, m, _ = _set(300, 1)
+    h = np.full(len(m), 0.07)
+    for a, b in zip(orc.direct_soft(x, v, m, h, 1.3), orc.direct(x, v, m, 0.07, 1.3)):
+        assert np.array_equal(a, b)
+
+
+def test_pair_forces_equal_and_opposite(orc):
+    x, v, m, h = _set(400, 2)
+    a, j, _ = orc.direct_soft(x, v, m, h, 1.0)
+    sa = np.sum(m[:, None] * np.abs(a))
+    assert np.max(np.abs((m[:, None] * a).sum(0))) < 1e-13 * sa
+    assert np.max(np.abs((m[:, None] * j).sum(0))) < 1e-12 * np.sum(m[:, None] * np.abs(j))
+    # and the one-sided choice (the target's own length only) is not
+    a1 = np.stack([orc.direct(x, v, m, h[i], 1.0, [i])[0][0] for i in range(40)])
+    assert np.max(np.abs(a1 - a[:40])) > 1e-6
+
+
+def test_poisson_identity_mean_kernel(orc):
+    """tr T_i = -4 pi G sum_j m_j (W(r, h_i) + W(r, h_j)) / 2."""
+    x, v, m, h = _set(250, 3)
+    _, _, T = orc.direct_soft(x, v, m, h, 1.0)
+    r = np.linalg.norm(x[None, :, :] - x[:, None, :], axis=2)
+    W = 0.5 * (W_m4(r, h[:, None]) + W_m4(r, h[None, :]))
+    np.fill_diagonal(W, 0.0)
+    ref = -4 * np.pi * (W * m[None, :]).sum(1)
+    np.testing.assert_allclose(T[:, 0] + T[:, 1] + T[:, 2], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+def test_tide_and_jerk_are_derivatives(orc):
+    x, v, m, h = _set(120, 4)
+    a, j, T = orc.direct_soft(x, v, m, h, 1.0)
+    d = 1e-6
+    for i in (0, 7, 50):
+        for b in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, b] += d
+            xm[i, b] -= d
+            ap = orc.direct_soft(xp, v, m, h, 1.0, [i])[0][0]
+            am = orc.direct_soft(xm, v, m, h, 1.0, [i])[0][0]
+            np.testing.assert_allclose((ap - am) / (2 * d), sym6(T)[i][:, b], rtol=1e-5,
+                                       atol=1e-6 * np.abs(T[i]).max())
+    ap = orc.direct_soft(x + d * v, v, m, h, 1.0)[0]
+    am = orc.direct_soft(x - d * v, v, m, h, 1.0)[0]
+    np.testing.assert_allclose((ap - am) / (2 * d), j, rtol=1e-5, atol=1e-6 * np.abs(j).max())
