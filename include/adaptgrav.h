@@ -115,6 +115,22 @@ enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 
        AG_OPT_GROUP_TARGETS = 5, AG_OPT_EWALD_OPEN = 6 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
+/* Per-particle softening lengths (Sec. 4: the paper's runs soften each
+ * element with its own, adaptive, length; here the lengths are given).
+ * h (n,) device FP64 in input order, copied at once (the caller may reuse
+ * it after the stream passes this call).  Every pair's kernel is then the
+ * mean of its two particles' M4 kernels, f = (f(r, h_i) + f(r, h_j)) / 2 and
+ * likewise D, so pair forces stay equal and opposite; a tree node acts as a
+ * multipole only beyond the largest length among its particles and the
+ * group's targets.  Applies to trees built after the call and to
+ * ag_grav_direct; the eps argument of the evaluations is then only
+ * validated.  A later build or direct sum over a different number of
+ * particles gives AG_ESTATE; ag_grav_backward on such a tree gives
+ * AG_ESTATE.  Lengths that are not positive and finite raise the device
+ * flag (AG_ENONFINITE at the next sync).  h = NULL or n = 0 returns to one
+ * length per evaluation (eps). */
+int ag_set_softening(ag_ctx *ctx, int64_t n, const double *h);
+
 /* Periodic boundaries (Sec. 4: the periodic problem's gravity uses Ewald
  * sums, its jerk only the nearest image).  box > 0 makes every later
  * ag_grav_eval, ag_grav_eval_batched and (ewald = 0 only) ag_grav_direct on

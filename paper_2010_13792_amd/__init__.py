@@ -37,7 +37,7 @@ ENTRY_POINTS = [
     "ag_grav_eval_batched", "ag_grav_direct", "ag_grav_timestep", "ag_adaptive_select",
     "ag_grav_predict", "ag_grav_backward", "ag_timing_enable", "ag_timing_read",
     "ag_kick_drift", "ag_set_option", "ag_graph_begin", "ag_graph_end", "ag_graph_replay",
-    "ag_force_log", "ag_grav_predict_poly", "ag_set_periodic",
+    "ag_force_log", "ag_grav_predict_poly", "ag_set_periodic", "ag_set_softening",
 ]
 AG_PRED_MAX_DEPTH = 4
 AG_OPT_WALK_WAVES_PER_CU = 1
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "ag_kick_drift": [P, I64, P, P, P, D, D],
         "ag_set_option": [P, I32, I64],
         "ag_set_periodic": [P, D, I32],
+        "ag_set_softening": [P, I64, P],
         "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
         "ag_force_log": [P, I64, P, I64, I32, P, D, P, P, P],
@@ -304,6 +305,13 @@ class Context:
                                     _ptr(jerk, torch.float64, (3,), "jerk", n),
                                     _ptr(t0, torch.float64, None, "t0", n), float(t),
                                     _ptr(acc_out, torch.float64, (3,), "acc_out", n)))
+
+    def set_softening(self, h=None):
+        """Per-particle softening lengths (device float64 (n,)); None clears."""
+        if h is None:
+            _check(_lib.ag_set_softening(self._h, 0, None))
+            return
+        _check(_lib.ag_set_softening(self._h, h.shape[0], _ptr(h, torch.float64, None, "h")))
 
     def set_periodic(self, box: float, ewald: bool = False):
         """Periodic cube of side ``box`` (0: open): nearest-image pairs, or

@@ -189,7 +189,7 @@ extern "C" int ag_destroy(ag_ctx* c) {
                       &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
                       &c->nd_64, &c->nd_w, &c->nd_wf, &c->in_list, &c->in_cnt, &c->in_off,
                       &c->tree_hdr, &c->lvl_list, &c->leaf_list, &c->child, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
-                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->ewald_tab, &c->ewald_q, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
+                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->ewald_tab, &c->ewald_q, &c->soft_h, &c->soft_s, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
                       &c->direct_part, &c->tmp_tidal, &c->sel_flag, &c->sel_off, &c->stats, &c->dflags};
     for (DevBuf* b : bufs) ag_release(*b);
     for (PhaseEvents& p : c->timing.pending) {
@@ -254,6 +254,9 @@ static int build_common(ag_ctx* c, int64_t n, const double* x, const double* v, 
     if (n_leaf < 1 || n_leaf > 64) return ag_fail(AG_EINVAL, "n_leaf must be in [1, 64] (got %d)", n_leaf);
     if (n_sys < 1 || n_sys > AG_MAX_SYS) return ag_fail(AG_EINVAL, "n_sys must be in [1, %d]", AG_MAX_SYS);
     if (batched && !offs) return ag_fail(AG_EINVAL, "sys_offsets must be non-null");
+    if (c->soft_n > 0 && c->soft_n != n)
+        return ag_fail(AG_ESTATE, "softening lengths were set for %lld particles, not %lld", (long long)c->soft_n,
+                       (long long)n);
     DeviceGuard g(c->device);
     c->built = false;
     c->host_n_nodes = -1;
@@ -356,6 +359,9 @@ extern "C" int ag_grav_direct(ag_ctx* c, int64_t n, const double* x, const doubl
     if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
     if (precision != AG_FP64 && precision != AG_FP32_PAIRS) return ag_fail(AG_EINVAL, "unknown precision %d", precision);
     if (c->ewald) return ag_fail(AG_ESTATE, "direct summation has no Ewald form (use ag_grav_eval with theta = 0)");
+    if (c->soft_n > 0 && c->soft_n != n)
+        return ag_fail(AG_ESTATE, "softening lengths were set for %lld particles, not %lld", (long long)c->soft_n,
+                       (long long)n);
     if (n_act < 0 || n_act > n) return ag_fail(AG_EINVAL, "n_active out of range");
     if (!idx && n_act != n) return ag_fail(AG_EINVAL, "active_idx = NULL requires n_active = n");
     if (n_act == 0) return AG_OK;
@@ -439,6 +445,30 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
         default:
             return ag_fail(AG_EINVAL, "unknown option %d", option);
     }
+}
+
+// softening lengths that are not positive and finite raise the device flag
+__global__ void k_check_soft(int64_t n, const double* __restrict__ h, int32_t* __restrict__ flags) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!(h[i] > 0.0) || !isfinite(h[i])) atomicOr(flags, AGF_NONFINITE);
+}
+
+extern "C" int ag_set_softening(ag_ctx* c, int64_t n, const double* h) {
+    AG_TRY(check_ctx(c));
+    if (!h || n == 0) {
+        c->soft_n = 0;
+        return AG_OK;
+    }
+    if (n < 0 || n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n must be in [0, 2^30]");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_ensure(c->soft_h, (size_t)n * sizeof(double)));
+    AG_HIP(hipMemcpyAsync(c->soft_h.p, h, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_check_soft, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, c->soft_h.as<double>(),
+                       c->dflags.as<int32_t>());
+    c->soft_n = n;
+    return check_launch("set softening");
 }
 
 extern "C" int ag_set_periodic(ag_ctx* c, double box, int32_t ewald) {
@@ -532,6 +562,7 @@ extern "C" int ag_grav_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, co
     AG_TRY(check_eval_args(c, idx, n_act, theta, eps, G));
     if (c->batched) return ag_fail(AG_ESTATE, "backward is not available for a batched tree");
     if (c->box > 0.0) return ag_fail(AG_ESTATE, "backward is not available with periodic boundaries");
+    if (c->tree_soft) return ag_fail(AG_ESTATE, "backward is not available with per-particle softening");
     if (!w || !dLdx || !dLdm) return ag_fail(AG_EINVAL, "w, dLdx and dLdm must be non-null");
     DeviceGuard g(c->device);
     AG_TRY(ag_launch_backward(c, idx, n_act, w, theta, eps, G, dLdx, dLdm));

@@ -76,6 +76,8 @@ struct ag_ctx {
     int ewald_open = 4;   // correction walk: opening angle 1 / ewald_open against the image points
     double ewald_tab_box = 0.0;   // box the Ewald table was built for
     double tree_box = 0.0;        // periodic box the tree was built in (positions wrapped into it)
+    int64_t soft_n = 0;           // per-particle softening lengths set for this many particles (0: none)
+    bool tree_soft = false;       // the current tree carries them
     int group_cap = 64;
     bool capturing = false;
     hipGraph_t graph = nullptr;
@@ -126,6 +128,8 @@ struct ag_ctx {
     DevBuf act_pos;               // i32 [n]: active sorted positions, ascending
     DevBuf act_off;               // i32 [n+1]: exclusive scan of act_flag
     DevBuf grp;                   // int4 [max groups]: start, count, system, -
+    DevBuf soft_h;                // f64 per-particle softening lengths, input order
+    DevBuf soft_s;                // f32 the same in key order (rounded up)
     DevBuf ewald_tab;             // f32 Ewald correction table (5 float4 per point)
     DevBuf ewald_q;               // i32 [8]: correction walk work-queue counters
     DevBuf grp_hdr;               // i32: [0] number of groups, [8..15] walk work-queue counters

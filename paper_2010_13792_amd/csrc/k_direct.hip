@@ -14,6 +14,9 @@
 //
 // Periodic cube of side L (kPer): d is replaced by its nearest image
 // d - L rint(d / L), in FP64, before anything else.
+//
+// Per-particle softening (kSoft): each pair's f and D are the means of the
+// target's and the source's kernels (hs, input order).
 #include "ag_internal.h"
 #include "pair.h"
 
@@ -24,10 +27,11 @@ constexpr int kParts = 12;       // g (3), j (3), S (6)
 
 __device__ __forceinline__ double near_img(double d, double L) { return d - L * rint(d / L); }
 
-template <bool kFP64, bool kPer>
+template <bool kFP64, bool kPer, bool kSoft>
 __global__ void __launch_bounds__(kT) k_direct(int64_t n, const double* __restrict__ x,
                                                const double* __restrict__ v,
                                                const double* __restrict__ m,
+                                               const double* __restrict__ hs,
                                                const int32_t* __restrict__ idx, int64_t n_act,
                                                double h, double L, int64_t chunk,
                                                double* __restrict__ part,
@@ -36,6 +40,7 @@ __global__ void __launch_bounds__(kT) k_direct(int64_t n, const double* __restri
     __shared__ float s_vx[kT], s_vy[kT], s_vz[kT];
     __shared__ double s_dvx[kFP64 ? kT : 1], s_dvy[kFP64 ? kT : 1], s_dvz[kFP64 ? kT : 1];
     __shared__ double s_m[kT];
+    __shared__ double s_h[kSoft ? kT : 1];
 
     const int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x;
     const bool live = k < n_act;
@@ -47,10 +52,11 @@ __global__ void __launch_bounds__(kT) k_direct(int64_t n, const double* __restri
             i = -1;
         }
     }
-    double xi = 0, yi = 0, zi = 0, vxi = 0, vyi = 0, vzi = 0;
+    double xi = 0, yi = 0, zi = 0, vxi = 0, vyi = 0, vzi = 0, hi_ = 1.0;
     if (i >= 0) {
         xi = x[3 * i]; yi = x[3 * i + 1]; zi = x[3 * i + 2];
         vxi = v[3 * i]; vyi = v[3 * i + 1]; vzi = v[3 * i + 2];
+        if (kSoft) hi_ = hs[i];
     }
     const int64_t j0 = (int64_t)blockIdx.y * chunk;
     const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
@@ -69,6 +75,7 @@ __global__ void __launch_bounds__(kT) k_direct(int64_t n, const double* __restri
             s_y[threadIdx.x] = x[3 * js + 1];
             s_z[threadIdx.x] = x[3 * js + 2];
             s_m[threadIdx.x] = m[js];
+            if (kSoft) s_h[threadIdx.x] = hs[js];
             if (kFP64) {
                 s_dvx[threadIdx.x] = v[3 * js];
                 s_dvy[threadIdx.x] = v[3 * js + 1];
@@ -91,8 +98,12 @@ __global__ void __launch_bounds__(kT) k_direct(int64_t n, const double* __restri
                     dy = near_img(dy, L);
                     dz = near_img(dz, L);
                 }
-                pair_interact<double>(dx, dy, dz, s_dvx[q] - vxi, s_dvy[q] - vyi, s_dvz[q] - vzi, mj, h2, hinv,
-                                      A);
+                if (kSoft)
+                    pair_interact_soft<double>(dx, dy, dz, s_dvx[q] - vxi, s_dvy[q] - vyi, s_dvz[q] - vzi, mj, hi_,
+                                               s_h[q], A);
+                else
+                    pair_interact<double>(dx, dy, dz, s_dvx[q] - vxi, s_dvy[q] - vyi, s_dvz[q] - vzi, mj, h2,
+                                          hinv, A);
             }
         } else {
             PairAcc<float> B;
@@ -105,8 +116,12 @@ __global__ void __launch_bounds__(kT) k_direct(int64_t n, const double* __restri
                     dy = near_img(dy, L);
                     dz = near_img(dz, L);
                 }
-                pair_interact<float>((float)dx, (float)dy, (float)dz, s_vx[q] - vxf, s_vy[q] - vyf,
-                                     s_vz[q] - vzf, mj, h2f, hinvf, B);
+                if (kSoft)
+                    pair_interact_soft<float>((float)dx, (float)dy, (float)dz, s_vx[q] - vxf, s_vy[q] - vyf,
+                                              s_vz[q] - vzf, mj, (float)hi_, (float)s_h[q], B);
+                else
+                    pair_interact<float>((float)dx, (float)dy, (float)dz, s_vx[q] - vxf, s_vy[q] - vyf,
+                                         s_vz[q] - vzf, mj, h2f, hinvf, B);
             }
             A.ax += B.ax; A.ay += B.ay; A.az += B.az;
             A.jx += B.jx; A.jy += B.jy; A.jz += B.jz;
@@ -173,18 +188,19 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
     const double L = c->box;
     int32_t* fl = c->dflags.as<int32_t>();
     hipStream_t st = c->stream;
-    if (precision == AG_FP64 && L > 0.0)
-        hipLaunchKernelGGL((k_direct<true, true>), grid, dim3(kT), 0, st, n, x, v, m, idx, n_act, eps, L, chunk,
-                           part, fl);
-    else if (precision == AG_FP64)
-        hipLaunchKernelGGL((k_direct<true, false>), grid, dim3(kT), 0, st, n, x, v, m, idx, n_act, eps, L, chunk,
-                           part, fl);
-    else if (L > 0.0)
-        hipLaunchKernelGGL((k_direct<false, true>), grid, dim3(kT), 0, st, n, x, v, m, idx, n_act, eps, L, chunk,
-                           part, fl);
-    else
-        hipLaunchKernelGGL((k_direct<false, false>), grid, dim3(kT), 0, st, n, x, v, m, idx, n_act, eps, L, chunk,
-                           part, fl);
+    const bool fp64 = precision == AG_FP64, per = L > 0.0, soft = c->soft_n > 0;
+    const double* hs = soft ? c->soft_h.as<double>() : nullptr;
+#define AG_DIRECT(A, B, C)                                                                                       \
+    hipLaunchKernelGGL((k_direct<A, B, C>), grid, dim3(kT), 0, st, n, x, v, m, hs, idx, n_act, eps, L, chunk, part, \
+                       fl)
+    if (fp64) {
+        if (per) { if (soft) AG_DIRECT(true, true, true); else AG_DIRECT(true, true, false); }
+        else { if (soft) AG_DIRECT(true, false, true); else AG_DIRECT(true, false, false); }
+    } else {
+        if (per) { if (soft) AG_DIRECT(false, true, true); else AG_DIRECT(false, true, false); }
+        else { if (soft) AG_DIRECT(false, false, true); else AG_DIRECT(false, false, false); }
+    }
+#undef AG_DIRECT
     int64_t rb = (n_act + 255) / 256;
     if (rb > 4096) rb = 4096;
     hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)rb), dim3(256), 0, c->stream, n, idx, n_act,

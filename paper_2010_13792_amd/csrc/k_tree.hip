@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restr
 __global__ void k_to_sorted(int64_t n, const int32_t* __restrict__ rank, const double* __restrict__ x,
                             const double* __restrict__ v, const double* __restrict__ m,
                             double4* __restrict__ spos, double4* __restrict__ svel, float4* __restrict__ svf,
-                            double pbox) {
+                            double pbox, const double* __restrict__ h, float* __restrict__ sh) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t p = rank[i];
@@ -352,6 +352,7 @@ __global__ void k_to_sorted(int64_t n, const int32_t* __restrict__ rank, const d
         spos[p] = make_double4(in_box(x[3 * i], pbox), in_box(x[3 * i + 1], pbox), in_box(x[3 * i + 2], pbox), mi);
         svel[p] = make_double4(vx, vy, vz, 0.0);
         svf[p] = make_float4((float)vx, (float)vy, (float)vz, (float)mi);
+        if (h) sh[p] = f_up(h[i]);   // per-particle softening, rounded up
     }
 }
 
@@ -696,8 +697,11 @@ __global__ void k_tree_close(int nblk, const int32_t* __restrict__ blk_max, int6
 // nd_64 layout per node (25 doubles): M, c(3), u(3), Q(6), Qd(6), lo(3), hi(3)
 constexpr int kM64 = 25;
 
+// lo4.w holds the largest softening length in the node (0 without
+// per-particle softening)
 __device__ void store_node(int64_t id, const double* r, double4* __restrict__ com, float4* __restrict__ lo4,
-                           float4* __restrict__ hi4, float4* __restrict__ mp, double* __restrict__ m64) {
+                           float4* __restrict__ hi4, float4* __restrict__ mp, double* __restrict__ m64,
+                           float hmax) {
     double* o = m64 + id * kM64;
 #pragma unroll
     for (int k = 0; k < kM64; ++k) o[k] = r[k];
@@ -708,7 +712,7 @@ __device__ void store_node(int64_t id, const double* r, double4* __restrict__ co
         L = e > L ? e : L;
     }
     com[id] = make_double4(r[1], r[2], r[3], L);
-    lo4[id] = make_float4(f_down(r[19]), f_down(r[20]), f_down(r[21]), 0.f);
+    lo4[id] = make_float4(f_down(r[19]), f_down(r[20]), f_down(r[21]), hmax);
     hi4[id] = make_float4(f_up(r[22]), f_up(r[23]), f_up(r[24]), 0.f);
     float4* q = mp + 4 * id;
     q[0] = make_float4((float)r[0], (float)r[4], (float)r[5], (float)r[6]);
@@ -810,6 +814,7 @@ struct NodeOut {
     float4* hi4;
     float4* mp;
     double* m64;
+    const float* sh;   // sorted softening lengths, or null
 };
 
 // sums over the eight lanes of one inner node (one lane per octant)
@@ -858,16 +863,18 @@ __global__ void k_leaf_moments(const int64_t* __restrict__ hdr, const int32_t* _
         const int4 L = link[id];
         MomentSums S;
         S.init();
+        float hm = 0.f;
         for (int q = L.y; q < L.y + L.z; ++q) {
             const double4 a = spos[q];
             const double4 u = svel[q];
             const double x[3] = {a.x, a.y, a.z}, v[3] = {u.x, u.y, u.z};
             S.add(a.w, x, v);
             S.box(x, x);
+            if (O.sh) hm = fmaxf(hm, O.sh[q]);
         }
         double r[kM64];
         S.finish(r);
-        store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64);
+        store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64, hm);
     }
 }
 
@@ -965,10 +972,14 @@ __global__ void __launch_bounds__(kThreads) k_inner_level(int level, const int32
             S.box(cm + 19, cm + 22);
         }
         oct_reduce(S);
+        float hm = ch >= 0 ? O.lo4[ch].w : 0.f;
+        hm = fmaxf(hm, __shfl_xor(hm, 1, 8));
+        hm = fmaxf(hm, __shfl_xor(hm, 2, 8));
+        hm = fmaxf(hm, __shfl_xor(hm, 4, 8));
         if (oct == 0) {
             double r[kM64];
             S.finish(r);
-            store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64);
+            store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64, hm);
         }
     }
 }
@@ -987,7 +998,7 @@ int grid_for(int64_t n, int threads = kThreads) {
 int moments_pass(ag_ctx* c) {
     hipStream_t st = c->stream;
     NodeOut O{c->nd_com.as<double4>(), c->nd_lo.as<float4>(), c->nd_hi.as<float4>(), c->nd_mp.as<float4>(),
-              c->nd_64.as<double>()};
+              c->nd_64.as<double>(), c->tree_soft ? c->soft_s.as<float>() : nullptr};
     const int64_t n = c->n;
     hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(n / 4 + 1)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
                        c->leaf_list.as<int32_t>(), c->nd_link.as<int4>(), c->spos.as<double4>(),
@@ -1092,8 +1103,11 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     }
 
     // 4. particle data into key order
+    c->tree_soft = c->soft_n > 0;
+    if (c->tree_soft) AG_TRY(ag_ensure(c->soft_s, (size_t)n * sizeof(float)));
     hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rank, x, v, m,
-                       c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->box);
+                       c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->box,
+                       c->tree_soft ? c->soft_h.as<double>() : nullptr, c->soft_s.as<float>());
     c->tree_box = c->box;
 
     // 5. topology
@@ -1131,6 +1145,7 @@ int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m
     const int64_t n = c->n;
     PhaseScope phase(c, AG_PHASE_BUILD);
     hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, c->rank.as<int32_t>(), x,
-                       v, m, c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->tree_box);
+                       v, m, c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->tree_box,
+                       c->tree_soft ? c->soft_h.as<double>() : nullptr, c->soft_s.as<float>());
     return moments_pass(c);
 }

@@ -65,6 +65,7 @@ struct Tree {
     const int32_t* __restrict__ sys_root;
     const double4* __restrict__ ws;    // adjoint: sorted weights (w, 1 if charged)
     const float4* __restrict__ wf;     // adjoint: node charges, 4 per node
+    const float* __restrict__ sh;      // sorted per-particle softening lengths, or null
 };
 
 struct Groups {
@@ -278,7 +279,20 @@ struct Target {
     int p;                 // sorted position
     bool grp;              // Ewald correction summed once for the whole group
     float g0x, g0y, g0z;   // group centre relative to the image origin
+    float h, hinv;         // the target's own softening length (per-particle softening)
 };
+
+// f and D of one softening length: the spline inside it, Newtonian beyond
+__device__ __forceinline__ void soft_fd(float r2, float h, float hinv, float& f, float& D) {
+    if (r2 >= h * h) {
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri2 = ri * ri;
+        f = ri * ri2;
+        D = -3.f * f * ri2;
+    } else {
+        spline_fd<float>(r2, hinv, f, D);
+    }
+}
 
 // ---- forward: g, j and S = -T from particle masses and node multipoles ----
 struct ForwardPolicy {
@@ -308,7 +322,7 @@ struct ForwardPolicy {
             dz = near_img(dz, O);
         }
         S.tile[lane] = make_float4((float)dx, (float)dy, (float)dz, u.w);
-        S.tile[kW + lane] = u;
+        S.tile[kW + lane] = make_float4(u.x, u.y, u.z, T.sh ? T.sh[pk] : u.w);   // .w: softening length
         S.tidx[lane] = pk;
     }
     // The quantities of pair_interact, written as multiply-add chains into
@@ -316,7 +330,7 @@ struct ForwardPolicy {
     // self pair has d = 0 exactly (both sides round the same FP64 position),
     // so it always takes the softened branch, where it is dropped.  Periodic:
     // each pair is taken at its own nearest image.
-    template <int kPer>
+    template <int kPer, bool kSoft>
     __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
                                      int k0, int ks, const WalkOut& O) {
         PairAcc<float> F;
@@ -334,17 +348,27 @@ struct ForwardPolicy {
             const float nx = u.x - t.vx, ny = u.y - t.vy, nz = u.z - t.vz;
             const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
             float mf, mD;
-            if (r2 >= h2) {
+            // per-particle softening: the pair is Newtonian beyond both lengths
+            const float hh = kSoft ? fmaxf(t.h, u.w) : 0.f;
+            if (r2 >= (kSoft ? hh * hh : h2)) {
                 const float ri = __builtin_amdgcn_rsqf(r2);
                 const float ri2 = ri * ri;
                 mf = q.w * (ri * ri2);
                 mD = -3.f * mf * ri2;
-            } else {
+            } else if (!kSoft) {
                 float f, D;
                 spline_fd<float>(r2, hinv, f, D);
                 const float mj = (S.tidx[k] == t.p) ? 0.f : q.w;
                 mf = mj * f;
                 mD = mj * D;
+            } else {
+                // the mean of the target's and the source's kernels
+                float f1, D1, f2, D2;
+                soft_fd(r2, t.h, t.hinv, f1, D1);
+                soft_fd(r2, u.w, 1.f / u.w, f2, D2);
+                const float mj = (S.tidx[k] == t.p) ? 0.f : 0.5f * q.w;
+                mf = mj * (f1 + f2);
+                mD = mj * (D1 + D2);
             }
             F.ax = __builtin_fmaf(mf, dx, F.ax);
             F.ay = __builtin_fmaf(mf, dy, F.ay);
@@ -467,9 +491,10 @@ struct AdjointPolicy {
         S.tile[kW + lane] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.f);
         S.tidx[lane] = pk;
     }
-    template <int kPer>
+    template <int kPer, bool kSoft>
     __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float h2, float hinv,
                                      int k0, int ks, const WalkOut&) {
+        static_assert(!kSoft, "the adjoint walk has one softening length");
         AdjAccF F{0.f, 0.f, 0.f, 0.f};
         for (int k = k0; k < cnt; k += ks) {
             const float4 q = S.tile[k];
@@ -854,7 +879,7 @@ struct EwaldPolicy {
             }
         }
     }
-    template <int kPer>
+    template <int kPer, bool kSoft>
     __device__ static void particles(const Lds& S, int cnt, const Target& t, Acc& acc, float, float, int k0,
                                      int ks, const WalkOut& O) {
         entries(S, cnt, t, acc, k0, ks, O);
@@ -902,7 +927,7 @@ struct EwaldPolicy {
     }
 };
 
-template <class Pol, int kPer>
+template <class Pol, int kPer, bool kSoft>
 __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, const Groups& Gr, const WalkOut& O,
                                            const int4 gd, float theta2, float eps2, float h2, float hinv) {
     const int lane = threadIdx.x;
@@ -937,6 +962,10 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     tg.g0x = (float)(gb.cx - gb.ox);
     tg.g0y = (float)(gb.cy - gb.oy);
     tg.g0z = (float)(gb.cz - gb.oz);
+    tg.h = kSoft ? T.sh[p_i] : 0.f;
+    tg.hinv = kSoft ? 1.f / tg.h : 0.f;
+    // multipoles only beyond every softening length of the group and the node
+    const float gh2 = kSoft ? ag_wave_max(tg.h * tg.h) : eps2;
     tg.vx = vi.x;
     tg.vy = vi.y;
     tg.vz = vi.z;
@@ -961,7 +990,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     auto flush_particles = [&](int base, int cnt) {
         if (lane < cnt) Pol::template stage_particle<kPer>(S, T, gb, lane, S.plist[base + lane], O);
         __syncthreads();
-        Pol::template particles<kPer>(S, cnt, tg, acc, h2, hinv, part, sub, O);
+        Pol::template particles<kPer, kSoft>(S, cnt, tg, acc, h2, hinv, part, sub, O);
         n_pp += (uint64_t)cnt;
         __syncthreads();
     };
@@ -1014,7 +1043,9 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
             } else {
                 const bool acc_ok =
                     Pol::kImageMac ? ewald_accept(gb, T.com[a], T.lo[a], T.hi[a], O)
-                                   : mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2, eps2, O.mac_offset, O);
+                                   : mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2,
+                                                      kSoft ? fmaxf(gh2, T.lo[a].w * T.lo[a].w) : eps2,
+                                                      O.mac_offset, O);
                 if (acc_ok && L.z > O.small_node) {
                     push_node = a;
                     ca = L.x;
@@ -1115,7 +1146,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
 // from the other queues when its own runs dry.  The register budget is held
 // to 128 VGPRs (four waves per SIMD); the few values this spills live
 // outside the interaction loops.
-template <class Pol, int kPer>
+template <class Pol, int kPer, bool kSoft = false>
 __global__ void __launch_bounds__(kW, 4) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
                                              float theta2, float eps2, float h2, float hinv) {
     __shared__ typename Pol::Lds S;
@@ -1143,7 +1174,7 @@ __global__ void __launch_bounds__(kW, 4) k_walk(Tree T, Groups Gr, WalkOut O, in
         const int g = s_g;
         __syncthreads();
         if (g < 0) break;
-        walk_group<Pol, kPer>(S, T, Gr, O, Gr.grp[g], theta2, eps2, h2, hinv);
+        walk_group<Pol, kPer, kSoft>(S, T, Gr, O, Gr.grp[g], theta2, eps2, h2, hinv);
         __syncthreads();
     }
 }
@@ -1570,6 +1601,7 @@ __global__ void k_inner_wlevel(int level, const int32_t* __restrict__ lvl, const
 static Tree make_tree(ag_ctx* c) {
     Tree T;
     T.com = c->nd_com.as<double4>();
+    T.sh = c->tree_soft ? c->soft_s.as<float>() : nullptr;
     T.lo = c->nd_lo.as<float4>();
     T.hi = c->nd_hi.as<float4>();
     T.link = c->nd_link.as<int4>();
@@ -1655,15 +1687,29 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
     int32_t* qctr = c->grp_hdr.as<int32_t>() + 8;
     {
         PhaseScope phase(c, AG_PHASE_WALK);
-        if (ewald)
-            hipLaunchKernelGGL((k_walk<ForwardPolicy, kEwald>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr,
-                               O, qctr, th * th, e2, e2, (float)(1.0 / eps));
-        else if (c->box > 0.0)
-            hipLaunchKernelGGL((k_walk<ForwardPolicy, kNear>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr,
-                               O, qctr, th * th, e2, e2, (float)(1.0 / eps));
-        else
-            hipLaunchKernelGGL((k_walk<ForwardPolicy, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr,
-                               O, qctr, th * th, e2, e2, (float)(1.0 / eps));
+        const Tree T = make_tree(c);
+        const float h2 = e2, hi = (float)(1.0 / eps);
+        hipStream_t st = c->stream;
+        if (c->tree_soft) {   // per-particle softening lengths
+            if (ewald)
+                hipLaunchKernelGGL((k_walk<ForwardPolicy, kEwald, true>), dim3(grid), dim3(kW), 0, st, T, Gr, O, qctr,
+                                   th * th, e2, h2, hi);
+            else if (c->box > 0.0)
+                hipLaunchKernelGGL((k_walk<ForwardPolicy, kNear, true>), dim3(grid), dim3(kW), 0, st, T, Gr, O, qctr,
+                                   th * th, e2, h2, hi);
+            else
+                hipLaunchKernelGGL((k_walk<ForwardPolicy, kOpen, true>), dim3(grid), dim3(kW), 0, st, T, Gr, O, qctr,
+                                   th * th, e2, h2, hi);
+        } else if (ewald) {
+            hipLaunchKernelGGL((k_walk<ForwardPolicy, kEwald>), dim3(grid), dim3(kW), 0, st, T, Gr, O, qctr, th * th,
+                               e2, h2, hi);
+        } else if (c->box > 0.0) {
+            hipLaunchKernelGGL((k_walk<ForwardPolicy, kNear>), dim3(grid), dim3(kW), 0, st, T, Gr, O, qctr, th * th,
+                               e2, h2, hi);
+        } else {
+            hipLaunchKernelGGL((k_walk<ForwardPolicy, kOpen>), dim3(grid), dim3(kW), 0, st, T, Gr, O, qctr, th * th,
+                               e2, h2, hi);
+        }
     }
     if (ewald && (acc || tidal)) {
         // what the periodic images add to g and T, at the same images

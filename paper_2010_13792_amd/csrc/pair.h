@@ -79,6 +79,44 @@ __device__ __forceinline__ void pair_interact(R dx, R dy, R dz, R nx, R ny, R nz
     A.syz += ty * dz;
 }
 
+// the same pair term with a softening length per particle: f and D are the
+// means of the two particles' kernels (each Newtonian beyond its own length)
+template <class R>
+__device__ __forceinline__ void pair_interact_soft(R dx, R dy, R dz, R nx, R ny, R nz, R mj, R hi_, R hj,
+                                                   PairAcc<R>& A) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    R fs[2], Ds[2];
+    const R hs[2] = {hi_, hj};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (r2 >= hs[k] * hs[k]) {
+            const R ri = ag_rsqrt(r2);
+            const R ri2 = ri * ri;
+            fs[k] = ri * ri2;
+            Ds[k] = R(-3) * fs[k] * ri2;
+        } else {
+            spline_fd<R>(r2, R(1) / hs[k], fs[k], Ds[k]);
+        }
+    }
+    const R mf = mj * (R(0.5) * (fs[0] + fs[1]));
+    const R mD = mj * (R(0.5) * (Ds[0] + Ds[1]));
+    A.ax += mf * dx;
+    A.ay += mf * dy;
+    A.az += mf * dz;
+    const R dn = dx * nx + dy * ny + dz * nz;
+    const R s = mD * dn;
+    A.jx += mf * nx + s * dx;
+    A.jy += mf * ny + s * dy;
+    A.jz += mf * nz + s * dz;
+    const R tx = mD * dx, ty = mD * dy, tz = mD * dz;
+    A.sxx += mf + tx * dx;
+    A.syy += mf + ty * dy;
+    A.szz += mf + tz * dz;
+    A.sxy += tx * dy;
+    A.sxz += tx * dz;
+    A.syz += ty * dz;
+}
+
 // algorithmic operation count of one particle-particle interaction outside
 // the softening kernel (fused multiply-add = 2, reciprocal square root = 1):
 //   d and nu 6, r2 5, rsqrt 1, powers 2, D 2, mf mD 2, g 6, d.nu 5, s 1,

@@ -160,6 +160,17 @@ def zeldovich_box(n_side, seed=6, box=1.0, growth=0.9, jitter=1e-3):
     return x, v, np.full(n, 1.0 / n)
 
 
+def neighbour_lengths(x, k=32, box=None):
+    """Per-particle lengths that follow the local particle spacing, as fully
+    adaptive softening does: the distance to the k-th nearest neighbour
+    (scipy's k-d tree; periodic images when ``box`` is given)."""
+    from scipy.spatial import cKDTree
+    pts = np.mod(x, box) if box else x
+    tree = cKDTree(pts, boxsize=box)
+    d, _ = tree.query(pts, k=k + 1)
+    return np.ascontiguousarray(d[:, k])
+
+
 def batched_plummer(nsys=256, seed=4, nmin=1024, nmax=65536, sigma=0.4):
     """``nsys`` independent Plummer systems (each M = 1, b = 1, r <= 10) with
     sizes log-uniform in [nmin, nmax] and active fractions uniform in
