@@ -18,6 +18,9 @@
             geometry of the paper's cosmological test), 64^3 and 128^3
             particles, every pair at its nearest image; build + walk time,
             evaluations/s and errors against the oracle on sampled targets.
+  softening N = 2^20 turbulent sphere with a softening length per particle
+            (the distance to the 32nd neighbour) against the same step with
+            one length: time, interactions and error against the oracle.
   copy      a plain device copy of 1 GiB, the calibration of the HBM byte
             counters (FETCH_SIZE, WRITE_SIZE) used for the walk's traffic.
 Inputs are seeded synthetic particle sets standing in for the paper's
@@ -438,6 +441,65 @@ def run_periodic(args):
             out["runs"][f"ewald {n_side}^3 theta=0.5"]["cpu_baseline"] = {
                 "value": 32 / t_ew, "unit": "force evals/s", "cores": oracle.num_threads(), "kind": "oracle",
                 "sample": f"32 targets of the {n} particles, Ewald direct sum"}
+    return out
+
+
+# ---------------------------------------------------------------------------
+def run_softening(args):
+    import oracle
+    n = args.n
+    x, v, m = workloads.turbulent_sphere(n, seed=2, grid=128)
+    log("softening: neighbour lengths (k = 32)")
+    h = workloads.neighbour_lengths(x, 32)
+    tx, tv, tm, th = _t(x), _t(v), _t(m), _t(h)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+    jerk, tid = torch.zeros_like(acc), torch.zeros((n, 6), dtype=torch.float64, device=DEV)
+    rows = np.random.default_rng(8).choice(n, 4096, replace=False)
+    out = {"workload": f"turbulent sphere N={n}, theta={args.theta}, lengths = 32nd-neighbour distance "
+                       f"(median {np.median(h):.2e}, 1-99% {np.percentile(h, 1):.2e}-{np.percentile(h, 99):.2e}) "
+                       f"vs one length eps={args.eps}", "runs": {}}
+    for mode in ("per-particle", "uniform"):
+        with ag.Context(0) as c:
+            c.set_option(ag.AG_OPT_MAC_OFFSET, args.mac_offset)
+            if mode == "per-particle":
+                c.set_softening(th)
+
+            def step():
+                c.tree_build(tx, tv, tm, args.n_leaf)
+                c.grav_eval(None, args.theta, args.eps, 1.0, acc, jerk, tid)
+
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            c.stats_reset()
+            e0, e1 = _events()
+            reps = 10
+            e0.record()
+            for _ in range(reps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            st = c.stats_read()
+            c.timing_enable(True)
+            c.timing_read(reset=True)
+            for _ in range(reps):
+                step()
+            ph = c.timing_read(reset=True)
+            c.timing_enable(False)
+        walk_ms = ph["walk"]["ms"] / reps
+        flops = (st["n_pp"] * PP_FLOPS + st["n_pn"] * PN_FLOPS) / reps
+        a = acc.cpu().numpy()[rows]
+        if mode == "per-particle":
+            ar, _, _ = oracle.direct_soft(x, v, m, h, 1.0, rows)
+        else:
+            ar, _, _ = oracle.direct(x, v, m, args.eps, 1.0, rows)
+        e = _rel(a, ar)
+        out["runs"][mode] = {"ms_per_step": ms, "evals_per_s": n / (ms * 1e-3), "build_ms": ph["build"]["ms"] / reps,
+                             "walk_ms": walk_ms, "walk_tflops": flops / (walk_ms * 1e-3) / 1e12,
+                             "per_target": {"pp": st["n_pp"] / reps / n, "pn": st["n_pn"] / reps / n},
+                             "median_rel_force_err": float(np.median(e)), "p99_rel_force_err": float(np.percentile(e, 99))}
+        log(f"softening {mode}: {out['runs'][mode]}")
     return out
 
 
