@@ -11,7 +11,9 @@ routine of the same name in ``oracle.c`` (built into ``liboracle.so`` by
   tidal tensor (whose Frobenius norm enters Eq. 7); optionally in a periodic
   cube with every pair at its nearest image (how the paper treats the jerk
   of periodic problems, Sec. 4); :func:`direct_soft` with a softening length
-  per particle (each pair takes the mean of its two kernels).
+  per particle (each pair takes the mean of its two kernels), and
+  :func:`neighbour_length`, the k-th neighbour distance those lengths
+  follow (plain numpy).
 * :func:`timestep` -- the tidal timestep of Eq. 7 and its power-of-two bin.
 * :func:`select` -- force-age counter (Eq. 3) and update condition (Eq. 4).
 * :func:`predict` -- jerk predictor (Eq. 6) in closed form ``a0 + j (t - t0)``.
@@ -174,6 +176,26 @@ def direct_soft(x, v, m, h, G, targets=None):
     _load().orc_field_soft(n, _ptr(x), _ptr(v), _ptr(m), _ptr(h), float(G), k, _ptr(p), _ptr(pv), _ptr(hp),
                            _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(tid))
     return acc, jerk, tid
+
+
+def neighbour_length(x, k, targets=None, chunk=256):
+    """Distance from each target particle to its k-th nearest other particle
+    (the length fully adaptive softening scales with), by brute force in
+    FP64: d^2 = (dx^2 + dy^2) + dz^2 with d = x_j - x_i, then the k-th
+    smallest over j != i, then its square root."""
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    tgt = np.arange(n, dtype=np.int64) if targets is None else np.asarray(targets, dtype=np.int64)
+    out = np.empty(tgt.size)
+    for a in range(0, tgt.size, chunk):
+        t = tgt[a:a + chunk]
+        dx = x[None, :, 0] - x[t, 0][:, None]
+        dy = x[None, :, 1] - x[t, 1][:, None]
+        dz = x[None, :, 2] - x[t, 2][:, None]
+        d2 = dx * dx + dy * dy + dz * dz
+        d2[np.arange(t.size), t] = np.inf        # not itself
+        out[a:a + chunk] = np.sqrt(np.partition(d2, k - 1, axis=1)[:, k - 1])
+    return out
 
 
 def ewald_unit(d, L, alpha=None, nr=3, nk=4):

@@ -4,6 +4,7 @@ bit to the single-length sum, keeps the pair forces equal and opposite,
 satisfies the Poisson identity with the mean kernel, and its T and j are
 finite differences of its g."""
 import numpy as np
+import pytest
 
 import workloads
 from test_oracle_field import W_m4, sym6
@@ -60,3 +61,29 @@ def test_tide_and_jerk_are_derivatives(orc):
     ap = orc.direct_soft(x + d * v, v, m, h, 1.0)[0]
     am = orc.direct_soft(x - d * v, v, m, h, 1.0)[0]
     np.testing.assert_allclose((ap - am) / (2 * d), j, rtol=1e-5, atol=1e-6 * np.abs(j).max())
+
+
+def test_neighbour_length_brute_force(orc):
+    """A plain loop over a small set, and scipy's k-d tree on a larger one."""
+    rng = np.random.default_rng(9)
+    x = rng.normal(size=(40, 3))
+    for k in (1, 5, 39):
+        got = orc.neighbour_length(x, k)
+        for i in range(40):
+            d = sorted(float(np.sqrt(np.sum((x[j] - x[i]) ** 2))) for j in range(40) if j != i)
+            assert abs(got[i] - d[k - 1]) <= 1e-15 * d[k - 1]
+    from scipy.spatial import cKDTree
+    x, _, _ = workloads.plummer(5000, seed=10)
+    ref = cKDTree(x).query(x, k=33)[0][:, 32]
+    np.testing.assert_allclose(orc.neighbour_length(x, 32), ref, rtol=1e-14)
+
+
+def test_neighbour_length_lattice(orc):
+    """On a cubic lattice of spacing a the 1st..6th neighbours sit at a,
+    the 7th..18th at a sqrt(2) (interior points)."""
+    a = 0.3
+    g = np.arange(7) * a
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    centre = [np.argmin(np.linalg.norm(x - 3 * a, axis=1))]
+    for k, d in ((1, a), (6, a), (7, a * np.sqrt(2)), (18, a * np.sqrt(2)), (19, a * np.sqrt(3))):
+        assert orc.neighbour_length(x, k, centre)[0] == pytest.approx(d, rel=1e-14)
