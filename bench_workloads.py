@@ -458,14 +458,25 @@ def run_softening(args):
     out = {"workload": f"turbulent sphere N={n}, theta={args.theta}, lengths = 32nd-neighbour distance "
                        f"(median {np.median(h):.2e}, 1-99% {np.percentile(h, 1):.2e}-{np.percentile(h, 99):.2e}) "
                        f"vs one length eps={args.eps}", "runs": {}}
-    for mode in ("per-particle", "uniform"):
+    # "adaptive": every step builds with the lengths found on the previous
+    # step's tree, then finds the new ones on the device (the particles do
+    # not move here, so from the second step on they are the host's lengths)
+    hdev = torch.zeros(n, dtype=torch.float64, device=DEV)
+    for mode in ("per-particle", "adaptive", "uniform"):
         with ag.Context(0) as c:
             c.set_option(ag.AG_OPT_MAC_OFFSET, args.mac_offset)
             if mode == "per-particle":
                 c.set_softening(th)
+            if mode == "adaptive":
+                c.tree_build(tx, tv, tm, args.n_leaf)
+                c.neighbour_lengths(32, hdev)
 
             def step():
+                if mode == "adaptive":
+                    c.set_softening(hdev)
                 c.tree_build(tx, tv, tm, args.n_leaf)
+                if mode == "adaptive":
+                    c.neighbour_lengths(32, hdev)
                 c.grav_eval(None, args.theta, args.eps, 1.0, acc, jerk, tid)
 
             for _ in range(2):
@@ -490,7 +501,13 @@ def run_softening(args):
         walk_ms = ph["walk"]["ms"] / reps
         flops = (st["n_pp"] * PP_FLOPS + st["n_pn"] * PN_FLOPS) / reps
         a = acc.cpu().numpy()[rows]
-        if mode == "per-particle":
+        extra = {}
+        if mode == "adaptive":
+            hd = hdev.cpu().numpy()
+            extra = {"neighbour_ms": ph["neighbour"]["ms"] / reps,
+                     "lengths_equal_host": bool(np.array_equal(hd, h)),
+                     "lengths_max_rel_diff": float(np.max(np.abs(hd - h) / h))}
+        if mode != "uniform":
             ar, _, _ = oracle.direct_soft(x, v, m, h, 1.0, rows)
         else:
             ar, _, _ = oracle.direct(x, v, m, args.eps, 1.0, rows)
@@ -498,7 +515,8 @@ def run_softening(args):
         out["runs"][mode] = {"ms_per_step": ms, "evals_per_s": n / (ms * 1e-3), "build_ms": ph["build"]["ms"] / reps,
                              "walk_ms": walk_ms, "walk_tflops": flops / (walk_ms * 1e-3) / 1e12,
                              "per_target": {"pp": st["n_pp"] / reps / n, "pn": st["n_pn"] / reps / n},
-                             "median_rel_force_err": float(np.median(e)), "p99_rel_force_err": float(np.percentile(e, 99))}
+                             "median_rel_force_err": float(np.median(e)), "p99_rel_force_err": float(np.percentile(e, 99)),
+                             **extra}
         log(f"softening {mode}: {out['runs'][mode]}")
     return out
 

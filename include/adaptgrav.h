@@ -131,6 +131,18 @@ int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
  * length per evaluation (eps). */
 int ag_set_softening(ag_ctx *ctx, int64_t n, const double *h);
 
+/* Adaptive softening lengths from the built tree (Sec. 4: each element's
+ * softening follows the local spacing; here that spacing is the distance to
+ * the k-th nearest other particle).  h (n,) device FP64, written in input
+ * order: h_i = sqrt(d2_k) with d2_k the k-th smallest of
+ * d2_ij = (dx^2 + dy^2) + dz^2 over j != i, d = x_j - x_i, each operation
+ * rounded once in FP64, so the result is exact up to that rounding.  The
+ * output can go straight to ag_set_softening (scaled first, if wanted).
+ * Needs a tree from ag_tree_build on an open (non-periodic) context;
+ * batched or periodic trees give AG_ESTATE.  k must be in [1, 64] and below
+ * n (AG_EINVAL).  Coincident particles give h = 0. */
+int ag_neighbour_lengths(ag_ctx *ctx, int32_t k, double *h);
+
 /* Periodic boundaries (Sec. 4: the periodic problem's gravity uses Ewald
  * sums, its jerk only the nearest image).  box > 0 makes every later
  * ag_grav_eval, ag_grav_eval_batched and (ewald = 0 only) ag_grav_direct on
@@ -179,9 +191,10 @@ int ag_graph_replay(ag_ctx *ctx);
  * AG_PHASE_GROUPS (active rows -> walk groups), AG_PHASE_WALK (forward
  * walk kernel only), AG_PHASE_DIRECT, AG_PHASE_STEP (timestep, select,
  * predict), AG_PHASE_ADJOINT (adjoint walk kernel only), AG_PHASE_EWALD
- * (the periodic images' correction walk). */
+ * (the periodic images' correction walk), AG_PHASE_NEIGHBOUR (the
+ * neighbour-length walk kernel only). */
 enum { AG_PHASE_BUILD = 0, AG_PHASE_GROUPS, AG_PHASE_WALK, AG_PHASE_DIRECT, AG_PHASE_STEP,
-       AG_PHASE_ADJOINT, AG_PHASE_EWALD, AG_NPHASE };
+       AG_PHASE_ADJOINT, AG_PHASE_EWALD, AG_PHASE_NEIGHBOUR, AG_NPHASE };
 int ag_timing_enable(ag_ctx *ctx, int enable);
 int ag_timing_read(ag_ctx *ctx, double *ms /* [AG_NPHASE] */, int64_t *launches /* [AG_NPHASE], nullable */,
                    int reset);

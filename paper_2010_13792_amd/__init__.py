@@ -38,6 +38,7 @@ ENTRY_POINTS = [
     "ag_grav_predict", "ag_grav_backward", "ag_timing_enable", "ag_timing_read",
     "ag_kick_drift", "ag_set_option", "ag_graph_begin", "ag_graph_end", "ag_graph_replay",
     "ag_force_log", "ag_grav_predict_poly", "ag_set_periodic", "ag_set_softening",
+    "ag_neighbour_lengths",
 ]
 AG_PRED_MAX_DEPTH = 4
 AG_OPT_WALK_WAVES_PER_CU = 1
@@ -46,7 +47,7 @@ AG_OPT_GROUP_SPAN = 3
 AG_OPT_MAC_OFFSET = 4
 AG_OPT_GROUP_TARGETS = 5
 AG_OPT_EWALD_OPEN = 6
-PHASES = ["build", "groups", "walk", "direct", "step", "adjoint", "ewald"]
+PHASES = ["build", "groups", "walk", "direct", "step", "adjoint", "ewald", "neighbour"]
 
 
 class AgError(RuntimeError):
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "ag_set_option": [P, I32, I64],
         "ag_set_periodic": [P, D, I32],
         "ag_set_softening": [P, I64, P],
+        "ag_neighbour_lengths": [P, I32, P],
         "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
         "ag_force_log": [P, I64, P, I64, I32, P, D, P, P, P],
@@ -312,6 +314,17 @@ class Context:
             _check(_lib.ag_set_softening(self._h, 0, None))
             return
         _check(_lib.ag_set_softening(self._h, h.shape[0], _ptr(h, torch.float64, None, "h")))
+
+    def neighbour_lengths(self, k: int, out=None):
+        """Distance of every particle to its k-th nearest other particle, from
+        the built tree (device float64 (n,), input order)."""
+        n = self.n
+        if out is None:
+            if n is None:
+                raise AgError(AG_ESTATE, "neighbour lengths before a tree build")
+            out = torch.empty(n, dtype=torch.float64, device=torch.device("cuda", self.device))
+        _check(_lib.ag_neighbour_lengths(self._h, int(k), _ptr(out, torch.float64, None, "out", n)))
+        return out
 
     def set_periodic(self, box: float, ewald: bool = False):
         """Periodic cube of side ``box`` (0: open): nearest-image pairs, or

@@ -186,6 +186,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
 int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m);
 int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps,
                    double G, double* acc, double* jerk, double* tidal);
+int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out);
 int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w,
                        double theta, double eps, double G, double* dLdx, double* dLdm);
 // exclusive scan of n int32 counts into out (n+1 entries; out[n] = total) on c->stream

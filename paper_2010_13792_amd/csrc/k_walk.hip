@@ -93,6 +93,9 @@ struct WalkOut {
     int etab_ne;
     float ewald_theta;  // correction walk: opening angle against the nearest image point
     float ewald_grp;    // groups of at most this half extent sum the correction once
+    double* knn_out;    // neighbour lengths (input order)
+    int knn_k;          // which neighbour
+    int64_t knn_n;
     double* dldx;       // adjoint outputs
     double* dldm;
     const double* tin;  // adjoint: tidal tensor rows of the charged targets
@@ -297,6 +300,7 @@ __device__ __forceinline__ void soft_fd(float r2, float h, float hinv, float& f,
 // ---- forward: g, j and S = -T from particle masses and node multipoles ----
 struct ForwardPolicy {
     static constexpr bool kSkipEmpty = false;
+    static constexpr bool kOpenAll = false;
     static constexpr bool kImageMac = false;
     static constexpr bool kGroupSum = false;
     using Lds = WalkLds<5>;
@@ -473,6 +477,7 @@ struct AdjAccF {
 };
 struct AdjointPolicy {
     static constexpr bool kSkipEmpty = true;   // nodes without charge add nothing
+    static constexpr bool kOpenAll = false;
     static constexpr bool kImageMac = false;
     static constexpr bool kGroupSum = false;
     using Lds = WalkLds<9>;
@@ -716,6 +721,7 @@ __device__ __forceinline__ bool ewald_accept(const GroupBox& g, const double4 c,
 // background that neutralises its own images).
 struct EwaldPolicy {
     static constexpr bool kSkipEmpty = false;
+    static constexpr bool kOpenAll = false;
     static constexpr bool kImageMac = true;
     static constexpr bool kGroupSum = true;
     using Lds = WalkLds<8>;
@@ -927,6 +933,148 @@ struct EwaldPolicy {
     }
 };
 
+// ---- k-th neighbour distance: the length fully adaptive softening follows ----
+// Every node is opened; a node whose box lies farther from the group's box
+// than the group's pruning radius is skipped.  Each target keeps its k
+// smallest squared distances (FP64, unordered) in LDS.  Before the walk the
+// targets take the particles within k sorted positions of the group, which
+// fills every list; the pruning radius is then the largest of the targets'
+// current k-th distances, and shrinks after every tile.  Distances are
+// d^2 = (dx^2 + dy^2) + dz^2 with d = x_j - x_i, each operation rounded once.
+constexpr int kKnnMax = 64;
+struct KnnLds : WalkLds<2> {
+    double lst[kW * kKnnMax];
+    double r2;
+    int win_lo, win_hi;   // sorted positions taken before the walk
+};
+struct KnnPolicy {
+    static constexpr bool kSkipEmpty = false;
+    static constexpr bool kOpenAll = true;
+    static constexpr bool kImageMac = false;
+    static constexpr bool kGroupSum = false;
+    using Lds = KnnLds;
+    struct Acc {
+        double x, y, z;   // the target
+        double kth;       // largest entry of its list
+        int cnt, imax;
+        __device__ void zero() {
+            kth = 0.0;
+            cnt = 0;
+            imax = 0;
+        }
+        __device__ void add(const Acc&) {}
+    };
+    // hipcc contracts a * b + c into one fma by default: not here
+    __device__ static double dist2(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+        return (dx * dx + dy * dy) + dz * dz;
+    }
+    __device__ static void insert(Lds& S, Acc& A, int slot, double d2, int k) {
+        double* L = S.lst + slot * kKnnMax;
+        if (A.cnt < k) {
+            L[A.cnt] = d2;
+            if (A.cnt == 0 || d2 > A.kth) {
+                A.kth = d2;
+                A.imax = A.cnt;
+            }
+            ++A.cnt;
+            return;
+        }
+        if (!(d2 < A.kth)) return;
+        L[A.imax] = d2;
+        double mx = L[0];
+        int im = 0;
+        for (int i = 1; i < k; ++i)
+            if (L[i] > mx) {
+                mx = L[i];
+                im = i;
+            }
+        A.kth = mx;
+        A.imax = im;
+    }
+    // radius^2 no target's k-th neighbour lies beyond (every list full)
+    __device__ static void update_radius(Lds& S, const Acc& A, bool owner, int k) {
+        const double mine = owner ? (A.cnt >= k ? A.kth : __builtin_huge_val()) : 0.0;
+        const double r2 = ag_wave_max(mine);
+        if (threadIdx.x == 0) S.r2 = r2;
+    }
+    // Both boxes are rounded outward, their gaps are exact in FP64, and the
+    // relative margin covers the rounding of the squares: a skipped node
+    // holds no particle at a computed d^2 <= r2.
+    __device__ static bool skip_node(const Lds& S, const Tree& T, const GroupBox& g, int a) {
+        const float4 lo = T.lo[a], hi = T.hi[a];
+        const double gx = fmax(fmax((double)lo.x - g.hix, (double)g.lox - hi.x), 0.0);
+        const double gy = fmax(fmax((double)lo.y - g.hiy, (double)g.loy - hi.y), 0.0);
+        const double gz = fmax(fmax((double)lo.z - g.hiz, (double)g.loz - hi.z), 0.0);
+        return gx * gx + gy * gy + gz * gz > S.r2 * (1.0 + 1e-12);
+    }
+    __device__ static void start(Lds& S, const Tree& T, const WalkOut& O, int4 gd, const Target& t, Acc& A,
+                                 int part, int slot, int count) {
+        const double4 xi = T.spos[t.p];
+        A.x = xi.x;
+        A.y = xi.y;
+        A.z = xi.z;
+        const int k = O.knn_k;
+        const int64_t lo = gd.x - k > 0 ? gd.x - k : 0;
+        const int64_t hi = gd.x + count + k < O.knn_n ? gd.x + count + k : O.knn_n;
+        if (threadIdx.x == 0) {
+            S.win_lo = (int)lo;
+            S.win_hi = (int)hi;
+        }
+        double4* P = reinterpret_cast<double4*>(S.tile);
+        for (int64_t base = lo; base < hi; base += kW) {
+            const int cw = hi - base < kW ? (int)(hi - base) : kW;
+            __syncthreads();
+            if ((int)threadIdx.x < cw) {
+                P[threadIdx.x] = T.spos[base + threadIdx.x];
+                S.tidx[threadIdx.x] = (int)(base + threadIdx.x);
+            }
+            __syncthreads();
+            if (part == 0)
+                for (int q = 0; q < cw; ++q) {
+                    if (S.tidx[q] == t.p) continue;
+                    insert(S, A, slot, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z), k);
+                }
+        }
+        update_radius(S, A, part == 0, k);
+        __syncthreads();
+    }
+    template <int kPer>
+    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox&, int lane, int pk, const WalkOut&) {
+        reinterpret_cast<double4*>(S.tile)[lane] = T.spos[pk];
+        S.tidx[lane] = pk;
+    }
+    template <int kPer>
+    __device__ static void stage_node(Lds&, const Tree&, const GroupBox&, int, int, const WalkOut&) {}
+    template <int kPer, bool kSoft>
+    __device__ static void particles(Lds& S, int cnt, const Target& t, Acc& A, float, float, int k0, int,
+                                     const WalkOut& O) {
+        const int k = O.knn_k;
+        const double4* P = reinterpret_cast<const double4*>(S.tile);
+        if (k0 == 0) {   // the target's first lane keeps its list
+            const int slot = threadIdx.x;
+            for (int q = 0; q < cnt; ++q) {
+                const int pk = S.tidx[q];
+                if (pk == t.p || (pk >= S.win_lo && pk < S.win_hi)) continue;
+                insert(S, A, slot, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z), k);
+            }
+        }
+        update_radius(S, A, k0 == 0, k);
+    }
+    __device__ static void nodes(const Lds&, int, const Target&, Acc&, int, int, const WalkOut&) {}
+    static __device__ void wave_sum(Acc&) {}
+    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
+        O.knn_out[T.perm[p]] = A.cnt >= O.knn_k ? sqrt(A.kth) : __builtin_huge_val();
+    }
+};
+
+template <class P>
+__device__ __forceinline__ bool policy_skips(const typename P::Lds& S, const Tree& T, const GroupBox& g, int a) {
+    if constexpr (P::kOpenAll) return KnnPolicy::skip_node(S, T, g, a);
+    else if constexpr (P::kSkipEmpty) return T.wf[8 * a].w == 0.f;
+    else return false;
+}
+
 template <class Pol, int kPer, bool kSoft>
 __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, const Groups& Gr, const WalkOut& O,
                                            const int4 gd, float theta2, float eps2, float h2, float hinv) {
@@ -971,9 +1119,10 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     tg.vz = vi.z;
     tg.p = p_i;
     tg.grp = Pol::kGroupSum && fmaxf(fmaxf(gb.hx, gb.hy), gb.hz) <= O.ewald_grp;
-
     typename Pol::Acc acc;
     acc.zero();
+    if constexpr (Pol::kOpenAll) Pol::start(S, T, O, gd, tg, acc, part, slot, count);
+
     uint64_t n_pp = 0, n_pn = 0;
 
     // ---- traversal state ----
@@ -1038,11 +1187,12 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
             const int a = ca;
             const int4 L = T.link[a];
             const bool leaf = (L.w & 0x100) != 0;
-            if (Pol::kSkipEmpty && T.wf[8 * a].w == 0.f) {
-                ca = L.x;                  // no charge below this node
+            if (policy_skips<Pol>(S, T, gb, a)) {
+                ca = L.x;                  // nothing below this node matters
             } else {
                 const bool acc_ok =
-                    Pol::kImageMac ? ewald_accept(gb, T.com[a], T.lo[a], T.hi[a], O)
+                    Pol::kOpenAll ? false
+                    : Pol::kImageMac ? ewald_accept(gb, T.com[a], T.lo[a], T.hi[a], O)
                                    : mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2,
                                                       kSoft ? fmaxf(gh2, T.lo[a].w * T.lo[a].w) : eps2,
                                                       O.mac_offset, O);
@@ -1661,6 +1811,23 @@ static WalkOut make_out(ag_ctx* c, double G) {
     O.etab_hinv = (float)(kEwaldPerBox / c->box);
     O.etab_range = (float)(c->box * kEwaldNE / kEwaldPerBox * (1.0 + 1e-4));   // a few ulps of slack
     return O;
+}
+
+// distance of every particle to its k-th nearest other particle, by a walk
+// that opens every node and prunes by distance
+int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out) {
+    int64_t mg = 0;
+    AG_TRY(ag_prepare_groups(c, nullptr, c->n, &mg));
+    Groups Gr{nullptr, c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    WalkOut O = make_out(c, 1.0);
+    O.stats = nullptr;
+    O.knn_out = h_out;
+    O.knn_k = k;
+    O.knn_n = c->n;
+    PhaseScope phase(c, AG_PHASE_NEIGHBOUR);
+    hipLaunchKernelGGL((k_walk<KnnPolicy, kOpen>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, c->stream,
+                       make_tree(c), Gr, O, c->grp_hdr.as<int32_t>() + 8, 0.f, 0.f, 0.f, 0.f);
+    return AG_OK;
 }
 
 int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps, double G, double* acc,
