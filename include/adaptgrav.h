@@ -131,6 +131,24 @@ int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
  * length per evaluation (eps). */
 int ag_set_softening(ag_ctx *ctx, int64_t n, const double *h);
 
+/* Relative opening test (Sec. 3: the paper's code opens tree nodes by the
+ * geometric criterion together with the relative criterion of Springel
+ * 2005).  With alpha > 0 every later forward walk (ag_grav_eval,
+ * ag_grav_eval_batched) uses a node, besides the geometric test, only where
+ * G M L^2 / r^4 <= alpha |a_old| (M the node's mass, L its largest box side,
+ * r the distance from its centre of mass to the target) and the target lies
+ * outside the cube of side 1.2 L about the centre of the node's box; a target
+ * group takes its nearest point and its smallest |a_old|, so each target
+ * opens at least as much as it would alone.  acc (n, 3) device FP64 in input
+ * order: the accelerations of the previous evaluation; their sizes are
+ * copied at once (rounded down to FP32), so the caller may overwrite acc.
+ * A target with |a_old| = 0 opens every node (direct summation).  An
+ * evaluation over a tree of another n gives AG_ESTATE, and so does
+ * ag_grav_backward while the test is on.  Non-finite sizes raise the device
+ * flag (AG_ENONFINITE at the next sync).  alpha = 0, acc = NULL or n = 0
+ * turns the test off.  alpha < 0 or non-finite: AG_EINVAL. */
+int ag_set_relative_opening(ag_ctx *ctx, double alpha, int64_t n, const double *acc);
+
 /* Adaptive softening lengths from the built tree (Sec. 4: each element's
  * softening follows the local spacing; here that spacing is the distance to
  * the k-th nearest other particle).  h (n,) device FP64, written in input

@@ -38,7 +38,7 @@ ENTRY_POINTS = [
     "ag_grav_predict", "ag_grav_backward", "ag_timing_enable", "ag_timing_read",
     "ag_kick_drift", "ag_set_option", "ag_graph_begin", "ag_graph_end", "ag_graph_replay",
     "ag_force_log", "ag_grav_predict_poly", "ag_set_periodic", "ag_set_softening",
-    "ag_neighbour_lengths",
+    "ag_neighbour_lengths", "ag_set_relative_opening",
 ]
 AG_PRED_MAX_DEPTH = 4
 AG_OPT_WALK_WAVES_PER_CU = 1
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "ag_set_periodic": [P, D, I32],
         "ag_set_softening": [P, I64, P],
         "ag_neighbour_lengths": [P, I32, P],
+        "ag_set_relative_opening": [P, D, I64, P],
         "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
         "ag_force_log": [P, I64, P, I64, I32, P, D, P, P, P],
@@ -314,6 +315,16 @@ class Context:
             _check(_lib.ag_set_softening(self._h, 0, None))
             return
         _check(_lib.ag_set_softening(self._h, h.shape[0], _ptr(h, torch.float64, None, "h")))
+
+    def set_relative_opening(self, alpha: float = 0.0, acc=None):
+        """Relative opening test with tolerance ``alpha`` against the sizes of
+        ``acc`` (device float64 (n, 3), the previous accelerations); alpha = 0
+        or acc = None turns it off."""
+        if acc is None or alpha == 0.0:
+            _check(_lib.ag_set_relative_opening(self._h, float(alpha), 0, None))
+            return
+        _check(_lib.ag_set_relative_opening(self._h, float(alpha), acc.shape[0],
+                                            _ptr(acc, torch.float64, (3,), "acc")))
 
     def neighbour_lengths(self, k: int, out=None):
         """Distance of every particle to its k-th nearest other particle, from

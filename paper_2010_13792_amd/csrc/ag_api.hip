@@ -189,7 +189,7 @@ extern "C" int ag_destroy(ag_ctx* c) {
                       &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
                       &c->nd_64, &c->nd_w, &c->nd_wf, &c->in_list, &c->in_cnt, &c->in_off,
                       &c->tree_hdr, &c->lvl_list, &c->leaf_list, &c->child, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
-                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->ewald_tab, &c->ewald_q, &c->soft_h, &c->soft_s, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
+                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->ewald_tab, &c->ewald_q, &c->soft_h, &c->soft_s, &c->rel_a, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
                       &c->direct_part, &c->tmp_tidal, &c->sel_flag, &c->sel_off, &c->stats, &c->dflags};
     for (DevBuf* b : bufs) ag_release(*b);
     for (PhaseEvents& p : c->timing.pending) {
@@ -323,6 +323,9 @@ static int check_eval_args(ag_ctx* c, const int32_t* idx, int64_t n_act, double 
     if (!(theta >= 0.0) || !std::isfinite(theta)) return ag_fail(AG_EINVAL, "theta must be >= 0 and finite");
     if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
     if (n_act < 0 || n_act > c->n) return ag_fail(AG_EINVAL, "n_active out of range");
+    if (c->rel_n > 0 && c->rel_n != c->n)
+        return ag_fail(AG_ESTATE, "the relative opening test was set for %lld particles, not %lld",
+                       (long long)c->rel_n, (long long)c->n);
     if (!idx && n_act != c->n && n_act != 0)
         return ag_fail(AG_EINVAL, "active_idx = NULL requires n_active = n (or 0)");
     return AG_OK;
@@ -471,6 +474,38 @@ extern "C" int ag_set_softening(ag_ctx* c, int64_t n, const double* h) {
     return check_launch("set softening");
 }
 
+// |a| of the previous evaluation as FP32, rounded down (the test then opens
+// at least as often as with the exact value); non-finite values raise the flag
+__global__ void k_rel_norm(int64_t n, const double* __restrict__ acc, float* __restrict__ out,
+                           int32_t* __restrict__ flags) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = sqrt(acc[3 * i] * acc[3 * i] + acc[3 * i + 1] * acc[3 * i + 1] + acc[3 * i + 2] * acc[3 * i + 2]);
+        if (!isfinite(a)) atomicOr(flags, AGF_NONFINITE);
+        float f = (float)a;
+        if ((double)f > a) f = nextafterf(f, 0.f);
+        out[i] = isfinite(a) ? f : 0.f;
+    }
+}
+
+extern "C" int ag_set_relative_opening(ag_ctx* c, double alpha, int64_t n, const double* acc) {
+    AG_TRY(check_ctx(c));
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return ag_fail(AG_EINVAL, "alpha must be >= 0 and finite");
+    if (alpha == 0.0 || !acc || n == 0) {
+        c->rel_n = 0;
+        return AG_OK;
+    }
+    if (n < 0 || n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n must be in [0, 2^30]");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_ensure(c->rel_a, (size_t)n * sizeof(float)));
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_rel_norm, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, acc, c->rel_a.as<float>(),
+                       c->dflags.as<int32_t>());
+    c->rel_n = n;
+    c->rel_alpha = alpha;
+    return check_launch("set relative opening");
+}
+
 extern "C" int ag_set_periodic(ag_ctx* c, double box, int32_t ewald) {
     AG_TRY(check_ctx(c));
     if (!(box >= 0.0) || !std::isfinite(box)) return ag_fail(AG_EINVAL, "box must be >= 0 and finite");
@@ -563,6 +598,7 @@ extern "C" int ag_grav_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, co
     if (c->batched) return ag_fail(AG_ESTATE, "backward is not available for a batched tree");
     if (c->box > 0.0) return ag_fail(AG_ESTATE, "backward is not available with periodic boundaries");
     if (c->tree_soft) return ag_fail(AG_ESTATE, "backward is not available with per-particle softening");
+    if (c->rel_n > 0) return ag_fail(AG_ESTATE, "backward is not available with the relative opening test");
     if (!w || !dLdx || !dLdm) return ag_fail(AG_EINVAL, "w, dLdx and dLdm must be non-null");
     DeviceGuard g(c->device);
     AG_TRY(ag_launch_backward(c, idx, n_act, w, theta, eps, G, dLdx, dLdm));

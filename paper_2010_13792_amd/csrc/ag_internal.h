@@ -77,6 +77,8 @@ struct ag_ctx {
     double ewald_tab_box = 0.0;   // box the Ewald table was built for
     double tree_box = 0.0;        // periodic box the tree was built in (positions wrapped into it)
     int64_t soft_n = 0;           // per-particle softening lengths set for this many particles (0: none)
+    int64_t rel_n = 0;            // relative opening test set for this many particles (0: off)
+    double rel_alpha = 0.0;
     bool tree_soft = false;       // the current tree carries them
     int group_cap = 64;
     bool capturing = false;
@@ -130,6 +132,7 @@ struct ag_ctx {
     DevBuf grp;                   // int4 [max groups]: start, count, system, -
     DevBuf soft_h;                // f64 per-particle softening lengths, input order
     DevBuf soft_s;                // f32 the same in key order (rounded up)
+    DevBuf rel_a;                 // f32 |a| of the previous evaluation, input order (rounded down)
     DevBuf ewald_tab;             // f32 Ewald correction table (5 float4 per point)
     DevBuf ewald_q;               // i32 [8]: correction walk work-queue counters
     DevBuf grp_hdr;               // i32: [0] number of groups, [8..15] walk work-queue counters

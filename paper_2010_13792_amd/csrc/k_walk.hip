@@ -84,6 +84,8 @@ struct WalkOut {
     int64_t iter_cap;   // > nodes + particles: every group finishes well within it
     int small_node;     // accepted nodes this small are summed pairwise
     bool mac_offset;    // opening test adds the centre-of-mass offset to the extent
+    const float* rel_a; // relative opening test: |a| of the last evaluation per row (null: off)
+    float rel_alpha;
     double box, box_inv;        // periodic cube side and inverse (periodic walks only)
     float boxf, boxf_inv, box_half;
     // Ewald correction table: (NE + 1)^3 points of spacing h over [0, NE h]^3,
@@ -107,6 +109,7 @@ struct GroupBox {
     double ox, oy, oz;          // origin of the source images (periodic walks; else the centre)
     float hx, hy, hz;           // half extents (rounded up)
     float lox, loy, loz, hix, hiy, hiz;   // absolute box, rounded outward
+    float amin;                 // relative opening test: smallest |a| of the group's targets
 };
 
 __device__ __forceinline__ float f_dn(double d) {
@@ -195,6 +198,41 @@ __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, c
     }
     const float sep2 = gx * gx + gy * gy + gz * gz;
     return r2 > 0.f && L * L <= theta2 * r2 && sep2 >= eps2;
+}
+
+// Relative opening test (Springel 2005), applied on top of the geometric
+// one: a node of mass M and extent L at distance r is used only if
+// G M L^2 / r^4 <= alpha |a_old|, the size the node's truncation error
+// scales with against a fraction of the target's last acceleration, and
+// only if the target lies outside the node's box enlarged 1.2 times about
+// its centre (a cube of side 1.2 L).  For a group, r is the distance from
+// the node's centre of mass to the group's box and |a_old| the smallest of
+// its targets, so every target passes; the cube must miss the whole group
+// box.
+template <int kPer>
+__device__ __forceinline__ bool rel_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
+                                           float mass, const WalkOut& O) {
+    double cdx = c.x - g.cx, cdy = c.y - g.cy, cdz = c.z - g.cz;
+    double bcx = 0.5 * ((double)lo.x + (double)hi.x) - g.cx;
+    double bcy = 0.5 * ((double)lo.y + (double)hi.y) - g.cy;
+    double bcz = 0.5 * ((double)lo.z + (double)hi.z) - g.cz;
+    if (kPer) {   // at the node's image about the image origin
+        cdx = near_img(c.x - g.ox, O) + (g.ox - g.cx);
+        cdy = near_img(c.y - g.oy, O) + (g.oy - g.cy);
+        cdz = near_img(c.z - g.oz, O) + (g.oz - g.cz);
+        bcx = near_img(bcx + (g.cx - g.ox), O) + (g.ox - g.cx);
+        bcy = near_img(bcy + (g.cy - g.oy), O) + (g.oy - g.cy);
+        bcz = near_img(bcz + (g.cz - g.oz), O) + (g.oz - g.cz);
+    }
+    const float rx = fmaxf(fabsf((float)cdx) - g.hx, 0.f);
+    const float ry = fmaxf(fabsf((float)cdy) - g.hy, 0.f);
+    const float rz = fmaxf(fabsf((float)cdz) - g.hz, 0.f);
+    const float r2 = rx * rx + ry * ry + rz * rz;
+    const float L = (float)c.w;
+    if (!(fabsf((float)O.G) * mass * L * L <= O.rel_alpha * g.amin * (r2 * r2))) return false;
+    const float e = 0.6f * L;   // half side of the enlarged cube
+    const bool meets = fabsf((float)bcx) < e + g.hx && fabsf((float)bcy) < e + g.hy && fabsf((float)bcz) < e + g.hz;
+    return !meets;
 }
 
 // particle-node interaction at quadrupole order.  d = node centre - target,
@@ -936,31 +974,39 @@ struct EwaldPolicy {
 // ---- k-th neighbour distance: the length fully adaptive softening follows ----
 // Every node is opened; a node whose box lies farther from the group's box
 // than the group's pruning radius is skipped.  Each target keeps its k
-// smallest squared distances (FP64, unordered) in LDS.  Before the walk the
-// targets take the particles within k sorted positions of the group, which
-// fills every list; the pruning radius is then the largest of the targets'
-// current k-th distances, and shrinks after every tile.  Distances are
+// smallest squared distances so far as an ascending list in LDS; a candidate
+// below the list's last entry goes to a small per-target buffer, and when
+// any buffer of the wave is full (and after every tile) each target sorts
+// its buffer and merges it into its list, keeping the k smallest.  Before
+// the walk the targets take the particles within k sorted positions of the
+// group, which fills every list; the pruning radius is then the largest of
+// the targets' k-th distances, and shrinks after every tile.  Distances are
 // d^2 = (dx^2 + dy^2) + dz^2 with d = x_j - x_i, each operation rounded once.
-constexpr int kKnnMax = 64;
+// Entry i of target slot s sits at [i * 64 + s], so the lanes of a wave touch
+// consecutive words; the list capacity kCap (16, 32 or 64) is the smallest
+// that holds k, which keeps the LDS of a wave small.
+constexpr int kKnnBuf = 8;
+template <int kCap>
 struct KnnLds : WalkLds<2> {
-    double lst[kW * kKnnMax];
+    double lst[kW * kCap];
+    double buf[kW * kKnnBuf];
     double r2;
     int win_lo, win_hi;   // sorted positions taken before the walk
 };
+template <int kCap>
 struct KnnPolicy {
     static constexpr bool kSkipEmpty = false;
     static constexpr bool kOpenAll = true;
     static constexpr bool kImageMac = false;
     static constexpr bool kGroupSum = false;
-    using Lds = KnnLds;
+    using Lds = KnnLds<kCap>;
     struct Acc {
         double x, y, z;   // the target
-        double kth;       // largest entry of its list
-        int cnt, imax;
+        double kth;       // last entry of its list (+inf while not full)
+        int nb;           // buffered candidates
         __device__ void zero() {
-            kth = 0.0;
-            cnt = 0;
-            imax = 0;
+            kth = __builtin_huge_val();
+            nb = 0;
         }
         __device__ void add(const Acc&) {}
     };
@@ -969,33 +1015,58 @@ struct KnnPolicy {
 #pragma clang fp contract(off)
         return (dx * dx + dy * dy) + dz * dz;
     }
-    __device__ static void insert(Lds& S, Acc& A, int slot, double d2, int k) {
-        double* L = S.lst + slot * kKnnMax;
-        if (A.cnt < k) {
-            L[A.cnt] = d2;
-            if (A.cnt == 0 || d2 > A.kth) {
-                A.kth = d2;
-                A.imax = A.cnt;
-            }
-            ++A.cnt;
-            return;
+    __device__ static void offer(Lds& S, Acc& A, int slot, double d2) {
+        if (d2 < A.kth) {
+            S.buf[A.nb * kW + slot] = d2;
+            ++A.nb;
         }
-        if (!(d2 < A.kth)) return;
-        L[A.imax] = d2;
-        double mx = L[0];
-        int im = 0;
-        for (int i = 1; i < k; ++i)
-            if (L[i] > mx) {
-                mx = L[i];
-                im = i;
-            }
-        A.kth = mx;
-        A.imax = im;
     }
-    // radius^2 no target's k-th neighbour lies beyond (every list full)
-    __device__ static void update_radius(Lds& S, const Acc& A, bool owner, int k) {
-        const double mine = owner ? (A.cnt >= k ? A.kth : __builtin_huge_val()) : 0.0;
-        const double r2 = ag_wave_max(mine);
+    // list <- the k smallest of list and buffer (both ascending)
+    __device__ static void merge(Lds& S, Acc& A, int slot, int k) {
+        double* B = S.buf + slot;
+        double* L = S.lst + slot;
+        const int nb = A.nb;
+        for (int i = 1; i < nb; ++i) {   // insertion sort of the buffer
+            const double x = B[i * kW];
+            int j = i;
+            while (j > 0) {
+                const double y = B[(j - 1) * kW];
+                if (!(y > x)) break;
+                B[j * kW] = y;
+                --j;
+            }
+            B[j * kW] = x;
+        }
+        // c buffered entries enter; the list's top c leave
+        int c = 0;
+        while (c < nb && c < k && B[c * kW] < L[(k - 1 - c) * kW]) ++c;
+        int w = k - 1, a = k - 1 - c, b = c - 1;
+        while (b >= 0) {               // backward merge in place (w >= a)
+            const double bv = B[b * kW];
+            if (a >= 0) {
+                const double av = L[a * kW];
+                if (av > bv) {
+                    L[w * kW] = av;
+                    --w;
+                    --a;
+                    continue;
+                }
+            }
+            L[w * kW] = bv;
+            --w;
+            --b;
+        }
+        A.kth = L[(k - 1) * kW];
+        A.nb = 0;
+    }
+    // merge every buffer once any of them is full
+    __device__ static void check_full(Lds& S, Acc& A, bool owner, int slot, int k) {
+        if (__ballot(A.nb == kKnnBuf) != 0 && owner && A.nb > 0) merge(S, A, slot, k);
+    }
+    // merge every buffer; radius^2 no target's k-th neighbour lies beyond
+    __device__ static void flush(Lds& S, Acc& A, bool owner, int slot, int k) {
+        if (owner && A.nb > 0) merge(S, A, slot, k);
+        const double r2 = ag_wave_max(owner ? A.kth : 0.0);
         if (threadIdx.x == 0) S.r2 = r2;
     }
     // Both boxes are rounded outward, their gaps are exact in FP64, and the
@@ -1010,11 +1081,14 @@ struct KnnPolicy {
     }
     __device__ static void start(Lds& S, const Tree& T, const WalkOut& O, int4 gd, const Target& t, Acc& A,
                                  int part, int slot, int count) {
+        const bool owner = part == 0;
         const double4 xi = T.spos[t.p];
         A.x = xi.x;
         A.y = xi.y;
         A.z = xi.z;
         const int k = O.knn_k;
+        if (owner)
+            for (int i = 0; i < k; ++i) S.lst[i * kW + slot] = __builtin_huge_val();
         const int64_t lo = gd.x - k > 0 ? gd.x - k : 0;
         const int64_t hi = gd.x + count + k < O.knn_n ? gd.x + count + k : O.knn_n;
         if (threadIdx.x == 0) {
@@ -1030,13 +1104,13 @@ struct KnnPolicy {
                 S.tidx[threadIdx.x] = (int)(base + threadIdx.x);
             }
             __syncthreads();
-            if (part == 0)
-                for (int q = 0; q < cw; ++q) {
-                    if (S.tidx[q] == t.p) continue;
-                    insert(S, A, slot, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z), k);
-                }
+            for (int q = 0; q < cw; ++q) {
+                if (owner && S.tidx[q] != t.p)
+                    offer(S, A, slot, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z));
+                check_full(S, A, owner, slot, k);
+            }
         }
-        update_radius(S, A, part == 0, k);
+        flush(S, A, owner, slot, k);
         __syncthreads();
     }
     template <int kPer>
@@ -1050,27 +1124,27 @@ struct KnnPolicy {
     __device__ static void particles(Lds& S, int cnt, const Target& t, Acc& A, float, float, int k0, int,
                                      const WalkOut& O) {
         const int k = O.knn_k;
+        const bool owner = k0 == 0;   // the target's first lane keeps its list
+        const int slot = threadIdx.x;
         const double4* P = reinterpret_cast<const double4*>(S.tile);
-        if (k0 == 0) {   // the target's first lane keeps its list
-            const int slot = threadIdx.x;
-            for (int q = 0; q < cnt; ++q) {
-                const int pk = S.tidx[q];
-                if (pk == t.p || (pk >= S.win_lo && pk < S.win_hi)) continue;
-                insert(S, A, slot, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z), k);
-            }
+        for (int q = 0; q < cnt; ++q) {
+            const int pk = S.tidx[q];
+            if (owner && pk != t.p && (pk < S.win_lo || pk >= S.win_hi))
+                offer(S, A, slot, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z));
+            check_full(S, A, owner, slot, k);
         }
-        update_radius(S, A, k0 == 0, k);
+        flush(S, A, owner, slot, k);
     }
     __device__ static void nodes(const Lds&, int, const Target&, Acc&, int, int, const WalkOut&) {}
     static __device__ void wave_sum(Acc&) {}
     __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
-        O.knn_out[T.perm[p]] = A.cnt >= O.knn_k ? sqrt(A.kth) : __builtin_huge_val();
+        O.knn_out[T.perm[p]] = sqrt(A.kth);
     }
 };
 
 template <class P>
 __device__ __forceinline__ bool policy_skips(const typename P::Lds& S, const Tree& T, const GroupBox& g, int a) {
-    if constexpr (P::kOpenAll) return KnnPolicy::skip_node(S, T, g, a);
+    if constexpr (P::kOpenAll) return P::skip_node(S, T, g, a);
     else if constexpr (P::kSkipEmpty) return T.wf[8 * a].w == 0.f;
     else return false;
 }
@@ -1119,6 +1193,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     tg.vz = vi.z;
     tg.p = p_i;
     tg.grp = Pol::kGroupSum && fmaxf(fmaxf(gb.hx, gb.hy), gb.hz) <= O.ewald_grp;
+    gb.amin = O.rel_a ? ag_wave_min(O.rel_a[T.perm[p_i]]) : 0.f;
     typename Pol::Acc acc;
     acc.zero();
     if constexpr (Pol::kOpenAll) Pol::start(S, T, O, gd, tg, acc, part, slot, count);
@@ -1195,7 +1270,9 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
                     : Pol::kImageMac ? ewald_accept(gb, T.com[a], T.lo[a], T.hi[a], O)
                                    : mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2,
                                                       kSoft ? fmaxf(gh2, T.lo[a].w * T.lo[a].w) : eps2,
-                                                      O.mac_offset, O);
+                                                      O.mac_offset, O) &&
+                                         (!O.rel_a || rel_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a],
+                                                                       T.mp[4 * a].x, O));
                 if (acc_ok && L.z > O.small_node) {
                     push_node = a;
                     ca = L.x;
@@ -1825,8 +1902,17 @@ int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out) {
     O.knn_k = k;
     O.knn_n = c->n;
     PhaseScope phase(c, AG_PHASE_NEIGHBOUR);
-    hipLaunchKernelGGL((k_walk<KnnPolicy, kOpen>), dim3((unsigned)walk_grid(c, mg)), dim3(kW), 0, c->stream,
-                       make_tree(c), Gr, O, c->grp_hdr.as<int32_t>() + 8, 0.f, 0.f, 0.f, 0.f);
+    const unsigned grid = (unsigned)walk_grid(c, mg);
+    int32_t* qctr = c->grp_hdr.as<int32_t>() + 8;
+    if (k <= 16)
+        hipLaunchKernelGGL((k_walk<KnnPolicy<16>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
+                           qctr, 0.f, 0.f, 0.f, 0.f);
+    else if (k <= 32)
+        hipLaunchKernelGGL((k_walk<KnnPolicy<32>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
+                           qctr, 0.f, 0.f, 0.f, 0.f);
+    else
+        hipLaunchKernelGGL((k_walk<KnnPolicy<64>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
+                           qctr, 0.f, 0.f, 0.f, 0.f);
     return AG_OK;
 }
 
@@ -1836,20 +1922,18 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
     AG_TRY(ag_prepare_groups(c, idx, n_act, &mg));
     Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
               c->grp_hdr.as<int32_t>()};
-    WalkOut O = make_out(c, G);
+    const bool ewald = c->box > 0.0 && c->ewald;
+    if (ewald) AG_TRY(ewald_table(c));
+    WalkOut O = make_out(c, G);   // after the table, for its address
     O.acc = acc;
     O.jerk = jerk;
     O.tidal = tidal;
+    if (c->rel_n > 0) {
+        O.rel_a = c->rel_a.as<float>();
+        O.rel_alpha = (float)c->rel_alpha;
+    }
     const float th = (float)theta;
     const float e2 = (float)(eps * eps);
-    const bool ewald = c->box > 0.0 && c->ewald;
-    if (ewald) {
-        AG_TRY(ewald_table(c));
-        O = make_out(c, G);   // with the table's address
-        O.acc = acc;
-        O.jerk = jerk;
-        O.tidal = tidal;
-    }
     const unsigned grid = (unsigned)walk_grid(c, mg);
     int32_t* qctr = c->grp_hdr.as<int32_t>() + 8;
     {
@@ -1885,6 +1969,7 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
         hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, c->stream, c->ewald_q.as<int32_t>(), (int64_t)8);
         WalkOut E = O;
         E.stats = nullptr;
+        E.rel_a = nullptr;
         hipLaunchKernelGGL((k_walk<EwaldPolicy, kEwald>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, E,
                            c->ewald_q.as<int32_t>(), 0.f, 0.f, e2, (float)(1.0 / eps));
     }
