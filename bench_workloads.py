@@ -522,6 +522,72 @@ def run_softening(args):
 
 
 # ---------------------------------------------------------------------------
+def run_relative(args):
+    """Geometric opening test alone at several theta against the combined
+    geometric + relative test at several alpha (|a_old| from the previous
+    evaluation, theta = 0.7): time per tree build + evaluation, interactions
+    per target and the force error against the oracle on sampled rows."""
+    import oracle
+    n = args.n
+    x, v, m = workloads.turbulent_sphere(n, seed=2, grid=128)
+    tx, tv, tm = _t(x), _t(v), _t(m)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+    jerk, tid = torch.zeros_like(acc), torch.zeros((n, 6), dtype=torch.float64, device=DEV)
+    rows = np.random.default_rng(8).choice(n, 4096, replace=False)
+    log("relative: oracle direct sum on 4096 sampled rows")
+    ar, _, _ = oracle.direct(x, v, m, args.eps, 1.0, rows)
+    # |a_old|: the previous evaluation (geometric test, theta = 0.7)
+    with ag.Context(0) as c:
+        c.tree_build(tx, tv, tm, args.n_leaf)
+        c.grav_eval(None, 0.7, args.eps, 1.0, acc, jerk, tid)
+        c.sync()
+    a_old = acc.clone()
+    out = {"workload": f"turbulent sphere N={n}, eps={args.eps}; |a_old| from a theta=0.7 evaluation", "runs": {}}
+    cases = [("geometric", th, 0.0) for th in (0.7, 0.5, 0.35)] + [("combined", 0.7, al)
+                                                                    for al in (0.01, 0.0025, 0.0005)]
+    for kind, th, al in cases:
+        with ag.Context(0) as c:
+            c.set_option(ag.AG_OPT_MAC_OFFSET, args.mac_offset)
+            if al > 0:
+                c.set_relative_opening(al, a_old)
+
+            def step():
+                c.tree_build(tx, tv, tm, args.n_leaf)
+                c.grav_eval(None, th, args.eps, 1.0, acc, jerk, tid)
+
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            c.stats_reset()
+            e0, e1 = _events()
+            reps = 10
+            e0.record()
+            for _ in range(reps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            st = c.stats_read()
+            c.timing_enable(True)
+            c.timing_read(reset=True)
+            for _ in range(reps):
+                step()
+            ph = c.timing_read(reset=True)
+            c.timing_enable(False)
+        walk_ms = ph["walk"]["ms"] / reps
+        flops = (st["n_pp"] * PP_FLOPS + st["n_pn"] * PN_FLOPS) / reps
+        e = _rel(acc.cpu().numpy()[rows], ar)
+        key = f"{kind} theta={th}" + (f" alpha={al}" if al > 0 else "")
+        out["runs"][key] = {"ms_per_step": ms, "evals_per_s": n / (ms * 1e-3), "walk_ms": walk_ms,
+                            "walk_tflops": flops / (walk_ms * 1e-3) / 1e12,
+                            "per_target": {"pp": st["n_pp"] / reps / n, "pn": st["n_pn"] / reps / n},
+                            "median_rel_force_err": float(np.median(e)),
+                            "p99_rel_force_err": float(np.percentile(e, 99))}
+        log(f"relative {key}: {out['runs'][key]}")
+    return out
+
+
+# ---------------------------------------------------------------------------
 def run_copy(args):
     n = 1 << 27                      # 2^27 doubles = 1 GiB
     a = torch.ones(n, dtype=torch.float64, device=DEV)

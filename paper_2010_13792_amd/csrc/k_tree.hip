@@ -713,7 +713,7 @@ __device__ void store_node(int64_t id, const double* r, double4* __restrict__ co
     }
     com[id] = make_double4(r[1], r[2], r[3], L);
     lo4[id] = make_float4(f_down(r[19]), f_down(r[20]), f_down(r[21]), hmax);
-    hi4[id] = make_float4(f_up(r[22]), f_up(r[23]), f_up(r[24]), 0.f);
+    hi4[id] = make_float4(f_up(r[22]), f_up(r[23]), f_up(r[24]), (float)r[0]);   // w: mass
     float4* q = mp + 4 * id;
     q[0] = make_float4((float)r[0], (float)r[4], (float)r[5], (float)r[6]);
     q[1] = make_float4((float)r[7], (float)r[8], (float)r[9], (float)r[10]);

@@ -86,6 +86,7 @@ struct WalkOut {
     bool mac_offset;    // opening test adds the centre-of-mass offset to the extent
     const float* rel_a; // relative opening test: |a| of the last evaluation per row (null: off)
     float rel_alpha;
+    float rel_g;        // |G| of the relative test
     double box, box_inv;        // periodic cube side and inverse (periodic walks only)
     float boxf, boxf_inv, box_half;
     // Ewald correction table: (NE + 1)^3 points of spacing h over [0, NE h]^3,
@@ -172,15 +173,16 @@ __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, c
         L += sqrtf(ox * ox + oy * oy + oz * oz);
     }
     float gx, gy, gz;
+    float bx, by, bz;   // box centre offset from the group centre (at its nearest image)
     if (!kPer) {
         gx = fmaxf(fmaxf(lo.x - g.hix, g.lox - hi.x), 0.f);
         gy = fmaxf(fmaxf(lo.y - g.hiy, g.loy - hi.y), 0.f);
         gz = fmaxf(fmaxf(lo.z - g.hiz, g.loz - hi.z), 0.f);
     } else {
         // box centre offset at its nearest image, and the half extents
-        const float bx = fabsf((float)(near_img(0.5 * ((double)lo.x + (double)hi.x) - g.ox, O) + (g.ox - g.cx)));
-        const float by = fabsf((float)(near_img(0.5 * ((double)lo.y + (double)hi.y) - g.oy, O) + (g.oy - g.cy)));
-        const float bz = fabsf((float)(near_img(0.5 * ((double)lo.z + (double)hi.z) - g.oz, O) + (g.oz - g.cz)));
+        bx = fabsf((float)(near_img(0.5 * ((double)lo.x + (double)hi.x) - g.ox, O) + (g.ox - g.cx)));
+        by = fabsf((float)(near_img(0.5 * ((double)lo.y + (double)hi.y) - g.oy, O) + (g.oy - g.cy)));
+        bz = fabsf((float)(near_img(0.5 * ((double)lo.z + (double)hi.z) - g.oz, O) + (g.oz - g.cz)));
         const float ex = 0.5f * (hi.x - lo.x) + g.hx;
         const float ey = 0.5f * (hi.y - lo.y) + g.hy;
         const float ez = 0.5f * (hi.z - lo.z) + g.hz;
@@ -197,42 +199,25 @@ __device__ __forceinline__ bool mac_accept(const GroupBox& g, const double4 c, c
         gz = fmaxf(bz - ez, 0.f);
     }
     const float sep2 = gx * gx + gy * gy + gz * gz;
-    return r2 > 0.f && L * L <= theta2 * r2 && sep2 >= eps2;
-}
-
-// Relative opening test (Springel 2005), applied on top of the geometric
-// one: a node of mass M and extent L at distance r is used only if
-// G M L^2 / r^4 <= alpha |a_old|, the size the node's truncation error
-// scales with against a fraction of the target's last acceleration, and
-// only if the target lies outside the node's box enlarged 1.2 times about
-// its centre (a cube of side 1.2 L).  For a group, r is the distance from
-// the node's centre of mass to the group's box and |a_old| the smallest of
-// its targets, so every target passes; the cube must miss the whole group
-// box.
-template <int kPer>
-__device__ __forceinline__ bool rel_accept(const GroupBox& g, const double4 c, const float4 lo, const float4 hi,
-                                           float mass, const WalkOut& O) {
-    double cdx = c.x - g.cx, cdy = c.y - g.cy, cdz = c.z - g.cz;
-    double bcx = 0.5 * ((double)lo.x + (double)hi.x) - g.cx;
-    double bcy = 0.5 * ((double)lo.y + (double)hi.y) - g.cy;
-    double bcz = 0.5 * ((double)lo.z + (double)hi.z) - g.cz;
-    if (kPer) {   // at the node's image about the image origin
-        cdx = near_img(c.x - g.ox, O) + (g.ox - g.cx);
-        cdy = near_img(c.y - g.oy, O) + (g.oy - g.cy);
-        cdz = near_img(c.z - g.oz, O) + (g.oz - g.cz);
-        bcx = near_img(bcx + (g.cx - g.ox), O) + (g.ox - g.cx);
-        bcy = near_img(bcy + (g.cy - g.oy), O) + (g.oy - g.cy);
-        bcz = near_img(bcz + (g.cz - g.oz), O) + (g.oz - g.cz);
+    if (!(r2 > 0.f && L * L <= theta2 * r2 && sep2 >= eps2)) return false;
+    if (!O.rel_a) return true;
+    // Relative test (Springel 2005) on top of the geometric one: a node of
+    // mass M (hi.w) and extent Ln at distance r is used only if
+    // G M Ln^2 / r^4 <= alpha |a_old|, the size its truncation error scales
+    // with against a fraction of the target's last acceleration, and only if
+    // the target lies outside the cube of side 1.2 Ln about the node's box
+    // centre.  For a group, r is the distance from the centre of mass to the
+    // group's box (r2 above) and |a_old| the smallest of its targets, so
+    // every target passes; the cube must miss the whole group box.
+    const float Ln = (float)c.w;
+    if (!(O.rel_g * hi.w * Ln * Ln <= O.rel_alpha * g.amin * (r2 * r2))) return false;
+    if (!kPer) {
+        bx = fabsf((float)(0.5 * ((double)lo.x + (double)hi.x) - g.cx));
+        by = fabsf((float)(0.5 * ((double)lo.y + (double)hi.y) - g.cy));
+        bz = fabsf((float)(0.5 * ((double)lo.z + (double)hi.z) - g.cz));
     }
-    const float rx = fmaxf(fabsf((float)cdx) - g.hx, 0.f);
-    const float ry = fmaxf(fabsf((float)cdy) - g.hy, 0.f);
-    const float rz = fmaxf(fabsf((float)cdz) - g.hz, 0.f);
-    const float r2 = rx * rx + ry * ry + rz * rz;
-    const float L = (float)c.w;
-    if (!(fabsf((float)O.G) * mass * L * L <= O.rel_alpha * g.amin * (r2 * r2))) return false;
-    const float e = 0.6f * L;   // half side of the enlarged cube
-    const bool meets = fabsf((float)bcx) < e + g.hx && fabsf((float)bcy) < e + g.hy && fabsf((float)bcz) < e + g.hz;
-    return !meets;
+    const float e = 0.6f * Ln;
+    return !(bx < e + g.hx && by < e + g.hy && bz < e + g.hz);
 }
 
 // particle-node interaction at quadrupole order.  d = node centre - target,
@@ -1270,9 +1255,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
                     : Pol::kImageMac ? ewald_accept(gb, T.com[a], T.lo[a], T.hi[a], O)
                                    : mac_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a], theta2,
                                                       kSoft ? fmaxf(gh2, T.lo[a].w * T.lo[a].w) : eps2,
-                                                      O.mac_offset, O) &&
-                                         (!O.rel_a || rel_accept<kPer>(gb, T.com[a], T.lo[a], T.hi[a],
-                                                                       T.mp[4 * a].x, O));
+                                                      O.mac_offset, O);
                 if (acc_ok && L.z > O.small_node) {
                     push_node = a;
                     ca = L.x;
@@ -1931,6 +1914,7 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
     if (c->rel_n > 0) {
         O.rel_a = c->rel_a.as<float>();
         O.rel_alpha = (float)c->rel_alpha;
+        O.rel_g = (float)fabs(G);
     }
     const float th = (float)theta;
     const float e2 = (float)(eps * eps);
