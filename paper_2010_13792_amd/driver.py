@@ -41,17 +41,22 @@ PREDICTORS = {"jerk": None, "none": None, "linear": 1, "quadratic": 2}
 class AdaptiveIntegrator:
     def __init__(self, ctx: Context, x, v, m, q_f: float, theta: float, eps: float, eta: float = 0.01,
                  G: float = 1.0, n_leaf: int = 16, rebuild_every: int = 1, step_shift: int = 0,
-                 predictor: str = "jerk"):
+                 predictor: str = "jerk", opening_alpha: float = 0.0):
         """step_shift h: the global step is 2^-h times the shortest gravity
         bin at t = 0 (h = 0: the step equals the shortest gravity step; h > 0
         models a non-gravity step constraint tighter than gravity's, the
         regime in which the scheme saves work).  predictor: "jerk" (Eq. 6),
         "none", "linear" or "quadratic" (polynomial through the last 2 or 3
-        fresh forces; fewer right after the start)."""
+        fresh forces; fewer right after the start).  opening_alpha > 0 adds
+        the relative opening test to every evaluation after the first, against
+        each particle's last fresh force."""
         if predictor not in PREDICTORS:
             raise ValueError(f"predictor must be one of {sorted(PREDICTORS)}")
         self.predictor = predictor
         self.order = PREDICTORS[predictor]
+        if not opening_alpha >= 0.0:
+            raise ValueError("opening_alpha must be >= 0")
+        self.opening_alpha = float(opening_alpha)
         self.ctx = ctx
         dev = x.device
         self.n = n = x.shape[0]
@@ -84,6 +89,7 @@ class AdaptiveIntegrator:
         self.evaluations = 0
         # initial forces for everybody, then the time grid
         ctx.tree_build(self.x, self.v, self.m, n_leaf)
+        ctx.set_relative_opening()   # no earlier force: the geometric test alone
         ctx.grav_eval(None, theta, eps, G, self.a0, self.jerk, self.tidal)
         ctx.grav_timestep(self.tidal, eta, 1.0, 60, self.dt_grav, self.bins)
         ctx.sync()
@@ -117,6 +123,7 @@ class AdaptiveIntegrator:
         k = int(self.n_active.item())
         if k > 0:
             idx = self.active[:k]
+            c.set_relative_opening(self.opening_alpha, self.a0 if self.opening_alpha > 0 else None)
             c.grav_eval(idx, self.theta, self.eps, self.G, self.a0, self.jerk, self.tidal)
             c.grav_timestep(self.tidal, self.eta, self.dt_max, 60, self.dt_grav, self.bins, idx=idx)
             if self.log is not None:

@@ -74,6 +74,27 @@ def test_adaptive_counts_and_force_error(ag, orc):
         assert np.median(err) < 2e-3
 
 
+def test_adaptive_relative_opening(ag, orc):
+    """The integrator with the relative opening test: the fresh forces of the
+    last step's active rows against the oracle's direct sum at the same
+    positions, and more accurate than the geometric test alone."""
+    from paper_2010_13792_amd.driver import AdaptiveIntegrator
+    n = 1 << 14
+    tx, tv, tm, (x, v, m) = _clumps(n)
+    errs = {}
+    with ag.Context(0) as c:
+        for alpha in (0.0, 0.0025):
+            ad = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.5, theta=0.7, eps=1e-3, opening_alpha=alpha)
+            for _ in range(6):
+                k = ad.step()
+            c.sync()
+            rows = ad.active[:k].cpu().numpy().astype(np.int64)[:1024]
+            ar, _, _ = orc.direct(ad.x.cpu().numpy(), ad.vpred.cpu().numpy(), m, 1e-3, 1.0, rows)
+            errs[alpha] = rel_err(ad.a0.cpu().numpy()[rows], ar)
+    assert np.percentile(errs[0.0025], 99) <= 2.5e-3
+    assert np.percentile(errs[0.0025], 99) < np.percentile(errs[0.0], 99)
+
+
 def _move(v, dev):
     if torch.is_tensor(v):
         return v.to(dev)
