@@ -41,7 +41,8 @@ PREDICTORS = {"jerk": None, "none": None, "linear": 1, "quadratic": 2}
 class AdaptiveIntegrator:
     def __init__(self, ctx: Context, x, v, m, q_f: float, theta: float, eps: float, eta: float = 0.01,
                  G: float = 1.0, n_leaf: int = 16, rebuild_every: int = 1, step_shift: int = 0,
-                 predictor: str = "jerk", opening_alpha: float = 0.0):
+                 predictor: str = "jerk", opening_alpha: float = 0.0, soft_k: int = 0,
+                 soft_scale: float = 1.0):
         """step_shift h: the global step is 2^-h times the shortest gravity
         bin at t = 0 (h = 0: the step equals the shortest gravity step; h > 0
         models a non-gravity step constraint tighter than gravity's, the
@@ -49,7 +50,11 @@ class AdaptiveIntegrator:
         "none", "linear" or "quadratic" (polynomial through the last 2 or 3
         fresh forces; fewer right after the start).  opening_alpha > 0 adds
         the relative opening test to every evaluation after the first, against
-        each particle's last fresh force."""
+        each particle's last fresh force.  soft_k > 0 softens every particle
+        with its own length, soft_scale times its distance to the soft_k-th
+        nearest neighbour, found on the device from each step's tree and used
+        from the next build on (so one step late; the first build is made
+        twice).  eps is then only validated."""
         if predictor not in PREDICTORS:
             raise ValueError(f"predictor must be one of {sorted(PREDICTORS)}")
         self.predictor = predictor
@@ -57,6 +62,9 @@ class AdaptiveIntegrator:
         if not opening_alpha >= 0.0:
             raise ValueError("opening_alpha must be >= 0")
         self.opening_alpha = float(opening_alpha)
+        if soft_k < 0 or not soft_scale > 0.0:
+            raise ValueError("soft_k must be >= 0 and soft_scale > 0")
+        self.soft_k, self.soft_scale = int(soft_k), float(soft_scale)
         self.ctx = ctx
         dev = x.device
         self.n = n = x.shape[0]
@@ -77,6 +85,7 @@ class AdaptiveIntegrator:
         self.active = torch.zeros(n, dtype=torch.int32, device=dev)
         self.n_active = torch.zeros(1, dtype=torch.int64, device=dev)
         self.vpred = torch.zeros_like(self.v)
+        self.h = torch.zeros(n, dtype=torch.float64, device=dev) if soft_k > 0 else None
         self.scratch = torch.zeros_like(self.x)
         self.log = None
         if self.order is not None:
@@ -88,7 +97,11 @@ class AdaptiveIntegrator:
         self.step_index = 0
         self.evaluations = 0
         # initial forces for everybody, then the time grid
+        ctx.set_softening()
         ctx.tree_build(self.x, self.v, self.m, n_leaf)
+        if self.h is not None:
+            self._lengths()
+            ctx.tree_build(self.x, self.v, self.m, n_leaf)
         ctx.set_relative_opening()   # no earlier force: the geometric test alone
         ctx.grav_eval(None, theta, eps, G, self.a0, self.jerk, self.tidal)
         ctx.grav_timestep(self.tidal, eta, 1.0, 60, self.dt_grav, self.bins)
@@ -105,6 +118,13 @@ class AdaptiveIntegrator:
         self.evaluations += n
         self._need_build = False
 
+    def _lengths(self):
+        """Lengths from the current tree, in use from the next build on."""
+        self.ctx.neighbour_lengths(self.soft_k, self.h)
+        if self.soft_scale != 1.0:
+            self.h.mul_(self.soft_scale)
+        self.ctx.set_softening(self.h)
+
     def step(self) -> int:
         c, dt = self.ctx, self.dt
         c.kick_drift(self.x, self.v, self.acc, 0.5 * dt, dt)
@@ -118,6 +138,8 @@ class AdaptiveIntegrator:
         if self._need_build or (self.step_index - 1) % self.rebuild_every == 0:
             c.tree_build(self.x, self.vpred, self.m, self.n_leaf)
             self._need_build = False
+            if self.h is not None:
+                self._lengths()
         else:
             c.tree_refit(self.x, self.vpred, self.m)
         k = int(self.n_active.item())
@@ -144,6 +166,8 @@ class AdaptiveIntegrator:
         s = {k: getattr(self, k).clone() for k in keys}
         if self.log is not None:
             s["log"] = tuple(a.clone() for a in self.log)
+        if self.h is not None:
+            s["h"] = self.h.clone()
         s.update(t=self.t, step_index=self.step_index, evaluations=self.evaluations, dt=self.dt,
                  dt_max=self.dt_max, tick_bin=self.tick_bin)
         return s
@@ -157,6 +181,9 @@ class AdaptiveIntegrator:
         if self.log is not None:
             for a, b in zip(self.log, s["log"]):
                 a.copy_(b)
+        if self.h is not None:
+            self.h.copy_(s["h"])
+            self.ctx.set_softening(self.h)
         for k in ["t", "step_index", "evaluations", "dt", "dt_max", "tick_bin"]:
             setattr(self, k, s[k])
         self._need_build = True

@@ -95,6 +95,45 @@ def test_adaptive_relative_opening(ag, orc):
     assert np.percentile(errs[0.0025], 99) < np.percentile(errs[0.0], 99)
 
 
+def test_adaptive_softening_integrator(ag, orc):
+    """Lengths from the device each step (32nd neighbour): the fresh forces
+    of the last step's active rows against the oracle's mean-kernel sum with
+    the lengths the evaluation used, and a bit-exact resume."""
+    from paper_2010_13792_amd.driver import AdaptiveIntegrator
+    n = 1 << 13
+    tx, tv, tm, (x, v, m) = _clumps(n)
+    kw = dict(q_f=0.5, theta=0.6, eps=1e-3, soft_k=32)
+    with ag.Context(0) as c:
+        ad = AdaptiveIntegrator(c, tx, tv, tm, **kw)
+        for _ in range(4):
+            ad.step()
+        h_used = ad.h.cpu().numpy().copy()      # set after this build: used by the next
+        k = ad.step()
+        c.sync()
+        xs = ad.x.cpu().numpy()
+        rows = ad.active[:k].cpu().numpy().astype(np.int64)[:1024]
+        ar, _, _ = orc.direct_soft(xs, ad.vpred.cpu().numpy(), m, h_used, 1.0, rows)
+        err = rel_err(ad.a0.cpu().numpy()[rows], ar)
+        assert np.median(err) <= 1e-3 and np.percentile(err, 99) <= 1e-2
+        # the lengths set after the last build are those of its positions
+        np.testing.assert_array_equal(ad.h.cpu().numpy(), orc.neighbour_length(xs, 32))
+        # resume
+        a = AdaptiveIntegrator(c, tx, tv, tm, **kw)
+        for _ in range(4):
+            a.step()
+        saved = a.state()
+        ref = [a.step() for _ in range(2)]
+        c.sync()
+        ref_state = a.state()
+        r = AdaptiveIntegrator(c, tx, tv, tm, **kw)
+        r.restore(saved)
+        got = [r.step() for _ in range(2)]
+        c.sync()
+        assert got == ref
+        for key in ["x", "v", "acc", "h"]:
+            assert torch.equal(r.state()[key], ref_state[key]), key
+
+
 def _move(v, dev):
     if torch.is_tensor(v):
         return v.to(dev)

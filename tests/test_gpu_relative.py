@@ -243,3 +243,34 @@ def test_relative_other_walks(ag, orc, mode):
           f"combined median {np.median(e1):.2e} p99 {np.percentile(e1, 99):.2e}", flush=True)
     assert np.percentile(e1, 99) <= np.percentile(e0, 99)
     assert np.percentile(e1, 99) <= alpha / 2
+
+
+def test_relative_batched(ag, orc):
+    """Batched systems: each system's targets use their own |a_old|; the
+    forces of the listed rows against the oracle, system by system."""
+    B = workloads.batched_plummer(nsys=6, seed=41, nmin=1024, nmax=8192)
+    x, v, m, off, act = B["x"], B["v"], B["m"], B["offsets"], B["active"]
+    n = len(m)
+    a_old = np.empty((n, 3))
+    for s in range(len(off) - 1):
+        sl = slice(off[s], off[s + 1])
+        a_old[sl], _, _ = orc.direct(x[sl], v[sl], m[sl], 0.01, 1.0)
+    errs = {}
+    for alpha in (0.0, 0.0025):
+        with ag.Context(0) as c:
+            c.tree_build_batched(_t(x), _t(v), _t(m), _t(off), 16)
+            c.set_relative_opening(alpha, _t(a_old) if alpha > 0 else None)
+            out = _outputs(n)
+            c.grav_eval_batched(_t(act, torch.int32), 0.5, 0.01, 1.0, *out)
+            c.sync()
+            a = out[0].cpu().numpy()
+        e = []
+        for s in range(len(off) - 1):
+            rows = act[(act >= off[s]) & (act < off[s + 1])]
+            sl = slice(off[s], off[s + 1])
+            ar, _, _ = orc.direct(x[sl], v[sl], m[sl], 0.01, 1.0, rows - off[s])
+            e.append(rel_err(a[rows], ar))
+        errs[alpha] = np.concatenate(e)
+    print(f"batched: geometric p99 {np.percentile(errs[0.0], 99):.2e}, combined p99 "
+          f"{np.percentile(errs[0.0025], 99):.2e}", flush=True)
+    assert np.percentile(errs[0.0025], 99) <= min(np.percentile(errs[0.0], 99), 0.0025 / 2)
