@@ -107,7 +107,7 @@ def test_adaptive_softening_integrator(ag, orc):
         ad = AdaptiveIntegrator(c, tx, tv, tm, **kw)
         for _ in range(4):
             ad.step()
-        h_used = ad.h.cpu().numpy().copy()      # set after this build: used by the next
+        h_used = ad.h.cpu().numpy().copy()      # set after the 4th step's tree: used by the 5th
         k = ad.step()
         c.sync()
         xs = ad.x.cpu().numpy()
