@@ -326,6 +326,7 @@ struct ForwardPolicy {
     static constexpr bool kOpenAll = false;
     static constexpr bool kImageMac = false;
     static constexpr bool kGroupSum = false;
+    static constexpr int kWaves = 4;   // launch bound: waves per SIMD (128 registers)
     using Lds = WalkLds<5>;
     struct Acc {
         PairAcc<double> a;
@@ -503,6 +504,7 @@ struct AdjointPolicy {
     static constexpr bool kOpenAll = false;
     static constexpr bool kImageMac = false;
     static constexpr bool kGroupSum = false;
+    static constexpr int kWaves = 4;   // launch bound: waves per SIMD (128 registers)
     using Lds = WalkLds<9>;
     struct Acc {
         double vx, vy, vz, s;
@@ -747,6 +749,7 @@ struct EwaldPolicy {
     static constexpr bool kOpenAll = false;
     static constexpr bool kImageMac = true;
     static constexpr bool kGroupSum = true;
+    static constexpr int kWaves = 4;   // launch bound: waves per SIMD (128 registers)
     using Lds = WalkLds<8>;
     struct Acc {
         // g 3, T 6, (group sums only) H 10; FP32 sums of at most a few
@@ -959,22 +962,21 @@ struct EwaldPolicy {
 // ---- k-th neighbour distance: the length fully adaptive softening follows ----
 // Every node is opened; a node whose box lies farther from the group's box
 // than the group's pruning radius is skipped.  Each target keeps its k
-// smallest squared distances so far as an ascending list in LDS; a candidate
-// below the list's last entry goes to a small per-target buffer, and when
-// any buffer of the wave is full (and after every tile) each target sorts
-// its buffer and merges it into its list, keeping the k smallest.  Before
-// the walk the targets take the particles within k sorted positions of the
-// group, which fills every list; the pruning radius is then the largest of
-// the targets' k-th distances, and shrinks after every tile.  Distances are
-// d^2 = (dx^2 + dy^2) + dz^2 with d = x_j - x_i, each operation rounded once.
-// Entry i of target slot s sits at [i * 64 + s], so the lanes of a wave touch
-// consecutive words; the list capacity kCap (16, 32 or 64) is the smallest
-// that holds k, which keeps the LDS of a wave small.
+// smallest squared distances so far in registers, as an ascending list of
+// kCap entries (16, 32 or 64, the smallest that holds k) whose first kCap - k
+// are -inf, so the k-th sits at the fixed last place.  A candidate below it
+// goes to a small buffer in LDS; when any buffer of the wave is full (and
+// after every tile) the buffered values are inserted one by one with the
+// branch-free network L'[i] = max(L[i-1], min(L[i], v)), whose entries are
+// independent of one another (a value not below the last entry leaves the
+// list as it is).  Before the walk the targets take the particles within k
+// sorted positions of the group, which fills every list; the pruning radius
+// is then the largest of the targets' k-th distances, and shrinks after
+// every tile.  Distances are d^2 = (dx^2 + dy^2) + dz^2 with d = x_j - x_i,
+// each operation rounded once.
 constexpr int kKnnBuf = 8;
-template <int kCap>
 struct KnnLds : WalkLds<2> {
-    double lst[kW * kCap];
-    double buf[kW * kKnnBuf];
+    double buf[kW * kKnnBuf];   // entry b of lane l at [b * 64 + l]
     double r2;
     int win_lo, win_hi;   // sorted positions taken before the walk
 };
@@ -984,15 +986,14 @@ struct KnnPolicy {
     static constexpr bool kOpenAll = true;
     static constexpr bool kImageMac = false;
     static constexpr bool kGroupSum = false;
-    using Lds = KnnLds<kCap>;
+    // the list's registers: 2 kCap of them
+    static constexpr int kWaves = kCap <= 16 ? 4 : (kCap <= 32 ? 3 : 2);
+    using Lds = KnnLds;
     struct Acc {
         double x, y, z;   // the target
-        double kth;       // last entry of its list (+inf while not full)
+        double L[kCap];   // ascending; the last entry is the k-th so far
         int nb;           // buffered candidates
-        __device__ void zero() {
-            kth = __builtin_huge_val();
-            nb = 0;
-        }
+        __device__ void zero() { nb = 0; }
         __device__ void add(const Acc&) {}
     };
     // hipcc contracts a * b + c into one fma by default: not here
@@ -1000,58 +1001,31 @@ struct KnnPolicy {
 #pragma clang fp contract(off)
         return (dx * dx + dy * dy) + dz * dz;
     }
-    __device__ static void offer(Lds& S, Acc& A, int slot, double d2) {
-        if (d2 < A.kth) {
-            S.buf[A.nb * kW + slot] = d2;
+    __device__ static void insert(Acc& A, double v) {
+#pragma unroll
+        for (int i = kCap - 1; i > 0; --i) A.L[i] = fmax(A.L[i - 1], fmin(A.L[i], v));
+        A.L[0] = fmin(A.L[0], v);
+    }
+    __device__ static void offer(Lds& S, Acc& A, double d2) {
+        if (d2 < A.L[kCap - 1]) {
+            S.buf[A.nb * kW + threadIdx.x] = d2;
             ++A.nb;
         }
     }
-    // list <- the k smallest of list and buffer (both ascending)
-    __device__ static void merge(Lds& S, Acc& A, int slot, int k) {
-        double* B = S.buf + slot;
-        double* L = S.lst + slot;
-        const int nb = A.nb;
-        for (int i = 1; i < nb; ++i) {   // insertion sort of the buffer
-            const double x = B[i * kW];
-            int j = i;
-            while (j > 0) {
-                const double y = B[(j - 1) * kW];
-                if (!(y > x)) break;
-                B[j * kW] = y;
-                --j;
-            }
-            B[j * kW] = x;
-        }
-        // c buffered entries enter; the list's top c leave
-        int c = 0;
-        while (c < nb && c < k && B[c * kW] < L[(k - 1 - c) * kW]) ++c;
-        int w = k - 1, a = k - 1 - c, b = c - 1;
-        while (b >= 0) {               // backward merge in place (w >= a)
-            const double bv = B[b * kW];
-            if (a >= 0) {
-                const double av = L[a * kW];
-                if (av > bv) {
-                    L[w * kW] = av;
-                    --w;
-                    --a;
-                    continue;
-                }
-            }
-            L[w * kW] = bv;
-            --w;
-            --b;
-        }
-        A.kth = L[(k - 1) * kW];
+    // every lane inserts its buffered values (called by the whole wave)
+    __device__ static void merge(Lds& S, Acc& A) {
+        const int nbmax = ag_wave_max(A.nb);
+        for (int b = 0; b < nbmax; ++b)
+            insert(A, b < A.nb ? S.buf[b * kW + threadIdx.x] : __builtin_huge_val());
         A.nb = 0;
     }
-    // merge every buffer once any of them is full
-    __device__ static void check_full(Lds& S, Acc& A, bool owner, int slot, int k) {
-        if (__ballot(A.nb == kKnnBuf) != 0 && owner && A.nb > 0) merge(S, A, slot, k);
+    __device__ static void check_full(Lds& S, Acc& A) {
+        if (__ballot(A.nb == kKnnBuf) != 0) merge(S, A);
     }
     // merge every buffer; radius^2 no target's k-th neighbour lies beyond
-    __device__ static void flush(Lds& S, Acc& A, bool owner, int slot, int k) {
-        if (owner && A.nb > 0) merge(S, A, slot, k);
-        const double r2 = ag_wave_max(owner ? A.kth : 0.0);
+    __device__ static void flush(Lds& S, Acc& A, bool owner) {
+        merge(S, A);
+        const double r2 = ag_wave_max(owner ? A.L[kCap - 1] : 0.0);
         if (threadIdx.x == 0) S.r2 = r2;
     }
     // Both boxes are rounded outward, their gaps are exact in FP64, and the
@@ -1065,15 +1039,15 @@ struct KnnPolicy {
         return gx * gx + gy * gy + gz * gz > S.r2 * (1.0 + 1e-12);
     }
     __device__ static void start(Lds& S, const Tree& T, const WalkOut& O, int4 gd, const Target& t, Acc& A,
-                                 int part, int slot, int count) {
+                                 int part, int, int count) {
         const bool owner = part == 0;
         const double4 xi = T.spos[t.p];
         A.x = xi.x;
         A.y = xi.y;
         A.z = xi.z;
         const int k = O.knn_k;
-        if (owner)
-            for (int i = 0; i < k; ++i) S.lst[i * kW + slot] = __builtin_huge_val();
+#pragma unroll
+        for (int i = 0; i < kCap; ++i) A.L[i] = i < kCap - k ? -__builtin_huge_val() : __builtin_huge_val();
         const int64_t lo = gd.x - k > 0 ? gd.x - k : 0;
         const int64_t hi = gd.x + count + k < O.knn_n ? gd.x + count + k : O.knn_n;
         if (threadIdx.x == 0) {
@@ -1090,12 +1064,11 @@ struct KnnPolicy {
             }
             __syncthreads();
             for (int q = 0; q < cw; ++q) {
-                if (owner && S.tidx[q] != t.p)
-                    offer(S, A, slot, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z));
-                check_full(S, A, owner, slot, k);
+                if (owner && S.tidx[q] != t.p) offer(S, A, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z));
+                check_full(S, A);
             }
         }
-        flush(S, A, owner, slot, k);
+        flush(S, A, owner);
         __syncthreads();
     }
     template <int kPer>
@@ -1107,23 +1080,21 @@ struct KnnPolicy {
     __device__ static void stage_node(Lds&, const Tree&, const GroupBox&, int, int, const WalkOut&) {}
     template <int kPer, bool kSoft>
     __device__ static void particles(Lds& S, int cnt, const Target& t, Acc& A, float, float, int k0, int,
-                                     const WalkOut& O) {
-        const int k = O.knn_k;
+                                     const WalkOut&) {
         const bool owner = k0 == 0;   // the target's first lane keeps its list
-        const int slot = threadIdx.x;
         const double4* P = reinterpret_cast<const double4*>(S.tile);
         for (int q = 0; q < cnt; ++q) {
             const int pk = S.tidx[q];
             if (owner && pk != t.p && (pk < S.win_lo || pk >= S.win_hi))
-                offer(S, A, slot, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z));
-            check_full(S, A, owner, slot, k);
+                offer(S, A, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z));
+            check_full(S, A);
         }
-        flush(S, A, owner, slot, k);
+        flush(S, A, owner);
     }
     __device__ static void nodes(const Lds&, int, const Target&, Acc&, int, int, const WalkOut&) {}
     static __device__ void wave_sum(Acc&) {}
     __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
-        O.knn_out[T.perm[p]] = sqrt(A.kth);
+        O.knn_out[T.perm[p]] = sqrt(A.L[kCap - 1]);
     }
 };
 
@@ -1329,6 +1300,8 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     if (Pol::kGroupSum && tg.grp) {
         // every lane summed its own share of the entries: add all 64
         Pol::wave_sum(acc);
+    } else if constexpr (Pol::kOpenAll) {
+        // (the neighbour walk's parts other than the first keep nothing)
     } else if (sub > 1) {
         // sum the parts of every target in LDS (the walk lists are free now)
         static_assert(sizeof(typename Pol::Lds) >= sizeof(typename Pol::Acc) * kW, "LDS too small");
@@ -1357,7 +1330,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
 // to 128 VGPRs (four waves per SIMD); the few values this spills live
 // outside the interaction loops.
 template <class Pol, int kPer, bool kSoft = false>
-__global__ void __launch_bounds__(kW, 4) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
+__global__ void __launch_bounds__(kW, Pol::kWaves) k_walk(Tree T, Groups Gr, WalkOut O, int* __restrict__ qctr,
                                              float theta2, float eps2, float h2, float hinv) {
     __shared__ typename Pol::Lds S;
     __shared__ int s_g;
