@@ -550,6 +550,22 @@ def run_relative(args):
             c.set_option(ag.AG_OPT_MAC_OFFSET, args.mac_offset)
             if al > 0:
                 c.set_relative_opening(al, a_old)
+            # targets per walk group by the autotuner (untimed): the relative
+            # test opens more near groups of small |a_old|, where smaller
+            # groups share the work over more waves
+            c.tree_build(tx, tv, tm, args.n_leaf)
+
+            def trial(p):
+                c.set_option(ag.AG_OPT_GROUP_TARGETS, p["group_targets"])
+                c.timing_enable(True)
+                c.timing_read(reset=True)
+                c.grav_eval(None, th, args.eps, 1.0, acc, jerk, tid)
+                ph = c.timing_read(reset=True)
+                c.timing_enable(False)
+                return ph["groups"]["ms"] + ph["walk"]["ms"]
+
+            tuned, _ = autotune.tune(trial, autotune.grid(group_targets=[64, 32, 16]), "relative", use_cache=False)
+            c.set_option(ag.AG_OPT_GROUP_TARGETS, tuned["group_targets"])
 
             def step():
                 c.tree_build(tx, tv, tm, args.n_leaf)
@@ -579,6 +595,7 @@ def run_relative(args):
         e = _rel(acc.cpu().numpy()[rows], ar)
         key = f"{kind} theta={th}" + (f" alpha={al}" if al > 0 else "")
         out["runs"][key] = {"ms_per_step": ms, "evals_per_s": n / (ms * 1e-3), "walk_ms": walk_ms,
+                            "group_targets": tuned["group_targets"],
                             "walk_tflops": flops / (walk_ms * 1e-3) / 1e12,
                             "per_target": {"pp": st["n_pp"] / reps / n, "pn": st["n_pn"] / reps / n},
                             "median_rel_force_err": float(np.median(e)),
