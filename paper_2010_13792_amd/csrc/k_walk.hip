@@ -741,7 +741,8 @@ __device__ __forceinline__ bool ewald_accept(const GroupBox& g, const double4 c,
 // its share, and each target expands about the group centre:
 //   dg(c - t) = dg(c) + dT(c) t - 1/2 H(c) t t,   dT(c - t) = dT(c) - H(c) t;
 // a wider group evaluates the table at every target's own separation (the
-// expansion's error falls as (t / |c - n L|)^3 <= (2 t / L)^3).  The
+// expansion's relative error falls as (t / |c - n L|)^3 <= (2 t / L)^3, at
+// most 2.4e-4 of the correction for t <= L / 32).  The
 // sum includes the target itself (dg(0) = 0; dT(0) is the tide of the
 // background that neutralises its own images).
 struct EwaldPolicy {
@@ -1810,7 +1811,7 @@ static int walk_grid(ag_ctx* c, int64_t max_groups) {
 // Ewald table: spacing box / 64 over the octant [0, box / 2]^3 of the cell
 constexpr int kEwaldPerBox = 64;
 constexpr int kEwaldNE = 32;
-constexpr int kEwaldGroupDiv = 512;   // groups of half extent <= box / 512 sum once
+constexpr int kEwaldGroupDiv = 32;    // groups of half extent <= box / 32 sum once
 
 static int ewald_table(ag_ctx* c) {
     if (c->ewald_tab_box == c->box && c->ewald_tab.bytes) return AG_OK;
