@@ -69,14 +69,22 @@ def test_coincident_and_small(ag, orc):
     z = rng.normal(size=(2, 3))
     h = _lengths(ag, z, 1)
     assert h[0] == h[1] == orc.neighbour_length(z, 1)[0]
+    w = np.tile(rng.normal(size=(1, 3)), (100, 1))        # all coincident
+    assert np.all(_lengths(ag, w, 40) == 0.0)
 
 
-def test_full_size_sampled(ag, orc):
-    n = 1 << 20
-    x, _, _ = workloads.turbulent_sphere(n, seed=2)
-    h = _lengths(ag, x, 32)
-    rows = np.random.default_rng(14).choice(n, 512, replace=False)
-    np.testing.assert_array_equal(h[rows], orc.neighbour_length(x, 32, targets=rows, chunk=32))
+@pytest.fixture(scope="module")
+def sphere_2p20():
+    return workloads.turbulent_sphere(1 << 20, seed=2)[0]
+
+
+@pytest.mark.parametrize("k", [16, 32, 64])
+def test_full_size_sampled(ag, orc, sphere_2p20, k):
+    x = sphere_2p20
+    n = len(x)
+    h = _lengths(ag, x, k)
+    rows = np.random.default_rng(14 + k).choice(n, 256, replace=False)
+    np.testing.assert_array_equal(h[rows], orc.neighbour_length(x, k, targets=rows, chunk=32))
     assert np.all(np.isfinite(h)) and np.all(h > 0)
 
 
