@@ -164,6 +164,29 @@ def test_walk_theta0_is_direct_sum(ctx, orc, n):
     assert st["n_pp"] > 0
 
 
+@pytest.mark.parametrize("n_leaf", [1, 16, 64])
+def test_walk_theta0_every_target_ragged(ctx, orc, n_leaf):
+    """theta = 0 at ragged sizes (one target, partial tiles and groups, a
+    few tiles): every target's g against the direct sum, measured against the
+    cancellation-free size G sum_j m_j |f d|.  The walk holds coordinates in
+    FP32 relative to the group centre, off by up to 2^-24 of the system size
+    R, so a pair at the softening length carries up to ~2^-24 2R / eps
+    relative error (5e-4 here, R <= 10, eps = 0.01; measured worst 5.3e-6);
+    a missing or repeated pair moves a target by ~1/n of its scale or more,
+    so the bound is 1e-4."""
+    for n in (1, 2, 3, 63, 64, 65, 127, 1000, 4097):
+        x, v, m = workloads.plummer(n, seed=100 + n)
+        eps = 0.01
+        a, j, t = _eval(ctx, x, v, m, 0.0, eps, n_leaf=n_leaf)
+        ar, jr, tr = orc.direct(x, v, m, eps, 1.0)
+        if n == 1:
+            assert np.all(a == 0.0) and np.all(t == 0.0)
+            continue
+        sa = orc.abs_scale(x, m, eps, 1.0)
+        e = np.linalg.norm(a - ar, axis=1) / sa
+        assert e.max() <= 1e-4, (n, n_leaf, float(e.max()))
+
+
 @pytest.mark.parametrize("theta", [0.5, 0.7])
 def test_walk_accuracy_turbulent_sphere(ctx, orc, theta):
     """Uniform sphere with k^-4 velocities, N = 2^16, eps = 1e-3, on 4096
