@@ -178,20 +178,27 @@ def direct_soft(x, v, m, h, G, targets=None):
     return acc, jerk, tid
 
 
-def neighbour_length(x, k, targets=None, chunk=256):
+def neighbour_length(x, k, targets=None, chunk=256, box=0.0):
     """Distance from each target particle to its k-th nearest other particle
     (the length fully adaptive softening scales with), by brute force in
     FP64: d^2 = (dx^2 + dy^2) + dz^2 with d = x_j - x_i, then the k-th
-    smallest over j != i, then its square root."""
+    smallest over j != i, then its square root.  box > 0: every difference
+    at its nearest image, d - box rint(d / box), each operation rounded
+    once (ties at half a box to the even multiple)."""
     x = _f64(x, (-1, 3))
     n = x.shape[0]
     tgt = np.arange(n, dtype=np.int64) if targets is None else np.asarray(targets, dtype=np.int64)
     out = np.empty(tgt.size)
+    L = float(box)
     for a in range(0, tgt.size, chunk):
         t = tgt[a:a + chunk]
         dx = x[None, :, 0] - x[t, 0][:, None]
         dy = x[None, :, 1] - x[t, 1][:, None]
         dz = x[None, :, 2] - x[t, 2][:, None]
+        if L > 0.0:
+            dx = dx - L * np.rint(dx / L)
+            dy = dy - L * np.rint(dy / L)
+            dz = dz - L * np.rint(dz / L)
         d2 = dx * dx + dy * dy + dz * dz
         d2[np.arange(t.size), t] = np.inf        # not itself
         out[a:a + chunk] = np.sqrt(np.partition(d2, k - 1, axis=1)[:, k - 1])

@@ -78,6 +78,33 @@ def test_neighbour_length_brute_force(orc):
     np.testing.assert_allclose(orc.neighbour_length(x, 32), ref, rtol=1e-14)
 
 
+def test_neighbour_length_periodic(orc):
+    """Nearest images: scipy's periodic k-d tree on clumps wrapped into the
+    unit cube (some clumps cut by the faces), a plain loop over explicit
+    images on a small set, and a lattice filling the box, where every point,
+    the corner ones included, has its 6 neighbours at the spacing."""
+    from scipy.spatial import cKDTree
+    x, _, _, _ = workloads.clumps(4000, seed=12)
+    x = np.mod(x, 1.0)
+    ref = cKDTree(x, boxsize=1.0).query(x, k=17)[0][:, 16]
+    np.testing.assert_allclose(orc.neighbour_length(x, 16, box=1.0), ref, rtol=1e-13)
+    rng = np.random.default_rng(13)
+    y = rng.uniform(0, 2.0, (30, 3))
+    shifts = np.array([[a, b, c] for a in (-2, 0, 2) for b in (-2, 0, 2) for c in (-2, 0, 2)], float)
+    for k in (1, 4):
+        got = orc.neighbour_length(y, k, box=2.0)
+        for i in range(30):
+            d = sorted(min(float(np.linalg.norm(y[j] + s - y[i])) for s in shifts) for j in range(30) if j != i)
+            assert abs(got[i] - d[k - 1]) <= 1e-14 * d[k - 1]
+    a = 0.25
+    g = np.arange(4) * a
+    lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    assert np.all(orc.neighbour_length(lat, 6, box=1.0) == a)
+    assert np.all(orc.neighbour_length(lat, 7, box=1.0) == pytest.approx(a * np.sqrt(2), rel=1e-15))
+    # without the box the corner points see only 3 neighbours at the spacing
+    assert orc.neighbour_length(lat, 6)[0] > a
+
+
 def test_neighbour_length_lattice(orc):
     """On a cubic lattice of spacing a the 1st..6th neighbours sit at a,
     the 7th..18th at a sqrt(2) (interior points)."""
