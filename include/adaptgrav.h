@@ -154,11 +154,13 @@ int ag_set_relative_opening(ag_ctx *ctx, double alpha, int64_t n, const double *
  * the k-th nearest other particle).  h (n,) device FP64, written in input
  * order: h_i = sqrt(d2_k) with d2_k the k-th smallest of
  * d2_ij = (dx^2 + dy^2) + dz^2 over j != i, d = x_j - x_i, each operation
- * rounded once in FP64, so the result is exact up to that rounding.  The
- * output can go straight to ag_set_softening (scaled first, if wanted).
- * Needs a tree from ag_tree_build on an open (non-periodic) context;
- * batched or periodic trees give AG_ESTATE.  k must be in [1, 64] and below
- * n (AG_EINVAL).  Coincident particles give h = 0. */
+ * rounded once in FP64, so the result is exact up to that rounding.  A tree
+ * built in a periodic box (ag_set_periodic before the build) takes every
+ * difference at its nearest image, d - box rint(d / box), from the
+ * positions as the tree holds them (wrapped into [0, box)).  The output can
+ * go straight to ag_set_softening (scaled first, if wanted).  Needs a tree
+ * from ag_tree_build; a batched tree gives AG_ESTATE.  k must be in [1, 64]
+ * and below n (AG_EINVAL).  Coincident particles give h = 0. */
 int ag_neighbour_lengths(ag_ctx *ctx, int32_t k, double *h);
 
 /* Periodic boundaries (Sec. 4: the periodic problem's gravity uses Ewald

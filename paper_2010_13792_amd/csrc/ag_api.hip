@@ -609,7 +609,6 @@ extern "C" int ag_neighbour_lengths(ag_ctx* c, int32_t k, double* h) {
     AG_TRY(check_ctx(c));
     if (!c->built) return ag_fail(AG_ESTATE, "neighbour lengths before a tree build");
     if (c->batched) return ag_fail(AG_ESTATE, "neighbour lengths are not available for a batched tree");
-    if (c->tree_box > 0.0) return ag_fail(AG_ESTATE, "neighbour lengths are not available for a periodic tree");
     if (k < 1 || k > 64) return ag_fail(AG_EINVAL, "k must be in [1, 64]");
     if ((int64_t)k >= c->n) return ag_fail(AG_EINVAL, "k must be below the number of particles");
     if (!h) return ag_fail(AG_EINVAL, "h must be non-null");

@@ -997,9 +997,19 @@ struct KnnPolicy {
         __device__ void zero() { nb = 0; }
         __device__ void add(const Acc&) {}
     };
-    // hipcc contracts a * b + c into one fma by default: not here
-    __device__ static double dist2(double dx, double dy, double dz) {
+    // hipcc contracts a * b + c into one fma by default: not here.  In a
+    // periodic tree every difference goes to its nearest image first,
+    // d - L rint(d / L) (the division correctly rounded).
+    template <int kPer>
+    __device__ static double dist2(const double4& p, const Acc& A, const WalkOut& O) {
 #pragma clang fp contract(off)
+        double dx = p.x - A.x, dy = p.y - A.y, dz = p.z - A.z;
+        if (kPer) {
+            const double L = O.box;
+            dx = dx - L * rint(dx / L);
+            dy = dy - L * rint(dy / L);
+            dz = dz - L * rint(dz / L);
+        }
         return (dx * dx + dy * dy) + dz * dz;
     }
     __device__ static void insert(Acc& A, double v) {
@@ -1032,13 +1042,25 @@ struct KnnPolicy {
     // Both boxes are rounded outward, their gaps are exact in FP64, and the
     // relative margin covers the rounding of the squares: a skipped node
     // holds no particle at a computed d^2 <= r2.
-    __device__ static bool skip_node(const Lds& S, const Tree& T, const GroupBox& g, int a) {
+    // Periodic: per axis the gap between two arcs of a circle of length L,
+    // the centres' distance taken the short way round less both half widths
+    // (every node lies inside the box, so no arc crosses the cut).
+    template <int kPer>
+    __device__ static double axis_gap(float lo, float hi, float glo, float ghi, const WalkOut& O) {
+        if (!kPer) return fmax(fmax((double)lo - ghi, (double)glo - hi), 0.0);
+        double c = fabs(0.5 * ((double)lo + hi) - 0.5 * ((double)glo + ghi));
+        c = fmin(c, O.box - c);
+        return fmax(c - 0.5 * (((double)hi - lo) + ((double)ghi - glo)), 0.0);
+    }
+    template <int kPer>
+    __device__ static bool skip_node(const Lds& S, const Tree& T, const GroupBox& g, int a, const WalkOut& O) {
         const float4 lo = T.lo[a], hi = T.hi[a];
-        const double gx = fmax(fmax((double)lo.x - g.hix, (double)g.lox - hi.x), 0.0);
-        const double gy = fmax(fmax((double)lo.y - g.hiy, (double)g.loy - hi.y), 0.0);
-        const double gz = fmax(fmax((double)lo.z - g.hiz, (double)g.loz - hi.z), 0.0);
+        const double gx = axis_gap<kPer>(lo.x, hi.x, g.lox, g.hix, O);
+        const double gy = axis_gap<kPer>(lo.y, hi.y, g.loy, g.hiy, O);
+        const double gz = axis_gap<kPer>(lo.z, hi.z, g.loz, g.hiz, O);
         return gx * gx + gy * gy + gz * gz > S.r2 * (1.0 + 1e-12);
     }
+    template <int kPer>
     __device__ static void start(Lds& S, const Tree& T, const WalkOut& O, int4 gd, const Target& t, Acc& A,
                                  int part, int, int count) {
         const bool owner = part == 0;
@@ -1065,7 +1087,7 @@ struct KnnPolicy {
             }
             __syncthreads();
             for (int q = 0; q < cw; ++q) {
-                if (owner && S.tidx[q] != t.p) offer(S, A, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z));
+                if (owner && S.tidx[q] != t.p) offer(S, A, dist2<kPer>(P[q], A, O));
                 check_full(S, A);
             }
         }
@@ -1081,13 +1103,13 @@ struct KnnPolicy {
     __device__ static void stage_node(Lds&, const Tree&, const GroupBox&, int, int, const WalkOut&) {}
     template <int kPer, bool kSoft>
     __device__ static void particles(Lds& S, int cnt, const Target& t, Acc& A, float, float, int k0, int,
-                                     const WalkOut&) {
+                                     const WalkOut& O) {
         const bool owner = k0 == 0;   // the target's first lane keeps its list
         const double4* P = reinterpret_cast<const double4*>(S.tile);
         for (int q = 0; q < cnt; ++q) {
             const int pk = S.tidx[q];
             if (owner && pk != t.p && (pk < S.win_lo || pk >= S.win_hi))
-                offer(S, A, dist2(P[q].x - A.x, P[q].y - A.y, P[q].z - A.z));
+                offer(S, A, dist2<kPer>(P[q], A, O));
             check_full(S, A);
         }
         flush(S, A, owner);
@@ -1099,9 +1121,10 @@ struct KnnPolicy {
     }
 };
 
-template <class P>
-__device__ __forceinline__ bool policy_skips(const typename P::Lds& S, const Tree& T, const GroupBox& g, int a) {
-    if constexpr (P::kOpenAll) return P::skip_node(S, T, g, a);
+template <class P, int kPer>
+__device__ __forceinline__ bool policy_skips(const typename P::Lds& S, const Tree& T, const GroupBox& g, int a,
+                                             const WalkOut& O) {
+    if constexpr (P::kOpenAll) return P::template skip_node<kPer>(S, T, g, a, O);
     else if constexpr (P::kSkipEmpty) return T.wf[8 * a].w == 0.f;
     else return false;
 }
@@ -1153,7 +1176,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
     gb.amin = O.rel_a ? ag_wave_min(O.rel_a[T.perm[p_i]]) : 0.f;
     typename Pol::Acc acc;
     acc.zero();
-    if constexpr (Pol::kOpenAll) Pol::start(S, T, O, gd, tg, acc, part, slot, count);
+    if constexpr (Pol::kOpenAll) Pol::template start<kPer>(S, T, O, gd, tg, acc, part, slot, count);
 
     uint64_t n_pp = 0, n_pn = 0;
 
@@ -1219,7 +1242,7 @@ __device__ __forceinline__ void walk_group(typename Pol::Lds& S, const Tree& T, 
             const int a = ca;
             const int4 L = T.link[a];
             const bool leaf = (L.w & 0x100) != 0;
-            if (policy_skips<Pol>(S, T, gb, a)) {
+            if (policy_skips<Pol, kPer>(S, T, gb, a, O)) {
                 ca = L.x;                  // nothing below this node matters
             } else {
                 const bool acc_ok =
@@ -1858,18 +1881,23 @@ int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out) {
     O.knn_out = h_out;
     O.knn_k = k;
     O.knn_n = c->n;
+    O.box = c->tree_box;   // nearest images in the box the tree was built in
     PhaseScope phase(c, AG_PHASE_NEIGHBOUR);
     const unsigned grid = (unsigned)walk_grid(c, mg);
     int32_t* qctr = c->grp_hdr.as<int32_t>() + 8;
-    if (k <= 16)
-        hipLaunchKernelGGL((k_walk<KnnPolicy<16>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
-                           qctr, 0.f, 0.f, 0.f, 0.f);
-    else if (k <= 32)
-        hipLaunchKernelGGL((k_walk<KnnPolicy<32>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
-                           qctr, 0.f, 0.f, 0.f, 0.f);
-    else
-        hipLaunchKernelGGL((k_walk<KnnPolicy<64>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
-                           qctr, 0.f, 0.f, 0.f, 0.f);
+    const Tree T = make_tree(c);
+    hipStream_t st = c->stream;
+#define AG_KNN(CAP, PER) \
+    hipLaunchKernelGGL((k_walk<KnnPolicy<CAP>, PER>), dim3(grid), dim3(kW), 0, st, T, Gr, O, qctr, 0.f, 0.f, 0.f, 0.f)
+    const bool per = c->tree_box > 0.0;
+    if (k <= 16) {
+        if (per) AG_KNN(16, kNear); else AG_KNN(16, kOpen);
+    } else if (k <= 32) {
+        if (per) AG_KNN(32, kNear); else AG_KNN(32, kOpen);
+    } else {
+        if (per) AG_KNN(64, kNear); else AG_KNN(64, kOpen);
+    }
+#undef AG_KNN
     return AG_OK;
 }
 

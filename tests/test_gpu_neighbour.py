@@ -18,11 +18,13 @@ def _t(a, dtype=None):
     return torch.tensor(a, device=DEV) if dtype is None else torch.tensor(a, dtype=dtype, device=DEV)
 
 
-def _lengths(ag, x, k, n_leaf=16):
+def _lengths(ag, x, k, n_leaf=16, box=0.0):
     n = x.shape[0]
     v = np.zeros((n, 3))
     m = np.full(n, 1.0 / n)
     with ag.Context(0) as c:
+        if box:
+            c.set_periodic(box)
         c.tree_build(_t(x), _t(v), _t(m), n_leaf)
         h = c.neighbour_lengths(k)
         c.sync()
@@ -88,6 +90,33 @@ def test_full_size_sampled(ag, orc, sphere_2p20, k):
     assert np.all(np.isfinite(h)) and np.all(h > 0)
 
 
+# ---- periodic trees: nearest images ------------------------------------------
+@pytest.mark.parametrize("k", [1, 16, 32, 64])
+def test_periodic_clumps_exact(ag, orc, k):
+    x, _, _, _ = workloads.clumps(6001, seed=21)
+    x = np.mod(x, 1.0)            # clumps cut by the faces
+    h = _lengths(ag, x, k, box=1.0)
+    np.testing.assert_array_equal(h, orc.neighbour_length(x, k, box=1.0))
+
+
+def test_periodic_uniform_and_box_size(ag, orc):
+    rng = np.random.default_rng(22)
+    for L in (1.0, 2.5):
+        x = rng.uniform(0.0, L, (5003, 3))
+        for n_leaf in (1, 16):
+            np.testing.assert_array_equal(_lengths(ag, x, 24, n_leaf, box=L), orc.neighbour_length(x, 24, box=L))
+
+
+def test_periodic_lattice(ag, orc):
+    a = 1.0 / 8                    # exact, so every difference is
+    g = np.arange(8) * a
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    for k in (6, 18, 26):
+        h = _lengths(ag, x, k, box=1.0)
+        np.testing.assert_array_equal(h, orc.neighbour_length(x, k, box=1.0))
+    assert np.all(_lengths(ag, x, 6, box=1.0) == a)   # the corners too
+
+
 def test_arguments(ag):
     x, v, m, _ = workloads.clumps(2048, seed=4)
     with ag.Context(0) as c:
@@ -99,11 +128,6 @@ def test_arguments(ag):
             with pytest.raises(ag.AgError) as e:
                 c.neighbour_lengths(bad)
             assert e.value.code == ag.AG_EINVAL
-        c.set_periodic(4.0)
-        c.tree_build(_t(x), _t(v), _t(m), 16)
-        with pytest.raises(ag.AgError) as e:
-            c.neighbour_lengths(8)
-        assert e.value.code == ag.AG_ESTATE
         c.set_periodic(0.0)
         off = _t([0, 1000, 2048], torch.int64)
         c.tree_build_batched(_t(x), _t(v), _t(m), off, 16)
