@@ -116,7 +116,8 @@ enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
 /* Per-particle softening lengths (Sec. 4: the paper's runs soften each
- * element with its own, adaptive, length; here the lengths are given).
+ * element with its own, adaptive, length; here the lengths are given, for
+ * instance by ag_neighbour_lengths from the previous tree).
  * h (n,) device FP64 in input order, copied at once (the caller may reuse
  * it after the stream passes this call).  Every pair's kernel is then the
  * mean of its two particles' M4 kernels, f = (f(r, h_i) + f(r, h_j)) / 2 and
