@@ -90,6 +90,23 @@ def test_full_size_sampled(ag, orc, sphere_2p20, k):
     assert np.all(np.isfinite(h)) and np.all(h > 0)
 
 
+def test_independent_of_grouping(ag):
+    """The lengths do not depend on how the targets are grouped (one target
+    per wave up to 64, ragged group sizes in between)."""
+    x, _, _, _ = workloads.clumps(6001, seed=23)
+    n = len(x)
+    out = []
+    for gt in (64, 17, 5, 1):
+        with ag.Context(0) as c:
+            c.set_option(ag.AG_OPT_GROUP_TARGETS, gt)
+            c.tree_build(_t(x), _t(np.zeros((n, 3))), _t(np.full(n, 1.0 / n)), 16)
+            h = c.neighbour_lengths(20)
+            c.sync()
+        out.append(h.cpu().numpy())
+    for h in out[1:]:
+        np.testing.assert_array_equal(h, out[0])
+
+
 # ---- periodic trees: nearest images ------------------------------------------
 @pytest.mark.parametrize("k", [1, 16, 32, 64])
 def test_periodic_clumps_exact(ag, orc, k):
