@@ -988,7 +988,7 @@ struct KnnPolicy {
     static constexpr bool kImageMac = false;
     static constexpr bool kGroupSum = false;
     // the list's registers: 2 kCap of them
-    static constexpr int kWaves = kCap <= 16 ? 4 : (kCap <= 32 ? 3 : 2);
+    static constexpr int kWaves = kCap <= 16 ? 4 : (kCap <= 32 ? 3 : 1);
     using Lds = KnnLds;
     struct Acc {
         double x, y, z;   // the target
