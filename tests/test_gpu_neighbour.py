@@ -64,7 +64,8 @@ def test_coincident_and_small(ag, orc):
     base = rng.normal(size=(300, 3))
     x = np.concatenate([base, base[:100], base[:50]])   # up to triples
     for k in (1, 2, 3, 40):
-        np.testing.assert_array_equal(_lengths(ag, x, k), orc.neighbour_length(x, k))
+        for n_leaf in (1, 16):   # one per leaf: the copies share the deepest cells
+            np.testing.assert_array_equal(_lengths(ag, x, k, n_leaf), orc.neighbour_length(x, k))
     assert np.all(_lengths(ag, x, 2)[:50] == 0.0)
     y = rng.normal(size=(65, 3))                         # k = n - 1: the farthest
     np.testing.assert_array_equal(_lengths(ag, y, 64), orc.neighbour_length(y, 64))
