@@ -361,3 +361,111 @@ def moments(x, v, m, idx):
     _load().orc_moments(ii.size, _ptr(ii), _ptr(x), _ptr(v), _ptr(m), _ptr(out))
     return {"M": out[0], "com": out[1:4], "u": out[4:7], "Q": out[7:13], "Qdot": out[13:19],
             "lo": out[19:22], "hi": out[22:25]}
+
+
+# ---- Price & Monaghan terms of fully adaptive softening --------------------
+# With h_i tied to the kernel-weighted number density, h_i^3 n_i = 3 N/(4 pi),
+# n_i = sum_j W(r_ij, h_i) (self included), the potential energy
+#   E = (G/2) sum_i sum_{j != i} m_i m_j phi(r_ij, h_i)
+# depends on the positions through the h_i too; -(1/m_i) dE/dx_i is the
+# mean-kernel force plus the correction computed here (numpy, O(n^2), for
+# small sets).  phi(r, h) = psi(r/h) / h is the potential of a unit mass
+# spread by the cubic spline of support h, so that phi'(r)/r is the force
+# kernel f of `kernel` (G = 1).
+
+def m4_shape(u):
+    """w(u), w'(u) of the cubic spline with support 1: W(r, h) = 8/(pi h^3) w(r/h)."""
+    u = np.asarray(u, dtype=np.float64)
+    w = np.where(u < 0.5, 1.0 - 6.0 * u**2 + 6.0 * u**3, np.where(u < 1.0, 2.0 * (1.0 - u)**3, 0.0))
+    wp = np.where(u < 0.5, -12.0 * u + 18.0 * u**2, np.where(u < 1.0, -6.0 * (1.0 - u)**2, 0.0))
+    return w, wp
+
+
+def soft_potential(u):
+    """psi(u): -1/u beyond the support; inside it the integral of u F(u)
+    (F = h^3 f) from 1, added to psi(1) = -1, in closed form."""
+    u = np.asarray(u, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        inner = 16.0 / 3 * u**2 - 48.0 / 5 * u**4 + 32.0 / 5 * u**5 - 14.0 / 5
+        outer = 32.0 / 3 * u**2 - 16.0 * u**3 + 48.0 / 5 * u**4 - 32.0 / 15 * u**5 + 1.0 / (15.0 * u) - 16.0 / 5
+        far = -1.0 / u
+    return np.where(u < 0.5, inner, np.where(u < 1.0, outer, far))
+
+
+def pm_lengths(x, n_ngb, iters=200):
+    """h_i with sum_j w(r_ij / h_i) = 3 n_ngb / 32 (self included), that is
+    h^3 n = 3 n_ngb / (4 pi); bisection in FP64 (the sum grows with h)."""
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    target = 3.0 * n_ngb / 32.0
+    if not (1.0 < target < n):
+        raise ValueError("need 32/3 < n_ngb < 32 n / 3")
+    h = np.empty(n)
+    for i in range(n):
+        r = np.sqrt(np.sum((x - x[i])**2, axis=1))
+        lo, hi = 0.0, 2.0 * r.max() + 1e-300
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            if m4_shape(r / mid)[0].sum() < target:
+                lo = mid
+            else:
+                hi = mid
+            if hi - lo <= 1e-16 * hi:
+                break
+        h[i] = 0.5 * (lo + hi)
+    return h
+
+
+def pm_terms(x, m, h, n_ngb, G):
+    """Per particle: Omega_i = 1 + (h/(3n)) dn/dh = -(32/(9 N)) sum_j u w'(u),
+    and Z_i = (G/2) m_i h_i / (3 n_i Omega_i) sum_{j != i} m_j dphi/dh(r_ij, h_i),
+    with dphi/dh = -(psi(u) + u^2 F(u)) / h^2."""
+    x, m, h = _f64(x, (-1, 3)), _f64(m).ravel(), _f64(h).ravel()
+    n = x.shape[0]
+    C = 3.0 * n_ngb / (4.0 * np.pi)
+    omega, Z = np.empty(n), np.empty(n)
+    for i in range(n):
+        r = np.sqrt(np.sum((x - x[i])**2, axis=1))
+        u = r / h[i]
+        _, wp = m4_shape(u)
+        omega[i] = -(32.0 / (9.0 * n_ngb)) * np.sum(u * wp)
+        f, _, _ = kernel(r, h[i])
+        F = f * h[i]**3
+        dphidh = -(soft_potential(u) + u * u * F) / h[i]**2
+        mm = m.copy()
+        mm[i] = 0.0
+        ni = C / h[i]**3
+        Z[i] = 0.5 * G * m[i] * h[i] / (3.0 * ni * omega[i]) * np.sum(mm * dphidh)
+    return omega, Z
+
+
+def pm_correction(x, m, h, n_ngb, G):
+    """The extra acceleration (n, 3): -(1/m_i) sum_{j != i} [Z_i W'(r, h_i)
+    + Z_j W'(r, h_j)] d / r with d = x_j - x_i and W' = dW/dr."""
+    x, m, h = _f64(x, (-1, 3)), _f64(m).ravel(), _f64(h).ravel()
+    _, Z = pm_terms(x, m, h, n_ngb, G)
+    n = x.shape[0]
+    a = np.zeros((n, 3))
+    for i in range(n):
+        d = x - x[i]
+        r = np.sqrt(np.sum(d * d, axis=1))
+        r[i] = 1.0
+        wpi = m4_shape(r / h[i])[1] * 8.0 / (np.pi * h[i]**4)
+        wpj = m4_shape(r / h)[1] * 8.0 / (np.pi * h**4)
+        c = Z[i] * wpi + Z * wpj
+        c[i] = 0.0
+        a[i] = -np.sum((c / r)[:, None] * d, axis=0) / m[i]
+    return a
+
+
+def pm_energy(x, m, n_ngb, G):
+    """E = (G/2) sum_i sum_{j != i} m_i m_j phi(r_ij, h_i) with h solved at x."""
+    x, m = _f64(x, (-1, 3)), _f64(m).ravel()
+    h = pm_lengths(x, n_ngb)
+    E = 0.0
+    for i in range(x.shape[0]):
+        r = np.sqrt(np.sum((x - x[i])**2, axis=1))
+        phi = soft_potential(r / h[i]) / h[i]
+        phi[i] = 0.0
+        E += m[i] * np.sum(m * phi)
+    return 0.5 * G * E

@@ -114,3 +114,58 @@ def test_neighbour_length_lattice(orc):
     centre = [np.argmin(np.linalg.norm(x - 3 * a, axis=1))]
     for k, d in ((1, a), (6, a), (7, a * np.sqrt(2)), (18, a * np.sqrt(2)), (19, a * np.sqrt(3))):
         assert orc.neighbour_length(x, k, centre)[0] == pytest.approx(d, rel=1e-14)
+
+
+# ---- Price & Monaghan terms (oracle only) -------------------------------------
+def test_soft_potential_kernel(orc):
+    """psi against the force kernel it must integrate: psi(1) = -1, and
+    psi(u) = -1 - int_u^1 s F(s) ds with F = h^3 f from `kernel` (scipy's
+    quadrature); the known centre value -14/5; continuity at 1/2 and 1."""
+    from scipy.integrate import quad
+    F = lambda s: orc.kernel(np.array([s]), 1.0)[0][0]
+    for u in (0.05, 0.3, 0.49, 0.5, 0.7, 0.95, 1.0):
+        ref = -1.0 - quad(lambda s: s * F(s), u, 1.0, epsabs=1e-14, epsrel=1e-13, points=[0.5])[0]
+        assert orc.soft_potential(u) == pytest.approx(ref, rel=1e-11, abs=1e-12)
+    assert orc.soft_potential(0.0) == pytest.approx(-2.8, rel=1e-15)
+    for u in (0.5, 1.0):
+        assert orc.soft_potential(u - 1e-12) == pytest.approx(orc.soft_potential(u), abs=1e-10)
+    assert orc.soft_potential(3.0) == pytest.approx(-1.0 / 3.0, rel=1e-15)
+
+
+def test_pm_lengths(orc):
+    """Every h_i satisfies its density condition, and scaling the positions
+    scales the lengths."""
+    rng = np.random.default_rng(31)
+    x = rng.uniform(0, 1, (60, 3))
+    h = orc.pm_lengths(x, 20)
+    for i in range(60):
+        s = orc.m4_shape(np.linalg.norm(x - x[i], axis=1) / h[i])[0].sum()
+        assert s == pytest.approx(3 * 20 / 32, rel=1e-13)
+    np.testing.assert_allclose(orc.pm_lengths(2.5 * x, 20), 2.5 * h, rtol=1e-13)
+
+
+def test_pm_force_is_energy_gradient(orc):
+    """The mean-kernel force plus the correction is -(1/m_i) dE/dx_i, the
+    energy's gradient with every h re-solved (central differences, step
+    1e-6); the mean-kernel force alone is not (the set is sparse, so the
+    lengths and the correction are large), and the correction conserves
+    momentum."""
+    rng = np.random.default_rng(32)
+    n, N, G = 30, 16, 1.3
+    x = rng.uniform(0, 1, (n, 3))
+    m = rng.uniform(0.5, 1.5, n)
+    h = orc.pm_lengths(x, N)
+    a = orc.direct_soft(x, np.zeros_like(x), m, h, G)[0]
+    ac = orc.pm_correction(x, m, h, N, G)
+    step = 1e-6
+    fd = np.zeros((n, 3))
+    for i in range(n):
+        for c in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, c] += step
+            xm[i, c] -= step
+            fd[i, c] = -(orc.pm_energy(xp, m, N, G) - orc.pm_energy(xm, m, N, G)) / (2 * step) / m[i]
+    scale = np.linalg.norm(fd, axis=1)
+    assert np.max(np.abs(a + ac - fd).max(axis=1) / scale) <= 1e-6
+    assert np.max(np.abs(a - fd).max(axis=1) / scale) >= 1e-2
+    assert np.abs((m[:, None] * ac).sum(axis=0)).max() <= 1e-13 * np.abs(m[:, None] * ac).sum()
