@@ -406,12 +406,12 @@ def pm_lengths(x, n_ngb, iters=200):
         lo, hi = 0.0, 2.0 * r.max() + 1e-300
         for _ in range(iters):
             mid = 0.5 * (lo + hi)
+            if mid <= lo or mid >= hi:   # no double left between the ends
+                break
             if m4_shape(r / mid)[0].sum() < target:
                 lo = mid
             else:
                 hi = mid
-            if hi - lo <= 1e-16 * hi:
-                break
         h[i] = 0.5 * (lo + hi)
     return h
 
