@@ -164,6 +164,39 @@ int ag_set_relative_opening(ag_ctx *ctx, double alpha, int64_t n, const double *
  * and below n (AG_EINVAL).  Coincident particles give h = 0. */
 int ag_neighbour_lengths(ag_ctx *ctx, int32_t k, double *h);
 
+/* Fully adaptive softening with the conservative correction of Price &
+ * Monaghan (2007), the form of adaptive softening the paper's runs use
+ * (Sec. 4).  Kernel: the cubic spline of support h, W(r, h) = 8/(pi h^3)
+ * w(r/h), w = 1 - 6u^2 + 6u^3 (u < 1/2), 2(1 - u)^3 (u < 1); psi(u)/h is
+ * the potential of a unit mass spread by W (-1/r outside the support).
+ * Open boundaries and an unbatched tree only (AG_ESTATE otherwise);
+ * n_ngb > 32/3 and below 32 n/3 (AG_EINVAL).
+ *
+ * ag_pm_lengths: h_i with 1 + sum_{j != i} w(r_ij / h_i) = 3 n_ngb / 32
+ * (a number density of n_ngb particles per 4/3 pi h^3) and
+ * Omega_i = -(32 / (9 n_ngb)) sum_j u w'(u), u = r_ij / h_i.  The support
+ * must hold fewer than 64 other particles: where the 64 nearest do not
+ * reach the root, h and omega are NaN there and the call returns AG_EINVAL
+ * (lower n_ngb).  h, omega (n,) device FP64, input order; synchronises.
+ * Needs a tree from ag_tree_build (any softening). */
+int ag_pm_lengths(ag_ctx *ctx, double n_ngb, double *h, double *omega);
+
+/* ag_pm_factors: Z_i = (G/2) m_i h_i / (3 n_i Omega_i) sum_{j != i} m_j
+ * dphi/dh(r_ij, h_i), n_i = 3 n_ngb / (4 pi h_i^3), dphi/dh the derivative
+ * of psi(r/h)/h at fixed r.  The lengths are those given to
+ * ag_set_softening before the tree build (AG_ESTATE if the tree was built
+ * without them); omega from ag_pm_lengths.  omega, z (n,) device FP64,
+ * input order. */
+int ag_pm_factors(ag_ctx *ctx, double n_ngb, double G, const double *omega, double *z);
+
+/* ag_pm_correct: the correction's acceleration, written to acc (n, 3):
+ * a_i = -(1/m_i) sum_{j != i} [Z_i W'(r, h_i) + Z_j W'(r, h_j)] d / r,
+ * d = x_j - x_i, W' = dW/dr; added to the softened gravity of the same
+ * lengths it gives the acceleration that conserves the energy
+ * (G/2) sum_i sum_{j != i} m_i m_j psi(r_ij / h_i) / h_i.  Lengths as for
+ * ag_pm_factors; z (n,) from it; coincident pairs add nothing. */
+int ag_pm_correct(ag_ctx *ctx, const double *z, double *acc);
+
 /* Periodic boundaries (Sec. 4: the periodic problem's gravity uses Ewald
  * sums, its jerk only the nearest image).  box > 0 makes every later
  * ag_grav_eval, ag_grav_eval_batched and (ewald = 0 only) ag_grav_direct on

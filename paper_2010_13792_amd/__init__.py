@@ -38,7 +38,7 @@ ENTRY_POINTS = [
     "ag_grav_predict", "ag_grav_backward", "ag_timing_enable", "ag_timing_read",
     "ag_kick_drift", "ag_set_option", "ag_graph_begin", "ag_graph_end", "ag_graph_replay",
     "ag_force_log", "ag_grav_predict_poly", "ag_set_periodic", "ag_set_softening",
-    "ag_neighbour_lengths", "ag_set_relative_opening",
+    "ag_neighbour_lengths", "ag_set_relative_opening", "ag_pm_lengths", "ag_pm_factors", "ag_pm_correct",
 ]
 AG_PRED_MAX_DEPTH = 4
 AG_OPT_WALK_WAVES_PER_CU = 1
@@ -98,6 +98,9 @@ def load_library(path: str = LIB_PATH):
         "ag_set_periodic": [P, D, I32],
         "ag_set_softening": [P, I64, P],
         "ag_neighbour_lengths": [P, I32, P],
+        "ag_pm_lengths": [P, D, P, P],
+        "ag_pm_factors": [P, D, D, P, P],
+        "ag_pm_correct": [P, P, P],
         "ag_set_relative_opening": [P, D, I64, P],
         "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
@@ -335,6 +338,36 @@ class Context:
                 raise AgError(AG_ESTATE, "neighbour lengths before a tree build")
             out = torch.empty(n, dtype=torch.float64, device=torch.device("cuda", self.device))
         _check(_lib.ag_neighbour_lengths(self._h, int(k), _ptr(out, torch.float64, None, "out", n)))
+        return out
+
+    def _pm_out(self, out, shape, name):
+        n = self.n
+        if out is None:
+            if n is None:
+                raise AgError(AG_ESTATE, "Price & Monaghan terms before a tree build")
+            out = torch.empty((n,) + shape, dtype=torch.float64, device=torch.device("cuda", self.device))
+        return out, _ptr(out, torch.float64, shape or None, name, n)
+
+    def pm_lengths(self, n_ngb: float, h=None, omega=None):
+        """Price & Monaghan lengths h and Omega from the built tree (device
+        float64 (n,) each, input order); synchronises."""
+        h, ph = self._pm_out(h, (), "h")
+        omega, po = self._pm_out(omega, (), "omega")
+        _check(_lib.ag_pm_lengths(self._h, float(n_ngb), ph, po))
+        return h, omega
+
+    def pm_factors(self, n_ngb: float, G: float, omega, z=None):
+        """The correction's factors Z (n,), with the softening lengths the
+        tree was built with and Omega from pm_lengths."""
+        z, pz = self._pm_out(z, (), "z")
+        _check(_lib.ag_pm_factors(self._h, float(n_ngb), float(G),
+                                  _ptr(omega, torch.float64, None, "omega", self.n), pz))
+        return z
+
+    def pm_correct(self, z, out=None):
+        """The correction's acceleration (n, 3) from the factors Z."""
+        out, pa = self._pm_out(out, (3,), "out")
+        _check(_lib.ag_pm_correct(self._h, _ptr(z, torch.float64, None, "z", self.n), pa))
         return out
 
     def set_periodic(self, box: float, ewald: bool = False):

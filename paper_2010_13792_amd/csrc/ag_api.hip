@@ -189,7 +189,7 @@ extern "C" int ag_destroy(ag_ctx* c) {
                       &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
                       &c->nd_64, &c->nd_w, &c->nd_wf, &c->in_list, &c->in_cnt, &c->in_off,
                       &c->tree_hdr, &c->lvl_list, &c->leaf_list, &c->child, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
-                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->ewald_tab, &c->ewald_q, &c->soft_h, &c->soft_s, &c->rel_a, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
+                      &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->ewald_tab, &c->ewald_q, &c->soft_h, &c->soft_s, &c->rel_a, &c->pm_brk, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
                       &c->direct_part, &c->tmp_tidal, &c->sel_flag, &c->sel_off, &c->stats, &c->dflags};
     for (DevBuf* b : bufs) ag_release(*b);
     for (PhaseEvents& p : c->timing.pending) {
@@ -603,6 +603,54 @@ extern "C" int ag_grav_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, co
     DeviceGuard g(c->device);
     AG_TRY(ag_launch_backward(c, idx, n_act, w, theta, eps, G, dLdx, dLdm));
     return check_launch("grav backward");
+}
+
+static int check_pm(ag_ctx* c, double n_ngb, bool lengths) {
+    AG_TRY(check_ctx(c));
+    if (!c->built) return ag_fail(AG_ESTATE, "Price & Monaghan terms before a tree build");
+    if (c->batched) return ag_fail(AG_ESTATE, "Price & Monaghan terms are not available for a batched tree");
+    if (c->tree_box > 0.0) return ag_fail(AG_ESTATE, "Price & Monaghan terms need open boundaries");
+    if (!lengths && !c->tree_soft)
+        return ag_fail(AG_ESTATE, "the tree was built without per-particle softening lengths");
+    if (!(n_ngb > 32.0 / 3.0) || !(n_ngb < 32.0 * (double)c->n / 3.0))
+        return ag_fail(AG_EINVAL, "n_ngb must lie in (32/3, 32 n/3)");
+    return AG_OK;
+}
+
+extern "C" int ag_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega) {
+    AG_TRY(check_pm(c, n_ngb, true));
+    if (!h || !omega) return ag_fail(AG_EINVAL, "h and omega must be non-null");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_pm_lengths(c, n_ngb, h, omega, 0));
+    AG_TRY(check_launch("Price & Monaghan lengths"));
+    int32_t f = 0;
+    AG_HIP(hipMemcpyAsync(&f, c->dflags.p, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    AG_HIP(hipStreamSynchronize(c->stream));
+    if (f & AGF_PMSHORT) {
+        // brackets [r_64, D / u*] close to one double within 128 halvings
+        // for any ratio below 2^75
+        AG_HIP(hipMemsetAsync(c->dflags.p, 0, sizeof(int32_t), c->stream));
+        for (int step = 1; step <= 128; ++step) AG_TRY(ag_launch_pm_lengths(c, n_ngb, h, omega, step));
+        AG_TRY(check_launch("Price & Monaghan lengths"));
+    }
+    return read_flags(c);
+}
+
+extern "C" int ag_pm_factors(ag_ctx* c, double n_ngb, double G, const double* omega, double* z) {
+    AG_TRY(check_pm(c, n_ngb, false));
+    if (!omega || !z) return ag_fail(AG_EINVAL, "omega and z must be non-null");
+    if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_pm_sum(c, 0, n_ngb, G, omega, nullptr, z, nullptr));
+    return check_launch("Price & Monaghan factors");
+}
+
+extern "C" int ag_pm_correct(ag_ctx* c, const double* z, double* acc) {
+    AG_TRY(check_pm(c, 16.0, false));
+    if (!z || !acc) return ag_fail(AG_EINVAL, "z and acc must be non-null");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_pm_sum(c, 1, 16.0, 0.0, nullptr, z, nullptr, acc));
+    return check_launch("Price & Monaghan correction");
 }
 
 extern "C" int ag_neighbour_lengths(ag_ctx* c, int32_t k, double* h) {

@@ -38,7 +38,7 @@ struct DevBuf {
 };
 
 // device-side flag bits (ag_ctx::dflags)
-enum { AGF_BADINDEX = 1, AGF_NONFINITE = 2, AGF_INTERNAL = 4 };
+enum { AGF_BADINDEX = 1, AGF_NONFINITE = 2, AGF_INTERNAL = 4, AGF_PMSHORT = 8 };
 
 constexpr int AG_MAX_LEVEL = 21;   // Morton digits: 21 x 3 bits = 63-bit keys
 constexpr int AG_MAX_SYS = 512;    // batched systems: 3 octal digits of prefix
@@ -133,6 +133,7 @@ struct ag_ctx {
     DevBuf soft_h;                // f64 per-particle softening lengths, input order
     DevBuf soft_s;                // f32 the same in key order (rounded up)
     DevBuf rel_a;                 // f32 |a| of the previous evaluation, input order (rounded down)
+    DevBuf pm_brk;                // Price & Monaghan lengths: bisection brackets (2 n doubles)
     DevBuf ewald_tab;             // f32 Ewald correction table (5 float4 per point)
     DevBuf ewald_q;               // i32 [8]: correction walk work-queue counters
     DevBuf grp_hdr;               // i32: [0] number of groups, [8..15] walk work-queue counters
@@ -190,6 +191,9 @@ int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m
 int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps,
                    double G, double* acc, double* jerk, double* tidal);
 int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out);
+int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int step);
+int ag_launch_pm_sum(ag_ctx* c, int mode, double n_ngb, double G, const double* omega, const double* z,
+                     double* z_out, double* acc);
 int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w,
                        double theta, double eps, double G, double* dLdx, double* dLdm);
 // exclusive scan of n int32 counts into out (n+1 entries; out[n] = total) on c->stream

@@ -99,6 +99,18 @@ struct WalkOut {
     double* knn_out;    // neighbour lengths (input order)
     int knn_k;          // which neighbour
     int64_t knn_n;
+    // Price & Monaghan terms (input order arrays)
+    double pm_ngb;      // > 0: the neighbour walk solves the density condition
+    double pm_G;
+    double* pm_omega;
+    const double* pm_h;
+    double* pm_lo;      // bisection brackets of the lengths (input order)
+    double* pm_hi;
+    double pm_hiscale;  // upper end of a bracket: this times the root's diagonal
+    const double* pm_om;
+    const double* pm_z;
+    double* pm_zout;
+    double* pm_acc;
     double* dldx;       // adjoint outputs
     double* dldm;
     const double* tin;  // adjoint: tidal tensor rows of the charged targets
@@ -960,6 +972,24 @@ struct EwaldPolicy {
     }
 };
 
+// ---- the cubic spline with support 1 for the Price & Monaghan terms ----
+// w(u) and w'(u) with W(r, h) = 8/(pi h^3) w(r/h); and -h^2 dphi/dh =
+// psi(u) + u^2 F(u), where phi(r, h) = psi(r/h)/h is the potential of the
+// spread unit mass and F = h^3 f its force kernel (the 1/u terms cancel):
+//   16 u^2 - 48 u^4 + 192/5 u^5 - 14/5               (u < 1/2)
+//   32 u^2 - 64 u^3 + 48 u^4 - 64/5 u^5 - 16/5        (1/2 <= u < 1), 0 beyond.
+__device__ __forceinline__ double m4_w(double u) {
+    return u < 0.5 ? 1.0 + u * u * (-6.0 + 6.0 * u) : (u < 1.0 ? 2.0 * (1.0 - u) * (1.0 - u) * (1.0 - u) : 0.0);
+}
+__device__ __forceinline__ double m4_wp(double u) {
+    return u < 0.5 ? u * (-12.0 + 18.0 * u) : (u < 1.0 ? -6.0 * (1.0 - u) * (1.0 - u) : 0.0);
+}
+__device__ __forceinline__ double m4_dphi(double u) {
+    const double u2 = u * u;
+    return u < 0.5 ? u2 * (16.0 + u2 * (-48.0 + u * (192.0 / 5.0))) - 14.0 / 5.0
+                   : (u < 1.0 ? u2 * (32.0 + u * (-64.0 + u * (48.0 - u * (64.0 / 5.0)))) - 16.0 / 5.0 : 0.0);
+}
+
 // ---- k-th neighbour distance: the length fully adaptive softening follows ----
 // Every node is opened; a node whose box lies farther from the group's box
 // than the group's pruning radius is skipped.  Each target keeps its k
@@ -1116,8 +1146,201 @@ struct KnnPolicy {
     }
     __device__ static void nodes(const Lds&, int, const Target&, Acc&, int, int, const WalkOut&) {}
     static __device__ void wave_sum(Acc&) {}
+    // Density mode (Price & Monaghan lengths): h with 1 + sum_i w(r_i / h) =
+    // 3 N / 32 over the listed neighbours (self counted as 1), by bisection;
+    // every particle within h is listed when the root lies inside the list's
+    // last distance or the list holds all the others.  Also Omega =
+    // -(32 / (9 N)) sum_i u_i w'(u_i).
     __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
-        O.knn_out[T.perm[p]] = sqrt(A.L[kCap - 1]);
+        const int64_t row = T.perm[p];
+        if (kCap != 64 || !(O.pm_ngb > 0.0)) {
+            O.knn_out[row] = sqrt(A.L[kCap - 1]);
+            return;
+        }
+        double r[kCap];
+#pragma unroll
+        for (int i = 0; i < kCap; ++i) r[i] = A.L[i] > 0.0 ? sqrt(A.L[i]) : (A.L[i] == 0.0 ? 0.0 : -1.0);
+        const double target = 3.0 * O.pm_ngb / 32.0;
+        auto sum_w = [&](double h) {
+            const double hinv = 1.0 / h;
+            double s = 1.0;
+#pragma unroll
+            for (int i = 0; i < kCap; ++i) s += r[i] >= 0.0 ? m4_w(r[i] * hinv) : 0.0;
+            return s;
+        };
+        const bool all = (int64_t)O.knn_k >= O.knn_n - 1;
+        double hi = r[kCap - 1] > 0.0 ? r[kCap - 1] : 1.0;
+        bool ok = true;
+        if (sum_w(hi) < target) {
+            if (all) {
+                for (int g = 0; g < 64 && sum_w(hi) < target; ++g) hi *= 2.0;
+            } else {
+                ok = false;
+            }
+        }
+        double lo = 0.0;
+        for (int it = 0; it < 64; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (sum_w(mid) < target) lo = mid; else hi = mid;
+        }
+        const double h = 0.5 * (lo + hi);
+        double su = 0.0;
+#pragma unroll
+        for (int i = 0; i < kCap; ++i) {
+            const double u = r[i] / h;
+            su += r[i] >= 0.0 ? u * m4_wp(u) : 0.0;
+        }
+        // where the list is too short the root lies beyond its last
+        // distance; the sum walk bisects from there (a bracket lo = hi marks
+        // a finished length)
+        if (!ok) {
+            atomicOr(O.flags, AGF_PMSHORT);
+            const int root = T.sys_root[0];
+            const float4 lo4 = T.lo[root], hi4 = T.hi[root];
+            const double ex = (double)hi4.x - lo4.x, ey = (double)hi4.y - lo4.y, ez = (double)hi4.z - lo4.z;
+            O.pm_lo[row] = r[kCap - 1];
+            O.pm_hi[row] = O.pm_hiscale * sqrt(ex * ex + ey * ey + ez * ez);
+        } else {
+            O.pm_lo[row] = h;
+            O.pm_hi[row] = h;
+        }
+        O.knn_out[row] = ok ? h : __builtin_nan("");
+        O.pm_omega[row] = ok ? -(32.0 / (9.0 * O.pm_ngb)) * su : __builtin_nan("");
+    }
+};
+
+// ---- Price & Monaghan sums over the pairs inside a kernel support ----
+// kMode 0: Z_i = -(G m_i h_i^2 / (6 C Omega_i)) sum_{j != i, r < h_i} m_j
+//          (psi + u^2 F)(r / h_i), C = 3 N / (4 pi) (number density n h^3);
+// kMode 1: a_i = -(1 / m_i) sum_{j != i} [Z_i W'(r, h_i) + Z_j W'(r, h_j)] d / r
+//          over r < max(h_i, h_j), W'(r, h) = 8 / (pi h^4) w'(r / h), d = x_j - x_i.
+// kMode 2: one bisection step of a length whose support holds more
+//          particles than the neighbour list: at the bracket's midpoint h,
+//          sum_j w(r / h) (self included) against 3 N / 32 halves the bracket;
+//          h and Omega at h are written.  Targets with a closed bracket
+//          take no part; a group with none left skips the whole tree.
+// The lengths are the per-particle softening lengths the tree was built
+// with (FP64, input order); each node's largest one (lo.w, a float) bounds
+// the sources' supports in mode 1.  Coincident pairs add nothing (w'(0) = 0).
+// Only the first lane of each target sums.
+struct PmLds : WalkLds<2> {
+    double hz[2 * kW];   // staged sources' h and Z
+    double r2;           // the group's largest h^2
+};
+template <int kMode>
+struct PmPolicy {
+    static constexpr bool kSkipEmpty = false;
+    static constexpr bool kOpenAll = true;
+    static constexpr bool kImageMac = false;
+    static constexpr bool kGroupSum = false;
+    static constexpr int kWaves = 4;
+    using Lds = PmLds;
+    struct Acc {
+        double x, y, z, m, h, zi;
+        double s, ax, ay, az;
+        __device__ void zero() { s = ax = ay = az = 0.0; }
+        __device__ void add(const Acc&) {}
+    };
+    template <int kPer>
+    __device__ static bool skip_node(const Lds& S, const Tree& T, const GroupBox& g, int a, const WalkOut&) {
+        const float4 lo = T.lo[a], hi = T.hi[a];
+        const double gx = fmax(fmax((double)lo.x - g.hix, (double)g.lox - hi.x), 0.0);
+        const double gy = fmax(fmax((double)lo.y - g.hiy, (double)g.loy - hi.y), 0.0);
+        const double gz = fmax(fmax((double)lo.z - g.hiz, (double)g.loz - hi.z), 0.0);
+        double R2 = S.r2;
+        if (kMode == 1) {
+            const double hn = (double)lo.w * (1.0 + 1e-6);   // covers the float rounding of each length
+            R2 = fmax(R2, hn * hn);
+        }
+        return gx * gx + gy * gy + gz * gz > R2 * (1.0 + 1e-12);
+    }
+    template <int kPer>
+    __device__ static void start(Lds& S, const Tree& T, const WalkOut& O, int4, const Target& t, Acc& A, int part,
+                                 int, int) {
+        const double4 xi = T.spos[t.p];
+        A.x = xi.x;
+        A.y = xi.y;
+        A.z = xi.z;
+        A.m = xi.w;
+        const int64_t row = T.perm[t.p];
+        if (kMode == 2) {
+            const double lo = O.pm_lo[row], hi = O.pm_hi[row], mid = 0.5 * (lo + hi);
+            A.h = mid > lo && mid < hi ? mid : 0.0;
+        } else {
+            A.h = O.pm_h[row];
+        }
+        A.zi = kMode == 1 ? O.pm_z[row] : 0.0;
+        const double r2 = ag_wave_max(part == 0 && A.h > 0.0 ? A.h * A.h : -1.0);
+        if (threadIdx.x == 0) S.r2 = r2;
+        __syncthreads();
+    }
+    template <int kPer>
+    __device__ static void stage_particle(Lds& S, const Tree& T, const GroupBox&, int lane, int pk, const WalkOut& O) {
+        reinterpret_cast<double4*>(S.tile)[lane] = T.spos[pk];
+        S.tidx[lane] = pk;
+        if (kMode == 1) {
+            const int64_t row = T.perm[pk];
+            S.hz[2 * lane] = O.pm_h[row];
+            S.hz[2 * lane + 1] = O.pm_z[row];
+        }
+    }
+    template <int kPer>
+    __device__ static void stage_node(Lds&, const Tree&, const GroupBox&, int, int, const WalkOut&) {}
+    template <int kPer, bool kSoft>
+    __device__ static void particles(Lds& S, int cnt, const Target& t, Acc& A, float, float, int k0, int,
+                                     const WalkOut&) {
+        if (k0 != 0) return;
+        const double4* P = reinterpret_cast<const double4*>(S.tile);
+        constexpr double k8pi = 8.0 / 3.14159265358979323846;
+        for (int q = 0; q < cnt; ++q) {
+            if (kMode == 2) {   // self included: w(0) = 1
+                const double4 pj = P[q];
+                const double dx = pj.x - A.x, dy = pj.y - A.y, dz = pj.z - A.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < A.h * A.h) {
+                    const double u = sqrt(r2) / A.h;
+                    A.s += m4_w(u);
+                    A.ax += u * m4_wp(u);
+                }
+                continue;
+            }
+            if (S.tidx[q] == t.p) continue;
+            const double4 pj = P[q];
+            const double dx = pj.x - A.x, dy = pj.y - A.y, dz = pj.z - A.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (kMode == 0) {
+                if (r2 < A.h * A.h) A.s += pj.w * m4_dphi(sqrt(r2) / A.h);
+            } else {
+                const double hj = S.hz[2 * q], zj = S.hz[2 * q + 1];
+                if (r2 > 0.0 && (r2 < A.h * A.h || r2 < hj * hj)) {
+                    const double r = sqrt(r2);
+                    const double hi4 = (A.h * A.h) * (A.h * A.h), hj4 = (hj * hj) * (hj * hj);
+                    const double c = k8pi * (A.zi * m4_wp(r / A.h) / hi4 + zj * m4_wp(r / hj) / hj4) / r;
+                    A.ax += c * dx;
+                    A.ay += c * dy;
+                    A.az += c * dz;
+                }
+            }
+        }
+    }
+    __device__ static void nodes(const Lds&, int, const Target&, Acc&, int, int, const WalkOut&) {}
+    static __device__ void wave_sum(Acc&) {}
+    __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
+        const int64_t row = T.perm[p];
+        if (kMode == 2) {
+            if (!(A.h > 0.0)) return;
+            if (A.s < 3.0 * O.pm_ngb / 32.0) O.pm_lo[row] = A.h;
+            else O.pm_hi[row] = A.h;
+            O.knn_out[row] = A.h;
+            O.pm_omega[row] = -(32.0 / (9.0 * O.pm_ngb)) * A.ax;
+        } else if (kMode == 0) {
+            const double C = 3.0 * O.pm_ngb / (4.0 * 3.14159265358979323846);
+            O.pm_zout[row] = -(O.pm_G * A.m * A.h * A.h / (6.0 * C * O.pm_om[row])) * A.s;
+        } else {
+            O.pm_acc[3 * row] = -A.ax / A.m;
+            O.pm_acc[3 * row + 1] = -A.ay / A.m;
+            O.pm_acc[3 * row + 2] = -A.az / A.m;
+        }
     }
 };
 
@@ -1898,6 +2121,70 @@ int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out) {
         if (per) AG_KNN(64, kNear); else AG_KNN(64, kOpen);
     }
 #undef AG_KNN
+    return AG_OK;
+}
+
+// Price & Monaghan lengths and Omega: the 64-neighbour walk in density mode
+// (step 0), then the sum walk's bisection steps for the lengths the list
+// cannot reach (step > 0; each launch re-arms the walk's work queues)
+int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int step) {
+    int64_t mg = 0;
+    AG_TRY(ag_prepare_groups(c, nullptr, c->n, &mg));
+    if (step == 0) AG_TRY(ag_ensure(c->pm_brk, (size_t)c->n * 2 * sizeof(double)));
+    Groups Gr{nullptr, c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    WalkOut O = make_out(c, 1.0);
+    O.stats = nullptr;
+    O.knn_out = h;
+    O.knn_k = c->n - 1 < 64 ? (int)(c->n - 1) : 64;
+    O.knn_n = c->n;
+    O.pm_ngb = n_ngb;
+    O.pm_omega = omega;
+    O.pm_lo = c->pm_brk.as<double>();
+    O.pm_hi = O.pm_lo + c->n;
+    // every particle lies within the root's diagonal D of every other, so
+    // at h = D / u* the sum is at least n (1 - 6 u*^2) >= 3 N / 32 (w(u) >=
+    // 1 - 6 u^2 for u < 1/2)
+    const double f = 3.0 * n_ngb / 32.0 / (double)c->n;
+    const double us = std::min(0.5, std::sqrt((1.0 - f) / 6.0));
+    O.pm_hiscale = 1.01 / us;
+    PhaseScope phase(c, AG_PHASE_NEIGHBOUR);
+    const unsigned grid = (unsigned)walk_grid(c, mg);
+    int32_t* qctr = c->grp_hdr.as<int32_t>() + 8;
+    if (step == 0) {
+        hipLaunchKernelGGL((k_walk<KnnPolicy<64>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
+                           qctr, 0.f, 0.f, 0.f, 0.f);
+    } else {
+        hipLaunchKernelGGL((k_walk<PmPolicy<2>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
+                           qctr, 0.f, 0.f, 0.f, 0.f);
+    }
+    return AG_OK;
+}
+
+// Price & Monaghan sums: Z (mode 0, z_out) or the correction (mode 1, acc)
+int ag_launch_pm_sum(ag_ctx* c, int mode, double n_ngb, double G, const double* omega, const double* z,
+                     double* z_out, double* acc) {
+    int64_t mg = 0;
+    AG_TRY(ag_prepare_groups(c, nullptr, c->n, &mg));
+    Groups Gr{nullptr, c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    WalkOut O = make_out(c, G);
+    O.stats = nullptr;
+    O.pm_ngb = n_ngb;
+    O.pm_G = G;
+    O.pm_h = c->soft_h.as<double>();
+    O.pm_om = omega;
+    O.pm_z = z;
+    O.pm_zout = z_out;
+    O.pm_acc = acc;
+    PhaseScope phase(c, AG_PHASE_NEIGHBOUR);
+    const unsigned grid = (unsigned)walk_grid(c, mg);
+    const Tree T = make_tree(c);
+    int32_t* qctr = c->grp_hdr.as<int32_t>() + 8;
+    if (mode == 0)
+        hipLaunchKernelGGL((k_walk<PmPolicy<0>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, T, Gr, O, qctr, 0.f, 0.f,
+                           0.f, 0.f);
+    else
+        hipLaunchKernelGGL((k_walk<PmPolicy<1>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, T, Gr, O, qctr, 0.f, 0.f,
+                           0.f, 0.f);
     return AG_OK;
 }
 
