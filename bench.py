@@ -131,7 +131,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="tree",
                     choices=["tree", "direct", "adaptive", "batched", "adjoint", "periodic", "softening", "relative",
-                             "copy"],
+                             "pm", "copy"],
                     help="tree: the headline line (default); the others measure the remaining "
                          "configurations and print their own JSON line (copy: a plain 1 GiB device "
                          "copy that calibrates the HBM byte counters)")

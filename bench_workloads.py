@@ -575,6 +575,80 @@ def run_softening(args):
 
 
 # ---------------------------------------------------------------------------
+def run_pm(args):
+    """Fully adaptive softening with the Price & Monaghan terms: each step
+    solves the lengths and Omega on the previous tree, rebuilds with those
+    lengths, evaluates the softened tree force, then the factors Z and the
+    correction.  Checked on sampled rows against the density condition and
+    Omega's definition (the lengths' definition over every particle)."""
+    import oracle
+    n, n_ngb = args.n, 32.0
+    x, v, m = workloads.turbulent_sphere(n, seed=2, grid=128)
+    tx, tv, tm = _t(x), _t(v), _t(m)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+    jerk, tid = torch.zeros_like(acc), torch.zeros((n, 6), dtype=torch.float64, device=DEV)
+    h = torch.empty(n, dtype=torch.float64, device=DEV)
+    om, z = torch.empty_like(h), torch.empty_like(h)
+    corr = torch.empty_like(acc)
+    names = ("lengths", "build", "gravity", "factors", "correction")
+    with ag.Context(0) as c:
+        c.set_option(ag.AG_OPT_MAC_OFFSET, args.mac_offset)
+        c.tree_build(tx, tv, tm, args.n_leaf)
+        c.pm_lengths(n_ngb, h, om)
+
+        def step(ev=None):
+            mark = (lambda i: ev[i].record()) if ev else (lambda i: None)
+            mark(0)
+            c.pm_lengths(n_ngb, h, om)
+            mark(1)
+            c.set_softening(h)
+            c.tree_build(tx, tv, tm, args.n_leaf)
+            mark(2)
+            c.grav_eval(None, args.theta, args.eps, 1.0, acc, jerk, tid)
+            mark(3)
+            c.pm_factors(n_ngb, 1.0, om, z)
+            mark(4)
+            c.pm_correct(z, corr)
+            mark(5)
+
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        reps = 5
+        e0, e1 = _events()
+        e0.record()
+        for _ in range(reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        phase = dict.fromkeys(names, 0.0)
+        for _ in range(reps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            step(ev)
+            torch.cuda.synchronize()
+            for i, k in enumerate(names):
+                phase[k] += ev[i].elapsed_time(ev[i + 1]) / reps
+    hh, oo = h.cpu().numpy(), om.cpu().numpy()
+    rows = np.random.default_rng(9).choice(n, 64, replace=False)
+    dens, omer = [], []
+    for i in rows:
+        u = np.sqrt(np.sum((x - x[i])**2, axis=1)) / hh[i]
+        w, wp = oracle.m4_shape(u)
+        dens.append(abs(w.sum() / (3.0 * n_ngb / 32.0) - 1.0))
+        omer.append(abs(oo[i] + 32.0 / (9.0 * n_ngb) * np.sum(u * wp)))
+    cn = np.linalg.norm(corr.cpu().numpy(), axis=1) / np.linalg.norm(acc.cpu().numpy(), axis=1)
+    out = {"workload": f"turbulent sphere N={n}, n_ngb={n_ngb:g}, theta={args.theta}",
+           "ms_per_step": ms, "phase_ms": phase,
+           "h_median": float(np.median(hh)), "h_1_99": [float(np.percentile(hh, 1)), float(np.percentile(hh, 99))],
+           "density_max_rel_err": float(max(dens)), "omega_max_abs_err": float(max(omer)),
+           "omega_median": float(np.median(oo)),
+           "correction_over_gravity_median": float(np.median(cn))}
+    log(f"pm: {out}")
+    return out
+
+
+# ---------------------------------------------------------------------------
 def run_relative(args):
     """Geometric opening test alone at several theta against the combined
     geometric + relative test at several alpha (|a_old| from the previous

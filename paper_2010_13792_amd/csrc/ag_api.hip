@@ -621,17 +621,30 @@ extern "C" int ag_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega) 
     AG_TRY(check_pm(c, n_ngb, true));
     if (!h || !omega) return ag_fail(AG_EINVAL, "h and omega must be non-null");
     DeviceGuard g(c->device);
-    AG_TRY(ag_launch_pm_lengths(c, n_ngb, h, omega, 0));
+    AG_TRY(ag_ensure(c->pm_brk, (size_t)c->n * (3 * sizeof(double) + sizeof(int32_t)) + kPmSteps * sizeof(int)));
+    // each step counts in a slot of its own (slot 0: the rows the list pass
+    // leaves to the sum walk)
+    int* cnt = reinterpret_cast<int*>(c->pm_brk.as<double>() + 3 * c->n);
+    AG_HIP(hipMemsetAsync(cnt, 0, kPmSteps * sizeof(int), c->stream));
+    AG_TRY(ag_launch_pm_lengths(c, n_ngb, h, omega, 0, 0));
     AG_TRY(check_launch("Price & Monaghan lengths"));
-    int32_t f = 0;
+    int32_t f = 0, n_left = 0;
     AG_HIP(hipMemcpyAsync(&f, c->dflags.p, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    AG_HIP(hipMemcpyAsync(&n_left, cnt, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     AG_HIP(hipStreamSynchronize(c->stream));
-    if (f & AGF_PMSHORT) {
-        // brackets [r_64, D / u*] close to one double within 128 halvings
-        // for any ratio below 2^75
+    if ((f & AGF_PMSHORT) && n_left > 0) {
+        // Newton steps of the sum walk until no length moves
         AG_HIP(hipMemsetAsync(c->dflags.p, 0, sizeof(int32_t), c->stream));
-        for (int step = 1; step <= 128; ++step) AG_TRY(ag_launch_pm_lengths(c, n_ngb, h, omega, step));
+        int step = 1, moving = 1;
+        for (; step < kPmSteps && moving; ++step) {
+            AG_TRY(ag_launch_pm_lengths(c, n_ngb, h, omega, step, n_left));
+            if (step % 4 == 0 || step == kPmSteps - 1) {
+                AG_HIP(hipMemcpyAsync(&moving, cnt + step, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+                AG_HIP(hipStreamSynchronize(c->stream));
+            }
+        }
         AG_TRY(check_launch("Price & Monaghan lengths"));
+        if (moving) return ag_fail(AG_EHIP, "Price & Monaghan lengths did not settle");
     }
     return read_flags(c);
 }

@@ -133,7 +133,7 @@ struct ag_ctx {
     DevBuf soft_h;                // f64 per-particle softening lengths, input order
     DevBuf soft_s;                // f32 the same in key order (rounded up)
     DevBuf rel_a;                 // f32 |a| of the previous evaluation, input order (rounded down)
-    DevBuf pm_brk;                // Price & Monaghan lengths: bisection brackets (2 n doubles)
+    DevBuf pm_brk;                // Price & Monaghan lengths: brackets and current lengths (3 n doubles), step counters, rows left to the sum walk (n)
     DevBuf ewald_tab;             // f32 Ewald correction table (5 float4 per point)
     DevBuf ewald_q;               // i32 [8]: correction walk work-queue counters
     DevBuf grp_hdr;               // i32: [0] number of groups, [8..15] walk work-queue counters
@@ -191,7 +191,8 @@ int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m
 int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps,
                    double G, double* acc, double* jerk, double* tidal);
 int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out);
-int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int step);
+constexpr int kPmSteps = 257;   // sum walk steps of the lengths (slot 0 unused) and their counters
+int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int step, int64_t n_left);
 int ag_launch_pm_sum(ag_ctx* c, int mode, double n_ngb, double G, const double* omega, const double* z,
                      double* z_out, double* acc);
 int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w,

@@ -106,6 +106,9 @@ struct WalkOut {
     const double* pm_h;
     double* pm_lo;      // bisection brackets of the lengths (input order)
     double* pm_hi;
+    double* pm_cur;     // the length the next sum walk evaluates
+    int* pm_active;     // sum walk: lengths still moving after it (list pass: lengths left to it)
+    int32_t* pm_idx;    // list pass: the rows left to the sum walk
     double pm_hiscale;  // upper end of a bracket: this times the root's diagonal
     const double* pm_om;
     const double* pm_z;
@@ -990,6 +993,31 @@ __device__ __forceinline__ double m4_dphi(double u) {
                    : (u < 1.0 ? u2 * (32.0 + u * (-64.0 + u * (48.0 - u * (64.0 / 5.0)))) - 16.0 / 5.0 : 0.0);
 }
 
+// One step of safeguarded Newton for S(h) = target with S increasing in h:
+// s = S(h), sd = sum u w'(u) (so dS/dh = -sd / h).  The bracket [lo, hi]
+// shrinks to the side of h the sign of S - target gives; the Newton point is
+// taken when it falls strictly inside the bracket (growing h at most
+// twofold), else twice h while h is below the root and the sum has no slope
+// there, else the bracket's midpoint.
+// Returns false once the length is settled, leaving hn = h: the step or the
+// bracket below 2e-14 h (above the rounding noise of a sum of many terms,
+// which keeps a tighter test from ever closing; Newton's last step had
+// already brought h to that noise).
+__device__ __forceinline__ bool pm_newton(double s, double sd, double target, double h, double& lo, double& hi,
+                                          double& hn) {
+    if (s < target) lo = h; else hi = h;
+    hn = h;
+    if (hi - lo <= 2e-14 * hi) return false;
+    double t = sd < 0.0 ? h + (s - target) * h / sd : -1.0;
+    // a settled Newton step is tested first: below an ulp it returns h
+    // itself, which the bracket test would take for a failed step
+    if (sd < 0.0 && fabs(t - h) <= 2e-14 * h) return false;
+    if (s < target && t > 2.0 * h) t = 2.0 * h;
+    if (!(t > lo && t < hi)) t = s < target && sd == 0.0 && 2.0 * h < hi ? 2.0 * h : 0.5 * (lo + hi);
+    hn = t;
+    return true;
+}
+
 // ---- k-th neighbour distance: the length fully adaptive softening follows ----
 // Every node is opened; a node whose box lies farther from the group's box
 // than the group's pruning radius is skipped.  Each target keeps its k
@@ -1146,11 +1174,11 @@ struct KnnPolicy {
     }
     __device__ static void nodes(const Lds&, int, const Target&, Acc&, int, int, const WalkOut&) {}
     static __device__ void wave_sum(Acc&) {}
-    // Density mode (Price & Monaghan lengths): h with 1 + sum_i w(r_i / h) =
-    // 3 N / 32 over the listed neighbours (self counted as 1), by bisection;
-    // every particle within h is listed when the root lies inside the list's
-    // last distance or the list holds all the others.  Also Omega =
-    // -(32 / (9 N)) sum_i u_i w'(u_i).
+    // Density mode (Price & Monaghan lengths): h with S(h) = 1 + sum_i
+    // w(r_i / h) = 3 N / 32 over the listed neighbours (self counted as 1),
+    // by pm_newton; every particle within h is listed when the root lies
+    // inside the list's last distance or the list holds all the others.
+    // Also Omega = -(32 / (9 N)) sum_i u_i w'(u_i) at h.
     __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
         const int64_t row = T.perm[p];
         if (kCap != 64 || !(O.pm_ngb > 0.0)) {
@@ -1161,51 +1189,53 @@ struct KnnPolicy {
 #pragma unroll
         for (int i = 0; i < kCap; ++i) r[i] = A.L[i] > 0.0 ? sqrt(A.L[i]) : (A.L[i] == 0.0 ? 0.0 : -1.0);
         const double target = 3.0 * O.pm_ngb / 32.0;
-        auto sum_w = [&](double h) {
+        auto sums = [&](double h, double& sd) {
             const double hinv = 1.0 / h;
-            double s = 1.0;
+            double sw = 1.0;
+            sd = 0.0;
 #pragma unroll
-            for (int i = 0; i < kCap; ++i) s += r[i] >= 0.0 ? m4_w(r[i] * hinv) : 0.0;
-            return s;
+            for (int i = 0; i < kCap; ++i) {
+                const double u = r[i] * hinv;
+                if (r[i] >= 0.0 && u < 1.0) {
+                    sw += m4_w(u);
+                    sd += u * m4_wp(u);
+                }
+            }
+            return sw;
         };
         const bool all = (int64_t)O.knn_k >= O.knn_n - 1;
-        double hi = r[kCap - 1] > 0.0 ? r[kCap - 1] : 1.0;
-        bool ok = true;
-        if (sum_w(hi) < target) {
-            if (all) {
-                for (int g = 0; g < 64 && sum_w(hi) < target; ++g) hi *= 2.0;
-            } else {
-                ok = false;
-            }
-        }
-        double lo = 0.0;
-        for (int it = 0; it < 64; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (sum_w(mid) < target) lo = mid; else hi = mid;
-        }
-        const double h = 0.5 * (lo + hi);
-        double su = 0.0;
-#pragma unroll
-        for (int i = 0; i < kCap; ++i) {
-            const double u = r[i] / h;
-            su += r[i] >= 0.0 ? u * m4_wp(u) : 0.0;
-        }
-        // where the list is too short the root lies beyond its last
-        // distance; the sum walk bisects from there (a bracket lo = hi marks
-        // a finished length)
-        if (!ok) {
+        double hi = r[kCap - 1] > 0.0 ? r[kCap - 1] : 1.0, sd = 0.0;
+        double shi = sums(hi, sd);
+        if (all)
+            for (int g = 0; g < 64 && shi < target; ++g) shi = sums(hi *= 2.0, sd);
+        if (shi < target) {
+            // the root lies beyond the list: the sum walk takes over from the
+            // list's last distance with a bracket closed by any length at
+            // which every particle counts (h = D / u*, D the root's diagonal)
             atomicOr(O.flags, AGF_PMSHORT);
+            O.pm_idx[atomicAdd(O.pm_active, 1)] = (int32_t)row;
             const int root = T.sys_root[0];
             const float4 lo4 = T.lo[root], hi4 = T.hi[root];
             const double ex = (double)hi4.x - lo4.x, ey = (double)hi4.y - lo4.y, ez = (double)hi4.z - lo4.z;
-            O.pm_lo[row] = r[kCap - 1];
+            O.pm_lo[row] = hi;
             O.pm_hi[row] = O.pm_hiscale * sqrt(ex * ex + ey * ey + ez * ez);
-        } else {
-            O.pm_lo[row] = h;
-            O.pm_hi[row] = h;
+            O.pm_cur[row] = 2.0 * hi;
+            O.knn_out[row] = __builtin_nan("");
+            O.pm_omega[row] = __builtin_nan("");
+            return;
         }
-        O.knn_out[row] = ok ? h : __builtin_nan("");
-        O.pm_omega[row] = ok ? -(32.0 / (9.0 * O.pm_ngb)) * su : __builtin_nan("");
+        double lo = 0.0, h = hi;
+        for (int it = 0; it < 200; ++it) {
+            const double s = sums(h, sd);
+            double hn;
+            if (!pm_newton(s, sd, target, h, lo, hi, hn)) break;
+            h = hn;
+        }
+        sums(h, sd);
+        O.pm_lo[row] = h;   // a closed bracket: the sum walk leaves it alone
+        O.pm_hi[row] = h;
+        O.knn_out[row] = h;
+        O.pm_omega[row] = -(32.0 / (9.0 * O.pm_ngb)) * sd;
     }
 };
 
@@ -1214,11 +1244,11 @@ struct KnnPolicy {
 //          (psi + u^2 F)(r / h_i), C = 3 N / (4 pi) (number density n h^3);
 // kMode 1: a_i = -(1 / m_i) sum_{j != i} [Z_i W'(r, h_i) + Z_j W'(r, h_j)] d / r
 //          over r < max(h_i, h_j), W'(r, h) = 8 / (pi h^4) w'(r / h), d = x_j - x_i.
-// kMode 2: one bisection step of a length whose support holds more
-//          particles than the neighbour list: at the bracket's midpoint h,
-//          sum_j w(r / h) (self included) against 3 N / 32 halves the bracket;
-//          h and Omega at h are written.  Targets with a closed bracket
-//          take no part; a group with none left skips the whole tree.
+// kMode 2: one pm_newton step of a length whose support holds more
+//          particles than the neighbour list: sum_j w(r / h) (self included)
+//          and sum_j u w'(u) at the current h; h and Omega at h are written.
+//          Targets with a closed bracket take no part; a group with none
+//          left skips the whole tree.
 // The lengths are the per-particle softening lengths the tree was built
 // with (FP64, input order); each node's largest one (lo.w, a float) bounds
 // the sources' supports in mode 1.  Coincident pairs add nothing (w'(0) = 0).
@@ -1264,8 +1294,7 @@ struct PmPolicy {
         A.m = xi.w;
         const int64_t row = T.perm[t.p];
         if (kMode == 2) {
-            const double lo = O.pm_lo[row], hi = O.pm_hi[row], mid = 0.5 * (lo + hi);
-            A.h = mid > lo && mid < hi ? mid : 0.0;
+            A.h = O.pm_lo[row] < O.pm_hi[row] ? O.pm_cur[row] : 0.0;
         } else {
             A.h = O.pm_h[row];
         }
@@ -1329,8 +1358,16 @@ struct PmPolicy {
         const int64_t row = T.perm[p];
         if (kMode == 2) {
             if (!(A.h > 0.0)) return;
-            if (A.s < 3.0 * O.pm_ngb / 32.0) O.pm_lo[row] = A.h;
-            else O.pm_hi[row] = A.h;
+            double lo = O.pm_lo[row], hi = O.pm_hi[row], hn;
+            if (pm_newton(A.s, A.ax, 3.0 * O.pm_ngb / 32.0, A.h, lo, hi, hn)) {
+                O.pm_lo[row] = lo;
+                O.pm_hi[row] = hi;
+                O.pm_cur[row] = hn;
+                atomicAdd(O.pm_active, 1);
+            } else {
+                O.pm_lo[row] = A.h;
+                O.pm_hi[row] = A.h;
+            }
             O.knn_out[row] = A.h;
             O.pm_omega[row] = -(32.0 / (9.0 * O.pm_ngb)) * A.ax;
         } else if (kMode == 0) {
@@ -2125,13 +2162,15 @@ int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out) {
 }
 
 // Price & Monaghan lengths and Omega: the 64-neighbour walk in density mode
-// (step 0), then the sum walk's bisection steps for the lengths the list
-// cannot reach (step > 0; each launch re-arms the walk's work queues)
-int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int step) {
+// (step 0), then the sum walk's Newton steps for the lengths the list
+// cannot reach (step > 0; each launch re-arms the walk's work queues), run
+// over the n_left rows the list pass left, grouped on their own)
+int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int step, int64_t n_left) {
     int64_t mg = 0;
-    AG_TRY(ag_prepare_groups(c, nullptr, c->n, &mg));
-    if (step == 0) AG_TRY(ag_ensure(c->pm_brk, (size_t)c->n * 2 * sizeof(double)));
-    Groups Gr{nullptr, c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    int32_t* left = reinterpret_cast<int32_t*>(reinterpret_cast<int*>(c->pm_brk.as<double>() + 3 * c->n) + kPmSteps);
+    AG_TRY(ag_prepare_groups(c, step == 0 ? nullptr : left, step == 0 ? c->n : n_left, &mg));
+    Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
+              c->grp_hdr.as<int32_t>()};
     WalkOut O = make_out(c, 1.0);
     O.stats = nullptr;
     O.knn_out = h;
@@ -2141,6 +2180,9 @@ int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int 
     O.pm_omega = omega;
     O.pm_lo = c->pm_brk.as<double>();
     O.pm_hi = O.pm_lo + c->n;
+    O.pm_cur = O.pm_hi + c->n;
+    O.pm_active = reinterpret_cast<int*>(O.pm_cur + c->n) + step;
+    O.pm_idx = left;
     // every particle lies within the root's diagonal D of every other, so
     // at h = D / u* the sum is at least n (1 - 6 u*^2) >= 3 N / 32 (w(u) >=
     // 1 - 6 u^2 for u < 1/2)
