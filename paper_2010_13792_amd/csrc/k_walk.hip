@@ -1224,7 +1224,10 @@ struct KnnPolicy {
             O.pm_omega[row] = __builtin_nan("");
             return;
         }
+        // start where S would meet the target if the listed neighbours filled
+        // the ball of radius hi uniformly (S - 1 growing as h^3)
         double lo = 0.0, h = hi;
+        if (shi > target) h = fmin(hi, hi * cbrt((target - 1.0) / (shi - 1.0)));
         for (int it = 0; it < 200; ++it) {
             const double s = sums(h, sd);
             double hn;
