@@ -174,11 +174,12 @@ int ag_neighbour_lengths(ag_ctx *ctx, int32_t k, double *h);
  *
  * ag_pm_lengths: h_i with 1 + sum_{j != i} w(r_ij / h_i) = 3 n_ngb / 32
  * (a number density of n_ngb particles per 4/3 pi h^3) and
- * Omega_i = -(32 / (9 n_ngb)) sum_j u w'(u), u = r_ij / h_i.  The support
- * must hold fewer than 64 other particles: where the 64 nearest do not
- * reach the root, h and omega are NaN there and the call returns AG_EINVAL
- * (lower n_ngb).  h, omega (n,) device FP64, input order; synchronises.
- * Needs a tree from ag_tree_build (any softening). */
+ * Omega_i = -(32 / (9 n_ngb)) sum_j u w'(u), u = r_ij / h_i, each h_i to a
+ * relative 2e-14 or better (safeguarded Newton).  Supports holding more
+ * than the 64 nearest neighbours are solved by further walks over those
+ * particles alone.  h, omega (n,) device FP64, input order; synchronises
+ * (AG_EHIP if a length has not settled after 256 walks).  Needs a tree from
+ * ag_tree_build (any softening). */
 int ag_pm_lengths(ag_ctx *ctx, double n_ngb, double *h, double *omega);
 
 /* ag_pm_factors: Z_i = (G/2) m_i h_i / (3 n_i Omega_i) sum_{j != i} m_j
