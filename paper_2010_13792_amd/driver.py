@@ -42,7 +42,7 @@ class AdaptiveIntegrator:
     def __init__(self, ctx: Context, x, v, m, q_f: float, theta: float, eps: float, eta: float = 0.01,
                  G: float = 1.0, n_leaf: int = 16, rebuild_every: int = 1, step_shift: int = 0,
                  predictor: str = "jerk", opening_alpha: float = 0.0, soft_k: int = 0,
-                 soft_scale: float = 1.0):
+                 soft_scale: float = 1.0, soft_pm: float = 0.0):
         """step_shift h: the global step is 2^-h times the shortest gravity
         bin at t = 0 (h = 0: the step equals the shortest gravity step; h > 0
         models a non-gravity step constraint tighter than gravity's, the
@@ -54,7 +54,12 @@ class AdaptiveIntegrator:
         with its own length, soft_scale times its distance to the soft_k-th
         nearest neighbour, found on the device from each step's tree and used
         from the next build on (so one step late; the first build is made
-        twice).  eps is then only validated."""
+        twice).  eps is then only validated.  soft_pm = N > 0 instead takes
+        the Price & Monaghan lengths (kernel-weighted number density of N
+        neighbours) solved on each new tree, rebuilds with them, and adds the
+        correction terms to every fresh force (exact only with a rebuild every
+        step: a refitted tree keeps the last lengths; the jerk leaves the
+        correction out)."""
         if predictor not in PREDICTORS:
             raise ValueError(f"predictor must be one of {sorted(PREDICTORS)}")
         self.predictor = predictor
@@ -64,7 +69,9 @@ class AdaptiveIntegrator:
         self.opening_alpha = float(opening_alpha)
         if soft_k < 0 or not soft_scale > 0.0:
             raise ValueError("soft_k must be >= 0 and soft_scale > 0")
-        self.soft_k, self.soft_scale = int(soft_k), float(soft_scale)
+        if not (soft_pm == 0.0 or soft_pm > 32.0 / 3.0) or (soft_pm > 0.0 and soft_k > 0):
+            raise ValueError("soft_pm must be 0 or above 32/3, and not combined with soft_k")
+        self.soft_k, self.soft_scale, self.soft_pm = int(soft_k), float(soft_scale), float(soft_pm)
         self.ctx = ctx
         dev = x.device
         self.n = n = x.shape[0]
@@ -85,7 +92,10 @@ class AdaptiveIntegrator:
         self.active = torch.zeros(n, dtype=torch.int32, device=dev)
         self.n_active = torch.zeros(1, dtype=torch.int64, device=dev)
         self.vpred = torch.zeros_like(self.v)
-        self.h = torch.zeros(n, dtype=torch.float64, device=dev) if soft_k > 0 else None
+        self.h = torch.zeros(n, dtype=torch.float64, device=dev) if soft_k > 0 or soft_pm > 0 else None
+        if soft_pm > 0:
+            self.omega, self.z = torch.zeros_like(self.h), torch.zeros_like(self.h)
+            self.corr = torch.zeros((n, 3), dtype=torch.float64, device=dev)
         self.scratch = torch.zeros_like(self.x)
         self.log = None
         if self.order is not None:
@@ -104,6 +114,7 @@ class AdaptiveIntegrator:
             ctx.tree_build(self.x, self.v, self.m, n_leaf)
         ctx.set_relative_opening()   # no earlier force: the geometric test alone
         ctx.grav_eval(None, theta, eps, G, self.a0, self.jerk, self.tidal)
+        self._pm_correct(None)
         ctx.grav_timestep(self.tidal, eta, 1.0, 60, self.dt_grav, self.bins)
         ctx.sync()
         dtg = self.dt_grav[torch.isfinite(self.dt_grav)]
@@ -120,10 +131,26 @@ class AdaptiveIntegrator:
 
     def _lengths(self):
         """Lengths from the current tree, in use from the next build on."""
-        self.ctx.neighbour_lengths(self.soft_k, self.h)
-        if self.soft_scale != 1.0:
-            self.h.mul_(self.soft_scale)
+        if self.soft_pm > 0:
+            self.ctx.pm_lengths(self.soft_pm, self.h, self.omega)
+        else:
+            self.ctx.neighbour_lengths(self.soft_k, self.h)
+            if self.soft_scale != 1.0:
+                self.h.mul_(self.soft_scale)
         self.ctx.set_softening(self.h)
+
+    def _pm_correct(self, idx):
+        """Add the Price & Monaghan correction to the fresh forces of idx
+        (None: every particle)."""
+        if self.soft_pm <= 0:
+            return
+        self.ctx.pm_factors(self.soft_pm, self.G, self.omega, self.z)
+        self.ctx.pm_correct(self.z, self.corr)
+        if idx is None:
+            self.a0.add_(self.corr)
+        else:
+            rows = idx.long()
+            self.a0.index_add_(0, rows, self.corr.index_select(0, rows))
 
     def step(self) -> int:
         c, dt = self.ctx, self.dt
@@ -140,6 +167,8 @@ class AdaptiveIntegrator:
             self._need_build = False
             if self.h is not None:
                 self._lengths()
+                if self.soft_pm > 0:   # the lengths of these positions
+                    c.tree_build(self.x, self.vpred, self.m, self.n_leaf)
         else:
             c.tree_refit(self.x, self.vpred, self.m)
         k = int(self.n_active.item())
@@ -147,6 +176,7 @@ class AdaptiveIntegrator:
             idx = self.active[:k]
             c.set_relative_opening(self.opening_alpha, self.a0 if self.opening_alpha > 0 else None)
             c.grav_eval(idx, self.theta, self.eps, self.G, self.a0, self.jerk, self.tidal)
+            self._pm_correct(idx)
             c.grav_timestep(self.tidal, self.eta, self.dt_max, 60, self.dt_grav, self.bins, idx=idx)
             if self.log is not None:
                 c.force_log(self.a0, self.t, *self.log, idx=idx)

@@ -11,7 +11,8 @@ def _x():
 
 
 @pytest.mark.parametrize("kw", [dict(predictor="cubic-spline"), dict(opening_alpha=-0.1),
-                                dict(opening_alpha=float("nan")), dict(soft_k=-1), dict(soft_k=8, soft_scale=0.0)])
+                                dict(opening_alpha=float("nan")), dict(soft_k=-1), dict(soft_k=8, soft_scale=0.0),
+                                dict(soft_pm=8.0), dict(soft_pm=-1.0), dict(soft_pm=32.0, soft_k=16)])
 def test_rejects_bad_arguments(kw):
     with pytest.raises(ValueError):
         AdaptiveIntegrator(None, _x(), _x(), torch.ones(4, dtype=torch.float64), q_f=0.5, theta=0.7, eps=1e-3, **kw)

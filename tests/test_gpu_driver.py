@@ -142,6 +142,41 @@ def _move(v, dev):
     return v
 
 
+
+
+def test_pm_softening_integrator(ag, orc):
+    """Price & Monaghan softening in the integrator (theta = 0, so the walk
+    is the direct sum up to its FP32 coordinates): the fresh forces at the
+    start and on the third step's active rows against the oracle's mean-kernel
+    sum plus correction, with the lengths solved at those positions."""
+    from paper_2010_13792_amd.driver import AdaptiveIntegrator
+    n, n_ngb = 1200, 32.0
+    tx, tv, tm, (x, v, m) = _clumps(n)
+    with ag.Context(0) as c:
+        ad = AdaptiveIntegrator(c, tx, tv, tm, q_f=0.5, theta=0.0, eps=1e-3, soft_pm=n_ngb)
+        c.sync()
+        for label, xs, vs, rows in [("start", x, v, np.arange(n))]:
+            hr = orc.pm_lengths(xs, n_ngb)
+            np.testing.assert_allclose(ad.h.cpu().numpy(), hr, rtol=1e-12)
+            ar = orc.direct_soft(xs, vs, m, hr, 1.0, rows)[0] + orc.pm_correction(xs, m, hr, n_ngb, 1.0)[rows]
+            err = rel_err(ad.a0.cpu().numpy()[rows], ar)
+            print(f"pm integrator {label}: max rel err {err.max():.2e}", flush=True)
+            assert np.max(err) <= 1e-4
+        for _ in range(2):
+            ad.step()
+        k = ad.step()
+        c.sync()
+        assert k > 0
+        xs, vs = ad.x.cpu().numpy(), ad.vpred.cpu().numpy()
+        rows = ad.active[:k].cpu().numpy().astype(np.int64)
+        hr = orc.pm_lengths(xs, n_ngb)
+        np.testing.assert_allclose(ad.h.cpu().numpy(), hr, rtol=1e-12)
+        ar = orc.direct_soft(xs, vs, m, hr, 1.0, rows)[0] + orc.pm_correction(xs, m, hr, n_ngb, 1.0)[rows]
+        err = rel_err(ad.a0.cpu().numpy()[rows], ar)
+        print(f"pm integrator step 3 ({k} active): max rel err {err.max():.2e}", flush=True)
+        assert np.max(err) <= 1e-4
+
+
 @pytest.mark.parametrize("predictor", ["jerk", "linear"])
 def test_adaptive_resume_bit_exact(ag, predictor):
     from paper_2010_13792_amd.driver import AdaptiveIntegrator
