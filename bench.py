@@ -45,10 +45,10 @@ PEAK_HBM_GBS = 8000.0
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "59ee4403bd67e705a8b906200f0bcaa4399f4c0cd630f41545300670b549d905",
+    "src_sha256": "1046151030b50a4773eee641d0cf920fcb4144ee88ca60435941961479041cc3",
     "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64},
-    "fetch_kib": 344219.8, "write_kib": 221067.2,
-    "fetch_factor": 1048576.0 / 524304.8, "write_factor": 1.0,
+    "fetch_kib": 340379.3, "write_kib": 221056.4,
+    "fetch_factor": 1048576.0 / 524305.2, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);

@@ -1039,7 +1039,9 @@ struct KnnLds : WalkLds<2> {
     double r2;
     int win_lo, win_hi;   // sorted positions taken before the walk
 };
-template <int kCap>
+// kDensity: the Price & Monaghan density mode of finish (its own kernel, so
+// that the plain lists keep their register budget)
+template <int kCap, bool kDensity = false>
 struct KnnPolicy {
     static constexpr bool kSkipEmpty = false;
     static constexpr bool kOpenAll = true;
@@ -1181,13 +1183,14 @@ struct KnnPolicy {
     // Also Omega = -(32 / (9 N)) sum_i u_i w'(u_i) at h.
     __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
         const int64_t row = T.perm[p];
-        if (kCap != 64 || !(O.pm_ngb > 0.0)) {
+        if constexpr (!kDensity) {
             O.knn_out[row] = sqrt(A.L[kCap - 1]);
             return;
         }
+        // the distances once (-1 for the leading -inf dummies)
         double r[kCap];
 #pragma unroll
-        for (int i = 0; i < kCap; ++i) r[i] = A.L[i] > 0.0 ? sqrt(A.L[i]) : (A.L[i] == 0.0 ? 0.0 : -1.0);
+        for (int i = 0; i < kCap; ++i) r[i] = A.L[i] >= 0.0 ? sqrt(A.L[i]) : -1.0;
         const double target = 3.0 * O.pm_ngb / 32.0;
         auto sums = [&](double h, double& sd) {
             const double hinv = 1.0 / h;
@@ -1204,7 +1207,8 @@ struct KnnPolicy {
             return sw;
         };
         const bool all = (int64_t)O.knn_k >= O.knn_n - 1;
-        double hi = r[kCap - 1] > 0.0 ? r[kCap - 1] : 1.0, sd = 0.0;
+        const double rl = r[kCap - 1];
+        double hi = rl > 0.0 ? rl : 1.0, sd = 0.0;
         double shi = sums(hi, sd);
         if (all)
             for (int g = 0; g < 64 && shi < target; ++g) shi = sums(hi *= 2.0, sd);
@@ -2196,8 +2200,8 @@ int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int 
     const unsigned grid = (unsigned)walk_grid(c, mg);
     int32_t* qctr = c->grp_hdr.as<int32_t>() + 8;
     if (step == 0) {
-        hipLaunchKernelGGL((k_walk<KnnPolicy<64>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
-                           qctr, 0.f, 0.f, 0.f, 0.f);
+        hipLaunchKernelGGL((k_walk<KnnPolicy<64, true>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr,
+                           O, qctr, 0.f, 0.f, 0.f, 0.f);
     } else {
         hipLaunchKernelGGL((k_walk<PmPolicy<2>, kOpen>), dim3(grid), dim3(kW), 0, c->stream, make_tree(c), Gr, O,
                            qctr, 0.f, 0.f, 0.f, 0.f);
