@@ -605,20 +605,21 @@ extern "C" int ag_grav_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, co
     return check_launch("grav backward");
 }
 
-static int check_pm(ag_ctx* c, double n_ngb, bool lengths) {
+// state shared by the three calls; a null n_ngb skips its range check
+static int check_pm(ag_ctx* c, const double* n_ngb, bool lengths) {
     AG_TRY(check_ctx(c));
     if (!c->built) return ag_fail(AG_ESTATE, "Price & Monaghan terms before a tree build");
     if (c->batched) return ag_fail(AG_ESTATE, "Price & Monaghan terms are not available for a batched tree");
     if (c->tree_box > 0.0) return ag_fail(AG_ESTATE, "Price & Monaghan terms need open boundaries");
     if (!lengths && !c->tree_soft)
         return ag_fail(AG_ESTATE, "the tree was built without per-particle softening lengths");
-    if (!(n_ngb > 32.0 / 3.0) || !(n_ngb < 32.0 * (double)c->n / 3.0))
+    if (n_ngb && (!(*n_ngb > 32.0 / 3.0) || !(*n_ngb < 32.0 * (double)c->n / 3.0)))
         return ag_fail(AG_EINVAL, "n_ngb must lie in (32/3, 32 n/3)");
     return AG_OK;
 }
 
 extern "C" int ag_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega) {
-    AG_TRY(check_pm(c, n_ngb, true));
+    AG_TRY(check_pm(c, &n_ngb, true));
     if (!h || !omega) return ag_fail(AG_EINVAL, "h and omega must be non-null");
     DeviceGuard g(c->device);
     AG_TRY(ag_ensure(c->pm_brk, (size_t)c->n * (3 * sizeof(double) + sizeof(int32_t)) + kPmSteps * sizeof(int)));
@@ -650,7 +651,7 @@ extern "C" int ag_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega) 
 }
 
 extern "C" int ag_pm_factors(ag_ctx* c, double n_ngb, double G, const double* omega, double* z) {
-    AG_TRY(check_pm(c, n_ngb, false));
+    AG_TRY(check_pm(c, &n_ngb, false));
     if (!omega || !z) return ag_fail(AG_EINVAL, "omega and z must be non-null");
     if (!std::isfinite(G)) return ag_fail(AG_EINVAL, "G must be finite");
     DeviceGuard g(c->device);
@@ -659,10 +660,10 @@ extern "C" int ag_pm_factors(ag_ctx* c, double n_ngb, double G, const double* om
 }
 
 extern "C" int ag_pm_correct(ag_ctx* c, const double* z, double* acc) {
-    AG_TRY(check_pm(c, 16.0, false));
+    AG_TRY(check_pm(c, nullptr, false));
     if (!z || !acc) return ag_fail(AG_EINVAL, "z and acc must be non-null");
     DeviceGuard g(c->device);
-    AG_TRY(ag_launch_pm_sum(c, 1, 16.0, 0.0, nullptr, z, nullptr, acc));
+    AG_TRY(ag_launch_pm_sum(c, 1, 0.0, 0.0, nullptr, z, nullptr, acc));
     return check_launch("Price & Monaghan correction");
 }
 

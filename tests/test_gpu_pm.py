@@ -146,6 +146,11 @@ def test_arguments(ag):
             c.pm_correct(zeros)
         assert e.value.code == ag.AG_ESTATE
         h, _ = c.pm_lengths(32.0)
+        _build(ag, c, x, m, h=h.cpu().numpy())
+        for bad in (5.0, float("nan")):
+            with pytest.raises(ag.AgError) as e:
+                c.pm_factors(bad, G, zeros)
+            assert e.value.code == ag.AG_EINVAL
         c.set_periodic(4.0)
         _build(ag, c, np.mod(x, 4.0), m, h=h.cpu().numpy())
         with pytest.raises(ag.AgError) as e:
