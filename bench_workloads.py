@@ -99,19 +99,23 @@ def run_direct(args):
 
 
 # ---------------------------------------------------------------------------
-def run_adaptive(args):
+def adaptive_comparison(n=1 << 22, steps=200, qs=(0.0, 0.125, 0.25, 0.5, 1.0), step_shift=0,
+                        predictors=("jerk",), rebuild_every=1, mac_offset=1, n_rows=4096, checkpoints=None,
+                        graph=False):
+    """The C3 comparison: the integrator of ``driver.py`` on 64 Plummer clumps
+    for every q_f of ``qs`` (0 = every step), eager steps with per-phase GPU
+    timing; the median error of the force in use against the oracle on
+    ``n_rows`` sampled particles at ``checkpoints``.  With ``graph`` each run
+    is repeated with one captured step replayed for every step (its total
+    time only; a graph carries no phase timing)."""
     import oracle
-    n = 1 << 22 if args.n == (1 << 20) else args.n
-    steps = args.adaptive_steps
-    # the offset-aware opening test (the default): with the plain one the fresh
-    # tree force on this clustered set sits at the 1e-3 median bound itself
-    mac_offset = args.mac_offset
     log(f"adaptive: generating {n} particles in 64 clumps")
     x, v, m, _ = workloads.clumps(n, seed=3)
     tx, tv, tm = _t(x), _t(v), _t(m)
     rng = np.random.default_rng(33)
-    rows = rng.choice(n, 4096, replace=False)
-    checkpoints = sorted({0, steps // 4, steps // 2, 3 * steps // 4, steps})
+    rows = rng.choice(n, n_rows, replace=False)
+    if checkpoints is None:
+        checkpoints = sorted({0, steps // 4, steps // 2, 3 * steps // 4, steps})
     # targets per walk group: autotuned on the initial particle set, all active
     with ag.Context(0) as c:
         c.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
@@ -132,17 +136,16 @@ def run_adaptive(args):
                                           reps=2, use_cache=False)
         del acc, jerk, tid
     log(f"adaptive: autotuner picked {tuned}")
-    qs = [float(q) for q in args.q_list.split(",")]
-    preds = [p.strip() for p in args.predictors.split(",") if p.strip()]
+    preds = list(predictors)
     plan = [(preds[0], q) for q in qs] + [(p, q) for p in preds[1:] for q in qs if q > 0]
     runs = {}
     for pred, q in plan:
+        kw = dict(q_f=q, theta=0.7, eps=1e-3, eta=0.01, rebuild_every=rebuild_every, step_shift=step_shift,
+                  predictor=pred)
         with ag.Context(0) as c:
             c.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
             c.set_option(ag.AG_OPT_GROUP_TARGETS, tuned["group_targets"])
-            integ = AdaptiveIntegrator(c, tx, tv, tm, q_f=q, theta=0.7, eps=1e-3, eta=0.01,
-                                       rebuild_every=args.rebuild_every, step_shift=args.step_shift,
-                                       predictor=pred)
+            integ = AdaptiveIntegrator(c, tx, tv, tm, **kw)
             c.sync()
             errs = {}
 
@@ -162,11 +165,11 @@ def run_adaptive(args):
             active_hist = []
             for s in range(1, steps + 1):
                 ev0.record()
-                k = integ.step()
+                integ.step()
                 ev1.record()
                 torch.cuda.synchronize()
                 total_ms += ev0.elapsed_time(ev1)
-                active_hist.append(k)
+                active_hist.append(integ.active_count())
                 if s in checkpoints:
                     check(s)
             ph = c.timing_read(reset=True)
@@ -176,7 +179,28 @@ def run_adaptive(args):
                                "walk_ms": ph["walk"]["ms"], "build_ms": ph["build"]["ms"],
                                "total_ms": total_ms, "median_rel_err_used_force": errs, "dt_step": integ.dt,
                                "tick_bin": integ.tick_bin, "mean_active_fraction": float(np.mean(active_hist)) / n}
-            log(f"adaptive {pred} q_f={q}: {runs[(pred, q)]}")
+            final = {k: integ.state()[k] for k in ("x", "acc")}
+        if graph and (pred == "jerk" or pred == "none") and rebuild_every == 1:
+            # the same run with one captured step replayed (no host work per step)
+            s_ = torch.cuda.Stream()
+            with ag.Context(0, s_) as c:
+                c.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
+                c.set_option(ag.AG_OPT_GROUP_TARGETS, tuned["group_targets"])
+                g = AdaptiveIntegrator(c, tx, tv, tm, **kw)
+                g.capture()                  # runs step 1 eagerly
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                c.sync()
+                e0.record(s_)
+                for _ in range(steps - 1):
+                    g.step()
+                e1.record(s_)
+                s_.synchronize()
+                same = all(torch.equal(g.state()[k], final[k]) for k in final)
+                runs[(pred, q)].update(graph_ms_per_step=e0.elapsed_time(e1) / (steps - 1),
+                                       graph_matches_eager=bool(same))
+                log(f"adaptive {pred} q_f={q}: graph replay {e0.elapsed_time(e1) / (steps - 1):.3f} ms/step, "
+                    f"final state equal to the eager run: {same}")
+        log(f"adaptive {pred} q_f={q}: {runs[(pred, q)]}")
     base = runs.get((preds[0], 0.0))
     res = {}
     for (pred, q), r in runs.items():
@@ -187,16 +211,27 @@ def run_adaptive(args):
                             gravity_speedup=base["gravity_ms"] / r["gravity_ms"],
                             walk_speedup=base["walk_ms"] / r["walk_ms"],
                             total_speedup=base["total_ms"] / r["total_ms"])
+            if "graph_ms_per_step" in r and "graph_ms_per_step" in base:
+                res[key]["graph_total_speedup"] = base["graph_ms_per_step"] / r["graph_ms_per_step"]
     ok = {}
     for (pred, q), r in runs.items():
         if max(r["median_rel_err_used_force"].values()) <= 1e-3:
             ok[pred] = max(ok.get(pred, 0.0), q)
     return {"workload": f"64 Plummer clumps N={n}, {steps} steps, theta=0.7 eps=1e-3 eta=0.01",
-            "metric": "adaptive vs every-step speedup", "rebuild_every": args.rebuild_every,
+            "metric": "adaptive vs every-step speedup", "rebuild_every": rebuild_every,
             "mac_offset": mac_offset, "autotune": {"best": tuned, "walk_ms": tune_table},
-            "step_shift": args.step_shift, "predictors": preds,
+            "step_shift": step_shift, "predictors": preds, "sampled_rows": n_rows, "checkpoints": checkpoints,
             "runs": res, "largest_q_f_within_1e-3": ok.get(preds[0]),
             "largest_q_f_within_1e-3_by_predictor": ok}
+
+
+def run_adaptive(args):
+    n = 1 << 22 if args.n == (1 << 20) else args.n
+    qs = [float(q) for q in args.q_list.split(",")]
+    preds = [p.strip() for p in args.predictors.split(",") if p.strip()]
+    return adaptive_comparison(n=n, steps=args.adaptive_steps, qs=qs, step_shift=args.step_shift,
+                               predictors=preds, rebuild_every=args.rebuild_every, mac_offset=args.mac_offset,
+                               graph=args.graph)
 
 
 # ---------------------------------------------------------------------------

@@ -109,13 +109,18 @@ const char *ag_last_error(void);
  *                              (mass and quadrupole) if its extent is at most
  *                              1 / value times its distance to the nearest
  *                              image point of the lattice [4]
+ *   AG_OPT_ADJOINT_OPEN        ag_grav_backward opens nodes at value % of its
+ *                              theta, in both of its walks: their kernels (the
+ *                              tidal tensor and J, 1/r^3) are one derivative
+ *                              deeper than the force's, and at 75 % they meet
+ *                              the force's error bound at the caller's theta [75]
  * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30, 0..1,
- * 1..64, 1..64) give AG_EINVAL. */
+ * 1..64, 1..64, 10..100) give AG_EINVAL. */
 enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3, AG_OPT_MAC_OFFSET = 4,
-       AG_OPT_GROUP_TARGETS = 5, AG_OPT_EWALD_OPEN = 6 };
+       AG_OPT_GROUP_TARGETS = 5, AG_OPT_EWALD_OPEN = 6, AG_OPT_ADJOINT_OPEN = 7 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
-/* Per-particle softening lengths (Sec. 4: the paper's runs soften each
+/* Per-particle softening lengths (Sec. 3: the paper's runs soften each
  * element with its own, adaptive, length; here the lengths are given, for
  * instance by ag_neighbour_lengths from the previous tree).
  * h (n,) device FP64 in input order, copied at once (the caller may reuse
@@ -150,7 +155,7 @@ int ag_set_softening(ag_ctx *ctx, int64_t n, const double *h);
  * turns the test off.  alpha < 0 or non-finite: AG_EINVAL. */
 int ag_set_relative_opening(ag_ctx *ctx, double alpha, int64_t n, const double *acc);
 
-/* Adaptive softening lengths from the built tree (Sec. 4: each element's
+/* Adaptive softening lengths from the built tree (Sec. 3: each element's
  * softening follows the local spacing; here that spacing is the distance to
  * the k-th nearest other particle).  h (n,) device FP64, written in input
  * order: h_i = sqrt(d2_k) with d2_k the k-th smallest of
@@ -159,14 +164,15 @@ int ag_set_relative_opening(ag_ctx *ctx, double alpha, int64_t n, const double *
  * built in a periodic box (ag_set_periodic before the build) takes every
  * difference at its nearest image, d - box rint(d / box), from the
  * positions as the tree holds them (wrapped into [0, box)).  The output can
- * go straight to ag_set_softening (scaled first, if wanted).  Needs a tree
- * from ag_tree_build; a batched tree gives AG_ESTATE.  k must be in [1, 64]
- * and below n (AG_EINVAL).  Coincident particles give h = 0. */
-int ag_neighbour_lengths(ag_ctx *ctx, int32_t k, double *h);
+ * go straight to ag_set_softening.  Each length is multiplied by scale
+ * (> 0 and finite; 1 gives the distance itself).  Needs a tree from
+ * ag_tree_build; a batched tree gives AG_ESTATE.  k must be in [1, 64] and
+ * below n (AG_EINVAL).  Coincident particles give h = 0. */
+int ag_neighbour_lengths(ag_ctx *ctx, int32_t k, double scale, double *h);
 
 /* Fully adaptive softening with the conservative correction of Price &
  * Monaghan (2007), the form of adaptive softening the paper's runs use
- * (Sec. 4).  Kernel: the cubic spline of support h, W(r, h) = 8/(pi h^3)
+ * (Sec. 3).  Kernel: the cubic spline of support h, W(r, h) = 8/(pi h^3)
  * w(r/h), w = 1 - 6u^2 + 6u^3 (u < 1/2), 2(1 - u)^3 (u < 1); psi(u)/h is
  * the potential of a unit mass spread by W (-1/r outside the support).
  * Open boundaries and an unbatched tree only (AG_ESTATE otherwise);
@@ -198,7 +204,15 @@ int ag_pm_factors(ag_ctx *ctx, double n_ngb, double G, const double *omega, doub
  * ag_pm_factors; z (n,) from it; coincident pairs add nothing. */
 int ag_pm_correct(ag_ctx *ctx, const double *z, double *acc);
 
-/* Periodic boundaries (Sec. 4: the periodic problem's gravity uses Ewald
+/* ag_pm_correct_add: the same correction ADDED to acc (n, 3), at the rows
+ * idx[0 .. *n_idx_dev) only (idx device int32, unique; the count is read
+ * on the device, as ag_adaptive_select leaves it), or at every row with
+ * idx = NULL.  Only the listed rows are walked, so an adaptive step pays
+ * for the rows it refreshes.  The factors z must cover every particle. */
+int ag_pm_correct_add(ag_ctx *ctx, const double *z, const int32_t *idx, const int64_t *n_idx_dev,
+                      double *acc);
+
+/* Periodic boundaries (Sec. 3.4: the periodic problem's gravity uses Ewald
  * sums, its jerk only the nearest image).  box > 0 makes every later
  * ag_grav_eval, ag_grav_eval_batched and (ewald = 0 only) ag_grav_direct on
  * this context periodic in a cube of side box; positions may lie in any
@@ -206,23 +220,28 @@ int ag_pm_correct(ag_ctx *ctx, const double *z, double *acc);
  * evaluating a tree built under another box gives AG_ESTATE (rebuild it).
  *   ewald = 0: every pair at its nearest image, d -> d - box * rint(d / box)
  *              per axis, for g, j and T alike.
+ *              The tree opening test then also requires, per axis, all of a
+ *              node's box to lie within half a box side of all of the
+ *              group's box, so every particle of an accepted node shares
+ *              one image.
  *   ewald = 1: g and T of all periodic images with a neutralising uniform
  *              background (Ewald's method, alpha = 2 / box), j at the
- *              nearest image.  A second walk adds the images' correction
- *              dg = g_periodic - g_single_image (and dT) from a table built
- *              on the device (spacing box / 64, second-order expansion
- *              about the nearest table point); nodes act through mass and
- *              quadrupole under an opening angle (AG_OPT_EWALD_OPEN) taken
- *              against the nearest image point, and a group no wider than
- *              box / 256 sums the correction once and expands it to second
- *              order about its centre.  The sum includes each
+ *              nearest image.  The forward walk takes every source at its
+ *              image about an origin o (the group centre rounded to a
+ *              multiple of box / 2, so no node below the root straddles
+ *              the planes where those images change); a second walk adds
+ *              the images' correction dg = g_periodic - g_single_image (and
+ *              dT) at the same images, from a table built on the device
+ *              (spacing box / 64, second-order expansion about the nearest
+ *              table point).  There nodes act through mass and quadrupole
+ *              under an opening angle (AG_OPT_EWALD_OPEN) taken against the
+ *              group's other images, and a group whose half extent is at
+ *              most box / 32 sums the correction once and expands it to
+ *              second order about its centre.  The sum includes each
  *              target's own images (its background tide, 4 pi G m / 3 box^3
  *              per axis).  ag_grav_direct then returns AG_ESTATE (theta = 0
  *              in ag_grav_eval is the direct sum).
- * The tree opening test also requires, per axis, all of a node's box to lie
- * within half a box side of all of the group's box, so every particle of an
- * accepted node shares one image.  box = 0 (with ewald = 0) restores open
- * boundaries, the default.  While a box is set, ag_grav_backward returns
+ * box = 0 (with ewald = 0) restores open boundaries, the default.  While a box is set, ag_grav_backward returns
  * AG_ESTATE.  box < 0 or not finite, ewald not 0 or 1, or ewald with
  * box = 0 give AG_EINVAL. */
 int ag_set_periodic(ag_ctx *ctx, double box, int32_t ewald);
@@ -233,7 +252,14 @@ int ag_set_periodic(ag_ctx *ctx, double box, int32_t ewald);
  * need must already exist (run the same sequence once before capturing).
  * ag_graph_replay launches the recorded sequence again on the stream with
  * the same pointers (refill the input arrays in place between replays).
- * Timing must be disabled while capturing. */
+ * Timing must be disabled while capturing.  A call that would grow a
+ * library buffer during the capture fails with AG_ESTATE; if a later call
+ * outside the capture grows one (moving it), ag_graph_replay refuses with
+ * AG_ESTATE until the sequence is captured again.  Calls whose count or
+ * time changes from step to step take it from device memory
+ * (ag_grav_eval_dev, ag_grav_timestep_dev, ag_grav_predict_age, with the
+ * count from ag_adaptive_select), so one captured adaptive step can be
+ * replayed for every later step. */
 int ag_graph_begin(ag_ctx *ctx);
 int ag_graph_end(ag_ctx *ctx);
 int ag_graph_replay(ag_ctx *ctx);
@@ -319,6 +345,17 @@ int ag_tree_export(ag_ctx *ctx, int64_t cap, int32_t *link, double *moments, int
 int ag_grav_eval(ag_ctx *ctx, const int32_t *active_idx, int64_t n_active, double theta,
                  double eps, double G, double *acc, double *jerk, double *tidal);
 
+/* ag_grav_eval with the number of listed rows read on the device: rows
+ * active_idx[0 .. *n_active_dev), the count ag_adaptive_select writes (the
+ * update set of Eq. 4 never visits the host).  active_idx and n_active_dev
+ * are device memory, active_idx of capacity n (the tree's); a count outside
+ * [0, n] raises the device flag (AG_EDEVICE at the next sync) and evaluates
+ * nothing.  n_total (device int64, nullable) gains the count: a running
+ * total of force evaluations kept on the device.  Otherwise as ag_grav_eval,
+ * and free of host synchronisation, so it may be captured in a graph. */
+int ag_grav_eval_dev(ag_ctx *ctx, const int32_t *active_idx, const int64_t *n_active_dev, double theta,
+                     double eps, double G, double *acc, double *jerk, double *tidal, int64_t *n_total);
+
 /* Batched variant after ag_tree_build_batched: active_idx lists global rows;
  * each target only feels its own system. */
 int ag_grav_eval_batched(ag_ctx *ctx, const int32_t *active_idx, int64_t n_active,
@@ -348,6 +385,13 @@ int ag_grav_timestep(ag_ctx *ctx, int64_t n, const int32_t *idx, int64_t n_idx,
                      const double *tidal, double eta, double dt_max, int32_t k_max,
                      double *dt_grav, int8_t *bin);
 
+/* ag_grav_timestep over rows idx[0 .. *n_idx_dev) (idx device int32 of
+ * capacity n, the count in device memory; a count outside [0, n] raises the
+ * device flag and processes none). */
+int ag_grav_timestep_dev(ag_ctx *ctx, int64_t n, const int32_t *idx, const int64_t *n_idx_dev,
+                         const double *tidal, double eta, double dt_max, int32_t k_max, double *dt_grav,
+                         int8_t *bin);
+
 /* Force-age bookkeeping (Eq. 3, Eq. 4) for all n particles at the start of
  * a step.  Time is integer: one tick is the step of bin tick_bin, so bin k
  * spans 2^(tick_bin - min(k, tick_bin)) ticks.  For each particle:
@@ -372,10 +416,21 @@ int ag_kick_drift(ag_ctx *ctx, int64_t n, double *x, double *v, const double *ac
  * multiply-add).  Equal to repeated application of Eq. 6 in exact arithmetic,
  * since the jerk only changes at a force update.  Rows with mask[i] == 0 are
  * left untouched (mask may be NULL = all rows).  acc_out may alias acc0.
- * jerk = NULL selects no predictor (acc_out = acc0, the ablation of Sec. 4.1;
+ * jerk = NULL selects no predictor (acc_out = acc0, the ablation of Sec. 3.1;
  * t0 may then be NULL too). */
 int ag_grav_predict(ag_ctx *ctx, int64_t n, const uint8_t *mask, const double *acc0,
                     const double *jerk, const double *t0, double t, double *acc_out);
+
+/* The Eq. 6 predictor with the elapsed time taken from the force-age
+ * counter of Eq. 3: acc_out_i = acc0_i + jerk_i (age_i * tick), age_ticks
+ * (n,) int64 the counters as ag_adaptive_select leaves them (the ticks since
+ * the row's last force update, 0 for the rows updated now) and tick the
+ * length of one tick.  With integer times (t = k tick, t0 = k0 tick) this
+ * equals ag_grav_predict bit for bit, and it takes no per-step argument, so
+ * a captured step replays unchanged.  mask, jerk = NULL and aliasing as in
+ * ag_grav_predict. */
+int ag_grav_predict_age(ag_ctx *ctx, int64_t n, const uint8_t *mask, const double *acc0, const double *jerk,
+                        const int64_t *age_ticks, double tick, double *acc_out);
 
 /* Deepest force log the polynomial predictor takes. */
 #define AG_PRED_MAX_DEPTH 4
@@ -393,6 +448,12 @@ int ag_grav_predict(ag_ctx *ctx, int64_t n, const uint8_t *mask, const double *a
  * ag_sync (AG_EDEVICE). */
 int ag_force_log(ag_ctx *ctx, int64_t n, const int32_t *idx, int64_t n_idx, int32_t depth,
                  const double *acc0, double t, double *hist_a, double *hist_t, int32_t *hist_n);
+
+/* ag_force_log over rows idx[0 .. *n_idx_dev) (idx device int32 of
+ * capacity n, the count in device memory; a count outside [0, n] raises the
+ * device flag and logs none). */
+int ag_force_log_dev(ag_ctx *ctx, int64_t n, const int32_t *idx, const int64_t *n_idx_dev, int32_t depth,
+                     const double *acc0, double t, double *hist_a, double *hist_t, int32_t *hist_n);
 
 /* Polynomial predictor (Sec. 2.2) from a log written by ag_force_log with
  * the same n and depth: for every row, the interpolating polynomial through
@@ -416,8 +477,10 @@ int ag_grav_predict_poly(ag_ctx *ctx, int64_t n, const uint8_t *mask, int32_t de
  *   dL/dx_k = G m_k sum_j J(d_kj) w_j + T_k w_k,   J = f I + D d d^T,
  *   dL/dm_k = -G sum_j f(r_kj) d_kj . w_j,         D = f'(r)/r,
  * with j running over the listed rows.  The sums are evaluated by a second
- * tree walk over the vector charges w (their sum and first moment per node,
- * under the same opening test); T_k comes from a fresh forward walk.
+ * tree walk over the vector charges w (per node their sum W0, first moment
+ * W1 = sum w y^T and second moment W2 = sum w y y^T about the node's centre
+ * of mass); T_k comes from a fresh forward walk.  Both walks open nodes at
+ * theta times AG_OPT_ADJOINT_OPEN / 100 (default 0.75 theta).
  * dLdx (n,3) and dLdm (n,) are overwritten for all n rows. */
 int ag_grav_backward(ag_ctx *ctx, const int32_t *active_idx, int64_t n_active,
                      const double *w, double theta, double eps, double G,

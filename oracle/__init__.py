@@ -10,7 +10,7 @@ routine of the same name in ``oracle.c`` (built into ``liboracle.so`` by
   the jerk (the particle discretisation of the jerk integral, Eq. 5) and the
   tidal tensor (whose Frobenius norm enters Eq. 7); optionally in a periodic
   cube with every pair at its nearest image (how the paper treats the jerk
-  of periodic problems, Sec. 4); :func:`direct_soft` with a softening length
+  of periodic problems, Sec. 3.4); :func:`direct_soft` with a softening length
   per particle (each pair takes the mean of its two kernels), and
   :func:`neighbour_length`, the k-th neighbour distance those lengths
   follow (plain numpy).

@@ -221,7 +221,7 @@ void orc_abs_scale(int64_t n, const double *x, const double *m, double eps, doub
 /* ---- per-particle softening ---------------------------------------------- */
 /*
  * Softening lengths that differ between particles (the paper's fully
- * adaptive softening, Sec. 4, with the lengths given): the pair kernel is
+ * adaptive softening, Sec. 3, with the lengths given): the pair kernel is
  * the mean of the two particles' kernels, so the pair force stays equal and
  * opposite,
  *   f_ij = (f(r, h_i) + f(r, h_j)) / 2,   D_ij = (D(r, h_i) + D(r, h_j)) / 2,
@@ -404,7 +404,7 @@ void orc_ewald_unit(int64_t n, const double *d, double L, double alpha, int nr, 
 }
 
 /* Periodic direct sum with Ewald's method for g and T (the jerk keeps the
- * nearest image only, as Sec. 4 states for its periodic problem):
+ * nearest image only, as Sec. 3.4 states for its periodic problem):
  *   g_i = G sum_{j != i} m_j f(r) d_ij  +  G sum_j m_j dg(d_ij),
  *   T_i = (nearest-image T)             +  G sum_j m_j dT(d_ij),
  * d_ij the nearest image; the softened single-image terms as in

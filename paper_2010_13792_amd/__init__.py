@@ -39,6 +39,7 @@ ENTRY_POINTS = [
     "ag_kick_drift", "ag_set_option", "ag_graph_begin", "ag_graph_end", "ag_graph_replay",
     "ag_force_log", "ag_grav_predict_poly", "ag_set_periodic", "ag_set_softening",
     "ag_neighbour_lengths", "ag_set_relative_opening", "ag_pm_lengths", "ag_pm_factors", "ag_pm_correct",
+    "ag_grav_eval_dev", "ag_grav_timestep_dev", "ag_grav_predict_age", "ag_pm_correct_add", "ag_force_log_dev",
 ]
 AG_PRED_MAX_DEPTH = 4
 AG_OPT_WALK_WAVES_PER_CU = 1
@@ -47,6 +48,7 @@ AG_OPT_GROUP_SPAN = 3
 AG_OPT_MAC_OFFSET = 4
 AG_OPT_GROUP_TARGETS = 5
 AG_OPT_EWALD_OPEN = 6
+AG_OPT_ADJOINT_OPEN = 7
 PHASES = ["build", "groups", "walk", "direct", "step", "adjoint", "ewald", "neighbour"]
 
 
@@ -90,6 +92,10 @@ def load_library(path: str = LIB_PATH):
         "ag_tree_export": [P, I64, P, P, P],
         "ag_grav_eval": [P, P, I64, D, D, D, P, P, P],
         "ag_grav_eval_batched": [P, P, I64, D, D, D, P, P, P],
+        "ag_grav_eval_dev": [P, P, P, D, D, D, P, P, P, P],
+        "ag_grav_timestep_dev": [P, I64, P, P, P, D, D, I32, P, P],
+        "ag_grav_predict_age": [P, I64, P, P, P, P, D, P],
+        "ag_pm_correct_add": [P, P, P, P, P],
         "ag_grav_direct": [P, I64, P, P, P, P, I64, D, D, ctypes.c_int, P, P, P],
         "ag_grav_timestep": [P, I64, P, I64, P, D, D, I32, P, P],
         "ag_adaptive_select": [P, I64, P, P, I64, I32, D, P, P, P, D],
@@ -97,7 +103,7 @@ def load_library(path: str = LIB_PATH):
         "ag_set_option": [P, I32, I64],
         "ag_set_periodic": [P, D, I32],
         "ag_set_softening": [P, I64, P],
-        "ag_neighbour_lengths": [P, I32, P],
+        "ag_neighbour_lengths": [P, I32, D, P],
         "ag_pm_lengths": [P, D, P, P],
         "ag_pm_factors": [P, D, D, P, P],
         "ag_pm_correct": [P, P, P],
@@ -105,6 +111,7 @@ def load_library(path: str = LIB_PATH):
         "ag_graph_begin": [P], "ag_graph_end": [P], "ag_graph_replay": [P],
         "ag_grav_predict": [P, I64, P, P, P, P, D, P],
         "ag_force_log": [P, I64, P, I64, I32, P, D, P, P, P],
+        "ag_force_log_dev": [P, I64, P, P, I32, P, D, P, P, P],
         "ag_grav_predict_poly": [P, I64, P, I32, I32, P, P, P, D, P],
         "ag_grav_backward": [P, P, I64, P, D, D, D, P, P],
         "ag_timing_enable": [P, ctypes.c_int],
@@ -171,6 +178,11 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    @property
+    def stream(self) -> torch.cuda.Stream:
+        """The torch stream the context's calls are ordered on."""
+        return self._stream
 
     def set_stream(self, stream: torch.cuda.Stream):
         self._stream = stream
@@ -251,6 +263,18 @@ class Context:
                   _ptr(jerk, torch.float64, (3,), "jerk", n),
                   _ptr(tidal, torch.float64, (6,), "tidal", n)))
 
+    def grav_eval_dev(self, active_idx, n_active_dev, theta, eps, G, acc, jerk, tidal, n_total=None):
+        """Tree gravity at rows active_idx[:n_active_dev[0]], the count read
+        on the device (no host synchronisation); n_total (int64 (1,)) gains
+        the count."""
+        n = self.n
+        _check(_lib.ag_grav_eval_dev(self._h, _ptr(active_idx, torch.int32, None, "active_idx", n),
+                                     _ptr(n_active_dev, torch.int64, None, "n_active_dev", 1), float(theta),
+                                     float(eps), float(G), _ptr(acc, torch.float64, (3,), "acc", n),
+                                     _ptr(jerk, torch.float64, (3,), "jerk", n),
+                                     _ptr(tidal, torch.float64, (6,), "tidal", n),
+                                     _ptr(n_total, torch.int64, None, "n_total", 1)))
+
     def grav_eval_batched(self, active_idx, theta, eps, G, acc, jerk, tidal):
         self.grav_eval(active_idx, theta, eps, G, acc, jerk, tidal, batched=True)
 
@@ -274,6 +298,16 @@ class Context:
                                      float(dt_max), int(k_max),
                                      _ptr(dt_grav, torch.float64, None, "dt_grav", n),
                                      _ptr(bins, torch.int8, None, "bin", n)))
+
+    def grav_timestep_dev(self, tidal, eta, dt_max, k_max, dt_grav, bins, idx, n_idx_dev):
+        """Eq. 7 timestep and bin at rows idx[:n_idx_dev[0]] (count on the device)."""
+        n = tidal.shape[0]
+        _check(_lib.ag_grav_timestep_dev(self._h, n, _ptr(idx, torch.int32, None, "idx", n),
+                                         _ptr(n_idx_dev, torch.int64, None, "n_idx_dev", 1),
+                                         _ptr(tidal, torch.float64, (6,), "tidal"), float(eta),
+                                         float(dt_max), int(k_max),
+                                         _ptr(dt_grav, torch.float64, None, "dt_grav", n),
+                                         _ptr(bins, torch.int8, None, "bin", n)))
 
     def adaptive_select(self, tf_ticks, bins, step_ticks, tick_bin, q_f, active_idx, n_active_dev,
                         t0=None, t=0.0):
@@ -312,6 +346,15 @@ class Context:
                                     _ptr(t0, torch.float64, None, "t0", n), float(t),
                                     _ptr(acc_out, torch.float64, (3,), "acc_out", n)))
 
+    def grav_predict_age(self, acc0, jerk, age_ticks, tick, acc_out, mask=None):
+        """Eq. 6 with t - t0 = age_ticks * tick (the Eq. 3 force-age counters)."""
+        n = acc0.shape[0]
+        _check(_lib.ag_grav_predict_age(self._h, n, _ptr(mask, torch.uint8, None, "mask", n),
+                                        _ptr(acc0, torch.float64, (3,), "acc0"),
+                                        _ptr(jerk, torch.float64, (3,), "jerk", n),
+                                        _ptr(age_ticks, torch.int64, None, "age_ticks", n), float(tick),
+                                        _ptr(acc_out, torch.float64, (3,), "acc_out", n)))
+
     def set_softening(self, h=None):
         """Per-particle softening lengths (device float64 (n,)); None clears."""
         if h is None:
@@ -329,15 +372,15 @@ class Context:
         _check(_lib.ag_set_relative_opening(self._h, float(alpha), acc.shape[0],
                                             _ptr(acc, torch.float64, (3,), "acc")))
 
-    def neighbour_lengths(self, k: int, out=None):
-        """Distance of every particle to its k-th nearest other particle, from
-        the built tree (device float64 (n,), input order)."""
+    def neighbour_lengths(self, k: int, out=None, scale: float = 1.0):
+        """Distance of every particle to its k-th nearest other particle, times
+        ``scale``, from the built tree (device float64 (n,), input order)."""
         n = self.n
         if out is None:
             if n is None:
                 raise AgError(AG_ESTATE, "neighbour lengths before a tree build")
             out = torch.empty(n, dtype=torch.float64, device=torch.device("cuda", self.device))
-        _check(_lib.ag_neighbour_lengths(self._h, int(k), _ptr(out, torch.float64, None, "out", n)))
+        _check(_lib.ag_neighbour_lengths(self._h, int(k), float(scale), _ptr(out, torch.float64, None, "out", n)))
         return out
 
     def _pm_out(self, out, shape, name):
@@ -370,6 +413,16 @@ class Context:
         _check(_lib.ag_pm_correct(self._h, _ptr(z, torch.float64, None, "z", self.n), pa))
         return out
 
+    def pm_correct_add(self, z, acc, idx=None, n_idx_dev=None):
+        """Add the correction's acceleration to acc (n, 3) at rows
+        idx[:n_idx_dev[0]] (count on the device), or at every row."""
+        if (idx is None) != (n_idx_dev is None):
+            raise ValueError("idx and n_idx_dev go together")
+        _check(_lib.ag_pm_correct_add(self._h, _ptr(z, torch.float64, None, "z", self.n),
+                                      _ptr(idx, torch.int32, None, "idx"),
+                                      _ptr(n_idx_dev, torch.int64, None, "n_idx_dev", 1),
+                                      _ptr(acc, torch.float64, (3,), "acc", self.n)))
+
     def set_periodic(self, box: float, ewald: bool = False):
         """Periodic cube of side ``box`` (0: open): nearest-image pairs, or
         with ``ewald`` the full periodic g and T (j stays nearest-image)."""
@@ -392,6 +445,13 @@ class Context:
         k = n if idx is None else idx.shape[0]
         _check(_lib.ag_force_log(self._h, n, _ptr(idx, torch.int32, None, "idx"), k, depth,
                                  _ptr(acc0, torch.float64, (3,), "acc0", n), float(t), pa, pt, pn))
+
+    def force_log_dev(self, acc0, t, hist_a, hist_t, hist_n, idx, n_idx_dev):
+        """force_log at rows idx[:n_idx_dev[0]] (count on the device)."""
+        depth, n, pa, pt, pn = self._log_ptrs(hist_a, hist_t, hist_n)
+        _check(_lib.ag_force_log_dev(self._h, n, _ptr(idx, torch.int32, None, "idx", n),
+                                     _ptr(n_idx_dev, torch.int64, None, "n_idx_dev", 1), depth,
+                                     _ptr(acc0, torch.float64, (3,), "acc0", n), float(t), pa, pt, pn))
 
     def grav_predict_poly(self, hist_a, hist_t, hist_n, order, t, acc_out, mask=None):
         depth, n, pa, pt, pn = self._log_ptrs(hist_a, hist_t, hist_n)

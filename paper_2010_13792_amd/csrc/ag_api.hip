@@ -20,9 +20,15 @@ int ag_fail(int code, const char* fmt, ...) {
 
 extern "C" const char* ag_last_error(void) { return g_err; }
 
-int ag_ensure(DevBuf& b, size_t bytes) {
+int ag_ensure(ag_ctx* c, DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (b.bytes >= bytes) return AG_OK;
+    // a captured graph holds the buffers' addresses: none may move while
+    // capturing, and a later move invalidates the graph (see ag_graph_replay)
+    if (c->capturing)
+        return ag_fail(AG_ESTATE, "a library buffer must grow to %zu bytes during graph capture: run the same "
+                       "sequence once before capturing", bytes);
+    ++c->alloc_epoch;
     if (b.p) {
         hipError_t e = hipFree(b.p);
         b.p = nullptr;
@@ -163,9 +169,9 @@ extern "C" int ag_create(ag_ctx** out, int device, void* stream) {
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     DeviceGuard g(device);
-    int r = ag_ensure(c->stats, 4 * sizeof(uint64_t));
-    if (r == AG_OK) r = ag_ensure(c->dflags, 4 * sizeof(int32_t));
-    if (r == AG_OK) r = ag_ensure(c->tree_hdr, kTreeHdrBytes);
+    int r = ag_ensure(c, c->stats, 4 * sizeof(uint64_t));
+    if (r == AG_OK) r = ag_ensure(c, c->dflags, 4 * sizeof(int32_t));
+    if (r == AG_OK) r = ag_ensure(c, c->tree_hdr, kTreeHdrBytes);
     if (r != AG_OK) {
         ag_destroy(c);
         return r;
@@ -341,6 +347,16 @@ extern "C" int ag_grav_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double
     return check_launch("grav eval");
 }
 
+extern "C" int ag_grav_eval_dev(ag_ctx* c, const int32_t* idx, const int64_t* n_act_dev, double theta,
+                                double eps, double G, double* acc, double* jerk, double* tidal, int64_t* n_total) {
+    AG_TRY(check_eval_args(c, idx, c ? c->n : 0, theta, eps, G));
+    if (c->batched) return ag_fail(AG_ESTATE, "tree was built batched: use ag_grav_eval_batched");
+    if (!idx || !n_act_dev) return ag_fail(AG_EINVAL, "active_idx and n_active_dev must be non-null");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_eval(c, idx, c->n, theta, eps, G, acc, jerk, tidal, n_act_dev, n_total));
+    return check_launch("grav eval dev");
+}
+
 extern "C" int ag_grav_eval_batched(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta,
                                     double eps, double G, double* acc, double* jerk, double* tidal) {
     AG_TRY(check_eval_args(c, idx, n_act, theta, eps, G));
@@ -388,6 +404,21 @@ extern "C" int ag_grav_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_
     DeviceGuard g(c->device);
     AG_TRY(ag_launch_timestep(c, n, idx, n_idx, tidal, eta, dt_max, k_max, dt, bin));
     return check_launch("grav timestep");
+}
+
+extern "C" int ag_grav_timestep_dev(ag_ctx* c, int64_t n, const int32_t* idx, const int64_t* n_idx_dev,
+                                    const double* tidal, double eta, double dt_max, int32_t k_max, double* dt,
+                                    int8_t* bin) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (!idx || !n_idx_dev) return ag_fail(AG_EINVAL, "idx and n_idx_dev must be non-null");
+    if (!tidal || !dt || !bin) return ag_fail(AG_EINVAL, "tidal, dt_grav and bin must be non-null");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return ag_fail(AG_EINVAL, "eta must be positive and finite");
+    if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return ag_fail(AG_EINVAL, "dt_max must be positive and finite");
+    if (k_max < 0 || k_max > 62) return ag_fail(AG_EINVAL, "k_max must be in [0, 62]");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_timestep(c, n, idx, n, tidal, eta, dt_max, k_max, dt, bin, n_idx_dev));
+    return check_launch("grav timestep dev");
 }
 
 extern "C" int ag_adaptive_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin,
@@ -441,6 +472,10 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
             if (value < 1 || value > 64) return ag_fail(AG_EINVAL, "Ewald opening value must be in [1, 64]");
             c->ewald_open = (int)value;
             return AG_OK;
+        case AG_OPT_ADJOINT_OPEN:
+            if (value < 10 || value > 100) return ag_fail(AG_EINVAL, "adjoint opening percentage must be in [10, 100]");
+            c->adj_open = (int)value;
+            return AG_OK;
         case AG_OPT_MAC_OFFSET:
             if (value != 0 && value != 1) return ag_fail(AG_EINVAL, "opening-test offset flag must be 0 or 1");
             c->mac_offset = (int)value;
@@ -464,7 +499,7 @@ extern "C" int ag_set_softening(ag_ctx* c, int64_t n, const double* h) {
     }
     if (n < 0 || n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n must be in [0, 2^30]");
     DeviceGuard g(c->device);
-    AG_TRY(ag_ensure(c->soft_h, (size_t)n * sizeof(double)));
+    AG_TRY(ag_ensure(c, c->soft_h, (size_t)n * sizeof(double)));
     AG_HIP(hipMemcpyAsync(c->soft_h.p, h, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
@@ -496,7 +531,7 @@ extern "C" int ag_set_relative_opening(ag_ctx* c, double alpha, int64_t n, const
     }
     if (n < 0 || n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n must be in [0, 2^30]");
     DeviceGuard g(c->device);
-    AG_TRY(ag_ensure(c->rel_a, (size_t)n * sizeof(float)));
+    AG_TRY(ag_ensure(c, c->rel_a, (size_t)n * sizeof(float)));
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_rel_norm, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, acc, c->rel_a.as<float>(),
@@ -539,12 +574,16 @@ extern "C" int ag_graph_end(ag_ctx* c) {
     c->graph = gr;
     c->graph_exec = nullptr;
     AG_HIP(hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0));
+    c->graph_epoch = c->alloc_epoch;
     return AG_OK;
 }
 
 extern "C" int ag_graph_replay(ag_ctx* c) {
     AG_TRY(check_ctx(c));
     if (!c->graph_exec) return ag_fail(AG_ESTATE, "no captured graph");
+    if (c->alloc_epoch != c->graph_epoch)
+        return ag_fail(AG_ESTATE, "a library buffer was reallocated after the capture (a later call needed more "
+                       "scratch): capture the sequence again");
     DeviceGuard g(c->device);
     AG_HIP(hipGraphLaunch(c->graph_exec, c->stream));
     return AG_OK;
@@ -561,6 +600,17 @@ extern "C" int ag_grav_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const 
     return check_launch("grav predict");
 }
 
+extern "C" int ag_grav_predict_age(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0, const double* j,
+                                   const int64_t* age_ticks, double tick, double* out) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (!a0 || !out || (j && !age_ticks)) return ag_fail(AG_EINVAL, "null pointer argument");
+    if (!std::isfinite(tick)) return ag_fail(AG_EINVAL, "tick must be finite");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_predict_age(c, n, mask, a0, j, age_ticks, tick, out));
+    return check_launch("grav predict age");
+}
+
 extern "C" int ag_force_log(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx, int32_t depth,
                             const double* a0, double t, double* ha, double* ht, int32_t* hn) {
     AG_TRY(check_ctx(c));
@@ -575,6 +625,19 @@ extern "C" int ag_force_log(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_
     DeviceGuard g(c->device);
     AG_TRY(ag_launch_force_log(c, n, idx, n_idx, depth, a0, t, ha, ht, hn));
     return check_launch("force log");
+}
+
+extern "C" int ag_force_log_dev(ag_ctx* c, int64_t n, const int32_t* idx, const int64_t* n_idx_dev, int32_t depth,
+                                const double* a0, double t, double* ha, double* ht, int32_t* hn) {
+    AG_TRY(check_ctx(c));
+    if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
+    if (n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n exceeds 2^30");
+    if (depth < 1 || depth > AG_PRED_MAX_DEPTH) return ag_fail(AG_EINVAL, "depth must be in [1, AG_PRED_MAX_DEPTH]");
+    if (!idx || !n_idx_dev || !a0 || !ha || !ht || !hn) return ag_fail(AG_EINVAL, "null pointer argument");
+    if (!std::isfinite(t)) return ag_fail(AG_EINVAL, "t must be finite");
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_force_log(c, n, idx, n, depth, a0, t, ha, ht, hn, n_idx_dev));
+    return check_launch("force log dev");
 }
 
 extern "C" int ag_grav_predict_poly(ag_ctx* c, int64_t n, const uint8_t* mask, int32_t depth, int32_t order,
@@ -622,7 +685,7 @@ extern "C" int ag_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega) 
     AG_TRY(check_pm(c, &n_ngb, true));
     if (!h || !omega) return ag_fail(AG_EINVAL, "h and omega must be non-null");
     DeviceGuard g(c->device);
-    AG_TRY(ag_ensure(c->pm_brk, (size_t)c->n * (3 * sizeof(double) + sizeof(int32_t)) + kPmSteps * sizeof(int)));
+    AG_TRY(ag_ensure(c, c->pm_brk, (size_t)c->n * (3 * sizeof(double) + sizeof(int32_t)) + kPmSteps * sizeof(int)));
     // each step counts in a slot of its own (slot 0: the rows the list pass
     // leaves to the sum walk)
     int* cnt = reinterpret_cast<int*>(c->pm_brk.as<double>() + 3 * c->n);
@@ -667,14 +730,26 @@ extern "C" int ag_pm_correct(ag_ctx* c, const double* z, double* acc) {
     return check_launch("Price & Monaghan correction");
 }
 
-extern "C" int ag_neighbour_lengths(ag_ctx* c, int32_t k, double* h) {
+extern "C" int ag_pm_correct_add(ag_ctx* c, const double* z, const int32_t* idx, const int64_t* n_idx_dev,
+                                 double* acc) {
+    AG_TRY(check_pm(c, nullptr, false));
+    if (!z || !acc) return ag_fail(AG_EINVAL, "z and acc must be non-null");
+    if (idx && !n_idx_dev) return ag_fail(AG_EINVAL, "n_idx_dev must be non-null with idx");
+    DeviceGuard g(c->device);
+    if (idx) AG_TRY(ag_launch_pm_sum(c, 1, 0.0, 0.0, nullptr, z, nullptr, acc, idx, n_idx_dev));
+    else AG_TRY(ag_launch_pm_sum(c, 1, 0.0, 0.0, nullptr, z, nullptr, acc, nullptr, nullptr, true));
+    return check_launch("Price & Monaghan correction (added)");
+}
+
+extern "C" int ag_neighbour_lengths(ag_ctx* c, int32_t k, double scale, double* h) {
     AG_TRY(check_ctx(c));
     if (!c->built) return ag_fail(AG_ESTATE, "neighbour lengths before a tree build");
     if (c->batched) return ag_fail(AG_ESTATE, "neighbour lengths are not available for a batched tree");
     if (k < 1 || k > 64) return ag_fail(AG_EINVAL, "k must be in [1, 64]");
     if ((int64_t)k >= c->n) return ag_fail(AG_EINVAL, "k must be below the number of particles");
     if (!h) return ag_fail(AG_EINVAL, "h must be non-null");
+    if (!(scale > 0.0) || !std::isfinite(scale)) return ag_fail(AG_EINVAL, "scale must be positive and finite");
     DeviceGuard g(c->device);
-    AG_TRY(ag_launch_knn(c, k, h));
+    AG_TRY(ag_launch_knn(c, k, scale, h));
     return check_launch("neighbour lengths");
 }

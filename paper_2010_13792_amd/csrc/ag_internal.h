@@ -82,6 +82,9 @@ struct ag_ctx {
     bool tree_soft = false;       // the current tree carries them
     int group_cap = 64;
     bool capturing = false;
+    uint64_t alloc_epoch = 0;     // bumped by every (re)allocation of a context buffer
+    uint64_t graph_epoch = 0;     // alloc_epoch when the graph was captured
+    int adj_open = 75;            // adjoint walks open nodes at adj_open % of theta
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 
@@ -152,7 +155,8 @@ struct ag_ctx {
     int64_t host_n_nodes = -1;    // cached after a synchronising read
 };
 
-int ag_ensure(DevBuf& b, size_t bytes);
+// grow-only device buffer of the context (AG_ESTATE while capturing a graph)
+int ag_ensure(ag_ctx* c, DevBuf& b, size_t bytes);
 void ag_release(DevBuf& b);
 
 // Records a start event on construction and a stop event on destruction on
@@ -173,7 +177,7 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
                      double* acc, double* jerk, double* tidal);
 int ag_launch_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx,
                        const double* tidal, double eta, double dt_max, int32_t k_max,
-                       double* dt, int8_t* bin);
+                       double* dt, int8_t* bin, const int64_t* n_dev = nullptr);
 int ag_launch_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin, int64_t step_ticks,
                      int32_t tick_bin, double q_f, int32_t* active_idx, int64_t* n_active_dev,
                      double* t0, double t);
@@ -181,26 +185,37 @@ int ag_launch_kick_drift(ag_ctx* c, int64_t n, double* x, double* v, const doubl
                          double dt_drift);
 int ag_launch_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0,
                       const double* j, const double* t0, double t, double* out);
+int ag_launch_predict_age(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0, const double* j,
+                          const int64_t* age, double tick, double* out);
 int ag_launch_force_log(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx, int32_t depth,
-                        const double* a0, double t, double* ha, double* ht, int32_t* hn);
+                        const double* a0, double t, double* ha, double* ht, int32_t* hn,
+                        const int64_t* n_dev = nullptr);
 int ag_launch_predict_poly(ag_ctx* c, int64_t n, const uint8_t* mask, int32_t depth, int32_t order,
                            const double* ha, const double* ht, const int32_t* hn, double t, double* out);
 int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
                     int32_t n_sys, const int64_t* sys_offsets, int32_t n_leaf);
 int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m);
 int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps,
-                   double G, double* acc, double* jerk, double* tidal);
-int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out);
+                   double G, double* acc, double* jerk, double* tidal, const int64_t* n_dev = nullptr,
+                   int64_t* n_total = nullptr);
+int ag_launch_knn(ag_ctx* c, int32_t k, double scale, double* h_out);
 constexpr int kPmSteps = 257;   // sum walk steps of the lengths (slot 0 unused) and their counters
 int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int step, int64_t n_left);
+// mode 0: Z of every particle into z_out; mode 1: the correction, written to
+// acc for every row (idx null; added with `add`) or added to acc at rows
+// idx[0 .. *n_dev)
 int ag_launch_pm_sum(ag_ctx* c, int mode, double n_ngb, double G, const double* omega, const double* z,
-                     double* z_out, double* acc);
+                     double* z_out, double* acc, const int32_t* idx = nullptr, const int64_t* n_dev = nullptr,
+                     bool add = false);
 int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w,
                        double theta, double eps, double G, double* dLdx, double* dLdm);
 // exclusive scan of n int32 counts into out (n+1 entries; out[n] = total) on c->stream
 int ag_scan_i32(ag_ctx* c, const int32_t* in, int32_t* out, int64_t n);
-// active rows -> ascending sorted positions and walk groups; returns upper bound of groups
-int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max_groups);
+// active rows -> ascending sorted positions and walk groups; returns upper bound of groups.
+// With n_dev set the list's length is read on the device (n_act is then its
+// capacity) and, with n_total set, added to *n_total on the device.
+int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max_groups, const int64_t* n_dev,
+                      int64_t* n_total);
 
 // ---------------------------------------------------------------------------
 // device helpers

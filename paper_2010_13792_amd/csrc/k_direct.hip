@@ -181,7 +181,7 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
     int64_t chunk = (n + nsplit - 1) / nsplit;
     chunk = (chunk + kT - 1) / kT * kT;
     nsplit = (n + chunk - 1) / chunk;
-    AG_TRY(ag_ensure(c->direct_part, (size_t)nsplit * kParts * (size_t)n_act * sizeof(double)));
+    AG_TRY(ag_ensure(c, c->direct_part, (size_t)nsplit * kParts * (size_t)n_act * sizeof(double)));
     double* part = c->direct_part.as<double>();
     PhaseScope phase(c, AG_PHASE_DIRECT);
     dim3 grid((unsigned)tblocks, (unsigned)nsplit);

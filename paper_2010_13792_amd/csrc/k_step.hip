@@ -41,10 +41,18 @@ __device__ __forceinline__ int tidal_bin(double n2, double eta, double dt_max, i
     return k > k_max ? k_max : k;
 }
 
-__global__ void k_timestep(int64_t n_rows, const int32_t* __restrict__ idx, int64_t n,
-                           const double* __restrict__ tidal, double eta, double sqrt_eta,
+// rows idx[0 .. n_rows), or with n_dev set idx[0 .. *n_dev) (a count outside
+// [0, n_rows] raises the flag and processes none)
+__global__ void k_timestep(int64_t n_rows, const int64_t* __restrict__ n_dev, const int32_t* __restrict__ idx,
+                           int64_t n, const double* __restrict__ tidal, double eta, double sqrt_eta,
                            double dt_max, int k_max, double* __restrict__ dt,
                            int8_t* __restrict__ bin, int32_t* __restrict__ flags) {
+    if (n_dev) {
+        const int64_t v = *n_dev;
+        const bool bad = v < 0 || v > n_rows;
+        if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flags, AGF_BADINDEX);
+        n_rows = bad ? 0 : v;
+    }
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_rows;
          k += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = idx ? (int64_t)idx[k] : k;
@@ -132,13 +140,42 @@ __global__ void k_predict(int64_t n, const uint8_t* __restrict__ mask, const dou
     }
 }
 
+// The same with t - t0 taken from the force-age counter of Eq. 3: a row's
+// counter holds the ticks since its last force update, so t - t0 = age * tick
+// (exact: an integer times a power of two).
+__global__ void k_predict_age(int64_t n, const uint8_t* __restrict__ mask, const double* __restrict__ a0,
+                              const double* __restrict__ j, const int64_t* __restrict__ age, double tick,
+                              double* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (mask && !mask[i]) continue;
+        if (!j) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[3 * i + c] = a0[3 * i + c];
+            continue;
+        }
+        double dt = (double)age[i] * tick;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double jd = j[3 * i + c] * dt;
+            out[3 * i + c] = a0[3 * i + c] + jd;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Polynomial predictor (Sec. 2.2): a log of each row's last `depth` fresh
 // forces, slot-major (slot 0 newest): hist_a (depth, n, 3), hist_t (depth, n)
 // ---------------------------------------------------------------------------
-__global__ void k_force_log(int64_t n_rows, const int32_t* __restrict__ idx, int64_t n, int depth,
-                            const double* __restrict__ a0, double t, double* __restrict__ ha,
+__global__ void k_force_log(int64_t n_rows, const int64_t* __restrict__ n_dev, const int32_t* __restrict__ idx,
+                            int64_t n, int depth, const double* __restrict__ a0, double t, double* __restrict__ ha,
                             double* __restrict__ ht, int32_t* __restrict__ hn, int32_t* __restrict__ flags) {
+    if (n_dev) {   // the count on the device (outside [0, n_rows]: flag, none)
+        const int64_t v = *n_dev;
+        const bool bad = v < 0 || v > n_rows;
+        if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flags, AGF_BADINDEX);
+        n_rows = bad ? 0 : v;
+    }
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_rows;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = idx ? (int64_t)idx[k] : k;
@@ -315,7 +352,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply2(const int32_t* __r
 int ag_scan_i32(ag_ctx* c, const int32_t* in, int32_t* out, int64_t n) {
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;
     if (ntiles < 1) ntiles = 1;
-    AG_TRY(ag_ensure(c->scan_tmp, (size_t)ntiles * sizeof(int32_t)));
+    AG_TRY(ag_ensure(c, c->scan_tmp, (size_t)ntiles * sizeof(int32_t)));
     int32_t* ts = c->scan_tmp.as<int32_t>();
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, c->stream, in, n, ts);
     if (ntiles <= (int64_t)kScanThreads * kScanTopItems) {
@@ -329,9 +366,9 @@ int ag_scan_i32(ag_ctx* c, const int32_t* in, int32_t* out, int64_t n) {
 }
 
 int ag_launch_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx, const double* tidal,
-                       double eta, double dt_max, int32_t k_max, double* dt, int8_t* bin) {
+                       double eta, double dt_max, int32_t k_max, double* dt, int8_t* bin, const int64_t* n_dev) {
     PhaseScope phase(c, AG_PHASE_STEP);
-    hipLaunchKernelGGL(k_timestep, dim3(grid_for(n_idx)), dim3(kThreads), 0, c->stream, n_idx, idx, n,
+    hipLaunchKernelGGL(k_timestep, dim3(grid_for(n_idx)), dim3(kThreads), 0, c->stream, n_idx, n_dev, idx, n,
                        tidal, eta, sqrt(eta), dt_max, (int)k_max, dt, bin, c->dflags.as<int32_t>());
     return AG_OK;
 }
@@ -345,9 +382,9 @@ int ag_launch_kick_drift(ag_ctx* c, int64_t n, double* x, double* v, const doubl
 }
 
 int ag_launch_force_log(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx, int32_t depth,
-                        const double* a0, double t, double* ha, double* ht, int32_t* hn) {
+                        const double* a0, double t, double* ha, double* ht, int32_t* hn, const int64_t* n_dev) {
     PhaseScope phase(c, AG_PHASE_STEP);
-    hipLaunchKernelGGL(k_force_log, dim3(grid_for(n_idx)), dim3(kThreads), 0, c->stream, n_idx, idx, n,
+    hipLaunchKernelGGL(k_force_log, dim3(grid_for(n_idx)), dim3(kThreads), 0, c->stream, n_idx, n_dev, idx, n,
                        (int)depth, a0, t, ha, ht, hn, c->dflags.as<int32_t>());
     return AG_OK;
 }
@@ -364,8 +401,8 @@ int ag_launch_select(ag_ctx* c, int64_t n, int64_t* tf, const int8_t* bin, int64
                      int32_t tick_bin, double q_f, int32_t* active_idx, int64_t* n_active_dev,
                      double* t0, double t) {
     PhaseScope phase(c, AG_PHASE_STEP);
-    AG_TRY(ag_ensure(c->sel_flag, (size_t)n * sizeof(int32_t)));
-    AG_TRY(ag_ensure(c->sel_off, (size_t)(n + 1) * sizeof(int32_t)));
+    AG_TRY(ag_ensure(c, c->sel_flag, (size_t)n * sizeof(int32_t)));
+    AG_TRY(ag_ensure(c, c->sel_off, (size_t)(n + 1) * sizeof(int32_t)));
     int32_t* flag = c->sel_flag.as<int32_t>();
     int32_t* off = c->sel_off.as<int32_t>();
     hipLaunchKernelGGL(k_select, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, tf, bin, step_ticks,
@@ -380,5 +417,13 @@ int ag_launch_predict(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a
                       const double* t0, double t, double* out) {
     PhaseScope phase(c, AG_PHASE_STEP);
     hipLaunchKernelGGL(k_predict, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, mask, a0, j, t0, t, out);
+    return AG_OK;
+}
+
+int ag_launch_predict_age(ag_ctx* c, int64_t n, const uint8_t* mask, const double* a0, const double* j,
+                          const int64_t* age, double tick, double* out) {
+    PhaseScope phase(c, AG_PHASE_STEP);
+    hipLaunchKernelGGL(k_predict_age, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, mask, a0, j, age, tick,
+                       out);
     return AG_OK;
 }

@@ -1028,25 +1028,25 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     // than n_leaf particles (or are system-prefix cells)
     const int64_t max_nodes = n + (int64_t)(AG_MAX_LEVEL + 1) * (n / (n_leaf + 1) + n_sys) + 1;
 
-    AG_TRY(ag_ensure(c->keys[0], n * 8)); AG_TRY(ag_ensure(c->keys[1], n * 8));
-    AG_TRY(ag_ensure(c->vals[0], n * 4)); AG_TRY(ag_ensure(c->vals[1], n * 4));
+    AG_TRY(ag_ensure(c, c->keys[0], n * 8)); AG_TRY(ag_ensure(c, c->keys[1], n * 8));
+    AG_TRY(ag_ensure(c, c->vals[0], n * 4)); AG_TRY(ag_ensure(c, c->vals[1], n * 4));
     const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
-    AG_TRY(ag_ensure(c->sort_hist, (size_t)(256 * nblocks + 256 + 1) * 4));
-    AG_TRY(ag_ensure(c->pos_off, (size_t)(256 * (int64_t)nblocks + 1 > n + 1 ? 256 * (int64_t)nblocks + 1 : n + 1) * 4));
-    AG_TRY(ag_ensure(c->perm, n * 4)); AG_TRY(ag_ensure(c->rank, n * 4));
-    AG_TRY(ag_ensure(c->spos, n * 32)); AG_TRY(ag_ensure(c->svel, n * 32)); AG_TRY(ag_ensure(c->svf, n * 16));
-    AG_TRY(ag_ensure(c->cdig, n * 4)); AG_TRY(ag_ensure(c->pos_cnt, (n + 1) * 4));
-    AG_TRY(ag_ensure(c->nd_com, max_nodes * 32)); AG_TRY(ag_ensure(c->nd_lo, max_nodes * 16));
-    AG_TRY(ag_ensure(c->nd_hi, max_nodes * 16)); AG_TRY(ag_ensure(c->nd_link, max_nodes * 16));
-    AG_TRY(ag_ensure(c->nd_mp, max_nodes * 64)); AG_TRY(ag_ensure(c->nd_64, max_nodes * kM64 * 8));
-    AG_TRY(ag_ensure(c->in_list, max_nodes * 4)); AG_TRY(ag_ensure(c->in_cnt, (n + 1) * 4));
-    AG_TRY(ag_ensure(c->in_off, (n + 1) * 4));
-    AG_TRY(ag_ensure(c->sys_off, (n_sys + 1) * 8)); AG_TRY(ag_ensure(c->sys_root, (n_sys + 1) * 4));
+    AG_TRY(ag_ensure(c, c->sort_hist, (size_t)(256 * nblocks + 256 + 1) * 4));
+    AG_TRY(ag_ensure(c, c->pos_off, (size_t)(256 * (int64_t)nblocks + 1 > n + 1 ? 256 * (int64_t)nblocks + 1 : n + 1) * 4));
+    AG_TRY(ag_ensure(c, c->perm, n * 4)); AG_TRY(ag_ensure(c, c->rank, n * 4));
+    AG_TRY(ag_ensure(c, c->spos, n * 32)); AG_TRY(ag_ensure(c, c->svel, n * 32)); AG_TRY(ag_ensure(c, c->svf, n * 16));
+    AG_TRY(ag_ensure(c, c->cdig, n * 4)); AG_TRY(ag_ensure(c, c->pos_cnt, (n + 1) * 4));
+    AG_TRY(ag_ensure(c, c->nd_com, max_nodes * 32)); AG_TRY(ag_ensure(c, c->nd_lo, max_nodes * 16));
+    AG_TRY(ag_ensure(c, c->nd_hi, max_nodes * 16)); AG_TRY(ag_ensure(c, c->nd_link, max_nodes * 16));
+    AG_TRY(ag_ensure(c, c->nd_mp, max_nodes * 64)); AG_TRY(ag_ensure(c, c->nd_64, max_nodes * kM64 * 8));
+    AG_TRY(ag_ensure(c, c->in_list, max_nodes * 4)); AG_TRY(ag_ensure(c, c->in_cnt, (n + 1) * 4));
+    AG_TRY(ag_ensure(c, c->in_off, (n + 1) * 4));
+    AG_TRY(ag_ensure(c, c->sys_off, (n_sys + 1) * 8)); AG_TRY(ag_ensure(c, c->sys_root, (n_sys + 1) * 4));
     const int64_t inner_bound = max_nodes - n;   // inner nodes never exceed this
-    AG_TRY(ag_ensure(c->lvl_list, (size_t)(inner_bound > 0 ? inner_bound : 1) * 4));
-    AG_TRY(ag_ensure(c->leaf_list, n * 4));   // at most one leaf starts at each position
-    AG_TRY(ag_ensure(c->child, (size_t)(inner_bound > 0 ? inner_bound : 1) * 32));
-    AG_TRY(ag_ensure(c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
+    AG_TRY(ag_ensure(c, c->lvl_list, (size_t)(inner_bound > 0 ? inner_bound : 1) * 4));
+    AG_TRY(ag_ensure(c, c->leaf_list, n * 4));   // at most one leaf starts at each position
+    AG_TRY(ag_ensure(c, c->child, (size_t)(inner_bound > 0 ? inner_bound : 1) * 32));
+    AG_TRY(ag_ensure(c, c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
 
     PhaseScope phase(c, AG_PHASE_BUILD);
     hipStream_t st = c->stream;
@@ -1104,7 +1104,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
 
     // 4. particle data into key order
     c->tree_soft = c->soft_n > 0;
-    if (c->tree_soft) AG_TRY(ag_ensure(c->soft_s, (size_t)n * sizeof(float)));
+    if (c->tree_soft) AG_TRY(ag_ensure(c, c->soft_s, (size_t)n * sizeof(float)));
     hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rank, x, v, m,
                        c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->box,
                        c->tree_soft ? c->soft_h.as<double>() : nullptr, c->soft_s.as<float>());

@@ -97,6 +97,7 @@ struct WalkOut {
     float ewald_theta;  // correction walk: opening angle against the nearest image point
     float ewald_grp;    // groups of at most this half extent sum the correction once
     double* knn_out;    // neighbour lengths (input order)
+    double knn_scale;   // ... each multiplied by this
     int knn_k;          // which neighbour
     int64_t knn_n;
     // Price & Monaghan terms (input order arrays)
@@ -114,6 +115,7 @@ struct WalkOut {
     const double* pm_z;
     double* pm_zout;
     double* pm_acc;
+    bool pm_add;        // correction: added to pm_acc (else written)
     double* dldx;       // adjoint outputs
     double* dldm;
     const double* tin;  // adjoint: tidal tensor rows of the charged targets
@@ -1184,7 +1186,7 @@ struct KnnPolicy {
     __device__ static void finish(const Tree& T, const WalkOut& O, const Acc& A, int p, const Target&) {
         const int64_t row = T.perm[p];
         if constexpr (!kDensity) {
-            O.knn_out[row] = sqrt(A.L[kCap - 1]);
+            O.knn_out[row] = O.knn_scale * sqrt(A.L[kCap - 1]);
             return;
         }
         // the distances once (-1 for the leading -inf dummies)
@@ -1380,6 +1382,10 @@ struct PmPolicy {
         } else if (kMode == 0) {
             const double C = 3.0 * O.pm_ngb / (4.0 * 3.14159265358979323846);
             O.pm_zout[row] = -(O.pm_G * A.m * A.h * A.h / (6.0 * C * O.pm_om[row])) * A.s;
+        } else if (O.pm_add) {
+            O.pm_acc[3 * row] += -A.ax / A.m;
+            O.pm_acc[3 * row + 1] += -A.ay / A.m;
+            O.pm_acc[3 * row + 2] += -A.az / A.m;
         } else {
             O.pm_acc[3 * row] = -A.ax / A.m;
             O.pm_acc[3 * row + 1] = -A.ay / A.m;
@@ -1778,9 +1784,23 @@ __global__ void k_fill0(int32_t* __restrict__ p, int64_t n) {
 // Active rows -> flags over sorted positions, without atomics: every listed
 // entry k stamps k + 1 at its position, then each entry checks that its own
 // stamp survived (a repeated row loses to one of its copies) and sets the flag.
-__global__ void k_mark_stamp(int64_t n_act, const int32_t* __restrict__ idx, int64_t n,
-                             const int32_t* __restrict__ rank, int32_t* __restrict__ stamp,
-                             int32_t* __restrict__ flags) {
+// The list's length is n_act, or, with n_dev set, the count stored at *n_dev
+// (at most n_act = n; a count outside [0, n] raises the flag and lists none).
+__device__ __forceinline__ int64_t list_len(int64_t n_act, const int64_t* __restrict__ n_dev) {
+    if (!n_dev) return n_act;
+    const int64_t v = *n_dev;
+    return (v < 0 || v > n_act) ? 0 : v;
+}
+
+__global__ void k_mark_stamp(int64_t n_act, const int64_t* __restrict__ n_dev, const int32_t* __restrict__ idx,
+                             int64_t n, const int32_t* __restrict__ rank, int32_t* __restrict__ stamp,
+                             int32_t* __restrict__ flags, int64_t* __restrict__ n_total) {
+    if (n_dev && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t v = *n_dev;
+        if (v < 0 || v > n_act) atomicOr(flags, AGF_BADINDEX);
+        else if (n_total) *n_total += v;   // running total of evaluations
+    }
+    n_act = list_len(n_act, n_dev);
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_act;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx[k];
@@ -1792,9 +1812,10 @@ __global__ void k_mark_stamp(int64_t n_act, const int32_t* __restrict__ idx, int
     }
 }
 
-__global__ void k_mark_check(int64_t n_act, const int32_t* __restrict__ idx, int64_t n,
-                             const int32_t* __restrict__ rank, const int32_t* __restrict__ stamp,
+__global__ void k_mark_check(int64_t n_act, const int64_t* __restrict__ n_dev, const int32_t* __restrict__ idx,
+                             int64_t n, const int32_t* __restrict__ rank, const int32_t* __restrict__ stamp,
                              int32_t* __restrict__ flag, int32_t* __restrict__ flags) {
+    n_act = list_len(n_act, n_dev);
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_act;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx[k];
@@ -1915,16 +1936,17 @@ int grid_for(int64_t n, int threads = 256) {
 
 }  // namespace
 
-int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max_groups) {
+int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max_groups, const int64_t* n_dev,
+                      int64_t* n_total) {
     const int64_t n = c->n;
     const int64_t mg = n_act + c->n_sys + 1;   // every group holds at least one target
-    AG_TRY(ag_ensure(c->act_flag, n * 4));
-    AG_TRY(ag_ensure(c->act_off, (n + 1) * 4));
-    AG_TRY(ag_ensure(c->act_pos, n * 4));
-    AG_TRY(ag_ensure(c->grp, mg * 16));
-    AG_TRY(ag_ensure(c->grp_hdr, (16 + AG_MAX_SYS + 1) * 4));
-    AG_TRY(ag_ensure(c->grp_cnt, (c->max_nodes + 1) * 4));
-    AG_TRY(ag_ensure(c->grp_off, (c->max_nodes + 1) * 4));
+    AG_TRY(ag_ensure(c, c->act_flag, n * 4));
+    AG_TRY(ag_ensure(c, c->act_off, (n + 1) * 4));
+    AG_TRY(ag_ensure(c, c->act_pos, n * 4));
+    AG_TRY(ag_ensure(c, c->grp, mg * 16));
+    AG_TRY(ag_ensure(c, c->grp_hdr, (16 + AG_MAX_SYS + 1) * 4));
+    AG_TRY(ag_ensure(c, c->grp_cnt, (c->max_nodes + 1) * 4));
+    AG_TRY(ag_ensure(c, c->grp_off, (c->max_nodes + 1) * 4));
     PhaseScope phase(c, AG_PHASE_GROUPS);
     hipStream_t st = c->stream;
     int32_t* flag = c->act_flag.as<int32_t>();
@@ -1933,9 +1955,9 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
     if (idx) {
         hipLaunchKernelGGL(k_fill0, dim3(grid_for(n)), dim3(256), 0, st, flag, n);
         // the scan output doubles as the stamp array until the scan runs
-        hipLaunchKernelGGL(k_mark_stamp, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, idx, n,
-                           c->rank.as<int32_t>(), off, c->dflags.as<int32_t>());
-        hipLaunchKernelGGL(k_mark_check, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, idx, n,
+        hipLaunchKernelGGL(k_mark_stamp, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, n_dev, idx, n,
+                           c->rank.as<int32_t>(), off, c->dflags.as<int32_t>(), n_total);
+        hipLaunchKernelGGL(k_mark_check, dim3(grid_for(n_act)), dim3(256), 0, st, n_act, n_dev, idx, n,
                            c->rank.as<int32_t>(), off, flag, c->dflags.as<int32_t>());
         AG_TRY(ag_scan_i32(c, flag, off, n));
         hipLaunchKernelGGL(k_compact_pos, dim3(grid_for(n)), dim3(256), 0, st, n, flag, off,
@@ -2106,7 +2128,7 @@ constexpr int kEwaldGroupDiv = 32;    // groups of half extent <= box / 32 sum o
 static int ewald_table(ag_ctx* c) {
     if (c->ewald_tab_box == c->box && c->ewald_tab.bytes) return AG_OK;
     const int np = (kEwaldNE + 1) * (kEwaldNE + 1) * (kEwaldNE + 1);
-    AG_TRY(ag_ensure(c->ewald_tab, (size_t)np * 5 * sizeof(float4)));
+    AG_TRY(ag_ensure(c, c->ewald_tab, (size_t)np * 5 * sizeof(float4)));
     hipLaunchKernelGGL(k_ewald_table, dim3((np + 127) / 128), dim3(128), 0, c->stream, c->box, kEwaldNE,
                        c->box / kEwaldPerBox, c->ewald_tab.as<float4>());
     c->ewald_tab_box = c->box;
@@ -2119,6 +2141,7 @@ static WalkOut make_out(ag_ctx* c, double G) {
     O.G = G;
     O.flags = c->dflags.as<int32_t>();
     O.iter_cap = c->max_nodes + c->n + 1024;
+    O.knn_scale = 1.0;
     O.small_node = c->small_node;
     O.mac_offset = c->mac_offset != 0;
     O.box = c->box;
@@ -2139,13 +2162,14 @@ static WalkOut make_out(ag_ctx* c, double G) {
 
 // distance of every particle to its k-th nearest other particle, by a walk
 // that opens every node and prunes by distance
-int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out) {
+int ag_launch_knn(ag_ctx* c, int32_t k, double scale, double* h_out) {
     int64_t mg = 0;
-    AG_TRY(ag_prepare_groups(c, nullptr, c->n, &mg));
+    AG_TRY(ag_prepare_groups(c, nullptr, c->n, &mg, nullptr, nullptr));
     Groups Gr{nullptr, c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
     WalkOut O = make_out(c, 1.0);
     O.stats = nullptr;
     O.knn_out = h_out;
+    O.knn_scale = scale;
     O.knn_k = k;
     O.knn_n = c->n;
     O.box = c->tree_box;   // nearest images in the box the tree was built in
@@ -2175,7 +2199,7 @@ int ag_launch_knn(ag_ctx* c, int32_t k, double* h_out) {
 int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int step, int64_t n_left) {
     int64_t mg = 0;
     int32_t* left = reinterpret_cast<int32_t*>(reinterpret_cast<int*>(c->pm_brk.as<double>() + 3 * c->n) + kPmSteps);
-    AG_TRY(ag_prepare_groups(c, step == 0 ? nullptr : left, step == 0 ? c->n : n_left, &mg));
+    AG_TRY(ag_prepare_groups(c, step == 0 ? nullptr : left, step == 0 ? c->n : n_left, &mg, nullptr, nullptr));
     Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
               c->grp_hdr.as<int32_t>()};
     WalkOut O = make_out(c, 1.0);
@@ -2211,10 +2235,11 @@ int ag_launch_pm_lengths(ag_ctx* c, double n_ngb, double* h, double* omega, int 
 
 // Price & Monaghan sums: Z (mode 0, z_out) or the correction (mode 1, acc)
 int ag_launch_pm_sum(ag_ctx* c, int mode, double n_ngb, double G, const double* omega, const double* z,
-                     double* z_out, double* acc) {
+                     double* z_out, double* acc, const int32_t* idx, const int64_t* n_dev, bool add) {
     int64_t mg = 0;
-    AG_TRY(ag_prepare_groups(c, nullptr, c->n, &mg));
-    Groups Gr{nullptr, c->grp.as<int4>(), c->grp_hdr.as<int32_t>()};
+    AG_TRY(ag_prepare_groups(c, idx, c->n, &mg, idx ? n_dev : nullptr, nullptr));
+    Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
+              c->grp_hdr.as<int32_t>()};
     WalkOut O = make_out(c, G);
     O.stats = nullptr;
     O.pm_ngb = n_ngb;
@@ -2224,6 +2249,7 @@ int ag_launch_pm_sum(ag_ctx* c, int mode, double n_ngb, double G, const double* 
     O.pm_z = z;
     O.pm_zout = z_out;
     O.pm_acc = acc;
+    O.pm_add = add || idx != nullptr;
     PhaseScope phase(c, AG_PHASE_NEIGHBOUR);
     const unsigned grid = (unsigned)walk_grid(c, mg);
     const Tree T = make_tree(c);
@@ -2238,9 +2264,9 @@ int ag_launch_pm_sum(ag_ctx* c, int mode, double n_ngb, double G, const double* 
 }
 
 int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, double eps, double G, double* acc,
-                   double* jerk, double* tidal) {
+                   double* jerk, double* tidal, const int64_t* n_dev, int64_t* n_total) {
     int64_t mg = 0;
-    AG_TRY(ag_prepare_groups(c, idx, n_act, &mg));
+    AG_TRY(ag_prepare_groups(c, idx, n_act, &mg, n_dev, n_total));
     Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
               c->grp_hdr.as<int32_t>()};
     const bool ewald = c->box > 0.0 && c->ewald;
@@ -2286,7 +2312,7 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
     }
     if (ewald && (acc || tidal)) {
         // what the periodic images add to g and T, at the same images
-        AG_TRY(ag_ensure(c->ewald_q, 8 * sizeof(int32_t)));
+        AG_TRY(ag_ensure(c, c->ewald_q, 8 * sizeof(int32_t)));
         PhaseScope phase(c, AG_PHASE_EWALD);
         hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, c->stream, c->ewald_q.as<int32_t>(), (int64_t)8);
         WalkOut E = O;
@@ -2300,16 +2326,20 @@ int ag_launch_eval(ag_ctx* c, const int32_t* idx, int64_t n_act, double theta, d
 
 // Adjoint of L = sum_k w_k . g_k:
 //   1. forward walk for T at the listed rows (the T_k w_k term);
-//   2. sorted weights (zero on unlisted rows) and their node moments W0, W1;
-//   3. adjoint walk over all n targets with the same opening test.
+//   2. sorted weights (zero on unlisted rows) and their node moments W0, W1, W2;
+//   3. adjoint walk over all n targets with the same opening test, both walks
+//      at theta * AG_OPT_ADJOINT_OPEN / 100.
 int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const double* w, double theta, double eps,
                        double G, double* dLdx, double* dLdm) {
     const int64_t n = c->n;
-    AG_TRY(ag_ensure(c->tmp_tidal, n * 6 * sizeof(double)));
-    AG_TRY(ag_ensure(c->wsorted, n * sizeof(double4)));
-    AG_TRY(ag_ensure(c->nd_w, c->max_nodes * kW64 * sizeof(double)));
-    AG_TRY(ag_ensure(c->nd_wf, c->max_nodes * 8 * sizeof(float4)));
+    AG_TRY(ag_ensure(c, c->tmp_tidal, n * 6 * sizeof(double)));
+    AG_TRY(ag_ensure(c, c->wsorted, n * sizeof(double4)));
+    AG_TRY(ag_ensure(c, c->nd_w, c->max_nodes * kW64 * sizeof(double)));
+    AG_TRY(ag_ensure(c, c->nd_wf, c->max_nodes * 8 * sizeof(float4)));
     double* tin = c->tmp_tidal.as<double>();
+    // both walks open nodes at a fraction of theta: their kernels (the tidal
+    // tensor and J, 1/r^3) are one derivative deeper than the force's
+    theta *= c->adj_open / 100.0;
     if (n_act > 0) AG_TRY(ag_launch_eval(c, idx, n_act, theta, eps, G, nullptr, nullptr, tin));
     // charges: the listed rows (flags of that evaluation), all rows, or none
     const int32_t* cflag = (n_act > 0 && !c->all_active) ? c->act_flag.as<int32_t>() : nullptr;
@@ -2332,7 +2362,7 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
                            c->nd_64.as<double>(),
                            c->nd_w.as<double>(), c->nd_wf.as<float4>());
     int64_t mg = 0;
-    AG_TRY(ag_prepare_groups(c, nullptr, n, &mg));   // every particle is a target
+    AG_TRY(ag_prepare_groups(c, nullptr, n, &mg, nullptr, nullptr));   // every particle is a target
     Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
               c->grp_hdr.as<int32_t>()};
     WalkOut O = make_out(c, G);

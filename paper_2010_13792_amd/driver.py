@@ -17,14 +17,17 @@ exact.  Bins deeper than the tick are clamped to it (updated every step).
 
 Step (kick-drift-kick):
   v += a dt/2;  x += v dt;  t += dt
-  select due particles (Eq. 3, Eq. 4), stamping t0 = t for them
+  select due particles (Eq. 3, Eq. 4); their number stays on the device
   tree rebuild (or refit every other step, see ``rebuild_every``) with the
   velocities predicted to time t (v + a dt/2)
   fresh g, j, T for the due particles; their dt_grav and bin
-  a = a0 + j (t - t0) for all particles (exact a0 for the due ones), or the
-  chosen variant
+  a = a0 + j (t - t0) for all particles (exact a0 for the due ones), with
+  t - t0 read from the force-age counter of Eq. 3, or the chosen variant
   v += a dt/2
 All arithmetic runs in the library's kernels; this module sequences calls.
+A step never waits for the device: the due rows are counted, grouped and
+evaluated on the device, so one step can be captured in a HIP graph
+(``capture``) and replayed for every later step.
 """
 from __future__ import annotations
 
@@ -73,6 +76,15 @@ class AdaptiveIntegrator:
             raise ValueError("soft_pm must be 0 or above 32/3, and not combined with soft_k")
         self.soft_k, self.soft_scale, self.soft_pm = int(soft_k), float(soft_scale), float(soft_pm)
         self.ctx = ctx
+        # every tensor operation of the integrator runs on the context's stream,
+        # after the caller's work on its own stream (which made x, v, m)
+        ctx.stream.wait_stream(torch.cuda.current_stream(x.device))
+        with torch.cuda.stream(ctx.stream):
+            self._setup(x, v, m, q_f, theta, eps, eta, G, n_leaf, rebuild_every, step_shift)
+
+    def _setup(self, x, v, m, q_f, theta, eps, eta, G, n_leaf, rebuild_every, step_shift):
+        ctx = self.ctx
+        soft_k, soft_pm = self.soft_k, self.soft_pm
         dev = x.device
         self.n = n = x.shape[0]
         self.x = x.clone()
@@ -91,11 +103,11 @@ class AdaptiveIntegrator:
         self.dt_grav = torch.zeros(n, dtype=torch.float64, device=dev)
         self.active = torch.zeros(n, dtype=torch.int32, device=dev)
         self.n_active = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.n_total = torch.zeros(1, dtype=torch.int64, device=dev)   # evaluations after the first
         self.vpred = torch.zeros_like(self.v)
         self.h = torch.zeros(n, dtype=torch.float64, device=dev) if soft_k > 0 or soft_pm > 0 else None
         if soft_pm > 0:
             self.omega, self.z = torch.zeros_like(self.h), torch.zeros_like(self.h)
-            self.corr = torch.zeros((n, 3), dtype=torch.float64, device=dev)
         self.scratch = torch.zeros_like(self.x)
         self.log = None
         if self.order is not None:
@@ -105,7 +117,7 @@ class AdaptiveIntegrator:
                         torch.zeros(n, dtype=torch.int32, device=dev))
         self.t = 0.0
         self.step_index = 0
-        self.evaluations = 0
+        self._graph = False
         # initial forces for everybody, then the time grid
         ctx.set_softening()
         ctx.tree_build(self.x, self.v, self.m, n_leaf)
@@ -114,7 +126,7 @@ class AdaptiveIntegrator:
             ctx.tree_build(self.x, self.v, self.m, n_leaf)
         ctx.set_relative_opening()   # no earlier force: the geometric test alone
         ctx.grav_eval(None, theta, eps, G, self.a0, self.jerk, self.tidal)
-        self._pm_correct(None)
+        self._pm_correct(None, None)
         ctx.grav_timestep(self.tidal, eta, 1.0, 60, self.dt_grav, self.bins)
         ctx.sync()
         dtg = self.dt_grav[torch.isfinite(self.dt_grav)]
@@ -126,7 +138,6 @@ class AdaptiveIntegrator:
         self.acc.copy_(self.a0)
         if self.log is not None:
             ctx.force_log(self.a0, 0.0, *self.log)
-        self.evaluations += n
         self._need_build = False
 
     def _lengths(self):
@@ -134,78 +145,121 @@ class AdaptiveIntegrator:
         if self.soft_pm > 0:
             self.ctx.pm_lengths(self.soft_pm, self.h, self.omega)
         else:
-            self.ctx.neighbour_lengths(self.soft_k, self.h)
-            if self.soft_scale != 1.0:
-                self.h.mul_(self.soft_scale)
+            self.ctx.neighbour_lengths(self.soft_k, self.h, scale=self.soft_scale)
         self.ctx.set_softening(self.h)
 
-    def _pm_correct(self, idx):
-        """Add the Price & Monaghan correction to the fresh forces of idx
-        (None: every particle)."""
+    def _pm_correct(self, idx, n_idx):
+        """Add the Price & Monaghan correction to the fresh forces of the rows
+        idx[:n_idx[0]] (None: every particle)."""
         if self.soft_pm <= 0:
             return
         self.ctx.pm_factors(self.soft_pm, self.G, self.omega, self.z)
-        self.ctx.pm_correct(self.z, self.corr)
-        if idx is None:
-            self.a0.add_(self.corr)
-        else:
-            rows = idx.long()
-            self.a0.index_add_(0, rows, self.corr.index_select(0, rows))
+        self.ctx.pm_correct_add(self.z, self.a0, idx, n_idx)
 
-    def step(self) -> int:
+    @property
+    def evaluations(self) -> int:
+        """Force evaluations so far, the first one included (synchronises)."""
+        return self.n + int(self.n_total.item())
+
+    def active_count(self) -> int:
+        """Rows the last step re-evaluated (synchronises)."""
+        return int(self.n_active.item())
+
+    def capturable(self) -> bool:
+        """A step can be captured once and replayed: every argument is fixed
+        (a tree rebuild each step, the jerk predictor or none, no Price &
+        Monaghan lengths, whose solve waits for the device)."""
+        return self.rebuild_every == 1 and self.soft_pm == 0 and self.log is None
+
+    def capture(self):
+        """Run one step, then record the next step's launches in a HIP graph;
+        every later ``step`` replays it.  The context's stream must not be
+        the legacy default stream."""
+        if not self.capturable():
+            raise ValueError("only rebuild_every = 1 with the jerk or no predictor and without "
+                             "Price & Monaghan softening can be captured")
+        self.step()                      # sizes every library buffer
+        self.ctx.graph_begin()
+        try:
+            self._launch(rebuild=True)
+        finally:
+            self.ctx.graph_end()
+        self._graph = True
+        self._need_build = False
+
+    def release_graph(self):
+        """Back to eager steps."""
+        self._graph = False
+
+    def _launch(self, rebuild: bool):
+        """Every launch of one step, on the context's stream (the copy too)."""
         c, dt = self.ctx, self.dt
-        c.kick_drift(self.x, self.v, self.acc, 0.5 * dt, dt)
-        self.t += dt
-        self.step_index += 1
-        c.adaptive_select(self.tf, self.bins, 1, self.tick_bin, self.q_f, self.active, self.n_active,
-                          t0=self.t0, t=self.t)
-        # velocities at time t for the jerk: v(t) ~ v(t - dt/2) + a dt/2
-        self.vpred.copy_(self.v)
-        c.kick_drift(self.scratch, self.vpred, self.acc, 0.5 * dt, 0.0)
-        if self._need_build or (self.step_index - 1) % self.rebuild_every == 0:
-            c.tree_build(self.x, self.vpred, self.m, self.n_leaf)
-            self._need_build = False
-            if self.h is not None:
-                self._lengths()
-                if self.soft_pm > 0:   # the lengths of these positions
-                    c.tree_build(self.x, self.vpred, self.m, self.n_leaf)
-        else:
-            c.tree_refit(self.x, self.vpred, self.m)
-        k = int(self.n_active.item())
-        if k > 0:
-            idx = self.active[:k]
+        with torch.cuda.stream(c.stream):
+            c.kick_drift(self.x, self.v, self.acc, 0.5 * dt, dt)
+            poly = self.log is not None
+            c.adaptive_select(self.tf, self.bins, 1, self.tick_bin, self.q_f, self.active, self.n_active,
+                              t0=self.t0 if poly else None, t=self.t)
+            # velocities at time t for the jerk: v(t) ~ v(t - dt/2) + a dt/2
+            self.vpred.copy_(self.v)
+            c.kick_drift(self.scratch, self.vpred, self.acc, 0.5 * dt, 0.0)
+            if rebuild:
+                c.tree_build(self.x, self.vpred, self.m, self.n_leaf)
+                if self.h is not None:
+                    self._lengths()
+                    if self.soft_pm > 0:   # the lengths of these positions
+                        c.tree_build(self.x, self.vpred, self.m, self.n_leaf)
+            else:
+                c.tree_refit(self.x, self.vpred, self.m)
             c.set_relative_opening(self.opening_alpha, self.a0 if self.opening_alpha > 0 else None)
-            c.grav_eval(idx, self.theta, self.eps, self.G, self.a0, self.jerk, self.tidal)
-            self._pm_correct(idx)
-            c.grav_timestep(self.tidal, self.eta, self.dt_max, 60, self.dt_grav, self.bins, idx=idx)
-            if self.log is not None:
-                c.force_log(self.a0, self.t, *self.log, idx=idx)
-        if self.predictor == "jerk":
-            c.grav_predict(self.a0, self.jerk, self.t0, self.t, self.acc)
-        elif self.predictor == "none":
-            c.grav_predict(self.a0, None, None, self.t, self.acc)
-        else:
-            c.grav_predict_poly(*self.log, self.order, self.t, self.acc)
-        c.kick_drift(self.x, self.v, self.acc, 0.5 * dt, 0.0)
-        self.evaluations += k
-        return k
+            c.grav_eval_dev(self.active, self.n_active, self.theta, self.eps, self.G, self.a0, self.jerk,
+                            self.tidal, n_total=self.n_total)
+            self._pm_correct(self.active, self.n_active)
+            c.grav_timestep_dev(self.tidal, self.eta, self.dt_max, 60, self.dt_grav, self.bins, self.active,
+                                self.n_active)
+            if poly:
+                c.force_log_dev(self.a0, self.t, *self.log, self.active, self.n_active)
+                c.grav_predict_poly(*self.log, self.order, self.t, self.acc)
+            else:   # t - t0 from the force-age counters (0 for the rows just updated)
+                c.grav_predict_age(self.a0, self.jerk if self.predictor == "jerk" else None, self.tf, dt,
+                                   self.acc)
+            c.kick_drift(self.x, self.v, self.acc, 0.5 * dt, 0.0)
+
+    def step(self):
+        """One kick-drift-kick step; returns without waiting for the device."""
+        self.t += self.dt
+        self.step_index += 1
+        if self._graph:
+            self.ctx.graph_replay()
+            return
+        rebuild = self._need_build or (self.step_index - 1) % self.rebuild_every == 0
+        self._need_build = False
+        self._launch(rebuild)
 
     def state(self) -> dict:
         """Everything needed to resume bit for bit (see ``restore``)."""
+        with torch.cuda.stream(self.ctx.stream):
+            return self._state()
+
+    def _state(self) -> dict:
         keys = ["x", "v", "a0", "jerk", "tidal", "acc", "t0", "tf", "bins", "dt_grav"]
         s = {k: getattr(self, k).clone() for k in keys}
         if self.log is not None:
             s["log"] = tuple(a.clone() for a in self.log)
         if self.h is not None:
             s["h"] = self.h.clone()
-        s.update(t=self.t, step_index=self.step_index, evaluations=self.evaluations, dt=self.dt,
-                 dt_max=self.dt_max, tick_bin=self.tick_bin)
+        s["n_total"] = self.n_total.clone()
+        s.update(t=self.t, step_index=self.step_index, dt=self.dt, dt_max=self.dt_max, tick_bin=self.tick_bin)
         return s
 
     def restore(self, s: dict):
         """Resume from ``state()``.  The next step rebuilds the tree, so the
         continuation is bit-identical when the saved step was followed by a
-        rebuild anyway (always with rebuild_every = 1)."""
+        rebuild anyway (always with rebuild_every = 1).  A captured graph
+        stays valid (the state is copied into the same arrays)."""
+        with torch.cuda.stream(self.ctx.stream):
+            self._restore(s)
+
+    def _restore(self, s: dict):
         for k in ["x", "v", "a0", "jerk", "tidal", "acc", "t0", "tf", "bins", "dt_grav"]:
             getattr(self, k).copy_(s[k])
         if self.log is not None:
@@ -214,6 +268,7 @@ class AdaptiveIntegrator:
         if self.h is not None:
             self.h.copy_(s["h"])
             self.ctx.set_softening(self.h)
-        for k in ["t", "step_index", "evaluations", "dt", "dt_max", "tick_bin"]:
+        self.n_total.copy_(s["n_total"])
+        for k in ["t", "step_index", "dt", "dt_max", "tick_bin"]:
             setattr(self, k, s[k])
         self._need_build = True

@@ -2,8 +2,8 @@
 times, on sampled outputs the FP64 oracle computes one by one: the tree walk
 on the 2^20 turbulent sphere and on the 2^22 clumps (theta = 0.7, the default
 offset-aware opening test), the 256-system batched walk, the adjoint
-on 2^18 particles, the timestep bins on the full-size tidal tensors, and the
-empty active set."""
+on 2^18 particles, the adaptive integrator on the 2^22 clumps, the timestep
+bins on the full-size tidal tensors, and the empty active set."""
 import numpy as np
 import pytest
 import torch
@@ -94,20 +94,70 @@ def test_batched_256_systems(ag, ctx, orc):
            *(np.concatenate([r[k] for r in ref]) for k in range(3)))
 
 
-def test_adjoint_2p18(ag, ctx, orc):
+def _mass_gradient_scale(orc, x, w, eps, rows):
+    """G sum_j |f(r_kj) d_kj . w_j|: the size of dL/dm_k before the randomly
+    signed terms cancel (its error is measured against this)."""
+    out = np.empty(len(rows))
+    for t, k in enumerate(rows):
+        d = x - x[k]
+        f, _, _ = orc.kernel(np.linalg.norm(d, axis=1), eps)
+        term = np.abs(f * np.sum(d * w, axis=1))
+        term[k] = 0.0
+        out[t] = term.sum()
+    return out
+
+
+@pytest.mark.parametrize("group_targets", [64, 32])
+def test_adjoint_2p18(ag, ctx, orc, group_targets):
+    """The C5 adjoint at theta = 0.6 (its walks open at 0.75 theta, the
+    default AG_OPT_ADJOINT_OPEN), in both group sizes the bench's autotuner
+    picks from: dL/dx against the oracle's exact gradient within the force's
+    bound (median 1e-3, 99th percentile 1e-2) on 1024 sampled particles, and
+    dL/dm against its cancellation-free size to the same bound on 256."""
     n = 1 << 18
     x, m, _ = workloads.uniform_sphere(n, seed=5)
     v = np.zeros_like(x)
     w = workloads.adjoint_weights(n, seed=5)
-    ctx.tree_build(_t(x), _t(v), _t(m), 16)
-    dx = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
-    dm = torch.zeros(n, dtype=torch.float64, device=DEV)
-    ctx.grav_backward(None, _t(w), 0.6, 1e-3, 1.0, dx, dm)
-    ctx.sync()
+    ctx.set_option(ag.AG_OPT_GROUP_TARGETS, group_targets)
+    try:
+        ctx.tree_build(_t(x), _t(v), _t(m), 16)
+        dx = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+        dm = torch.zeros(n, dtype=torch.float64, device=DEV)
+        ctx.grav_backward(None, _t(w), 0.6, 1e-3, 1.0, dx, dm)
+        ctx.sync()
+    finally:
+        ctx.set_option(ag.AG_OPT_GROUP_TARGETS, 64)
     rows = np.random.default_rng(24).choice(n, 1024, replace=False)
     rx, rm = orc.adjoint(x, m, w, 1e-3, 1.0, rows)
     e = rel_err(dx.cpu().numpy()[rows], rx)
-    assert np.median(e) <= 5e-3 and np.percentile(e, 99) <= 5e-2
+    em = np.abs(dm.cpu().numpy()[rows[:256]] - rm[:256]) / _mass_gradient_scale(orc, x, w, 1e-3, rows[:256])
+    print("dL/dx", np.median(e), np.percentile(e, 99), "dL/dm", np.median(em), np.percentile(em, 99))
+    assert np.median(e) <= 1e-3 and np.percentile(e, 99) <= 1e-2
+    assert np.median(em) <= 1e-3 and np.percentile(em, 99) <= 1e-2
+
+
+def test_adaptive_clumps_2p22(ag, orc):
+    """The C3 integrator at full size: 2^22 particles in 64 clumps, q_f = 1/4,
+    a global step a quarter of the shortest gravity bin, 20 steps; the force
+    in use (fresh or predicted) against the oracle's direct sum at the
+    current positions on 512 sampled particles after steps 10 and 20: median
+    within the metric's 1e-3; fewer evaluations than every step."""
+    from paper_2010_13792_amd.driver import AdaptiveIntegrator
+    n = 1 << 22
+    x, v, m, _ = workloads.clumps(n, seed=3)
+    rows = np.random.default_rng(31).choice(n, 512, replace=False)
+    with ag.Context(0) as c:
+        ad = AdaptiveIntegrator(c, _t(x), _t(v), _t(m), q_f=0.25, theta=0.7, eps=1e-3, step_shift=2)
+        for s in range(1, 21):
+            ad.step()
+            if s in (10, 20):
+                c.sync()
+                ar, _, _ = orc.direct(ad.x.cpu().numpy(), ad.vpred.cpu().numpy(), m, 1e-3, 1.0, rows)
+                e = rel_err(ad.acc.cpu().numpy()[rows], ar)
+                print(f"step {s}: {ad.active_count()} active, force in use median {np.median(e):.3e} "
+                      f"p99 {np.percentile(e, 99):.3e}", flush=True)
+                assert np.median(e) <= 1e-3
+        assert n < ad.evaluations - n < 20 * n
 
 
 def test_empty_active_set(ag, ctx):

@@ -27,8 +27,12 @@ def _lengths(ag, x, k, n_leaf=16, box=0.0):
             c.set_periodic(box)
         c.tree_build(_t(x), _t(v), _t(m), n_leaf)
         h = c.neighbour_lengths(k)
+        hs = c.neighbour_lengths(k, scale=0.7)
         c.sync()
-    return h.cpu().numpy()
+    h = h.cpu().numpy()
+    # the scale multiplies each length once, in FP64
+    np.testing.assert_array_equal(hs.cpu().numpy(), 0.7 * h)
+    return h
 
 
 @pytest.mark.parametrize("k", [1, 7, 32, 64])
@@ -145,6 +149,10 @@ def test_arguments(ag):
         for bad in (0, 65, -3):
             with pytest.raises(ag.AgError) as e:
                 c.neighbour_lengths(bad)
+            assert e.value.code == ag.AG_EINVAL
+        for bad in (0.0, -1.0, float("inf"), float("nan")):
+            with pytest.raises(ag.AgError) as e:
+                c.neighbour_lengths(8, scale=bad)
             assert e.value.code == ag.AG_EINVAL
         c.set_periodic(0.0)
         off = _t([0, 1000, 2048], torch.int64)

@@ -1,5 +1,5 @@
 """GPU parity in a periodic cube, every pair at its nearest image (the jerk
-treatment of Sec. 4): the direct sum against the oracle's (FP64 to 1e-12 of
+treatment of Sec. 3.4): the direct sum against the oracle's (FP64 to 1e-12 of
 the cancellation-free scale), and the tree walk against it to the tree
 tolerances, on clumps straddling the faces (inputs in several images), a
 pancake-mode lattice and a uniform box."""
@@ -274,15 +274,22 @@ def test_ewald_tree(ag, orc, name):
 
 def test_ewald_lattice(ag, orc):
     """A perfect lattice is the uniform box: no force, and the tide of the
-    mean density, (4 pi / 3) G M / L^3 per axis, off-diagonals zero -- up to
-    the tree's error, measured against the cancellation-free sizes."""
-    k, L = 24, 2.0
+    mean density, (4 pi / 3) G M / L^3 per axis, off-diagonals zero.  The
+    mean tide is exact up to rounding.  Per particle, the walk's g and T
+    differ from these by the tree's truncation error, which scales with the
+    cancellation-free size of the fields the two walks sum (the single image
+    about the walk's image origin, of order the nearest-image size S, and the
+    images' correction, of order G M / L^2, resp. G M / L^3) and, at
+    quadrupole order, with theta^3: the tree bounds at theta = 0.7 (g median
+    1e-3, T median 5e-3; 99th percentiles 1e-2, 5e-2, taken here as the
+    maximum over the sample) times (theta / 0.7)^3."""
+    k, L, theta = 24, 2.0, 0.5
     g = (np.arange(k) + 0.5) * L / k
     x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
     n = len(x)
     m = np.full(n, 1.0 / n)
     eps = L / k / 8
-    a, _, T = _tree_ewald(ag, L, x, np.zeros_like(x), m, 0.5, eps)
+    a, _, T = _tree_ewald(ag, L, x, np.zeros_like(x), m, theta, eps)
     c = 4 * np.pi / 3 / L**3
     rows = np.random.default_rng(5).choice(n, 64, replace=False)
     sa, _, st = _scales(orc, x, np.zeros_like(x), m, eps, rows, L)
@@ -292,12 +299,14 @@ def test_ewald_lattice(ag, orc):
     dT[:, :3] -= c
     w = np.array([1, 1, 1, 2, 2, 2], dtype=float)
     et = np.sqrt((dT**2 * w).sum(1)) / st
-    print(f"\nEwald lattice: T diag mean {T[:, :3].mean():.6e} vs {c:.6e}; against the cancellation-free "
-          f"sizes g median {np.median(ea):.2e} max {ea.max():.2e}, T median {np.median(et):.2e} max {et.max():.2e}")
+    f = (theta / 0.7) ** 3
+    print(f"\nEwald lattice: T diag mean {T[:, :3].mean():.6e} vs {c:.6e}; max |g| {np.abs(a).max():.2e}; "
+          f"against the cancellation-free sizes g median {np.median(ea):.2e} max {ea.max():.2e}, "
+          f"T median {np.median(et):.2e} max {et.max():.2e}; bounds x {f:.3f}")
     # the mean tide is the background's, exactly up to rounding
     assert abs(T[:, :3].mean() - c) <= 1e-5 * c
-    assert np.median(ea) <= 1e-3 and ea.max() <= 1e-2
-    assert np.median(et) <= 5e-3 and et.max() <= 5e-2
+    assert np.median(ea) <= 1e-3 * f and ea.max() <= 1e-2 * f
+    assert np.median(et) <= 5e-3 * f and et.max() <= 5e-2 * f
 
 
 def test_ewald_arguments(ag):

@@ -89,6 +89,24 @@ def test_factors_and_correction(ag, cases):
             z, a = z.cpu().numpy(), a.cpu().numpy()
             np.testing.assert_allclose(z, zr, rtol=0, atol=1e-12 * np.abs(zr).max())
             np.testing.assert_allclose(a, ar, rtol=0, atol=1e-12 * np.abs(ar).max())
+        # the correction added at a list of rows (count on the device) equals
+        # the written one there and leaves every other row as it was
+        n = len(x)
+        rows = np.random.default_rng(7).permutation(n)[: n // 3].astype(np.int32)
+        base = np.random.default_rng(8).normal(size=(n, 3))
+        with ag.Context(0) as c:
+            _build(ag, c, x, m, 16, h=hr)
+            full = c.pm_correct(_t(zr))
+            acc = _t(base)
+            c.pm_correct_add(_t(zr), acc, _t(rows), torch.tensor([len(rows)], dtype=torch.int64, device=DEV))
+            acc_all = _t(base)
+            c.pm_correct_add(_t(zr), acc_all)
+            c.sync()
+        full, acc, acc_all = full.cpu().numpy(), acc.cpu().numpy(), acc_all.cpu().numpy()
+        other = np.setdiff1d(np.arange(n), rows)
+        np.testing.assert_array_equal(acc[other], base[other])
+        np.testing.assert_array_equal(acc[rows], base[rows] + full[rows])
+        np.testing.assert_array_equal(acc_all, base + full)
 
 
 def test_chain_on_device(ag, orc, cases):

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Ewald sums (the periodic g and T of Sec. 4's
+"""Pins of the oracle's Ewald sums (the periodic g and T of Sec. 3.4's
 cosmological problem; the jerk stays nearest-image there).
 
 Fixed by: independence of the splitting parameter alpha (a wrong sign or

@@ -1,6 +1,6 @@
 """Pins of the oracle's periodic mode: every pair at its nearest image in a
 cube of side L (the treatment the paper gives the jerk of its periodic
-problem, Sec. 4).  Fixed by: the open-boundary sum when the box is large, the
+problem, Sec. 3.4).  Fixed by: the open-boundary sum when the box is large, the
 closed form of a pair whose nearest image lies across the boundary,
 invariance under a shift of every particle modulo L, Newton's third law,
 cubic-lattice symmetry, the Poisson identity, and finite differences."""
