@@ -369,6 +369,21 @@ int ag_grav_direct(ag_ctx *ctx, int64_t n, const double *x, const double *v, con
                    const int32_t *active_idx, int64_t n_active, double eps, double G,
                    int precision, double *acc, double *jerk, double *tidal);
 
+/* ag_grav_direct for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, checks and kernels, and bit-identical results, but the
+ * call allocates nothing.  Its scratch (the per-split sums of a small target
+ * set, 12.6 MB) is a fixed array of the library on each device, looked up
+ * when the first context on that device is created; the launch shape bounds
+ * the scratch for every n and n_active, so no size is refused (a larger
+ * need would give AG_EINVAL).  Every call on one device shares that array:
+ * calls that overlap on one device (other streams, other contexts, other
+ * threads) race, so order them on one stream.  Not recorded by the phase
+ * timing. */
+int ag_grav_direct_noalloc(ag_ctx *ctx, int64_t n, const double *x, const double *v, const double *m,
+                           const int32_t *active_idx, int64_t n_active, double eps, double G, int precision,
+                           double *acc, double *jerk, double *tidal);
+
 /* ---- timestep, bookkeeping, predictor (Sec. 2, Sec. 3) ------------------- */
 
 /* Tidal timestep (Eq. 7) dt_grav = sqrt(eta) (|T|_F^2 / 6)^(-1/4) and its

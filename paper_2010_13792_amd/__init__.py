@@ -40,6 +40,7 @@ ENTRY_POINTS = [
     "ag_force_log", "ag_grav_predict_poly", "ag_set_periodic", "ag_set_softening",
     "ag_neighbour_lengths", "ag_set_relative_opening", "ag_pm_lengths", "ag_pm_factors", "ag_pm_correct",
     "ag_grav_eval_dev", "ag_grav_timestep_dev", "ag_grav_predict_age", "ag_pm_correct_add", "ag_force_log_dev",
+    "ag_grav_direct_noalloc",
 ]
 AG_PRED_MAX_DEPTH = 4
 AG_OPT_WALK_WAVES_PER_CU = 1
@@ -97,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "ag_grav_predict_age": [P, I64, P, P, P, P, D, P],
         "ag_pm_correct_add": [P, P, P, P, P],
         "ag_grav_direct": [P, I64, P, P, P, P, I64, D, D, ctypes.c_int, P, P, P],
+        "ag_grav_direct_noalloc": [P, I64, P, P, P, P, I64, D, D, ctypes.c_int, P, P, P],
         "ag_grav_timestep": [P, I64, P, I64, P, D, D, I32, P, P],
         "ag_adaptive_select": [P, I64, P, P, I64, I32, D, P, P, P, D],
         "ag_kick_drift": [P, I64, P, P, P, D, D],
@@ -278,10 +280,13 @@ class Context:
     def grav_eval_batched(self, active_idx, theta, eps, G, acc, jerk, tidal):
         self.grav_eval(active_idx, theta, eps, G, acc, jerk, tidal, batched=True)
 
-    def grav_direct(self, x, v, m, active_idx, eps, G, acc, jerk, tidal, precision=AG_FP64):
+    def grav_direct(self, x, v, m, active_idx, eps, G, acc, jerk, tidal, precision=AG_FP64, noalloc=False):
+        """Direct summation; ``noalloc`` calls ag_grav_direct_noalloc (no
+        device allocation; library-held scratch shared per device)."""
         n = x.shape[0]
         k = n if active_idx is None else active_idx.shape[0]
-        _check(_lib.ag_grav_direct(self._h, n, _ptr(x, torch.float64, (3,), "x"),
+        fn = _lib.ag_grav_direct_noalloc if noalloc else _lib.ag_grav_direct
+        _check(fn(self._h, n, _ptr(x, torch.float64, (3,), "x"),
                                    _ptr(v, torch.float64, (3,), "v", n),
                                    _ptr(m, torch.float64, None, "m", n),
                                    _ptr(active_idx, torch.int32, None, "active_idx"), k,

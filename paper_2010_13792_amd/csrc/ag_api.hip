@@ -63,7 +63,7 @@ static hipEvent_t take_event(Timing& t) {
 }
 
 PhaseScope::PhaseScope(ag_ctx* ctx, int ph) : c(ctx), phase(ph) {
-    if (!c->timing.on) return;
+    if (!c->timing.on || ph < 0) return;   // a negative phase records nothing
     a = take_event(c->timing);
     if (a) (void)hipEventRecord(a, c->stream);
 }
@@ -119,28 +119,12 @@ extern "C" int ag_timing_read(ag_ctx* c, double* ms, int64_t* launches, int rese
 
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 int check_ctx(ag_ctx* c) {
     if (!c) return ag_fail(AG_EINVAL, "null context");
     return AG_OK;
 }
 
-int check_launch(const char* what) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return ag_fail(AG_EHIP, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
-    return AG_OK;
-}
+int check_launch(const char* what) { return ag_check_launch(what); }
 
 int read_flags(ag_ctx* c) {
     int32_t f = 0;
@@ -157,6 +141,12 @@ int read_flags(ag_ctx* c) {
 }
 
 }  // namespace
+
+int ag_check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ag_fail(AG_EHIP, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
+    return AG_OK;
+}
 
 // clears counters that kernels leave at zero after each use
 __global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
@@ -175,7 +165,12 @@ extern "C" int ag_create(ag_ctx** out, int device, void* stream) {
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     DeviceGuard g(device);
-    int r = ag_ensure(c, c->stats, 4 * sizeof(uint64_t));
+    int r = ag_direct_noalloc_init(device);
+    if (r != AG_OK) {
+        delete c;
+        return r;
+    }
+    r = ag_ensure(c, c->stats, 4 * sizeof(uint64_t));
     if (r == AG_OK) r = ag_ensure(c, c->dflags, 4 * sizeof(int32_t));
     if (r == AG_OK) r = ag_ensure(c, c->tree_hdr, kTreeHdrBytes);
     if (r != AG_OK) {
@@ -373,9 +368,8 @@ extern "C" int ag_grav_eval_batched(ag_ctx* c, const int32_t* idx, int64_t n_act
     return check_launch("grav eval batched");
 }
 
-extern "C" int ag_grav_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
-                              const int32_t* idx, int64_t n_act, double eps, double G, int precision,
-                              double* acc, double* jerk, double* tidal) {
+int ag_direct_check(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m, const int32_t* idx,
+                    int64_t n_act, double eps, double G, int precision) {
     AG_TRY(check_ctx(c));
     if (n <= 0) return ag_fail(AG_EINVAL, "n must be positive");
     if (n > (int64_t)1 << 30) return ag_fail(AG_EINVAL, "n exceeds 2^30");
@@ -389,6 +383,13 @@ extern "C" int ag_grav_direct(ag_ctx* c, int64_t n, const double* x, const doubl
                        (long long)n);
     if (n_act < 0 || n_act > n) return ag_fail(AG_EINVAL, "n_active out of range");
     if (!idx && n_act != n) return ag_fail(AG_EINVAL, "active_idx = NULL requires n_active = n");
+    return AG_OK;
+}
+
+extern "C" int ag_grav_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                              const int32_t* idx, int64_t n_act, double eps, double G, int precision,
+                              double* acc, double* jerk, double* tidal) {
+    AG_TRY(ag_direct_check(c, n, x, v, m, idx, n_act, eps, G, precision));
     if (n_act == 0) return AG_OK;
     DeviceGuard g(c->device);
     const size_t bytes = ag_direct_scratch_bytes(n, n_act);

@@ -157,10 +157,31 @@ struct ag_ctx {
 
 // grow-only device buffer of the context (AG_ESTATE while capturing a graph)
 int ag_ensure(ag_ctx* c, DevBuf& b, size_t bytes);
+
+// makes a device current for a scope and restores the previous one
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// argument checks of ag_grav_direct (shared by its allocation-free variant)
+int ag_direct_check(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m, const int32_t* idx,
+                    int64_t n_act, double eps, double G, int precision);
+// the allocation-free direct sum's scratch on the current device: looked up
+// once per device (ag_create calls it with the device current)
+int ag_direct_noalloc_init(int device);
+int ag_check_launch(const char* what);
 void ag_release(DevBuf& b);
 
 // Records a start event on construction and a stop event on destruction on
-// the context's stream, when timing is enabled.
+// the context's stream, when timing is enabled and the phase is not negative.
 struct PhaseScope {
     ag_ctx* c;
     int phase;
@@ -176,7 +197,7 @@ struct PhaseScope {
 // first ag_direct_count_bytes() are zero (and are left zero)
 int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
                      const int32_t* idx, int64_t n_act, double eps, double G, int precision,
-                     double* acc, double* jerk, double* tidal, void* scratch);
+                     double* acc, double* jerk, double* tidal, void* scratch, bool timed = true);
 size_t ag_direct_scratch_bytes(int64_t n, int64_t n_act);
 size_t ag_direct_count_bytes();
 int ag_launch_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx,

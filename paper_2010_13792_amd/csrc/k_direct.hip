@@ -30,6 +30,8 @@
 //
 // Per-particle softening (kSoft): each pair's f and D are the means of the
 // target's and the source's kernels (hs, input order).
+#include <mutex>
+
 #include "ag_internal.h"
 #include "pair.h"
 
@@ -341,7 +343,7 @@ size_t ag_direct_count_bytes() { return kCountBytes; }
 
 int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
                      const int32_t* idx, int64_t n_act, double eps, double G, int precision,
-                     double* acc, double* jerk, double* tidal, void* scratch) {
+                     double* acc, double* jerk, double* tidal, void* scratch, bool timed) {
     int64_t tiles, nsplit, chunk;
     ag_direct_shape(n, n_act, &tiles, &nsplit, &chunk);
     DirectArgs P{};
@@ -363,7 +365,7 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
     P.jerk = jerk;
     P.tidal = tidal;
     P.flags = c->dflags.as<int32_t>();
-    PhaseScope phase(c, AG_PHASE_DIRECT);
+    PhaseScope phase(c, timed ? AG_PHASE_DIRECT : -1);
     dim3 grid((unsigned)tiles, (unsigned)nsplit);
     hipStream_t st = c->stream;
     const bool fp64 = precision == AG_FP64, per = P.L > 0.0, soft = P.hs != nullptr;
@@ -377,4 +379,59 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
     }
 #undef AG_DIRECT
     return AG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free direct sum, for callers that cannot allocate device
+// memory: the split counters and split sums live in a file-scope device array
+// of fixed size.  The launch shape bounds the scratch for every size (a split
+// happens only with fewer than kDirectBlocks target tiles, so tiles x splits
+// < 2 kDirectBlocks), so no call is refused for its size.  Every call on a
+// device shares that device's copy of the array: calls that overlap on one
+// device race.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocBytes = kCountBytes + (size_t)(2 * kDirectBlocks) * kParts * kTile * sizeof(double);
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};   // the array's address on each device
+}  // namespace
+
+int ag_direct_noalloc_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return ag_fail(AG_EINVAL, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return AG_OK;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return ag_fail(AG_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
+    // the split counters start at zero; each launch leaves them at zero
+    e = hipMemset(p, 0, kCountBytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return ag_fail(AG_EHIP, "clearing the direct-sum scratch failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+    return AG_OK;
+}
+
+extern "C" int ag_grav_direct_noalloc(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                                      const int32_t* idx, int64_t n_act, double eps, double G, int precision,
+                                      double* acc, double* jerk, double* tidal) {
+    AG_TRY(ag_direct_check(c, n, x, v, m, idx, n_act, eps, G, precision));
+    if (n_act == 0) return AG_OK;
+    const size_t bytes = ag_direct_scratch_bytes(n, n_act);
+    if (bytes > kNoAllocBytes)
+        return ag_fail(AG_EINVAL, "the direct sum needs %zu bytes of scratch, above the %zu this entry point holds",
+                       bytes, kNoAllocBytes);
+    void* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = c->device < kMaxDevices ? g_scratch_ptr[c->device] : nullptr;
+    }
+    if (!p) return ag_fail(AG_ESTATE, "no direct-sum scratch on device %d", c->device);
+    DeviceGuard g(c->device);
+    AG_TRY(ag_launch_direct(c, n, x, v, m, idx, n_act, eps, G, precision, acc, jerk, tidal, bytes > 0 ? p : nullptr,
+                            false));
+    return ag_check_launch("grav direct (no allocation)");
 }
