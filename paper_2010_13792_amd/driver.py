@@ -159,11 +159,13 @@ class AdaptiveIntegrator:
     @property
     def evaluations(self) -> int:
         """Force evaluations so far, the first one included (synchronises)."""
-        return self.n + int(self.n_total.item())
+        with torch.cuda.stream(self.ctx.stream):
+            return self.n + int(self.n_total.item())
 
     def active_count(self) -> int:
         """Rows the last step re-evaluated (synchronises)."""
-        return int(self.n_active.item())
+        with torch.cuda.stream(self.ctx.stream):
+            return int(self.n_active.item())
 
     def capturable(self) -> bool:
         """A step can be captured once and replayed: every argument is fixed
@@ -236,9 +238,14 @@ class AdaptiveIntegrator:
         self._launch(rebuild)
 
     def state(self) -> dict:
-        """Everything needed to resume bit for bit (see ``restore``)."""
+        """Everything needed to resume bit for bit (see ``restore``): copies
+        made on the context's stream, ready for use on the caller's stream."""
+        caller = torch.cuda.current_stream(self.x.device)
+        self.ctx.stream.wait_stream(caller)
         with torch.cuda.stream(self.ctx.stream):
-            return self._state()
+            s = self._state()
+        caller.wait_stream(self.ctx.stream)
+        return s
 
     def _state(self) -> dict:
         keys = ["x", "v", "a0", "jerk", "tidal", "acc", "t0", "tf", "bins", "dt_grav"]
@@ -256,6 +263,7 @@ class AdaptiveIntegrator:
         continuation is bit-identical when the saved step was followed by a
         rebuild anyway (always with rebuild_every = 1).  A captured graph
         stays valid (the state is copied into the same arrays)."""
+        self.ctx.stream.wait_stream(torch.cuda.current_stream(self.x.device))
         with torch.cuda.stream(self.ctx.stream):
             self._restore(s)
 
