@@ -177,6 +177,12 @@ extern "C" int ag_create(ag_ctx** out, int device, void* stream) {
         ag_destroy(c);
         return r;
     }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->depth_host), sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->depth_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        ag_destroy(c);
+        return ag_fail(AG_EHIP, "context initialisation failed (pinned depth word)");
+    }
     if (hipMemsetAsync(c->stats.p, 0, 4 * sizeof(uint64_t), c->stream) != hipSuccess ||
         hipMemsetAsync(c->dflags.p, 0, 4 * sizeof(int32_t), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -192,7 +198,7 @@ extern "C" int ag_destroy(ag_ctx* c) {
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->sort_hist, &c->perm,
-                      &c->rank, &c->spos, &c->svel, &c->svf, &c->cdig, &c->pos_cnt, &c->pos_off,
+                      &c->rank, &c->spos, &c->svel, &c->svf, &c->cdig, &c->cd_min, &c->pos_cnt, &c->pos_off,
                       &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
                       &c->nd_64, &c->nd_w, &c->nd_wf, &c->in_list, &c->in_cnt, &c->in_off,
                       &c->tree_hdr, &c->lvl_list, &c->leaf_list, &c->child, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
@@ -206,6 +212,8 @@ extern "C" int ag_destroy(ag_ctx* c) {
     for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->depth_ev) (void)hipEventDestroy(c->depth_ev);
+    if (c->depth_host) (void)hipHostFree(c->depth_host);
     delete c;
     return AG_OK;
 }

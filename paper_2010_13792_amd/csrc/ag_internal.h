@@ -105,6 +105,7 @@ struct ag_ctx {
     DevBuf svel;                  // double4 [n]: sorted vx, vy, vz, 0
     DevBuf svf;                   // float4  [n]: sorted vx, vy, vz, m (FP32 copies)
     DevBuf cdig;                  // i32 [n]: octal digits shared with the previous key
+    DevBuf cd_min;                // i32: their minima over runs of 16, 256, ... 2^24 positions
     DevBuf pos_cnt, pos_off;      // i32 [n+1]: nodes starting at each position, offsets
     DevBuf scan_tmp;              // scan block partials
 
@@ -153,6 +154,12 @@ struct ag_ctx {
     DevBuf dflags;                // i32 [1]
 
     int64_t host_n_nodes = -1;    // cached after a synchronising read
+    // depth of the last tree seen by the host (pinned copy + event, read when
+    // the next build starts without waiting): plans the moments' launches
+    int64_t* depth_host = nullptr;
+    hipEvent_t depth_ev = nullptr;
+    bool depth_pending = false;
+    int seen_max_level = -1;
 };
 
 // grow-only device buffer of the context (AG_ESTATE while capturing a graph)

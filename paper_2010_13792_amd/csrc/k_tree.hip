@@ -23,6 +23,9 @@
 //      its first member, shifted to the centre of mass at the end.
 #include <float.h>
 
+#include <algorithm>
+#include <climits>
+
 #include "ag_internal.h"
 
 namespace {
@@ -52,7 +55,7 @@ __device__ __forceinline__ int sys_of(const int64_t* __restrict__ off, int n_sys
 // ---------------------------------------------------------------------------
 // 1. bounding cubes
 // ---------------------------------------------------------------------------
-constexpr int64_t kBoxChunk = 8192;
+constexpr int64_t kBoxChunk = 2048;
 
 // One block opens a build: system offsets (checked; NULL = one system), the
 // empty bounding boxes, the first box workgroup of each system (exclusive
@@ -98,11 +101,18 @@ __device__ __forceinline__ double in_box(double q, double pbox) {
     return pbox > 0.0 ? q - pbox * floor(q / pbox) : q;
 }
 
-__global__ void __launch_bounds__(kThreads) k_box(const double* __restrict__ x, const int64_t* __restrict__ off,
-                                                  int n_sys, const int32_t* __restrict__ blk_off,
-                                                  uint64_t* __restrict__ box, int32_t* __restrict__ flags,
-                                                  double pbox) {
-    __shared__ double s_red[6][kThreads / 64];
+// Each workgroup of 384 threads (a multiple of 3, so a thread always meets
+// the same coordinate) reads kBoxChunk consecutive rows as one contiguous run
+// of doubles and writes its per-coordinate minima and maxima (order-preserving
+// integers) to part[6 b ..]; k_box_reduce combines the workgroups of each
+// system.  Non-finite coordinates raise the flag and are left out.
+constexpr int kBoxThreads = 384;
+
+__global__ void __launch_bounds__(kBoxThreads) k_box(const double* __restrict__ x, const int64_t* __restrict__ off,
+                                                     int n_sys, const int32_t* __restrict__ blk_off,
+                                                     uint64_t* __restrict__ part, int32_t* __restrict__ flags,
+                                                     double pbox) {
+    __shared__ uint64_t s_red[6][kBoxThreads / 64];
     const int b = blockIdx.x;
     if (b >= blk_off[n_sys]) return;
     int lo = 0, hi = n_sys;
@@ -113,33 +123,71 @@ __global__ void __launch_bounds__(kThreads) k_box(const double* __restrict__ x, 
     const int s = lo;
     const int64_t i0 = off[s] + (int64_t)(b - blk_off[s]) * kBoxChunk;
     const int64_t i1 = i0 + kBoxChunk < off[s + 1] ? i0 + kBoxChunk : off[s + 1];
-    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    const int c = threadIdx.x % 3;   // kBoxThreads is a multiple of 3
+    double mn = DBL_MAX, mx = -DBL_MAX;
     bool bad = false;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double q = x[3 * i + c];
-            if (!isfinite(q)) { bad = true; continue; }
-            q = in_box(q, pbox);
-            mn[c] = q < mn[c] ? q : mn[c];
-            mx[c] = q > mx[c] ? q : mx[c];
+    for (int64_t j = 3 * i0 + threadIdx.x; j < 3 * i1; j += kBoxThreads) {
+        double q = x[j];
+        if (!isfinite(q)) {
+            bad = true;
+            continue;
         }
+        q = in_box(q, pbox);
+        mn = q < mn ? q : mn;
+        mx = q > mx ? q : mx;
     }
     if (bad) atomicOr(flags, AGF_NONFINITE);
-    const int lane = ag_lane(), w = threadIdx.x >> 6;
+    // per coordinate: the wave's lanes of that coordinate, then the waves
+    uint64_t omn[3], omx[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double a = ag_wave_min(mn[c]), z = ag_wave_max(mx[c]);
-        if (lane == 0) { s_red[c][w] = a; s_red[3 + c][w] = z; }
+    for (int k = 0; k < 3; ++k) {
+        omn[k] = ag_wave_min(k == c ? ag_ord(mn) : ~0ull);
+        omx[k] = ag_wave_max(k == c ? ag_ord(mx) : 0ull);
+    }
+    const int lane = ag_lane(), w = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_red[k][w] = omn[k];
+            s_red[3 + k][w] = omx[k];
+        }
     }
     __syncthreads();
     if (threadIdx.x < 6) {
-        const int c = threadIdx.x;
-        double r = s_red[c][0];
-        for (int k = 1; k < kThreads / 64; ++k)
-            r = c < 3 ? (s_red[c][k] < r ? s_red[c][k] : r) : (s_red[c][k] > r ? s_red[c][k] : r);
-        if (c < 3) atomicMin((unsigned long long*)&box[6 * s + c], (unsigned long long)ag_ord(r));
-        else atomicMax((unsigned long long*)&box[6 * s + c], (unsigned long long)ag_ord(r));
+        const int k = threadIdx.x;
+        uint64_t r = s_red[k][0];
+        for (int q = 1; q < kBoxThreads / 64; ++q) r = k < 3 ? (s_red[k][q] < r ? s_red[k][q] : r)
+                                                           : (s_red[k][q] > r ? s_red[k][q] : r);
+        part[6 * (int64_t)b + k] = r;
+    }
+}
+
+// one workgroup per system: its box from the partial boxes of its workgroups
+__global__ void k_box_reduce(int n_sys, const int32_t* __restrict__ blk_off, const uint64_t* __restrict__ part,
+                             uint64_t* __restrict__ box) {
+    __shared__ uint64_t s_red[6][4];
+    const int s = blockIdx.x;
+    if (s >= n_sys) return;
+    uint64_t v[6] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull};
+    for (int b = blk_off[s] + threadIdx.x; b < blk_off[s + 1]; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const uint64_t q = part[6 * (int64_t)b + k];
+            v[k] = k < 3 ? (q < v[k] ? q : v[k]) : (q > v[k] ? q : v[k]);
+        }
+    const int lane = ag_lane(), w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const uint64_t r = k < 3 ? ag_wave_min(v[k]) : ag_wave_max(v[k]);
+        if (lane == 0) s_red[k][w] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        uint64_t r = s_red[k][0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = k < 3 ? (s_red[k][q] < r ? s_red[k][q] : r)
+                                                                  : (s_red[k][q] > r ? s_red[k][q] : r);
+        box[6 * s + k] = r;
     }
 }
 
@@ -365,10 +413,99 @@ __device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
     return (__clzll(d) - 1) / 3;   // bit 63 is always clear
 }
 
-__global__ void k_cdig(int64_t n, const uint64_t* __restrict__ keys, int32_t* __restrict__ cd) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x)
-        cd[p] = p == 0 ? -1 : common_digits(keys[p - 1], keys[p]);
+// Minima of the shared-digit counts over aligned runs of 16^(k+1) positions,
+// k = 0 .. 5 (16 positions up to 2^24): the search for a far cell end skips
+// whole runs with them.  Levels 0-2 are written by k_cdig (a workgroup pass
+// covers 4096 positions), levels 3-5 by k_cd_min_top.
+constexpr int kCdLevels = 6;
+struct CdMin {
+    int32_t* lev[kCdLevels];
+};
+constexpr int kRun = 256;                 // threads of k_cdig
+constexpr int64_t kCdPass = 16 * kRun;   // positions per k_cdig workgroup pass
+
+__global__ void __launch_bounds__(kRun) k_cdig(int64_t n, const uint64_t* __restrict__ keys, int32_t* __restrict__ cd,
+                                               CdMin M) {
+    __shared__ int s_w[16][kRun / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t g = blockIdx.x; g * kCdPass < n; g += gridDim.x) {
+        for (int j = 0; j < 16; ++j) {
+            const int64_t p = g * kCdPass + j * kRun + threadIdx.x;
+            int v = INT_MAX;
+            if (p < n) {
+                v = p == 0 ? -1 : common_digits(keys[p - 1], keys[p]);
+                cd[p] = v;
+            }
+            int m16 = v;   // runs of 16 (level 0)
+            m16 = min(m16, __shfl_xor(m16, 1, 16));
+            m16 = min(m16, __shfl_xor(m16, 2, 16));
+            m16 = min(m16, __shfl_xor(m16, 4, 16));
+            m16 = min(m16, __shfl_xor(m16, 8, 16));
+            if ((threadIdx.x & 15) == 0) M.lev[0][p >> 4] = m16;
+            const int wv = ag_wave_min(v);
+            if (lane == 0) s_w[j][w] = wv;
+        }
+        __syncthreads();
+        if (threadIdx.x < 16) {   // runs of 256 (level 1), then of 4096 (level 2)
+            int m = s_w[threadIdx.x][0];
+            for (int k = 1; k < kRun / 64; ++k) m = s_w[threadIdx.x][k] < m ? s_w[threadIdx.x][k] : m;
+            M.lev[1][g * 16 + threadIdx.x] = m;
+            m = min(m, __shfl_xor(m, 1, 16));
+            m = min(m, __shfl_xor(m, 2, 16));
+            m = min(m, __shfl_xor(m, 4, 16));
+            m = min(m, __shfl_xor(m, 8, 16));
+            if (threadIdx.x == 0) M.lev[2][g] = m;
+        }
+        __syncthreads();
+    }
+}
+
+// levels 3-5 from level 2 (one workgroup); cnt[k] entries at level k
+struct CdCounts {
+    int64_t cnt[kCdLevels];
+};
+__global__ void k_cd_min_top(CdMin M, CdCounts C) {
+    for (int k = 3; k < kCdLevels; ++k) {
+        for (int64_t i = threadIdx.x; i < C.cnt[k]; i += blockDim.x) {
+            int m = INT_MAX;
+            for (int j = 0; j < 16; ++j) {
+                const int64_t q = 16 * i + j;
+                if (q < C.cnt[k - 1]) m = min(m, M.lev[k - 1][q]);
+            }
+            M.lev[k][i] = m;
+        }
+        __syncthreads();
+    }
+}
+
+// first position q' >= q with cd[q'] < l (n if none): finish q's run of 16,
+// then skip whole runs by their minima, climbing a level each time a run of
+// the level above is passed, and search the run found downwards
+__device__ int64_t next_below(int64_t n, const int32_t* __restrict__ cd, const CdMin& M, int64_t q, int l) {
+    if (q >= n) return n;
+    for (; q & 15; ++q) {
+        if (q >= n) return n;
+        if (cd[q] < l) return q;
+    }
+    int lev = 0;
+    int64_t idx = q >> 4;
+    for (;;) {
+        if ((idx << (4 * (lev + 1))) >= n) return n;
+        if (M.lev[lev][idx] < l) break;
+        ++idx;
+        if ((idx & 15) == 0 && lev < kCdLevels - 1) {
+            ++lev;
+            idx >>= 4;
+        }
+    }
+    while (lev > 0) {
+        --lev;
+        idx <<= 4;
+        while (M.lev[lev][idx] >= l) ++idx;
+    }
+    q = idx << 4;
+    while (cd[q] >= l) ++q;
+    return q;
 }
 
 struct TopoParams {
@@ -377,65 +514,56 @@ struct TopoParams {
     int sys_levels;
 };
 
-__device__ __forceinline__ bool is_split(const TopoParams& P, int level, int64_t count_or_big) {
-    if (level < P.sys_levels) return true;
-    return level < AG_MAX_LEVEL && count_or_big > P.n_leaf;
-}
+// Nodes starting at each position, and how many of them are inner nodes
+// (all but the last, which is a leaf), from a window of the shared-digit
+// counts in LDS (cd' = -1 past the end, so the end bounds every cell):
+//  - the node at level c + 1 (c = cd[p]) exists iff p = 0 or the level-c cell
+//    holding p is split: c below the system levels, or c < 21 and the cell
+//    (from the last a < p with cd[a] < c to the first q > p with cd'[q] < c)
+//    holds more than n_leaf particles;
+//  - the cell of level l starting at p holds at most n_leaf particles iff
+//    some q in (p, p + n_leaf] has cd'[q] < l, i.e. iff l > mn, mn the
+//    minimum of cd' there; so the leaf is at L = max(c + 1, system levels,
+//    min(21, mn + 1)) and L - c nodes start at p.
+constexpr int kWin = 64;   // largest n_leaf
 
-// end of the level-l cell starting at p if it holds <= n_leaf particles,
-// else -1 (bounded forward scan of the shared-digit counts)
-__device__ __forceinline__ int64_t small_cell_end(const TopoParams& P, const int32_t* __restrict__ cd,
-                                                  int64_t p, int l) {
-    int64_t q = p + 1;
-    const int64_t lim = p + P.n_leaf;
-    while (q < P.n && q <= lim) {
-        if (cd[q] < l) return q;
-        ++q;
-    }
-    if (q >= P.n && P.n - p <= P.n_leaf) return P.n;
-    return -1;
-}
-
-// does the level-c cell containing p (which does not start at p) get split?
-__device__ __forceinline__ bool parent_split(const TopoParams& P, const int32_t* __restrict__ cd, int64_t p,
-                                             int c) {
-    if (c < P.sys_levels) return true;
-    if (c >= AG_MAX_LEVEL) return false;
-    int64_t a = p - 1;
-    int steps = 0;
-    while (cd[a] >= c) {       // cd[0] = -1 stops the scan
-        --a;
-        if (++steps > P.n_leaf) return true;
-    }
-    int64_t q = p + 1;
-    while (q < P.n && cd[q] >= c) {
-        ++q;
-        if (++steps > P.n_leaf) return true;
-    }
-    return (q - a) > P.n_leaf;
-}
-
-// number of tree nodes starting at position p
-__device__ __forceinline__ int nodes_at(const TopoParams& P, const int32_t* __restrict__ cd, int64_t p) {
-    const int c = cd[p];
-    if (p > 0 && (c >= AG_MAX_LEVEL || !parent_split(P, cd, p, c))) return 0;
-    int cnt = 0;
-    for (int l = c + 1; l <= AG_MAX_LEVEL; ++l) {
-        ++cnt;
-        const int64_t e = small_cell_end(P, cd, p, l);
-        const bool small = e >= 0;
-        if (!is_split(P, l, small ? 0 : P.n_leaf + 1)) break;
-    }
-    return cnt;
-}
-
-// nodes starting at each position, and how many of them are inner nodes
-// (all but the last, which is a leaf)
-__global__ void k_count_nodes(TopoParams P, const int32_t* __restrict__ cd, int32_t* __restrict__ cnt,
-                              int32_t* __restrict__ icnt) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int k = nodes_at(P, cd, p);
+__global__ void __launch_bounds__(kThreads) k_count_nodes(TopoParams P, const int32_t* __restrict__ cd,
+                                                          int32_t* __restrict__ cnt, int32_t* __restrict__ icnt) {
+    __shared__ int s_cd[kThreads + 2 * kWin];
+    const int W = P.n_leaf;
+    for (int64_t p0 = (int64_t)blockIdx.x * kThreads; p0 < P.n; p0 += (int64_t)gridDim.x * kThreads) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < kThreads + 2 * W; k += kThreads) {
+            const int64_t q = p0 - W + k;
+            s_cd[k] = (q >= 0 && q < P.n) ? cd[q] : -1;
+        }
+        __syncthreads();
+        const int64_t p = p0 + threadIdx.x;
+        if (p >= P.n) continue;
+        const int* w = s_cd + W + threadIdx.x;   // w[0] = cd[p], w[k] = cd'[p + k]
+        const int c = w[0];
+        int k = 0;
+        bool exists = true;
+        if (p > 0) {
+            if (c >= AG_MAX_LEVEL) {
+                exists = false;
+            } else if (c >= P.sys_levels) {
+                int db = 0, df = 0;   // distance back to the cell's start, forward to its end (0: beyond the window)
+                for (int j = 1; j <= W; ++j)
+                    if (!db && p - j >= 0 && w[-j] < c) db = j;
+                for (int j = 1; j <= W; ++j)
+                    if (!df && w[j] < c) df = j;
+                exists = !db || !df || db + df > W;
+            }
+        }
+        if (exists) {
+            int mn = INT_MAX;
+            for (int j = 1; j <= W; ++j) mn = w[j] < mn ? w[j] : mn;
+            int L = mn + 1 < AG_MAX_LEVEL ? mn + 1 : AG_MAX_LEVEL;
+            L = L > c + 1 ? L : c + 1;
+            L = L > P.sys_levels ? L : P.sys_levels;
+            k = L - c;
+        }
         cnt[p] = k;
         icnt[p] = k > 0 ? k - 1 : 0;
     }
@@ -614,29 +742,93 @@ __global__ void __launch_bounds__(kThreads) k_seg_sort(TopoParams P, const int32
     }
 }
 
-// Writes every node's link and lists the inner nodes (in pre-order).
-__global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, const int32_t* __restrict__ cd,
-                              const int32_t* __restrict__ off, const int32_t* __restrict__ ioff,
-                              int4* __restrict__ link, int32_t* __restrict__ ilist, int32_t* __restrict__ leaves,
-                              int64_t* __restrict__ hdr, int32_t* __restrict__ blk_max) {
-    __shared__ int s_lc[AG_MAX_LEVEL + 1];   // inner nodes of this block per level
-    if (threadIdx.x <= AG_MAX_LEVEL) s_lc[threadIdx.x] = 0;
-    __syncthreads();
+// Writes every node's link and lists the inner nodes (in pre-order).  The
+// end of the cell of node (l, p) is the first q > p with cd'[q] < l; ends do
+// not decrease from the deepest node at p (the leaf) to the shallowest, so
+// each search continues from the end below it, in the LDS window (this run
+// and n_leaf + 1 beyond, with minima per 16).  A node whose end lies beyond
+// the window, and every node above it at p, is left to k_far_ends: p and the
+// deepest such node go to a list (their skip and count fields are written
+// there), so the long searches run on their own instead of stalling the
+// waves of this kernel.  The list is gathered per workgroup in LDS and
+// appended with one global atomic per flush; the inner nodes per level and
+// the deepest level go to per-workgroup slots that k_tree_close adds up, so
+// no address is shared by the workgroups' atomics.
+constexpr int kWriteBlocks = 2048;   // eight workgroups per CU at most
+constexpr int kFarLds = 1024;        // far entries held in LDS between flushes
+constexpr int kLevels = AG_MAX_LEVEL + 1;
+
+__global__ void __launch_bounds__(kThreads) k_write_nodes(TopoParams P, const int32_t* __restrict__ cd,
+                                                          const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ ioff, int4* __restrict__ link,
+                                                          int32_t* __restrict__ ilist, int32_t* __restrict__ leaves,
+                                                          int64_t* __restrict__ hdr, int32_t* __restrict__ blk,
+                                                          int32_t* __restrict__ far_p, int32_t* __restrict__ far_t) {
+    constexpr int kLds = kThreads + kWin + 1;
+    __shared__ int s_lc[kLevels];   // inner nodes of this workgroup per level
+    __shared__ int s_cd[kLds];
+    __shared__ int s_m16[kLds / 16];
+    __shared__ int s_fp[kFarLds], s_ft[kFarLds];
+    __shared__ int s_fn, s_fbase;
+    if (threadIdx.x < kLevels) s_lc[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_fn = 0;
+    const int LW = kThreads + P.n_leaf + 1;   // positions held in s_cd
     const int64_t n_nodes = off[P.n];
     int maxl = 0;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
-         p += (int64_t)gridDim.x * blockDim.x) {
+    auto flush = [&]() {   // whole workgroup; s_fn entries in LDS
+        __syncthreads();
+        if (threadIdx.x == 0) s_fbase = s_fn ? atomicAdd(reinterpret_cast<int32_t*>(hdr + 3), s_fn) : 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < s_fn; i += kThreads) {
+            far_p[s_fbase + i] = s_fp[i];
+            far_t[s_fbase + i] = s_ft[i];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_fn = 0;
+    };
+    for (int64_t p0 = (int64_t)blockIdx.x * kThreads; p0 < P.n; p0 += (int64_t)gridDim.x * kThreads) {
+        __syncthreads();
+        if (s_fn > kFarLds - kThreads) flush();   // room for this run's entries
+        for (int k = threadIdx.x; k < LW; k += kThreads) {
+            const int64_t q = p0 + k;
+            s_cd[k] = q < P.n ? cd[q] : -1;   // -1 past the end: it ends every cell
+        }
+        __syncthreads();
+        if (threadIdx.x < LW / 16) {
+            int m = s_cd[16 * threadIdx.x];
+            for (int j = 1; j < 16; ++j) m = min(m, s_cd[16 * threadIdx.x + j]);
+            s_m16[threadIdx.x] = m;
+        }
+        __syncthreads();
+        const int64_t p = p0 + threadIdx.x;
+        if (p >= P.n) continue;
         const int k = off[p + 1] - off[p];
         if (k == 0) continue;
-        const int c = cd[p];
-        for (int t = 0; t < k; ++t) {
+        const int c = s_cd[threadIdx.x];
+        int j = (int)threadIdx.x + 1;   // search position (window index)
+        bool far = false;
+        for (int t = k - 1; t >= 0; --t) {
             const int l = c + 1 + t;
-            const int64_t id = off[p] + t;
-            int64_t e = small_cell_end(P, cd, p, l);
-            if (e < 0) e = cell_end(P, keys, p, l);
-            const int64_t skip = e < P.n ? (int64_t)off[e] : n_nodes;
+            int64_t e = -1;
+            if (!far) {
+                for (; j < LW && (j & 15); ++j)
+                    if (s_cd[j] < l) { e = p0 + j; break; }
+                if (e < 0) {
+                    for (; j + 16 <= LW && s_m16[j >> 4] >= l; j += 16) {}
+                    for (; j < LW; ++j)
+                        if (s_cd[j] < l) { e = p0 + j; break; }
+                }
+                if (e < 0) {   // beyond the window: this node and the ones above it
+                    far = true;
+                    const int q = atomicAdd(&s_fn, 1);
+                    s_fp[q] = (int)p;
+                    s_ft[q] = t;
+                }
+            }
             const bool leaf = (t == k - 1);
-            link[id] = make_int4((int)skip, (int)p, (int)(e - p), l | (leaf ? 0x100 : 0));
+            const int64_t id = off[p] + t;
+            const int skip = far ? 0 : (int)(e < P.n ? (int64_t)off[e] : n_nodes);
+            link[id] = make_int4(skip, (int)p, far ? 0 : (int)(e - p), l | (leaf ? 0x100 : 0));
             if (!leaf) {
                 ilist[ioff[p] + t] = (int32_t)id;
                 atomicAdd(&s_lc[l], 1);
@@ -646,18 +838,18 @@ __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, c
             maxl = l > maxl ? l : maxl;
         }
     }
-    __syncthreads();
-    if (threadIdx.x <= AG_MAX_LEVEL && s_lc[threadIdx.x] > 0)
-        atomicAdd(reinterpret_cast<int32_t*>(hdr + 8) + kLvlCnt + threadIdx.x, s_lc[threadIdx.x]);
-    // per-block deepest level (reduced by k_tree_close, no global atomics)
+    flush();
+    // per-workgroup inner nodes per level and deepest level, reduced by k_tree_close
     __shared__ int s_max[kThreads / 64];
     maxl = ag_wave_max(maxl);
     if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = maxl;
     __syncthreads();
+    int32_t* row = blk + (int64_t)blockIdx.x * (kLevels + 1);
+    if (threadIdx.x < kLevels) row[threadIdx.x] = s_lc[threadIdx.x];
     if (threadIdx.x == 0) {
         int mb = s_max[0];
-        for (int w = 1; w < kThreads / 64; ++w) mb = s_max[w] > mb ? s_max[w] : mb;
-        blk_max[blockIdx.x] = mb;
+        for (int w2 = 1; w2 < kThreads / 64; ++w2) mb = s_max[w2] > mb ? s_max[w2] : mb;
+        row[kLevels] = mb;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hdr[0] = n_nodes;
@@ -665,21 +857,109 @@ __global__ void k_write_nodes(TopoParams P, const uint64_t* __restrict__ keys, c
     }
 }
 
-// One block closes the topology: hdr[1] = deepest level (from the per-block
-// maxima of k_write_nodes) and the root node of every system.
-__global__ void k_tree_close(int nblk, const int32_t* __restrict__ blk_max, int64_t* __restrict__ hdr, int n_sys,
+// Entries at level k of the shared-digit minima (k = -1: the counts
+// themselves), each covering 16^(k + 1) positions; INT_MAX past the end.
+__device__ __forceinline__ int cd_level(int64_t n, const int32_t* __restrict__ cd, const CdMin& M, int k,
+                                        int64_t j) {
+    if (k < 0) return j < n ? cd[j] : INT_MAX;
+    const int64_t span = (int64_t)1 << (4 * (k + 1));
+    return j < (n + span - 1) / span ? M.lev[k][j] : INT_MAX;
+}
+
+// next_below for a group of 16 lanes (lane s = 0..15 of the group; every
+// lane of the group takes the same path): climb from q, reading at each
+// level the entries up to the next boundary of the level above (all of them
+// start at or after the positions already passed), until one holds a count
+// below l; then descend through its 16 children per level.  About two loads
+// per level of the distance instead of up to sixteen.
+__device__ int64_t next_below16(int64_t n, const int32_t* __restrict__ cd, const CdMin& M, int64_t q, int l,
+                                int s) {
+    if (q >= n) return n;
+    const int gsh = ag_lane() & 48;   // the group's bits in a wave ballot
+    int k = -1;
+    int64_t cur = q;   // aligned to the span of level k
+    int64_t i;
+    for (;;) {
+        const int sh = 4 * (k + 1);
+        const int64_t idx = cur >> sh;
+        const int64_t lim = ((idx >> 4) + 1) << 4;
+        const int64_t j = idx + s;
+        const int v = j < lim ? cd_level(n, cd, M, k, j) : INT_MAX;
+        const unsigned hit = (unsigned)(__ballot(v < l) >> gsh) & 0xffffu;
+        if (hit) {
+            i = idx + __builtin_ctz(hit);
+            break;
+        }
+        cur = lim << sh;
+        if (cur >= n) return n;
+        if (k < kCdLevels - 1) ++k;   // cur is now aligned to the next level's span
+    }
+    for (; k >= 0; --k) {
+        const int v = cd_level(n, cd, M, k - 1, 16 * i + s);
+        const unsigned hit = (unsigned)(__ballot(v < l) >> gsh) & 0xffffu;
+        i = 16 * i + __builtin_ctz(hit);   // the minimum below l lies in one of the children
+    }
+    return i;
+}
+
+// Skip and count fields of the nodes k_write_nodes listed: a group of 16
+// lanes per entry (p, t) takes the nodes t, t - 1, .. 0 at p, each end found
+// from the one below it, the first from the end of the window k_write_nodes
+// searched (no shared-digit count there is below the level of node t, so
+// none is below the levels above it either).
+__global__ void __launch_bounds__(kThreads) k_far_ends(TopoParams P, const int32_t* __restrict__ cd, CdMin M,
+                                                       const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ far_p,
+                                                       const int32_t* __restrict__ far_t,
+                                                       const int64_t* __restrict__ hdr, int4* __restrict__ link) {
+    const int64_t nq = hdr[3];
+    const int64_t n_nodes = off[P.n];
+    const int s = threadIdx.x & 15;
+    for (int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4; g < nq;
+         g += ((int64_t)gridDim.x * blockDim.x) >> 4) {
+        const int64_t p = far_p[g];
+        const int c = cd[p];
+        int64_t e = (p & ~(int64_t)(kThreads - 1)) + kThreads + P.n_leaf + 1;
+        for (int t = far_t[g]; t >= 0; --t) {
+            e = next_below16(P.n, cd, M, e, c + 1 + t, s);
+            if (s == 0) {
+                int4* L = link + off[p] + t;
+                L->x = (int)(e < P.n ? (int64_t)off[e] : n_nodes);
+                L->z = (int)(e - p);
+            }
+        }
+    }
+}
+
+// One block closes the topology: the inner nodes per level and hdr[1] =
+// deepest level (from the per-workgroup rows of k_write_nodes) and the root
+// node of every system.
+__global__ void k_tree_close(int nblk, const int32_t* __restrict__ blk, int64_t* __restrict__ hdr, int n_sys,
                              int sys_levels, const int64_t* __restrict__ off, const int32_t* __restrict__ cd,
                              const int32_t* __restrict__ noff, int32_t* __restrict__ root) {
-    int m = 0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = blk_max[b] > m ? blk_max[b] : m;
-    m = ag_wave_max(m);
-    __shared__ int s_m[16];
-    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __shared__ int s_sum[kLevels + 1][16];
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int v[kLevels + 1];
+#pragma unroll
+    for (int l = 0; l <= kLevels; ++l) v[l] = 0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {   // a row per thread: its loads all in flight
+        const int32_t* row = blk + (int64_t)b * (kLevels + 1);
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) v[l] += row[l];
+        v[kLevels] = row[kLevels] > v[kLevels] ? row[kLevels] : v[kLevels];
+    }
+#pragma unroll
+    for (int l = 0; l <= kLevels; ++l) {
+        const int r = l < kLevels ? ag_wave_sum(v[l]) : ag_wave_max(v[l]);
+        if ((threadIdx.x & 63) == 0) s_sum[l][w] = r;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = s_m[w] > m ? s_m[w] : m;
-        m = s_m[0] > m ? s_m[0] : m;
-        hdr[1] = m;
+    if (threadIdx.x <= kLevels) {
+        const int l = threadIdx.x;
+        int t = 0;
+        for (int k = 0; k < nw; ++k) t = l < kLevels ? t + s_sum[l][k] : (s_sum[l][k] > t ? s_sum[l][k] : t);
+        if (l < kLevels) reinterpret_cast<int32_t*>(hdr + 8)[kLvlCnt + l] = t;
+        else hdr[1] = t;
     }
     for (int s = threadIdx.x; s < n_sys; s += blockDim.x) {
         const int64_t p0 = off[s];
@@ -697,28 +977,73 @@ __global__ void k_tree_close(int nblk, const int32_t* __restrict__ blk_max, int6
 // nd_64 layout per node (25 doubles): M, c(3), u(3), Q(6), Qd(6), lo(3), hi(3)
 constexpr int kM64 = 25;
 
-// lo4.w holds the largest softening length in the node (0 without
-// per-particle softening)
-__device__ void store_node(int64_t id, const double* r, double4* __restrict__ com, float4* __restrict__ lo4,
-                           float4* __restrict__ hi4, float4* __restrict__ mp, double* __restrict__ m64,
-                           float hmax) {
-    double* o = m64 + id * kM64;
+struct NodeOut {
+    double4* com;
+    float4* lo4;
+    float4* hi4;
+    float4* mp;
+    double* m64;
+    const float* sh;   // sorted softening lengths, or null
+};
+
+__device__ __forceinline__ uint4 u4_d2(double a, double b) {
+    const unsigned long long x = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long y = (unsigned long long)__double_as_longlong(b);
+    return make_uint4((unsigned)x, (unsigned)(x >> 32), (unsigned)y, (unsigned)(y >> 32));
+}
+__device__ __forceinline__ uint4 u4_f4(float a, float b, float c, float d) {
+    return make_uint4(__float_as_uint(a), __float_as_uint(b), __float_as_uint(c), __float_as_uint(d));
+}
+
+// Writes node id's record from a group of eight lanes that all hold it
+// (lane s = 0..7), so that each store instruction writes whole runs: the 25
+// FP64 moments as runs of eight doubles, and the FP32 copies as one 16-byte
+// store per lane (centre of mass and extent in two, box low, box high, the
+// four packed multipole words).  lo4.w holds the largest softening length in
+// the node (0 without per-particle softening), hi4.w the mass.
+__device__ __forceinline__ void store_node8(int64_t id, int s, const double* r, const NodeOut& O, float hmax) {
+    // the lane's words are picked by masks, not by indexing or selects on
+    // s, which the compiler would turn into an indexed copy in scratch
+    unsigned long long m8[8];
 #pragma unroll
-    for (int k = 0; k < kM64; ++k) o[k] = r[k];
+    for (int k = 0; k < 8; ++k) m8[k] = 0ull - (unsigned long long)(s == k);
+    double* o = O.m64 + id * kM64;
+#pragma unroll
+    for (int b = 0; b < 24; b += 8) {
+        unsigned long long v = 0ull;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v |= (unsigned long long)__double_as_longlong(r[b + k]) & m8[k];
+        o[b + s] = __longlong_as_double((long long)v);
+    }
+    if (s == 0) o[24] = r[24];
     double L = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double e = r[22 + c] - r[19 + c];
+        const double e = r[22 + c] - r[19 + c];
         L = e > L ? e : L;
     }
-    com[id] = make_double4(r[1], r[2], r[3], L);
-    lo4[id] = make_float4(f_down(r[19]), f_down(r[20]), f_down(r[21]), hmax);
-    hi4[id] = make_float4(f_up(r[22]), f_up(r[23]), f_up(r[24]), (float)r[0]);   // w: mass
-    float4* q = mp + 4 * id;
-    q[0] = make_float4((float)r[0], (float)r[4], (float)r[5], (float)r[6]);
-    q[1] = make_float4((float)r[7], (float)r[8], (float)r[9], (float)r[10]);
-    q[2] = make_float4((float)r[11], (float)r[12], (float)r[13], (float)r[14]);
-    q[3] = make_float4((float)r[15], (float)r[16], (float)r[17], (float)r[18]);
+    const uint4 w0 = u4_d2(r[1], r[2]), w1 = u4_d2(r[3], L);
+    const uint4 w2 = u4_f4(f_down(r[19]), f_down(r[20]), f_down(r[21]), hmax);
+    const uint4 w3 = u4_f4(f_up(r[22]), f_up(r[23]), f_up(r[24]), (float)r[0]);
+    const uint4 w4 = u4_f4((float)r[0], (float)r[4], (float)r[5], (float)r[6]);
+    const uint4 w5 = u4_f4((float)r[7], (float)r[8], (float)r[9], (float)r[10]);
+    const uint4 w6 = u4_f4((float)r[11], (float)r[12], (float)r[13], (float)r[14]);
+    const uint4 w7 = u4_f4((float)r[15], (float)r[16], (float)r[17], (float)r[18]);
+    const uint4 w[8] = {w0, w1, w2, w3, w4, w5, w6, w7};
+    uint4 val = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const unsigned mk = (unsigned)m8[k];
+        val.x |= w[k].x & mk;
+        val.y |= w[k].y & mk;
+        val.z |= w[k].z & mk;
+        val.w |= w[k].w & mk;
+    }
+    uint4* dst = s < 2 ? reinterpret_cast<uint4*>(O.com + id) + s
+               : s == 2 ? reinterpret_cast<uint4*>(O.lo4 + id)
+               : s == 3 ? reinterpret_cast<uint4*>(O.hi4 + id)
+                        : reinterpret_cast<uint4*>(O.mp + 4 * id) + (s - 4);
+    *dst = val;
 }
 
 // Q  += m (3 y y^T - |y|^2 I),  Qd += m (3 (y w^T + w y^T) - 2 (y.w) I)
@@ -779,24 +1104,18 @@ struct MomentSums {
     // r: M, c(3), u(3), Q(6), Qd(6), lo(3), hi(3)
     __device__ void finish(double* r) const {
         r[0] = M;
-        const double Mi = M > 0.0 ? 1.0 / M : 0.0;
-        double E[3] = {0, 0, 0}, F[3] = {0, 0, 0};
+        // branch-free (a massless cell takes the centre of its box and
+        // velocity zero), which keeps r in registers
+        const bool pos = M > 0.0;
+        const double Mi = pos ? 1.0 / M : 0.0;
+        double E[3], F[3];
         for (int c = 0; c < 3; ++c) {
             r[19 + c] = lo[c];
             r[22 + c] = hi[c];
-        }
-        if (M > 0.0) {
-            for (int c = 0; c < 3; ++c) {
-                E[c] = e[c] * Mi;
-                F[c] = f[c] * Mi;
-                r[1 + c] = r0[c] + E[c];
-                r[4 + c] = u0[c] + F[c];
-            }
-        } else {   // massless cell: centre of its box, velocity zero
-            for (int c = 0; c < 3; ++c) {
-                r[1 + c] = 0.5 * (lo[c] + hi[c]);
-                r[4 + c] = 0.0;
-            }
+            E[c] = e[c] * Mi;
+            F[c] = f[c] * Mi;
+            r[1 + c] = pos ? r0[c] + E[c] : 0.5 * (lo[c] + hi[c]);
+            r[4 + c] = pos ? u0[c] + F[c] : 0.0;
         }
         double q[6], qd[6];
         for (int k = 0; k < 6; ++k) q[k] = qd[k] = 0.0;
@@ -808,32 +1127,45 @@ struct MomentSums {
     }
 };
 
-struct NodeOut {
-    double4* com;
-    float4* lo4;
-    float4* hi4;
-    float4* mp;
-    double* m64;
-    const float* sh;   // sorted softening lengths, or null
-};
-
-// sums over the eight lanes of one inner node (one lane per octant)
+// Reductions over the eight lanes of a group (aligned to eight, all
+// active) by DPP moves, which stay in the vector unit (no LDS permutes):
+// partners at xor 1 and xor 2 within each quad, then the mirror lane within
+// each eight (lane 7 - i, which is in the other quad).  Every lane ends with
+// the same bits: each step adds two values that are equal on both partners.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror
+template <int C> __device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, C, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), C, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int C> __device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), C, 0xF, 0xF, false));
+}
 __device__ __forceinline__ double oct_sum(double v) {
-    v += __shfl_xor(v, 1, 8);
-    v += __shfl_xor(v, 2, 8);
-    v += __shfl_xor(v, 4, 8);
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
     return v;
 }
 __device__ __forceinline__ double oct_min(double v) {
-    v = fmin(v, __shfl_xor(v, 1, 8));
-    v = fmin(v, __shfl_xor(v, 2, 8));
-    v = fmin(v, __shfl_xor(v, 4, 8));
+    v = fmin(v, dpp_f64<kDppXor1>(v));
+    v = fmin(v, dpp_f64<kDppXor2>(v));
+    v = fmin(v, dpp_f64<kDppHalfMirror>(v));
     return v;
 }
 __device__ __forceinline__ double oct_max(double v) {
-    v = fmax(v, __shfl_xor(v, 1, 8));
-    v = fmax(v, __shfl_xor(v, 2, 8));
-    v = fmax(v, __shfl_xor(v, 4, 8));
+    v = fmax(v, dpp_f64<kDppXor1>(v));
+    v = fmax(v, dpp_f64<kDppXor2>(v));
+    v = fmax(v, dpp_f64<kDppHalfMirror>(v));
+    return v;
+}
+__device__ __forceinline__ float oct_maxf(float v) {
+    v = fmaxf(v, dpp_f32<kDppXor1>(v));
+    v = fmaxf(v, dpp_f32<kDppXor2>(v));
+    v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
     return v;
 }
 __device__ __forceinline__ void oct_reduce(MomentSums& S) {
@@ -847,34 +1179,6 @@ __device__ __forceinline__ void oct_reduce(MomentSums& S) {
     for (int k = 0; k < 6; ++k) {
         S.Q[k] = oct_sum(S.Q[k]);
         S.Qd[k] = oct_sum(S.Qd[k]);
-    }
-}
-
-// every leaf from its particles (one thread per leaf of the dense leaf list;
-// a leaf's particles are contiguous and its record is written by one lane,
-// which keeps the scattered node writes to one instruction per field)
-__global__ void k_leaf_moments(const int64_t* __restrict__ hdr, const int32_t* __restrict__ leaves,
-                               const int4* __restrict__ link, const double4* __restrict__ spos,
-                               const double4* __restrict__ svel, NodeOut O) {
-    const int64_t nl = hdr[0] - hdr[2];
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nl;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int id = leaves[t];
-        const int4 L = link[id];
-        MomentSums S;
-        S.init();
-        float hm = 0.f;
-        for (int q = L.y; q < L.y + L.z; ++q) {
-            const double4 a = spos[q];
-            const double4 u = svel[q];
-            const double x[3] = {a.x, a.y, a.z}, v[3] = {u.x, u.y, u.z};
-            S.add(a.w, x, v);
-            S.box(x, x);
-            if (O.sh) hm = fmaxf(hm, O.sh[q]);
-        }
-        double r[kM64];
-        S.finish(r);
-        store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64, hm);
     }
 }
 
@@ -934,52 +1238,97 @@ __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restr
     }
 }
 
-// inner nodes of one level from their children (one launch per level, from
-// the deepest up, so every child is complete when its parent is combined).
-// Eight lanes per node, one per octant: each lane forms its child's terms
-// about the first child's centre of mass and velocity, and the eight lanes
-// sum them by shuffles.
-__global__ void __launch_bounds__(kThreads) k_inner_level(int level, const int32_t* __restrict__ lvl,
+// Forms inner node id (inner index in) from its children, one lane per
+// octant of a group of eight lanes, all active: each lane forms its child's
+// terms about the first child's centre of mass and velocity, and the eight
+// lanes sum them by shuffles.
+__device__ void form_inner(int in, int id, int oct, const int32_t* __restrict__ child, const NodeOut& O) {
+    const int ch = child[8 * (int64_t)in + oct];
+    // the first octant that holds a child supplies the reference point
+    const uint64_t occ = __ballot(ch >= 0);
+    const unsigned gm = (unsigned)((occ >> (ag_lane() & ~7)) & 0xffu);   // every inner node has a child
+    const int chf = gm ? child[8 * (int64_t)in + __builtin_ctz(gm)] : -1;
+    MomentSums S;
+    S.init();
+    for (int c = 0; c < 3; ++c) {
+        S.r0[c] = chf >= 0 ? O.m64[(int64_t)chf * kM64 + 1 + c] : 0.0;
+        S.u0[c] = chf >= 0 ? O.m64[(int64_t)chf * kM64 + 4 + c] : 0.0;
+    }
+    S.first = false;
+    if (ch >= 0) {
+        const double* cm = O.m64 + (int64_t)ch * kM64;
+        S.add(cm[0], cm + 1, cm + 4);
+        for (int k = 0; k < 6; ++k) {
+            S.Q[k] += cm[7 + k];
+            S.Qd[k] += cm[13 + k];
+        }
+        S.box(cm + 19, cm + 22);
+    }
+    oct_reduce(S);
+    const float hm = oct_maxf(ch >= 0 ? O.lo4[ch].w : 0.f);
+    double r[kM64];
+    S.finish(r);
+    store_node8(id, oct, r, O, hm);
+}
+
+// Every leaf from its particles: a group of eight lanes per leaf (leaf list
+// order, so a wave reads a contiguous run of particles), each lane summing
+// every eighth particle about the leaf's first one, the eight sums added by
+// shuffles and the record written by the whole group.
+__global__ void __launch_bounds__(kThreads) k_leaf_moments(const int64_t* __restrict__ hdr,
+                                                           const int32_t* __restrict__ leaves,
+                                                           const int4* __restrict__ link,
+                                                           const double4* __restrict__ spos,
+                                                           const double4* __restrict__ svel, NodeOut O) {
+    const int64_t nl = hdr[0] - hdr[2];
+    const int s = threadIdx.x & 7;
+    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) >> 3;
+    for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3; g < nl; g += stride) {
+        const int id = leaves[g];
+        const int4 L = link[id];
+        MomentSums S;
+        S.init();
+        {
+            const double4 a = spos[L.y], u = svel[L.y];
+            S.r0[0] = a.x; S.r0[1] = a.y; S.r0[2] = a.z;
+            S.u0[0] = u.x; S.u0[1] = u.y; S.u0[2] = u.z;
+            S.first = false;
+        }
+        float hm = 0.f;
+        for (int q = L.y + s; q < L.y + L.z; q += 8) {
+            const double4 a = spos[q];
+            const double4 u = svel[q];
+            const double x[3] = {a.x, a.y, a.z}, v[3] = {u.x, u.y, u.z};
+            S.add(a.w, x, v);
+            S.box(x, x);
+            if (O.sh) hm = fmaxf(hm, O.sh[q]);
+        }
+        oct_reduce(S);
+        hm = oct_maxf(hm);
+        double r[kM64];
+        S.finish(r);
+        store_node8(id, s, r, O, hm);
+    }
+}
+
+// Inner nodes of levels l_hi down to l_lo from their children, eight lanes
+// per node: one level per launch (l_hi = l_lo, any grid; launched from the
+// deepest up, so every child is complete when its parent is formed), or
+// several in a single-workgroup launch, the workgroup barrier between levels
+// ordering each level after its children's.
+__global__ void __launch_bounds__(kThreads) k_inner_level(int l_hi, int l_lo, const int32_t* __restrict__ lvl,
                                                           const int32_t* __restrict__ lvl_list,
                                                           const int32_t* __restrict__ ilist,
                                                           const int32_t* __restrict__ child, NodeOut O) {
-    const int t_lo = lvl[kLvlOff + level], t_hi = lvl[kLvlOff + level + 1];
     const int oct = threadIdx.x & 7;
     const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
     const int64_t nslot = ((int64_t)gridDim.x * blockDim.x) >> 3;
-    for (int64_t t = t_lo + slot; t < t_hi; t += nslot) {   // uniform over the eight lanes
-        const int in = lvl_list[t];
-        const int id = ilist[in];
-        const int ch = child[8 * (int64_t)in + oct];
-        // the first octant that holds a child supplies the reference point
-        const uint64_t occ = __ballot(ch >= 0);
-        const unsigned gm = (unsigned)((occ >> (ag_lane() & ~7)) & 0xffu);   // every inner node has a child
-        const int chf = gm ? child[8 * (int64_t)in + __builtin_ctz(gm)] : -1;
-        MomentSums S;
-        S.init();
-        for (int c = 0; c < 3; ++c) {
-            S.r0[c] = chf >= 0 ? O.m64[(int64_t)chf * kM64 + 1 + c] : 0.0;
-            S.u0[c] = chf >= 0 ? O.m64[(int64_t)chf * kM64 + 4 + c] : 0.0;
-        }
-        S.first = false;
-        if (ch >= 0) {
-            const double* cm = O.m64 + (int64_t)ch * kM64;
-            S.add(cm[0], cm + 1, cm + 4);
-            for (int k = 0; k < 6; ++k) {
-                S.Q[k] += cm[7 + k];
-                S.Qd[k] += cm[13 + k];
-            }
-            S.box(cm + 19, cm + 22);
-        }
-        oct_reduce(S);
-        float hm = ch >= 0 ? O.lo4[ch].w : 0.f;
-        hm = fmaxf(hm, __shfl_xor(hm, 1, 8));
-        hm = fmaxf(hm, __shfl_xor(hm, 2, 8));
-        hm = fmaxf(hm, __shfl_xor(hm, 4, 8));
-        if (oct == 0) {
-            double r[kM64];
-            S.finish(r);
-            store_node(id, r, O.com, O.lo4, O.hi4, O.mp, O.m64, hm);
+    for (int level = l_hi; level >= l_lo; --level) {
+        if (level < l_hi) __syncthreads();   // single-workgroup launches only
+        const int t_lo = lvl[kLvlOff + level], t_hi = lvl[kLvlOff + level + 1];
+        for (int64_t t = t_lo + slot; t < t_hi; t += nslot) {   // uniform over the eight lanes
+            const int in = lvl_list[t];
+            form_inner(in, ilist[in], oct, child, O);
         }
     }
 }
@@ -995,12 +1344,18 @@ int grid_for(int64_t n, int threads = kThreads) {
     return (int)(b < 1 ? 1 : b);
 }
 
+// Moments: the leaves, then the inner levels from the deepest up.  The
+// levels below the deepest of the last build whose depth the host has seen
+// (c->seen_max_level; 20 if none) take one single-workgroup launch (they are
+// usually empty), the levels from there to 3 one launch each, and levels 2-0
+// (at most 73 nodes) one single-workgroup launch.  A deeper tree than
+// expected is still complete, only slower.
 int moments_pass(ag_ctx* c) {
     hipStream_t st = c->stream;
     NodeOut O{c->nd_com.as<double4>(), c->nd_lo.as<float4>(), c->nd_hi.as<float4>(), c->nd_mp.as<float4>(),
               c->nd_64.as<double>(), c->tree_soft ? c->soft_s.as<float>() : nullptr};
     const int64_t n = c->n;
-    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(n / 4 + 1)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
+    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(8 * n)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
                        c->leaf_list.as<int32_t>(), c->nd_link.as<int4>(), c->spos.as<double4>(),
                        c->svel.as<double4>(), O);
     // level-21 cells are always leaves; empty levels exit at once
@@ -1008,9 +1363,19 @@ int moments_pass(ag_ctx* c) {
     int g = grid_for(8 * (inner_bound > 0 ? inner_bound : 1));
     if (g > 1024) g = 1024;
     const int32_t* lvl = reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8);
-    for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
-        hipLaunchKernelGGL(k_inner_level, dim3(g), dim3(kThreads), 0, st, l, lvl, c->lvl_list.as<int32_t>(),
-                           c->in_list.as<int32_t>(), c->child.as<int32_t>(), O);
+    constexpr int kTop = 2;
+    int lc = c->seen_max_level - 1;   // inner nodes lie above the deepest level
+    if (c->seen_max_level < 0 || lc > AG_MAX_LEVEL - 1) lc = AG_MAX_LEVEL - 1;
+    if (lc < kTop + 1) lc = kTop;
+    const int32_t* ll = c->lvl_list.as<int32_t>();
+    const int32_t* il = c->in_list.as<int32_t>();
+    const int32_t* ch = c->child.as<int32_t>();
+    if (lc < AG_MAX_LEVEL - 1)
+        hipLaunchKernelGGL(k_inner_level, dim3(1), dim3(kThreads), 0, st, AG_MAX_LEVEL - 1, lc + 1, lvl, ll, il, ch,
+                           O);
+    for (int l = lc; l > kTop; --l)
+        hipLaunchKernelGGL(k_inner_level, dim3(g), dim3(kThreads), 0, st, l, l, lvl, ll, il, ch, O);
+    hipLaunchKernelGGL(k_inner_level, dim3(1), dim3(kThreads), 0, st, kTop, 0, lvl, ll, il, ch, O);
     return AG_OK;
 }
 
@@ -1031,11 +1396,29 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     AG_TRY(ag_ensure(c, c->keys[0], n * 8)); AG_TRY(ag_ensure(c, c->keys[1], n * 8));
     AG_TRY(ag_ensure(c, c->vals[0], n * 4)); AG_TRY(ag_ensure(c, c->vals[1], n * 4));
     const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
-    AG_TRY(ag_ensure(c, c->sort_hist, (size_t)(256 * nblocks + 256 + 1) * 4));
+    // (also the bounding boxes' per-workgroup partials before the sort, and
+    // k_write_nodes' per-workgroup rows after it)
+    const int wblocks = std::min(grid_for(n), kWriteBlocks);
+    AG_TRY(ag_ensure(c, c->sort_hist, std::max({(size_t)(256 * nblocks + 256 + 1) * 4,
+                                                (size_t)(n / kBoxChunk + n_sys + 1) * 6 * sizeof(uint64_t),
+                                                (size_t)wblocks * (kLevels + 1) * sizeof(int32_t)})));
     AG_TRY(ag_ensure(c, c->pos_off, (size_t)(256 * (int64_t)nblocks + 1 > n + 1 ? 256 * (int64_t)nblocks + 1 : n + 1) * 4));
     AG_TRY(ag_ensure(c, c->perm, n * 4)); AG_TRY(ag_ensure(c, c->rank, n * 4));
     AG_TRY(ag_ensure(c, c->spos, n * 32)); AG_TRY(ag_ensure(c, c->svel, n * 32)); AG_TRY(ag_ensure(c, c->svf, n * 16));
     AG_TRY(ag_ensure(c, c->cdig, n * 4)); AG_TRY(ag_ensure(c, c->pos_cnt, (n + 1) * 4));
+    // minima of the shared-digit counts: level 0 per 16 positions (16 per run of
+    // 256), levels k >= 1 per 16^(k+1)
+    int64_t cd_cnt[kCdLevels], cd_tot = 0;
+    const int64_t passes = (n + kCdPass - 1) / kCdPass;   // k_cdig writes levels 0-2 for whole passes
+    cd_cnt[0] = passes * 256;
+    cd_cnt[1] = passes * 16;
+    cd_cnt[2] = passes;
+    for (int k = 3; k < kCdLevels; ++k) {
+        const int64_t span = (int64_t)1 << (4 * (k + 1));
+        cd_cnt[k] = (n + span - 1) / span;
+    }
+    for (int k = 0; k < kCdLevels; ++k) cd_tot += cd_cnt[k];
+    AG_TRY(ag_ensure(c, c->cd_min, (size_t)cd_tot * sizeof(int32_t)));
     AG_TRY(ag_ensure(c, c->nd_com, max_nodes * 32)); AG_TRY(ag_ensure(c, c->nd_lo, max_nodes * 16));
     AG_TRY(ag_ensure(c, c->nd_hi, max_nodes * 16)); AG_TRY(ag_ensure(c, c->nd_link, max_nodes * 16));
     AG_TRY(ag_ensure(c, c->nd_mp, max_nodes * 64)); AG_TRY(ag_ensure(c, c->nd_64, max_nodes * kM64 * 8));
@@ -1048,6 +1431,11 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     AG_TRY(ag_ensure(c, c->child, (size_t)(inner_bound > 0 ? inner_bound : 1) * 32));
     AG_TRY(ag_ensure(c, c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
 
+    if (c->depth_pending && !c->capturing && hipEventQuery(c->depth_ev) == hipSuccess) {
+        c->seen_max_level = (int)*c->depth_host;
+        c->depth_pending = false;
+    }
+
     PhaseScope phase(c, AG_PHASE_BUILD);
     hipStream_t st = c->stream;
     int32_t* flags = c->dflags.as<int32_t>();
@@ -1057,11 +1445,21 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     // 1. bounding cubes
     uint64_t* box = c->sys_box.as<uint64_t>();
     int32_t* blk_off = reinterpret_cast<int32_t*>(box + 6 * n_sys);
+    CdMin M;
+    {
+        int32_t* q = c->cd_min.as<int32_t>();
+        for (int k = 0; k < kCdLevels; ++k) {
+            M.lev[k] = q;
+            q += cd_cnt[k];
+        }
+    }
     hipLaunchKernelGGL(k_build_init, dim3(1), dim3(512), 0, st, n_sys, n, sys_offsets, off, flags, box, blk_off, hdr,
                        (int)(kTreeHdrBytes / 8));
     const int64_t box_blocks = n / kBoxChunk + n_sys + 1;
-    hipLaunchKernelGGL(k_box, dim3((unsigned)box_blocks), dim3(kThreads), 0, st, x, off, n_sys, blk_off, box, flags,
-                       c->box);
+    uint64_t* box_part = reinterpret_cast<uint64_t*>(c->sort_hist.p);   // free until the sort
+    hipLaunchKernelGGL(k_box, dim3((unsigned)box_blocks), dim3(kBoxThreads), 0, st, x, off, n_sys, blk_off, box_part,
+                       flags, c->box);
+    hipLaunchKernelGGL(k_box_reduce, dim3((unsigned)n_sys), dim3(256), 0, st, n_sys, blk_off, box_part, box);
 
     // 2. keys
     uint64_t* k0 = c->keys[0].as<uint64_t>();
@@ -1112,7 +1510,13 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
 
     // 5. topology
     int32_t* cd = c->cdig.as<int32_t>();
-    hipLaunchKernelGGL(k_cdig, dim3(grid_for(n)), dim3(kThreads), 0, st, n, k0, cd);
+    {
+        int64_t cb = passes < 4096 ? passes : 4096;
+        hipLaunchKernelGGL(k_cdig, dim3((unsigned)cb), dim3(kRun), 0, st, n, k0, cd, M);
+        CdCounts C;
+        for (int k = 0; k < kCdLevels; ++k) C.cnt[k] = cd_cnt[k];
+        hipLaunchKernelGGL(k_cd_min_top, dim3(1), dim3(1024), 0, st, M, C);
+    }
     TopoParams P{n, n_leaf, sys_levels};
     int32_t* pcnt = c->pos_cnt.as<int32_t>();
     int32_t* poff = c->pos_off.as<int32_t>();
@@ -1121,12 +1525,21 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     hipLaunchKernelGGL(k_count_nodes, dim3(grid_for(n)), dim3(kThreads), 0, st, P, cd, pcnt, icnt);
     AG_TRY(ag_scan_i32(c, pcnt, poff, n));
     AG_TRY(ag_scan_i32(c, icnt, ioff, n));
-    const int wblocks = grid_for(n);
-    int32_t* blk_max = c->sort_hist.as<int32_t>();   // free after the sort; >= 256 nblocks entries
-    hipLaunchKernelGGL(k_write_nodes, dim3(wblocks), dim3(kThreads), 0, st, P, k0, cd, poff, ioff,
-                       c->nd_link.as<int4>(), c->in_list.as<int32_t>(), c->leaf_list.as<int32_t>(), hdr, blk_max);
-    hipLaunchKernelGGL(k_tree_close, dim3(1), dim3(1024), 0, st, wblocks, blk_max, hdr, n_sys, sys_levels, off, cd,
+    // (the node counts are free after their scans: they hold the list of far
+    // ends; the sort's histograms hold the per-workgroup rows)
+    int32_t* blk_rows = c->sort_hist.as<int32_t>();
+    hipLaunchKernelGGL(k_write_nodes, dim3(wblocks), dim3(kThreads), 0, st, P, cd, poff, ioff,
+                       c->nd_link.as<int4>(), c->in_list.as<int32_t>(), c->leaf_list.as<int32_t>(), hdr, blk_rows,
+                       pcnt, icnt);
+    hipLaunchKernelGGL(k_far_ends, dim3(grid_for(n / 16 + 1)), dim3(kThreads), 0, st, P, cd, M, poff, pcnt, icnt,
+                       hdr, c->nd_link.as<int4>());
+    hipLaunchKernelGGL(k_tree_close, dim3(1), dim3(1024), 0, st, wblocks, blk_rows, hdr, n_sys, sys_levels, off, cd,
                        poff, c->sys_root.as<int32_t>());
+    if (!c->capturing && c->depth_host) {   // this tree's depth, for the next build's launch plan
+        (void)hipMemcpyAsync(c->depth_host, hdr + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+        (void)hipEventRecord(c->depth_ev, st);
+        c->depth_pending = true;
+    }
     hipLaunchKernelGGL(k_level_lists, dim3(grid_for(inner_bound) < 1024 ? grid_for(inner_bound) : 1024),
                        dim3(kThreads), 0, st, hdr, c->in_list.as<int32_t>(), c->nd_link.as<int4>(), k0,
                        c->child.as<int4>(), reinterpret_cast<int32_t*>(hdr + 8), c->lvl_list.as<int32_t>());
