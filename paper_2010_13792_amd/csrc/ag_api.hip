@@ -201,7 +201,7 @@ extern "C" int ag_destroy(ag_ctx* c) {
                       &c->rank, &c->spos, &c->svel, &c->svf, &c->cdig, &c->cd_min, &c->pos_cnt, &c->pos_off,
                       &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
                       &c->nd_64, &c->nd_w, &c->nd_wf, &c->in_list, &c->in_cnt, &c->in_off,
-                      &c->tree_hdr, &c->lvl_list, &c->leaf_list, &c->child, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
+                      &c->tree_hdr, &c->lvl_list, &c->leaf_list, &c->leaf_pos, &c->child, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,
                       &c->act_pos, &c->act_off, &c->grp, &c->grp_hdr, &c->ewald_tab, &c->ewald_q, &c->soft_h, &c->soft_s, &c->rel_a, &c->pm_brk, &c->grp_cnt, &c->grp_off, &c->sys_act, &c->wsorted,
                       &c->direct_part, &c->tmp_tidal, &c->sel_flag, &c->sel_off, &c->stats, &c->dflags};
     for (DevBuf* b : bufs) ag_release(*b);

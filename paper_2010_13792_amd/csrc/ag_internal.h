@@ -120,9 +120,10 @@ struct ag_ctx {
     DevBuf in_list;               // i32 [max_nodes]: inner nodes in pre-order
     DevBuf in_cnt, in_off;        // i32 [n+1]: inner nodes starting at each position, offsets
     DevBuf tree_hdr;              // i64 [8]: n_nodes, max_level, inner nodes; then the level table (kLvl*)
-    DevBuf lvl_list;              // i32 [inner bound]: inner nodes grouped by level
+    DevBuf lvl_list;              // i32 [inner bound]: inner node ids grouped by level
     DevBuf leaf_list;             // i32 [n]: leaf node ids in pre-order
-    DevBuf child;                 // i32 [8 x inner bound]: children of each inner node by octant (-1: none)
+    DevBuf leaf_pos;              // i32 [n+1]: first position of each leaf, then n
+    DevBuf child;                 // i32 [8 x inner bound]: children by octant (-1: none) of the node in the same lvl_list slot
 
     DevBuf sys_off;               // i64 [n_sys+1]
     DevBuf sys_root;              // i32 [n_sys]: root node per system

@@ -245,7 +245,7 @@ __global__ void k_keys(int64_t n, const double* __restrict__ x, const int64_t* _
 // ---------------------------------------------------------------------------
 // 3. stable LSD radix sort, 8 bits per pass
 // ---------------------------------------------------------------------------
-constexpr int kRsItems = 8;
+constexpr int kRsItems = 16;
 constexpr int kRsTile = kThreads * kRsItems;
 
 __global__ void __launch_bounds__(kThreads) k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
@@ -301,11 +301,15 @@ __global__ void __launch_bounds__(kThreads) k_rs_rowscan(const int32_t* __restri
     if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-// Stable scatter of one tile of (key, value) pairs by one 8-bit digit.  The
-// tile is first ranked and reordered by digit in LDS (ballot matching within
-// each wave, per-wave counts across the block), then written out in digit
-// order so that each digit's run goes to consecutive addresses.  With `rank`
-// set (last pass), rank[value] receives the value's final position.
+// Stable scatter of one tile of (key, value) pairs by one 8-bit digit.  Each
+// wave ranks its own contiguous run of the tile (kRsItems rows of 64) with no
+// workgroup barrier: lanes with equal digits are matched by ballots, and the
+// wave keeps a running count per digit in its own LDS row, read by all the
+// matched lanes before their first lane adds the group's size.  One scan per
+// digit over the four waves then places every element in the tile's
+// digit-ordered LDS copy, which is written out so that each digit's run goes
+// to consecutive addresses.  With `rank` set (last pass), rank[value]
+// receives the value's final position.
 __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restrict__ kin,
                                                          const int32_t* __restrict__ vin, int64_t n,
                                                          int shift, int nblocks,
@@ -319,26 +323,35 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restr
     __shared__ int s_val[kRsTile];
     __shared__ int s_gofs[256];   // global position of the tile's first digit-d element minus its tile slot
     __shared__ int s_loc[256];    // tile slot of the first digit-d element
-    __shared__ int s_run[256];
-    __shared__ int s_w[4][256];
+    __shared__ int s_w[4][256];   // per-wave digit counts, then per-wave offsets within the digit
     __shared__ int s_tmp[kThreads / 64];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     {
         int all;
         const int base_d = block_excl_scan256(tot[t], s_tmp, &all);
         const int loc = block_excl_scan256(hist[(int64_t)t * nblocks + blockIdx.x], s_tmp, &all);
         s_loc[t] = loc;
         s_gofs[t] = base_d + hoff[(int64_t)t * nblocks + blockIdx.x] - loc;
-        s_run[t] = 0;
     }
-    const int w = t >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_w[q][t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * (kRsItems * 64);
+    uint64_t key[kRsItems];
+    int32_t val[kRsItems];
+    int rk[kRsItems];
+#pragma unroll
     for (int k = 0; k < kRsItems; ++k) {
-        const int64_t i = base + k * kThreads + t;
+        const int64_t i = base + k * 64 + lane;
         const bool valid = i < n;
-        const uint64_t key = valid ? kin[i] : 0ull;
-        const int32_t val = valid ? vin[i] : 0;
-        const int d = (int)((key >> shift) & 255);
+        key[k] = valid ? kin[i] : 0ull;
+        val[k] = valid ? vin[i] : 0;
+    }
+    int* cnt_w = s_w[w];
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+        const bool valid = base + k * 64 + lane < n;
+        const int d = (int)((key[k] >> shift) & 255);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -347,61 +360,82 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restr
             peers &= bit ? bb : ~bb;
         }
         const int r = ag_prefix_count(peers);
-        const int cnt = __popcll(peers);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s_w[q][t] = 0;
-        __syncthreads();
-        if (valid && r == 0) s_w[w][d] = cnt;
-        __syncthreads();
-        {
-            int run = s_run[t];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = s_w[q][t];
-                s_w[q][t] = run;
-                run += c;
-            }
-            s_run[t] = run;
-        }
-        __syncthreads();
-        if (valid) {
-            const int slot = s_loc[d] + s_w[w][d] + r;
-            s_key[slot] = key;
-            s_val[slot] = val;
-        }
-        __syncthreads();
+        int before = 0;
+        if (valid) before = cnt_w[d];   // every matched lane reads the count ...
+        if (valid && r == 0) cnt_w[d] = before + __popcll(peers);   // ... before the first one adds to it
+        rk[k] = before + r;
     }
-    const int64_t rem = n - base;
+    __syncthreads();
+    {
+        int run = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = s_w[q][t];
+            s_w[q][t] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+        if (base + k * 64 + lane < n) {
+            const int d = (int)((key[k] >> shift) & 255);
+            const int slot = s_loc[d] + cnt_w[d] + rk[k];
+            s_key[slot] = key[k];
+            s_val[slot] = val[k];
+        }
+    }
+    __syncthreads();
+    const int64_t rem = n - (int64_t)blockIdx.x * kRsTile;
     const int nvalid = rem < kRsTile ? (int)rem : kRsTile;
     for (int j = t; j < nvalid; j += kThreads) {
-        const uint64_t key = s_key[j];
-        const int d = (int)((key >> shift) & 255);
+        const uint64_t kj = s_key[j];
+        const int d = (int)((kj >> shift) & 255);
         const int pos = s_gofs[d] + j;
-        kout[pos] = key;
-        const int32_t val = s_val[j];
-        vout[pos] = val;
-        if (rank) rank[val] = pos;
+        kout[pos] = kj;
+        const int32_t vj = s_val[j];
+        vout[pos] = vj;
+        if (rank) rank[vj] = pos;
     }
+}
+
+int grid_for(int64_t n, int threads = kThreads) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b > 8192) b = 8192;
+    return (int)(b < 1 ? 1 : b);
 }
 
 // ---------------------------------------------------------------------------
 // 4. particle data into key order: coalesced reads in input order, each row
-//    written to its sorted position (scattered 32-byte stores)
+//    written to its sorted position (scattered 32-byte stores).  Positions
+//    and velocities go in two passes, so that the lines each pass scatters
+//    into stay few enough to be merged in the last-level cache before they
+//    reach HBM; the FP32 velocity copies are written later, in order, by
+//    the leaf moments.
 // ---------------------------------------------------------------------------
-__global__ void k_to_sorted(int64_t n, const int32_t* __restrict__ rank, const double* __restrict__ x,
-                            const double* __restrict__ v, const double* __restrict__ m,
-                            double4* __restrict__ spos, double4* __restrict__ svel, float4* __restrict__ svf,
-                            double pbox, const double* __restrict__ h, float* __restrict__ sh) {
+__global__ void k_to_sorted_pos(int64_t n, const int32_t* __restrict__ rank, const double* __restrict__ x,
+                                const double* __restrict__ m, double4* __restrict__ spos, double pbox,
+                                const double* __restrict__ h, float* __restrict__ sh) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t p = rank[i];
-        const double mi = m[i];
-        const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
-        spos[p] = make_double4(in_box(x[3 * i], pbox), in_box(x[3 * i + 1], pbox), in_box(x[3 * i + 2], pbox), mi);
-        svel[p] = make_double4(vx, vy, vz, 0.0);
-        svf[p] = make_float4((float)vx, (float)vy, (float)vz, (float)mi);
+        spos[p] = make_double4(in_box(x[3 * i], pbox), in_box(x[3 * i + 1], pbox), in_box(x[3 * i + 2], pbox), m[i]);
         if (h) sh[p] = f_up(h[i]);   // per-particle softening, rounded up
     }
+}
+__global__ void k_to_sorted_vel(int64_t n, const int32_t* __restrict__ rank, const double* __restrict__ v,
+                                double4* __restrict__ svel) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        svel[rank[i]] = make_double4(v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0);
+}
+void launch_to_sorted(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m, double pbox) {
+    const int32_t* rank = c->rank.as<int32_t>();
+    hipLaunchKernelGGL(k_to_sorted_pos, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, rank, x, m,
+                       c->spos.as<double4>(), pbox, c->tree_soft ? c->soft_h.as<double>() : nullptr,
+                       c->soft_s.as<float>());
+    hipLaunchKernelGGL(k_to_sorted_vel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, rank, v,
+                       c->svel.as<double4>());
 }
 
 // ---------------------------------------------------------------------------
@@ -762,6 +796,7 @@ __global__ void __launch_bounds__(kThreads) k_write_nodes(TopoParams P, const in
                                                           const int32_t* __restrict__ off,
                                                           const int32_t* __restrict__ ioff, int4* __restrict__ link,
                                                           int32_t* __restrict__ ilist, int32_t* __restrict__ leaves,
+                                                          int32_t* __restrict__ leaf_pos,
                                                           int64_t* __restrict__ hdr, int32_t* __restrict__ blk,
                                                           int32_t* __restrict__ far_p, int32_t* __restrict__ far_t) {
     constexpr int kLds = kThreads + kWin + 1;
@@ -833,7 +868,9 @@ __global__ void __launch_bounds__(kThreads) k_write_nodes(TopoParams P, const in
                 ilist[ioff[p] + t] = (int32_t)id;
                 atomicAdd(&s_lc[l], 1);
             } else {
-                leaves[off[p] - ioff[p]] = (int32_t)id;   // leaves before p = nodes - inner nodes before p
+                const int64_t lf = off[p] - ioff[p];   // leaves before p = nodes - inner nodes before p
+                leaves[lf] = (int32_t)id;
+                leaf_pos[lf] = (int32_t)p;
             }
             maxl = l > maxl ? l : maxl;
         }
@@ -932,9 +969,10 @@ __global__ void __launch_bounds__(kThreads) k_far_ends(TopoParams P, const int32
 }
 
 // One block closes the topology: the inner nodes per level and hdr[1] =
-// deepest level (from the per-workgroup rows of k_write_nodes) and the root
-// node of every system.
-__global__ void k_tree_close(int nblk, const int32_t* __restrict__ blk, int64_t* __restrict__ hdr, int n_sys,
+// deepest level (from the per-workgroup rows of k_write_nodes), the end of
+// the leaves' start list, and the root node of every system.
+__global__ void k_tree_close(int nblk, const int32_t* __restrict__ blk, int64_t* __restrict__ hdr,
+                             int32_t* __restrict__ leaf_pos, int64_t n, int n_sys,
                              int sys_levels, const int64_t* __restrict__ off, const int32_t* __restrict__ cd,
                              const int32_t* __restrict__ noff, int32_t* __restrict__ root) {
     __shared__ int s_sum[kLevels + 1][16];
@@ -961,6 +999,7 @@ __global__ void k_tree_close(int nblk, const int32_t* __restrict__ blk, int64_t*
         if (l < kLevels) reinterpret_cast<int32_t*>(hdr + 8)[kLvlCnt + l] = t;
         else hdr[1] = t;
     }
+    if (threadIdx.x == 0) leaf_pos[hdr[0] - hdr[2]] = (int32_t)n;
     for (int s = threadIdx.x; s < n_sys; s += blockDim.x) {
         const int64_t p0 = off[s];
         if (off[s + 1] <= p0) {
@@ -995,55 +1034,61 @@ __device__ __forceinline__ uint4 u4_f4(float a, float b, float c, float d) {
     return make_uint4(__float_as_uint(a), __float_as_uint(b), __float_as_uint(c), __float_as_uint(d));
 }
 
-// Writes node id's record from a group of eight lanes that all hold it
-// (lane s = 0..7), so that each store instruction writes whole runs: the 25
-// FP64 moments as runs of eight doubles, and the FP32 copies as one 16-byte
-// store per lane (centre of mass and extent in two, box low, box high, the
-// four packed multipole words).  lo4.w holds the largest softening length in
-// the node (0 without per-particle softening), hi4.w the mass.
-__device__ __forceinline__ void store_node8(int64_t id, int s, const double* r, const NodeOut& O, float hmax) {
+// Writes node id's record from a group of G lanes (aligned to G, all
+// active) that all hold it (lane s = 0..G-1), so that each store instruction
+// writes whole runs: the 25 FP64 moments as runs of G doubles, and the FP32
+// copies as 16-byte words, word s of every G (centre of mass and extent in
+// two, box low, box high, the four packed multipole words).  lo4.w holds the
+// largest softening length in the node (0 without per-particle softening),
+// hi4.w the mass.
+template <int G>
+__device__ __forceinline__ void store_node_g(int64_t id, int s, const double* r, const NodeOut& O, float hmax) {
     // the lane's words are picked by masks, not by indexing or selects on
     // s, which the compiler would turn into an indexed copy in scratch
-    unsigned long long m8[8];
+    unsigned long long mk[G];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) m8[k] = 0ull - (unsigned long long)(s == k);
+    for (int k = 0; k < G; ++k) mk[k] = 0ull - (unsigned long long)(s == k);
     double* o = O.m64 + id * kM64;
 #pragma unroll
-    for (int b = 0; b < 24; b += 8) {
+    for (int b = 0; b < kM64; b += G) {
         unsigned long long v = 0ull;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v |= (unsigned long long)__double_as_longlong(r[b + k]) & m8[k];
-        o[b + s] = __longlong_as_double((long long)v);
+        for (int k = 0; k < G; ++k)
+            if (b + k < kM64) v |= (unsigned long long)__double_as_longlong(r[b + k]) & mk[k];
+        if (b + s < kM64) o[b + s] = __longlong_as_double((long long)v);
     }
-    if (s == 0) o[24] = r[24];
     double L = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double e = r[22 + c] - r[19 + c];
         L = e > L ? e : L;
     }
-    const uint4 w0 = u4_d2(r[1], r[2]), w1 = u4_d2(r[3], L);
-    const uint4 w2 = u4_f4(f_down(r[19]), f_down(r[20]), f_down(r[21]), hmax);
-    const uint4 w3 = u4_f4(f_up(r[22]), f_up(r[23]), f_up(r[24]), (float)r[0]);
-    const uint4 w4 = u4_f4((float)r[0], (float)r[4], (float)r[5], (float)r[6]);
-    const uint4 w5 = u4_f4((float)r[7], (float)r[8], (float)r[9], (float)r[10]);
-    const uint4 w6 = u4_f4((float)r[11], (float)r[12], (float)r[13], (float)r[14]);
-    const uint4 w7 = u4_f4((float)r[15], (float)r[16], (float)r[17], (float)r[18]);
-    const uint4 w[8] = {w0, w1, w2, w3, w4, w5, w6, w7};
-    uint4 val = make_uint4(0u, 0u, 0u, 0u);
+    const uint4 w[8] = {u4_d2(r[1], r[2]),
+                        u4_d2(r[3], L),
+                        u4_f4(f_down(r[19]), f_down(r[20]), f_down(r[21]), hmax),
+                        u4_f4(f_up(r[22]), f_up(r[23]), f_up(r[24]), (float)r[0]),
+                        u4_f4((float)r[0], (float)r[4], (float)r[5], (float)r[6]),
+                        u4_f4((float)r[7], (float)r[8], (float)r[9], (float)r[10]),
+                        u4_f4((float)r[11], (float)r[12], (float)r[13], (float)r[14]),
+                        u4_f4((float)r[15], (float)r[16], (float)r[17], (float)r[18])};
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const unsigned mk = (unsigned)m8[k];
-        val.x |= w[k].x & mk;
-        val.y |= w[k].y & mk;
-        val.z |= w[k].z & mk;
-        val.w |= w[k].w & mk;
+    for (int b = 0; b < 8; b += G) {
+        uint4 val = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const unsigned m = (unsigned)mk[k];
+            val.x |= w[b + k].x & m;
+            val.y |= w[b + k].y & m;
+            val.z |= w[b + k].z & m;
+            val.w |= w[b + k].w & m;
+        }
+        const int wi = b + s;
+        uint4* dst = wi < 2 ? reinterpret_cast<uint4*>(O.com + id) + wi
+                   : wi == 2 ? reinterpret_cast<uint4*>(O.lo4 + id)
+                   : wi == 3 ? reinterpret_cast<uint4*>(O.hi4 + id)
+                             : reinterpret_cast<uint4*>(O.mp + 4 * id) + (wi - 4);
+        *dst = val;
     }
-    uint4* dst = s < 2 ? reinterpret_cast<uint4*>(O.com + id) + s
-               : s == 2 ? reinterpret_cast<uint4*>(O.lo4 + id)
-               : s == 3 ? reinterpret_cast<uint4*>(O.hi4 + id)
-                        : reinterpret_cast<uint4*>(O.mp + 4 * id) + (s - 4);
-    *dst = val;
 }
 
 // Q  += m (3 y y^T - |y|^2 I),  Qd += m (3 (y w^T + w y^T) - 2 (y.w) I)
@@ -1127,11 +1172,12 @@ struct MomentSums {
     }
 };
 
-// Reductions over the eight lanes of a group (aligned to eight, all
-// active) by DPP moves, which stay in the vector unit (no LDS permutes):
-// partners at xor 1 and xor 2 within each quad, then the mirror lane within
-// each eight (lane 7 - i, which is in the other quad).  Every lane ends with
-// the same bits: each step adds two values that are equal on both partners.
+// Reductions over the G lanes of a group (G = 2, 4 or 8, aligned to G,
+// all active) by DPP moves, which stay in the vector unit (no LDS
+// permutes): partners at xor 1 and xor 2 within each quad, then the mirror
+// lane within each eight (lane 7 - i, which is in the other quad).  Every
+// lane ends with the same bits: each step adds two values that are equal on
+// both partners.
 constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
 constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141;  // row_half_mirror
@@ -1144,50 +1190,52 @@ template <int C> __device__ __forceinline__ double dpp_f64(double v) {
 template <int C> __device__ __forceinline__ float dpp_f32(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), C, 0xF, 0xF, false));
 }
-__device__ __forceinline__ double oct_sum(double v) {
-    v += dpp_f64<kDppXor1>(v);
-    v += dpp_f64<kDppXor2>(v);
-    v += dpp_f64<kDppHalfMirror>(v);
+template <int G> __device__ __forceinline__ double grp_sum(double v) {
+    if (G >= 2) v += dpp_f64<kDppXor1>(v);
+    if (G >= 4) v += dpp_f64<kDppXor2>(v);
+    if (G >= 8) v += dpp_f64<kDppHalfMirror>(v);
     return v;
 }
-__device__ __forceinline__ double oct_min(double v) {
-    v = fmin(v, dpp_f64<kDppXor1>(v));
-    v = fmin(v, dpp_f64<kDppXor2>(v));
-    v = fmin(v, dpp_f64<kDppHalfMirror>(v));
+template <int G> __device__ __forceinline__ double grp_min(double v) {
+    if (G >= 2) v = fmin(v, dpp_f64<kDppXor1>(v));
+    if (G >= 4) v = fmin(v, dpp_f64<kDppXor2>(v));
+    if (G >= 8) v = fmin(v, dpp_f64<kDppHalfMirror>(v));
     return v;
 }
-__device__ __forceinline__ double oct_max(double v) {
-    v = fmax(v, dpp_f64<kDppXor1>(v));
-    v = fmax(v, dpp_f64<kDppXor2>(v));
-    v = fmax(v, dpp_f64<kDppHalfMirror>(v));
+template <int G> __device__ __forceinline__ double grp_max(double v) {
+    if (G >= 2) v = fmax(v, dpp_f64<kDppXor1>(v));
+    if (G >= 4) v = fmax(v, dpp_f64<kDppXor2>(v));
+    if (G >= 8) v = fmax(v, dpp_f64<kDppHalfMirror>(v));
     return v;
 }
-__device__ __forceinline__ float oct_maxf(float v) {
-    v = fmaxf(v, dpp_f32<kDppXor1>(v));
-    v = fmaxf(v, dpp_f32<kDppXor2>(v));
-    v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
+template <int G> __device__ __forceinline__ float grp_maxf(float v) {
+    if (G >= 2) v = fmaxf(v, dpp_f32<kDppXor1>(v));
+    if (G >= 4) v = fmaxf(v, dpp_f32<kDppXor2>(v));
+    if (G >= 8) v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
     return v;
 }
-__device__ __forceinline__ void oct_reduce(MomentSums& S) {
-    S.M = oct_sum(S.M);
+template <int G> __device__ __forceinline__ void grp_reduce(MomentSums& S) {
+    S.M = grp_sum<G>(S.M);
     for (int c = 0; c < 3; ++c) {
-        S.e[c] = oct_sum(S.e[c]);
-        S.f[c] = oct_sum(S.f[c]);
-        S.lo[c] = oct_min(S.lo[c]);
-        S.hi[c] = oct_max(S.hi[c]);
+        S.e[c] = grp_sum<G>(S.e[c]);
+        S.f[c] = grp_sum<G>(S.f[c]);
+        S.lo[c] = grp_min<G>(S.lo[c]);
+        S.hi[c] = grp_max<G>(S.hi[c]);
     }
     for (int k = 0; k < 6; ++k) {
-        S.Q[k] = oct_sum(S.Q[k]);
-        S.Qd[k] = oct_sum(S.Qd[k]);
+        S.Q[k] = grp_sum<G>(S.Q[k]);
+        S.Qd[k] = grp_sum<G>(S.Qd[k]);
     }
 }
 
-// For every inner node: its children by octant (-1 where an octant is
+// For every inner node: its place in the list of inner nodes grouped by
+// level (order within a level is immaterial: every block ranks its nodes per
+// level in LDS and takes one slot range per level with a global atomic;
+// block 0 also writes the level offsets), where the slot receives the node's
+// id and, in the child rows, its children by octant (-1 where an octant is
 // empty), from the pre-order links (the first child follows the node, the
-// next follows the first child's subtree, ...), and its place in the list of
-// inner-node indices grouped by level (order within a level is immaterial:
-// every block ranks its nodes per level in LDS and takes one slot range per
-// level with a global atomic; block 0 also writes the level offsets).
+// next follows the first child's subtree, ...).  A level's kernels then read
+// a node and its children from the same slot.
 __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restrict__ hdr,
                                                           const int32_t* __restrict__ ilist,
                                                           const int4* __restrict__ link,
@@ -1210,22 +1258,19 @@ __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restr
     if (blockIdx.x == 0 && threadIdx.x <= AG_MAX_LEVEL + 1) lvl[kLvlOff + threadIdx.x] = s_off[threadIdx.x];
     for (int64_t t0 = (int64_t)blockIdx.x * kThreads; t0 < ni; t0 += (int64_t)gridDim.x * kThreads) {
         const int64_t t = t0 + threadIdx.x;
-        int id = -1, l = 0, r = 0;
+        int node = -1, l = 0, r = 0;
+        int c8[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
         if (t < ni) {
-            const int node = ilist[t];
+            node = ilist[t];
             const int4 L = link[node];
             l = L.w & 0xff;
-            id = (int)t;   // listed by inner index
             r = atomicAdd(&s_cnt[l], 1);
             const int sh = 63 - 3 * (l + 1);   // the children's own octal digit
-            int c8[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
             for (int ch = node + 1, k8 = 0; ch < L.x && k8 < 8; ++k8) {
                 const int4 C = link[ch];
                 c8[(int)((keys[C.y] >> sh) & 7)] = ch;
                 ch = C.x;
             }
-            child[2 * t] = make_int4(c8[0], c8[1], c8[2], c8[3]);
-            child[2 * t + 1] = make_int4(c8[4], c8[5], c8[6], c8[7]);
         }
         __syncthreads();
         if (threadIdx.x <= AG_MAX_LEVEL && s_cnt[threadIdx.x] > 0) {
@@ -1233,21 +1278,28 @@ __global__ void __launch_bounds__(kThreads) k_level_lists(const int64_t* __restr
             s_cnt[threadIdx.x] = 0;
         }
         __syncthreads();
-        if (id >= 0) lvl_list[s_off[l] + s_base[l] + r] = id;
+        if (node >= 0) {
+            const int64_t slot = s_off[l] + s_base[l] + r;
+            lvl_list[slot] = node;
+            child[2 * slot] = make_int4(c8[0], c8[1], c8[2], c8[3]);
+            child[2 * slot + 1] = make_int4(c8[4], c8[5], c8[6], c8[7]);
+        }
         __syncthreads();
     }
 }
 
-// Forms inner node id (inner index in) from its children, one lane per
-// octant of a group of eight lanes, all active: each lane forms its child's
-// terms about the first child's centre of mass and velocity, and the eight
-// lanes sum them by shuffles.
-__device__ void form_inner(int in, int id, int oct, const int32_t* __restrict__ child, const NodeOut& O) {
-    const int ch = child[8 * (int64_t)in + oct];
-    // the first octant that holds a child supplies the reference point
-    const uint64_t occ = __ballot(ch >= 0);
-    const unsigned gm = (unsigned)((occ >> (ag_lane() & ~7)) & 0xffu);   // every inner node has a child
-    const int chf = gm ? child[8 * (int64_t)in + __builtin_ctz(gm)] : -1;
+// Forms inner node id (child row in) from its children with a group of G
+// lanes (aligned to G, all active), lane s taking octants s, s + G, ...:
+// each lane forms its children's terms about the first child's centre of
+// mass and velocity, and the lanes sum them by DPP moves.
+template <int G>
+__device__ void form_inner(int in, int id, int s, const int32_t* __restrict__ child, const NodeOut& O) {
+    const int4 ca = reinterpret_cast<const int4*>(child)[2 * (int64_t)in];
+    const int4 cb = reinterpret_cast<const int4*>(child)[2 * (int64_t)in + 1];
+    const int c8[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+    int chf = -1;   // the first octant that holds a child supplies the reference point
+#pragma unroll
+    for (int k = 7; k >= 0; --k) chf = c8[k] >= 0 ? c8[k] : chf;
     MomentSums S;
     S.init();
     for (int c = 0; c < 3; ++c) {
@@ -1255,81 +1307,94 @@ __device__ void form_inner(int in, int id, int oct, const int32_t* __restrict__ 
         S.u0[c] = chf >= 0 ? O.m64[(int64_t)chf * kM64 + 4 + c] : 0.0;
     }
     S.first = false;
-    if (ch >= 0) {
-        const double* cm = O.m64 + (int64_t)ch * kM64;
-        S.add(cm[0], cm + 1, cm + 4);
-        for (int k = 0; k < 6; ++k) {
-            S.Q[k] += cm[7 + k];
-            S.Qd[k] += cm[13 + k];
+    float hm = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8 / G; ++j) {
+        int ch = 0;   // c8[s + j G], picked by masks (no indexing by the lane number)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ch |= c8[k] & -(int)(k == s + j * G);
+        if (ch >= 0) {
+            const double* cm = O.m64 + (int64_t)ch * kM64;
+            S.add(cm[0], cm + 1, cm + 4);
+            for (int k = 0; k < 6; ++k) {
+                S.Q[k] += cm[7 + k];
+                S.Qd[k] += cm[13 + k];
+            }
+            S.box(cm + 19, cm + 22);
+            hm = fmaxf(hm, O.lo4[ch].w);
         }
-        S.box(cm + 19, cm + 22);
     }
-    oct_reduce(S);
-    const float hm = oct_maxf(ch >= 0 ? O.lo4[ch].w : 0.f);
+    grp_reduce<G>(S);
+    hm = grp_maxf<G>(hm);
     double r[kM64];
     S.finish(r);
-    store_node8(id, oct, r, O, hm);
+    store_node_g<G>(id, s, r, O, hm);
 }
 
-// Every leaf from its particles: a group of eight lanes per leaf (leaf list
-// order, so a wave reads a contiguous run of particles), each lane summing
-// every eighth particle about the leaf's first one, the eight sums added by
-// shuffles and the record written by the whole group.
+// Every leaf from its particles: a group of kLeafLanes lanes per leaf (leaf
+// list order, so a wave reads a contiguous run of particles), each lane
+// summing every kLeafLanes-th particle about the leaf's first one, the sums
+// added across the group by DPP moves and the record written by the whole
+// group.  The FP32 copies of the velocities and masses (for the walk) are
+// written here as well, in order.
+constexpr int kLeafLanes = 4;
+constexpr int kInnerLanes = 8;
 __global__ void __launch_bounds__(kThreads) k_leaf_moments(const int64_t* __restrict__ hdr,
                                                            const int32_t* __restrict__ leaves,
-                                                           const int4* __restrict__ link,
+                                                           const int32_t* __restrict__ leaf_pos,
                                                            const double4* __restrict__ spos,
-                                                           const double4* __restrict__ svel, NodeOut O) {
+                                                           const double4* __restrict__ svel,
+                                                           float4* __restrict__ svf, NodeOut O) {
+    constexpr int G = kLeafLanes;
     const int64_t nl = hdr[0] - hdr[2];
-    const int s = threadIdx.x & 7;
-    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) >> 3;
-    for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3; g < nl; g += stride) {
+    const int s = threadIdx.x & (G - 1);
+    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / G;
+    for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; g < nl; g += stride) {
         const int id = leaves[g];
-        const int4 L = link[id];
+        const int p0 = leaf_pos[g], p1 = leaf_pos[g + 1];   // the leaves cover the positions in order
         MomentSums S;
         S.init();
         {
-            const double4 a = spos[L.y], u = svel[L.y];
+            const double4 a = spos[p0], u = svel[p0];
             S.r0[0] = a.x; S.r0[1] = a.y; S.r0[2] = a.z;
             S.u0[0] = u.x; S.u0[1] = u.y; S.u0[2] = u.z;
             S.first = false;
         }
         float hm = 0.f;
-        for (int q = L.y + s; q < L.y + L.z; q += 8) {
+        for (int q = p0 + s; q < p1; q += G) {
             const double4 a = spos[q];
             const double4 u = svel[q];
+            svf[q] = make_float4((float)u.x, (float)u.y, (float)u.z, (float)a.w);
             const double x[3] = {a.x, a.y, a.z}, v[3] = {u.x, u.y, u.z};
             S.add(a.w, x, v);
             S.box(x, x);
             if (O.sh) hm = fmaxf(hm, O.sh[q]);
         }
-        oct_reduce(S);
-        hm = oct_maxf(hm);
+        grp_reduce<G>(S);
+        hm = grp_maxf<G>(hm);
         double r[kM64];
         S.finish(r);
-        store_node8(id, s, r, O, hm);
+        store_node_g<G>(id, s, r, O, hm);
     }
 }
 
-// Inner nodes of levels l_hi down to l_lo from their children, eight lanes
-// per node: one level per launch (l_hi = l_lo, any grid; launched from the
+// Inner nodes of levels l_hi down to l_lo from their children, kInnerLanes
+// lanes per node: one level per launch (l_hi = l_lo, any grid; launched from the
 // deepest up, so every child is complete when its parent is formed), or
 // several in a single-workgroup launch, the workgroup barrier between levels
 // ordering each level after its children's.
 __global__ void __launch_bounds__(kThreads) k_inner_level(int l_hi, int l_lo, const int32_t* __restrict__ lvl,
                                                           const int32_t* __restrict__ lvl_list,
-                                                          const int32_t* __restrict__ ilist,
                                                           const int32_t* __restrict__ child, NodeOut O) {
-    const int oct = threadIdx.x & 7;
-    const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-    const int64_t nslot = ((int64_t)gridDim.x * blockDim.x) >> 3;
+    constexpr int G = kInnerLanes;
+    const int s = threadIdx.x & (G - 1);
+    const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t nslot = ((int64_t)gridDim.x * blockDim.x) / G;
     for (int level = l_hi; level >= l_lo; --level) {
         if (level < l_hi) __syncthreads();   // single-workgroup launches only
         const int t_lo = lvl[kLvlOff + level], t_hi = lvl[kLvlOff + level + 1];
-        for (int64_t t = t_lo + slot; t < t_hi; t += nslot) {   // uniform over the eight lanes
-            const int in = lvl_list[t];
-            form_inner(in, ilist[in], oct, child, O);
-        }
+        for (int64_t t = t_lo + slot; t < t_hi; t += nslot)   // uniform over the group
+            form_inner<G>((int)t, lvl_list[t], s, child, O);
     }
 }
 
@@ -1337,11 +1402,6 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
-}
-int grid_for(int64_t n, int threads = kThreads) {
-    int64_t b = (n + threads - 1) / threads;
-    if (b > 8192) b = 8192;
-    return (int)(b < 1 ? 1 : b);
 }
 
 // Moments: the leaves, then the inner levels from the deepest up.  The
@@ -1355,12 +1415,12 @@ int moments_pass(ag_ctx* c) {
     NodeOut O{c->nd_com.as<double4>(), c->nd_lo.as<float4>(), c->nd_hi.as<float4>(), c->nd_mp.as<float4>(),
               c->nd_64.as<double>(), c->tree_soft ? c->soft_s.as<float>() : nullptr};
     const int64_t n = c->n;
-    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(8 * n)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
-                       c->leaf_list.as<int32_t>(), c->nd_link.as<int4>(), c->spos.as<double4>(),
-                       c->svel.as<double4>(), O);
+    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(kLeafLanes * n)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
+                       c->leaf_list.as<int32_t>(), c->leaf_pos.as<int32_t>(), c->spos.as<double4>(),
+                       c->svel.as<double4>(), c->svf.as<float4>(), O);
     // level-21 cells are always leaves; empty levels exit at once
     const int64_t inner_bound = c->max_nodes - n;
-    int g = grid_for(8 * (inner_bound > 0 ? inner_bound : 1));
+    int g = grid_for(kInnerLanes * (inner_bound > 0 ? inner_bound : 1));
     if (g > 1024) g = 1024;
     const int32_t* lvl = reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8);
     constexpr int kTop = 2;
@@ -1368,14 +1428,12 @@ int moments_pass(ag_ctx* c) {
     if (c->seen_max_level < 0 || lc > AG_MAX_LEVEL - 1) lc = AG_MAX_LEVEL - 1;
     if (lc < kTop + 1) lc = kTop;
     const int32_t* ll = c->lvl_list.as<int32_t>();
-    const int32_t* il = c->in_list.as<int32_t>();
     const int32_t* ch = c->child.as<int32_t>();
     if (lc < AG_MAX_LEVEL - 1)
-        hipLaunchKernelGGL(k_inner_level, dim3(1), dim3(kThreads), 0, st, AG_MAX_LEVEL - 1, lc + 1, lvl, ll, il, ch,
-                           O);
+        hipLaunchKernelGGL(k_inner_level, dim3(1), dim3(kThreads), 0, st, AG_MAX_LEVEL - 1, lc + 1, lvl, ll, ch, O);
     for (int l = lc; l > kTop; --l)
-        hipLaunchKernelGGL(k_inner_level, dim3(g), dim3(kThreads), 0, st, l, l, lvl, ll, il, ch, O);
-    hipLaunchKernelGGL(k_inner_level, dim3(1), dim3(kThreads), 0, st, kTop, 0, lvl, ll, il, ch, O);
+        hipLaunchKernelGGL(k_inner_level, dim3(g), dim3(kThreads), 0, st, l, l, lvl, ll, ch, O);
+    hipLaunchKernelGGL(k_inner_level, dim3(1), dim3(kThreads), 0, st, kTop, 0, lvl, ll, ch, O);
     return AG_OK;
 }
 
@@ -1428,6 +1486,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     const int64_t inner_bound = max_nodes - n;   // inner nodes never exceed this
     AG_TRY(ag_ensure(c, c->lvl_list, (size_t)(inner_bound > 0 ? inner_bound : 1) * 4));
     AG_TRY(ag_ensure(c, c->leaf_list, n * 4));   // at most one leaf starts at each position
+    AG_TRY(ag_ensure(c, c->leaf_pos, (n + 1) * 4));
     AG_TRY(ag_ensure(c, c->child, (size_t)(inner_bound > 0 ? inner_bound : 1) * 32));
     AG_TRY(ag_ensure(c, c->sys_box, 6 * n_sys * 8 + 8 * (n_sys + 1)));
 
@@ -1503,9 +1562,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     // 4. particle data into key order
     c->tree_soft = c->soft_n > 0;
     if (c->tree_soft) AG_TRY(ag_ensure(c, c->soft_s, (size_t)n * sizeof(float)));
-    hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rank, x, v, m,
-                       c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->box,
-                       c->tree_soft ? c->soft_h.as<double>() : nullptr, c->soft_s.as<float>());
+    launch_to_sorted(c, n, x, v, m, c->box);
     c->tree_box = c->box;
 
     // 5. topology
@@ -1529,11 +1586,13 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     // ends; the sort's histograms hold the per-workgroup rows)
     int32_t* blk_rows = c->sort_hist.as<int32_t>();
     hipLaunchKernelGGL(k_write_nodes, dim3(wblocks), dim3(kThreads), 0, st, P, cd, poff, ioff,
-                       c->nd_link.as<int4>(), c->in_list.as<int32_t>(), c->leaf_list.as<int32_t>(), hdr, blk_rows,
+                       c->nd_link.as<int4>(), c->in_list.as<int32_t>(), c->leaf_list.as<int32_t>(),
+                       c->leaf_pos.as<int32_t>(), hdr, blk_rows,
                        pcnt, icnt);
     hipLaunchKernelGGL(k_far_ends, dim3(grid_for(n / 16 + 1)), dim3(kThreads), 0, st, P, cd, M, poff, pcnt, icnt,
                        hdr, c->nd_link.as<int4>());
-    hipLaunchKernelGGL(k_tree_close, dim3(1), dim3(1024), 0, st, wblocks, blk_rows, hdr, n_sys, sys_levels, off, cd,
+    hipLaunchKernelGGL(k_tree_close, dim3(1), dim3(1024), 0, st, wblocks, blk_rows, hdr, c->leaf_pos.as<int32_t>(),
+                       n, n_sys, sys_levels, off, cd,
                        poff, c->sys_root.as<int32_t>());
     if (!c->capturing && c->depth_host) {   // this tree's depth, for the next build's launch plan
         (void)hipMemcpyAsync(c->depth_host, hdr + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st);
@@ -1557,8 +1616,6 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
 int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m) {
     const int64_t n = c->n;
     PhaseScope phase(c, AG_PHASE_BUILD);
-    hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, c->rank.as<int32_t>(), x,
-                       v, m, c->spos.as<double4>(), c->svel.as<double4>(), c->svf.as<float4>(), c->tree_box,
-                       c->tree_soft ? c->soft_h.as<double>() : nullptr, c->soft_s.as<float>());
+    launch_to_sorted(c, n, x, v, m, c->tree_box);
     return moments_pass(c);
 }

@@ -2057,14 +2057,13 @@ __global__ void k_leaf_wmoments(const int64_t* __restrict__ hdr, const int32_t* 
 //   W1_bc  = sum (W1_bc + W0_b dl_c)
 //   W2_bce = sum (W2_bce + W1_bc dl_e + W1_be dl_c + W0_b dl_c dl_e)
 __global__ void k_inner_wlevel(int level, const int32_t* __restrict__ lvl, const int32_t* __restrict__ lvl_list,
-                               const int32_t* __restrict__ ilist, const int4* __restrict__ child,
+                               const int4* __restrict__ child,
                                const double* __restrict__ m64, double* __restrict__ w64, float4* __restrict__ wf) {
     const int t_lo = lvl[kLvlOff + level], t_hi = lvl[kLvlOff + level + 1];
     for (int64_t t = t_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t_hi;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int in = lvl_list[t];
-        const int id = ilist[in];
-        const int4 c0 = child[2 * in], c1 = child[2 * in + 1];
+        const int id = lvl_list[t];   // a level's nodes and their child rows share slots
+        const int4 c0 = child[2 * t], c1 = child[2 * t + 1];
         const int ch8[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
         const double* c = m64 + (int64_t)id * 25 + 1;
         double r[kW64];
@@ -2358,7 +2357,7 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
     for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_inner_wlevel, dim3(g), dim3(256), 0, st, l,
                            reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8),
-                           c->lvl_list.as<int32_t>(), c->in_list.as<int32_t>(), c->child.as<int4>(),
+                           c->lvl_list.as<int32_t>(), c->child.as<int4>(),
                            c->nd_64.as<double>(),
                            c->nd_w.as<double>(), c->nd_wf.as<float4>());
     int64_t mg = 0;
