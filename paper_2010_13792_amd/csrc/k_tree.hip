@@ -776,21 +776,74 @@ __global__ void __launch_bounds__(kThreads) k_seg_sort(TopoParams P, const int32
     }
 }
 
-// Writes every node's link and lists the inner nodes (in pre-order).  The
-// end of the cell of node (l, p) is the first q > p with cd'[q] < l; ends do
-// not decrease from the deepest node at p (the leaf) to the shallowest, so
-// each search continues from the end below it, in the LDS window (this run
-// and n_leaf + 1 beyond, with minima per 16).  A node whose end lies beyond
-// the window, and every node above it at p, is left to k_far_ends: p and the
-// deepest such node go to a list (their skip and count fields are written
-// there), so the long searches run on their own instead of stalling the
-// waves of this kernel.  The list is gathered per workgroup in LDS and
-// appended with one global atomic per flush; the inner nodes per level and
-// the deepest level go to per-workgroup slots that k_tree_close adds up, so
-// no address is shared by the workgroups' atomics.
+// Writes every node's link and lists the inner nodes (in pre-order) and the
+// leaves with their first positions.  The end of the cell of node (l, p) is
+// the first q > p with cd'[q] < l; ends do not decrease from the deepest node
+// at p (the leaf) to the shallowest, so each search continues from the end
+// below it.  Every wave works on its own run of 64 positions with its own LDS
+// window (the run and kWaveLook positions past it: the shared-digit counts,
+// their minima per 16 and the node offsets, so a skip inside the window
+// costs no global load), and no wave waits at a workgroup barrier for
+// another's searches.  A node whose
+// end lies beyond the window, and every node above it at p, is left to
+// k_far_ends: p and the deepest such node go to a list (their skip and count
+// fields are written there), gathered per wave in LDS and appended to the
+// global list with one atomic per workgroup (or per wave when its LDS list
+// fills).  The inner nodes per level and the deepest level go to
+// per-workgroup slots that k_tree_close adds up.
 constexpr int kWriteBlocks = 2048;   // eight workgroups per CU at most
-constexpr int kFarLds = 1024;        // far entries held in LDS between flushes
+constexpr int kWaveLook = 208;       // positions searched past a wave's run (>= n_leaf + 1)
+constexpr int kWaveWin = 64 + kWaveLook;   // 17 runs of 16
+constexpr int kWinRuns = kWaveWin / 16;
+constexpr int kFarWave = 256;        // far entries held per wave between flushes
 constexpr int kLevels = AG_MAX_LEVEL + 1;
+
+// orders a wave's LDS accesses around it (the wave's lanes share the window)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// index of the first entry at or after j in one run of 16 window entries
+// (four 16-byte reads) that is below l, or INT_MAX
+__device__ __forceinline__ int run_first_below(const int* __restrict__ cdw, int run, int j, int l) {
+    int r = INT_MAX;
+#pragma unroll
+    for (int g = 3; g >= 0; --g) {   // from the back: the first hit wins
+        const int4 v = reinterpret_cast<const int4*>(cdw)[4 * run + g];
+        const int b = 16 * run + 4 * g;
+        r = (b + 3 >= j && v.w < l) ? b + 3 : r;
+        r = (b + 2 >= j && v.z < l) ? b + 2 : r;
+        r = (b + 1 >= j && v.y < l) ? b + 1 : r;
+        r = (b >= j && v.x < l) ? b : r;
+    }
+    return r;
+}
+
+// First window index q >= j with a shared-digit count below l, or kWaveWin
+// if none: the run holding j, then the first later run whose minimum is
+// below l (all kWinRuns minima read at once), then that run.  Fixed-length
+// reads instead of a scan that stops at the hit keep the scalar unit, which
+// the divergent loops of a scan keep busy, free.
+__device__ __forceinline__ int win_first_below(const int* __restrict__ cdw, const int* __restrict__ m16w, int j,
+                                               int l) {
+    if (j >= kWaveWin) return kWaveWin;
+    const int rj = j >> 4;
+    int q = run_first_below(cdw, rj, j, l);
+    if (q != INT_MAX) return q;
+    int rf = INT_MAX;
+#pragma unroll
+    for (int g = (kWinRuns + 3) / 4 - 1; g >= 0; --g) {
+        const int4 m = reinterpret_cast<const int4*>(m16w)[g];
+        rf = (4 * g + 3 > rj && 4 * g + 3 < kWinRuns && m.w < l) ? 4 * g + 3 : rf;
+        rf = (4 * g + 2 > rj && 4 * g + 2 < kWinRuns && m.z < l) ? 4 * g + 2 : rf;
+        rf = (4 * g + 1 > rj && 4 * g + 1 < kWinRuns && m.y < l) ? 4 * g + 1 : rf;
+        rf = (4 * g > rj && m.x < l) ? 4 * g : rf;
+    }
+    if (rf == INT_MAX) return kWaveWin;
+    return run_first_below(cdw, rf, 0, l);
+}
 
 __global__ void __launch_bounds__(kThreads) k_write_nodes(TopoParams P, const int32_t* __restrict__ cd,
                                                           const int32_t* __restrict__ off,
@@ -799,93 +852,112 @@ __global__ void __launch_bounds__(kThreads) k_write_nodes(TopoParams P, const in
                                                           int32_t* __restrict__ leaf_pos,
                                                           int64_t* __restrict__ hdr, int32_t* __restrict__ blk,
                                                           int32_t* __restrict__ far_p, int32_t* __restrict__ far_t) {
-    constexpr int kLds = kThreads + kWin + 1;
+    constexpr int kWaves = kThreads / 64;
     __shared__ int s_lc[kLevels];   // inner nodes of this workgroup per level
-    __shared__ int s_cd[kLds];
-    __shared__ int s_m16[kLds / 16];
-    __shared__ int s_fp[kFarLds], s_ft[kFarLds];
-    __shared__ int s_fn, s_fbase;
+    __shared__ __align__(16) int s_cd[kWaves][kWaveWin];
+    __shared__ int s_off[kWaves][kWaveWin];
+    __shared__ __align__(16) int s_m16[kWaves][(kWinRuns + 3) / 4 * 4];
+    __shared__ int s_fp[kWaves][kFarWave], s_ft[kWaves][kFarWave];
+    __shared__ int s_fn[kWaves], s_fbase;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x < kLevels) s_lc[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s_fn = 0;
-    const int LW = kThreads + P.n_leaf + 1;   // positions held in s_cd
+    if (lane == 0) s_fn[w] = 0;
+    __syncthreads();
+    int* cdw = s_cd[w];
+    int* offw = s_off[w];
+    int* m16w = s_m16[w];
+    constexpr int LW = kWaveWin;
     const int64_t n_nodes = off[P.n];
     int maxl = 0;
-    auto flush = [&]() {   // whole workgroup; s_fn entries in LDS
-        __syncthreads();
-        if (threadIdx.x == 0) s_fbase = s_fn ? atomicAdd(reinterpret_cast<int32_t*>(hdr + 3), s_fn) : 0;
-        __syncthreads();
-        for (int i = threadIdx.x; i < s_fn; i += kThreads) {
-            far_p[s_fbase + i] = s_fp[i];
-            far_t[s_fbase + i] = s_ft[i];
+    for (int64_t p0 = ((int64_t)blockIdx.x * kWaves + w) * 64; p0 < P.n; p0 += (int64_t)gridDim.x * kThreads) {
+        wave_sync();
+        const int nf = s_fn[w];
+        if (nf > kFarWave - 64) {   // room for this run's entries: flush the wave's list
+            int base = 0;
+            if (lane == 0) base = atomicAdd(reinterpret_cast<int32_t*>(hdr + 3), nf);
+            base = __shfl(base, 0, 64);
+            for (int i = lane; i < nf; i += 64) {
+                far_p[base + i] = s_fp[w][i];
+                far_t[base + i] = s_ft[w][i];
+            }
+            wave_sync();
+            if (lane == 0) s_fn[w] = 0;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) s_fn = 0;
-    };
-    for (int64_t p0 = (int64_t)blockIdx.x * kThreads; p0 < P.n; p0 += (int64_t)gridDim.x * kThreads) {
-        __syncthreads();
-        if (s_fn > kFarLds - kThreads) flush();   // room for this run's entries
-        for (int k = threadIdx.x; k < LW; k += kThreads) {
+        for (int k = lane; k < LW; k += 64) {
             const int64_t q = p0 + k;
-            s_cd[k] = q < P.n ? cd[q] : -1;   // -1 past the end: it ends every cell
+            cdw[k] = q < P.n ? cd[q] : -1;   // -1 past the end: it ends every cell
+            offw[k] = q <= P.n ? off[q] : 0;
         }
-        __syncthreads();
-        if (threadIdx.x < LW / 16) {
-            int m = s_cd[16 * threadIdx.x];
-            for (int j = 1; j < 16; ++j) m = min(m, s_cd[16 * threadIdx.x + j]);
-            s_m16[threadIdx.x] = m;
+        wave_sync();
+        if (lane < kWinRuns) {
+            int m = cdw[16 * lane];
+            for (int j = 1; j < 16; ++j) m = min(m, cdw[16 * lane + j]);
+            m16w[lane] = m;
         }
-        __syncthreads();
-        const int64_t p = p0 + threadIdx.x;
+        wave_sync();
+        const int64_t p = p0 + lane;
         if (p >= P.n) continue;
-        const int k = off[p + 1] - off[p];
+        const int op = offw[lane];
+        const int k = offw[lane + 1] - op;
         if (k == 0) continue;
-        const int c = s_cd[threadIdx.x];
-        int j = (int)threadIdx.x + 1;   // search position (window index)
+        const int iop = ioff[p];
+        const int c = cdw[lane];
+        int j = lane + 1;   // search position (window index)
         bool far = false;
         for (int t = k - 1; t >= 0; --t) {
             const int l = c + 1 + t;
             int64_t e = -1;
             if (!far) {
-                for (; j < LW && (j & 15); ++j)
-                    if (s_cd[j] < l) { e = p0 + j; break; }
-                if (e < 0) {
-                    for (; j + 16 <= LW && s_m16[j >> 4] >= l; j += 16) {}
-                    for (; j < LW; ++j)
-                        if (s_cd[j] < l) { e = p0 + j; break; }
-                }
+                j = win_first_below(cdw, m16w, j, l);
+                if (j < LW) e = p0 + j;
                 if (e < 0) {   // beyond the window: this node and the ones above it
                     far = true;
-                    const int q = atomicAdd(&s_fn, 1);
-                    s_fp[q] = (int)p;
-                    s_ft[q] = t;
+                    const int q = atomicAdd(&s_fn[w], 1);
+                    s_fp[w][q] = (int)p;
+                    s_ft[w][q] = t;
                 }
             }
             const bool leaf = (t == k - 1);
-            const int64_t id = off[p] + t;
-            const int skip = far ? 0 : (int)(e < P.n ? (int64_t)off[e] : n_nodes);
+            const int64_t id = op + t;
+            const int skip = far ? 0 : offw[e - p0];   // off[n] = n_nodes past the end
             link[id] = make_int4(skip, (int)p, far ? 0 : (int)(e - p), l | (leaf ? 0x100 : 0));
             if (!leaf) {
-                ilist[ioff[p] + t] = (int32_t)id;
+                ilist[iop + t] = (int32_t)id;
                 atomicAdd(&s_lc[l], 1);
             } else {
-                const int64_t lf = off[p] - ioff[p];   // leaves before p = nodes - inner nodes before p
+                const int64_t lf = op - iop;   // leaves before p = nodes - inner nodes before p
                 leaves[lf] = (int32_t)id;
                 leaf_pos[lf] = (int32_t)p;
             }
             maxl = l > maxl ? l : maxl;
         }
     }
-    flush();
+    // the workgroup's far entries: one global atomic for all its waves
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int q = 0; q < kWaves; ++q) tot += s_fn[q];
+        s_fbase = tot ? atomicAdd(reinterpret_cast<int32_t*>(hdr + 3), tot) : 0;
+    }
+    __syncthreads();
+    {
+        int base = s_fbase;
+        for (int q = 0; q < w; ++q) base += s_fn[q];
+        for (int i = lane; i < s_fn[w]; i += 64) {
+            far_p[base + i] = s_fp[w][i];
+            far_t[base + i] = s_ft[w][i];
+        }
+    }
     // per-workgroup inner nodes per level and deepest level, reduced by k_tree_close
-    __shared__ int s_max[kThreads / 64];
+    __shared__ int s_max[kWaves];
     maxl = ag_wave_max(maxl);
-    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = maxl;
+    if (lane == 0) s_max[w] = maxl;
     __syncthreads();
     int32_t* row = blk + (int64_t)blockIdx.x * (kLevels + 1);
     if (threadIdx.x < kLevels) row[threadIdx.x] = s_lc[threadIdx.x];
     if (threadIdx.x == 0) {
         int mb = s_max[0];
-        for (int w2 = 1; w2 < kThreads / 64; ++w2) mb = s_max[w2] > mb ? s_max[w2] : mb;
+        for (int w2 = 1; w2 < kWaves; ++w2) mb = s_max[w2] > mb ? s_max[w2] : mb;
         row[kLevels] = mb;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -956,7 +1028,7 @@ __global__ void __launch_bounds__(kThreads) k_far_ends(TopoParams P, const int32
          g += ((int64_t)gridDim.x * blockDim.x) >> 4) {
         const int64_t p = far_p[g];
         const int c = cd[p];
-        int64_t e = (p & ~(int64_t)(kThreads - 1)) + kThreads + P.n_leaf + 1;
+        int64_t e = (p & ~(int64_t)63) + kWaveWin;   // the end of the wave's window
         for (int t = far_t[g]; t >= 0; --t) {
             e = next_below16(P.n, cd, M, e, c + 1 + t, s);
             if (s == 0) {
