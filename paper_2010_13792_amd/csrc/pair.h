@@ -117,8 +117,3 @@ __device__ __forceinline__ void pair_interact_soft(R dx, R dy, R dz, R nx, R ny,
     A.syz += ty * dz;
 }
 
-// algorithmic operation count of one particle-particle interaction outside
-// the softening kernel (fused multiply-add = 2, reciprocal square root = 1):
-//   d and nu 6, r2 5, rsqrt 1, powers 2, D 2, mf mD 2, g 6, d.nu 5, s 1,
-//   j 12, t 3, S 15                                     = 60
-constexpr int AG_PP_FLOPS = 60;
