@@ -114,10 +114,17 @@ const char *ag_last_error(void);
  *                              tidal tensor and J, 1/r^3) are one derivative
  *                              deeper than the force's, and at 75 % they meet
  *                              the force's error bound at the caller's theta [75]
+ *   AG_OPT_MEM_LIMIT           most bytes of device memory the context's own
+ *                              buffers may hold together; a call that would
+ *                              grow them past it fails with AG_ENOMEM before
+ *                              freeing or launching anything (a failed build
+ *                              leaves no tree: later calls that need one give
+ *                              AG_ESTATE until a build succeeds); 0 = no limit
+ *                              beyond the device's own [0]
  * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30, 0..1,
- * 1..64, 1..64, 10..100) give AG_EINVAL. */
+ * 1..64, 1..64, 10..100, >= 0) give AG_EINVAL. */
 enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3, AG_OPT_MAC_OFFSET = 4,
-       AG_OPT_GROUP_TARGETS = 5, AG_OPT_EWALD_OPEN = 6, AG_OPT_ADJOINT_OPEN = 7 };
+       AG_OPT_GROUP_TARGETS = 5, AG_OPT_EWALD_OPEN = 6, AG_OPT_ADJOINT_OPEN = 7, AG_OPT_MEM_LIMIT = 8 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
 /* Per-particle softening lengths (Sec. 3: the paper's runs soften each

@@ -50,6 +50,7 @@ AG_OPT_MAC_OFFSET = 4
 AG_OPT_GROUP_TARGETS = 5
 AG_OPT_EWALD_OPEN = 6
 AG_OPT_ADJOINT_OPEN = 7
+AG_OPT_MEM_LIMIT = 8
 PHASES = ["build", "groups", "walk", "direct", "step", "adjoint", "ewald", "neighbour"]
 
 

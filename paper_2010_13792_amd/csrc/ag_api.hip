@@ -28,9 +28,13 @@ int ag_ensure(ag_ctx* c, DevBuf& b, size_t bytes) {
     if (c->capturing)
         return ag_fail(AG_ESTATE, "a library buffer must grow to %zu bytes during graph capture: run the same "
                        "sequence once before capturing", bytes);
+    if (c->mem_limit > 0 && c->dev_bytes - b.bytes + bytes > c->mem_limit)
+        return ag_fail(AG_ENOMEM, "growing a buffer to %zu bytes would take the context's buffers to %zu bytes, "
+                       "past its memory limit of %zu", bytes, c->dev_bytes - b.bytes + bytes, c->mem_limit);
     ++c->alloc_epoch;
     if (b.p) {
         hipError_t e = hipFree(b.p);
+        c->dev_bytes -= b.bytes;
         b.p = nullptr;
         b.bytes = 0;
         if (e != hipSuccess) return ag_fail(AG_EHIP, "hipFree failed: %s", hipGetErrorString(e));
@@ -42,6 +46,7 @@ int ag_ensure(ag_ctx* c, DevBuf& b, size_t bytes) {
         return ag_fail(AG_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
     b.bytes = bytes;
+    c->dev_bytes += bytes;
     return AG_OK;
 }
 
@@ -499,6 +504,10 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
         case AG_OPT_ADJOINT_OPEN:
             if (value < 10 || value > 100) return ag_fail(AG_EINVAL, "adjoint opening percentage must be in [10, 100]");
             c->adj_open = (int)value;
+            return AG_OK;
+        case AG_OPT_MEM_LIMIT:
+            if (value < 0) return ag_fail(AG_EINVAL, "memory limit must be >= 0 bytes (0: none)");
+            c->mem_limit = (size_t)value;
             return AG_OK;
         case AG_OPT_MAC_OFFSET:
             if (value != 0 && value != 1) return ag_fail(AG_EINVAL, "opening-test offset flag must be 0 or 1");

@@ -155,6 +155,8 @@ struct ag_ctx {
     DevBuf dflags;                // i32 [1]
 
     int64_t host_n_nodes = -1;    // cached after a synchronising read
+    size_t dev_bytes = 0;         // bytes held by the buffers above
+    size_t mem_limit = 0;         // AG_OPT_MEM_LIMIT (0: none)
     // depth of the last tree seen by the host (pinned copy + event, read when
     // the next build starts without waiting): plans the moments' launches
     int64_t* depth_host = nullptr;

@@ -1,7 +1,7 @@
 """GPU edge cases of the tree path: positions far from the origin (the walk's
 FP32 coordinates are taken relative to each group, so a large common offset
 must cost no accuracy), a single particle, and a two-body system whose
-field has a closed form."""
+field has a closed form; the memory limit's AG_ENOMEM path."""
 import numpy as np
 import pytest
 import torch
@@ -61,3 +61,38 @@ def test_two_bodies_closed_form(ag):
         assert np.allclose(a[i], ga, rtol=1e-6, atol=0)
         assert np.allclose(j[i], gj, rtol=1e-5, atol=1e-6 * np.abs(gj).max())
         assert np.allclose(T[i], gT, rtol=1e-5, atol=1e-6 * np.abs(gT).max())
+
+
+def test_memory_limit_gives_enomem_and_recovers(ag):
+    """AG_ENOMEM forced by the context's memory limit: a build that would
+    grow the buffers past it fails before freeing or launching anything and
+    leaves no tree (an evaluation then gives AG_ESTATE); with the limit
+    lifted the same context builds and evaluates bit for bit as a fresh
+    one."""
+    n = 20000
+    x, v, m = workloads.plummer(n, seed=12)
+    tx, tv, tm = _t(x), _t(v), _t(m)
+    with pytest.raises(ag.AgError) as bad:
+        with ag.Context(0) as c:
+            c.set_option(ag.AG_OPT_MEM_LIMIT, -1)
+    assert bad.value.code == ag.AG_EINVAL
+    with ag.Context(0) as c:
+        c.set_option(ag.AG_OPT_MEM_LIMIT, 1 << 20)   # far below what 20000 particles need
+        with pytest.raises(ag.AgError) as e:
+            c.tree_build(tx, tv, tm, 16)
+        assert e.value.code == ag.AG_ENOMEM
+        acc = torch.zeros((n, 3), dtype=torch.float64, device=DEV)
+        rows = torch.arange(n, dtype=torch.int32, device=DEV)
+        with pytest.raises(ag.AgError) as e2:
+            c.grav_eval(rows, 0.7, 1e-3, 1.0, acc, None, None)
+        assert e2.value.code == ag.AG_ESTATE
+        c.set_option(ag.AG_OPT_MEM_LIMIT, 0)
+        c.tree_build(tx, tv, tm, 16)
+        c.grav_eval(None, 0.7, 1e-3, 1.0, acc, None, None)
+        c.sync()
+    ref = torch.zeros_like(acc)
+    with ag.Context(0) as c:
+        c.tree_build(tx, tv, tm, 16)
+        c.grav_eval(None, 0.7, 1e-3, 1.0, ref, None, None)
+        c.sync()
+    assert torch.equal(acc, ref)
