@@ -45,16 +45,17 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of the walk kernel at the default workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of the 4
-# dispatches of the tuned configuration)
+# walk dispatches of a --no-tune run, the configuration named below)
 # scaled by what the same counters read for a plain 1 GiB device copy
 # (FETCH_SIZE 524305 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  Valid only
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "1046151030b50a4773eee641d0cf920fcb4144ee88ca60435941961479041cc3",
-    "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64},
-    "fetch_kib": 340379.3, "write_kib": 221056.4,
-    "fetch_factor": 1048576.0 / 524305.2, "write_factor": 1.0,
+    "src_sha256": "438756c1d1ef03a312477d50d5a481bfaf97224881c1433434b6bcd6f58a43b4",
+    "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64,
+                 "waves_per_cu": 16},
+    "fetch_kib": 349194.5, "write_kib": 221082.1,
+    "fetch_factor": 1048576.0 / 524304.6, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);
@@ -63,9 +64,10 @@ WALK_EXECUTED_FP32_FLOPS = (2515748660.0 + 22349236.0) * 64
 WALK_SOURCES = ("paper_2010_13792_amd/csrc/k_walk.hip", "paper_2010_13792_amd/csrc/pair.h",
                 "paper_2010_13792_amd/csrc/ag_internal.h")
 # algorithmic bytes of one build: per particle, read x, v, m (56), write them
-# in key order (56), keys and rows (24); per node, link 16, centre 32, box 32,
-# FP32 moments 64 and FP64 moments 200 (344)
-BUILD_BYTES_PER_PARTICLE = 56 + 56 + 24
+# in key order (spos + svel as double4 and FP32 velocities: 80), keys and rows
+# (24); per node, link 16, centre 32, box 32, FP32 moments 64 and FP64
+# moments 200 (344)
+BUILD_BYTES_PER_PARTICLE = 56 + 80 + 24
 BUILD_BYTES_PER_NODE = 344
 
 
@@ -78,16 +80,17 @@ def walk_src_digest():
     return h.hexdigest()
 
 
-def walk_counters_valid(args, group_targets):
+def walk_counters_valid(args, tuned):
     w = WALK_COUNTERS["workload"]
-    same = ((args.n, args.theta, args.eps, args.n_leaf, args.mac_offset, group_targets) ==
-            (w["n"], w["theta"], w["eps"], w["n_leaf"], w["mac_offset"], w["group_targets"]))
+    same = ((args.n, args.theta, args.eps, args.n_leaf, args.mac_offset, tuned["group_targets"],
+             tuned["waves_per_cu"]) ==
+            (w["n"], w["theta"], w["eps"], w["n_leaf"], w["mac_offset"], w["group_targets"], w["waves_per_cu"]))
     return same and walk_src_digest() == WALK_COUNTERS["src_sha256"]
 
 
-def walk_traffic(args, group_targets):
+def walk_traffic(args, tuned):
     """HBM bytes per walk launch from the stored counters, or None."""
-    if not walk_counters_valid(args, group_targets):
+    if not walk_counters_valid(args, tuned):
         return None
     return 1024.0 * (WALK_COUNTERS["fetch_kib"] * WALK_COUNTERS["fetch_factor"] +
                      WALK_COUNTERS["write_kib"] * WALK_COUNTERS["write_factor"])
@@ -130,6 +133,11 @@ def parse():
     ap.add_argument("--theta", type=float, default=0.7)
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--n-leaf", type=int, default=16)
+    ap.add_argument("--tune-leaf", type=int, default=1, choices=[0, 1],
+                    help="1: the autotuner also picks the leaf size from {8, 16, 32} and --n-leaf")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner: --n-leaf, 64 targets per group, 16 walk waves per CU "
+                         "(the configuration the stored walk counters were taken at)")
     ap.add_argument("--cpu-seconds", type=float, default=30.0,
                     help="upper bound on the host time of the oracle baseline sample")
     ap.add_argument("--sample", type=int, default=16384,
@@ -144,7 +152,7 @@ def parse():
                     help="adaptive workload: also replay one captured step per step and time it")
     ap.add_argument("--workload", default="tree",
                     choices=["tree", "direct", "adaptive", "batched", "adjoint", "periodic", "softening", "relative",
-                             "pm", "copy"],
+                             "pm", "build", "copy"],
                     help="tree: the headline line (default); the others measure the remaining "
                          "configurations and print their own JSON line (copy: a plain 1 GiB device "
                          "copy that calibrates the HBM byte counters)")
@@ -202,22 +210,33 @@ def main():
     ctx = ag.Context(0)
     mac_offset = args.mac_offset
     ctx.set_option(ag.AG_OPT_MAC_OFFSET, mac_offset)
-    ctx.tree_build(tx, tv, tm, args.n_leaf)
-    # targets per walk group, picked by the autotuner on this particle set (untimed)
+    # leaf size, targets per walk group and resident walk waves per CU, picked
+    # by the autotuner on this particle set (untimed): each candidate's tree
+    # build, grouping and walk
     from paper_2010_13792_amd import autotune
 
     def trial(p):
         ctx.set_option(ag.AG_OPT_GROUP_TARGETS, p["group_targets"])
+        ctx.set_option(ag.AG_OPT_WALK_WAVES_PER_CU, p["waves_per_cu"])
         ctx.timing_enable(True)
         ctx.timing_read(reset=True)
+        ctx.tree_build(tx, tv, tm, p["n_leaf"])
         ctx.grav_eval(None, args.theta, args.eps, G, acc, jerk, tid)
         ph = ctx.timing_read(reset=True)
         ctx.timing_enable(False)
-        return ph["groups"]["ms"] + ph["walk"]["ms"]
+        return ph["build"]["ms"] + ph["groups"]["ms"] + ph["walk"]["ms"]
 
-    tuned, tune_table = autotune.tune(trial, autotune.grid(group_targets=[64, 32]),
-                                      f"tree|n={n}|theta={args.theta}", use_cache=False)
+    leaves = sorted({args.n_leaf, 8, 16, 32}) if args.tune_leaf else [args.n_leaf]
+    if args.no_tune:
+        tuned, tune_table = {"n_leaf": args.n_leaf, "group_targets": 64, "waves_per_cu": 16}, {}
+    else:
+        tuned, tune_table = autotune.tune(trial, autotune.grid(n_leaf=leaves, group_targets=[64, 32],
+                                                               waves_per_cu=[8, 12, 16]),
+                                          f"tree|n={n}|theta={args.theta}", use_cache=False)
     ctx.set_option(ag.AG_OPT_GROUP_TARGETS, tuned["group_targets"])
+    ctx.set_option(ag.AG_OPT_WALK_WAVES_PER_CU, tuned["waves_per_cu"])
+    args.n_leaf = tuned["n_leaf"]
+    ctx.tree_build(tx, tv, tm, args.n_leaf)
     log(f"bench: autotuner picked {tuned}")
     # time grid from the initial forces: dt_max = 2^ceil(log2 max dt), tick = deepest bin
     ctx.grav_eval(None, args.theta, args.eps, G, acc, jerk, tid)
@@ -273,7 +292,7 @@ def main():
     value = evals_per_step / (ms_step * 1e-3)
     build_ms = phases["build"]["ms"] / max(1, phases["build"]["launches"])
     build_bytes = n * BUILD_BYTES_PER_PARTICLE + nn * BUILD_BYTES_PER_NODE
-    traffic = walk_traffic(args, tuned["group_targets"])
+    traffic = walk_traffic(args, tuned)
     log(f"bench: {ms_step:.3f} ms/step, walk {walk_ms:.3f} ms, {achieved_tflops:.2f} TFLOP/s")
 
     # accuracy on a sample against the FP64 oracle; the same run times the oracle
@@ -365,7 +384,7 @@ def main():
             "workload": f"turbulent uniform sphere N=2^{int(np.log2(n))} tree walk, all active",
             "n": n, "theta": args.theta, "eps": args.eps, "n_leaf": args.n_leaf,
             "multipoles": "monopole+quadrupole", "accumulation": "f64", "mac_offset": mac_offset,
-            "autotune": {"best": tuned, "walk_ms": tune_table},
+            "autotune": {"best": tuned, "build_groups_walk_ms": tune_table},
             "step": "build+groups+walk+timestep+select+predict",
             "median_rel_force_err": err_med, "p99_rel_force_err": err_p99,
             "value_measured": value,
@@ -378,7 +397,7 @@ def main():
             "kernel": "k_walk", "kernel_ms": walk_ms,
             "flops_per_launch": walk_flops,
             "executed_fp32_tflops": (WALK_EXECUTED_FP32_FLOPS / (walk_ms * 1e-3) / 1e12
-                                     if walk_counters_valid(args, tuned["group_targets"]) else None),
+                                     if walk_counters_valid(args, tuned) else None),
             "peak_published": PEAK_FP32_PACKED_SPEC,
             "frac_published": achieved_tflops / PEAK_FP32_PACKED_SPEC,
             "peak_measured": None if peak is None else peak["fp32_fma_tflops"],

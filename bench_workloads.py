@@ -21,6 +21,8 @@
   softening N = 2^20 turbulent sphere with a softening length per particle
             (the distance to the 32nd neighbour) against the same step with
             one length: time, interactions and error against the oracle.
+  build     the tree build alone on the 2^22 clumps and the 2^20 turbulent
+            sphere (n_leaf = 16): time per build and its algorithmic bytes.
   copy      a plain device copy of 1 GiB, the calibration of the HBM byte
             counters (FETCH_SIZE, WRITE_SIZE) used for the walk's traffic.
 Inputs are seeded synthetic particle sets standing in for the paper's
@@ -767,6 +769,44 @@ def run_relative(args):
 
 
 # ---------------------------------------------------------------------------
+# algorithmic bytes of one build: per particle, read x, v, m (56), write them
+# in key order (spos + svel as double4 and FP32 velocities: 80), Morton keys
+# and row indices (8 + 4, written and read once: 24); per node, link 16,
+# centre 32, box 32, FP32 moments 64 and FP64 moments 200 (344)
+BUILD_BYTES_PER_PARTICLE = 56 + 80 + 24
+BUILD_BYTES_PER_NODE = 344
+
+
+def run_build(args):
+    out = {"workload": "tree build (n_leaf 16)", "peak_hbm_gbs": 8000.0,
+           "bytes_per_particle": BUILD_BYTES_PER_PARTICLE, "bytes_per_node": BUILD_BYTES_PER_NODE, "sets": {}}
+    sets = {"clumps_2p22": lambda: workloads.clumps(1 << 22, seed=3)[:3],
+            "turbulent_sphere_2p20": lambda: workloads.turbulent_sphere(1 << 20, seed=2, grid=128)}
+    for name, make in sets.items():
+        x, v, m = make()
+        n = len(m)
+        tx, tv, tm = _t(x), _t(v), _t(m)
+        with ag.Context(0) as c:
+            for _ in range(3):
+                c.tree_build(tx, tv, tm, 16)
+            c.sync()
+            c.timing_enable(True)
+            c.timing_read(reset=True)
+            reps = 20
+            for _ in range(reps):
+                c.tree_build(tx, tv, tm, 16)
+            ph = c.timing_read(reset=True)
+            c.timing_enable(False)
+            nn, levels = c.tree_info()
+        ms = ph["build"]["ms"] / reps
+        nbytes = n * BUILD_BYTES_PER_PARTICLE + nn * BUILD_BYTES_PER_NODE
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out["sets"][name] = {"n": n, "nodes": nn, "levels": levels, "ms_per_build": ms,
+                             "algorithmic_bytes": nbytes, "gbs": gbs, "frac_hbm": gbs / 8000.0}
+        log(f"build {name}: {ms:.3f} ms, {nn} nodes, {gbs:.0f} GB/s")
+    return out
+
+
 def run_copy(args):
     n = 1 << 27                      # 2^27 doubles = 1 GiB
     a = torch.ones(n, dtype=torch.float64, device=DEV)
