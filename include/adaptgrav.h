@@ -114,6 +114,16 @@ const char *ag_last_error(void);
  *                              tidal tensor and J, 1/r^3) are one derivative
  *                              deeper than the force's, and at 75 % they meet
  *                              the force's error bound at the caller's theta [75]
+ *   AG_OPT_GROUP_SPLIT         a group of 33 .. value targets is walked as two
+ *                              halves (a wave gives each of k targets 64 / k
+ *                              whole lanes, so 33 .. 42 targets leave lanes
+ *                              idle that halves of 17 .. 21 use); 0 = never [42]
+ *   AG_OPT_GROUP_PACK          1: the targets of consecutive child cells (one
+ *                              run, inside their parent's cell) are cut into
+ *                              groups of AG_OPT_GROUP_TARGETS and a remainder,
+ *                              a child's targets possibly in two groups; 0:
+ *                              runs are cut between children, so no group
+ *                              reaches the cap unless its children fill it [0]
  *   AG_OPT_MEM_LIMIT           most bytes of device memory the context's own
  *                              buffers may hold together; a call that would
  *                              grow them past it fails with AG_ENOMEM before
@@ -122,9 +132,10 @@ const char *ag_last_error(void);
  *                              AG_ESTATE until a build succeeds); 0 = no limit
  *                              beyond the device's own [0]
  * Values outside the documented ranges (1..64, 0..16, 0 or 64..2^30, 0..1,
- * 1..64, 1..64, 10..100, >= 0) give AG_EINVAL. */
+ * 1..64, 1..64, 10..100, 0 or 33..64, 0..1, >= 0) give AG_EINVAL. */
 enum { AG_OPT_WALK_WAVES_PER_CU = 1, AG_OPT_SMALL_NODE = 2, AG_OPT_GROUP_SPAN = 3, AG_OPT_MAC_OFFSET = 4,
-       AG_OPT_GROUP_TARGETS = 5, AG_OPT_EWALD_OPEN = 6, AG_OPT_ADJOINT_OPEN = 7, AG_OPT_MEM_LIMIT = 8 };
+       AG_OPT_GROUP_TARGETS = 5, AG_OPT_EWALD_OPEN = 6, AG_OPT_ADJOINT_OPEN = 7, AG_OPT_MEM_LIMIT = 8,
+       AG_OPT_GROUP_SPLIT = 9, AG_OPT_GROUP_PACK = 10 };
 int ag_set_option(ag_ctx *ctx, int32_t option, int64_t value);
 
 /* Per-particle softening lengths (Sec. 3: the paper's runs soften each

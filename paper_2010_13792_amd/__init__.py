@@ -51,6 +51,8 @@ AG_OPT_GROUP_TARGETS = 5
 AG_OPT_EWALD_OPEN = 6
 AG_OPT_ADJOINT_OPEN = 7
 AG_OPT_MEM_LIMIT = 8
+AG_OPT_GROUP_SPLIT = 9
+AG_OPT_GROUP_PACK = 10
 PHASES = ["build", "groups", "walk", "direct", "step", "adjoint", "ewald", "neighbour"]
 
 

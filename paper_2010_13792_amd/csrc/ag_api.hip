@@ -505,6 +505,15 @@ extern "C" int ag_set_option(ag_ctx* c, int32_t option, int64_t value) {
             if (value < 10 || value > 100) return ag_fail(AG_EINVAL, "adjoint opening percentage must be in [10, 100]");
             c->adj_open = (int)value;
             return AG_OK;
+        case AG_OPT_GROUP_SPLIT:
+            if (value != 0 && (value < 33 || value > 64))
+                return ag_fail(AG_EINVAL, "group split bound must be 0 or in [33, 64]");
+            c->group_split = (int)value;
+            return AG_OK;
+        case AG_OPT_GROUP_PACK:
+            if (value != 0 && value != 1) return ag_fail(AG_EINVAL, "group packing flag must be 0 or 1");
+            c->group_pack = (int)value;
+            return AG_OK;
         case AG_OPT_MEM_LIMIT:
             if (value < 0) return ag_fail(AG_EINVAL, "memory limit must be >= 0 bytes (0: none)");
             c->mem_limit = (size_t)value;

@@ -81,6 +81,8 @@ struct ag_ctx {
     double rel_alpha = 0.0;
     bool tree_soft = false;       // the current tree carries them
     int group_cap = 64;
+    int group_split = 42;  // groups of 33 .. group_split targets are split in two (0: none)
+    int group_pack = 0;    // 1: runs of children are cut every group_cap targets
     bool capturing = false;
     uint64_t alloc_epoch = 0;     // bumped by every (re)allocation of a context buffer
     uint64_t graph_epoch = 0;     // alloc_epoch when the graph was captured

@@ -1842,6 +1842,8 @@ struct GroupCtx {
     int sys_levels;
     int span;   // cap on the particles of a group's cells (0 = none)
     int cap;    // targets per group (at most one wave)
+    int split;  // groups of 33 .. split targets are emitted as two halves (0 = none)
+    int pack;   // 1: runs of small children are cut every `cap` targets, not at child boundaries
 };
 
 __device__ __forceinline__ int sys_of_pos(const GroupCtx& C, int64_t p) {
@@ -1865,9 +1867,20 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
     // compact group even if few of its particles are active
     const bool big = forced || a > C.cap || (C.span > 0 && !leaf && L.z > C.span);
     int ng = 0;
-    auto emit = [&](int start, int cnt, int64_t pos) {
+    auto emit1 = [&](int start, int cnt, int64_t pos) {
         if (out) out[ng] = make_int4(start, cnt, C.n_sys > 1 ? sys_of_pos(C, pos) : 0, 0);
         ++ng;
+    };
+    // a wave gives each of k targets 64 / k lanes (whole lanes): 33 .. 42
+    // targets leave a third or more of the lanes idle, two halves of 17 .. 21
+    // use three lanes each
+    auto emit = [&](int start, int cnt, int64_t pos) {
+        if (C.split > 0 && cnt > 32 && cnt <= C.split) {
+            emit1(start, cnt / 2, pos);
+            emit1(start + cnt / 2, cnt - cnt / 2, pos);
+        } else {
+            emit1(start, cnt, pos);
+        }
     };
     if (!big) {
         if (id == 0 && a > 0) emit(a0, a, L.y);   // a small whole tree is one group
@@ -1879,6 +1892,16 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
     }
     int run_start = 0, run_cnt = 0, run_span = 0;
     int64_t run_pos = 0;
+    // (pack: a run, contiguous in the target order, is cut into groups of
+    // `cap` targets and a remainder, which may split a child between two
+    // groups; the groups stay inside this node's cell)
+    auto emit_run = [&](int start, int cnt, int64_t pos) {
+        if (!C.pack) {
+            emit(start, cnt, pos);
+            return;
+        }
+        for (int k = 0; k < cnt; k += C.cap) emit(start + k, cnt - k < C.cap ? cnt - k : C.cap, pos);
+    };
     for (int ch = id + 1, k8 = 0; ch < L.x && k8 < 8; ch = C.link[ch].x, ++k8) {
         const int4 Lc = C.link[ch];
         const int c0 = C.aoff ? C.aoff[Lc.y] : Lc.y;
@@ -1886,14 +1909,14 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
         const bool leafc = (Lc.w & 0x100) != 0;
         const bool bigc = (Lc.w & 0xff) < C.sys_levels || ac > C.cap || (C.span > 0 && !leafc && Lc.z > C.span);
         if (bigc || ac == 0 || forced) {
-            if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
+            if (run_cnt > 0) emit_run(run_start, run_cnt, run_pos);
             run_cnt = 0;
             run_span = 0;
             if (forced && !bigc && ac > 0) emit(c0, ac, Lc.y);
             continue;
         }
-        if (run_cnt + ac > C.cap || (C.span > 0 && run_span + Lc.z > C.span)) {
-            if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
+        if ((!C.pack && run_cnt + ac > C.cap) || (C.span > 0 && run_span + Lc.z > C.span)) {
+            if (run_cnt > 0) emit_run(run_start, run_cnt, run_pos);
             run_cnt = 0;
             run_span = 0;
         }
@@ -1904,7 +1927,7 @@ __device__ int node_groups(const GroupCtx& C, int id, int4* __restrict__ out) {
         run_cnt += ac;
         run_span += Lc.z;
     }
-    if (run_cnt > 0) emit(run_start, run_cnt, run_pos);
+    if (run_cnt > 0) emit_run(run_start, run_cnt, run_pos);
     return ng;
 }
 
@@ -1966,7 +1989,7 @@ int ag_prepare_groups(ag_ctx* c, const int32_t* idx, int64_t n_act, int64_t* max
     // with every particle active the flags, their scan and the position list
     // are the identity: the grouping and the walk use sorted positions directly
     GroupCtx C{c->nd_link.as<int4>(), idx ? off : (const int32_t*)nullptr, c->sys_off.as<int64_t>(), c->n_sys,
-               c->sys_levels, c->group_span, c->group_cap};
+               c->sys_levels, c->group_span, c->group_cap, c->group_split, c->group_pack};
     const int64_t* hdr = c->tree_hdr.as<int64_t>();
     int32_t* gcnt = c->grp_cnt.as<int32_t>();
     int32_t* goff = c->grp_off.as<int32_t>();

@@ -187,6 +187,50 @@ def test_walk_theta0_every_target_ragged(ctx, orc, n_leaf):
         assert e.max() <= 1e-4, (n, n_leaf, float(e.max()))
 
 
+@pytest.mark.parametrize("split,pack", [(0, 0), (0, 1), (42, 1)])
+def test_walk_group_split_and_pack(ag, ctx, orc, split, pack):
+    """Groups of 33 .. 42 targets walked whole (AG_OPT_GROUP_SPLIT 0; the
+    default walks them as two halves) and runs of children cut every 64
+    targets (AG_OPT_GROUP_PACK): at theta = 0 every target still gets the
+    direct sum (same bound as the default grouping, at ragged sizes); at
+    theta = 0.7 the error against the oracle stays within the metric's bound
+    and the group count differs from the default's; bad values are
+    refused."""
+    try:
+        ctx.set_option(ag.AG_OPT_GROUP_SPLIT, split)
+        ctx.set_option(ag.AG_OPT_GROUP_PACK, pack)
+        for n in (40, 65, 1000, 4097):
+            x, v, m = workloads.plummer(n, seed=300 + n)
+            a, _, _ = _eval(ctx, x, v, m, 0.0, 0.01)
+            ar, _, _ = orc.direct(x, v, m, 0.01, 1.0)
+            e = np.linalg.norm(a - ar, axis=1) / orc.abs_scale(x, m, 0.01, 1.0)
+            assert e.max() <= 1e-4, (n, float(e.max()))
+        x, v, m = workloads.turbulent_sphere(1 << 15, seed=7, grid=32)
+        rows = np.random.default_rng(3).choice(len(m), 256, replace=False)
+        ar, _, _ = orc.direct(x, v, m, 1e-3, 1.0, rows)
+        groups = {}
+        for on in (False, True):   # against the default grouping (split 42, no packing)
+            ctx.set_option(ag.AG_OPT_GROUP_SPLIT, split if on else 42)
+            ctx.set_option(ag.AG_OPT_GROUP_PACK, pack if on else 0)
+            ctx.stats_reset()
+            a, _, _ = _eval(ctx, x, v, m, 0.7, 1e-3)
+            st = ctx.stats_read()
+            groups[on] = st["n_groups"]
+            assert st["n_targets"] == len(m)
+            e = rel_err(a[rows], ar)
+            assert np.median(e) <= 1e-3 and np.percentile(e, 99) <= 1e-2, (on, np.median(e))
+        assert groups[True] != groups[False]
+        for bad in (-1, 1, 32, 65):
+            with pytest.raises(ag.AgError):
+                ctx.set_option(ag.AG_OPT_GROUP_SPLIT, bad)
+        for bad in (-1, 2):
+            with pytest.raises(ag.AgError):
+                ctx.set_option(ag.AG_OPT_GROUP_PACK, bad)
+    finally:
+        ctx.set_option(ag.AG_OPT_GROUP_SPLIT, 42)
+        ctx.set_option(ag.AG_OPT_GROUP_PACK, 0)
+
+
 @pytest.mark.parametrize("theta", [0.5, 0.7])
 def test_walk_accuracy_turbulent_sphere(ctx, orc, theta):
     """Uniform sphere with k^-4 velocities, N = 2^16, eps = 1e-3, on 4096
