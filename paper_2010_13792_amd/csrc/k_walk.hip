@@ -2079,9 +2079,14 @@ __global__ void k_leaf_wmoments(const int64_t* __restrict__ hdr, const int32_t* 
 // Shifted to the parent centre (y = y_child + dl):
 //   W1_bc  = sum (W1_bc + W0_b dl_c)
 //   W2_bce = sum (W2_bce + W1_bc dl_e + W1_be dl_c + W0_b dl_c dl_e)
-__global__ void k_inner_wlevel(int level, const int32_t* __restrict__ lvl, const int32_t* __restrict__ lvl_list,
-                               const int4* __restrict__ child,
+// Levels l_hi down to l_lo: one level per launch (l_hi = l_lo, any grid),
+// or several in a single-workgroup launch, the workgroup barrier between
+// levels ordering each level after its children's.
+__global__ void k_inner_wlevel(int l_hi, int l_lo, const int32_t* __restrict__ lvl,
+                               const int32_t* __restrict__ lvl_list, const int4* __restrict__ child,
                                const double* __restrict__ m64, double* __restrict__ w64, float4* __restrict__ wf) {
+  for (int level = l_hi; level >= l_lo; --level) {
+    if (level < l_hi) __syncthreads();   // single-workgroup launches only
     const int t_lo = lvl[kLvlOff + level], t_hi = lvl[kLvlOff + level + 1];
     for (int64_t t = t_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t_hi;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -2112,6 +2117,7 @@ __global__ void k_inner_wlevel(int level, const int32_t* __restrict__ lvl, const
         }
         store_w(id, r, w64, wf);
     }
+  }
 }
 
 }  // namespace
@@ -2377,12 +2383,27 @@ int ag_launch_backward(ag_ctx* c, const int32_t* idx, int64_t n_act, const doubl
     const int64_t inner_bound = c->max_nodes - n;
     int g = grid_for(inner_bound > 0 ? inner_bound : 1);
     if (g > 128) g = 128;
-    for (int l = AG_MAX_LEVEL - 1; l >= 0; --l)
-        hipLaunchKernelGGL(k_inner_wlevel, dim3(g), dim3(256), 0, st, l,
-                           reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8),
-                           c->lvl_list.as<int32_t>(), c->child.as<int4>(),
-                           c->nd_64.as<double>(),
-                           c->nd_w.as<double>(), c->nd_wf.as<float4>());
+    {
+        // levels below the deepest the host has seen in one single-workgroup
+        // launch (usually empty), then one launch per level down to 3, and
+        // levels 2-0 (at most 73 nodes) in one single-workgroup launch
+        const int32_t* lvl = reinterpret_cast<const int32_t*>(c->tree_hdr.as<int64_t>() + 8);
+        const int32_t* ll = c->lvl_list.as<int32_t>();
+        const int4* ch = c->child.as<int4>();
+        const double* m64 = c->nd_64.as<double>();
+        double* w64 = c->nd_w.as<double>();
+        float4* wf = c->nd_wf.as<float4>();
+        constexpr int kTop = 2;
+        int lc = c->seen_max_level - 1;
+        if (c->seen_max_level < 0 || lc > AG_MAX_LEVEL - 1) lc = AG_MAX_LEVEL - 1;
+        if (lc < kTop + 1) lc = kTop;
+        if (lc < AG_MAX_LEVEL - 1)
+            hipLaunchKernelGGL(k_inner_wlevel, dim3(1), dim3(256), 0, st, AG_MAX_LEVEL - 1, lc + 1, lvl, ll, ch, m64,
+                               w64, wf);
+        for (int l = lc; l > kTop; --l)
+            hipLaunchKernelGGL(k_inner_wlevel, dim3(g), dim3(256), 0, st, l, l, lvl, ll, ch, m64, w64, wf);
+        hipLaunchKernelGGL(k_inner_wlevel, dim3(1), dim3(256), 0, st, kTop, 0, lvl, ll, ch, m64, w64, wf);
+    }
     int64_t mg = 0;
     AG_TRY(ag_prepare_groups(c, nullptr, n, &mg, nullptr, nullptr));   // every particle is a target
     Groups Gr{c->all_active ? (const int32_t*)nullptr : c->act_pos.as<int32_t>(), c->grp.as<int4>(),
