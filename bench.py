@@ -368,12 +368,12 @@ def main():
         # checks every 13 steps: a spacing prime to the bins' power-of-two
         # update cycles, so the checks meet every phase of them
         cps = sorted(set(range(0, a_steps + 1, 13)) | {a_steps})
+        qs = (0.0, 0.125, 0.15625, 0.1875, 0.25)
         cmp = bench_workloads.adaptive_comparison(
-            n=1 << 22, steps=a_steps, qs=(0.0, 0.125, 0.25), step_shift=2, n_rows=1024, checkpoints=cps,
-            graph=True)
+            n=1 << 22, steps=a_steps, qs=qs, step_shift=2, n_rows=768, checkpoints=cps, graph=True)
         base = cmp["runs"]["0.0"]
         per_q = {}
-        for key in ("0.125", "0.25"):
+        for key in (str(q) for q in qs[1:]):
             r = cmp["runs"][key]
             per_q[key] = {
                 "eval_ratio": r["eval_ratio"], "gravity_time_ratio": r["gravity_speedup"],
