@@ -126,15 +126,24 @@ __global__ void __launch_bounds__(kBoxThreads) k_box(const double* __restrict__ 
     const int c = threadIdx.x % 3;   // kBoxThreads is a multiple of 3
     double mn = DBL_MAX, mx = -DBL_MAX;
     bool bad = false;
-    for (int64_t j = 3 * i0 + threadIdx.x; j < 3 * i1; j += kBoxThreads) {
-        double q = x[j];
-        if (!isfinite(q)) {
+    // all of the thread's loads issued before any is used
+    constexpr int kPer = 3 * kBoxChunk / kBoxThreads;
+    double q[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t j = 3 * i0 + threadIdx.x + (int64_t)k * kBoxThreads;
+        q[k] = j < 3 * i1 ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (3 * i0 + threadIdx.x + (int64_t)k * kBoxThreads >= 3 * i1) continue;
+        if (!isfinite(q[k])) {
             bad = true;
             continue;
         }
-        q = in_box(q, pbox);
-        mn = q < mn ? q : mn;
-        mx = q > mx ? q : mx;
+        const double u = in_box(q[k], pbox);
+        mn = u < mn ? u : mn;
+        mx = u > mx ? u : mx;
     }
     if (bad) atomicOr(flags, AGF_NONFINITE);
     // per coordinate: the wave's lanes of that coordinate, then the waves
