@@ -434,6 +434,7 @@ def run_periodic(args):
             t_a = time.perf_counter()
             ref["ewald"] = (er, *oracle.direct(x, v, m, eps, 1.0, er, box=1.0, ewald=True))
             t_ew = time.perf_counter() - t_a
+        tuned_sets = {}
         for mode in ("nearest", "ewald"):
             for theta in (0.5, 0.7):
                 with ag.Context(0) as c:
@@ -443,6 +444,22 @@ def run_periodic(args):
                         c.tree_build(tx, tv, tm, 16)
                         c.grav_eval(None, theta, eps, 1.0, acc, jerk, tid)
 
+                    # group size and split depend on the box size (64^3 runs
+                    # faster with 32-target groups, 128^3 with 64)
+                    def trial(p):
+                        c.set_option(ag.AG_OPT_GROUP_TARGETS, p["group_targets"])
+                        c.set_option(ag.AG_OPT_GROUP_SPLIT, p["group_split"])
+                        e0, e1 = _events()
+                        e0.record()
+                        step()
+                        e1.record()
+                        torch.cuda.synchronize()
+                        return e0.elapsed_time(e1)
+
+                    tuned, _ = autotune.tune(trial, autotune.grid(group_targets=[64, 32], group_split=[0, 42]),
+                                             f"periodic|{mode}|{n_side}|{theta}", reps=2, use_cache=False)
+                    trial(tuned)
+                    tuned_sets[(mode, theta)] = tuned
                     for _ in range(2):
                         step()
                     torch.cuda.synchronize()
@@ -465,7 +482,8 @@ def run_periodic(args):
                     c.timing_enable(False)
                 walk_ms = ph["walk"]["ms"] / reps
                 flops = (st["n_pp"] * PP_FLOPS + st["n_pn"] * PN_FLOPS) / reps
-                r = {"n": n, "theta": theta, "eps": eps, "ms_per_step": ms, "evals_per_s": n / (ms * 1e-3),
+                r = {"n": n, "theta": theta, "eps": eps, "autotune": tuned, "ms_per_step": ms,
+                     "evals_per_s": n / (ms * 1e-3),
                      "build_ms": ph["build"]["ms"] / reps, "walk_ms": walk_ms, "ewald_ms": ph["ewald"]["ms"] / reps,
                      "walk_tflops": flops / (walk_ms * 1e-3) / 1e12,
                      "walk_frac_of_peak": flops / (walk_ms * 1e-3) / 1e12 / PEAK_TFLOPS,
@@ -488,6 +506,8 @@ def run_periodic(args):
         hdev = _t(hl)
         with ag.Context(0) as c:
             c.set_periodic(1.0, ewald=True)
+            c.set_option(ag.AG_OPT_GROUP_TARGETS, tuned_sets[("ewald", 0.5)]["group_targets"])
+            c.set_option(ag.AG_OPT_GROUP_SPLIT, tuned_sets[("ewald", 0.5)]["group_split"])
 
             def step():
                 c.set_softening(hdev)
@@ -513,6 +533,7 @@ def run_periodic(args):
             ph = c.timing_read(reset=True)
             c.timing_enable(False)
         r = {"n": n, "theta": 0.5, "lengths": "32nd-neighbour distance at the nearest image",
+             "options": tuned_sets[("ewald", 0.5)],
              "ms_per_step": ms, "evals_per_s": n / (ms * 1e-3), "build_ms": ph["build"]["ms"] / reps,
              "neighbour_ms": ph["neighbour"]["ms"] / reps, "walk_ms": ph["walk"]["ms"] / reps,
              "ewald_ms": ph["ewald"]["ms"] / reps,

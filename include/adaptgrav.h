@@ -390,9 +390,10 @@ int ag_grav_direct(ag_ctx *ctx, int64_t n, const double *x, const double *v, con
 /* ag_grav_direct for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same arguments, checks and kernels, and bit-identical results, but the
- * call allocates nothing.  Its scratch (the per-split sums of a small target
- * set, 12.6 MB) is a fixed array of the library on each device, looked up
- * when the first context on that device is created; the launch shape bounds
+ * call allocates nothing.  Its scratch (the per-split sums of a target set
+ * too small to fill the device, 384 KiB) is a fixed array of the library on
+ * each device, looked up when the first context on that device is created;
+ * the launch shape bounds
  * the scratch for every n and n_active, so no size is refused (a larger
  * need would give AG_EINVAL).  Every call on one device shares that array:
  * calls that overlap on one device (other streams, other contexts, other

@@ -153,12 +153,6 @@ int ag_check_launch(const char* what) {
     return AG_OK;
 }
 
-// clears counters that kernels leave at zero after each use
-__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
-}
-
 extern "C" int ag_create(ag_ctx** out, int device, void* stream) {
     if (!out) return ag_fail(AG_EINVAL, "out is null");
     *out = nullptr;
@@ -406,13 +400,7 @@ extern "C" int ag_grav_direct(ag_ctx* c, int64_t n, const double* x, const doubl
     if (n_act == 0) return AG_OK;
     DeviceGuard g(c->device);
     const size_t bytes = ag_direct_scratch_bytes(n, n_act);
-    if (bytes > 0) {
-        const void* before = c->direct_part.p;
-        AG_TRY(ag_ensure(c, c->direct_part, bytes));
-        if (c->direct_part.p != before)   // a new buffer: its split counters start at zero
-            hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, c->stream, c->direct_part.as<uint32_t>(),
-                               (int64_t)(ag_direct_count_bytes() / sizeof(uint32_t)));
-    }
+    if (bytes > 0) AG_TRY(ag_ensure(c, c->direct_part, bytes));
     AG_TRY(ag_launch_direct(c, n, x, v, m, idx, n_act, eps, G, precision, acc, jerk, tidal,
                             bytes > 0 ? c->direct_part.p : nullptr));
     return check_launch("grav direct");

@@ -147,7 +147,7 @@ struct ag_ctx {
     DevBuf grp_cnt, grp_off;      // i32 [max_nodes (+1)]: groups owned per node, offsets
     DevBuf sys_act;               // i32 [n_sys + 1]
     DevBuf wsorted;               // double4 [n]: adjoint weights in sorted order
-    DevBuf direct_part;           // direct sum: split counters (zero between calls), then FP64 partial sums
+    DevBuf direct_part;           // direct sum: FP64 per-split sums of a small target set
     DevBuf tmp_tidal;             // double [n*6]
     DevBuf sel_flag;              // i32 [n]: due flags of the last select
     DevBuf sel_off;               // i32 [n+1]: their exclusive scan
@@ -205,13 +205,12 @@ struct PhaseScope {
 // ---------------------------------------------------------------------------
 // launchers implemented in the kernel translation units
 // ---------------------------------------------------------------------------
-// direct summation; scratch holds ag_direct_scratch_bytes(n, n_act) bytes whose
-// first ag_direct_count_bytes() are zero (and are left zero)
+// direct summation; scratch holds ag_direct_scratch_bytes(n, n_act) bytes (the
+// per-split sums of a small target set; nothing need be cleared)
 int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
                      const int32_t* idx, int64_t n_act, double eps, double G, int precision,
                      double* acc, double* jerk, double* tidal, void* scratch, bool timed = true);
 size_t ag_direct_scratch_bytes(int64_t n, int64_t n_act);
-size_t ag_direct_count_bytes();
 int ag_launch_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx,
                        const double* tidal, double eta, double dt_max, int32_t k_max,
                        double* dt, int8_t* bin, const int64_t* n_dev = nullptr);

@@ -1,28 +1,33 @@
 // k_direct.hip -- softened direct summation of g, j and T (all sources act
 // on each listed target), in FP64 or with FP32 pair terms.
 //
-// Layout: a workgroup of four waves owns 64 targets (one per lane, the same
-// 64 in every wave) and one contiguous chunk of sources.  The chunk is
-// staged through LDS 256 sources at a time (one coalesced load per thread);
-// wave w sums sources w, w + 4, ... of every staged tile, reading them as LDS
-// broadcasts, so the four waves of a workgroup interleave their pair chains
-// on the SIMDs of one CU.  At the end the four waves' sums are added in LDS
-// in a fixed order.  The self pair is left out by a test that only the
-// tiles holding one of the wave's own targets run.  The Newtonian f and D
-// are formed on every lane; the kernel interior replaces them where some
-// lane of the wave has a source inside its softening length (a
-// wave-uniform branch).  A small target set is split over sources (grid.y) so
-// the launch holds enough workgroups to fill the 256 CUs; each split writes
-// its FP64 sums to scratch, and the last split of a target tile to finish
-// (an agent-scope counter per tile) adds all splits in split order and
-// writes the rows -- one launch, bit-reproducible, and the counter is back
-// at zero afterwards.
+// Layout: a workgroup of eight waves owns T = 64 / Gs targets.  Each wave
+// holds all T targets, Gs times over: lane l serves target l mod T in lane
+// group l / T, and the 8 Gs lane groups of the workgroup each sum their own
+// subset of the sources (source q of a staged tile belongs to subset
+// q mod 8 Gs).  Gs (1 .. 16) is the smallest that gives enough workgroups to
+// fill the chip, so a target set of a few thousand still spreads over every
+// SIMD without any exchange between workgroups.  Sources are staged through
+// LDS 1024 at a time (two coalesced loads per thread); the Gs groups of a
+// wave read Gs neighbouring sources at once (broadcasts within each group).
+// At the end the subsets are added in a fixed tree: across the lane groups
+// of a wave by butterfly shuffles, then across the eight waves in LDS in
+// wave order -- bit-reproducible, no scratch and no atomics.  Only a target
+// set too small to fill the chip even at Gs = 16 is also split over sources
+// (grid.y): each split writes its FP64 sums to scratch and a second kernel
+// adds them in split order (the kernel boundary orders the two, so no
+// device-wide fence is needed).
+//
+// The self pair is left out by a test that only the staged tiles holding one
+// of the wave's own targets run.  The Newtonian f and D are formed on every
+// lane; the kernel interior replaces them where some lane of the wave has a
+// source inside its softening length (a wave-uniform branch).
 //
 // FP64 mode: every operation in FP64; 1/sqrt(r^2) from the hardware's FP64
 // reciprocal square root estimate refined by two Newton steps.
 // FP32-pair mode: the separation d = x_j - x_i is formed in FP64 and rounded
 // once to FP32 (the exact relative coordinate), the pair term is computed in
-// FP32, and each wave's FP32 sum over one staged tile is folded into FP64
+// FP32, and each lane's FP32 sum over one staged tile is folded into FP64
 // accumulators.
 //
 // Periodic cube of side L (kPer): d is replaced by its nearest image
@@ -37,44 +42,54 @@
 
 namespace {
 
-constexpr int kTile = 64;        // targets per workgroup (one per lane)
-constexpr int kWaves = 4;        // waves per workgroup, each on a quarter of every source tile
-constexpr int kThreads = kTile * kWaves;
-constexpr int kSrc = kThreads;   // sources per staged tile
-constexpr int kParts = 12;       // g (3), j (3), S (6)
+constexpr int kWaves = 8;                // waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kSrc = 2 * kThreads;       // sources per staged tile
+constexpr int kParts = 12;               // g (3), j (3), S (6)
+constexpr int kMaxGroups = 16;           // lane groups per wave (targets per workgroup >= 4)
 
 __device__ __forceinline__ double near_img(double d, double L) { return d - L * rint(d / L); }
 
-// 1/sqrt(x), x > 0 normal: the hardware estimate plus two Newton steps
-// y <- y (3 - x y^2) / 2 (each step squares the relative error)
+// 1/sqrt(x), x > 0 normal: the hardware estimate y (relative error near
+// 2^-23) corrected once by the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
+// in e = 1 - x y^2, to second order: the relative error left is about
+// (5/16) e^3, far below FP64 rounding, for five operations (two Newton steps
+// take eight)
 __device__ __forceinline__ double rsqrt_f64(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const double e = __builtin_fma(-x * y, y, 1.0);
-        y = __builtin_fma(0.5 * y, e, y);
-    }
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = __builtin_fma(-x * y, y, 1.0);
+    const double p = __builtin_fma(0.375, e, 0.5);
+    return __builtin_fma(y * e, p, y);
 }
 
-// The pair term of pair.h with the reciprocal square roots above.  The
-// Newtonian f and D are formed for every lane; the kernel interior replaces
-// them only where some lane of the wave has a source inside its softening
-// length (a wave-uniform branch, rarely taken).
 template <class R>
-__device__ __forceinline__ void pair_any(R dx, R dy, R dz, R nx, R ny, R nz, R mj, R h2, R hinv, PairAcc<R>& A) {
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    R ri;
-    if constexpr (sizeof(R) == 8) ri = rsqrt_f64(r2);
-    else ri = __builtin_amdgcn_rsqf(r2);
-    const R ri2 = ri * ri;
-    R f = ri * ri2;
-    R D = R(-3) * f * ri2;
-    if (__ballot(r2 < h2) != 0) {
-        if (r2 < h2) spline_fd<R>(r2, hinv, f, D);
+__device__ __forceinline__ R rsqrt_any(R r2) {
+    if constexpr (sizeof(R) == 8) return rsqrt_f64(r2);
+    else return __builtin_amdgcn_rsqf(r2);
+}
+
+// The sums of one target: g, j and S = sum m [f I + D d d^T], whose
+// diagonal term sum m f is kept once (smf) and added to the three diagonal
+// entries at the end.
+template <class R>
+struct DirAcc {
+    R ax, ay, az, jx, jy, jz, sxx, syy, szz, sxy, sxz, syz, smf;
+    __device__ __forceinline__ void zero() {
+        ax = ay = az = jx = jy = jz = sxx = syy = szz = sxy = sxz = syz = smf = R(0);
     }
-    const R mf = mj * f;
-    const R mD = mj * D;
+    template <class Q>
+    __device__ __forceinline__ void add(const DirAcc<Q>& B) {
+        ax += B.ax; ay += B.ay; az += B.az;
+        jx += B.jx; jy += B.jy; jz += B.jz;
+        sxx += B.sxx; syy += B.syy; szz += B.szz;
+        sxy += B.sxy; sxz += B.sxz; syz += B.syz;
+        smf += B.smf;
+    }
+};
+
+// one pair's terms from mf = m f and mD = m D (pair.h states the formulas)
+template <class R>
+__device__ __forceinline__ void pair_add(R dx, R dy, R dz, R nx, R ny, R nz, R mf, R mD, DirAcc<R>& A) {
     A.ax += mf * dx;
     A.ay += mf * dy;
     A.az += mf * dz;
@@ -84,12 +99,51 @@ __device__ __forceinline__ void pair_any(R dx, R dy, R dz, R nx, R ny, R nz, R m
     A.jy += mf * ny + s * dy;
     A.jz += mf * nz + s * dz;
     const R tx = mD * dx, ty = mD * dy, tz = mD * dz;
-    A.sxx += mf + tx * dx;
-    A.syy += mf + ty * dy;
-    A.szz += mf + tz * dz;
+    A.smf += mf;
+    A.sxx += tx * dx;
+    A.syy += ty * dy;
+    A.szz += tz * dz;
     A.sxy += tx * dy;
     A.sxz += tx * dz;
     A.syz += ty * dz;
+}
+
+// The Newtonian f and D are formed for every lane; the kernel interior
+// replaces them only where some lane of the wave has a source inside its
+// softening length (a wave-uniform branch, rarely taken).
+template <class R>
+__device__ __forceinline__ void pair_any(R dx, R dy, R dz, R nx, R ny, R nz, R mj, R h2, R hinv, DirAcc<R>& A) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R ri = rsqrt_any<R>(r2);
+    const R ri2 = ri * ri;
+    R mf = mj * (ri * ri2);
+    R mD = mf * (R(-3) * ri2);   // m D = m f (-3 / r^2) outside the kernel
+    if (__ballot(r2 < h2) != 0) {
+        if (r2 < h2) {
+            R f, D;
+            spline_fd<R>(r2, hinv, f, D);
+            mf = mj * f;
+            mD = mj * D;
+        }
+    }
+    pair_add<R>(dx, dy, dz, nx, ny, nz, mf, mD, A);
+}
+
+// per-particle softening: f and D are the means of the target's and the
+// source's kernels, each Newtonian beyond its own length
+template <class R>
+__device__ __forceinline__ void pair_soft(R dx, R dy, R dz, R nx, R ny, R nz, R mj, R hi_, R hj, DirAcc<R>& A) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R ri = rsqrt_any<R>(r2);
+    const R ri2 = ri * ri;
+    const R fN = ri * ri2;
+    const R DN = R(-3) * fN * ri2;
+    R fs[2] = {fN, fN}, Ds[2] = {DN, DN};
+    const R hs[2] = {hi_, hj};
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (r2 < hs[k] * hs[k]) spline_fd<R>(r2, R(1) / hs[k], fs[k], Ds[k]);
+    pair_add<R>(dx, dy, dz, nx, ny, nz, mj * (R(0.5) * (fs[0] + fs[1])), mj * (R(0.5) * (Ds[0] + Ds[1])), A);
 }
 
 struct DirectArgs {
@@ -101,10 +155,10 @@ struct DirectArgs {
     const int32_t* idx;      // listed rows (null: 0 .. n_act)
     int64_t n_act;
     double h, L, G;
-    int64_t chunk;           // sources per split (a multiple of kSrc)
+    int tshift;              // log2 of the targets per workgroup T (T = 64 / Gs)
+    int64_t chunk;           // sources per split
     int nsplit;
-    double* part;            // [tile][split][component][lane] FP64 sums (nsplit > 1)
-    uint32_t* count;         // [tile] splits finished (nsplit > 1), zero between calls
+    double* part;            // [tile][split][component][T] FP64 sums (nsplit > 1)
     double* acc;
     double* jerk;
     double* tidal;
@@ -117,73 +171,94 @@ union DirectLds {
         double vx[kSrc], vy[kSrc], vz[kSrc];
         double h[kSrc];
     } src;
-    double red[kWaves - 1][kParts][kTile];   // waves 1..3 hand their sums to wave 0
+    double red[kWaves][kParts][64];   // each wave's sums per target, added in wave order
 };
 
-// wave w's share of one staged tile of cnt sources: FP64 pair terms; with
-// kExcl the source at tile slot qs (the target itself) is left out
-template <bool kPer, bool kSoft, bool kExcl>
-__device__ __forceinline__ void pair_at(const DirectLds& S, const DirectArgs& P, int q, int qs, double xi, double yi,
-                                        double zi, double vxi, double vyi, double vzi, double hi_, double h2,
-                                        double hinv, PairAcc<double>& A) {
-    const double mj = (kExcl && q == qs) ? 0.0 : S.src.m[q];
-    double dx = S.src.x[q] - xi, dy = S.src.y[q] - yi, dz = S.src.z[q] - zi;
+// the separation and relative velocity of staged source q from the target
+template <bool kPer>
+__device__ __forceinline__ void sep_at(const DirectLds& S, const DirectArgs& P, int q, double xi, double yi, double zi,
+                                       double vxi, double vyi, double vzi, double& dx, double& dy, double& dz,
+                                       double& nx, double& ny, double& nz) {
+    dx = S.src.x[q] - xi;
+    dy = S.src.y[q] - yi;
+    dz = S.src.z[q] - zi;
     if (kPer) {
         dx = near_img(dx, P.L);
         dy = near_img(dy, P.L);
         dz = near_img(dz, P.L);
     }
-    const double nx = S.src.vx[q] - vxi, ny = S.src.vy[q] - vyi, nz = S.src.vz[q] - vzi;
-    if (kSoft) pair_interact_soft<double>(dx, dy, dz, nx, ny, nz, mj, hi_, S.src.h[q], A);
-    else pair_any<double>(dx, dy, dz, nx, ny, nz, mj, h2, hinv, A);
+    nx = S.src.vx[q] - vxi;
+    ny = S.src.vy[q] - vyi;
+    nz = S.src.vz[q] - vzi;
 }
 
+// a lane's share of one staged tile of cnt sources: q = q0, q0 + stride, ...;
+// with kExcl the source at tile slot qs (the lane's own target) is left out.
+// FP64 pair terms.
 template <bool kPer, bool kSoft, bool kExcl>
-__device__ __forceinline__ void pairs_tile(const DirectLds& S, const DirectArgs& P, int w, int cnt, int qs, double xi,
-                                           double yi, double zi, double vxi, double vyi, double vzi, double hi_,
-                                           double h2, double hinv, PairAcc<double>& A) {
-    for (int q = w; q < cnt; q += kWaves)
-        pair_at<kPer, kSoft, kExcl>(S, P, q, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2, hinv, A);
+__device__ __forceinline__ void pairs_tile(const DirectLds& S, const DirectArgs& P, int q0, int stride, int cnt,
+                                           int qs, double xi, double yi, double zi, double vxi, double vyi,
+                                           double vzi, double hi_, double h2, double hinv, DirAcc<double>& A) {
+    for (int q = q0; q < cnt; q += stride) {
+        double dx, dy, dz, nx, ny, nz;
+        sep_at<kPer>(S, P, q, xi, yi, zi, vxi, vyi, vzi, dx, dy, dz, nx, ny, nz);
+        const double mj = (kExcl && q == qs) ? 0.0 : S.src.m[q];
+        if (kSoft) pair_soft<double>(dx, dy, dz, nx, ny, nz, mj, hi_, S.src.h[q], A);
+        else pair_any<double>(dx, dy, dz, nx, ny, nz, mj, h2, hinv, A);
+    }
 }
 
 // the same with FP32 pair terms on the FP64 separations rounded once
 template <bool kPer, bool kSoft, bool kExcl>
-__device__ __forceinline__ void pairs_tile_f32(const DirectLds& S, const DirectArgs& P, int w, int cnt, int qs,
-                                               double xi, double yi, double zi, double vxi, double vyi, double vzi,
-                                               double hi_, float h2f, float hinvf, PairAcc<float>& B) {
-    for (int q = w; q < cnt; q += kWaves) {
+__device__ __forceinline__ void pairs_tile_f32(const DirectLds& S, const DirectArgs& P, int q0, int stride, int cnt,
+                                               int qs, double xi, double yi, double zi, double vxi, double vyi,
+                                               double vzi, double hi_, float h2f, float hinvf, DirAcc<float>& B) {
+    for (int q = q0; q < cnt; q += stride) {
+        double dx, dy, dz, nx, ny, nz;
+        sep_at<kPer>(S, P, q, xi, yi, zi, vxi, vyi, vzi, dx, dy, dz, nx, ny, nz);
         const float mj = (kExcl && q == qs) ? 0.0f : (float)S.src.m[q];
-        double dx = S.src.x[q] - xi, dy = S.src.y[q] - yi, dz = S.src.z[q] - zi;
-        if (kPer) {
-            dx = near_img(dx, P.L);
-            dy = near_img(dy, P.L);
-            dz = near_img(dz, P.L);
-        }
-        const float nx = (float)(S.src.vx[q] - vxi), ny = (float)(S.src.vy[q] - vyi), nz = (float)(S.src.vz[q] - vzi);
         if (kSoft)
-            pair_interact_soft<float>((float)dx, (float)dy, (float)dz, nx, ny, nz, mj, (float)hi_, (float)S.src.h[q],
-                                      B);
+            pair_soft<float>((float)dx, (float)dy, (float)dz, (float)nx, (float)ny, (float)nz, mj, (float)hi_,
+                             (float)S.src.h[q], B);
         else
-            pair_any<float>((float)dx, (float)dy, (float)dz, nx, ny, nz, mj, h2f, hinvf, B);
+            pair_any<float>((float)dx, (float)dy, (float)dz, (float)nx, (float)ny, (float)nz, mj, h2f, hinvf, B);
     }
 }
 
-template <bool kFP64, bool kPer, bool kSoft>
-__global__ void __launch_bounds__(kThreads) k_direct(DirectArgs P) {
-    __shared__ DirectLds S;
-    __shared__ bool s_last;
-    const int lane = threadIdx.x & (kTile - 1);
-    const int w = threadIdx.x / kTile;
-    const int64_t k = (int64_t)blockIdx.x * kTile + lane;
-    const bool live = k < P.n_act;
-    int64_t i = -1;
-    if (live) {
-        i = P.idx ? (int64_t)P.idx[k] : k;
-        if (i < 0 || i >= P.n) {
-            if (w == 0) atomicOr(P.flags, AGF_BADINDEX);
-            i = -1;
-        }
+// one target row's outputs from its FP64 sums (component c of 12)
+__device__ __forceinline__ void write_row(const DirectArgs& P, int64_t r, int c, double sum) {
+    if (c < 3) {
+        if (P.acc) P.acc[3 * r + c] = P.G * sum;
+    } else if (c < 6) {
+        if (P.jerk) P.jerk[3 * r + c - 3] = P.G * sum;
+    } else if (P.tidal) {
+        P.tidal[6 * r + c - 6] = -P.G * sum;
     }
+}
+
+// the row of listed target k, or -1 (past the list, or a bad index: flagged)
+__device__ __forceinline__ int64_t target_row(const DirectArgs& P, int64_t k, bool flag) {
+    if (k >= P.n_act) return -1;
+    const int64_t i = P.idx ? (int64_t)P.idx[k] : k;
+    if (i < 0 || i >= P.n) {
+        if (flag) atomicOr(P.flags, AGF_BADINDEX);
+        return -1;
+    }
+    return i;
+}
+
+// (a register count of at most 128 keeps two workgroups, 16 waves, per CU)
+template <bool kFP64, bool kPer, bool kSoft>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_direct(DirectArgs P) {
+    __shared__ DirectLds S;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int T = 1 << P.tshift;               // targets per workgroup
+    const int Gs = 64 >> P.tshift;             // lane groups per wave
+    const int t = lane & (T - 1);
+    const int sub = w * Gs + (lane >> P.tshift);   // this lane's source subset
+    const int nsub = kWaves * Gs;
+    const int64_t i = target_row(P, (int64_t)blockIdx.x * T + t, lane < T && w == 0);
     double xi = 0, yi = 0, zi = 0, vxi = 0, vyi = 0, vzi = 0, hi_ = 1.0;
     if (i >= 0) {
         xi = P.x[3 * i]; yi = P.x[3 * i + 1]; zi = P.x[3 * i + 2];
@@ -193,159 +268,136 @@ __global__ void __launch_bounds__(kThreads) k_direct(DirectArgs P) {
     const int64_t j0 = (int64_t)blockIdx.y * P.chunk;
     const int64_t j1 = j0 + P.chunk < P.n ? j0 + P.chunk : P.n;
 
-    PairAcc<double> A;
+    DirAcc<double> A;
     A.zero();
     const double h2 = P.h * P.h, hinv = 1.0 / P.h;
     const float h2f = (float)h2, hinvf = (float)hinv;
-
     for (int64_t t0 = j0; t0 < j1; t0 += kSrc) {
-        const int64_t js = t0 + threadIdx.x;
         __syncthreads();
-        if (js < j1) {
-            S.src.x[threadIdx.x] = P.x[3 * js];
-            S.src.y[threadIdx.x] = P.x[3 * js + 1];
-            S.src.z[threadIdx.x] = P.x[3 * js + 2];
-            S.src.m[threadIdx.x] = P.m[js];
-            S.src.vx[threadIdx.x] = P.v[3 * js];
-            S.src.vy[threadIdx.x] = P.v[3 * js + 1];
-            S.src.vz[threadIdx.x] = P.v[3 * js + 2];
-            if (kSoft) S.src.h[threadIdx.x] = P.hs[js];
+#pragma unroll
+        for (int u = threadIdx.x; u < kSrc; u += kThreads) {
+            const int64_t js = t0 + u;
+            if (js < j1) {
+                S.src.x[u] = P.x[3 * js];
+                S.src.y[u] = P.x[3 * js + 1];
+                S.src.z[u] = P.x[3 * js + 2];
+                S.src.m[u] = P.m[js];
+                S.src.vx[u] = P.v[3 * js];
+                S.src.vy[u] = P.v[3 * js + 1];
+                S.src.vz[u] = P.v[3 * js + 2];
+                if (kSoft) S.src.h[u] = P.hs[js];
+            }
         }
         __syncthreads();
         const int cnt = (int)((j1 - t0) < kSrc ? (j1 - t0) : kSrc);
         // the self pair is left out: only the tiles that hold one of the
-        // wave's own targets (one tile in n / 256 when every row is listed)
-        // pay for the test
+        // wave's own targets pay for the test
         const bool self_here = __ballot(i >= t0 && i < t0 + cnt) != 0;
         if (i < 0) continue;
-        const int qs = self_here ? (int)(i - t0) : -1;   // -1 never matches
+        const int qs = (i >= t0 && i < t0 + cnt) ? (int)(i - t0) : -1;   // -1 never matches
         if (kFP64) {
-            if (self_here) pairs_tile<kPer, kSoft, true>(S, P, w, cnt, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2, hinv, A);
-            else pairs_tile<kPer, kSoft, false>(S, P, w, cnt, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2, hinv, A);
+            if (self_here) pairs_tile<kPer, kSoft, true>(S, P, sub, nsub, cnt, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2, hinv, A);
+            else pairs_tile<kPer, kSoft, false>(S, P, sub, nsub, cnt, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2, hinv, A);
         } else {
-            PairAcc<float> B;
+            DirAcc<float> B;
             B.zero();
             if (self_here)
-                pairs_tile_f32<kPer, kSoft, true>(S, P, w, cnt, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2f, hinvf, B);
+                pairs_tile_f32<kPer, kSoft, true>(S, P, sub, nsub, cnt, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2f, hinvf, B);
             else
-                pairs_tile_f32<kPer, kSoft, false>(S, P, w, cnt, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2f, hinvf, B);
-            A.ax += B.ax; A.ay += B.ay; A.az += B.az;
-            A.jx += B.jx; A.jy += B.jy; A.jz += B.jz;
-            A.sxx += B.sxx; A.syy += B.syy; A.szz += B.szz;
-            A.sxy += B.sxy; A.sxz += B.sxz; A.syz += B.syz;
+                pairs_tile_f32<kPer, kSoft, false>(S, P, sub, nsub, cnt, qs, xi, yi, zi, vxi, vyi, vzi, hi_, h2f, hinvf, B);
+            A.add(B);
         }
     }
-    // the four waves' sums, added in wave order by wave 0
-    double vals[kParts] = {A.ax, A.ay, A.az, A.jx, A.jy, A.jz, A.sxx, A.syy, A.szz, A.sxy, A.sxz, A.syz};
+    // the Gs lane groups of the wave: a butterfly over lane offsets T, 2T, ...
+    // (every lane of a target ends with the same tree sum)
+    double vals[kParts] = {A.ax,         A.ay,         A.az,         A.jx,  A.jy,  A.jz,
+                           A.smf + A.sxx, A.smf + A.syy, A.smf + A.szz, A.sxy, A.sxz, A.syz};
+    for (int off = T; off < 64; off <<= 1) {
+#pragma unroll
+        for (int c = 0; c < kParts; ++c) vals[c] += __shfl_xor(vals[c], off);
+    }
     __syncthreads();   // every wave is done with the staged sources
-    if (w > 0) {
+    if (lane < T) {
 #pragma unroll
-        for (int c = 0; c < kParts; ++c) S.red[w - 1][c][lane] = vals[c];
+        for (int c = 0; c < kParts; ++c) S.red[w][c][lane] = vals[c];
     }
     __syncthreads();
+    // the eight waves, added in wave order: one thread per (component, target)
     const int64_t tile = blockIdx.x;
-    if (w == 0) {
+    for (int e = threadIdx.x; e < kParts * T; e += kThreads) {
+        const int c = e >> P.tshift, tt = e & (T - 1);
+        double sum = S.red[0][c][tt];
 #pragma unroll
-        for (int c = 0; c < kParts; ++c)
-            vals[c] = (vals[c] + S.red[0][c][lane]) + (S.red[1][c][lane] + S.red[2][c][lane]);
+        for (int ww = 1; ww < kWaves; ++ww) sum += S.red[ww][c][tt];
         if (P.nsplit == 1) {
-            if (i >= 0) {
-                if (P.acc) {
-                    P.acc[3 * i] = P.G * vals[0]; P.acc[3 * i + 1] = P.G * vals[1]; P.acc[3 * i + 2] = P.G * vals[2];
-                }
-                if (P.jerk) {
-                    P.jerk[3 * i] = P.G * vals[3]; P.jerk[3 * i + 1] = P.G * vals[4]; P.jerk[3 * i + 2] = P.G * vals[5];
-                }
-                if (P.tidal) {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) P.tidal[6 * i + c] = -P.G * vals[6 + c];
-                }
-            }
-            return;
-        }
-        double* p = P.part + ((tile * P.nsplit + blockIdx.y) * kParts) * kTile + lane;
-#pragma unroll
-        for (int c = 0; c < kParts; ++c) p[c * kTile] = vals[c];
-    }
-    if (P.nsplit == 1) return;
-    // the last split of this tile to finish adds them all, in split order
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t done =
-            __hip_atomic_fetch_add(P.count + tile, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = done == (uint32_t)(P.nsplit - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // (every thread) see the other splits' sums
-    // every thread adds the splits of three (component, target) entries in
-    // split order, its loads issued eight splits at a time
-    const double* base = P.part + tile * P.nsplit * (kParts * kTile);
-    for (int e = threadIdx.x; e < kParts * kTile; e += kThreads) {
-        const int c = e / kTile, l = e % kTile;
-        double sum = 0.0;
-        int q = 0;
-        for (; q + 8 <= P.nsplit; q += 8) {
-            double t[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) t[u] = base[(q + u) * (kParts * kTile) + e];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) sum += t[u];
-        }
-        for (; q < P.nsplit; ++q) sum += base[q * (kParts * kTile) + e];
-        const int64_t kk = tile * kTile + l;
-        if (kk >= P.n_act) continue;
-        const int64_t r = P.idx ? (int64_t)P.idx[kk] : kk;
-        if (r < 0 || r >= P.n) continue;
-        if (c < 3) {
-            if (P.acc) P.acc[3 * r + c] = P.G * sum;
-        } else if (c < 6) {
-            if (P.jerk) P.jerk[3 * r + c - 3] = P.G * sum;
-        } else if (P.tidal) {
-            P.tidal[6 * r + c - 6] = -P.G * sum;
+            const int64_t r = target_row(P, tile * T + tt, false);
+            if (r >= 0) write_row(P, r, c, sum);
+        } else {
+            P.part[((tile * P.nsplit + blockIdx.y) * kParts + c) * T + tt] = sum;
         }
     }
-    if (threadIdx.x == 0) P.count[tile] = 0u;   // ready for the next call
+}
+
+// the splits of each target tile added in split order (a split launch only)
+__global__ void __launch_bounds__(256) k_direct_splits(DirectArgs P, int64_t tiles) {
+    const int T = 1 << P.tshift;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, component, target)
+    if (e >= tiles * kParts * T) return;
+    const int64_t tile = e / (kParts * T);
+    const int c = (int)((e / T) % kParts), tt = (int)(e & (T - 1));
+    const double* p = P.part + (tile * P.nsplit * kParts + c) * T + tt;
+    double sum = 0.0;
+    for (int q = 0; q < P.nsplit; ++q) sum += p[(int64_t)q * kParts * T];
+    const int64_t r = target_row(P, tile * T + tt, false);
+    if (r >= 0) write_row(P, r, c, sum);
 }
 
 }  // namespace
 
-// Launch shape: target tiles of 64 and a source split that gives at least
-// kDirectBlocks workgroups (so a split happens only with fewer tiles than
-// that).  Scratch, with a split: a counter per tile at the start (fixed
-// place, zero between calls: the last split of a tile resets it), then one
-// FP64 sum per tile, split, component and target.
-constexpr int64_t kDirectBlocks = 1024;
-constexpr size_t kCountBytes = kDirectBlocks * sizeof(uint32_t);
+// Launch shape: the fewest lane groups per wave Gs (1 .. 16) that give at
+// least kDirectBlocks workgroups (two per CU); only below that at Gs = 16 is
+// the source range split as well (grid.y), so that tiles x splits stays
+// below 2 kDirectBlocks.  Each split covers a multiple of the 8 Gs subsets.
+constexpr int64_t kDirectBlocks = 512;
 
-void ag_direct_shape(int64_t n, int64_t n_act, int64_t* tiles, int64_t* nsplit, int64_t* chunk) {
-    const int64_t t = (n_act + kTile - 1) / kTile;
-    int64_t s = (kDirectBlocks + t - 1) / t;
-    const int64_t max_split = (n + kSrc - 1) / kSrc;
-    if (s > max_split) s = max_split;
-    if (s > 65535) s = 65535;
-    if (s < 1) s = 1;
+void ag_direct_shape(int64_t n, int64_t n_act, int* tshift, int64_t* tiles, int64_t* nsplit, int64_t* chunk) {
+    int ts = 6;
+    int64_t t = (n_act + 63) >> 6;
+    while (ts > 2 && t < kDirectBlocks) {
+        --ts;
+        t = (n_act + (1 << ts) - 1) >> ts;
+    }
+    const int64_t nsub = (int64_t)kWaves * (64 >> ts);
+    int64_t s = 1;
+    if (t < kDirectBlocks) {
+        s = (kDirectBlocks + t - 1) / t;
+        const int64_t max_split = (n + nsub - 1) / nsub;
+        if (s > max_split) s = max_split;
+        if (s > 65535) s = 65535;
+        if (s < 1) s = 1;
+    }
     int64_t c = (n + s - 1) / s;
-    c = (c + kSrc - 1) / kSrc * kSrc;
+    c = (c + nsub - 1) / nsub * nsub;
+    *tshift = ts;
     *tiles = t;
     *nsplit = (n + c - 1) / c;
     *chunk = c;
 }
 
 size_t ag_direct_scratch_bytes(int64_t n, int64_t n_act) {
+    int ts;
     int64_t t, s, c;
-    ag_direct_shape(n, n_act, &t, &s, &c);
+    ag_direct_shape(n, n_act, &ts, &t, &s, &c);
     if (s <= 1) return 0;
-    return kCountBytes + (size_t)t * s * kParts * kTile * sizeof(double);
+    return (size_t)t * s * kParts * ((size_t)1 << ts) * sizeof(double);
 }
-
-size_t ag_direct_count_bytes() { return kCountBytes; }
 
 int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
                      const int32_t* idx, int64_t n_act, double eps, double G, int precision,
                      double* acc, double* jerk, double* tidal, void* scratch, bool timed) {
+    int tshift;
     int64_t tiles, nsplit, chunk;
-    ag_direct_shape(n, n_act, &tiles, &nsplit, &chunk);
+    ag_direct_shape(n, n_act, &tshift, &tiles, &nsplit, &chunk);
     DirectArgs P{};
     P.n = n;
     P.x = x;
@@ -357,10 +409,10 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
     P.h = eps;
     P.L = c->box;
     P.G = G;
+    P.tshift = tshift;
     P.chunk = chunk;
     P.nsplit = (int)nsplit;
-    P.count = nsplit > 1 ? reinterpret_cast<uint32_t*>(scratch) : nullptr;
-    P.part = nsplit > 1 ? reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) + kCountBytes) : nullptr;
+    P.part = nsplit > 1 ? reinterpret_cast<double*>(scratch) : nullptr;
     P.acc = acc;
     P.jerk = jerk;
     P.tidal = tidal;
@@ -378,20 +430,24 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
         else { if (soft) AG_DIRECT(false, false, true); else AG_DIRECT(false, false, false); }
     }
 #undef AG_DIRECT
+    if (nsplit > 1) {
+        const int64_t work = tiles * kParts * ((int64_t)1 << tshift);
+        hipLaunchKernelGGL(k_direct_splits, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, P, tiles);
+    }
     return AG_OK;
 }
 
 // ---------------------------------------------------------------------------
 // The allocation-free direct sum, for callers that cannot allocate device
-// memory: the split counters and split sums live in a file-scope device array
-// of fixed size.  The launch shape bounds the scratch for every size (a split
-// happens only with fewer than kDirectBlocks target tiles, so tiles x splits
+// memory: the split sums live in a file-scope device array of fixed size.
+// The launch shape bounds the scratch for every size (a split happens only
+// with fewer than kDirectBlocks target tiles of 4, so tiles x splits
 // < 2 kDirectBlocks), so no call is refused for its size.  Every call on a
 // device shares that device's copy of the array: calls that overlap on one
 // device race.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr size_t kNoAllocBytes = kCountBytes + (size_t)(2 * kDirectBlocks) * kParts * kTile * sizeof(double);
+constexpr size_t kNoAllocBytes = (size_t)(2 * kDirectBlocks) * kParts * 4 * sizeof(double);
 __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 constexpr int kMaxDevices = 64;
@@ -407,10 +463,6 @@ int ag_direct_noalloc_init(int device) {
     hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
     if (e != hipSuccess || !p)
         return ag_fail(AG_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
-    // the split counters start at zero; each launch leaves them at zero
-    e = hipMemset(p, 0, kCountBytes);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) return ag_fail(AG_EHIP, "clearing the direct-sum scratch failed: %s", hipGetErrorString(e));
     g_scratch_ptr[device] = p;
     return AG_OK;
 }
