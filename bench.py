@@ -51,11 +51,11 @@ PEAK_HBM_GBS = 8000.0
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "00827a62f91acc9cffccd454fbe12243bfe061dbd83400b6095f58195d81c89c",
+    "src_sha256": "643ed7ed30712f36ab3830f030f22e6221727022ca41bc27532ca1b120fa4c46",
     "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64,
                  "waves_per_cu": 16, "group_split": 42, "group_pack": 0},
-    "fetch_kib": 354244.1, "write_kib": 222398.0,
-    "fetch_factor": 1048576.0 / 524304.6, "write_factor": 1.0,
+    "fetch_kib": 351918.5, "write_kib": 222333.9,
+    "fetch_factor": 1048576.0 / 524304.9, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);

@@ -91,6 +91,24 @@ def test_direct_ragged_and_subsets(ag, ctx, orc, n, frac):
         assert np.median(tensor_rel_err(t[act], tr)) <= tol
 
 
+@pytest.mark.parametrize("n", [9000, 20000, 40000])
+def test_direct_wide_target_sets(ag, ctx, orc, n):
+    """Every row a target at sizes where each workgroup holds 16, 32 and 64
+    targets (4, 2 and 1 lane groups per wave): sampled rows against the
+    oracle, in both precisions, with a ragged last tile."""
+    x, v, m = workloads.plummer(n, seed=n)
+    eps, G = 0.01, 1.0
+    rows = np.random.default_rng(n).choice(n, 64, replace=False)
+    rows = np.concatenate([rows, [0, n - 1]])
+    ar, jr, tr = orc.direct(x, v, m, eps, G, rows)
+    for prec, tol in ((ag.AG_FP64, 1e-12), (ag.AG_FP32_PAIRS, 1e-5)):
+        a, j, t = _run_direct(ag, ctx, x, v, m, eps, G, prec)
+        assert np.all(np.isfinite(a)) and np.all(np.isfinite(t))
+        assert np.median(rel_err(a[rows], ar)) <= tol
+        assert np.median(rel_err(j[rows], jr)) <= tol
+        assert np.median(tensor_rel_err(t[rows], tr)) <= tol
+
+
 def test_direct_coincident_and_softened(ag, ctx, orc):
     """Coincident particles and pairs inside the softening length."""
     rng = np.random.default_rng(9)

@@ -1,8 +1,9 @@
 """The allocation-free direct sum (ag_grav_direct_noalloc) against
 ag_grav_direct: the same kernels on library-held scratch, so the results are
-bit-identical; two calls in a row, the second with a smaller input (the
-shared scratch and its split counters are reused), in both precisions, with
-a listed subset and with every row; and its argument checks."""
+bit-identical; two calls in a row that both split their sources over
+workgroups (small listed target sets), the second with a smaller input (the
+shared scratch is reused), then every row of a set that fills the device
+without a split; in both precisions; and its argument checks."""
 import numpy as np
 import pytest
 import torch
@@ -24,7 +25,10 @@ def _outputs(n):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_noalloc_matches_direct(ag, prec):
     p = ag.AG_FP64 if prec == "fp64" else ag.AG_FP32_PAIRS
-    cases = [(4096, None), (1500, np.random.default_rng(2).permutation(1500)[:333])]   # second: smaller
+    # the first needs nearly the whole scratch (475 tiles of 4 targets, 2 splits),
+    # the second is smaller, the third splits nothing
+    cases = [(20000, np.random.default_rng(1).permutation(20000)[:1900]),
+             (1500, np.random.default_rng(2).permutation(1500)[:333]), (4096, None)]
     with ag.Context(0) as c:
         for n, act in cases:
             x, v, m = workloads.plummer(n, seed=n)
