@@ -46,7 +46,7 @@ constexpr int kWaves = 8;                // waves per workgroup
 constexpr int kThreads = 64 * kWaves;
 constexpr int kSrc = 2 * kThreads;       // sources per staged tile
 constexpr int kParts = 12;               // g (3), j (3), S (6)
-constexpr int kMaxGroups = 16;           // lane groups per wave (targets per workgroup >= 4)
+constexpr int kMinTShift = 2;            // at least 4 targets per workgroup (at most 16 lane groups)
 
 __device__ __forceinline__ double near_img(double d, double L) { return d - L * rint(d / L); }
 
@@ -363,7 +363,7 @@ constexpr int64_t kDirectBlocks = 512;
 void ag_direct_shape(int64_t n, int64_t n_act, int* tshift, int64_t* tiles, int64_t* nsplit, int64_t* chunk) {
     int ts = 6;
     int64_t t = (n_act + 63) >> 6;
-    while (ts > 2 && t < kDirectBlocks) {
+    while (ts > kMinTShift && t < kDirectBlocks) {
         --ts;
         t = (n_act + (1 << ts) - 1) >> ts;
     }
