@@ -71,7 +71,8 @@ def test_direct_fp32_pairs_plummer_4096(ag, ctx, orc):
 
 @pytest.mark.parametrize("n,frac", [(1, 1.0), (2, 1.0), (257, 1.0), (1000, 0.3), (3001, 0.01)])
 def test_direct_ragged_and_subsets(ag, ctx, orc, n, frac):
-    """Ragged sizes (not multiples of the 256-wide tile), partial active sets
+    """Ragged sizes (not multiples of the target tile or the staged source tile),
+    small target sets split over workgroups, partial active sets
     in random order; rows not listed stay untouched."""
     x, v, m = workloads.plummer(n, seed=n)
     m = m * np.random.default_rng(n).uniform(0.5, 1.5, n)
