@@ -88,6 +88,33 @@ def test_direct_periodic(ag, orc, prec):
         assert np.median(tensor_rel_err(T, Tr)) <= 1e-4
 
 
+@pytest.mark.parametrize("n,frac", [(9000, 1.0), (3001, 0.05)])
+def test_direct_periodic_launch_shapes(ag, orc, n, frac):
+    """The nearest-image direct sum at the launch shapes the 3001-particle
+    test does not reach: 16 targets per workgroup (every row of 9000), and a
+    small listed set whose sources are split over workgroups; sampled rows
+    against the oracle at the FP64 bound of the cancellation-free sizes."""
+    L, eps = 1.0, 1e-2
+    x, v, m = _clumps_in_box(n, seed=n)
+    act = None if frac == 1.0 else np.sort(workloads.random_subset(n, frac, seed=n))
+    rows = np.random.default_rng(n).choice(n if act is None else act, 48, replace=False)
+    for prec in ("fp64", "fp32"):
+        p = ag.AG_FP64 if prec == "fp64" else ag.AG_FP32_PAIRS
+        a, j, T = _direct(ag, L, x, v, m, eps, p, act)
+        ar, jr, Tr = orc.direct(x, v, m, eps, 1.0, rows, box=L)
+        if act is not None:
+            other = np.setdiff1d(np.arange(n), act)
+            assert np.all(np.isnan(a[other]))
+        if prec == "fp64":
+            sa, sj, st = _scales(orc, x, v, m, eps, rows, L)
+            assert np.max(np.abs(a[rows] - ar).max(axis=1) / sa) <= 1e-12
+            assert np.max(np.abs(j[rows] - jr).max(axis=1) / sj) <= 1e-12
+            assert np.max(np.abs(T[rows] - Tr).max(axis=1) / st) <= 1e-12
+        else:
+            assert np.median(rel_err(a[rows], ar)) <= 1e-5
+            assert np.median(tensor_rel_err(T[rows], Tr)) <= 1e-4
+
+
 def _tree_case(name):
     if name == "clumps":
         x, v, m = _clumps_in_box(1 << 15)

@@ -62,6 +62,38 @@ def test_direct_soft(ag, orc, prec):
         assert np.median(tensor_rel_err(T, Tr)) <= 1e-4
 
 
+@pytest.mark.parametrize("n,frac", [(9000, 1.0), (3001, 0.05)])
+def test_direct_soft_launch_shapes(ag, orc, n, frac):
+    """Per-particle softening in the direct sum at 16 targets per workgroup
+    (every row of 9000) and with a small listed set split over workgroups;
+    sampled rows against the oracle."""
+    x, v, m, h = _clumps_soft(n, seed=n)
+    act = None if frac == 1.0 else np.sort(workloads.random_subset(n, frac, seed=n))
+    rows = np.random.default_rng(n).choice(n if act is None else act, 48, replace=False)
+    ar, jr, Tr = orc.direct_soft(x, v, m, h, 1.0, rows)
+    sa = _bound(x, m, h, rows)
+    for prec in ("fp64", "fp32"):
+        with ag.Context(0) as c:
+            c.set_softening(_t(h))
+            out = _outputs(n)
+            ia = None if act is None else _t(act.astype(np.int32), torch.int32)
+            c.grav_direct(_t(x), _t(v), _t(m), ia, 1e-3, 1.0, *out,
+                          precision=ag.AG_FP64 if prec == "fp64" else ag.AG_FP32_PAIRS)
+            c.sync()
+        a, j, T = (o.cpu().numpy() for o in out)
+        if act is not None:
+            other = np.setdiff1d(np.arange(n), act)
+            assert np.all(np.isnan(a[other]))
+        if prec == "fp64":
+            assert np.max(np.abs(a[rows] - ar).max(axis=1) / sa) <= 1e-12
+            assert np.median(rel_err(a[rows], ar)) <= 1e-12
+            assert np.median(tensor_rel_err(T[rows], Tr)) <= 1e-11
+            assert np.median(rel_err(j[rows], jr)) <= 1e-11
+        else:
+            assert np.median(rel_err(a[rows], ar)) <= 1e-5
+            assert np.median(tensor_rel_err(T[rows], Tr)) <= 1e-4
+
+
 def _tree_soft(ag, x, v, m, h, theta, active=None, box=0.0, ewald=False):
     with ag.Context(0) as c:
         if box:
