@@ -64,10 +64,10 @@ WALK_EXECUTED_FP32_FLOPS = (2494782010.0 + 22164085.0) * 64
 WALK_SOURCES = ("paper_2010_13792_amd/csrc/k_walk.hip", "paper_2010_13792_amd/csrc/pair.h",
                 "paper_2010_13792_amd/csrc/ag_internal.h")
 # algorithmic bytes of one build: per particle, read x, v, m (56), write them
-# in key order (spos + svel as double4 and FP32 velocities: 80), keys and rows
-# (24); per node, link 16, centre 32, box 32, FP32 moments 64 and FP64
+# in key order (positions and masses as double4, FP32 velocities and masses:
+# 48), keys and rows (24); per node, link 16, centre 32, box 32, FP32 moments 64 and FP64
 # moments 200 (344)
-BUILD_BYTES_PER_PARTICLE = 56 + 80 + 24
+BUILD_BYTES_PER_PARTICLE = 56 + 48 + 24
 BUILD_BYTES_PER_NODE = 344
 
 

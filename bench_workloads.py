@@ -804,10 +804,11 @@ def run_relative(args):
 
 # ---------------------------------------------------------------------------
 # algorithmic bytes of one build: per particle, read x, v, m (56), write them
-# in key order (spos + svel as double4 and FP32 velocities: 80), Morton keys
+# in key order (positions and masses as double4, FP32 velocities and masses:
+# 48), Morton keys
 # and row indices (8 + 4, written and read once: 24); per node, link 16,
 # centre 32, box 32, FP32 moments 64 and FP64 moments 200 (344)
-BUILD_BYTES_PER_PARTICLE = 56 + 80 + 24
+BUILD_BYTES_PER_PARTICLE = 56 + 48 + 24
 BUILD_BYTES_PER_NODE = 344
 
 

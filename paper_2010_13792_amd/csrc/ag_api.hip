@@ -197,7 +197,7 @@ extern "C" int ag_destroy(ag_ctx* c) {
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->sort_hist, &c->perm,
-                      &c->rank, &c->spos, &c->svel, &c->svf, &c->cdig, &c->cd_min, &c->pos_cnt, &c->pos_off,
+                      &c->rank, &c->spos, &c->svf, &c->cdig, &c->cd_min, &c->pos_cnt, &c->pos_off,
                       &c->scan_tmp, &c->nd_com, &c->nd_lo, &c->nd_hi, &c->nd_link, &c->nd_mp,
                       &c->nd_64, &c->nd_w, &c->nd_wf, &c->in_list, &c->in_cnt, &c->in_off,
                       &c->tree_hdr, &c->lvl_list, &c->leaf_list, &c->leaf_pos, &c->child, &c->sys_off, &c->sys_root, &c->sys_box, &c->act_flag,

@@ -104,7 +104,6 @@ struct ag_ctx {
     DevBuf perm;                  // i32 [n]: sorted position -> input row
     DevBuf rank;                  // i32 [n]: input row -> sorted position
     DevBuf spos;                  // double4 [n]: sorted x, y, z, m
-    DevBuf svel;                  // double4 [n]: sorted vx, vy, vz, 0
     DevBuf svf;                   // float4  [n]: sorted vx, vy, vz, m (FP32 copies)
     DevBuf cdig;                  // i32 [n]: octal digits shared with the previous key
     DevBuf cd_min;                // i32: their minima over runs of 16, 256, ... 2^24 positions

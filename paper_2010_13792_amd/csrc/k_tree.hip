@@ -416,11 +416,13 @@ int grid_for(int64_t n, int threads = kThreads) {
 
 // ---------------------------------------------------------------------------
 // 4. particle data into key order: coalesced reads in input order, each row
-//    written to its sorted position (scattered 32-byte stores).  Positions
-//    and velocities go in two passes, so that the lines each pass scatters
-//    into stay few enough to be merged in the last-level cache before they
-//    reach HBM; the FP32 velocity copies are written later, in order, by
-//    the leaf moments.
+//    written to its sorted position (scattered 32-byte stores, which the
+//    last-level cache merges before they reach HBM).  Velocities are not
+//    written in key order: the leaf moments read them through the sorted
+//    rows (perm) and write the FP32 copies the walk uses, in order.
+//    (Reading the positions that way too, with no scatter at all, was slower
+//    on randomly ordered input: the gathered 24-byte reads cost more than
+//    the merged stores.)
 // ---------------------------------------------------------------------------
 __global__ void k_to_sorted_pos(int64_t n, const int32_t* __restrict__ rank, const double* __restrict__ x,
                                 const double* __restrict__ m, double4* __restrict__ spos, double pbox,
@@ -432,19 +434,11 @@ __global__ void k_to_sorted_pos(int64_t n, const int32_t* __restrict__ rank, con
         if (h) sh[p] = f_up(h[i]);   // per-particle softening, rounded up
     }
 }
-__global__ void k_to_sorted_vel(int64_t n, const int32_t* __restrict__ rank, const double* __restrict__ v,
-                                double4* __restrict__ svel) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        svel[rank[i]] = make_double4(v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0);
-}
-void launch_to_sorted(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m, double pbox) {
+void launch_to_sorted(ag_ctx* c, int64_t n, const double* x, const double* m, double pbox) {
     const int32_t* rank = c->rank.as<int32_t>();
     hipLaunchKernelGGL(k_to_sorted_pos, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, rank, x, m,
                        c->spos.as<double4>(), pbox, c->tree_soft ? c->soft_h.as<double>() : nullptr,
                        c->soft_s.as<float>());
-    hipLaunchKernelGGL(k_to_sorted_vel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, n, rank, v,
-                       c->svel.as<double4>());
 }
 
 // ---------------------------------------------------------------------------
@@ -1416,15 +1410,17 @@ __device__ void form_inner(int in, int id, int s, const int32_t* __restrict__ ch
 // list order, so a wave reads a contiguous run of particles), each lane
 // summing every kLeafLanes-th particle about the leaf's first one, the sums
 // added across the group by DPP moves and the record written by the whole
-// group.  The FP32 copies of the velocities and masses (for the walk) are
-// written here as well, in order.
+// group.  The velocities are read from the caller's array through the
+// sorted rows (perm: position -> input row); their FP32 copies, with the
+// masses (for the walk), are written here in order.
 constexpr int kLeafLanes = 4;
 constexpr int kInnerLanes = 8;
 __global__ void __launch_bounds__(kThreads) k_leaf_moments(const int64_t* __restrict__ hdr,
                                                            const int32_t* __restrict__ leaves,
                                                            const int32_t* __restrict__ leaf_pos,
                                                            const double4* __restrict__ spos,
-                                                           const double4* __restrict__ svel,
+                                                           const int32_t* __restrict__ perm,
+                                                           const double* __restrict__ v,
                                                            float4* __restrict__ svf, NodeOut O) {
     constexpr int G = kLeafLanes;
     const int64_t nl = hdr[0] - hdr[2];
@@ -1436,18 +1432,20 @@ __global__ void __launch_bounds__(kThreads) k_leaf_moments(const int64_t* __rest
         MomentSums S;
         S.init();
         {
-            const double4 a = spos[p0], u = svel[p0];
+            const double4 a = spos[p0];
+            const int64_t r = perm[p0];
             S.r0[0] = a.x; S.r0[1] = a.y; S.r0[2] = a.z;
-            S.u0[0] = u.x; S.u0[1] = u.y; S.u0[2] = u.z;
+            S.u0[0] = v[3 * r]; S.u0[1] = v[3 * r + 1]; S.u0[2] = v[3 * r + 2];
             S.first = false;
         }
         float hm = 0.f;
         for (int q = p0 + s; q < p1; q += G) {
             const double4 a = spos[q];
-            const double4 u = svel[q];
-            svf[q] = make_float4((float)u.x, (float)u.y, (float)u.z, (float)a.w);
-            const double x[3] = {a.x, a.y, a.z}, v[3] = {u.x, u.y, u.z};
-            S.add(a.w, x, v);
+            const int64_t r = perm[q];
+            const double u[3] = {v[3 * r], v[3 * r + 1], v[3 * r + 2]};
+            svf[q] = make_float4((float)u[0], (float)u[1], (float)u[2], (float)a.w);
+            const double x[3] = {a.x, a.y, a.z};
+            S.add(a.w, x, u);
             S.box(x, x);
             if (O.sh) hm = fmaxf(hm, O.sh[q]);
         }
@@ -1491,14 +1489,14 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 // usually empty), the levels from there to 3 one launch each, and levels 2-0
 // (at most 73 nodes) one single-workgroup launch.  A deeper tree than
 // expected is still complete, only slower.
-int moments_pass(ag_ctx* c) {
+int moments_pass(ag_ctx* c, const double* v) {
     hipStream_t st = c->stream;
     NodeOut O{c->nd_com.as<double4>(), c->nd_lo.as<float4>(), c->nd_hi.as<float4>(), c->nd_mp.as<float4>(),
               c->nd_64.as<double>(), c->tree_soft ? c->soft_s.as<float>() : nullptr};
     const int64_t n = c->n;
     hipLaunchKernelGGL(k_leaf_moments, dim3(grid_for(kLeafLanes * n)), dim3(kThreads), 0, st, c->tree_hdr.as<int64_t>(),
                        c->leaf_list.as<int32_t>(), c->leaf_pos.as<int32_t>(), c->spos.as<double4>(),
-                       c->svel.as<double4>(), c->svf.as<float4>(), O);
+                       c->perm.as<int32_t>(), v, c->svf.as<float4>(), O);
     // level-21 cells are always leaves; empty levels exit at once
     const int64_t inner_bound = c->max_nodes - n;
     int g = grid_for(kInnerLanes * (inner_bound > 0 ? inner_bound : 1));
@@ -1543,7 +1541,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
                                                 (size_t)wblocks * (kLevels + 1) * sizeof(int32_t)})));
     AG_TRY(ag_ensure(c, c->pos_off, (size_t)(256 * (int64_t)nblocks + 1 > n + 1 ? 256 * (int64_t)nblocks + 1 : n + 1) * 4));
     AG_TRY(ag_ensure(c, c->perm, n * 4)); AG_TRY(ag_ensure(c, c->rank, n * 4));
-    AG_TRY(ag_ensure(c, c->spos, n * 32)); AG_TRY(ag_ensure(c, c->svel, n * 32)); AG_TRY(ag_ensure(c, c->svf, n * 16));
+    AG_TRY(ag_ensure(c, c->spos, n * 32)); AG_TRY(ag_ensure(c, c->svf, n * 16));
     AG_TRY(ag_ensure(c, c->cdig, n * 4)); AG_TRY(ag_ensure(c, c->pos_cnt, (n + 1) * 4));
     // minima of the shared-digit counts: level 0 per 16 positions (16 per run of
     // 256), levels k >= 1 per 16^(k+1)
@@ -1643,7 +1641,7 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     // 4. particle data into key order
     c->tree_soft = c->soft_n > 0;
     if (c->tree_soft) AG_TRY(ag_ensure(c, c->soft_s, (size_t)n * sizeof(float)));
-    launch_to_sorted(c, n, x, v, m, c->box);
+    launch_to_sorted(c, n, x, m, c->box);
     c->tree_box = c->box;
 
     // 5. topology
@@ -1691,12 +1689,12 @@ int ag_launch_build(ag_ctx* c, int64_t n, const double* x, const double* v, cons
     c->max_nodes = max_nodes;
 
     // 6. moments
-    return moments_pass(c);
+    return moments_pass(c, v);
 }
 
 int ag_launch_refit(ag_ctx* c, const double* x, const double* v, const double* m) {
     const int64_t n = c->n;
     PhaseScope phase(c, AG_PHASE_BUILD);
-    launch_to_sorted(c, n, x, v, m, c->tree_box);
-    return moments_pass(c);
+    launch_to_sorted(c, n, x, m, c->tree_box);
+    return moments_pass(c, v);
 }
