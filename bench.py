@@ -51,11 +51,11 @@ PEAK_HBM_GBS = 8000.0
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "643ed7ed30712f36ab3830f030f22e6221727022ca41bc27532ca1b120fa4c46",
+    "src_sha256": "6d4a046208e744de5f6e286ecc031d2d15db1256dbd304f8320e3b0042d32e76",
     "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64,
                  "waves_per_cu": 16, "group_split": 42, "group_pack": 0},
-    "fetch_kib": 351918.5, "write_kib": 222333.9,
-    "fetch_factor": 1048576.0 / 524304.9, "write_factor": 1.0,
+    "fetch_kib": 348710.7, "write_kib": 222364.4,
+    "fetch_factor": 1048576.0 / 524304.6, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);
