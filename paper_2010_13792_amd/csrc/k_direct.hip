@@ -24,7 +24,7 @@
 // source inside its softening length (a wave-uniform branch).
 //
 // FP64 mode: every operation in FP64; 1/sqrt(r^2) from the hardware's FP64
-// reciprocal square root estimate refined by two Newton steps.
+// reciprocal square root estimate and one third-order correction (rsqrt_f64).
 // FP32-pair mode: the separation d = x_j - x_i is formed in FP64 and rounded
 // once to FP32 (the exact relative coordinate), the pair term is computed in
 // FP32, and each lane's FP32 sum over one staged tile is folded into FP64
@@ -50,8 +50,9 @@ constexpr int kMinTShift = 2;            // at least 4 targets per workgroup (at
 
 __device__ __forceinline__ double near_img(double d, double L) { return d - L * rint(d / L); }
 
-// 1/sqrt(x), x > 0 normal: the hardware estimate y (relative error near
-// 2^-23) corrected once by the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
+// 1/sqrt(x), x > 0 normal: the hardware estimate y (relative error at most
+// about 2^-24 over arguments spread across 40 decades, as measured on
+// gfx950) corrected once by the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
 // in e = 1 - x y^2, to second order: the relative error left is about
 // (5/16) e^3, far below FP64 rounding, for five operations (two Newton steps
 // take eight)
