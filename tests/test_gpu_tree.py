@@ -282,14 +282,18 @@ def test_walk_partial_active(ctx, orc, frac):
 
 
 def test_refit_after_drift(ctx, orc):
+    """Refit with drifted positions and changed velocities (both read from
+    the refit's own arrays): node moments, velocity moments included, and
+    the forces match the oracle on the new state."""
     n = 30000
     x, v, m = workloads.plummer(n, seed=8)
     ctx.tree_build(_t(x), _t(v), _t(m), 16)
     x2 = x + 0.01 * v
-    ctx.tree_refit(_t(x2), _t(v), _t(m))
+    v2 = 1.3 * v + np.random.default_rng(9).normal(scale=0.05, size=v.shape)
+    ctx.tree_refit(_t(x2), _t(v2), _t(m))
     link, mom, perm = (t.cpu().numpy() for t in ctx.tree_export())
-    _check_topology(link, mom, perm, n, 16, x2, v, m, orc, sample=100, cells=False)
-    a, _, _ = _eval(ctx, x2, v, m, 0.6, 0.01, build=False)
+    _check_topology(link, mom, perm, n, 16, x2, v2, m, orc, sample=100, cells=False)
+    a, _, _ = _eval(ctx, x2, v2, m, 0.6, 0.01, build=False)
     rows = np.arange(0, n, 7)
     ar, _, _ = orc.direct(x2, v, m, 0.01, 1.0, rows)
     ea = rel_err(a[rows], ar)
