@@ -46,6 +46,26 @@ def test_noalloc_matches_direct(ag, prec):
                 assert torch.all(torch.isnan(got[0][_t(other)]))
 
 
+@pytest.mark.parametrize("n,k", [(2048, 1), (2048, 2047), (65536, 3), (65536, 2047), (1 << 20, 511),
+                                 (1 << 20, 2047), (1 << 20, 2048)])
+def test_noalloc_refuses_no_size(ag, n, k):
+    """Target sets on both sides of the split threshold (below 2048 the
+    sources are split over workgroups and the scratch holds the split sums;
+    2048 and up need none), up to 2^20 sources: the fixed scratch always
+    suffices, and the results equal the allocating entry point's bit for bit."""
+    x, v, m = workloads.plummer(n, seed=k)
+    act = np.random.default_rng(k).choice(n, k, replace=False).astype(np.int32)
+    tx, tv, tm, ia = _t(x), _t(v), _t(m), _t(act, torch.int32)
+    with ag.Context(0) as c:
+        ref, got = _outputs(n), _outputs(n)
+        c.grav_direct(tx, tv, tm, ia, 0.01, 1.0, *ref)
+        c.grav_direct(tx, tv, tm, ia, 0.01, 1.0, *got, noalloc=True)
+        c.sync()
+    for r, g in zip(ref, got):
+        assert torch.equal(torch.nan_to_num(r), torch.nan_to_num(g)), (n, k)
+    assert torch.all(torch.isfinite(got[0][ia.long()]))
+
+
 def test_noalloc_arguments(ag):
     x, v, m = workloads.plummer(64, seed=3)
     with ag.Context(0) as c:
