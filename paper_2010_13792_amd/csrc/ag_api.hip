@@ -399,7 +399,7 @@ extern "C" int ag_grav_direct(ag_ctx* c, int64_t n, const double* x, const doubl
     AG_TRY(ag_direct_check(c, n, x, v, m, idx, n_act, eps, G, precision));
     if (n_act == 0) return AG_OK;
     DeviceGuard g(c->device);
-    const size_t bytes = ag_direct_scratch_bytes(n, n_act);
+    const size_t bytes = ag_direct_scratch_bytes(n, n_act, precision);
     if (bytes > 0) AG_TRY(ag_ensure(c, c->direct_part, bytes));
     AG_TRY(ag_launch_direct(c, n, x, v, m, idx, n_act, eps, G, precision, acc, jerk, tidal,
                             bytes > 0 ? c->direct_part.p : nullptr));

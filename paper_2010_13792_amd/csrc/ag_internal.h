@@ -204,12 +204,12 @@ struct PhaseScope {
 // ---------------------------------------------------------------------------
 // launchers implemented in the kernel translation units
 // ---------------------------------------------------------------------------
-// direct summation; scratch holds ag_direct_scratch_bytes(n, n_act) bytes (the
+// direct summation; scratch holds ag_direct_scratch_bytes(n, n_act, precision) bytes (the
 // per-split sums of a small target set; nothing need be cleared)
 int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, const double* m,
                      const int32_t* idx, int64_t n_act, double eps, double G, int precision,
                      double* acc, double* jerk, double* tidal, void* scratch, bool timed = true);
-size_t ag_direct_scratch_bytes(int64_t n, int64_t n_act);
+size_t ag_direct_scratch_bytes(int64_t n, int64_t n_act, int precision);
 int ag_launch_timestep(ag_ctx* c, int64_t n, const int32_t* idx, int64_t n_idx,
                        const double* tidal, double eta, double dt_max, int32_t k_max,
                        double* dt, int8_t* bin, const int64_t* n_dev = nullptr);

@@ -10,6 +10,9 @@
 // SIMD without any exchange between workgroups.  Sources are staged through
 // LDS 1024 at a time (two coalesced loads per thread); the Gs groups of a
 // wave read Gs neighbouring sources at once (broadcasts within each group).
+// FP64 runs one workgroup per CU with up to 256 registers and takes kChains
+// sources per lane at a time (independent dependency chains); FP32 pairs
+// run two workgroups per CU within 128 registers, one source at a time.
 // At the end the subsets are added in a fixed tree: across the lane groups
 // of a wave by butterfly shuffles, then across the eight waves in LDS in
 // wave order -- bit-reproducible, no scratch and no atomics.  Only a target
@@ -46,6 +49,7 @@ constexpr int kWaves = 8;                // waves per workgroup
 constexpr int kThreads = 64 * kWaves;
 constexpr int kSrc = 2 * kThreads;       // sources per staged tile
 constexpr int kParts = 12;               // g (3), j (3), S (6)
+constexpr int kChains = 4;                // FP64 sources per lane per iteration
 constexpr int kMinTShift = 2;            // at least 4 targets per workgroup (at most 16 lane groups)
 
 __device__ __forceinline__ double near_img(double d, double L) { return d - L * rint(d / L); }
@@ -195,12 +199,48 @@ __device__ __forceinline__ void sep_at(const DirectLds& S, const DirectArgs& P, 
 
 // a lane's share of one staged tile of cnt sources: q = q0, q0 + stride, ...;
 // with kExcl the source at tile slot qs (the lane's own target) is left out.
-// FP64 pair terms.
+// FP64 pair terms; without per-particle softening kChains sources at a time
+// (independent dependency chains: the FP64 launch runs two waves per SIMD).
 template <bool kPer, bool kSoft, bool kExcl>
 __device__ __forceinline__ void pairs_tile(const DirectLds& S, const DirectArgs& P, int q0, int stride, int cnt,
                                            int qs, double xi, double yi, double zi, double vxi, double vyi,
                                            double vzi, double hi_, double h2, double hinv, DirAcc<double>& A) {
-    for (int q = q0; q < cnt; q += stride) {
+    int q = q0;
+    if constexpr (!kSoft && kChains > 1) {
+        constexpr int C = kChains;
+        for (; q + (C - 1) * stride < cnt; q += C * stride) {
+            double dx[C], dy[C], dz[C], nx[C], ny[C], nz[C], r2[C], mf[C], mD[C], mj[C];
+            bool inside = false;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int qc = q + c * stride;
+                sep_at<kPer>(S, P, qc, xi, yi, zi, vxi, vyi, vzi, dx[c], dy[c], dz[c], nx[c], ny[c], nz[c]);
+                mj[c] = (kExcl && qc == qs) ? 0.0 : S.src.m[qc];
+                r2[c] = dx[c] * dx[c] + dy[c] * dy[c] + dz[c] * dz[c];
+                inside = inside || r2[c] < h2;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double ri = rsqrt_f64(r2[c]);
+                const double ri2 = ri * ri;
+                mf[c] = mj[c] * (ri * ri2);
+                mD[c] = mf[c] * (-3.0 * ri2);
+            }
+            if (__ballot(inside) != 0) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (r2[c] < h2) {
+                        double f, D;
+                        spline_fd<double>(r2[c], hinv, f, D);
+                        mf[c] = mj[c] * f;
+                        mD[c] = mj[c] * D;
+                    }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) pair_add<double>(dx[c], dy[c], dz[c], nx[c], ny[c], nz[c], mf[c], mD[c], A);
+        }
+    }
+    for (; q < cnt; q += stride) {
         double dx, dy, dz, nx, ny, nz;
         sep_at<kPer>(S, P, q, xi, yi, zi, vxi, vyi, vzi, dx, dy, dz, nx, ny, nz);
         const double mj = (kExcl && q == qs) ? 0.0 : S.src.m[q];
@@ -248,10 +288,8 @@ __device__ __forceinline__ int64_t target_row(const DirectArgs& P, int64_t k, bo
     return i;
 }
 
-// (a register count of at most 128 keeps two workgroups, 16 waves, per CU)
 template <bool kFP64, bool kPer, bool kSoft>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_direct(DirectArgs P) {
-    __shared__ DirectLds S;
+__device__ __forceinline__ void direct_body(DirectLds& S, const DirectArgs& P) {
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int T = 1 << P.tshift;               // targets per workgroup
@@ -339,6 +377,20 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     }
 }
 
+// FP64: one workgroup per CU (kBlocks64), up to 256 registers for the
+// chains of kChains pairs; FP32 pairs: two workgroups per CU (kBlocks32), at
+// most 128 registers
+template <bool kPer, bool kSoft>
+__global__ void __launch_bounds__(kThreads) k_direct64(DirectArgs P) {
+    __shared__ DirectLds S;
+    direct_body<true, kPer, kSoft>(S, P);
+}
+template <bool kPer, bool kSoft>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_direct32(DirectArgs P) {
+    __shared__ DirectLds S;
+    direct_body<false, kPer, kSoft>(S, P);
+}
+
 // the splits of each target tile added in split order (a split launch only)
 __global__ void __launch_bounds__(256) k_direct_splits(DirectArgs P, int64_t tiles) {
     const int T = 1 << P.tshift;
@@ -356,22 +408,27 @@ __global__ void __launch_bounds__(256) k_direct_splits(DirectArgs P, int64_t til
 }  // namespace
 
 // Launch shape: the fewest lane groups per wave Gs (1 .. 16) that give at
-// least kDirectBlocks workgroups (two per CU); only below that at Gs = 16 is
-// the source range split as well (grid.y), so that tiles x splits stays
-// below 2 kDirectBlocks.  Each split covers a multiple of the 8 Gs subsets.
-constexpr int64_t kDirectBlocks = 512;
+// least `blocks` workgroups (kBlocks64 = one per CU for FP64, kBlocks32 = two
+// per CU for FP32 pairs); only below that at Gs = 16 is the source range
+// split as well (grid.y), so that tiles x splits stays below 2 blocks.  Each
+// split covers a multiple of the 8 Gs subsets.
+constexpr int64_t kBlocks64 = 256;
+constexpr int64_t kBlocks32 = 512;
+constexpr int64_t kDirectBlocks = kBlocks64 > kBlocks32 ? kBlocks64 : kBlocks32;   // bounds the split scratch
 
-void ag_direct_shape(int64_t n, int64_t n_act, int* tshift, int64_t* tiles, int64_t* nsplit, int64_t* chunk) {
+void ag_direct_shape(int64_t n, int64_t n_act, int precision, int* tshift, int64_t* tiles, int64_t* nsplit,
+                     int64_t* chunk) {
+    const int64_t blocks = precision == AG_FP64 ? kBlocks64 : kBlocks32;
     int ts = 6;
     int64_t t = (n_act + 63) >> 6;
-    while (ts > kMinTShift && t < kDirectBlocks) {
+    while (ts > kMinTShift && t < blocks) {
         --ts;
         t = (n_act + (1 << ts) - 1) >> ts;
     }
     const int64_t nsub = (int64_t)kWaves * (64 >> ts);
     int64_t s = 1;
-    if (t < kDirectBlocks) {
-        s = (kDirectBlocks + t - 1) / t;
+    if (t < blocks) {
+        s = (blocks + t - 1) / t;
         const int64_t max_split = (n + nsub - 1) / nsub;
         if (s > max_split) s = max_split;
         if (s > 65535) s = 65535;
@@ -385,10 +442,10 @@ void ag_direct_shape(int64_t n, int64_t n_act, int* tshift, int64_t* tiles, int6
     *chunk = c;
 }
 
-size_t ag_direct_scratch_bytes(int64_t n, int64_t n_act) {
+size_t ag_direct_scratch_bytes(int64_t n, int64_t n_act, int precision) {
     int ts;
     int64_t t, s, c;
-    ag_direct_shape(n, n_act, &ts, &t, &s, &c);
+    ag_direct_shape(n, n_act, precision, &ts, &t, &s, &c);
     if (s <= 1) return 0;
     return (size_t)t * s * kParts * ((size_t)1 << ts) * sizeof(double);
 }
@@ -398,7 +455,7 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
                      double* acc, double* jerk, double* tidal, void* scratch, bool timed) {
     int tshift;
     int64_t tiles, nsplit, chunk;
-    ag_direct_shape(n, n_act, &tshift, &tiles, &nsplit, &chunk);
+    ag_direct_shape(n, n_act, precision, &tshift, &tiles, &nsplit, &chunk);
     DirectArgs P{};
     P.n = n;
     P.x = x;
@@ -422,13 +479,13 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
     dim3 grid((unsigned)tiles, (unsigned)nsplit);
     hipStream_t st = c->stream;
     const bool fp64 = precision == AG_FP64, per = P.L > 0.0, soft = P.hs != nullptr;
-#define AG_DIRECT(A, B, C) hipLaunchKernelGGL((k_direct<A, B, C>), grid, dim3(kThreads), 0, st, P)
+#define AG_DIRECT(K, B, C) hipLaunchKernelGGL((K<B, C>), grid, dim3(kThreads), 0, st, P)
     if (fp64) {
-        if (per) { if (soft) AG_DIRECT(true, true, true); else AG_DIRECT(true, true, false); }
-        else { if (soft) AG_DIRECT(true, false, true); else AG_DIRECT(true, false, false); }
+        if (per) { if (soft) AG_DIRECT(k_direct64, true, true); else AG_DIRECT(k_direct64, true, false); }
+        else { if (soft) AG_DIRECT(k_direct64, false, true); else AG_DIRECT(k_direct64, false, false); }
     } else {
-        if (per) { if (soft) AG_DIRECT(false, true, true); else AG_DIRECT(false, true, false); }
-        else { if (soft) AG_DIRECT(false, false, true); else AG_DIRECT(false, false, false); }
+        if (per) { if (soft) AG_DIRECT(k_direct32, true, true); else AG_DIRECT(k_direct32, true, false); }
+        else { if (soft) AG_DIRECT(k_direct32, false, true); else AG_DIRECT(k_direct32, false, false); }
     }
 #undef AG_DIRECT
     if (nsplit > 1) {
@@ -442,8 +499,9 @@ int ag_launch_direct(ag_ctx* c, int64_t n, const double* x, const double* v, con
 // The allocation-free direct sum, for callers that cannot allocate device
 // memory: the split sums live in a file-scope device array of fixed size.
 // The launch shape bounds the scratch for every size (a split happens only
-// with fewer than kDirectBlocks target tiles of 4, so tiles x splits
-// < 2 kDirectBlocks), so no call is refused for its size.  Every call on a
+// with fewer target tiles of 4 than the precision's workgroup count, at most
+// kDirectBlocks, so tiles x splits < 2 kDirectBlocks), so no call is refused
+// for its size.  Every call on a
 // device shares that device's copy of the array: calls that overlap on one
 // device race.
 // ---------------------------------------------------------------------------
@@ -473,7 +531,7 @@ extern "C" int ag_grav_direct_noalloc(ag_ctx* c, int64_t n, const double* x, con
                                       double* acc, double* jerk, double* tidal) {
     AG_TRY(ag_direct_check(c, n, x, v, m, idx, n_act, eps, G, precision));
     if (n_act == 0) return AG_OK;
-    const size_t bytes = ag_direct_scratch_bytes(n, n_act);
+    const size_t bytes = ag_direct_scratch_bytes(n, n_act, precision);
     if (bytes > kNoAllocBytes)
         return ag_fail(AG_EINVAL, "the direct sum needs %zu bytes of scratch, above the %zu this entry point holds",
                        bytes, kNoAllocBytes);

@@ -94,9 +94,10 @@ def test_direct_ragged_and_subsets(ag, ctx, orc, n, frac):
 
 @pytest.mark.parametrize("n", [9000, 20000, 40000])
 def test_direct_wide_target_sets(ag, ctx, orc, n):
-    """Every row a target at sizes where each workgroup holds 16, 32 and 64
-    targets (4, 2 and 1 lane groups per wave): sampled rows against the
-    oracle, in both precisions, with a ragged last tile."""
+    """Every row a target at sizes where each workgroup holds 16 to 64
+    targets (4, 2 or 1 lane groups per wave; FP64 launches half as many
+    workgroups as FP32 pairs, so the two take different shapes): sampled
+    rows against the oracle, in both precisions, with a ragged last tile."""
     x, v, m = workloads.plummer(n, seed=n)
     eps, G = 0.01, 1.0
     rows = np.random.default_rng(n).choice(n, 64, replace=False)

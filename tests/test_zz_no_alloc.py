@@ -25,9 +25,9 @@ def _outputs(n):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_noalloc_matches_direct(ag, prec):
     p = ag.AG_FP64 if prec == "fp64" else ag.AG_FP32_PAIRS
-    # the first needs nearly the whole scratch (475 tiles of 4 targets, 2 splits),
-    # the second is smaller, the third splits nothing
-    cases = [(20000, np.random.default_rng(1).permutation(20000)[:1900]),
+    # both of the first two split their sources in either precision (250 and
+    # 84 tiles of 4 targets), the second is smaller; the third splits nothing
+    cases = [(20000, np.random.default_rng(1).permutation(20000)[:1000]),
              (1500, np.random.default_rng(2).permutation(1500)[:333]), (4096, None)]
     with ag.Context(0) as c:
         for n, act in cases:
@@ -46,20 +46,23 @@ def test_noalloc_matches_direct(ag, prec):
                 assert torch.all(torch.isnan(got[0][_t(other)]))
 
 
-@pytest.mark.parametrize("n,k", [(2048, 1), (2048, 2047), (65536, 3), (65536, 2047), (1 << 20, 511),
-                                 (1 << 20, 2047), (1 << 20, 2048)])
-def test_noalloc_refuses_no_size(ag, n, k):
-    """Target sets on both sides of the split threshold (below 2048 the
-    sources are split over workgroups and the scratch holds the split sums;
-    2048 and up need none), up to 2^20 sources: the fixed scratch always
-    suffices, and the results equal the allocating entry point's bit for bit."""
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,k", [(2048, 1), (2048, 1023), (2048, 2047), (65536, 3), (65536, 1024), (65536, 2047),
+                                 (1 << 20, 511), (1 << 20, 2047), (1 << 20, 2048)])
+def test_noalloc_refuses_no_size(ag, n, k, prec):
+    """Target sets on both sides of the split thresholds (the sources are
+    split over workgroups below 1024 targets in FP64 and below 2048 with FP32
+    pairs, and the scratch holds the split sums), up to 2^20 sources: the
+    fixed scratch always suffices, and the results equal the allocating entry
+    point's bit for bit."""
+    p = ag.AG_FP64 if prec == "fp64" else ag.AG_FP32_PAIRS
     x, v, m = workloads.plummer(n, seed=k)
     act = np.random.default_rng(k).choice(n, k, replace=False).astype(np.int32)
     tx, tv, tm, ia = _t(x), _t(v), _t(m), _t(act, torch.int32)
     with ag.Context(0) as c:
         ref, got = _outputs(n), _outputs(n)
-        c.grav_direct(tx, tv, tm, ia, 0.01, 1.0, *ref)
-        c.grav_direct(tx, tv, tm, ia, 0.01, 1.0, *got, noalloc=True)
+        c.grav_direct(tx, tv, tm, ia, 0.01, 1.0, *ref, precision=p)
+        c.grav_direct(tx, tv, tm, ia, 0.01, 1.0, *got, precision=p, noalloc=True)
         c.sync()
     for r, g in zip(ref, got):
         assert torch.equal(torch.nan_to_num(r), torch.nan_to_num(g)), (n, k)
