@@ -51,11 +51,11 @@ PEAK_HBM_GBS = 8000.0
 # while the walk kernel's sources hash to `src_sha256`; reported as null
 # otherwise, or for another workload.
 WALK_COUNTERS = {
-    "src_sha256": "6d4a046208e744de5f6e286ecc031d2d15db1256dbd304f8320e3b0042d32e76",
+    "src_sha256": "30ac2560443a8882c15bb3a317bb901a8600b4370058d644dd844c9bc248bb53",
     "workload": {"n": 1 << 20, "theta": 0.7, "eps": 1e-3, "n_leaf": 16, "mac_offset": 1, "group_targets": 64,
                  "waves_per_cu": 16, "group_split": 42, "group_pack": 0},
-    "fetch_kib": 348710.7, "write_kib": 222364.4,
-    "fetch_factor": 1048576.0 / 524304.6, "write_factor": 1.0,
+    "fetch_kib": 349323.4, "write_kib": 222362.8,
+    "fetch_factor": 1048576.0 / 524304.5, "write_factor": 1.0,
 }
 # FP32 flops the hardware executed in one walk launch at the same workload
 # (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS, per wave instruction, times 64 lanes);
